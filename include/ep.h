@@ -1,0 +1,194 @@
+/*
+ * ep.h -- C ABI of the MI355X cardiac electrophysiology voxel time-stepper.
+ *
+ * The library advances the operator-split, matrix-free finite-volume
+ * monodomain / bidomain equations on a voxel grid (thesis "Computational
+ * Tools for Cardiac Simulation", Algorithm chapter, section
+ * "Electrophysiology"): a pointwise Mitchell-Schaeffer update by explicit
+ * Euler (Reaction subsection; eqn:ms1, eqn:ms2), then diffusion through the
+ * conductivity tensor field (eqn:sigma1) either explicitly or by implicit
+ * Euler solved with Jacobi-preconditioned CG (Linear Solver chapter,
+ * "Implicit Euler"), and for the bidomain model the elliptic extracellular
+ * equation (second line of eqn:bidomain1) by FP32 PCG inside FP64 iterative
+ * refinement.
+ *
+ * Conventions shared by every call:
+ *  - Every call returns an ep_status; EP_OK is 0.  No C++ exception crosses
+ *    the ABI.  ep_last_error(g) gives a message for the last failure on g.
+ *  - Box layout: flat index (x*ny + y)*nz + z, z fastest, n = {nx, ny, nz}.
+ *  - Units: lengths mm, times ms, diffusivities mm^2/ms, v dimensionless.
+ *    chi_m*C_m = 1; the monodomain factor lambda/(1+lambda) is folded into
+ *    the conductivities the caller passes.
+ *  - Host pointers are borrowed for the duration of a call and copied.
+ *    Device memory belongs to the grid.
+ *  - A handle is not thread-safe; distinct handles may run concurrently on
+ *    distinct streams.  All work of a handle is ordered on its stream.
+ */
+#ifndef EP_H_
+#define EP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EP_API __attribute__((visibility("default")))
+
+typedef struct ep_grid_s* ep_grid;
+
+typedef enum {
+  EP_OK = 0,
+  EP_ERR_ARG = 1,         /* invalid argument: sizes, NULL, non-unit fibre,
+                             negative conductivity, unstable explicit dt, ... */
+  EP_ERR_OOM = 2,         /* device allocation failed */
+  EP_ERR_HIP = 3,         /* a HIP runtime call failed */
+  EP_ERR_NOCONV = 4,      /* a CG / refinement solve hit its iteration limit;
+                             the state was still advanced with the last iterate */
+  EP_ERR_NONFINITE = 5,   /* a non-finite potential appeared; sticky until
+                             ep_write_state */
+  EP_ERR_STATE = 6,       /* call out of order (e.g. ep_step before
+                             ep_set_conductivity_fibres) */
+  EP_ERR_UNSUPPORTED = 7  /* combination not implemented */
+} ep_status;
+
+typedef enum { EP_F64 = 0, EP_F32 = 1 } ep_prec;       /* bulk state + stencil */
+typedef enum { EP_MONO = 0, EP_BIDO = 1 } ep_model;
+typedef enum { EP_DIFF_EXPLICIT = 0, EP_DIFF_BE_PCG = 1 } ep_diff;
+typedef enum { EP_V = 0, EP_W = 1, EP_PHIE = 2, EP_TACT = 3 } ep_field;
+
+/* Mitchell-Schaeffer constants (eqn:ms1, eqn:ms2).  exc multiplies J_in
+ * (ionic excitability).  Above v_gate the gate relaxes as -w/tau_close. */
+typedef struct {
+  double tau_in, tau_out, tau_open, tau_close, v_gate, exc;
+} ep_ionic;
+
+/* Stimulus current amp (1/ms) added to dv/dt (J_stim of eqn:ms1) on tissue
+ * voxels p with lo <= p < hi per axis and, when radius > 0, whose centre
+ * ((p + 0.5) h, mm) lies within radius of center: dx*dx + dy*dy + dz*dz <=
+ * radius*radius evaluated in FP64 in that order.  Active at step n when
+ * t_on <= n*dt < t_off (FP64). */
+typedef struct {
+  int32_t lo[3], hi[3];
+  double center[3];
+  double radius;
+  double amp, t_on, t_off;
+} ep_stim;
+
+typedef struct {
+  int32_t n[3];              /* voxels per axis, each >= 1 */
+  double h;                  /* voxel width (mm), > 0 */
+  const uint8_t* mask;       /* host, n0*n1*n2 box layout, nonzero = tissue;
+                                NULL = all tissue */
+  ep_model model;
+  ep_prec prec;
+  ep_diff diff;              /* monodomain diffusion; bidomain is explicit */
+  double dt;                 /* ms, > 0 */
+  ep_ionic ionic;
+  const ep_stim* stim;       /* host array of n_stim entries (may be NULL if 0) */
+  int32_t n_stim;
+  double act_threshold;      /* activation threshold theta (0 < theta < 1) */
+  double pcg_rtol;           /* implicit-Euler PCG: stop at ||r|| <= rtol ||b|| */
+  int32_t pcg_maxit;
+  double ell_rtol;           /* bidomain elliptic refinement tolerance */
+  int32_t ell_max_outer;     /* max refinement (outer) iterations */
+  int32_t ell_inner_maxit;   /* max inner FP32 PCG iterations per outer */
+  void* stream;              /* hipStream_t (e.g. a torch stream) or NULL for
+                                the library's own stream */
+} ep_grid_desc;
+
+typedef struct {
+  int64_t steps;             /* steps advanced by the call */
+  int64_t step;              /* global step counter after the call */
+  double t;                  /* step * dt (ms) */
+  int64_t cg_iters;          /* PCG / inner iterations over the call */
+  int32_t cg_max;            /* largest iteration count of one solve */
+  int32_t ell_outer;         /* refinement iterations over the call */
+  double q_stim;             /* injected charge dt*h^3*sum J_stim over the call (FP64) */
+  double mass;               /* h^3 * sum over tissue of v after the call (FP64) */
+  double relres;             /* last relative residual of a solve */
+} ep_step_info;
+
+typedef struct {
+  int32_t outer;             /* refinement iterations */
+  int64_t inner_iters;       /* FP32 PCG iterations in total */
+  double relres;             /* final ||b - K phi|| / ||b|| in FP64 */
+} ep_solve_info;
+
+/* Create a grid.  Validates the description, builds the brick map of the
+ * tissue mask (voxel geometry as in the Geometry chapter: tissue voxels are
+ * the volume pass of the SDF encoding), allocates device state (v = 0,
+ * w = 1 on tissue, phi = 0, T_act = +inf) and copies stimuli.  On failure
+ * *out is NULL.  Errors: EP_ERR_ARG (bad sizes/values, NULL desc or out,
+ * no tissue, bidomain tissue not one face-connected component),
+ * EP_ERR_OOM, EP_ERR_HIP. */
+EP_API ep_status ep_create_grid(const ep_grid_desc* d, ep_grid* out);
+
+/* Set the conductivity from a unit fibre field (eqn:sigma1):
+ *   D_p = s_p * (sig_t I + (sig_l - sig_t) f_p f_p^T),
+ * fibre: host FP64, 3 per voxel, box layout; must be unit (| |f| - 1 | <=
+ * 1e-6) on tissue.  scale: host FP64 per voxel (> 0 on tissue) or NULL for 1.
+ * sig_el, sig_et: extracellular pair for EP_BIDO (ignored for EP_MONO).
+ * Builds the face / edge coefficients of the 19-point operator on the
+ * device (face tensor = mean of the two voxel tensors, edge tensor = mean
+ * of the four voxel tensors of the 2x2 block; terms touching non-tissue are
+ * dropped: no-flux) and the Jacobi diagonal.  For explicit diffusion it
+ * checks dt * lambda_max(-A) < 2 (EP_ERR_ARG otherwise).
+ * Errors: EP_ERR_ARG, EP_ERR_HIP. */
+EP_API ep_status ep_set_conductivity_fibres(ep_grid g, const double* fibre,
+                                            const double* scale, double sig_l,
+                                            double sig_t, double sig_el,
+                                            double sig_et);
+
+/* Advance nsteps operator-split steps (reaction, then diffusion; bidomain:
+ * reaction, elliptic solve for phi_e from v*, parabolic update).  Activation
+ * times are recorded at the first step with v_n < theta <= v_{n+1}, linearly
+ * interpolated.  info may be NULL.  Synchronises the stream once at the end.
+ * Errors: EP_ERR_STATE (no conductivity yet), EP_ERR_NONFINITE,
+ * EP_ERR_NOCONV (state still advanced), EP_ERR_HIP. */
+EP_API ep_status ep_step(ep_grid g, int32_t nsteps, ep_step_info* info);
+
+/* Solve the bidomain elliptic equation -(A_i + A_e) phi = A_i v for the
+ * current v (second line of eqn:bidomain1, heart only, no-flux, gauge
+ * sum_tissue phi = 0): FP32 Jacobi-PCG inner solves inside FP64 iterative
+ * refinement until ||b - K phi|| <= rel_tol ||b|| (FP64), warm-started from
+ * the stored phi.  EP_BIDO grids only (EP_ERR_UNSUPPORTED otherwise). */
+EP_API ep_status ep_solve_elliptic(ep_grid g, double rel_tol, int32_t max_outer,
+                                   ep_solve_info* info);
+
+/* Copy a field to host FP64 in box layout (n0*n1*n2 entries); non-tissue
+ * voxels read 0 (v, w, phi) or +inf (T_act).  Synchronises the stream.
+ * Errors: EP_ERR_ARG (NULL, n too small, bad field), EP_ERR_HIP. */
+EP_API ep_status ep_read_state(ep_grid g, ep_field f, double* host_out, size_t n);
+
+/* Overwrite a field from host FP64 in box layout; values at non-tissue
+ * voxels are ignored.  Clears the sticky non-finite flag.  For EP_TACT,
+ * +inf marks "not yet activated". */
+EP_API ep_status ep_write_state(ep_grid g, ep_field f, const double* host_in, size_t n);
+
+/* Global step counter (t_n = step * dt); settable to restart a run. */
+EP_API ep_status ep_get_step(ep_grid g, int64_t* step);
+EP_API ep_status ep_set_step(ep_grid g, int64_t step);
+
+/* Counts: tissue voxels, active 8x8x8 bricks, device bytes held. */
+EP_API ep_status ep_grid_stats(ep_grid g, int64_t* n_tissue, int64_t* n_bricks,
+                               int64_t* device_bytes);
+
+/* Kernel timing for measurement: when enabled, the library records HIP
+ * events around every launch of the dominant kernel of the configured path
+ * (kernel_id 0: the diffusion stencil / SpMV, 1: the CG vector update) on
+ * the grid's stream; ep_kernel_time returns the summed milliseconds and the
+ * launch count since the last enable. */
+EP_API ep_status ep_kernel_timing(ep_grid g, int32_t enable);
+EP_API ep_status ep_kernel_time(ep_grid g, int32_t kernel_id, double* total_ms,
+                                int64_t* launches);
+
+EP_API ep_status ep_destroy_grid(ep_grid g);
+EP_API const char* ep_status_string(ep_status s);
+EP_API const char* ep_last_error(ep_grid g);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EP_H_ */

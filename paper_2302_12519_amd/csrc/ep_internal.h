@@ -1,0 +1,163 @@
+// Internal declarations of the HIP voxel-EP library (not part of the ABI).
+//
+// Data layout in HBM.  The box is cut into 8x8x8 bricks; only bricks that
+// hold at least one tissue voxel are stored ("active" bricks, ids 0..nb-1 in
+// x-major brick order), followed by one all-zero "ghost" brick (id nb) that
+// stands in for every missing neighbour.  Inside a brick the 512 voxels are
+// z-fastest: local index l = (lx*8 + ly)*8 + lz, so one 64-lane wavefront
+// reads one x-plane of a brick as 256 contiguous bytes (FP32).  Every
+// per-voxel array (state, coefficients, CG vectors) is (nb+1)*512 long and
+// indexed brick*512 + l.  A neighbour table nbr[(nb+1)*27] maps each brick
+// and offset (dx,dy,dz) in {-1,0,1}^3 to a brick id (ghost when absent).
+//
+// Non-tissue voxels inside active bricks hold v = 0, w = 1 (the ionic rest
+// point, a bitwise fixed point of the update) and every stencil coefficient
+// touching them is zero, so kernels need no mask on the hot path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ep {
+
+constexpr int kB = 8;         // brick edge
+constexpr int kBV = 512;      // voxels per brick
+constexpr int kH = 10;        // brick edge plus a one-voxel halo on each side
+constexpr int kTile = 1000;   // kH^3
+constexpr int kHalo = 480;    // face (6x64) + edge (12x8) halo cells; corners unused
+constexpr int kNbr = 27;
+constexpr int kXcd = 8;       // MI355X: 8 accelerator complex dies
+constexpr int kRedThreads = 1024;
+
+// Coefficient slots of the 19-point operator, per voxel p:
+//   CX, CY, CZ: face weight between p and p+e_d, Dface_dd / h^2
+//   CXY, CXZ, CYZ: edge weight of the 2x2 block whose lower corner is p,
+//                 Dedge_dd' / (2 h^2)
+enum { CX = 0, CY = 1, CZ = 2, CXY = 3, CXZ = 4, CYZ = 5 };
+
+template <typename T>
+struct IonicT {
+  T inv_tau_in, inv_tau_out, inv_tau_open, inv_tau_close, v_gate, exc;
+};
+
+template <typename T>
+struct CoefSet {
+  const T* c[6];
+};
+
+template <typename T>
+struct CoefOut {
+  T* c[6];
+};
+
+// Device-resident scalars of one CG solve.  Every CG kernel reads `done`
+// first and returns at once when it is set, so a fixed sequence of launches
+// can be enqueued without a host round trip per iteration.
+struct CGScalars {
+  double rz;      // (r, M^-1 r)
+  double pq;      // (p, K p)
+  double rr;      // (r, r)
+  double bb;      // (b, b) (or the initial (r, r) for refinement inner solves)
+  double tol2;    // rtol^2
+  double alpha, beta;
+  double rsum;    // sum of r over tissue (elliptic gauge)
+  int it, maxit, done, fail;
+};
+
+enum RedOp {
+  RED_BE_INIT = 0,    // partials (rz, bb, rr) -> start a solve
+  RED_ALPHA = 1,      // partial pq -> alpha
+  RED_BETA = 2,       // partials (rr, rz) -> beta, convergence
+  RED_SUM = 3,        // generic: sum K partials into out[0..K)
+  RED_INNER_INIT = 4  // partials (rz, rr) -> start an inner solve (bb := rr)
+};
+
+struct LaunchCfg {
+  int nb;       // active bricks
+  int grid;     // blocks launched (multiple of kXcd, >= nb)
+  hipStream_t stream;
+};
+
+inline int grid_for(int nb) { return ((nb + kXcd - 1) / kXcd) * kXcd; }
+
+// ---- kernel launchers (ep_kernels.hip) ----------------------------------
+void launch_tensor_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask,
+                         const double* fib, const double* scale, double sig_l, double sig_t,
+                         double h, double* tens /*6 arrays, scratch*/, double* c64[6],
+                         float* c32[6]);
+
+template <typename T>
+void launch_explicit(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v,
+                     const T* w, const T* jstim, T* vout, T* wout, T* tact,
+                     IonicT<T> ion, T dt, T theta, double tn, int* flags);
+
+template <typename T>
+void launch_ionic(const LaunchCfg& L, const T* v, const T* w, const T* jstim, T* vs,
+                  T* wout, IonicT<T> ion, T dt);
+
+template <typename T>
+void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v,
+                    const T* w, const T* jstim, const T* dinv, T* x, T* wout, T* r,
+                    IonicT<T> ion, T dt, double* partials);
+
+template <typename T>
+void launch_spmv(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* r,
+                 const T* dinv, const T* pold, T* pnew, T* q, T c0, T c1, int first,
+                 const CGScalars* cg, double* partials);
+
+template <typename T>
+void launch_cg_update(const LaunchCfg& L, T* x, T* r, const T* p, const T* q,
+                      const T* dinv, const CGScalars* cg, double* partials);
+
+void launch_reduce(hipStream_t s, RedOp op, const double* partials, int nparts, int K,
+                   CGScalars* cg, double* out);
+void launch_reduce_init(hipStream_t s, RedOp op, const double* partials, int nparts, int K,
+                        CGScalars* cg, double tol2, int maxit);
+void launch_block_max(const LaunchCfg& L, const int* nbr, CoefSet<double> c,
+                      double* partials);
+void launch_scale(const LaunchCfg& L, double* x, const double* y, const double* sums);
+
+template <typename T>
+void launch_activation(const LaunchCfg& L, const T* vold, const T* vnew, T* tact, T dt,
+                       T theta, double tn, int* flags);
+
+template <typename T>
+void launch_dinv(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1,
+                 const uint8_t* mask, T* dinv);
+
+template <typename T>
+void launch_sum(const LaunchCfg& L, const T* x, double* partials);
+
+template <typename T>
+void launch_stim_scatter(hipStream_t s, const int64_t* idx, const double* val, int n, T* jstim,
+                         double* qstep);
+
+void launch_q_accum(hipStream_t s, double* qacc, const double* qstep, double scale);
+
+// bidomain
+template <typename T>
+void launch_resid64(const LaunchCfg& L, const int* nbr, CoefSet<double> ci, CoefSet<double> ck,
+                    const T* vs, const double* phi, const uint8_t* mask, double* r64,
+                    double* partials);
+
+void launch_inner_init(const LaunchCfg& L, const double* r64, const uint8_t* mask,
+                       const double* sums, double inv_count, const float* dinv, float* x,
+                       float* r, double* partials);
+
+void launch_phi_correct(const LaunchCfg& L, double* phi, const float* d, const uint8_t* mask,
+                        double* partials);
+
+void launch_phi_shift(const LaunchCfg& L, double* phi, const uint8_t* mask, const double* sum,
+                      double inv_count);
+
+template <typename T>
+void launch_parabolic(const LaunchCfg& L, const int* nbr, CoefSet<T> ci, const T* vs,
+                      const double* phi, const T* vold, T* vout, T* tact, T dt, T theta,
+                      double tn, int* flags);
+
+template <typename T>
+void launch_apply(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* x, T* y,
+                  double* partials);
+
+}  // namespace ep

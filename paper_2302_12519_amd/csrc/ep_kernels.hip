@@ -1,0 +1,879 @@
+// HIP kernels of the voxel-EP step for gfx950 (MI355X).
+//
+// One 512-thread workgroup (8 wavefronts) owns one 8x8x8 brick: thread t is
+// voxel l = t (z fastest), so every wavefront touches one contiguous brick
+// x-plane.  Stencil kernels stage the brick plus its face/edge halo (the
+// 19-point operator needs no corner cells) in LDS, recomputing cheap
+// pointwise work (the ionic update, the CG search direction) for halo cells
+// instead of writing it to HBM and reading it back.  Nothing here is a dense
+// contraction, so there is no MFMA: every kernel is bound by HBM traffic.
+//
+// Reductions are deterministic: each block writes its partial sums (FP64) to
+// a fixed slot, and one 1024-thread block sums the slots in a fixed order.
+#include <cmath>
+
+#include "ep_internal.h"
+
+namespace ep {
+namespace {
+
+__device__ __forceinline__ int tidx(int x, int y, int z) { return (x * kH + y) * kH + z; }
+
+// Workgroups are dealt round-robin to the 8 XCDs; hand each XCD a contiguous
+// run of bricks so that halo neighbours tend to sit in the same L2.
+__device__ __forceinline__ int block_brick() {
+  const int per = gridDim.x / kXcd;
+  const int b = blockIdx.x;
+  return (b % kXcd) * per + b / kXcd;
+}
+
+// Halo cell k in [0, 480): 6 faces x 64 cells, then 12 edges x 8 cells.
+// Coordinates are tile coordinates in [0, 10) (0 and 9 are the halo).
+__device__ __forceinline__ void halo_cell(int k, int& hx, int& hy, int& hz) {
+  if (k < 384) {
+    const int f = k >> 6, m = k & 63;
+    const int d = f >> 1, side = (f & 1) ? 9 : 0;
+    const int i = (m >> 3) + 1, j = (m & 7) + 1;
+    if (d == 0) { hx = side; hy = i; hz = j; }
+    else if (d == 1) { hx = i; hy = side; hz = j; }
+    else { hx = i; hy = j; hz = side; }
+  } else {
+    const int k2 = k - 384;
+    const int e = k2 >> 3, t = (k2 & 7) + 1;
+    const int pair = e >> 2;
+    const int s1 = (e & 2) ? 9 : 0, s2 = (e & 1) ? 9 : 0;
+    if (pair == 0) { hx = s1; hy = s2; hz = t; }
+    else if (pair == 1) { hx = s1; hy = t; hz = s2; }
+    else { hx = t; hy = s1; hz = s2; }
+  }
+}
+
+// global index of tile cell (hx, hy, hz) of the brick whose neighbour row is nbs
+__device__ __forceinline__ int tile_global(const int* nbs, int hx, int hy, int hz) {
+  const int ox = (hx == 0) ? 0 : (hx == 9 ? 2 : 1);
+  const int oy = (hy == 0) ? 0 : (hy == 9 ? 2 : 1);
+  const int oz = (hz == 0) ? 0 : (hz == 9 ? 2 : 1);
+  const int bk = nbs[ox * 9 + oy * 3 + oz];
+  return bk * kBV + ((((hx + 7) & 7) * 8 + ((hy + 7) & 7)) * 8 + ((hz + 7) & 7));
+}
+
+// global index of voxel (lx+dx, ly+dy, lz+dz), d in {-1, 0, 1}
+__device__ __forceinline__ int nb_global(const int* nbs, int brick, int lx, int ly, int lz,
+                                         int dx, int dy, int dz) {
+  const int tx = lx + dx, ty = ly + dy, tz = lz + dz;
+  const int ox = tx < 0 ? 0 : (tx > 7 ? 2 : 1);
+  const int oy = ty < 0 ? 0 : (ty > 7 ? 2 : 1);
+  const int oz = tz < 0 ? 0 : (tz > 7 ? 2 : 1);
+  const int slot = ox * 9 + oy * 3 + oz;
+  const int bk = (slot == 13) ? brick : nbs[slot];
+  return bk * kBV + (((tx & 7) * 8 + (ty & 7)) * 8 + (tz & 7));
+}
+
+// The 18 off-centre weights of voxel p of the 19-point operator, in the order
+//  0 ax(p)   1 ax(p-x)  2 ay(p)   3 ay(p-y)  4 az(p)   5 az(p-z)
+//  6 bxy(p)  7 bxy(p-x-y)  8 bxy(p-y)  9 bxy(p-x)
+// 10 bxz(p) 11 bxz(p-x-z) 12 bxz(p-z) 13 bxz(p-x)
+// 14 byz(p) 15 byz(p-y-z) 16 byz(p-z) 17 byz(p-y)
+template <typename T>
+__device__ __forceinline__ void gather18(const CoefSet<T>& c, const int* nbs, int brick, int lx,
+                                         int ly, int lz, T k[18]) {
+  const int g = brick * kBV + (lx * 8 + ly) * 8 + lz;
+  k[0] = c.c[CX][g];
+  k[1] = c.c[CX][nb_global(nbs, brick, lx, ly, lz, -1, 0, 0)];
+  k[2] = c.c[CY][g];
+  k[3] = c.c[CY][nb_global(nbs, brick, lx, ly, lz, 0, -1, 0)];
+  k[4] = c.c[CZ][g];
+  k[5] = c.c[CZ][nb_global(nbs, brick, lx, ly, lz, 0, 0, -1)];
+  k[6] = c.c[CXY][g];
+  k[7] = c.c[CXY][nb_global(nbs, brick, lx, ly, lz, -1, -1, 0)];
+  k[8] = c.c[CXY][nb_global(nbs, brick, lx, ly, lz, 0, -1, 0)];
+  k[9] = c.c[CXY][nb_global(nbs, brick, lx, ly, lz, -1, 0, 0)];
+  k[10] = c.c[CXZ][g];
+  k[11] = c.c[CXZ][nb_global(nbs, brick, lx, ly, lz, -1, 0, -1)];
+  k[12] = c.c[CXZ][nb_global(nbs, brick, lx, ly, lz, 0, 0, -1)];
+  k[13] = c.c[CXZ][nb_global(nbs, brick, lx, ly, lz, -1, 0, 0)];
+  k[14] = c.c[CYZ][g];
+  k[15] = c.c[CYZ][nb_global(nbs, brick, lx, ly, lz, 0, -1, -1)];
+  k[16] = c.c[CYZ][nb_global(nbs, brick, lx, ly, lz, 0, 0, -1)];
+  k[17] = c.c[CYZ][nb_global(nbs, brick, lx, ly, lz, 0, -1, 0)];
+}
+
+// (A u)_p from the LDS tile s at tile cell C.  Faces: a (u_q - u_p).  Each
+// 2x2 block in plane (d, d') couples p with its diagonal partner: +b along
+// (+d,+d') / (-d,-d') and -b along (+d,-d') / (-d,+d').
+template <typename T>
+__device__ __forceinline__ T apply19(const T* s, int C, const T k[18]) {
+  const T u = s[C];
+  T a = k[0] * (s[C + 100] - u) + k[1] * (s[C - 100] - u) + k[2] * (s[C + 10] - u) +
+        k[3] * (s[C - 10] - u) + k[4] * (s[C + 1] - u) + k[5] * (s[C - 1] - u);
+  a += k[6] * (s[C + 110] - u) + k[7] * (s[C - 110] - u) - k[8] * (s[C + 90] - u) -
+       k[9] * (s[C - 90] - u);
+  a += k[10] * (s[C + 101] - u) + k[11] * (s[C - 101] - u) - k[12] * (s[C + 99] - u) -
+       k[13] * (s[C - 99] - u);
+  a += k[14] * (s[C + 11] - u) + k[15] * (s[C - 11] - u) - k[16] * (s[C + 9] - u) -
+       k[17] * (s[C - 9] - u);
+  return a;
+}
+
+template <typename T>
+__device__ __forceinline__ T diag19(const T k[18]) {
+  return -(k[0] + k[1] + k[2] + k[3] + k[4] + k[5]) - (k[6] + k[7]) + (k[8] + k[9]) -
+         (k[10] + k[11]) + (k[12] + k[13]) - (k[14] + k[15]) + (k[16] + k[17]);
+}
+
+// One explicit Euler step of Mitchell-Schaeffer; the gate branch is decided
+// on the pre-step v and taken as a select.
+template <typename T>
+__device__ __forceinline__ void ms_step(T v, T w, T js, const IonicT<T>& p, T dt, T& vs,
+                                        T& ws) {
+  const T jin = p.exc * v * v * (T(1) - v) * w * p.inv_tau_in;
+  const T jout = -v * p.inv_tau_out;
+  const T dw = (v < p.v_gate) ? (T(1) - w) * p.inv_tau_open : -w * p.inv_tau_close;
+  vs = v + dt * (jin + jout + js);
+  ws = w + dt * dw;
+}
+
+// Sum K per-thread doubles over the block; thread k < K writes slot k.
+template <int K>
+__device__ __forceinline__ void block_partials(double (&v)[K], double* partials) {
+  __shared__ double red[K][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[k][wave] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
+    partials[threadIdx.x * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void idle_partials(double* partials) {
+  if (partials && threadIdx.x < K) partials[threadIdx.x * gridDim.x + blockIdx.x] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// coefficient encoding (once per conductivity change)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBV) void k_tensor(int nb, const uint8_t* __restrict__ mask,
+                                                const double* __restrict__ fib,
+                                                const double* __restrict__ scale, double sig_l,
+                                                double sig_t, double* __restrict__ tens,
+                                                int64_t stride) {
+  const int brick = block_brick();
+  if (brick >= nb) return;
+  const int g = brick * kBV + threadIdx.x;
+  const bool t = mask[g] != 0;
+  const double s = scale ? scale[g] : 1.0;
+  const double f0 = fib[3 * (int64_t)g], f1 = fib[3 * (int64_t)g + 1], f2 = fib[3 * (int64_t)g + 2];
+  const double a = sig_l - sig_t;
+  tens[0 * stride + g] = t ? s * (sig_t + a * f0 * f0) : 0.0;
+  tens[1 * stride + g] = t ? s * (sig_t + a * f1 * f1) : 0.0;
+  tens[2 * stride + g] = t ? s * (sig_t + a * f2 * f2) : 0.0;
+  tens[3 * stride + g] = t ? s * (a * f0 * f1) : 0.0;
+  tens[4 * stride + g] = t ? s * (a * f0 * f2) : 0.0;
+  tens[5 * stride + g] = t ? s * (a * f1 * f2) : 0.0;
+}
+
+// Face weight: mean of the two voxel tensors / h^2 when both are tissue.
+// Edge weight: mean of the four voxel tensors of the 2x2 block / (2 h^2)
+// when all four are tissue.  Terms touching non-tissue are dropped (no flux).
+__global__ __launch_bounds__(kBV) void k_coefs(int nb, const int* __restrict__ nbr,
+                                               const uint8_t* __restrict__ mask,
+                                               const double* __restrict__ tens, int64_t stride,
+                                               double inv_h2, CoefOut<double> out64,
+                                               CoefOut<float> out32) {
+  __shared__ int nbs[kNbr];
+  const int brick = block_brick();
+  if (brick >= nb) return;
+  const int t = threadIdx.x;
+  if (t < kNbr) nbs[t] = nbr[brick * kNbr + t];
+  __syncthreads();
+  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
+  const int g = brick * kBV + t;
+  const int gx = nb_global(nbs, brick, lx, ly, lz, 1, 0, 0);
+  const int gy = nb_global(nbs, brick, lx, ly, lz, 0, 1, 0);
+  const int gz = nb_global(nbs, brick, lx, ly, lz, 0, 0, 1);
+  const int gxy = nb_global(nbs, brick, lx, ly, lz, 1, 1, 0);
+  const int gxz = nb_global(nbs, brick, lx, ly, lz, 1, 0, 1);
+  const int gyz = nb_global(nbs, brick, lx, ly, lz, 0, 1, 1);
+  const bool m0 = mask[g] != 0, mx = mask[gx] != 0, my = mask[gy] != 0, mz = mask[gz] != 0;
+  const bool mxy = mask[gxy] != 0, mxz = mask[gxz] != 0, myz = mask[gyz] != 0;
+  double c[6];
+  c[CX] = (m0 && mx) ? 0.5 * (tens[0 * stride + g] + tens[0 * stride + gx]) * inv_h2 : 0.0;
+  c[CY] = (m0 && my) ? 0.5 * (tens[1 * stride + g] + tens[1 * stride + gy]) * inv_h2 : 0.0;
+  c[CZ] = (m0 && mz) ? 0.5 * (tens[2 * stride + g] + tens[2 * stride + gz]) * inv_h2 : 0.0;
+  c[CXY] = (m0 && mx && my && mxy)
+               ? 0.25 * (tens[3 * stride + g] + tens[3 * stride + gx] + tens[3 * stride + gy] +
+                         tens[3 * stride + gxy]) * (0.5 * inv_h2)
+               : 0.0;
+  c[CXZ] = (m0 && mx && mz && mxz)
+               ? 0.25 * (tens[4 * stride + g] + tens[4 * stride + gx] + tens[4 * stride + gz] +
+                         tens[4 * stride + gxz]) * (0.5 * inv_h2)
+               : 0.0;
+  c[CYZ] = (m0 && my && mz && myz)
+               ? 0.25 * (tens[5 * stride + g] + tens[5 * stride + gy] + tens[5 * stride + gz] +
+                         tens[5 * stride + gyz]) * (0.5 * inv_h2)
+               : 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    if (out64.c[k]) out64.c[k][g] = c[k];
+    if (out32.c[k]) out32.c[k][g] = static_cast<float>(c[k]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// explicit monodomain step: ionic + 19-point diffusion + activation, fused
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_explicit(int nb, const int* __restrict__ nbr,
+                                                  CoefSet<T> c, const T* __restrict__ v,
+                                                  const T* __restrict__ w,
+                                                  const T* __restrict__ jstim,
+                                                  T* __restrict__ vout, T* __restrict__ wout,
+                                                  T* __restrict__ tact, IonicT<T> ion, T dt,
+                                                  T theta, double tn, int* flags) {
+  __shared__ T s[kTile];
+  __shared__ int nbs[kNbr];
+  const int brick = block_brick();
+  if (brick >= nb) return;
+  const int t = threadIdx.x;
+  if (t < kNbr) nbs[t] = nbr[brick * kNbr + t];
+  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
+  const int g = brick * kBV + t;
+  const T v0 = v[g], w0 = w[g];
+  T vs, ws;
+  ms_step(v0, w0, jstim ? jstim[g] : T(0), ion, dt, vs, ws);
+  const int C = tidx(lx + 1, ly + 1, lz + 1);
+  s[C] = vs;
+  __syncthreads();
+  for (int k = t; k < kHalo; k += kBV) {
+    int hx, hy, hz;
+    halo_cell(k, hx, hy, hz);
+    const int gg = tile_global(nbs, hx, hy, hz);
+    T a, b;
+    ms_step(v[gg], w[gg], jstim ? jstim[gg] : T(0), ion, dt, a, b);
+    s[tidx(hx, hy, hz)] = a;
+  }
+  __syncthreads();
+  T k18[18];
+  gather18(c, nbs, brick, lx, ly, lz, k18);
+  const T vn = vs + dt * apply19(s, C, k18);
+  vout[g] = vn;
+  wout[g] = ws;
+  if (v0 < theta && theta <= vn) {
+    if (isinf(tact[g])) tact[g] = static_cast<T>(tn) + dt * (theta - v0) / (vn - v0);
+  }
+  if (!isfinite(vn)) flags[0] = 1;
+}
+
+// pointwise ionic update (bidomain reaction sub-step)
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_ionic(int nb, const T* __restrict__ v,
+                                               const T* __restrict__ w,
+                                               const T* __restrict__ jstim, T* __restrict__ vs,
+                                               T* __restrict__ wout, IonicT<T> ion, T dt) {
+  const int brick = block_brick();
+  if (brick >= nb) return;
+  const int g = brick * kBV + threadIdx.x;
+  T a, b;
+  ms_step(v[g], w[g], jstim ? jstim[g] : T(0), ion, dt, a, b);
+  vs[g] = a;
+  wout[g] = b;
+}
+
+// ---------------------------------------------------------------------------
+// implicit Euler diffusion by Jacobi-PCG:  (I - dt A) x = v*,  x0 = v*
+// ---------------------------------------------------------------------------
+// Reaction fused with the initial residual r0 = b - (I - dt A) b = dt A v*.
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__ nbr,
+                                                 CoefSet<T> c, const T* __restrict__ v,
+                                                 const T* __restrict__ w,
+                                                 const T* __restrict__ jstim,
+                                                 const T* __restrict__ dinv, T* __restrict__ x,
+                                                 T* __restrict__ wout, T* __restrict__ r,
+                                                 IonicT<T> ion, T dt, double* partials) {
+  __shared__ T s[kTile];
+  __shared__ int nbs[kNbr];
+  const int brick = block_brick();
+  if (brick >= nb) { idle_partials<3>(partials); return; }
+  const int t = threadIdx.x;
+  if (t < kNbr) nbs[t] = nbr[brick * kNbr + t];
+  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
+  const int g = brick * kBV + t;
+  T vs, ws;
+  ms_step(v[g], w[g], jstim ? jstim[g] : T(0), ion, dt, vs, ws);
+  const int C = tidx(lx + 1, ly + 1, lz + 1);
+  s[C] = vs;
+  __syncthreads();
+  for (int k = t; k < kHalo; k += kBV) {
+    int hx, hy, hz;
+    halo_cell(k, hx, hy, hz);
+    const int gg = tile_global(nbs, hx, hy, hz);
+    T a, b;
+    ms_step(v[gg], w[gg], jstim ? jstim[gg] : T(0), ion, dt, a, b);
+    s[tidx(hx, hy, hz)] = a;
+  }
+  __syncthreads();
+  T k18[18];
+  gather18(c, nbs, brick, lx, ly, lz, k18);
+  const T rr = dt * apply19(s, C, k18);
+  x[g] = vs;
+  wout[g] = ws;
+  r[g] = rr;
+  const double rd = static_cast<double>(rr);
+  double acc[3] = {rd * static_cast<double>(dinv[g]) * rd,
+                   static_cast<double>(vs) * static_cast<double>(vs), rd * rd};
+  block_partials<3>(acc, partials);
+}
+
+// q = c0 p + c1 A p with the search direction p = M^-1 r + beta p_old formed
+// on the fly (also for halo cells), written once for the owned voxels.
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_spmv(int nb, const int* __restrict__ nbr, CoefSet<T> c,
+                                              const T* __restrict__ r,
+                                              const T* __restrict__ dinv,
+                                              const T* __restrict__ pold, T* __restrict__ pnew,
+                                              T* __restrict__ q, T c0, T c1, int first,
+                                              const CGScalars* __restrict__ cg,
+                                              double* partials) {
+  if (cg->done) return;
+  __shared__ T s[kTile];
+  __shared__ int nbs[kNbr];
+  const int brick = block_brick();
+  if (brick >= nb) { idle_partials<1>(partials); return; }
+  const int t = threadIdx.x;
+  if (t < kNbr) nbs[t] = nbr[brick * kNbr + t];
+  const T beta = first ? T(0) : static_cast<T>(cg->beta);
+  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
+  const int g = brick * kBV + t;
+  const T pn = first ? dinv[g] * r[g] : dinv[g] * r[g] + beta * pold[g];
+  const int C = tidx(lx + 1, ly + 1, lz + 1);
+  s[C] = pn;
+  __syncthreads();
+  for (int k = t; k < kHalo; k += kBV) {
+    int hx, hy, hz;
+    halo_cell(k, hx, hy, hz);
+    const int gg = tile_global(nbs, hx, hy, hz);
+    s[tidx(hx, hy, hz)] = first ? dinv[gg] * r[gg] : dinv[gg] * r[gg] + beta * pold[gg];
+  }
+  __syncthreads();
+  T k18[18];
+  gather18(c, nbs, brick, lx, ly, lz, k18);
+  const T qv = c0 * pn + c1 * apply19(s, C, k18);
+  pnew[g] = pn;
+  q[g] = qv;
+  double acc[1] = {static_cast<double>(pn) * static_cast<double>(qv)};
+  block_partials<1>(acc, partials);
+}
+
+// x += alpha p; r -= alpha q; partials (r.r, r.M^-1 r)
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_cg_update(int nb, T* __restrict__ x, T* __restrict__ r,
+                                                   const T* __restrict__ p,
+                                                   const T* __restrict__ q,
+                                                   const T* __restrict__ dinv,
+                                                   const CGScalars* __restrict__ cg,
+                                                   double* partials) {
+  if (cg->done) return;
+  const int brick = block_brick();
+  if (brick >= nb) { idle_partials<2>(partials); return; }
+  const int g = brick * kBV + threadIdx.x;
+  const T alpha = static_cast<T>(cg->alpha);
+  x[g] = x[g] + alpha * p[g];
+  const T rn = r[g] - alpha * q[g];
+  r[g] = rn;
+  const double rd = static_cast<double>(rn);
+  double acc[2] = {rd * rd, rd * static_cast<double>(dinv[g]) * rd};
+  block_partials<2>(acc, partials);
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce(int op, const double* __restrict__ partials,
+                                                       int nparts, int K, CGScalars* cg,
+                                                       double* out, double tol2, int maxit) {
+  if ((op == RED_ALPHA || op == RED_BETA) && cg->done) return;
+  __shared__ double sm[3][kRedThreads];
+  const int t = threadIdx.x;
+  for (int k = 0; k < K; ++k) {
+    double s = 0.0;
+    for (int i = t; i < nparts; i += kRedThreads) s += partials[k * nparts + i];
+    sm[k][t] = s;
+  }
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if (t < w)
+      for (int k = 0; k < K; ++k) sm[k][t] += sm[k][t + w];
+    __syncthreads();
+  }
+  if (t != 0) return;
+  const double S0 = sm[0][0], S1 = K > 1 ? sm[1][0] : 0.0, S2 = K > 2 ? sm[2][0] : 0.0;
+  switch (op) {
+    case RED_BE_INIT:   // (rz, bb, rr)
+      cg->rz = S0; cg->bb = S1; cg->rr = S2;
+      cg->it = 0; cg->alpha = 0.0; cg->beta = 0.0; cg->fail = 0;
+      cg->tol2 = tol2; cg->maxit = maxit;
+      cg->done = (S1 == 0.0 || S2 <= tol2 * S1) ? 1 : 0;
+      break;
+    case RED_INNER_INIT:   // (rz, rr); tolerance relative to the initial residual
+      cg->rz = S0; cg->rr = S1; cg->bb = S1;
+      cg->it = 0; cg->alpha = 0.0; cg->beta = 0.0; cg->fail = 0;
+      cg->tol2 = tol2; cg->maxit = maxit;
+      cg->done = (S1 == 0.0) ? 1 : 0;
+      break;
+    case RED_ALPHA:
+      if (!(S0 > 0.0) || !isfinite(S0)) { cg->done = 1; cg->fail = 1; }
+      else cg->alpha = cg->rz / S0;
+      break;
+    case RED_BETA:   // (rr, rz)
+      cg->it += 1;
+      cg->rr = S0;
+      if (!isfinite(S0)) { cg->done = 1; cg->fail = 1; }
+      else if (S0 <= cg->tol2 * cg->bb) cg->done = 1;
+      else if (cg->it >= cg->maxit) { cg->done = 1; cg->fail = 1; }
+      else { cg->beta = S1 / cg->rz; cg->rz = S1; }
+      break;
+    default:
+      for (int k = 0; k < K; ++k) out[k] = sm[k][0];
+      break;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_activation(int nb, const T* __restrict__ vold,
+                                                    const T* __restrict__ vnew,
+                                                    T* __restrict__ tact, T dt, T theta,
+                                                    double tn, int* flags) {
+  const int brick = block_brick();
+  if (brick >= nb) return;
+  const int g = brick * kBV + threadIdx.x;
+  const T v0 = vold[g], vn = vnew[g];
+  if (v0 < theta && theta <= vn) {
+    if (isinf(tact[g])) tact[g] = static_cast<T>(tn) + dt * (theta - v0) / (vn - v0);
+  }
+  if (!isfinite(vn)) flags[0] = 1;
+}
+
+// Jacobi: dinv = 1 / (c0 + c1 A_pp) where positive, else 0.
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_dinv(int nb, const int* __restrict__ nbr, CoefSet<T> c,
+                                              T c0, T c1, T* __restrict__ dinv) {
+  __shared__ int nbs[kNbr];
+  const int brick = block_brick();
+  if (brick >= nb) return;
+  const int t = threadIdx.x;
+  if (t < kNbr) nbs[t] = nbr[brick * kNbr + t];
+  __syncthreads();
+  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
+  T k18[18];
+  gather18(c, nbs, brick, lx, ly, lz, k18);
+  const T d = c0 + c1 * diag19(k18);
+  dinv[brick * kBV + t] = d > T(0) ? T(1) / d : T(0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_sum(int nb, const T* __restrict__ x, double* partials) {
+  const int brick = block_brick();
+  if (brick >= nb) { idle_partials<1>(partials); return; }
+  double acc[1] = {static_cast<double>(x[brick * kBV + threadIdx.x])};
+  block_partials<1>(acc, partials);
+}
+
+// scatter the current stimulus currents; qstep = sum of the values (FP64)
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_stim_scatter(const int64_t* __restrict__ idx,
+                                                             const double* __restrict__ val,
+                                                             int n, T* __restrict__ jstim,
+                                                             double* qstep) {
+  __shared__ double sm[kRedThreads];
+  const int t = threadIdx.x;
+  double s = 0.0;
+  for (int i = t; i < n; i += kRedThreads) {
+    jstim[idx[i]] = static_cast<T>(val[i]);
+    s += val[i];
+  }
+  sm[t] = s;
+  __syncthreads();
+  for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+    if (t < w) sm[t] += sm[t + w];
+    __syncthreads();
+  }
+  if (t == 0) qstep[0] = sm[0];
+}
+
+__global__ void k_q_accum(double* qacc, const double* qstep, double scale) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) qacc[0] += scale * qstep[0];
+}
+
+// ---------------------------------------------------------------------------
+// bidomain
+// ---------------------------------------------------------------------------
+// r = b - K phi in FP64 with b = A_i v* and K = -(A_i + A_e) (coefficient set
+// ck holds A_i + A_e).  Partials: (r.r, sum r, b.b).
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_resid64(int nb, const int* __restrict__ nbr,
+                                                 CoefSet<double> ci, CoefSet<double> ck,
+                                                 const T* __restrict__ vs,
+                                                 const double* __restrict__ phi,
+                                                 double* __restrict__ r64, double* partials) {
+  __shared__ double sa[kTile];
+  __shared__ double sb[kTile];
+  __shared__ int nbs[kNbr];
+  const int brick = block_brick();
+  if (brick >= nb) { idle_partials<3>(partials); return; }
+  const int t = threadIdx.x;
+  if (t < kNbr) nbs[t] = nbr[brick * kNbr + t];
+  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
+  const int g = brick * kBV + t;
+  const int C = tidx(lx + 1, ly + 1, lz + 1);
+  sa[C] = static_cast<double>(vs[g]);
+  sb[C] = phi[g];
+  __syncthreads();
+  for (int k = t; k < kHalo; k += kBV) {
+    int hx, hy, hz;
+    halo_cell(k, hx, hy, hz);
+    const int gg = tile_global(nbs, hx, hy, hz);
+    sa[tidx(hx, hy, hz)] = static_cast<double>(vs[gg]);
+    sb[tidx(hx, hy, hz)] = phi[gg];
+  }
+  __syncthreads();
+  double k18[18];
+  gather18(ci, nbs, brick, lx, ly, lz, k18);
+  const double b = apply19(sa, C, k18);
+  gather18(ck, nbs, brick, lx, ly, lz, k18);
+  const double r = b + apply19(sb, C, k18);
+  r64[g] = r;
+  double acc[3] = {r * r, r, b * b};
+  block_partials<3>(acc, partials);
+}
+
+// inner solve start: r32 = (r64 - mean) on tissue, x32 = 0; partials (rz, rr)
+__global__ __launch_bounds__(kBV) void k_inner_init(int nb, const double* __restrict__ r64,
+                                                    const uint8_t* __restrict__ mask,
+                                                    const double* __restrict__ sums,
+                                                    double inv_count,
+                                                    const float* __restrict__ dinv,
+                                                    float* __restrict__ x,
+                                                    float* __restrict__ r, double* partials) {
+  const int brick = block_brick();
+  if (brick >= nb) { idle_partials<2>(partials); return; }
+  const int g = brick * kBV + threadIdx.x;
+  const double mean = sums[1] * inv_count;
+  const float rv = mask[g] ? static_cast<float>(r64[g] - mean) : 0.0f;
+  r[g] = rv;
+  x[g] = 0.0f;
+  const double rd = static_cast<double>(rv);
+  double acc[2] = {rd * static_cast<double>(dinv[g]) * rd, rd * rd};
+  block_partials<2>(acc, partials);
+}
+
+// phi += d (FP64); partial sum of phi
+__global__ __launch_bounds__(kBV) void k_phi_correct(int nb, double* __restrict__ phi,
+                                                     const float* __restrict__ d,
+                                                     const uint8_t* __restrict__ mask,
+                                                     double* partials) {
+  const int brick = block_brick();
+  if (brick >= nb) { idle_partials<1>(partials); return; }
+  const int g = brick * kBV + threadIdx.x;
+  const double p = mask[g] ? phi[g] + static_cast<double>(d[g]) : 0.0;
+  phi[g] = p;
+  double acc[1] = {p};
+  block_partials<1>(acc, partials);
+}
+
+__global__ __launch_bounds__(kBV) void k_phi_shift(int nb, double* __restrict__ phi,
+                                                   const uint8_t* __restrict__ mask,
+                                                   const double* __restrict__ sum,
+                                                   double inv_count) {
+  const int brick = block_brick();
+  if (brick >= nb) return;
+  const int g = brick * kBV + threadIdx.x;
+  const double mean = sum[0] * inv_count;
+  phi[g] = mask[g] ? phi[g] - mean : 0.0;
+}
+
+// v_{n+1} = v* + dt A_i (v* + phi), with the activation check
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_parabolic(int nb, const int* __restrict__ nbr,
+                                                   CoefSet<T> ci, const T* __restrict__ vs,
+                                                   const double* __restrict__ phi,
+                                                   const T* __restrict__ vold,
+                                                   T* __restrict__ vout, T* __restrict__ tact,
+                                                   T dt, T theta, double tn, int* flags) {
+  __shared__ T s[kTile];
+  __shared__ int nbs[kNbr];
+  const int brick = block_brick();
+  if (brick >= nb) return;
+  const int t = threadIdx.x;
+  if (t < kNbr) nbs[t] = nbr[brick * kNbr + t];
+  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
+  const int g = brick * kBV + t;
+  const int C = tidx(lx + 1, ly + 1, lz + 1);
+  const T vsg = vs[g];
+  s[C] = vsg + static_cast<T>(phi[g]);
+  __syncthreads();
+  for (int k = t; k < kHalo; k += kBV) {
+    int hx, hy, hz;
+    halo_cell(k, hx, hy, hz);
+    const int gg = tile_global(nbs, hx, hy, hz);
+    s[tidx(hx, hy, hz)] = vs[gg] + static_cast<T>(phi[gg]);
+  }
+  __syncthreads();
+  T k18[18];
+  gather18(ci, nbs, brick, lx, ly, lz, k18);
+  const T vn = vsg + dt * apply19(s, C, k18);
+  vout[g] = vn;
+  const T v0 = vold[g];
+  if (v0 < theta && theta <= vn) {
+    if (isinf(tact[g])) tact[g] = static_cast<T>(tn) + dt * (theta - v0) / (vn - v0);
+  }
+  if (!isfinite(vn)) flags[0] = 1;
+}
+
+// y = A x; partials (y.y, x.y)
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_apply(int nb, const int* __restrict__ nbr, CoefSet<T> c,
+                                               const T* __restrict__ x, T* __restrict__ y,
+                                               double* partials) {
+  __shared__ T s[kTile];
+  __shared__ int nbs[kNbr];
+  const int brick = block_brick();
+  if (brick >= nb) { idle_partials<2>(partials); return; }
+  const int t = threadIdx.x;
+  if (t < kNbr) nbs[t] = nbr[brick * kNbr + t];
+  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
+  const int g = brick * kBV + t;
+  const int C = tidx(lx + 1, ly + 1, lz + 1);
+  const T xg = x[g];
+  s[C] = xg;
+  __syncthreads();
+  for (int k = t; k < kHalo; k += kBV) {
+    int hx, hy, hz;
+    halo_cell(k, hx, hy, hz);
+    s[tidx(hx, hy, hz)] = x[tile_global(nbs, hx, hy, hz)];
+  }
+  __syncthreads();
+  T k18[18];
+  gather18(c, nbs, brick, lx, ly, lz, k18);
+  const T yv = apply19(s, C, k18);
+  y[g] = yv;
+  double acc[2] = {static_cast<double>(yv) * static_cast<double>(yv),
+                   static_cast<double>(xg) * static_cast<double>(yv)};
+  if (partials) block_partials<2>(acc, partials);
+}
+
+// Per-block maximum of the Gershgorin row bound |A_pp| + sum_q |A_pq|.
+__global__ __launch_bounds__(kBV) void k_block_max(int nb, const int* __restrict__ nbr,
+                                                   CoefSet<double> c, double* partials) {
+  __shared__ int nbs[kNbr];
+  __shared__ double red[kBV / 64];
+  const int brick = block_brick();
+  if (brick >= nb) { if (threadIdx.x == 0) partials[blockIdx.x] = 0.0; return; }
+  const int t = threadIdx.x;
+  if (t < kNbr) nbs[t] = nbr[brick * kNbr + t];
+  __syncthreads();
+  double k18[18];
+  gather18(c, nbs, brick, t >> 6, (t >> 3) & 7, t & 7, k18);
+  double gsum = fabs(diag19(k18));
+  for (int i = 0; i < 18; ++i) gsum += fabs(k18[i]);
+  for (int off = 32; off > 0; off >>= 1) gsum = fmax(gsum, __shfl_xor(gsum, off, 64));
+  if ((t & 63) == 0) red[t >> 6] = gsum;
+  __syncthreads();
+  if (t == 0) {
+    double m = 0.0;
+    for (int i = 0; i < kBV / 64; ++i) m = fmax(m, red[i]);
+    partials[blockIdx.x] = m;
+  }
+}
+
+// x = y / sqrt(sums[0]) (power iteration normalisation)
+__global__ __launch_bounds__(kBV) void k_scale(int nb, double* __restrict__ x,
+                                               const double* __restrict__ y,
+                                               const double* __restrict__ sums) {
+  const int brick = block_brick();
+  if (brick >= nb) return;
+  const int g = brick * kBV + threadIdx.x;
+  const double n2 = sums[0];
+  x[g] = n2 > 0.0 ? y[g] / sqrt(n2) : 0.0;
+}
+
+}  // namespace
+
+void launch_block_max(const LaunchCfg& L, const int* nbr, CoefSet<double> c,
+                      double* partials) {
+  k_block_max<<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, c, partials);
+}
+
+void launch_scale(const LaunchCfg& L, double* x, const double* y, const double* sums) {
+  k_scale<<<L.grid, kBV, 0, L.stream>>>(L.nb, x, y, sums);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void launch_tensor_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask,
+                         const double* fib, const double* scale, double sig_l, double sig_t,
+                         double h, double* tens, double* c64[6], float* c32[6]) {
+  const int64_t stride = (int64_t)(L.nb + 1) * kBV;
+  k_tensor<<<L.grid, kBV, 0, L.stream>>>(L.nb, mask, fib, scale, sig_l, sig_t, tens, stride);
+  CoefOut<double> o64;
+  CoefOut<float> o32;
+  for (int k = 0; k < 6; ++k) {
+    o64.c[k] = c64 ? c64[k] : nullptr;
+    o32.c[k] = c32 ? c32[k] : nullptr;
+  }
+  k_coefs<<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, mask, tens, stride, 1.0 / (h * h), o64, o32);
+}
+
+template <typename T>
+void launch_explicit(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v, const T* w,
+                     const T* jstim, T* vout, T* wout, T* tact, IonicT<T> ion, T dt, T theta,
+                     double tn, int* flags) {
+  k_explicit<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, vout, wout, tact, ion,
+                                              dt, theta, tn, flags);
+}
+
+template <typename T>
+void launch_ionic(const LaunchCfg& L, const T* v, const T* w, const T* jstim, T* vs, T* wout,
+                  IonicT<T> ion, T dt) {
+  k_ionic<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, v, w, jstim, vs, wout, ion, dt);
+}
+
+template <typename T>
+void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v, const T* w,
+                    const T* jstim, const T* dinv, T* x, T* wout, T* r, IonicT<T> ion, T dt,
+                    double* partials) {
+  k_be_init<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, dinv, x, wout, r, ion,
+                                             dt, partials);
+}
+
+template <typename T>
+void launch_spmv(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* r, const T* dinv,
+                 const T* pold, T* pnew, T* q, T c0, T c1, int first, const CGScalars* cg,
+                 double* partials) {
+  k_spmv<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, c, r, dinv, pold, pnew, q, c0, c1, first,
+                                          cg, partials);
+}
+
+template <typename T>
+void launch_cg_update(const LaunchCfg& L, T* x, T* r, const T* p, const T* q, const T* dinv,
+                      const CGScalars* cg, double* partials) {
+  k_cg_update<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, x, r, p, q, dinv, cg, partials);
+}
+
+void launch_reduce(hipStream_t s, RedOp op, const double* partials, int nparts, int K,
+                   CGScalars* cg, double* out) {
+  k_reduce<<<1, kRedThreads, 0, s>>>(static_cast<int>(op), partials, nparts, K, cg, out, 0.0, 0);
+}
+
+void launch_reduce_init(hipStream_t s, RedOp op, const double* partials, int nparts, int K,
+                        CGScalars* cg, double tol2, int maxit) {
+  k_reduce<<<1, kRedThreads, 0, s>>>(static_cast<int>(op), partials, nparts, K, cg, nullptr,
+                                     tol2, maxit);
+}
+
+template <typename T>
+void launch_activation(const LaunchCfg& L, const T* vold, const T* vnew, T* tact, T dt, T theta,
+                       double tn, int* flags) {
+  k_activation<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, vold, vnew, tact, dt, theta, tn, flags);
+}
+
+template <typename T>
+void launch_dinv(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1,
+                 const uint8_t* /*mask*/, T* dinv) {
+  k_dinv<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, c, c0, c1, dinv);
+}
+
+template <typename T>
+void launch_sum(const LaunchCfg& L, const T* x, double* partials) {
+  k_sum<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, x, partials);
+}
+
+template <typename T>
+void launch_stim_scatter(hipStream_t s, const int64_t* idx, const double* val, int n, T* jstim,
+                         double* qstep) {
+  k_stim_scatter<T><<<1, kRedThreads, 0, s>>>(idx, val, n, jstim, qstep);
+}
+
+void launch_q_accum(hipStream_t s, double* qacc, const double* qstep, double scale) {
+  k_q_accum<<<1, 64, 0, s>>>(qacc, qstep, scale);
+}
+
+template <typename T>
+void launch_resid64(const LaunchCfg& L, const int* nbr, CoefSet<double> ci, CoefSet<double> ck,
+                    const T* vs, const double* phi, const uint8_t* /*mask*/, double* r64,
+                    double* partials) {
+  k_resid64<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, ci, ck, vs, phi, r64, partials);
+}
+
+void launch_inner_init(const LaunchCfg& L, const double* r64, const uint8_t* mask,
+                       const double* sums, double inv_count, const float* dinv, float* x,
+                       float* r, double* partials) {
+  k_inner_init<<<L.grid, kBV, 0, L.stream>>>(L.nb, r64, mask, sums, inv_count, dinv, x, r,
+                                             partials);
+}
+
+void launch_phi_correct(const LaunchCfg& L, double* phi, const float* d, const uint8_t* mask,
+                        double* partials) {
+  k_phi_correct<<<L.grid, kBV, 0, L.stream>>>(L.nb, phi, d, mask, partials);
+}
+
+void launch_phi_shift(const LaunchCfg& L, double* phi, const uint8_t* mask, const double* sum,
+                      double inv_count) {
+  k_phi_shift<<<L.grid, kBV, 0, L.stream>>>(L.nb, phi, mask, sum, inv_count);
+}
+
+template <typename T>
+void launch_parabolic(const LaunchCfg& L, const int* nbr, CoefSet<T> ci, const T* vs,
+                      const double* phi, const T* vold, T* vout, T* tact, T dt, T theta,
+                      double tn, int* flags) {
+  k_parabolic<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, ci, vs, phi, vold, vout, tact, dt,
+                                               theta, tn, flags);
+}
+
+template <typename T>
+void launch_apply(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* x, T* y,
+                  double* partials) {
+  k_apply<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, c, x, y, partials);
+}
+
+#define EP_INST(T)                                                                             \
+  template void launch_explicit<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*,         \
+                                   const T*, const T*, T*, T*, T*, IonicT<T>, T, T, double,    \
+                                   int*);                                                      \
+  template void launch_ionic<T>(const LaunchCfg&, const T*, const T*, const T*, T*, T*,        \
+                                IonicT<T>, T);                                                 \
+  template void launch_be_init<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*,          \
+                                  const T*, const T*, const T*, T*, T*, T*, IonicT<T>, T,      \
+                                  double*);                                                    \
+  template void launch_spmv<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*, const T*,   \
+                               const T*, T*, T*, T, T, int, const CGScalars*, double*);        \
+  template void launch_cg_update<T>(const LaunchCfg&, T*, T*, const T*, const T*, const T*,    \
+                                    const CGScalars*, double*);                                \
+  template void launch_activation<T>(const LaunchCfg&, const T*, const T*, T*, T, T, double,   \
+                                     int*);                                                    \
+  template void launch_dinv<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T,                 \
+                               const uint8_t*, T*);                                            \
+  template void launch_sum<T>(const LaunchCfg&, const T*, double*);                            \
+  template void launch_stim_scatter<T>(hipStream_t, const int64_t*, const double*, int, T*,    \
+                                       double*);                                               \
+  template void launch_resid64<T>(const LaunchCfg&, const int*, CoefSet<double>,              \
+                                  CoefSet<double>, const T*, const double*, const uint8_t*,    \
+                                  double*, double*);                                           \
+  template void launch_parabolic<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*,        \
+                                    const double*, const T*, T*, T*, T, T, double, int*);      \
+  template void launch_apply<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*, T*,        \
+                                double*);                                                      \
+
+
+EP_INST(float)
+EP_INST(double)
+
+}  // namespace ep

@@ -1,0 +1,1112 @@
+// Host runtime of the voxel-EP library: grid object, brick map, device
+// buffers, stimulus bookkeeping, the time-step drivers (explicit, implicit
+// Euler PCG, bidomain with mixed-precision elliptic refinement) and the C ABI
+// declared in include/ep.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ep.h"
+#include "ep_internal.h"
+
+using namespace ep;
+
+namespace {
+
+constexpr double kInf = std::numeric_limits<double>::infinity();
+// Inner FP32 PCG of the elliptic refinement: relative reduction per outer step.
+constexpr double kInnerRtol = 1e-3;
+
+struct HostSync {          // pinned read-back block
+  CGScalars cg;
+  double sums[4];
+  double qacc;
+  int flags[4];
+};
+
+struct TimerPair {
+  hipEvent_t a, b;
+};
+
+// kernel kinds that can be timed (ep_kernel_time ids)
+enum { KT_STENCIL = 0, KT_UPDATE = 1, KT_PARABOLIC = 2, KT_RESID = 3, kTimers = 4 };
+
+}  // namespace
+
+struct ep_grid_s {
+  // description
+  int n[3] = {0, 0, 0};
+  double h = 0, dt = 0, theta = 0.5;
+  ep_model model = EP_MONO;
+  ep_prec prec = EP_F64;
+  ep_diff diff = EP_DIFF_EXPLICIT;
+  ep_ionic ionic{};
+  double pcg_rtol = 1e-6, ell_rtol = 1e-8;
+  int pcg_maxit = 50, ell_max_outer = 8, ell_inner_maxit = 2000;
+  std::vector<ep_stim> stims;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+
+  // layout
+  int nbx = 0, nby = 0, nbz = 0, nb = 0;
+  std::vector<int> brick_id;   // nbx*nby*nbz -> id or -1
+  std::vector<int> brick_pos;  // id -> (bx, by, bz)
+  std::vector<uint8_t> hmask;  // (nb+1)*512 brick layout
+  int64_t n_tissue = 0;
+  int64_t nvox = 0;            // (nb+1)*512
+  LaunchCfg L{};
+  int grid = 0;
+
+  // device
+  std::vector<void*> allocs;
+  int64_t dev_bytes = 0;
+  int* d_nbr = nullptr;
+  uint8_t* d_mask = nullptr;
+  void* d_v[2] = {nullptr, nullptr};
+  void* d_w[2] = {nullptr, nullptr};
+  void* d_tact = nullptr;
+  void* d_jstim = nullptr;
+  void* d_c[6] = {};          // monodomain D / intracellular, state precision
+  double* d_ci64[6] = {};     // bidomain: A_i in FP64
+  double* d_ck64[6] = {};     // bidomain: A_i + A_e in FP64
+  float* d_ck32[6] = {};      // bidomain: A_i + A_e in FP32
+  void* d_r = nullptr;        // PCG vectors (state precision)
+  void* d_p[2] = {nullptr, nullptr};
+  void* d_q = nullptr;
+  void* d_dinv = nullptr;
+  void* d_vs = nullptr;       // bidomain v*
+  double* d_phi = nullptr;
+  double* d_r64 = nullptr;
+  float* d_x32 = nullptr;
+  float* d_r32 = nullptr;
+  float* d_p32[2] = {nullptr, nullptr};
+  float* d_q32 = nullptr;
+  float* d_dinvk = nullptr;
+  double* d_partials = nullptr;
+  CGScalars* d_cg = nullptr;
+  int* d_flags = nullptr;
+  double* d_sums = nullptr;    // 8 doubles
+  double* d_qacc = nullptr;
+  double* d_qstep = nullptr;
+  int64_t* d_stim_idx = nullptr;
+  double* d_stim_val = nullptr;
+  HostSync* hs = nullptr;      // pinned
+
+  // stimulus bookkeeping
+  std::vector<int64_t> stim_u;                 // unique stimulated voxels (global index)
+  std::vector<std::vector<int32_t>> stim_cov;  // per stimulus: positions in stim_u
+  std::vector<double> stim_vals;
+  std::vector<char> stim_active;
+  bool stim_built = false;
+
+  // state
+  int cur = 0;
+  int64_t step = 0;
+  bool has_cond = false;
+  bool nonfinite = false;
+  int last_iters = 4;
+  int last_inner = 50;
+  std::string err;
+
+  // timing
+  bool timing = false;
+  size_t tused[kTimers] = {};
+  std::vector<TimerPair> tk[kTimers];
+  double tms[kTimers] = {};
+  int64_t tcount[kTimers] = {};
+};
+
+namespace {
+
+ep_status fail(ep_grid g, ep_status s, const std::string& msg) {
+  if (g) g->err = msg;
+  return s;
+}
+
+#define HIPCHK(g, expr)                                                            \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail((g), EP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t elem_size(ep_prec p) { return p == EP_F64 ? sizeof(double) : sizeof(float); }
+
+template <typename P>
+ep_status dalloc(ep_grid g, P** out, size_t bytes) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(g, EP_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  e = hipMemsetAsync(p, 0, bytes, g->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(p);
+    return fail(g, EP_ERR_HIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
+  }
+  g->allocs.push_back(p);
+  g->dev_bytes += static_cast<int64_t>(bytes);
+  *out = static_cast<P*>(p);
+  return EP_OK;
+}
+
+#define TRY(expr)                     \
+  do {                                \
+    ep_status s_ = (expr);            \
+    if (s_ != EP_OK) return s_;       \
+  } while (0)
+
+inline int64_t box_index(const ep_grid g, int x, int y, int z) {
+  return (static_cast<int64_t>(x) * g->n[1] + y) * g->n[2] + z;
+}
+
+// global (brick-layout) index of box voxel (x, y, z), or -1 if its brick is absent
+inline int64_t brick_index(const ep_grid g, int x, int y, int z) {
+  const int id = g->brick_id[(static_cast<int64_t>(x >> 3) * g->nby + (y >> 3)) * g->nbz + (z >> 3)];
+  if (id < 0) return -1;
+  return static_cast<int64_t>(id) * kBV + (((x & 7) * 8 + (y & 7)) * 8 + (z & 7));
+}
+
+template <typename T>
+CoefSet<T> coefs(const ep_grid g) {
+  CoefSet<T> c;
+  for (int k = 0; k < 6; ++k) c.c[k] = static_cast<const T*>(g->d_c[k]);
+  return c;
+}
+
+CoefSet<double> cset64(double* const a[6]) {
+  CoefSet<double> c;
+  for (int k = 0; k < 6; ++k) c.c[k] = a[k];
+  return c;
+}
+
+CoefSet<float> cset32(float* const a[6]) {
+  CoefSet<float> c;
+  for (int k = 0; k < 6; ++k) c.c[k] = a[k];
+  return c;
+}
+
+template <typename T>
+IonicT<T> ionic_t(const ep_grid g) {
+  IonicT<T> p;
+  p.inv_tau_in = static_cast<T>(1.0 / g->ionic.tau_in);
+  p.inv_tau_out = static_cast<T>(1.0 / g->ionic.tau_out);
+  p.inv_tau_open = static_cast<T>(1.0 / g->ionic.tau_open);
+  p.inv_tau_close = static_cast<T>(1.0 / g->ionic.tau_close);
+  p.v_gate = static_cast<T>(g->ionic.v_gate);
+  p.exc = static_cast<T>(g->ionic.exc);
+  return p;
+}
+
+// ---- timing ---------------------------------------------------------------
+TimerPair* timer_begin(ep_grid g, int id) {
+  if (!g->timing) return nullptr;
+  if (g->tused[id] == g->tk[id].size()) {
+    TimerPair tp;
+    if (hipEventCreate(&tp.a) != hipSuccess || hipEventCreate(&tp.b) != hipSuccess) return nullptr;
+    g->tk[id].push_back(tp);
+  }
+  TimerPair* tp = &g->tk[id][g->tused[id]++];
+  (void)hipEventRecord(tp->a, g->stream);
+  return tp;
+}
+
+void timer_end(ep_grid g, TimerPair* tp) {
+  if (tp) (void)hipEventRecord(tp->b, g->stream);
+}
+
+void timer_collect(ep_grid g) {
+  for (int id = 0; id < kTimers; ++id) {
+    for (size_t i = 0; i < g->tused[id]; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, g->tk[id][i].a, g->tk[id][i].b) == hipSuccess) {
+        g->tms[id] += ms;
+        g->tcount[id] += 1;
+      }
+    }
+    g->tused[id] = 0;
+  }
+}
+
+// ---- stimulus -------------------------------------------------------------
+ep_status build_stimuli(ep_grid g) {
+  std::vector<int64_t> all;
+  std::vector<std::vector<int64_t>> per(g->stims.size());
+  for (size_t k = 0; k < g->stims.size(); ++k) {
+    const ep_stim& s = g->stims[k];
+    for (int x = std::max(0, s.lo[0]); x < std::min(g->n[0], s.hi[0]); ++x)
+      for (int y = std::max(0, s.lo[1]); y < std::min(g->n[1], s.hi[1]); ++y)
+        for (int z = std::max(0, s.lo[2]); z < std::min(g->n[2], s.hi[2]); ++z) {
+          const int64_t gi = brick_index(g, x, y, z);
+          if (gi < 0 || !g->hmask[gi]) continue;
+          if (s.radius > 0.0) {
+            const double dx = (x + 0.5) * g->h - s.center[0];
+            const double dy = (y + 0.5) * g->h - s.center[1];
+            const double dz = (z + 0.5) * g->h - s.center[2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (!(r2 <= s.radius * s.radius)) continue;
+          }
+          per[k].push_back(gi);
+          all.push_back(gi);
+        }
+  }
+  std::sort(all.begin(), all.end());
+  all.erase(std::unique(all.begin(), all.end()), all.end());
+  g->stim_u = all;
+  g->stim_cov.assign(g->stims.size(), {});
+  for (size_t k = 0; k < per.size(); ++k)
+    for (int64_t gi : per[k])
+      g->stim_cov[k].push_back(static_cast<int32_t>(
+          std::lower_bound(all.begin(), all.end(), gi) - all.begin()));
+  g->stim_vals.assign(all.size(), 0.0);
+  g->stim_active.assign(g->stims.size(), 0);
+  if (!all.empty()) {
+    TRY(dalloc(g, &g->d_stim_idx, all.size() * sizeof(int64_t)));
+    TRY(dalloc(g, &g->d_stim_val, all.size() * sizeof(double)));
+    HIPCHK(g, hipMemcpyAsync(g->d_stim_idx, all.data(), all.size() * sizeof(int64_t),
+                             hipMemcpyHostToDevice, g->stream));
+  }
+  g->stim_built = false;
+  return EP_OK;
+}
+
+// Refresh the stimulus current field for step `step`; returns the field
+// pointer, or nullptr when no stimulus is active.
+template <typename T>
+ep_status update_stimulus(ep_grid g, int64_t step, const T** jstim) {
+  *jstim = nullptr;
+  if (g->stim_u.empty()) return EP_OK;
+  const double tn = static_cast<double>(step) * g->dt;
+  bool any = false, changed = !g->stim_built;
+  for (size_t k = 0; k < g->stims.size(); ++k) {
+    const char a = (g->stims[k].t_on <= tn && tn < g->stims[k].t_off) ? 1 : 0;
+    any = any || a;
+    if (a != g->stim_active[k]) changed = true;
+    g->stim_active[k] = a;
+  }
+  if (changed) {
+    std::fill(g->stim_vals.begin(), g->stim_vals.end(), 0.0);
+    for (size_t k = 0; k < g->stims.size(); ++k)
+      if (g->stim_active[k])
+        for (int32_t u : g->stim_cov[k]) g->stim_vals[u] += g->stims[k].amp;
+    HIPCHK(g, hipMemcpyAsync(g->d_stim_val, g->stim_vals.data(),
+                             g->stim_vals.size() * sizeof(double), hipMemcpyHostToDevice,
+                             g->stream));
+    // the copy reads pageable host memory; keep it alive until it has run
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    launch_stim_scatter<T>(g->stream, g->d_stim_idx, g->d_stim_val,
+                           static_cast<int>(g->stim_u.size()), static_cast<T*>(g->d_jstim),
+                           g->d_qstep);
+    g->stim_built = true;
+  }
+  if (any) {
+    launch_q_accum(g->stream, g->d_qacc, g->d_qstep, g->dt * g->h * g->h * g->h);
+    *jstim = static_cast<const T*>(g->d_jstim);
+  }
+  return EP_OK;
+}
+
+// ---- one CG solve (device-resident scalars; host polls `done` in chunks) ----
+template <typename T>
+ep_status pcg_loop(ep_grid g, CoefSet<T> c, T* x, T* r, T* p0, T* p1, T* q, const T* dinv,
+                   T c0, T c1, int maxit, int* chunk_hint, int* iters, bool* failed) {
+  const int G = g->grid;
+  T* p[2] = {p0, p1};
+  int pa = 0;
+  bool first = true;
+  int enq = 0;
+  int chunk = std::max(1, *chunk_hint);
+  for (;;) {
+    for (int i = 0; i < chunk; ++i) {
+      TimerPair* t0 = timer_begin(g, KT_STENCIL);
+      launch_spmv<T>(g->L, g->d_nbr, c, r, dinv, p[pa], p[1 - pa], q, c0, c1, first ? 1 : 0,
+                     g->d_cg, g->d_partials);
+      timer_end(g, t0);
+      launch_reduce(g->stream, RED_ALPHA, g->d_partials, G, 1, g->d_cg, nullptr);
+      TimerPair* t1 = timer_begin(g, KT_UPDATE);
+      launch_cg_update<T>(g->L, x, r, p[1 - pa], q, dinv, g->d_cg, g->d_partials);
+      timer_end(g, t1);
+      launch_reduce(g->stream, RED_BETA, g->d_partials, G, 2, g->d_cg, nullptr);
+      pa = 1 - pa;
+      first = false;
+    }
+    enq += chunk;
+    HIPCHK(g, hipMemcpyAsync(&g->hs->cg, g->d_cg, sizeof(CGScalars), hipMemcpyDeviceToHost,
+                             g->stream));
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    if (g->hs->cg.done || enq > maxit) break;
+    chunk = std::min(4, std::max(1, maxit + 1 - enq));
+  }
+  *iters = g->hs->cg.it;
+  *failed = g->hs->cg.fail != 0 || !g->hs->cg.done;
+  *chunk_hint = std::max(1, g->hs->cg.it);
+  return EP_OK;
+}
+
+// ---- step drivers -----------------------------------------------------------
+template <typename T>
+ep_status step_explicit(ep_grid g, const T* jstim) {
+  const int c = g->cur, n = 1 - c;
+  TimerPair* t0 = timer_begin(g, KT_STENCIL);
+  launch_explicit<T>(g->L, g->d_nbr, coefs<T>(g), static_cast<const T*>(g->d_v[c]),
+                     static_cast<const T*>(g->d_w[c]), jstim, static_cast<T*>(g->d_v[n]),
+                     static_cast<T*>(g->d_w[n]), static_cast<T*>(g->d_tact), ionic_t<T>(g),
+                     static_cast<T>(g->dt), static_cast<T>(g->theta),
+                     static_cast<double>(g->step) * g->dt, g->d_flags);
+  timer_end(g, t0);
+  return EP_OK;
+}
+
+template <typename T>
+ep_status step_be(ep_grid g, const T* jstim, ep_step_info* acc) {
+  const int c = g->cur, n = 1 - c;
+  T* x = static_cast<T*>(g->d_v[n]);
+  T* r = static_cast<T*>(g->d_r);
+  const T* dinv = static_cast<const T*>(g->d_dinv);
+  launch_be_init<T>(g->L, g->d_nbr, coefs<T>(g), static_cast<const T*>(g->d_v[c]),
+                    static_cast<const T*>(g->d_w[c]), jstim, dinv, x,
+                    static_cast<T*>(g->d_w[n]), r, ionic_t<T>(g), static_cast<T>(g->dt),
+                    g->d_partials);
+  launch_reduce_init(g->stream, RED_BE_INIT, g->d_partials, g->grid, 3, g->d_cg,
+                     g->pcg_rtol * g->pcg_rtol, g->pcg_maxit);
+  int iters = 0;
+  bool failed = false;
+  TRY(pcg_loop<T>(g, coefs<T>(g), x, r, static_cast<T*>(g->d_p[0]), static_cast<T*>(g->d_p[1]),
+                  static_cast<T*>(g->d_q), dinv, T(1), static_cast<T>(-g->dt), g->pcg_maxit,
+                  &g->last_iters, &iters, &failed));
+  launch_activation<T>(g->L, static_cast<const T*>(g->d_v[c]), x, static_cast<T*>(g->d_tact),
+                       static_cast<T>(g->dt), static_cast<T>(g->theta),
+                       static_cast<double>(g->step) * g->dt, g->d_flags);
+  acc->cg_iters += iters;
+  acc->cg_max = std::max(acc->cg_max, iters);
+  if (g->hs->cg.bb > 0) acc->relres = std::sqrt(g->hs->cg.rr / g->hs->cg.bb);
+  if (failed) g->hs->flags[1] = 1;
+  return EP_OK;
+}
+
+// Mixed-precision elliptic solve for phi given the source potential vsrc
+// (FP64 refinement around FP32 Jacobi-PCG inner solves).
+template <typename T>
+ep_status elliptic(ep_grid g, const T* vsrc, double rtol, int max_outer, ep_solve_info* out) {
+  const int G = g->grid;
+  const double inv_count = 1.0 / static_cast<double>(g->n_tissue);
+  int outer = 0;
+  int64_t inner_total = 0;
+  double relres = 0.0;
+  bool corrected = false;
+  bool ok = false;
+  for (;;) {
+    TimerPair* tr = timer_begin(g, KT_RESID);
+    launch_resid64<T>(g->L, g->d_nbr, cset64(g->d_ci64), cset64(g->d_ck64), vsrc, g->d_phi,
+                      g->d_mask, g->d_r64, g->d_partials);
+    timer_end(g, tr);
+    launch_reduce(g->stream, RED_SUM, g->d_partials, G, 3, g->d_cg, g->d_sums);
+    HIPCHK(g, hipMemcpyAsync(g->hs->sums, g->d_sums, 3 * sizeof(double), hipMemcpyDeviceToHost,
+                             g->stream));
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    const double rr = g->hs->sums[0], bb = g->hs->sums[2];
+    if (bb == 0.0) {   // zero source: phi = 0 in the gauge
+      HIPCHK(g, hipMemsetAsync(g->d_phi, 0, static_cast<size_t>(g->nvox) * sizeof(double),
+                               g->stream));
+      relres = 0.0;
+      corrected = false;
+      ok = true;
+      break;
+    }
+    relres = std::sqrt(rr / bb);
+    if (relres <= rtol) { ok = true; break; }
+    if (!std::isfinite(relres) || outer >= max_outer) break;
+    launch_inner_init(g->L, g->d_r64, g->d_mask, g->d_sums, inv_count, g->d_dinvk, g->d_x32,
+                      g->d_r32, g->d_partials);
+    launch_reduce_init(g->stream, RED_INNER_INIT, g->d_partials, G, 2, g->d_cg,
+                       kInnerRtol * kInnerRtol, g->ell_inner_maxit);
+    int iters = 0;
+    bool failed = false;
+    TRY(pcg_loop<float>(g, cset32(g->d_ck32), g->d_x32, g->d_r32, g->d_p32[0], g->d_p32[1],
+                        g->d_q32, g->d_dinvk, 0.0f, -1.0f, g->ell_inner_maxit, &g->last_inner,
+                        &iters, &failed));
+    inner_total += iters;
+    launch_phi_correct(g->L, g->d_phi, g->d_x32, g->d_mask, g->d_partials);
+    launch_reduce(g->stream, RED_SUM, g->d_partials, G, 1, g->d_cg, g->d_sums + 4);
+    corrected = true;
+    ++outer;
+  }
+  if (corrected) launch_phi_shift(g->L, g->d_phi, g->d_mask, g->d_sums + 4, inv_count);
+  if (out) {
+    out->outer = outer;
+    out->inner_iters = inner_total;
+    out->relres = relres;
+  }
+  return ok ? EP_OK : EP_ERR_NOCONV;
+}
+
+template <typename T>
+ep_status step_bido(ep_grid g, const T* jstim, ep_step_info* acc) {
+  const int c = g->cur, n = 1 - c;
+  T* vs = static_cast<T*>(g->d_vs);
+  launch_ionic<T>(g->L, static_cast<const T*>(g->d_v[c]), static_cast<const T*>(g->d_w[c]), jstim,
+                  vs, static_cast<T*>(g->d_w[n]), ionic_t<T>(g), static_cast<T>(g->dt));
+  ep_solve_info si{};
+  ep_status s = elliptic<T>(g, vs, g->ell_rtol, g->ell_max_outer, &si);
+  if (s == EP_ERR_NOCONV) g->hs->flags[1] = 1;
+  else if (s != EP_OK) return s;
+  acc->cg_iters += si.inner_iters;
+  acc->cg_max = std::max<int32_t>(acc->cg_max, static_cast<int32_t>(si.inner_iters));
+  acc->ell_outer += si.outer;
+  acc->relres = si.relres;
+  TimerPair* t0 = timer_begin(g, KT_PARABOLIC);
+  launch_parabolic<T>(g->L, g->d_nbr, coefs<T>(g), vs, g->d_phi,
+                      static_cast<const T*>(g->d_v[c]), static_cast<T*>(g->d_v[n]),
+                      static_cast<T*>(g->d_tact), static_cast<T>(g->dt),
+                      static_cast<T>(g->theta), static_cast<double>(g->step) * g->dt,
+                      g->d_flags);
+  timer_end(g, t0);
+  return EP_OK;
+}
+
+template <typename T>
+ep_status run_steps(ep_grid g, int32_t nsteps, ep_step_info* info) {
+  ep_step_info acc{};
+  HIPCHK(g, hipMemsetAsync(g->d_qacc, 0, sizeof(double), g->stream));
+  g->hs->flags[1] = 0;
+  for (int32_t s = 0; s < nsteps; ++s) {
+    const T* jstim = nullptr;
+    TRY(update_stimulus<T>(g, g->step, &jstim));
+    if (g->model == EP_BIDO) {
+      TRY(step_bido<T>(g, jstim, &acc));
+    } else if (g->diff == EP_DIFF_BE_PCG) {
+      TRY(step_be<T>(g, jstim, &acc));
+    } else {
+      TRY(step_explicit<T>(g, jstim));
+    }
+    g->cur = 1 - g->cur;
+    g->step += 1;
+  }
+  const int noconv = g->hs->flags[1];
+  launch_sum<T>(g->L, static_cast<const T*>(g->d_v[g->cur]), g->d_partials);
+  launch_reduce(g->stream, RED_SUM, g->d_partials, g->grid, 1, g->d_cg, g->d_sums + 6);
+  HIPCHK(g, hipGetLastError());
+  HIPCHK(g, hipMemcpyAsync(g->hs->sums + 3, g->d_sums + 6, sizeof(double), hipMemcpyDeviceToHost,
+                           g->stream));
+  HIPCHK(g, hipMemcpyAsync(&g->hs->qacc, g->d_qacc, sizeof(double), hipMemcpyDeviceToHost,
+                           g->stream));
+  HIPCHK(g, hipMemcpyAsync(g->hs->flags, g->d_flags, sizeof(int), hipMemcpyDeviceToHost,
+                           g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  timer_collect(g);
+  const double h3 = g->h * g->h * g->h;
+  acc.steps = nsteps;
+  acc.step = g->step;
+  acc.t = static_cast<double>(g->step) * g->dt;
+  acc.q_stim = g->hs->qacc;
+  acc.mass = h3 * g->hs->sums[3];
+  if (info) *info = acc;
+  if (g->hs->flags[0]) g->nonfinite = true;
+  if (g->nonfinite) return fail(g, EP_ERR_NONFINITE, "non-finite potential");
+  if (noconv) return fail(g, EP_ERR_NOCONV, "a linear solve hit its iteration limit");
+  return EP_OK;
+}
+
+// dt * lambda_max(-A) < 2: accept on the Gershgorin bound, else estimate
+// lambda_max by 200 power iterations and accept below 2 / 1.02.
+ep_status check_explicit_stability(ep_grid g, double* const c64[6]) {
+  const int G = g->grid;
+  launch_block_max(g->L, g->d_nbr, cset64(c64), g->d_partials);
+  std::vector<double> part(G);
+  HIPCHK(g, hipMemcpyAsync(part.data(), g->d_partials, G * sizeof(double), hipMemcpyDeviceToHost,
+                           g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  const double gersh = *std::max_element(part.begin(), part.end());
+  if (g->dt * gersh < 2.0) return EP_OK;
+  double *x = nullptr, *y = nullptr;
+  const size_t bytes = static_cast<size_t>(g->nvox) * sizeof(double);
+  TRY(dalloc(g, &x, bytes));
+  TRY(dalloc(g, &y, bytes));
+  std::vector<double> hx(g->nvox, 0.0);
+  uint64_t st = 0x9E3779B97F4A7C15ull;
+  for (int64_t i = 0; i < g->nb * (int64_t)kBV; ++i) {
+    st ^= st << 13; st ^= st >> 7; st ^= st << 17;
+    hx[i] = g->hmask[i] ? (static_cast<double>(st >> 11) * 0x1.0p-53 - 0.5) : 0.0;
+  }
+  HIPCHK(g, hipMemcpyAsync(x, hx.data(), bytes, hipMemcpyHostToDevice, g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  double lam = 0.0;
+  for (int it = 0; it < 200; ++it) {
+    launch_apply<double>(g->L, g->d_nbr, cset64(c64), x, y, g->d_partials);
+    launch_reduce(g->stream, RED_SUM, g->d_partials, G, 2, g->d_cg, g->d_sums);
+    launch_scale(g->L, x, y, g->d_sums);
+  }
+  HIPCHK(g, hipMemcpyAsync(g->hs->sums, g->d_sums, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                           g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  // x was unit before the last apply: lambda ~ |x . A x|
+  lam = std::fabs(g->hs->sums[1]);
+  if (g->dt * lam * 1.02 >= 2.0) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "explicit diffusion unstable: dt*lambda_max(-A) ~ %.3f >= 2",
+             g->dt * lam);
+    return fail(g, EP_ERR_ARG, buf);
+  }
+  return EP_OK;
+}
+
+// 6-connected components of the tissue (host BFS), for the bidomain gauge
+int64_t tissue_components(const std::vector<uint8_t>& m, const int n[3]) {
+  const int64_t N = static_cast<int64_t>(n[0]) * n[1] * n[2];
+  std::vector<uint8_t> seen(N, 0);
+  std::vector<int64_t> stack;
+  int64_t comps = 0;
+  for (int64_t s = 0; s < N; ++s) {
+    if (!m[s] || seen[s]) continue;
+    ++comps;
+    seen[s] = 1;
+    stack.push_back(s);
+    while (!stack.empty()) {
+      const int64_t p = stack.back();
+      stack.pop_back();
+      const int z = static_cast<int>(p % n[2]);
+      const int y = static_cast<int>((p / n[2]) % n[1]);
+      const int x = static_cast<int>(p / (static_cast<int64_t>(n[1]) * n[2]));
+      const int c[3] = {x, y, z};
+      for (int d = 0; d < 3; ++d)
+        for (int sgn = -1; sgn <= 1; sgn += 2) {
+          int q3[3] = {c[0], c[1], c[2]};
+          q3[d] += sgn;
+          if (q3[d] < 0 || q3[d] >= n[d]) continue;
+          const int64_t q = (static_cast<int64_t>(q3[0]) * n[1] + q3[1]) * n[2] + q3[2];
+          if (m[q] && !seen[q]) { seen[q] = 1; stack.push_back(q); }
+        }
+    }
+  }
+  return comps;
+}
+
+ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
+  for (int k = 0; k < 3; ++k)
+    if (d->n[k] < 1 || d->n[k] > 4096) return fail(g, EP_ERR_ARG, "n must be in [1, 4096]");
+  if (!(d->h > 0) || !std::isfinite(d->h)) return fail(g, EP_ERR_ARG, "h must be > 0");
+  if (!(d->dt > 0) || !std::isfinite(d->dt)) return fail(g, EP_ERR_ARG, "dt must be > 0");
+  if (d->model != EP_MONO && d->model != EP_BIDO) return fail(g, EP_ERR_ARG, "bad model");
+  if (d->prec != EP_F64 && d->prec != EP_F32) return fail(g, EP_ERR_ARG, "bad precision");
+  if (d->diff != EP_DIFF_EXPLICIT && d->diff != EP_DIFF_BE_PCG)
+    return fail(g, EP_ERR_ARG, "bad diffusion scheme");
+  if (d->model == EP_BIDO && d->diff != EP_DIFF_EXPLICIT)
+    return fail(g, EP_ERR_UNSUPPORTED, "bidomain parabolic part is explicit only");
+  if (d->n_stim < 0 || (d->n_stim > 0 && !d->stim)) return fail(g, EP_ERR_ARG, "bad stimuli");
+  const ep_ionic& io = d->ionic;
+  if (!(io.tau_in > 0) || !(io.tau_out > 0) || !(io.tau_open > 0) || !(io.tau_close > 0) ||
+      !std::isfinite(io.v_gate) || !std::isfinite(io.exc) || io.exc < 0)
+    return fail(g, EP_ERR_ARG, "ionic time constants must be > 0 and exc >= 0");
+  if (!(d->act_threshold > 0 && d->act_threshold < 1))
+    return fail(g, EP_ERR_ARG, "act_threshold must be in (0, 1)");
+  if (d->diff == EP_DIFF_BE_PCG && (!(d->pcg_rtol > 0) || d->pcg_maxit < 1))
+    return fail(g, EP_ERR_ARG, "pcg_rtol > 0 and pcg_maxit >= 1 required");
+  if (d->model == EP_BIDO &&
+      (!(d->ell_rtol > 0) || d->ell_max_outer < 1 || d->ell_inner_maxit < 1))
+    return fail(g, EP_ERR_ARG, "ell_rtol > 0, ell_max_outer >= 1, ell_inner_maxit >= 1 required");
+  for (int k = 0; k < d->n_stim; ++k) {
+    const ep_stim& s = d->stim[k];
+    if (!std::isfinite(s.amp) || !std::isfinite(s.radius) || std::isnan(s.t_on) ||
+        std::isnan(s.t_off))
+      return fail(g, EP_ERR_ARG, "non-finite stimulus field");
+  }
+
+  std::copy(d->n, d->n + 3, g->n);
+  g->h = d->h;
+  g->dt = d->dt;
+  g->model = d->model;
+  g->prec = d->prec;
+  g->diff = d->diff;
+  g->ionic = d->ionic;
+  g->theta = d->act_threshold;
+  g->pcg_rtol = d->pcg_rtol;
+  g->pcg_maxit = d->pcg_maxit;
+  g->ell_rtol = d->ell_rtol;
+  g->ell_max_outer = d->ell_max_outer;
+  g->ell_inner_maxit = d->ell_inner_maxit;
+  g->stims.assign(d->stim, d->stim + d->n_stim);
+
+  if (d->stream) {
+    g->stream = static_cast<hipStream_t>(d->stream);
+  } else {
+    HIPCHK(g, hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+    g->own_stream = true;
+  }
+
+  // brick map
+  const int64_t N = static_cast<int64_t>(g->n[0]) * g->n[1] * g->n[2];
+  std::vector<uint8_t> boxmask(N, 1);
+  if (d->mask)
+    for (int64_t i = 0; i < N; ++i) boxmask[i] = d->mask[i] ? 1 : 0;
+  g->nbx = (g->n[0] + 7) / 8;
+  g->nby = (g->n[1] + 7) / 8;
+  g->nbz = (g->n[2] + 7) / 8;
+  const int64_t NB = static_cast<int64_t>(g->nbx) * g->nby * g->nbz;
+  g->brick_id.assign(NB, -1);
+  int64_t tissue = 0;
+  for (int x = 0; x < g->n[0]; ++x)
+    for (int y = 0; y < g->n[1]; ++y)
+      for (int z = 0; z < g->n[2]; ++z)
+        if (boxmask[box_index(g, x, y, z)]) {
+          ++tissue;
+          g->brick_id[(static_cast<int64_t>(x >> 3) * g->nby + (y >> 3)) * g->nbz + (z >> 3)] = 0;
+        }
+  if (tissue == 0) return fail(g, EP_ERR_ARG, "mask holds no tissue");
+  int nb = 0;
+  for (int64_t b = 0; b < NB; ++b)
+    if (g->brick_id[b] >= 0) {
+      g->brick_id[b] = nb++;
+      g->brick_pos.push_back(static_cast<int>(b / (static_cast<int64_t>(g->nby) * g->nbz)));
+      g->brick_pos.push_back(static_cast<int>((b / g->nbz) % g->nby));
+      g->brick_pos.push_back(static_cast<int>(b % g->nbz));
+    }
+  if (static_cast<int64_t>(nb + 1) * kBV >= (int64_t(1) << 31))
+    return fail(g, EP_ERR_ARG, "grid too large for 32-bit brick indexing");
+  g->nb = nb;
+  g->n_tissue = tissue;
+  g->nvox = static_cast<int64_t>(nb + 1) * kBV;
+  g->grid = grid_for(nb);
+  g->L.nb = nb;
+  g->L.grid = g->grid;
+  g->L.stream = g->stream;
+  if (g->model == EP_BIDO && tissue_components(boxmask, g->n) != 1)
+    return fail(g, EP_ERR_ARG, "bidomain tissue must be one face-connected component");
+
+  std::vector<int> hnbr(static_cast<size_t>(nb + 1) * kNbr, nb);
+  for (int id = 0; id < nb; ++id) {
+    const int bx = g->brick_pos[3 * id], by = g->brick_pos[3 * id + 1], bz = g->brick_pos[3 * id + 2];
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dz = -1; dz <= 1; ++dz) {
+          const int x = bx + dx, y = by + dy, z = bz + dz;
+          int v = nb;
+          if (x >= 0 && y >= 0 && z >= 0 && x < g->nbx && y < g->nby && z < g->nbz) {
+            const int id2 = g->brick_id[(static_cast<int64_t>(x) * g->nby + y) * g->nbz + z];
+            if (id2 >= 0) v = id2;
+          }
+          hnbr[static_cast<size_t>(id) * kNbr + (dx + 1) * 9 + (dy + 1) * 3 + (dz + 1)] = v;
+        }
+  }
+  g->hmask.assign(g->nvox, 0);
+  for (int x = 0; x < g->n[0]; ++x)
+    for (int y = 0; y < g->n[1]; ++y)
+      for (int z = 0; z < g->n[2]; ++z)
+        if (boxmask[box_index(g, x, y, z)]) g->hmask[brick_index(g, x, y, z)] = 1;
+
+  // device buffers
+  const size_t es = elem_size(g->prec);
+  const size_t vb = static_cast<size_t>(g->nvox) * es;
+  TRY(dalloc(g, &g->d_nbr, hnbr.size() * sizeof(int)));
+  TRY(dalloc(g, &g->d_mask, static_cast<size_t>(g->nvox)));
+  for (int k = 0; k < 2; ++k) {
+    TRY(dalloc(g, &g->d_v[k], vb));
+    TRY(dalloc(g, &g->d_w[k], vb));
+  }
+  TRY(dalloc(g, &g->d_tact, vb));
+  TRY(dalloc(g, &g->d_jstim, vb));
+  for (int k = 0; k < 6; ++k) TRY(dalloc(g, &g->d_c[k], vb));
+  TRY(dalloc(g, &g->d_partials, static_cast<size_t>(g->grid) * 4 * sizeof(double)));
+  TRY(dalloc(g, &g->d_cg, sizeof(CGScalars)));
+  TRY(dalloc(g, &g->d_flags, 4 * sizeof(int)));
+  TRY(dalloc(g, &g->d_sums, 8 * sizeof(double)));
+  TRY(dalloc(g, &g->d_qacc, sizeof(double)));
+  TRY(dalloc(g, &g->d_qstep, sizeof(double)));
+  TRY(dalloc(g, &g->d_phi, static_cast<size_t>(g->nvox) * sizeof(double)));
+  if (g->diff == EP_DIFF_BE_PCG) {
+    TRY(dalloc(g, &g->d_r, vb));
+    TRY(dalloc(g, &g->d_p[0], vb));
+    TRY(dalloc(g, &g->d_p[1], vb));
+    TRY(dalloc(g, &g->d_q, vb));
+    TRY(dalloc(g, &g->d_dinv, vb));
+  }
+  if (g->model == EP_BIDO) {
+    const size_t b64 = static_cast<size_t>(g->nvox) * sizeof(double);
+    const size_t b32 = static_cast<size_t>(g->nvox) * sizeof(float);
+    TRY(dalloc(g, &g->d_vs, vb));
+    TRY(dalloc(g, &g->d_r64, b64));
+    for (int k = 0; k < 6; ++k) {
+      TRY(dalloc(g, &g->d_ci64[k], b64));
+      TRY(dalloc(g, &g->d_ck64[k], b64));
+      TRY(dalloc(g, &g->d_ck32[k], b32));
+    }
+    TRY(dalloc(g, &g->d_x32, b32));
+    TRY(dalloc(g, &g->d_r32, b32));
+    TRY(dalloc(g, &g->d_p32[0], b32));
+    TRY(dalloc(g, &g->d_p32[1], b32));
+    TRY(dalloc(g, &g->d_q32, b32));
+    TRY(dalloc(g, &g->d_dinvk, b32));
+  }
+  {
+    void* p = nullptr;
+    HIPCHK(g, hipHostMalloc(&p, sizeof(HostSync), hipHostMallocDefault));
+    g->hs = static_cast<HostSync*>(p);
+    std::memset(g->hs, 0, sizeof(HostSync));
+  }
+  HIPCHK(g, hipMemcpyAsync(g->d_nbr, hnbr.data(), hnbr.size() * sizeof(int),
+                           hipMemcpyHostToDevice, g->stream));
+  HIPCHK(g, hipMemcpyAsync(g->d_mask, g->hmask.data(), g->hmask.size(), hipMemcpyHostToDevice,
+                           g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  TRY(build_stimuli(g));
+  // initial state: v = 0, w = 1 (tissue and non-tissue of active bricks), T_act = +inf
+  std::vector<double> zero(N, 0.0), inf(N, kInf);
+  TRY(ep_write_state(g, EP_V, zero.data(), N));
+  {
+    std::vector<double> one(N, 1.0);
+    TRY(ep_write_state(g, EP_W, one.data(), N));
+  }
+  TRY(ep_write_state(g, EP_TACT, inf.data(), N));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  return EP_OK;
+}
+
+template <typename T>
+ep_status write_field(ep_grid g, ep_field f, const double* in) {
+  const size_t es = (f == EP_PHIE) ? sizeof(double) : sizeof(T);
+  std::vector<unsigned char> buf(static_cast<size_t>(g->nvox) * es, 0);
+  T* bt = reinterpret_cast<T*>(buf.data());
+  double* bd = reinterpret_cast<double*>(buf.data());
+  const int64_t nreal = static_cast<int64_t>(g->nb) * kBV;
+  // defaults for non-tissue voxels of active bricks (the ghost brick stays 0)
+  for (int64_t i = 0; i < nreal; ++i) {
+    if (f == EP_W) bt[i] = T(1);
+    else if (f == EP_TACT) bt[i] = static_cast<T>(kInf);
+  }
+  for (int x = 0; x < g->n[0]; ++x)
+    for (int y = 0; y < g->n[1]; ++y)
+      for (int z = 0; z < g->n[2]; ++z) {
+        const int64_t gi = brick_index(g, x, y, z);
+        if (gi < 0 || !g->hmask[gi]) continue;
+        const double v = in[box_index(g, x, y, z)];
+        if (f == EP_PHIE) bd[gi] = v;
+        else bt[gi] = static_cast<T>(v);
+      }
+  void* dst = nullptr;
+  switch (f) {
+    case EP_V: dst = g->d_v[g->cur]; break;
+    case EP_W: dst = g->d_w[g->cur]; break;
+    case EP_PHIE: dst = g->d_phi; break;
+    case EP_TACT: dst = g->d_tact; break;
+  }
+  HIPCHK(g, hipMemcpyAsync(dst, buf.data(), buf.size(), hipMemcpyHostToDevice, g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  return EP_OK;
+}
+
+template <typename T>
+ep_status read_field(ep_grid g, ep_field f, double* out) {
+  const size_t es = (f == EP_PHIE) ? sizeof(double) : sizeof(T);
+  std::vector<unsigned char> buf(static_cast<size_t>(g->nvox) * es);
+  const void* src = nullptr;
+  switch (f) {
+    case EP_V: src = g->d_v[g->cur]; break;
+    case EP_W: src = g->d_w[g->cur]; break;
+    case EP_PHIE: src = g->d_phi; break;
+    case EP_TACT: src = g->d_tact; break;
+  }
+  HIPCHK(g, hipMemcpyAsync(buf.data(), src, buf.size(), hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  const T* bt = reinterpret_cast<const T*>(buf.data());
+  const double* bd = reinterpret_cast<const double*>(buf.data());
+  const double off = (f == EP_TACT) ? kInf : 0.0;
+  for (int x = 0; x < g->n[0]; ++x)
+    for (int y = 0; y < g->n[1]; ++y)
+      for (int z = 0; z < g->n[2]; ++z) {
+        const int64_t gi = brick_index(g, x, y, z);
+        double v = off;
+        if (gi >= 0 && g->hmask[gi]) v = (f == EP_PHIE) ? bd[gi] : static_cast<double>(bt[gi]);
+        out[box_index(g, x, y, z)] = v;
+      }
+  return EP_OK;
+}
+
+ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, double sl,
+                        double st, double sel, double set_) {
+  if (!fibre) return fail(g, EP_ERR_ARG, "fibre is NULL");
+  if (!(sl >= 0) || !(st >= 0) || !std::isfinite(sl) || !std::isfinite(st))
+    return fail(g, EP_ERR_ARG, "conductivities must be finite and >= 0");
+  if (g->model == EP_BIDO && (!(sel >= 0) || !(set_ >= 0) || !std::isfinite(sel) ||
+                              !std::isfinite(set_)))
+    return fail(g, EP_ERR_ARG, "extracellular conductivities must be finite and >= 0");
+  // fibres / scale to brick layout, validated on tissue
+  std::vector<double> hf(static_cast<size_t>(g->nvox) * 3, 0.0), hsc;
+  if (scale) hsc.assign(g->nvox, 0.0);
+  for (int x = 0; x < g->n[0]; ++x)
+    for (int y = 0; y < g->n[1]; ++y)
+      for (int z = 0; z < g->n[2]; ++z) {
+        const int64_t gi = brick_index(g, x, y, z);
+        if (gi < 0 || !g->hmask[gi]) continue;
+        const int64_t bi = box_index(g, x, y, z);
+        const double f0 = fibre[3 * bi], f1 = fibre[3 * bi + 1], f2 = fibre[3 * bi + 2];
+        const double nrm = std::sqrt(f0 * f0 + f1 * f1 + f2 * f2);
+        if (!(std::fabs(nrm - 1.0) <= 1e-6))
+          return fail(g, EP_ERR_ARG, "fibre is not a unit vector on a tissue voxel");
+        hf[3 * gi] = f0;
+        hf[3 * gi + 1] = f1;
+        hf[3 * gi + 2] = f2;
+        if (scale) {
+          const double s = scale[bi];
+          if (!(s > 0) || !std::isfinite(s))
+            return fail(g, EP_ERR_ARG, "scale must be finite and > 0 on tissue");
+          hsc[gi] = s;
+        }
+      }
+  double *dfib = nullptr, *dsc = nullptr, *tens = nullptr;
+  const size_t b64 = static_cast<size_t>(g->nvox) * sizeof(double);
+  hipError_t e = hipMalloc(&dfib, 3 * b64);
+  if (e == hipSuccess && scale) e = hipMalloc(&dsc, b64);
+  if (e == hipSuccess) e = hipMalloc(&tens, 6 * b64);
+  double* tmp64[6] = {};
+  const bool need64 = (g->prec == EP_F64) || g->model == EP_BIDO || g->diff == EP_DIFF_EXPLICIT;
+  if (e == hipSuccess && need64)
+    for (int k = 0; k < 6 && e == hipSuccess; ++k) e = hipMalloc(&tmp64[k], b64);
+  auto cleanup = [&]() {
+    (void)hipFree(dfib);
+    (void)hipFree(dsc);
+    (void)hipFree(tens);
+    for (int k = 0; k < 6; ++k) (void)hipFree(tmp64[k]);
+  };
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    cleanup();
+    return fail(g, EP_ERR_OOM, "temporary allocation for coefficient encoding failed");
+  }
+  ep_status rc = EP_OK;
+  do {
+    if (hipMemcpyAsync(dfib, hf.data(), 3 * b64, hipMemcpyHostToDevice, g->stream) != hipSuccess ||
+        (scale && hipMemcpyAsync(dsc, hsc.data(), b64, hipMemcpyHostToDevice, g->stream) != hipSuccess) ||
+        hipMemsetAsync(tens, 0, 6 * b64, g->stream) != hipSuccess) {
+      rc = fail(g, EP_ERR_HIP, "upload of fibres failed");
+      break;
+    }
+    // monodomain / intracellular set in state precision (+ FP64 twin for checks)
+    float* c32[6];
+    double* c64[6];
+    for (int k = 0; k < 6; ++k) {
+      c32[k] = static_cast<float*>(g->d_c[k]);
+      c64[k] = g->model == EP_BIDO ? g->d_ci64[k] : tmp64[k];
+    }
+    if (g->prec == EP_F64)
+      for (int k = 0; k < 6; ++k) c64[k] = static_cast<double*>(g->d_c[k]);
+    launch_tensor_coefs(g->L, g->d_nbr, g->d_mask, dfib, dsc, sl, st, g->h, tens,
+                        need64 ? c64 : nullptr, g->prec == EP_F32 ? c32 : nullptr);
+    if (g->model == EP_BIDO) {
+      if (g->prec == EP_F64) {
+        // FP64 state: d_c already holds A_i in FP64; copy it into the FP64 twin
+        for (int k = 0; k < 6; ++k)
+          (void)hipMemcpyAsync(g->d_ci64[k], g->d_c[k], b64, hipMemcpyDeviceToDevice, g->stream);
+      }
+      // A_i + A_e: both tensors share the fibre field and scale, and the
+      // operator is linear in the tensor, so the sum is the operator of
+      // D_i + D_e = s((sT_i + sT_e) I + ((sL_i - sT_i) + (sL_e - sT_e)) f f^T).
+      launch_tensor_coefs(g->L, g->d_nbr, g->d_mask, dfib, dsc, sl + sel, st + set_, g->h, tens,
+                          g->d_ck64, g->d_ck32);
+      launch_dinv<float>(g->L, g->d_nbr, cset32(g->d_ck32), 0.0f, -1.0f, g->d_mask, g->d_dinvk);
+    }
+    if (g->diff == EP_DIFF_BE_PCG) {
+      if (g->prec == EP_F64)
+        launch_dinv<double>(g->L, g->d_nbr, coefs<double>(g), 1.0, -g->dt, g->d_mask,
+                            static_cast<double*>(g->d_dinv));
+      else
+        launch_dinv<float>(g->L, g->d_nbr, coefs<float>(g), 1.0f, static_cast<float>(-g->dt),
+                           g->d_mask, static_cast<float*>(g->d_dinv));
+    }
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(g->stream) != hipSuccess) {
+      rc = fail(g, EP_ERR_HIP, "coefficient kernels failed");
+      break;
+    }
+    if (g->diff == EP_DIFF_EXPLICIT) {
+      double* const* cc = (g->prec == EP_F64) ? reinterpret_cast<double* const*>(g->d_c)
+                                              : (g->model == EP_BIDO ? g->d_ci64 : tmp64);
+      rc = check_explicit_stability(g, cc);
+    }
+  } while (false);
+  (void)hipStreamSynchronize(g->stream);
+  cleanup();
+  if (rc == EP_OK) g->has_cond = true;
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+EP_API ep_status ep_create_grid(const ep_grid_desc* d, ep_grid* out) {
+  if (!out) return EP_ERR_ARG;
+  *out = nullptr;
+  if (!d) return EP_ERR_ARG;
+  ep_grid g = new (std::nothrow) ep_grid_s();
+  if (!g) return EP_ERR_OOM;
+  ep_status s;
+  try {
+    s = create_impl(d, g);
+  } catch (const std::bad_alloc&) {
+    s = fail(g, EP_ERR_OOM, "host allocation failed");
+  } catch (...) {
+    s = fail(g, EP_ERR_HIP, "unexpected exception");
+  }
+  if (s != EP_OK) {
+    static thread_local std::string last;
+    last = g->err;
+    ep_destroy_grid(g);
+    return s;
+  }
+  *out = g;
+  return EP_OK;
+}
+
+EP_API ep_status ep_set_conductivity_fibres(ep_grid g, const double* fibre, const double* scale,
+                                            double sig_l, double sig_t, double sig_el,
+                                            double sig_et) {
+  if (!g) return EP_ERR_ARG;
+  try {
+    return set_cond_impl(g, fibre, scale, sig_l, sig_t, sig_el, sig_et);
+  } catch (const std::bad_alloc&) {
+    return fail(g, EP_ERR_OOM, "host allocation failed");
+  }
+}
+
+EP_API ep_status ep_step(ep_grid g, int32_t nsteps, ep_step_info* info) {
+  if (!g) return EP_ERR_ARG;
+  if (nsteps < 0) return fail(g, EP_ERR_ARG, "nsteps must be >= 0");
+  if (!g->has_cond) return fail(g, EP_ERR_STATE, "ep_set_conductivity_fibres not called");
+  if (g->nonfinite) return fail(g, EP_ERR_NONFINITE, "state is non-finite; write a new state");
+  try {
+    return g->prec == EP_F64 ? run_steps<double>(g, nsteps, info)
+                             : run_steps<float>(g, nsteps, info);
+  } catch (const std::bad_alloc&) {
+    return fail(g, EP_ERR_OOM, "host allocation failed");
+  }
+}
+
+EP_API ep_status ep_solve_elliptic(ep_grid g, double rel_tol, int32_t max_outer,
+                                   ep_solve_info* info) {
+  if (!g) return EP_ERR_ARG;
+  if (g->model != EP_BIDO) return fail(g, EP_ERR_UNSUPPORTED, "monodomain grid");
+  if (!g->has_cond) return fail(g, EP_ERR_STATE, "ep_set_conductivity_fibres not called");
+  if (!(rel_tol > 0) || max_outer < 1) return fail(g, EP_ERR_ARG, "rel_tol > 0, max_outer >= 1");
+  ep_status s = g->prec == EP_F64
+                    ? elliptic<double>(g, static_cast<const double*>(g->d_v[g->cur]), rel_tol,
+                                       max_outer, info)
+                    : elliptic<float>(g, static_cast<const float*>(g->d_v[g->cur]), rel_tol,
+                                      max_outer, info);
+  if (hipStreamSynchronize(g->stream) != hipSuccess)
+    return fail(g, EP_ERR_HIP, "stream synchronisation failed");
+  if (s == EP_ERR_NOCONV) return fail(g, s, "elliptic refinement did not converge");
+  return s;
+}
+
+EP_API ep_status ep_read_state(ep_grid g, ep_field f, double* host_out, size_t n) {
+  if (!g || !host_out) return EP_ERR_ARG;
+  if (f < EP_V || f > EP_TACT) return fail(g, EP_ERR_ARG, "bad field");
+  const size_t N = static_cast<size_t>(g->n[0]) * g->n[1] * g->n[2];
+  if (n < N) return fail(g, EP_ERR_ARG, "output buffer too small");
+  try {
+    return g->prec == EP_F64 ? read_field<double>(g, f, host_out) : read_field<float>(g, f, host_out);
+  } catch (const std::bad_alloc&) {
+    return fail(g, EP_ERR_OOM, "host allocation failed");
+  }
+}
+
+EP_API ep_status ep_write_state(ep_grid g, ep_field f, const double* host_in, size_t n) {
+  if (!g || !host_in) return EP_ERR_ARG;
+  if (f < EP_V || f > EP_TACT) return fail(g, EP_ERR_ARG, "bad field");
+  const size_t N = static_cast<size_t>(g->n[0]) * g->n[1] * g->n[2];
+  if (n < N) return fail(g, EP_ERR_ARG, "input buffer too small");
+  try {
+    ep_status s = g->prec == EP_F64 ? write_field<double>(g, f, host_in)
+                                    : write_field<float>(g, f, host_in);
+    if (s == EP_OK) {
+      g->nonfinite = false;
+      HIPCHK(g, hipMemsetAsync(g->d_flags, 0, 4 * sizeof(int), g->stream));
+      HIPCHK(g, hipStreamSynchronize(g->stream));
+    }
+    return s;
+  } catch (const std::bad_alloc&) {
+    return fail(g, EP_ERR_OOM, "host allocation failed");
+  }
+}
+
+EP_API ep_status ep_get_step(ep_grid g, int64_t* step) {
+  if (!g || !step) return EP_ERR_ARG;
+  *step = g->step;
+  return EP_OK;
+}
+
+EP_API ep_status ep_set_step(ep_grid g, int64_t step) {
+  if (!g || step < 0) return EP_ERR_ARG;
+  g->step = step;
+  g->stim_built = false;
+  return EP_OK;
+}
+
+EP_API ep_status ep_grid_stats(ep_grid g, int64_t* n_tissue, int64_t* n_bricks,
+                               int64_t* device_bytes) {
+  if (!g) return EP_ERR_ARG;
+  if (n_tissue) *n_tissue = g->n_tissue;
+  if (n_bricks) *n_bricks = g->nb;
+  if (device_bytes) *device_bytes = g->dev_bytes;
+  return EP_OK;
+}
+
+EP_API ep_status ep_kernel_timing(ep_grid g, int32_t enable) {
+  if (!g) return EP_ERR_ARG;
+  g->timing = enable != 0;
+  for (int k = 0; k < kTimers; ++k) {
+    g->tms[k] = 0;
+    g->tcount[k] = 0;
+    g->tused[k] = 0;
+  }
+  return EP_OK;
+}
+
+EP_API ep_status ep_kernel_time(ep_grid g, int32_t kernel_id, double* total_ms,
+                                int64_t* launches) {
+  if (!g || kernel_id < 0 || kernel_id >= kTimers) return EP_ERR_ARG;
+  if (total_ms) *total_ms = g->tms[kernel_id];
+  if (launches) *launches = g->tcount[kernel_id];
+  return EP_OK;
+}
+
+EP_API ep_status ep_destroy_grid(ep_grid g) {
+  if (!g) return EP_ERR_ARG;
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  for (void* p : g->allocs) (void)hipFree(p);
+  for (int k = 0; k < kTimers; ++k)
+    for (auto& tp : g->tk[k]) {
+      (void)hipEventDestroy(tp.a);
+      (void)hipEventDestroy(tp.b);
+    }
+  if (g->hs) (void)hipHostFree(g->hs);
+  if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
+  delete g;
+  return EP_OK;
+}
+
+EP_API const char* ep_status_string(ep_status s) {
+  switch (s) {
+    case EP_OK: return "EP_OK";
+    case EP_ERR_ARG: return "EP_ERR_ARG";
+    case EP_ERR_OOM: return "EP_ERR_OOM";
+    case EP_ERR_HIP: return "EP_ERR_HIP";
+    case EP_ERR_NOCONV: return "EP_ERR_NOCONV";
+    case EP_ERR_NONFINITE: return "EP_ERR_NONFINITE";
+    case EP_ERR_STATE: return "EP_ERR_STATE";
+    case EP_ERR_UNSUPPORTED: return "EP_ERR_UNSUPPORTED";
+  }
+  return "EP_ERR_UNKNOWN";
+}
+
+EP_API const char* ep_last_error(ep_grid g) {
+  return g ? g->err.c_str() : "";
+}
+
+}  // extern "C"

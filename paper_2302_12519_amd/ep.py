@@ -1,0 +1,241 @@
+"""ctypes binding of the HIP voxel-EP library (include/ep.h).
+
+Argument marshalling only: every step of the method runs in the HIP library
+``libep_hip.so`` built in this package directory.  If the library is missing
+the import fails loudly; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libep_hip.so")
+
+EP_OK, EP_ERR_ARG, EP_ERR_OOM, EP_ERR_HIP, EP_ERR_NOCONV, EP_ERR_NONFINITE, EP_ERR_STATE, \
+    EP_ERR_UNSUPPORTED = range(8)
+EP_F64, EP_F32 = 0, 1
+EP_MONO, EP_BIDO = 0, 1
+EP_DIFF_EXPLICIT, EP_DIFF_BE_PCG = 0, 1
+FIELDS = {"v": 0, "w": 1, "phi": 2, "tact": 3}
+KERNELS = {"stencil": 0, "update": 1, "parabolic": 2, "resid": 3}
+
+
+class EPError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class Ionic(C.Structure):
+    _fields_ = [("tau_in", C.c_double), ("tau_out", C.c_double), ("tau_open", C.c_double),
+                ("tau_close", C.c_double), ("v_gate", C.c_double), ("exc", C.c_double)]
+
+
+class Stim(C.Structure):
+    _fields_ = [("lo", C.c_int32 * 3), ("hi", C.c_int32 * 3), ("center", C.c_double * 3),
+                ("radius", C.c_double), ("amp", C.c_double), ("t_on", C.c_double),
+                ("t_off", C.c_double)]
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("h", C.c_double), ("mask", C.c_void_p),
+                ("model", C.c_int), ("prec", C.c_int), ("diff", C.c_int), ("dt", C.c_double),
+                ("ionic", Ionic), ("stim", C.POINTER(Stim)), ("n_stim", C.c_int32),
+                ("act_threshold", C.c_double), ("pcg_rtol", C.c_double),
+                ("pcg_maxit", C.c_int32), ("ell_rtol", C.c_double),
+                ("ell_max_outer", C.c_int32), ("ell_inner_maxit", C.c_int32),
+                ("stream", C.c_void_p)]
+
+
+class StepInfo(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("step", C.c_int64), ("t", C.c_double),
+                ("cg_iters", C.c_int64), ("cg_max", C.c_int32), ("ell_outer", C.c_int32),
+                ("q_stim", C.c_double), ("mass", C.c_double), ("relres", C.c_double)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("outer", C.c_int32), ("inner_iters", C.c_int64), ("relres", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    lib = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    lib.ep_create_grid.argtypes = [C.POINTER(GridDesc), C.POINTER(vp)]
+    lib.ep_set_conductivity_fibres.argtypes = [vp, vp, vp, C.c_double, C.c_double, C.c_double,
+                                               C.c_double]
+    lib.ep_step.argtypes = [vp, C.c_int32, C.POINTER(StepInfo)]
+    lib.ep_solve_elliptic.argtypes = [vp, C.c_double, C.c_int32, C.POINTER(SolveInfo)]
+    lib.ep_read_state.argtypes = [vp, C.c_int, vp, C.c_size_t]
+    lib.ep_write_state.argtypes = [vp, C.c_int, vp, C.c_size_t]
+    lib.ep_get_step.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.ep_set_step.argtypes = [vp, C.c_int64]
+    lib.ep_grid_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                  C.POINTER(C.c_int64)]
+    lib.ep_kernel_timing.argtypes = [vp, C.c_int32]
+    lib.ep_kernel_time.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.ep_destroy_grid.argtypes = [vp]
+    lib.ep_status_string.argtypes = [C.c_int]
+    lib.ep_status_string.restype = C.c_char_p
+    lib.ep_last_error.argtypes = [vp]
+    lib.ep_last_error.restype = C.c_char_p
+    for name in ("ep_create_grid", "ep_set_conductivity_fibres", "ep_step", "ep_solve_elliptic",
+                 "ep_read_state", "ep_write_state", "ep_get_step", "ep_set_step",
+                 "ep_grid_stats", "ep_kernel_timing", "ep_kernel_time", "ep_destroy_grid"):
+        getattr(lib, name).restype = C.c_int
+    return lib
+
+
+lib = _load()
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Grid:
+    """One simulation grid on the GPU (see include/ep.h for the semantics)."""
+
+    def __init__(self, n, h, dt, mask=None, model="mono", prec="f32", diff="explicit",
+                 ionic=None, stims=(), theta=0.5, pcg_rtol=1e-6, pcg_maxit=50,
+                 ell_rtol=1e-8, ell_max_outer=8, ell_inner_maxit=4000, stream=None):
+        self.n = tuple(int(k) for k in n)
+        self.N = int(np.prod(self.n))
+        d = GridDesc()
+        d.n[:] = list(self.n)
+        d.h = float(h)
+        self._mask = None
+        if mask is not None:
+            self._mask = np.ascontiguousarray(mask, dtype=np.uint8).ravel()
+            if self._mask.size != self.N:
+                raise ValueError("mask size does not match n")
+            d.mask = _p(self._mask)
+        d.model = EP_BIDO if model == "bido" else EP_MONO
+        d.prec = EP_F64 if prec == "f64" else EP_F32
+        d.diff = EP_DIFF_BE_PCG if diff == "be_pcg" else EP_DIFF_EXPLICIT
+        d.dt = float(dt)
+        io = ionic or {}
+        for k in ("tau_in", "tau_out", "tau_open", "tau_close", "v_gate", "exc"):
+            setattr(d.ionic, k, float(io[k]))
+        stims = list(stims)
+        self._stims = (Stim * max(1, len(stims)))()
+        for k, s in enumerate(stims):
+            self._stims[k].lo[:] = [int(v) for v in s.lo]
+            self._stims[k].hi[:] = [int(v) for v in s.hi]
+            self._stims[k].center[:] = [float(v) for v in s.center]
+            self._stims[k].radius = float(s.radius)
+            self._stims[k].amp = float(s.amp)
+            self._stims[k].t_on = float(s.t_on)
+            self._stims[k].t_off = float(s.t_off)
+        d.stim = C.cast(self._stims, C.POINTER(Stim))
+        d.n_stim = len(stims)
+        d.act_threshold = float(theta)
+        d.pcg_rtol, d.pcg_maxit = float(pcg_rtol), int(pcg_maxit)
+        d.ell_rtol, d.ell_max_outer = float(ell_rtol), int(ell_max_outer)
+        d.ell_inner_maxit = int(ell_inner_maxit)
+        d.stream = stream
+        self._desc = d
+        self._h = C.c_void_p()
+        self._check(lib.ep_create_grid(C.byref(d), C.byref(self._h)), "ep_create_grid",
+                    handle=False)
+
+    @classmethod
+    def from_instance(cls, inst, prec=None, **kw):
+        """Create from a problem-instance object (attributes n, h, dt, mask,
+        model, prec, diff, ionic, stims, theta, tolerances) and set its
+        conductivity."""
+        g = cls(inst.n, inst.h, inst.dt, mask=inst.mask, model=inst.model,
+                prec=prec or inst.prec, diff=inst.diff, ionic=inst.ionic, stims=inst.stims,
+                theta=inst.theta, pcg_rtol=inst.pcg_rtol, pcg_maxit=inst.pcg_maxit,
+                ell_rtol=inst.ell_rtol, **kw)
+        g.set_conductivity(inst.fibre, inst.scale, inst.sigma_l, inst.sigma_t,
+                           inst.sigma_el, inst.sigma_et)
+        return g
+
+    def _check(self, st, what, handle=True):
+        if st != EP_OK:
+            msg = lib.ep_last_error(self._h).decode() if handle and self._h else ""
+            name = lib.ep_status_string(st).decode()
+            raise EPError(st, f"{what}: {name} {msg}".strip())
+
+    def set_conductivity(self, fibre, scale, sig_l, sig_t, sig_el=0.0, sig_et=0.0):
+        f = np.ascontiguousarray(fibre, dtype=np.float64).reshape(self.N * 3)
+        s = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64).ravel()
+        self._check(lib.ep_set_conductivity_fibres(self._h, _p(f), None if s is None else _p(s),
+                                                   sig_l, sig_t, sig_el, sig_et),
+                    "ep_set_conductivity_fibres")
+
+    def step(self, nsteps, check=True):
+        info = StepInfo()
+        st = lib.ep_step(self._h, int(nsteps), C.byref(info))
+        if check:
+            self._check(st, "ep_step")
+        out = {k: getattr(info, k) for k, _ in StepInfo._fields_}
+        out["status"] = st
+        return out
+
+    def solve_elliptic(self, rtol=1e-8, max_outer=8, check=True):
+        info = SolveInfo()
+        st = lib.ep_solve_elliptic(self._h, float(rtol), int(max_outer), C.byref(info))
+        if check:
+            self._check(st, "ep_solve_elliptic")
+        out = {k: getattr(info, k) for k, _ in SolveInfo._fields_}
+        out["status"] = st
+        return out
+
+    def read(self, field):
+        out = np.empty(self.N, dtype=np.float64)
+        self._check(lib.ep_read_state(self._h, FIELDS[field], _p(out), self.N), "ep_read_state")
+        return out.reshape(self.n)
+
+    def write(self, field, values):
+        a = np.ascontiguousarray(values, dtype=np.float64).ravel()
+        if a.size != self.N:
+            raise ValueError("size mismatch")
+        self._check(lib.ep_write_state(self._h, FIELDS[field], _p(a), self.N), "ep_write_state")
+
+    @property
+    def step_index(self):
+        s = C.c_int64()
+        self._check(lib.ep_get_step(self._h, C.byref(s)), "ep_get_step")
+        return s.value
+
+    @step_index.setter
+    def step_index(self, v):
+        self._check(lib.ep_set_step(self._h, int(v)), "ep_set_step")
+
+    def stats(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(lib.ep_grid_stats(self._h, C.byref(a), C.byref(b), C.byref(c)),
+                    "ep_grid_stats")
+        return {"n_tissue": a.value, "n_bricks": b.value, "device_bytes": c.value}
+
+    def kernel_timing(self, enable=True):
+        self._check(lib.ep_kernel_timing(self._h, 1 if enable else 0), "ep_kernel_timing")
+
+    def kernel_time(self, kernel):
+        ms, cnt = C.c_double(), C.c_int64()
+        self._check(lib.ep_kernel_time(self._h, KERNELS[kernel], C.byref(ms), C.byref(cnt)),
+                    "ep_kernel_time")
+        return ms.value, cnt.value
+
+    def close(self):
+        if self._h:
+            lib.ep_destroy_grid(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,242 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded inputs.  Bars: FP64 path <= 1e-12 relative per step; FP32
+path <= 1e-4 max-abs normalised potential after 1000 steps with activation
+times within one dt; implicit / elliptic solves to their tolerances."""
+import math
+
+import numpy as np
+import pytest
+
+import ep_inputs as E
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2302_12519_amd as P
+    return P
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def shell_inst(n, seed=9, n_stim=3, diff="explicit", prec="f64", dt=0.02, sig=(0.2, 0.05),
+               model="mono", sig_e=(0.0, 0.0), scale=None):
+    shape, mask, fib, stims = E.shell(n, seed, n_stim)
+    return E.Instance(name=f"shell{n}", n=shape, h=0.25, dt=dt, steps=0, mask=mask, fibre=fib,
+                      scale=scale, sigma_l=sig[0], sigma_t=sig[1], sigma_el=sig_e[0],
+                      sigma_et=sig_e[1], stims=stims, model=model, diff=diff, prec=prec)
+
+
+# ---------------------------------------------------------------------------
+# FP64 path: one step from an identical state, every step of a run
+# ---------------------------------------------------------------------------
+def test_plain_box_fp64_every_step(P, orc):
+    """32^3 all-tissue box, isotropic 0.1, x = 0 stimulus, dt 0.01, FP64:
+    each of 1000 steps matches the oracle step from the same state to 1e-12."""
+    inst = E.plain_box(32, steps=1000, prec="f64")
+    say("case plain_box_32 fp64 per-step")
+    g = P.Grid.from_instance(inst)
+    o = orc.Oracle(inst)
+    worst = 0.0
+    for n in range(1000):
+        if n % 50 == 0 or n < 3:
+            # compare one step from the identical (GPU) state
+            v, w = g.read("v"), g.read("w")
+            o.set_state(v=v, w=w, step=n)
+            o.run(1)
+            g.step(1)
+            worst = max(worst, rel(g.read("v"), o.field("v")))
+        else:
+            g.step(1)
+    assert worst <= 1e-12, worst
+    # whole-trajectory difference from identical initial states
+    g2 = P.Grid.from_instance(inst)
+    o2 = orc.Oracle(inst)
+    g2.step(1000)
+    o2.run(1000)
+    traj = rel(g2.read("v"), o2.field("v"))
+    say(f"plain_box_32 fp64: per-step worst {worst:.2e}, 1000-step trajectory {traj:.2e}")
+    assert traj <= 1e-10, traj
+    T, To = g2.read("tact"), o2.field("tact")
+    fin = np.isfinite(To)
+    assert np.array_equal(np.isfinite(T), fin)
+    assert np.abs(T[fin] - To[fin]).max() <= 1e-9
+
+
+@pytest.mark.parametrize("n", [20, 29])
+def test_shell_fp64_anisotropic_one_step(P, orc, n):
+    """Masked anisotropic 19-point operator on a ragged (non multiple of 8)
+    shell grid: random state, one explicit step, FP64."""
+    inst = shell_inst(n)
+    say(f"case shell_{n} fp64 explicit one-step")
+    g = P.Grid.from_instance(inst)
+    o = orc.Oracle(inst)
+    v0, w0 = E.random_state(inst, 21)
+    for step0 in (0, 100):      # with and without the stimulus window
+        g.write("v", v0)
+        g.write("w", w0)
+        g.step_index = step0
+        o.set_state(v=v0, w=w0, step=step0)
+        g.step(1)
+        o.run(1)
+        assert rel(g.read("v"), o.field("v")) <= 1e-12
+        assert rel(g.read("w"), o.field("w")) <= 1e-12
+
+
+def test_shell_fp64_scaled_conductivity_run(P, orc):
+    inst = shell_inst(24, scale=E.smooth_scale((24, 24, 24), 77, sigma_vox=3.0))
+    say("case shell_24 fp64 scaled 200 steps")
+    g = P.Grid.from_instance(inst)
+    o = orc.Oracle(inst)
+    info = g.step(200)
+    rc, oi = o.run(200)
+    assert rel(g.read("v"), o.field("v")) <= 1e-10
+    assert abs(info["q_stim"] - oi.q_stim) <= 1e-12 * oi.q_stim
+    assert abs(info["mass"] - oi.mass) <= 1e-10 * abs(oi.mass)
+
+
+def test_be_pcg_fp64_one_step(P, orc):
+    inst = shell_inst(26, diff="be_pcg", dt=0.05)
+    inst.pcg_rtol = 1e-13
+    inst.pcg_maxit = 200
+    say("case shell_26 fp64 BE-PCG one-step")
+    g = P.Grid.from_instance(inst)
+    o = orc.Oracle(inst)
+    v0, w0 = E.random_state(inst, 5)
+    g.write("v", v0)
+    g.write("w", w0)
+    o.set_state(v=v0, w=w0)
+    info = g.step(1)
+    o.run(1)
+    assert info["cg_iters"] > 3
+    assert rel(g.read("v"), o.field("v")) <= 1e-11
+
+
+# ---------------------------------------------------------------------------
+# FP32 path against the FP64 oracle
+# ---------------------------------------------------------------------------
+def test_plain_box_fp32_1000_steps(P, orc):
+    inst = E.plain_box(32, steps=1000, prec="f32")
+    say("case plain_box_32 fp32 1000 steps")
+    g = P.Grid.from_instance(inst)
+    o = orc.Oracle(inst)
+    g.step(1000)
+    o.run(1000)
+    err = np.abs(g.read("v") - o.field("v")).max() / np.abs(o.field("v")).max()
+    T, To = g.read("tact"), o.field("tact")
+    fin = np.isfinite(To) & np.isfinite(T)
+    say(f"plain_box_32 fp32: max-abs normalised {err:.2e}, T_act max diff "
+        f"{np.abs(T[fin] - To[fin]).max():.2e} ms")
+    assert err <= 1e-4
+    assert np.abs(T[fin] - To[fin]).max() <= inst.dt
+    assert (np.isfinite(T) != np.isfinite(To)).sum() <= 0.001 * T.size
+
+
+def test_be_pcg_fp32_run(P, orc):
+    """Implicit-Euler Jacobi-PCG (rtol 1e-6) in FP32 on an anisotropic shell
+    with ball stimuli, 200 steps of dt 0.05, against the FP64 oracle."""
+    inst = E.aniso_be(40, steps=200)
+    say("case aniso_be_40 fp32 200 steps")
+    g = P.Grid.from_instance(inst)
+    o = orc.Oracle(inst)
+    info = g.step(200)
+    o.run(200)
+    err = np.abs(g.read("v") - o.field("v")).max() / np.abs(o.field("v")).max()
+    T, To = g.read("tact"), o.field("tact")
+    fin = np.isfinite(To) & np.isfinite(T)
+    say(f"aniso_be_40 fp32: iters {info['cg_iters']} (max {info['cg_max']}), "
+        f"err {err:.2e}, dT {np.abs(T[fin] - To[fin]).max():.2e}")
+    assert err <= 1e-4
+    assert np.abs(T[fin] - To[fin]).max() <= inst.dt
+
+
+# ---------------------------------------------------------------------------
+# bidomain
+# ---------------------------------------------------------------------------
+def test_elliptic_solve_residual_in_fp64(P, orc):
+    """ep_solve_elliptic reaches ||b - K phi|| <= 1e-8 ||b||, measured by the
+    oracle's own FP64 operators; the gauge sum phi = 0 holds."""
+    inst = shell_inst(32, model="bido", sig=(0.17, 0.019), sig_e=(0.62, 0.24), prec="f32")
+    inst.ell_rtol = 1e-8
+    say("case bidomain shell_32 elliptic")
+    g = P.Grid.from_instance(inst)
+    o = orc.Oracle(inst)
+    rng = np.random.default_rng(3)
+    v = (0.5 + 0.5 * np.sin(np.arange(inst.nb).reshape(inst.n) * 0.37)) * inst.mask
+    g.write("v", v)
+    vg = g.read("v")                     # FP32-rounded potential as the solver sees it
+    info = g.solve_elliptic(1e-8, 10)
+    phi = g.read("phi")
+    b = orc.apply(inst.n, inst.h, inst.mask, o.Di, vg)
+    Kphi = -(orc.apply(inst.n, inst.h, inst.mask, o.Di, phi)
+             + orc.apply(inst.n, inst.h, inst.mask, o.De, phi))
+    relres = np.linalg.norm(b - Kphi) / np.linalg.norm(b)
+    say(f"elliptic: outer {info['outer']} inner {info['inner_iters']} relres(gpu) "
+        f"{info['relres']:.2e} relres(oracle) {relres:.2e}")
+    assert relres <= 2e-8
+    assert abs(phi[inst.mask > 0].sum()) <= 1e-9 * np.abs(phi).sum()
+    ref, _ = o.solve_elliptic(b)
+    assert rel(phi, ref) <= 1e-5
+
+
+def test_bidomain_steps(P, orc):
+    inst = shell_inst(24, model="bido", sig=(0.17, 0.019), sig_e=(0.62, 0.24), prec="f32",
+                      dt=0.05, n_stim=3)
+    inst.ell_rtol = 1e-8
+    say("case bidomain shell_24 100 steps")
+    g = P.Grid.from_instance(inst)
+    o = orc.Oracle(inst)
+    info = g.step(100)
+    o.run(100)
+    err = np.abs(g.read("v") - o.field("v")).max() / np.abs(o.field("v")).max()
+    perr = rel(g.read("phi"), o.field("phi"))
+    say(f"bidomain_24: outer {info['ell_outer']} inner {info['cg_iters']} v err {err:.2e} "
+        f"phi err {perr:.2e}")
+    assert err <= 1e-4
+    assert perr <= 1e-3
+
+
+# ---------------------------------------------------------------------------
+# error behaviour
+# ---------------------------------------------------------------------------
+def test_error_codes(P):
+    ep = P.ep
+    inst = E.plain_box(8, steps=1, prec="f32")
+    say("case error codes")
+    with pytest.raises(P.EPError) as e:
+        P.Grid((0, 8, 8), 0.25, 0.01, ionic=inst.ionic)
+    assert e.value.status == ep.EP_ERR_ARG
+    with pytest.raises(P.EPError) as e:
+        P.Grid((8, 8, 8), 0.25, 0.01, mask=np.zeros((8, 8, 8)), ionic=inst.ionic)
+    assert e.value.status == ep.EP_ERR_ARG
+    g = P.Grid((8, 8, 8), 0.25, 0.01, ionic=inst.ionic)
+    assert g.step(1, check=False)["status"] == ep.EP_ERR_STATE
+    bad = inst.fibre.copy()
+    bad[1, 1, 1] = (1.0, 1.0, 0.0)
+    with pytest.raises(P.EPError) as e:
+        g.set_conductivity(bad, None, 0.1, 0.1)
+    assert e.value.status == ep.EP_ERR_ARG
+    # explicit stability: dt * lambda_max >= 2 is rejected
+    g2 = P.Grid((8, 8, 8), 0.25, 0.2, ionic=inst.ionic)
+    with pytest.raises(P.EPError) as e:
+        g2.set_conductivity(inst.fibre, None, 0.2, 0.2)
+    assert e.value.status == ep.EP_ERR_ARG
+    g.set_conductivity(inst.fibre, None, 0.1, 0.1)
+    v = np.zeros((8, 8, 8))
+    v[3, 3, 3] = np.nan
+    g.write("v", v)
+    assert g.step(1, check=False)["status"] == ep.EP_ERR_NONFINITE
+    assert g.step(1, check=False)["status"] == ep.EP_ERR_NONFINITE   # sticky
+    g.write("v", np.zeros((8, 8, 8)))
+    assert g.step(1, check=False)["status"] == ep.EP_OK
+    # monodomain grid has no elliptic solve
+    assert g.solve_elliptic(check=False)["status"] == ep.EP_ERR_UNSUPPORTED
