@@ -1,0 +1,179 @@
+"""Benchmark: voxel-steps/s of the voxel cardiac-EP time step on one MI355X.
+
+Default workload: anisotropic monodomain on a 256^3 ventricle-like shell
+(~30 % tissue, sigma 0.2/0.05 mm^2/ms, transmural +-60 deg fibres, 16 seeded
+ball stimuli), FP32 state, implicit-Euler diffusion by Jacobi-PCG, dt 0.05 ms.
+One "step" is one full operator-split time step (reaction, PCG diffusion
+solve, activation times).  Inputs are seeded and synthetic and already
+resident in HBM when timing starts.
+
+Prints ONE JSON line with the metric, the live-measured roofline of the
+dominant kernel (HIP events on the library's stream) and the FP64 oracle
+timed on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+# Algorithmic HBM bytes per tissue voxel for one launch of each kernel
+# (FP32 state; each array read or written once):
+#   PCG SpMV  q = (I - dt A) p with p = M^-1 r + beta p_old formed on the fly:
+#             reads r, M^-1, p_old (12 B) and 6 coefficients (24 B),
+#             writes p, q (8 B)                                   -> 44 B
+#   PCG update x += alpha p, r -= alpha q: reads x, r, p, q, M^-1 (20 B),
+#             writes x, r (8 B)                                   -> 28 B
+#   explicit fused step: reads v, w (8 B) + 24 B coefficients, writes v, w -> 40 B
+ALGO_BYTES = {"stencil_be": 44, "update": 28, "stencil_explicit": 40}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256, help="grid edge of the shell workload")
+    ap.add_argument("--rtol", type=float, default=1e-7)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="budget for the oracle CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles",
+                                                           "traffic_spmv_aniso_be_256.txt"))
+    return ap.parse_args()
+
+
+def read_traffic(path):
+    """Per-launch HBM bytes of the SpMV from the committed counter summary
+    (line 'traffic_bytes_per_launch: X' and 'kernel_source_sha: S'); None if
+    absent or taken on another kernel version."""
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    try:
+        import hashlib
+        src = open(os.path.join(ROOT, "paper_2302_12519_amd", "csrc", "ep_kernels.hip"), "rb").read()
+        if vals.get("kernel_source_sha") != hashlib.sha256(src).hexdigest()[:16]:
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(inst, budget_s):
+    """The FP64 oracle on the host cores: the first steps of the same workload
+    from rest, until the time budget is spent (at least one step)."""
+    import oracle
+    o = oracle.Oracle(inst)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        o.run(1)
+        steps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": inst.nt * steps / dt, "unit": "voxel-steps/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"first {steps} step(s) of the same {inst.n[0]}^3 workload from rest, "
+                      f"FP64, CG to 1e-13, {dt:.1f} s wall"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
+              "(the grid is not sharded across GPUs)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    import ep_inputs as E
+    from paper_2302_12519_amd import Grid
+
+    t_gen = time.perf_counter()
+    inst = E.aniso_be(a.n, steps=a.warmup + a.steps)
+    inst.pcg_rtol = a.rtol
+    gen_s = time.perf_counter() - t_gen
+    g = Grid.from_instance(inst)
+    st = g.stats()
+    print(f"# workload {inst.name}: N_t {inst.nt}, bricks {st['n_bricks']}, "
+          f"device {st['device_bytes'] / 2**20:.0f} MiB, generated in {gen_s:.1f} s",
+          file=sys.stderr, flush=True)
+
+    if a.warmup:
+        g.step(a.warmup)
+    torch.cuda.synchronize()
+    g.kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = g.step(a.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    spmv_ms, spmv_n = g.kernel_time("stencil")
+    upd_ms, upd_n = g.kernel_time("update")
+    g.kernel_timing(False)
+
+    value = inst.nt * a.steps / elapsed
+    avg_spmv = spmv_ms / max(spmv_n, 1)
+    achieved = ALGO_BYTES["stencil_be"] * inst.nt / (avg_spmv * 1e-3) / 1e9
+    traffic = read_traffic(a.traffic_file)
+    out = {
+        "metric": "voxel-steps/s",
+        "value": value,
+        "unit": "voxel-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * elapsed / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"aniso_be_{a.n}: monodomain FP32, {a.n}^3 ellipsoidal shell "
+                               f"({inst.nt} tissue voxels), 19-point anisotropic stencil, "
+                               f"implicit Euler by Jacobi-PCG rtol {a.rtol:g}, dt {inst.dt} ms",
+                   "n_tissue": inst.nt, "grid": list(inst.n), "dt_ms": inst.dt},
+        "roofline": {"bound": "hbm", "kernel": "k_spmv<float>", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "algo_bytes_per_launch": ALGO_BYTES["stencil_be"] * inst.nt,
+                     "avg_launch_us": 1e3 * avg_spmv, "launches": spmv_n},
+        "cg": {"iters_total": info["cg_iters"], "iters_per_step": info["cg_iters"] / a.steps,
+               "iters_max": info["cg_max"],
+               "update_avg_us": 1e3 * upd_ms / max(upd_n, 1),
+               "update_gbs": ALGO_BYTES["update"] * inst.nt / (upd_ms / max(upd_n, 1) * 1e-3) / 1e9},
+    }
+    if not a.no_parity:
+        # one-step parity from the GPU's current state against the FP64 oracle
+        import oracle
+        o = oracle.Oracle(inst)
+        o.set_state(v=g.read("v"), w=g.read("w"), step=g.step_index)
+        g.step(1)
+        o.run(1)
+        v, ref = g.read("v"), o.field("v")
+        out["parity_one_step"] = float(np.abs(v - ref).max() / np.abs(ref).max())
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inst, a.cpu_seconds)
+    g.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

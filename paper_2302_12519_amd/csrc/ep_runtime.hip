@@ -524,7 +524,9 @@ ep_status check_explicit_stability(ep_grid g, double* const c64[6]) {
   HIPCHK(g, hipMemcpyAsync(part.data(), g->d_partials, G * sizeof(double), hipMemcpyDeviceToHost,
                            g->stream));
   HIPCHK(g, hipStreamSynchronize(g->stream));
-  const double gersh = *std::max_element(part.begin(), part.end());
+  double gersh = 0.0;
+  for (double v : part) gersh = (v > gersh || std::isnan(v)) ? v : gersh;
+  if (std::isnan(gersh)) return fail(g, EP_ERR_ARG, "non-finite diffusion coefficients");
   if (g->dt * gersh < 2.0) return EP_OK;
   double *x = nullptr, *y = nullptr;
   const size_t bytes = static_cast<size_t>(g->nvox) * sizeof(double);
@@ -549,7 +551,7 @@ ep_status check_explicit_stability(ep_grid g, double* const c64[6]) {
   HIPCHK(g, hipStreamSynchronize(g->stream));
   // x was unit before the last apply: lambda ~ |x . A x|
   lam = std::fabs(g->hs->sums[1]);
-  if (g->dt * lam * 1.02 >= 2.0) {
+  if (!(g->dt * lam * 1.02 < 2.0)) {
     char buf[160];
     snprintf(buf, sizeof buf, "explicit diffusion unstable: dt*lambda_max(-A) ~ %.3f >= 2",
              g->dt * lam);
@@ -885,6 +887,13 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
         (scale && hipMemcpyAsync(dsc, hsc.data(), b64, hipMemcpyHostToDevice, g->stream) != hipSuccess) ||
         hipMemsetAsync(tens, 0, 6 * b64, g->stream) != hipSuccess) {
       rc = fail(g, EP_ERR_HIP, "upload of fibres failed");
+      break;
+    }
+    // the ghost brick of every coefficient array must read zero
+    for (int k = 0; k < 6 && tmp64[k]; ++k)
+      if (hipMemsetAsync(tmp64[k], 0, b64, g->stream) != hipSuccess) rc = EP_ERR_HIP;
+    if (rc != EP_OK) {
+      rc = fail(g, EP_ERR_HIP, "clearing coefficient scratch failed");
       break;
     }
     // monodomain / intracellular set in state precision (+ FP64 twin for checks)
