@@ -48,6 +48,8 @@ def parse():
                     help="budget for the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (for HBM counter scaling)")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles",
                                                            "traffic_spmv_aniso_be_256.txt"))
     return ap.parse_args()
@@ -105,6 +107,15 @@ def main():
     torch.cuda.set_device(0)
     import ep_inputs as E
     from paper_2302_12519_amd import Grid
+
+    if a.copy_calibration:
+        # plain copy of known size: 1 GiB read + 1 GiB written
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
 
     t_gen = time.perf_counter()
     inst = E.aniso_be(a.n, steps=a.warmup + a.steps)

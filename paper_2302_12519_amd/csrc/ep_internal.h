@@ -75,11 +75,17 @@ enum RedOp {
 
 struct LaunchCfg {
   int nb;       // active bricks
-  int grid;     // blocks launched (multiple of kXcd, >= nb)
+  int grid;     // blocks of a one-brick-per-block launch (multiple of kXcd, >= nb)
+  int pgrid;    // blocks of a persistent launch (multiple of kXcd, <= grid)
   hipStream_t stream;
 };
 
 inline int grid_for(int nb) { return ((nb + kXcd - 1) / kXcd) * kXcd; }
+// persistent launches: at most 4 blocks of 512 threads per CU on 256 CUs
+inline int pgrid_for(int nb) {
+  const int g = grid_for(nb);
+  return g < 1024 ? g : 1024;
+}
 
 // ---- kernel launchers (ep_kernels.hip) ----------------------------------
 void launch_tensor_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask,
@@ -96,24 +102,29 @@ template <typename T>
 void launch_ionic(const LaunchCfg& L, const T* v, const T* w, const T* jstim, T* vs,
                   T* wout, IonicT<T> ion, T dt);
 
+// Persistent CG kernels (L.pgrid blocks).  Each launch reduces the partials
+// `prev` of the launch before it (L.pgrid per component) into the solver
+// scalars read from `cin`, publishes them in `cout` and leaves its own
+// partials in `parts`.  init_kind: 0 after k_be_init, 1 after k_inner_init.
 template <typename T>
 void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v,
                     const T* w, const T* jstim, const T* dinv, T* x, T* wout, T* r,
-                    IonicT<T> ion, T dt, double* partials);
+                    IonicT<T> ion, T dt, CGScalars* cout, double* parts, double tol2,
+                    int maxit);
 
 template <typename T>
 void launch_spmv(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* r,
                  const T* dinv, const T* pold, T* pnew, T* q, T c0, T c1, int first,
-                 const CGScalars* cg, double* partials);
+                 int init_kind, const CGScalars* cin, CGScalars* cout, const double* prev,
+                 double* parts);
 
 template <typename T>
 void launch_cg_update(const LaunchCfg& L, T* x, T* r, const T* p, const T* q,
-                      const T* dinv, const CGScalars* cg, double* partials);
+                      const T* dinv, const CGScalars* cin, CGScalars* cout, const double* prev,
+                      double* parts);
 
-void launch_reduce(hipStream_t s, RedOp op, const double* partials, int nparts, int K,
-                   CGScalars* cg, double* out);
-void launch_reduce_init(hipStream_t s, RedOp op, const double* partials, int nparts, int K,
-                        CGScalars* cg, double tol2, int maxit);
+// out[k] = sum of partials[k*nparts .. (k+1)*nparts) in a fixed order
+void launch_reduce_sum(hipStream_t s, const double* partials, int nparts, int K, double* out);
 void launch_block_max(const LaunchCfg& L, const int* nbr, CoefSet<double> c,
                       double* partials);
 void launch_scale(const LaunchCfg& L, double* x, const double* y, const double* sums);
@@ -123,8 +134,7 @@ void launch_activation(const LaunchCfg& L, const T* vold, const T* vnew, T* tact
                        T theta, double tn, int* flags);
 
 template <typename T>
-void launch_dinv(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1,
-                 const uint8_t* mask, T* dinv);
+void launch_dinv(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, T* dinv);
 
 template <typename T>
 void launch_sum(const LaunchCfg& L, const T* x, double* partials);
@@ -138,12 +148,11 @@ void launch_q_accum(hipStream_t s, double* qacc, const double* qstep, double sca
 // bidomain
 template <typename T>
 void launch_resid64(const LaunchCfg& L, const int* nbr, CoefSet<double> ci, CoefSet<double> ck,
-                    const T* vs, const double* phi, const uint8_t* mask, double* r64,
-                    double* partials);
+                    const T* vs, const double* phi, double* r64, double* partials);
 
 void launch_inner_init(const LaunchCfg& L, const double* r64, const uint8_t* mask,
                        const double* sums, double inv_count, const float* dinv, float* x,
-                       float* r, double* partials);
+                       float* r, CGScalars* cout, double* parts, double tol2, int maxit);
 
 void launch_phi_correct(const LaunchCfg& L, double* phi, const float* d, const uint8_t* mask,
                         double* partials);

@@ -5,11 +5,16 @@
 // x-plane.  Stencil kernels stage the brick plus its face/edge halo (the
 // 19-point operator needs no corner cells) in LDS, recomputing cheap
 // pointwise work (the ionic update, the CG search direction) for halo cells
-// instead of writing it to HBM and reading it back.  Nothing here is a dense
-// contraction, so there is no MFMA: every kernel is bound by HBM traffic.
+// instead of writing it to HBM and reading it back.  Every global load a
+// thread needs (its own voxel, one halo cell, the 18 operator weights) is
+// issued before the single barrier that publishes the tile, so the loads of
+// a brick overlap instead of forming dependent round trips.  Nothing here is
+// a dense contraction, so there is no MFMA: every kernel is HBM-bound.
 //
 // Reductions are deterministic: each block writes its partial sums (FP64) to
-// a fixed slot, and one 1024-thread block sums the slots in a fixed order.
+// a fixed slot; the last block to finish (device-scope counter) sums the
+// slots in block order and updates the solver scalars, so a CG iteration
+// needs no separate reduction launch.
 #include <cmath>
 
 #include "ep_internal.h"
@@ -78,24 +83,30 @@ template <typename T>
 __device__ __forceinline__ void gather18(const CoefSet<T>& c, const int* nbs, int brick, int lx,
                                          int ly, int lz, T k[18]) {
   const int g = brick * kBV + (lx * 8 + ly) * 8 + lz;
+  const int gx = nb_global(nbs, brick, lx, ly, lz, -1, 0, 0);
+  const int gy = nb_global(nbs, brick, lx, ly, lz, 0, -1, 0);
+  const int gz = nb_global(nbs, brick, lx, ly, lz, 0, 0, -1);
+  const int gxy = nb_global(nbs, brick, lx, ly, lz, -1, -1, 0);
+  const int gxz = nb_global(nbs, brick, lx, ly, lz, -1, 0, -1);
+  const int gyz = nb_global(nbs, brick, lx, ly, lz, 0, -1, -1);
   k[0] = c.c[CX][g];
-  k[1] = c.c[CX][nb_global(nbs, brick, lx, ly, lz, -1, 0, 0)];
+  k[1] = c.c[CX][gx];
   k[2] = c.c[CY][g];
-  k[3] = c.c[CY][nb_global(nbs, brick, lx, ly, lz, 0, -1, 0)];
+  k[3] = c.c[CY][gy];
   k[4] = c.c[CZ][g];
-  k[5] = c.c[CZ][nb_global(nbs, brick, lx, ly, lz, 0, 0, -1)];
+  k[5] = c.c[CZ][gz];
   k[6] = c.c[CXY][g];
-  k[7] = c.c[CXY][nb_global(nbs, brick, lx, ly, lz, -1, -1, 0)];
-  k[8] = c.c[CXY][nb_global(nbs, brick, lx, ly, lz, 0, -1, 0)];
-  k[9] = c.c[CXY][nb_global(nbs, brick, lx, ly, lz, -1, 0, 0)];
+  k[7] = c.c[CXY][gxy];
+  k[8] = c.c[CXY][gy];
+  k[9] = c.c[CXY][gx];
   k[10] = c.c[CXZ][g];
-  k[11] = c.c[CXZ][nb_global(nbs, brick, lx, ly, lz, -1, 0, -1)];
-  k[12] = c.c[CXZ][nb_global(nbs, brick, lx, ly, lz, 0, 0, -1)];
-  k[13] = c.c[CXZ][nb_global(nbs, brick, lx, ly, lz, -1, 0, 0)];
+  k[11] = c.c[CXZ][gxz];
+  k[12] = c.c[CXZ][gz];
+  k[13] = c.c[CXZ][gx];
   k[14] = c.c[CYZ][g];
-  k[15] = c.c[CYZ][nb_global(nbs, brick, lx, ly, lz, 0, -1, -1)];
-  k[16] = c.c[CYZ][nb_global(nbs, brick, lx, ly, lz, 0, 0, -1)];
-  k[17] = c.c[CYZ][nb_global(nbs, brick, lx, ly, lz, 0, -1, 0)];
+  k[15] = c.c[CYZ][gyz];
+  k[16] = c.c[CYZ][gz];
+  k[17] = c.c[CYZ][gy];
 }
 
 // (A u)_p from the LDS tile s at tile cell C.  Faces: a (u_q - u_p).  Each
@@ -152,6 +163,43 @@ __device__ __forceinline__ void block_partials(double (&v)[K], double* partials)
     for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
     partials[threadIdx.x * gridDim.x + blockIdx.x] = s;
   }
+}
+
+// Brick m of this block in a persistent launch: XCD x = block % 8 owns the
+// contiguous brick range [x*per, (x+1)*per); its blocks stride through it.
+// Returns -1 when the block has no brick m.
+__device__ __forceinline__ int pbrick(int m, int nb) {
+  const int x = blockIdx.x % kXcd, j = blockIdx.x / kXcd;
+  const int gper = gridDim.x / kXcd;
+  const int per = (nb + kXcd - 1) / kXcd;
+  const int b = x * per + j + m * gper;
+  return (b < (x + 1) * per && b < nb) ? b : -1;
+}
+
+// Sum the K partial sums the previous launch left (n per component) in a
+// fixed order.  Every block computes the identical totals, so no block has
+// to wait for another and nothing is communicated within the launch.
+template <int K>
+__device__ __forceinline__ void sum_prev(const double* __restrict__ parts, int n, double (&S)[K]) {
+  __shared__ double red[K][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double x = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) x += parts[k * n + i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[k][wave] = x;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += red[k][w];
+    S[k] = t;
+  }
+  __syncthreads();
 }
 
 template <int K>
@@ -229,6 +277,34 @@ __global__ __launch_bounds__(kBV) void k_coefs(int nb, const int* __restrict__ n
   }
 }
 
+// Common prologue of the stencil kernels: the thread's own voxel, its halo
+// cell (threads < 480) and their tile cells.
+struct Cell {
+  int lx, ly, lz, g, C;     // own voxel
+  bool has_halo;
+  int hg, hC;               // halo cell: global index and tile cell
+};
+
+__device__ __forceinline__ Cell cell_setup(const int* nbs, int brick) {
+  Cell c;
+  const int t = threadIdx.x;
+  c.lx = t >> 6;
+  c.ly = (t >> 3) & 7;
+  c.lz = t & 7;
+  c.g = brick * kBV + t;
+  c.C = tidx(c.lx + 1, c.ly + 1, c.lz + 1);
+  c.has_halo = t < kHalo;
+  c.hg = 0;
+  c.hC = 0;
+  if (c.has_halo) {
+    int hx, hy, hz;
+    halo_cell(t, hx, hy, hz);
+    c.hg = tile_global(nbs, hx, hy, hz);
+    c.hC = tidx(hx, hy, hz);
+  }
+  return c;
+}
+
 // ---------------------------------------------------------------------------
 // explicit monodomain step: ionic + 19-point diffusion + activation, fused
 // ---------------------------------------------------------------------------
@@ -244,32 +320,33 @@ __global__ __launch_bounds__(kBV) void k_explicit(int nb, const int* __restrict_
   __shared__ int nbs[kNbr];
   const int brick = block_brick();
   if (brick >= nb) return;
-  const int t = threadIdx.x;
-  if (t < kNbr) nbs[t] = nbr[brick * kNbr + t];
-  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
-  const int g = brick * kBV + t;
-  const T v0 = v[g], w0 = w[g];
-  T vs, ws;
-  ms_step(v0, w0, jstim ? jstim[g] : T(0), ion, dt, vs, ws);
-  const int C = tidx(lx + 1, ly + 1, lz + 1);
-  s[C] = vs;
+  if (threadIdx.x < kNbr) nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
   __syncthreads();
-  for (int k = t; k < kHalo; k += kBV) {
-    int hx, hy, hz;
-    halo_cell(k, hx, hy, hz);
-    const int gg = tile_global(nbs, hx, hy, hz);
+  const Cell q = cell_setup(nbs, brick);
+  const T v0 = v[q.g], w0 = w[q.g];
+  const T j0 = jstim ? jstim[q.g] : T(0);
+  T hv = T(0), hw = T(0), hj = T(0);
+  if (q.has_halo) {
+    hv = v[q.hg];
+    hw = w[q.hg];
+    hj = jstim ? jstim[q.hg] : T(0);
+  }
+  T k18[18];
+  gather18(c, nbs, brick, q.lx, q.ly, q.lz, k18);
+  T vs, ws;
+  ms_step(v0, w0, j0, ion, dt, vs, ws);
+  s[q.C] = vs;
+  if (q.has_halo) {
     T a, b;
-    ms_step(v[gg], w[gg], jstim ? jstim[gg] : T(0), ion, dt, a, b);
-    s[tidx(hx, hy, hz)] = a;
+    ms_step(hv, hw, hj, ion, dt, a, b);
+    s[q.hC] = a;
   }
   __syncthreads();
-  T k18[18];
-  gather18(c, nbs, brick, lx, ly, lz, k18);
-  const T vn = vs + dt * apply19(s, C, k18);
-  vout[g] = vn;
-  wout[g] = ws;
+  const T vn = vs + dt * apply19(s, q.C, k18);
+  vout[q.g] = vn;
+  wout[q.g] = ws;
   if (v0 < theta && theta <= vn) {
-    if (isinf(tact[g])) tact[g] = static_cast<T>(tn) + dt * (theta - v0) / (vn - v0);
+    if (isinf(tact[q.g])) tact[q.g] = static_cast<T>(tn) + dt * (theta - v0) / (vn - v0);
   }
   if (!isfinite(vn)) flags[0] = 1;
 }
@@ -292,7 +369,15 @@ __global__ __launch_bounds__(kBV) void k_ionic(int nb, const T* __restrict__ v,
 // ---------------------------------------------------------------------------
 // implicit Euler diffusion by Jacobi-PCG:  (I - dt A) x = v*,  x0 = v*
 // ---------------------------------------------------------------------------
+// The CG kernels run persistently (about four blocks per CU, each looping
+// over its bricks).  Each launch first sums the partial sums the previous
+// launch left (one per block, fixed order, identical in every block), updates
+// the solver scalars from them, and block 0 publishes the scalars for the
+// host and the next launch.  Partials and scalars are double-buffered: a
+// launch reads `prev` / `cin` and writes `parts` / `cout`.
+
 // Reaction fused with the initial residual r0 = b - (I - dt A) b = dt A v*.
+// Partials: (r.M^-1 r, b.b, r.r).
 template <typename T>
 __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__ nbr,
                                                  CoefSet<T> c, const T* __restrict__ v,
@@ -300,106 +385,185 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
                                                  const T* __restrict__ jstim,
                                                  const T* __restrict__ dinv, T* __restrict__ x,
                                                  T* __restrict__ wout, T* __restrict__ r,
-                                                 IonicT<T> ion, T dt, double* partials) {
+                                                 IonicT<T> ion, T dt, CGScalars* cout,
+                                                 double* parts, double tol2, int maxit) {
   __shared__ T s[kTile];
   __shared__ int nbs[kNbr];
-  const int brick = block_brick();
-  if (brick >= nb) { idle_partials<3>(partials); return; }
-  const int t = threadIdx.x;
-  if (t < kNbr) nbs[t] = nbr[brick * kNbr + t];
-  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
-  const int g = brick * kBV + t;
-  T vs, ws;
-  ms_step(v[g], w[g], jstim ? jstim[g] : T(0), ion, dt, vs, ws);
-  const int C = tidx(lx + 1, ly + 1, lz + 1);
-  s[C] = vs;
-  __syncthreads();
-  for (int k = t; k < kHalo; k += kBV) {
-    int hx, hy, hz;
-    halo_cell(k, hx, hy, hz);
-    const int gg = tile_global(nbs, hx, hy, hz);
-    T a, b;
-    ms_step(v[gg], w[gg], jstim ? jstim[gg] : T(0), ion, dt, a, b);
-    s[tidx(hx, hy, hz)] = a;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    CGScalars st = {};
+    st.tol2 = tol2;
+    st.maxit = maxit;
+    *cout = st;
   }
-  __syncthreads();
-  T k18[18];
-  gather18(c, nbs, brick, lx, ly, lz, k18);
-  const T rr = dt * apply19(s, C, k18);
-  x[g] = vs;
-  wout[g] = ws;
-  r[g] = rr;
-  const double rd = static_cast<double>(rr);
-  double acc[3] = {rd * static_cast<double>(dinv[g]) * rd,
-                   static_cast<double>(vs) * static_cast<double>(vs), rd * rd};
-  block_partials<3>(acc, partials);
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int m = 0;; ++m) {
+    const int brick = pbrick(m, nb);
+    if (brick < 0) break;
+    if (threadIdx.x < kNbr) nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
+    __syncthreads();
+    const Cell q = cell_setup(nbs, brick);
+    const T v0 = v[q.g], w0 = w[q.g];
+    const T j0 = jstim ? jstim[q.g] : T(0);
+    const T dg = dinv[q.g];
+    T hv = T(0), hw = T(0), hj = T(0);
+    if (q.has_halo) {
+      hv = v[q.hg];
+      hw = w[q.hg];
+      hj = jstim ? jstim[q.hg] : T(0);
+    }
+    T k18[18];
+    gather18(c, nbs, brick, q.lx, q.ly, q.lz, k18);
+    T vs, ws;
+    ms_step(v0, w0, j0, ion, dt, vs, ws);
+    s[q.C] = vs;
+    if (q.has_halo) {
+      T a, b;
+      ms_step(hv, hw, hj, ion, dt, a, b);
+      s[q.hC] = a;
+    }
+    __syncthreads();
+    const T rr = dt * apply19(s, q.C, k18);
+    x[q.g] = vs;
+    wout[q.g] = ws;
+    r[q.g] = rr;
+    const double rd = static_cast<double>(rr);
+    acc[0] += rd * static_cast<double>(dg) * rd;
+    acc[1] += static_cast<double>(vs) * static_cast<double>(vs);
+    acc[2] += rd * rd;
+  }
+  block_partials<3>(acc, parts);
+}
+
+// Start or continue a solve from the previous launch's partials; returns the
+// scalars of this iteration (identical in every block).
+//  first, init_kind 0: partials (rz, bb, rr) of k_be_init
+//  first, init_kind 1: partials (rz, rr) of k_inner_init (tolerance relative
+//                      to the initial residual)
+//  otherwise:          partials (rr, rz) of k_cg_update -> beta, convergence
+__device__ __forceinline__ CGScalars cg_advance(const CGScalars& in, const double* prev,
+                                                int first, int init_kind) {
+  CGScalars st = in;
+  if (first) {
+    if (init_kind == 0) {
+      double S[3];
+      sum_prev<3>(prev, gridDim.x, S);
+      st.rz = S[0]; st.bb = S[1]; st.rr = S[2];
+      st.done = (S[1] == 0.0 || S[2] <= in.tol2 * S[1]) ? 1 : 0;
+    } else {
+      double S[2];
+      sum_prev<2>(prev, gridDim.x, S);
+      st.rz = S[0]; st.rr = S[1]; st.bb = S[1];
+      st.done = (S[1] == 0.0) ? 1 : 0;
+    }
+    st.it = 0; st.beta = 0.0; st.alpha = 0.0; st.fail = 0;
+  } else {
+    double S[2];
+    sum_prev<2>(prev, gridDim.x, S);
+    st.it = in.it + 1;
+    st.rr = S[0];
+    if (!isfinite(S[0])) { st.done = 1; st.fail = 1; }
+    else if (S[0] <= in.tol2 * in.bb) st.done = 1;
+    else if (st.it >= in.maxit) { st.done = 1; st.fail = 1; }
+    else { st.beta = S[1] / in.rz; st.rz = S[1]; }
+  }
+  return st;
 }
 
 // q = c0 p + c1 A p with the search direction p = M^-1 r + beta p_old formed
 // on the fly (also for halo cells), written once for the owned voxels.
+// Partial: (p.q).
 template <typename T>
 __global__ __launch_bounds__(kBV) void k_spmv(int nb, const int* __restrict__ nbr, CoefSet<T> c,
                                               const T* __restrict__ r,
                                               const T* __restrict__ dinv,
                                               const T* __restrict__ pold, T* __restrict__ pnew,
                                               T* __restrict__ q, T c0, T c1, int first,
-                                              const CGScalars* __restrict__ cg,
-                                              double* partials) {
-  if (cg->done) return;
+                                              int init_kind, const CGScalars* __restrict__ cin,
+                                              CGScalars* cout, const double* __restrict__ prev,
+                                              double* parts) {
+  const CGScalars in = *cin;
+  if (in.done) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *cout = in;
+    return;
+  }
+  const CGScalars st = cg_advance(in, prev, first, init_kind);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *cout = st;
+  if (st.done) return;
   __shared__ T s[kTile];
   __shared__ int nbs[kNbr];
-  const int brick = block_brick();
-  if (brick >= nb) { idle_partials<1>(partials); return; }
-  const int t = threadIdx.x;
-  if (t < kNbr) nbs[t] = nbr[brick * kNbr + t];
-  const T beta = first ? T(0) : static_cast<T>(cg->beta);
-  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
-  const int g = brick * kBV + t;
-  const T pn = first ? dinv[g] * r[g] : dinv[g] * r[g] + beta * pold[g];
-  const int C = tidx(lx + 1, ly + 1, lz + 1);
-  s[C] = pn;
-  __syncthreads();
-  for (int k = t; k < kHalo; k += kBV) {
-    int hx, hy, hz;
-    halo_cell(k, hx, hy, hz);
-    const int gg = tile_global(nbs, hx, hy, hz);
-    s[tidx(hx, hy, hz)] = first ? dinv[gg] * r[gg] : dinv[gg] * r[gg] + beta * pold[gg];
+  const T beta = static_cast<T>(st.beta);
+  double acc[1] = {0.0};
+  for (int m = 0;; ++m) {
+    const int brick = pbrick(m, nb);
+    if (brick < 0) break;
+    if (threadIdx.x < kNbr) nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
+    __syncthreads();
+    const Cell e = cell_setup(nbs, brick);
+    const T rg = r[e.g], dg = dinv[e.g];
+    const T po = first ? T(0) : pold[e.g];
+    T hr = T(0), hd = T(0), hp = T(0);
+    if (e.has_halo) {
+      hr = r[e.hg];
+      hd = dinv[e.hg];
+      hp = first ? T(0) : pold[e.hg];
+    }
+    T k18[18];
+    gather18(c, nbs, brick, e.lx, e.ly, e.lz, k18);
+    const T pn = dg * rg + beta * po;
+    s[e.C] = pn;
+    if (e.has_halo) s[e.hC] = hd * hr + beta * hp;
+    __syncthreads();
+    const T qv = c0 * pn + c1 * apply19(s, e.C, k18);
+    pnew[e.g] = pn;
+    q[e.g] = qv;
+    acc[0] += static_cast<double>(pn) * static_cast<double>(qv);
   }
-  __syncthreads();
-  T k18[18];
-  gather18(c, nbs, brick, lx, ly, lz, k18);
-  const T qv = c0 * pn + c1 * apply19(s, C, k18);
-  pnew[g] = pn;
-  q[g] = qv;
-  double acc[1] = {static_cast<double>(pn) * static_cast<double>(qv)};
-  block_partials<1>(acc, partials);
+  block_partials<1>(acc, parts);
 }
 
-// x += alpha p; r -= alpha q; partials (r.r, r.M^-1 r)
+// alpha = (r, M^-1 r) / (p, q) from the SpMV partials; x += alpha p;
+// r -= alpha q.  Partials: (r.r, r.M^-1 r).
 template <typename T>
 __global__ __launch_bounds__(kBV) void k_cg_update(int nb, T* __restrict__ x, T* __restrict__ r,
                                                    const T* __restrict__ p,
                                                    const T* __restrict__ q,
                                                    const T* __restrict__ dinv,
-                                                   const CGScalars* __restrict__ cg,
-                                                   double* partials) {
-  if (cg->done) return;
-  const int brick = block_brick();
-  if (brick >= nb) { idle_partials<2>(partials); return; }
-  const int g = brick * kBV + threadIdx.x;
-  const T alpha = static_cast<T>(cg->alpha);
-  x[g] = x[g] + alpha * p[g];
-  const T rn = r[g] - alpha * q[g];
-  r[g] = rn;
-  const double rd = static_cast<double>(rn);
-  double acc[2] = {rd * rd, rd * static_cast<double>(dinv[g]) * rd};
-  block_partials<2>(acc, partials);
+                                                   const CGScalars* __restrict__ cin,
+                                                   CGScalars* cout,
+                                                   const double* __restrict__ prev,
+                                                   double* parts) {
+  const CGScalars in = *cin;
+  if (in.done) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *cout = in;
+    return;
+  }
+  double S[1];
+  sum_prev<1>(prev, gridDim.x, S);
+  CGScalars st = in;
+  st.pq = S[0];
+  if (!(S[0] > 0.0) || !isfinite(S[0])) { st.done = 1; st.fail = 1; }
+  else st.alpha = in.rz / S[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *cout = st;
+  if (st.done) return;
+  const T alpha = static_cast<T>(st.alpha);
+  double acc[2] = {0.0, 0.0};
+  for (int m = 0;; ++m) {
+    const int brick = pbrick(m, nb);
+    if (brick < 0) break;
+    const int g = brick * kBV + threadIdx.x;
+    const T xg = x[g], pg = p[g], rg = r[g], qg = q[g], dg = dinv[g];
+    x[g] = xg + alpha * pg;
+    const T rn = rg - alpha * qg;
+    r[g] = rn;
+    const double rd = static_cast<double>(rn);
+    acc[0] += rd * rd;
+    acc[1] += rd * static_cast<double>(dg) * rd;
+  }
+  block_partials<2>(acc, parts);
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_reduce(int op, const double* __restrict__ partials,
-                                                       int nparts, int K, CGScalars* cg,
-                                                       double* out, double tol2, int maxit) {
-  if ((op == RED_ALPHA || op == RED_BETA) && cg->done) return;
+__global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict__ partials,
+                                                       int nparts, int K, double* out) {
   __shared__ double sm[3][kRedThreads];
   const int t = threadIdx.x;
   for (int k = 0; k < K; ++k) {
@@ -413,37 +577,8 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce(int op, const double* __
       for (int k = 0; k < K; ++k) sm[k][t] += sm[k][t + w];
     __syncthreads();
   }
-  if (t != 0) return;
-  const double S0 = sm[0][0], S1 = K > 1 ? sm[1][0] : 0.0, S2 = K > 2 ? sm[2][0] : 0.0;
-  switch (op) {
-    case RED_BE_INIT:   // (rz, bb, rr)
-      cg->rz = S0; cg->bb = S1; cg->rr = S2;
-      cg->it = 0; cg->alpha = 0.0; cg->beta = 0.0; cg->fail = 0;
-      cg->tol2 = tol2; cg->maxit = maxit;
-      cg->done = (S1 == 0.0 || S2 <= tol2 * S1) ? 1 : 0;
-      break;
-    case RED_INNER_INIT:   // (rz, rr); tolerance relative to the initial residual
-      cg->rz = S0; cg->rr = S1; cg->bb = S1;
-      cg->it = 0; cg->alpha = 0.0; cg->beta = 0.0; cg->fail = 0;
-      cg->tol2 = tol2; cg->maxit = maxit;
-      cg->done = (S1 == 0.0) ? 1 : 0;
-      break;
-    case RED_ALPHA:
-      if (!(S0 > 0.0) || !isfinite(S0)) { cg->done = 1; cg->fail = 1; }
-      else cg->alpha = cg->rz / S0;
-      break;
-    case RED_BETA:   // (rr, rz)
-      cg->it += 1;
-      cg->rr = S0;
-      if (!isfinite(S0)) { cg->done = 1; cg->fail = 1; }
-      else if (S0 <= cg->tol2 * cg->bb) cg->done = 1;
-      else if (cg->it >= cg->maxit) { cg->done = 1; cg->fail = 1; }
-      else { cg->beta = S1 / cg->rz; cg->rz = S1; }
-      break;
-    default:
-      for (int k = 0; k < K; ++k) out[k] = sm[k][0];
-      break;
-  }
+  if (t == 0)
+    for (int k = 0; k < K; ++k) out[k] = sm[k][0];
 }
 
 template <typename T>
@@ -528,50 +663,56 @@ __global__ __launch_bounds__(kBV) void k_resid64(int nb, const int* __restrict__
   __shared__ int nbs[kNbr];
   const int brick = block_brick();
   if (brick >= nb) { idle_partials<3>(partials); return; }
-  const int t = threadIdx.x;
-  if (t < kNbr) nbs[t] = nbr[brick * kNbr + t];
-  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
-  const int g = brick * kBV + t;
-  const int C = tidx(lx + 1, ly + 1, lz + 1);
-  sa[C] = static_cast<double>(vs[g]);
-  sb[C] = phi[g];
+  if (threadIdx.x < kNbr) nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
   __syncthreads();
-  for (int k = t; k < kHalo; k += kBV) {
-    int hx, hy, hz;
-    halo_cell(k, hx, hy, hz);
-    const int gg = tile_global(nbs, hx, hy, hz);
-    sa[tidx(hx, hy, hz)] = static_cast<double>(vs[gg]);
-    sb[tidx(hx, hy, hz)] = phi[gg];
+  const Cell q = cell_setup(nbs, brick);
+  sa[q.C] = static_cast<double>(vs[q.g]);
+  sb[q.C] = phi[q.g];
+  if (q.has_halo) {
+    sa[q.hC] = static_cast<double>(vs[q.hg]);
+    sb[q.hC] = phi[q.hg];
   }
   __syncthreads();
   double k18[18];
-  gather18(ci, nbs, brick, lx, ly, lz, k18);
-  const double b = apply19(sa, C, k18);
-  gather18(ck, nbs, brick, lx, ly, lz, k18);
-  const double r = b + apply19(sb, C, k18);
-  r64[g] = r;
+  gather18(ci, nbs, brick, q.lx, q.ly, q.lz, k18);
+  const double b = apply19(sa, q.C, k18);
+  gather18(ck, nbs, brick, q.lx, q.ly, q.lz, k18);
+  const double r = b + apply19(sb, q.C, k18);
+  r64[q.g] = r;
   double acc[3] = {r * r, r, b * b};
   block_partials<3>(acc, partials);
 }
 
-// inner solve start: r32 = (r64 - mean) on tissue, x32 = 0; partials (rz, rr)
+// inner solve start: r32 = (r64 - mean) on tissue, x32 = 0.  Persistent
+// like the CG kernels; partials (r.M^-1 r, r.r).
 __global__ __launch_bounds__(kBV) void k_inner_init(int nb, const double* __restrict__ r64,
                                                     const uint8_t* __restrict__ mask,
                                                     const double* __restrict__ sums,
                                                     double inv_count,
                                                     const float* __restrict__ dinv,
                                                     float* __restrict__ x,
-                                                    float* __restrict__ r, double* partials) {
-  const int brick = block_brick();
-  if (brick >= nb) { idle_partials<2>(partials); return; }
-  const int g = brick * kBV + threadIdx.x;
+                                                    float* __restrict__ r, CGScalars* cout,
+                                                    double* parts, double tol2, int maxit) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    CGScalars st = {};
+    st.tol2 = tol2;
+    st.maxit = maxit;
+    *cout = st;
+  }
   const double mean = sums[1] * inv_count;
-  const float rv = mask[g] ? static_cast<float>(r64[g] - mean) : 0.0f;
-  r[g] = rv;
-  x[g] = 0.0f;
-  const double rd = static_cast<double>(rv);
-  double acc[2] = {rd * static_cast<double>(dinv[g]) * rd, rd * rd};
-  block_partials<2>(acc, partials);
+  double acc[2] = {0.0, 0.0};
+  for (int m = 0;; ++m) {
+    const int brick = pbrick(m, nb);
+    if (brick < 0) break;
+    const int g = brick * kBV + threadIdx.x;
+    const float rv = mask[g] ? static_cast<float>(r64[g] - mean) : 0.0f;
+    r[g] = rv;
+    x[g] = 0.0f;
+    const double rd = static_cast<double>(rv);
+    acc[0] += rd * static_cast<double>(dinv[g]) * rd;
+    acc[1] += rd * rd;
+  }
+  block_partials<2>(acc, parts);
 }
 
 // phi += d (FP64); partial sum of phi
@@ -611,28 +752,27 @@ __global__ __launch_bounds__(kBV) void k_parabolic(int nb, const int* __restrict
   __shared__ int nbs[kNbr];
   const int brick = block_brick();
   if (brick >= nb) return;
-  const int t = threadIdx.x;
-  if (t < kNbr) nbs[t] = nbr[brick * kNbr + t];
-  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
-  const int g = brick * kBV + t;
-  const int C = tidx(lx + 1, ly + 1, lz + 1);
-  const T vsg = vs[g];
-  s[C] = vsg + static_cast<T>(phi[g]);
+  if (threadIdx.x < kNbr) nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
   __syncthreads();
-  for (int k = t; k < kHalo; k += kBV) {
-    int hx, hy, hz;
-    halo_cell(k, hx, hy, hz);
-    const int gg = tile_global(nbs, hx, hy, hz);
-    s[tidx(hx, hy, hz)] = vs[gg] + static_cast<T>(phi[gg]);
+  const Cell q = cell_setup(nbs, brick);
+  const T vsg = vs[q.g];
+  const double pg = phi[q.g];
+  const T v0 = vold[q.g];
+  T hv = T(0);
+  double hp = 0.0;
+  if (q.has_halo) {
+    hv = vs[q.hg];
+    hp = phi[q.hg];
   }
-  __syncthreads();
   T k18[18];
-  gather18(ci, nbs, brick, lx, ly, lz, k18);
-  const T vn = vsg + dt * apply19(s, C, k18);
-  vout[g] = vn;
-  const T v0 = vold[g];
+  gather18(ci, nbs, brick, q.lx, q.ly, q.lz, k18);
+  s[q.C] = vsg + static_cast<T>(pg);
+  if (q.has_halo) s[q.hC] = hv + static_cast<T>(hp);
+  __syncthreads();
+  const T vn = vsg + dt * apply19(s, q.C, k18);
+  vout[q.g] = vn;
   if (v0 < theta && theta <= vn) {
-    if (isinf(tact[g])) tact[g] = static_cast<T>(tn) + dt * (theta - v0) / (vn - v0);
+    if (isinf(tact[q.g])) tact[q.g] = static_cast<T>(tn) + dt * (theta - v0) / (vn - v0);
   }
   if (!isfinite(vn)) flags[0] = 1;
 }
@@ -646,24 +786,17 @@ __global__ __launch_bounds__(kBV) void k_apply(int nb, const int* __restrict__ n
   __shared__ int nbs[kNbr];
   const int brick = block_brick();
   if (brick >= nb) { idle_partials<2>(partials); return; }
-  const int t = threadIdx.x;
-  if (t < kNbr) nbs[t] = nbr[brick * kNbr + t];
-  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
-  const int g = brick * kBV + t;
-  const int C = tidx(lx + 1, ly + 1, lz + 1);
-  const T xg = x[g];
-  s[C] = xg;
+  if (threadIdx.x < kNbr) nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
   __syncthreads();
-  for (int k = t; k < kHalo; k += kBV) {
-    int hx, hy, hz;
-    halo_cell(k, hx, hy, hz);
-    s[tidx(hx, hy, hz)] = x[tile_global(nbs, hx, hy, hz)];
-  }
-  __syncthreads();
+  const Cell q = cell_setup(nbs, brick);
+  const T xg = x[q.g];
+  s[q.C] = xg;
+  if (q.has_halo) s[q.hC] = x[q.hg];
   T k18[18];
-  gather18(c, nbs, brick, lx, ly, lz, k18);
-  const T yv = apply19(s, C, k18);
-  y[g] = yv;
+  gather18(c, nbs, brick, q.lx, q.ly, q.lz, k18);
+  __syncthreads();
+  const T yv = apply19(s, q.C, k18);
+  y[q.g] = yv;
   double acc[2] = {static_cast<double>(yv) * static_cast<double>(yv),
                    static_cast<double>(xg) * static_cast<double>(yv)};
   if (partials) block_partials<2>(acc, partials);
@@ -706,6 +839,9 @@ __global__ __launch_bounds__(kBV) void k_scale(int nb, double* __restrict__ x,
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
 void launch_block_max(const LaunchCfg& L, const int* nbr, CoefSet<double> c,
                       double* partials) {
   k_block_max<<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, c, partials);
@@ -715,9 +851,6 @@ void launch_scale(const LaunchCfg& L, double* x, const double* y, const double* 
   k_scale<<<L.grid, kBV, 0, L.stream>>>(L.nb, x, y, sums);
 }
 
-// ---------------------------------------------------------------------------
-// launchers
-// ---------------------------------------------------------------------------
 void launch_tensor_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask,
                          const double* fib, const double* scale, double sig_l, double sig_t,
                          double h, double* tens, double* c64[6], float* c32[6]) {
@@ -749,34 +882,28 @@ void launch_ionic(const LaunchCfg& L, const T* v, const T* w, const T* jstim, T*
 template <typename T>
 void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v, const T* w,
                     const T* jstim, const T* dinv, T* x, T* wout, T* r, IonicT<T> ion, T dt,
-                    double* partials) {
-  k_be_init<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, dinv, x, wout, r, ion,
-                                             dt, partials);
+                    CGScalars* cout, double* parts, double tol2, int maxit) {
+  k_be_init<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, dinv, x, wout, r, ion,
+                                              dt, cout, parts, tol2, maxit);
 }
 
 template <typename T>
 void launch_spmv(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* r, const T* dinv,
-                 const T* pold, T* pnew, T* q, T c0, T c1, int first, const CGScalars* cg,
-                 double* partials) {
-  k_spmv<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, c, r, dinv, pold, pnew, q, c0, c1, first,
-                                          cg, partials);
+                 const T* pold, T* pnew, T* q, T c0, T c1, int first, int init_kind,
+                 const CGScalars* cin, CGScalars* cout, const double* prev, double* parts) {
+  k_spmv<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, r, dinv, pold, pnew, q, c0, c1, first,
+                                           init_kind, cin, cout, prev, parts);
 }
 
 template <typename T>
 void launch_cg_update(const LaunchCfg& L, T* x, T* r, const T* p, const T* q, const T* dinv,
-                      const CGScalars* cg, double* partials) {
-  k_cg_update<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, x, r, p, q, dinv, cg, partials);
+                      const CGScalars* cin, CGScalars* cout, const double* prev,
+                      double* parts) {
+  k_cg_update<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, x, r, p, q, dinv, cin, cout, prev, parts);
 }
 
-void launch_reduce(hipStream_t s, RedOp op, const double* partials, int nparts, int K,
-                   CGScalars* cg, double* out) {
-  k_reduce<<<1, kRedThreads, 0, s>>>(static_cast<int>(op), partials, nparts, K, cg, out, 0.0, 0);
-}
-
-void launch_reduce_init(hipStream_t s, RedOp op, const double* partials, int nparts, int K,
-                        CGScalars* cg, double tol2, int maxit) {
-  k_reduce<<<1, kRedThreads, 0, s>>>(static_cast<int>(op), partials, nparts, K, cg, nullptr,
-                                     tol2, maxit);
+void launch_reduce_sum(hipStream_t s, const double* partials, int nparts, int K, double* out) {
+  k_reduce<<<1, kRedThreads, 0, s>>>(partials, nparts, K, out);
 }
 
 template <typename T>
@@ -786,8 +913,7 @@ void launch_activation(const LaunchCfg& L, const T* vold, const T* vnew, T* tact
 }
 
 template <typename T>
-void launch_dinv(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1,
-                 const uint8_t* /*mask*/, T* dinv) {
+void launch_dinv(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, T* dinv) {
   k_dinv<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, c, c0, c1, dinv);
 }
 
@@ -808,16 +934,15 @@ void launch_q_accum(hipStream_t s, double* qacc, const double* qstep, double sca
 
 template <typename T>
 void launch_resid64(const LaunchCfg& L, const int* nbr, CoefSet<double> ci, CoefSet<double> ck,
-                    const T* vs, const double* phi, const uint8_t* /*mask*/, double* r64,
-                    double* partials) {
+                    const T* vs, const double* phi, double* r64, double* partials) {
   k_resid64<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, ci, ck, vs, phi, r64, partials);
 }
 
 void launch_inner_init(const LaunchCfg& L, const double* r64, const uint8_t* mask,
                        const double* sums, double inv_count, const float* dinv, float* x,
-                       float* r, double* partials) {
-  k_inner_init<<<L.grid, kBV, 0, L.stream>>>(L.nb, r64, mask, sums, inv_count, dinv, x, r,
-                                             partials);
+                       float* r, CGScalars* cout, double* parts, double tol2, int maxit) {
+  k_inner_init<<<L.pgrid, kBV, 0, L.stream>>>(L.nb, r64, mask, sums, inv_count, dinv, x, r, cout,
+                                              parts, tol2, maxit);
 }
 
 void launch_phi_correct(const LaunchCfg& L, double* phi, const float* d, const uint8_t* mask,
@@ -852,26 +977,24 @@ void launch_apply(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* x, 
                                 IonicT<T>, T);                                                 \
   template void launch_be_init<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*,          \
                                   const T*, const T*, const T*, T*, T*, T*, IonicT<T>, T,      \
-                                  double*);                                                    \
+                                  CGScalars*, double*, double, int);                           \
   template void launch_spmv<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*, const T*,   \
-                               const T*, T*, T*, T, T, int, const CGScalars*, double*);        \
+                               const T*, T*, T*, T, T, int, int, const CGScalars*, CGScalars*, \
+                               const double*, double*);                                        \
   template void launch_cg_update<T>(const LaunchCfg&, T*, T*, const T*, const T*, const T*,    \
-                                    const CGScalars*, double*);                                \
+                                    const CGScalars*, CGScalars*, const double*, double*);     \
   template void launch_activation<T>(const LaunchCfg&, const T*, const T*, T*, T, T, double,   \
                                      int*);                                                    \
-  template void launch_dinv<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T,                 \
-                               const uint8_t*, T*);                                            \
+  template void launch_dinv<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T, T*);            \
   template void launch_sum<T>(const LaunchCfg&, const T*, double*);                            \
   template void launch_stim_scatter<T>(hipStream_t, const int64_t*, const double*, int, T*,    \
                                        double*);                                               \
   template void launch_resid64<T>(const LaunchCfg&, const int*, CoefSet<double>,              \
-                                  CoefSet<double>, const T*, const double*, const uint8_t*,    \
-                                  double*, double*);                                           \
+                                  CoefSet<double>, const T*, const double*, double*, double*); \
   template void launch_parabolic<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*,        \
                                     const double*, const T*, T*, T*, T, T, double, int*);      \
   template void launch_apply<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*, T*,        \
-                                double*);                                                      \
-
+                                double*);
 
 EP_INST(float)
 EP_INST(double)

@@ -89,8 +89,9 @@ struct ep_grid_s {
   float* d_p32[2] = {nullptr, nullptr};
   float* d_q32 = nullptr;
   float* d_dinvk = nullptr;
-  double* d_partials = nullptr;
-  CGScalars* d_cg = nullptr;
+  double* d_partials = nullptr;   // per-block partial sums of one-brick-per-block launches
+  double* d_cgp[2] = {nullptr, nullptr};  // persistent CG launches: ping-pong partials
+  CGScalars* d_cg = nullptr;      // two solver-scalar records, ping-pong
   int* d_flags = nullptr;
   double* d_sums = nullptr;    // 8 doubles
   double* d_qacc = nullptr;
@@ -315,31 +316,40 @@ ep_status update_stimulus(ep_grid g, int64_t step, const T** jstim) {
 }
 
 // ---- one CG solve (device-resident scalars; host polls `done` in chunks) ----
+// One CG solve after its init launch (scalars in d_cg[0], partials in
+// d_cgp[0]).  Launch order: SpMV(first), then pairs (update, SpMV); each SpMV
+// decides from the update before it whether the solve has converged.  The
+// host polls the scalars once per chunk of pairs (one round trip per solve
+// when the chunk matches the previous solve's iteration count).
 template <typename T>
 ep_status pcg_loop(ep_grid g, CoefSet<T> c, T* x, T* r, T* p0, T* p1, T* q, const T* dinv,
-                   T c0, T c1, int maxit, int* chunk_hint, int* iters, bool* failed) {
-  const int G = g->grid;
+                   T c0, T c1, int init_kind, int maxit, int* chunk_hint, int* iters,
+                   bool* failed) {
+  CGScalars* A = g->d_cg;
+  CGScalars* B = g->d_cg + 1;
+  double* P0 = g->d_cgp[0];
+  double* P1 = g->d_cgp[1];
   T* p[2] = {p0, p1};
   int pa = 0;
-  bool first = true;
+  auto spmv = [&](int first) {
+    TimerPair* t0 = timer_begin(g, KT_STENCIL);
+    launch_spmv<T>(g->L, g->d_nbr, c, r, dinv, p[pa], p[1 - pa], q, c0, c1, first, init_kind,
+                   A, B, P0, P1);
+    timer_end(g, t0);
+    pa = 1 - pa;
+  };
+  spmv(1);
   int enq = 0;
   int chunk = std::max(1, *chunk_hint);
   for (;;) {
     for (int i = 0; i < chunk; ++i) {
-      TimerPair* t0 = timer_begin(g, KT_STENCIL);
-      launch_spmv<T>(g->L, g->d_nbr, c, r, dinv, p[pa], p[1 - pa], q, c0, c1, first ? 1 : 0,
-                     g->d_cg, g->d_partials);
-      timer_end(g, t0);
-      launch_reduce(g->stream, RED_ALPHA, g->d_partials, G, 1, g->d_cg, nullptr);
       TimerPair* t1 = timer_begin(g, KT_UPDATE);
-      launch_cg_update<T>(g->L, x, r, p[1 - pa], q, dinv, g->d_cg, g->d_partials);
+      launch_cg_update<T>(g->L, x, r, p[pa], q, dinv, B, A, P1, P0);
       timer_end(g, t1);
-      launch_reduce(g->stream, RED_BETA, g->d_partials, G, 2, g->d_cg, nullptr);
-      pa = 1 - pa;
-      first = false;
+      spmv(0);
     }
     enq += chunk;
-    HIPCHK(g, hipMemcpyAsync(&g->hs->cg, g->d_cg, sizeof(CGScalars), hipMemcpyDeviceToHost,
+    HIPCHK(g, hipMemcpyAsync(&g->hs->cg, B, sizeof(CGScalars), hipMemcpyDeviceToHost,
                              g->stream));
     HIPCHK(g, hipStreamSynchronize(g->stream));
     if (g->hs->cg.done || enq > maxit) break;
@@ -374,13 +384,11 @@ ep_status step_be(ep_grid g, const T* jstim, ep_step_info* acc) {
   launch_be_init<T>(g->L, g->d_nbr, coefs<T>(g), static_cast<const T*>(g->d_v[c]),
                     static_cast<const T*>(g->d_w[c]), jstim, dinv, x,
                     static_cast<T*>(g->d_w[n]), r, ionic_t<T>(g), static_cast<T>(g->dt),
-                    g->d_partials);
-  launch_reduce_init(g->stream, RED_BE_INIT, g->d_partials, g->grid, 3, g->d_cg,
-                     g->pcg_rtol * g->pcg_rtol, g->pcg_maxit);
+                    g->d_cg, g->d_cgp[0], g->pcg_rtol * g->pcg_rtol, g->pcg_maxit);
   int iters = 0;
   bool failed = false;
   TRY(pcg_loop<T>(g, coefs<T>(g), x, r, static_cast<T*>(g->d_p[0]), static_cast<T*>(g->d_p[1]),
-                  static_cast<T*>(g->d_q), dinv, T(1), static_cast<T>(-g->dt), g->pcg_maxit,
+                  static_cast<T*>(g->d_q), dinv, T(1), static_cast<T>(-g->dt), 0, g->pcg_maxit,
                   &g->last_iters, &iters, &failed));
   launch_activation<T>(g->L, static_cast<const T*>(g->d_v[c]), x, static_cast<T*>(g->d_tact),
                        static_cast<T>(g->dt), static_cast<T>(g->theta),
@@ -406,9 +414,9 @@ ep_status elliptic(ep_grid g, const T* vsrc, double rtol, int max_outer, ep_solv
   for (;;) {
     TimerPair* tr = timer_begin(g, KT_RESID);
     launch_resid64<T>(g->L, g->d_nbr, cset64(g->d_ci64), cset64(g->d_ck64), vsrc, g->d_phi,
-                      g->d_mask, g->d_r64, g->d_partials);
+                      g->d_r64, g->d_partials);
     timer_end(g, tr);
-    launch_reduce(g->stream, RED_SUM, g->d_partials, G, 3, g->d_cg, g->d_sums);
+    launch_reduce_sum(g->stream, g->d_partials, G, 3, g->d_sums);
     HIPCHK(g, hipMemcpyAsync(g->hs->sums, g->d_sums, 3 * sizeof(double), hipMemcpyDeviceToHost,
                              g->stream));
     HIPCHK(g, hipStreamSynchronize(g->stream));
@@ -425,17 +433,16 @@ ep_status elliptic(ep_grid g, const T* vsrc, double rtol, int max_outer, ep_solv
     if (relres <= rtol) { ok = true; break; }
     if (!std::isfinite(relres) || outer >= max_outer) break;
     launch_inner_init(g->L, g->d_r64, g->d_mask, g->d_sums, inv_count, g->d_dinvk, g->d_x32,
-                      g->d_r32, g->d_partials);
-    launch_reduce_init(g->stream, RED_INNER_INIT, g->d_partials, G, 2, g->d_cg,
-                       kInnerRtol * kInnerRtol, g->ell_inner_maxit);
+                      g->d_r32, g->d_cg, g->d_cgp[0], kInnerRtol * kInnerRtol,
+                      g->ell_inner_maxit);
     int iters = 0;
     bool failed = false;
     TRY(pcg_loop<float>(g, cset32(g->d_ck32), g->d_x32, g->d_r32, g->d_p32[0], g->d_p32[1],
-                        g->d_q32, g->d_dinvk, 0.0f, -1.0f, g->ell_inner_maxit, &g->last_inner,
-                        &iters, &failed));
+                        g->d_q32, g->d_dinvk, 0.0f, -1.0f, 1, g->ell_inner_maxit,
+                        &g->last_inner, &iters, &failed));
     inner_total += iters;
     launch_phi_correct(g->L, g->d_phi, g->d_x32, g->d_mask, g->d_partials);
-    launch_reduce(g->stream, RED_SUM, g->d_partials, G, 1, g->d_cg, g->d_sums + 4);
+    launch_reduce_sum(g->stream, g->d_partials, G, 1, g->d_sums + 4);
     corrected = true;
     ++outer;
   }
@@ -492,7 +499,7 @@ ep_status run_steps(ep_grid g, int32_t nsteps, ep_step_info* info) {
   }
   const int noconv = g->hs->flags[1];
   launch_sum<T>(g->L, static_cast<const T*>(g->d_v[g->cur]), g->d_partials);
-  launch_reduce(g->stream, RED_SUM, g->d_partials, g->grid, 1, g->d_cg, g->d_sums + 6);
+  launch_reduce_sum(g->stream, g->d_partials, g->grid, 1, g->d_sums + 6);
   HIPCHK(g, hipGetLastError());
   HIPCHK(g, hipMemcpyAsync(g->hs->sums + 3, g->d_sums + 6, sizeof(double), hipMemcpyDeviceToHost,
                            g->stream));
@@ -543,7 +550,7 @@ ep_status check_explicit_stability(ep_grid g, double* const c64[6]) {
   double lam = 0.0;
   for (int it = 0; it < 200; ++it) {
     launch_apply<double>(g->L, g->d_nbr, cset64(c64), x, y, g->d_partials);
-    launch_reduce(g->stream, RED_SUM, g->d_partials, G, 2, g->d_cg, g->d_sums);
+    launch_reduce_sum(g->stream, g->d_partials, G, 2, g->d_sums);
     launch_scale(g->L, x, y, g->d_sums);
   }
   HIPCHK(g, hipMemcpyAsync(g->hs->sums, g->d_sums, 2 * sizeof(double), hipMemcpyDeviceToHost,
@@ -678,6 +685,7 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   g->grid = grid_for(nb);
   g->L.nb = nb;
   g->L.grid = g->grid;
+  g->L.pgrid = pgrid_for(nb);
   g->L.stream = g->stream;
   if (g->model == EP_BIDO && tissue_components(boxmask, g->n) != 1)
     return fail(g, EP_ERR_ARG, "bidomain tissue must be one face-connected component");
@@ -716,7 +724,9 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   TRY(dalloc(g, &g->d_jstim, vb));
   for (int k = 0; k < 6; ++k) TRY(dalloc(g, &g->d_c[k], vb));
   TRY(dalloc(g, &g->d_partials, static_cast<size_t>(g->grid) * 4 * sizeof(double)));
-  TRY(dalloc(g, &g->d_cg, sizeof(CGScalars)));
+  TRY(dalloc(g, &g->d_cg, 2 * sizeof(CGScalars)));
+  for (int k = 0; k < 2; ++k)
+    TRY(dalloc(g, &g->d_cgp[k], static_cast<size_t>(g->L.pgrid) * 3 * sizeof(double)));
   TRY(dalloc(g, &g->d_flags, 4 * sizeof(int)));
   TRY(dalloc(g, &g->d_sums, 8 * sizeof(double)));
   TRY(dalloc(g, &g->d_qacc, sizeof(double)));
@@ -918,15 +928,15 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
       // D_i + D_e = s((sT_i + sT_e) I + ((sL_i - sT_i) + (sL_e - sT_e)) f f^T).
       launch_tensor_coefs(g->L, g->d_nbr, g->d_mask, dfib, dsc, sl + sel, st + set_, g->h, tens,
                           g->d_ck64, g->d_ck32);
-      launch_dinv<float>(g->L, g->d_nbr, cset32(g->d_ck32), 0.0f, -1.0f, g->d_mask, g->d_dinvk);
+      launch_dinv<float>(g->L, g->d_nbr, cset32(g->d_ck32), 0.0f, -1.0f, g->d_dinvk);
     }
     if (g->diff == EP_DIFF_BE_PCG) {
       if (g->prec == EP_F64)
-        launch_dinv<double>(g->L, g->d_nbr, coefs<double>(g), 1.0, -g->dt, g->d_mask,
+        launch_dinv<double>(g->L, g->d_nbr, coefs<double>(g), 1.0, -g->dt,
                             static_cast<double*>(g->d_dinv));
       else
         launch_dinv<float>(g->L, g->d_nbr, coefs<float>(g), 1.0f, static_cast<float>(-g->dt),
-                           g->d_mask, static_cast<float*>(g->d_dinv));
+                           static_cast<float*>(g->d_dinv));
     }
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(g->stream) != hipSuccess) {
       rc = fail(g, EP_ERR_HIP, "coefficient kernels failed");
