@@ -28,13 +28,12 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 
 # Algorithmic HBM bytes per tissue voxel for one launch of each kernel
 # (FP32 state; each array read or written once):
-#   PCG SpMV  q = (I - dt A) p with p = M^-1 r + beta p_old formed on the fly:
-#             reads r, M^-1, p_old (12 B) and 6 coefficients (24 B),
-#             writes p, q (8 B)                                   -> 44 B
-#   PCG update x += alpha p, r -= alpha q: reads x, r, p, q, M^-1 (20 B),
-#             writes x, r (8 B)                                   -> 28 B
-#   explicit fused step: reads v, w (8 B) + 24 B coefficients, writes v, w -> 40 B
-ALGO_BYTES = {"stencil_be": 44, "update": 28, "stencil_explicit": 40}
+#   one PCG iteration (one-reduction form, k_cgcg): reads x, r, M^-1, p, s, w
+#             (24 B) and the 6 operator weights (24 B), writes x, r, p, s, w
+#             (20 B)                                                   -> 68 B
+#   CG set-up u0 = M^-1 r0, w0 = K u0: reads r, M^-1, weights, writes w -> 36 B
+#   explicit fused step: reads v, w (8 B) + 24 B weights, writes v, w   -> 40 B
+ALGO_BYTES = {"cg_iter": 68, "cg_setup": 36, "stencil_explicit": 40}
 
 
 def parse():
@@ -137,13 +136,14 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
-    spmv_ms, spmv_n = g.kernel_time("stencil")
-    upd_ms, upd_n = g.kernel_time("update")
+    it_ms, it_n = g.kernel_time("stencil")
+    set_ms, set_n = g.kernel_time("cg_setup")
+    tail_ms, tail_n = g.kernel_time("cg_tail")
     g.kernel_timing(False)
 
     value = inst.nt * a.steps / elapsed
-    avg_spmv = spmv_ms / max(spmv_n, 1)
-    achieved = ALGO_BYTES["stencil_be"] * inst.nt / (avg_spmv * 1e-3) / 1e9
+    avg_it = it_ms / max(it_n, 1)
+    achieved = ALGO_BYTES["cg_iter"] * inst.nt / (avg_it * 1e-3) / 1e9
     traffic = read_traffic(a.traffic_file)
     out = {
         "metric": "voxel-steps/s",
@@ -162,14 +162,15 @@ def main():
                                f"({inst.nt} tissue voxels), 19-point anisotropic stencil, "
                                f"implicit Euler by Jacobi-PCG rtol {a.rtol:g}, dt {inst.dt} ms",
                    "n_tissue": inst.nt, "grid": list(inst.n), "dt_ms": inst.dt},
-        "roofline": {"bound": "hbm", "kernel": "k_spmv<float>", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "algo_bytes_per_launch": ALGO_BYTES["stencil_be"] * inst.nt,
-                     "avg_launch_us": 1e3 * avg_spmv, "launches": spmv_n},
+        "roofline": {"bound": "hbm", "kernel": "k_cgcg<float> (one PCG iteration)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algo_bytes_per_launch": ALGO_BYTES["cg_iter"] * inst.nt,
+                     "avg_launch_us": 1e3 * avg_it, "launches": it_n},
         "cg": {"iters_total": info["cg_iters"], "iters_per_step": info["cg_iters"] / a.steps,
                "iters_max": info["cg_max"],
-               "update_avg_us": 1e3 * upd_ms / max(upd_n, 1),
-               "update_gbs": ALGO_BYTES["update"] * inst.nt / (upd_ms / max(upd_n, 1) * 1e-3) / 1e9},
+               "setup_avg_us": 1e3 * set_ms / max(set_n, 1),
+               "tail_avg_us": 1e3 * tail_ms / max(tail_n, 1), "tail_launches": tail_n},
     }
     if not a.no_parity:
         # one-step parity from the GPU's current state against the FP64 oracle

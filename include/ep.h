@@ -176,10 +176,12 @@ EP_API ep_status ep_grid_stats(ep_grid g, int64_t* n_tissue, int64_t* n_bricks,
                                int64_t* device_bytes);
 
 /* Kernel timing for measurement: when enabled, the library records HIP
- * events around every launch of the dominant kernel of the configured path
- * (kernel_id 0: the diffusion stencil / SpMV, 1: the CG vector update) on
- * the grid's stream; ep_kernel_time returns the summed milliseconds and the
- * launch count since the last enable. */
+ * events around every launch of the timed kernels on the grid's stream;
+ * ep_kernel_time returns the summed milliseconds and the launch count since
+ * the last enable.  kernel_id 0: the fused explicit step, or one full
+ * implicit-Euler / inner PCG iteration (the dominant kernel); 1: the CG
+ * set-up launch; 2: the bidomain parabolic stencil; 3: the FP64 elliptic
+ * residual; 4: CG launches that only detected convergence. */
 EP_API ep_status ep_kernel_timing(ep_grid g, int32_t enable);
 EP_API ep_status ep_kernel_time(ep_grid g, int32_t kernel_id, double* total_ms,
                                 int64_t* launches);

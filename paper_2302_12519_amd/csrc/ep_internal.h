@@ -81,10 +81,12 @@ struct LaunchCfg {
 };
 
 inline int grid_for(int nb) { return ((nb + kXcd - 1) / kXcd) * kXcd; }
-// persistent launches: at most 4 blocks of 512 threads per CU on 256 CUs
-inline int pgrid_for(int nb) {
+// persistent launches: as many 512-thread blocks as stay resident on the
+// 256 CUs (the one-reduction CG kernel needs 86 VGPRs in FP32, 126 in FP64:
+// 2 blocks per CU)
+inline int pgrid_for(int nb, bool /*fp64*/) {
   const int g = grid_for(nb);
-  return g < 1024 ? g : 1024;
+  return g < 512 ? g : 512;
 }
 
 // ---- kernel launchers (ep_kernels.hip) ----------------------------------
@@ -105,23 +107,24 @@ void launch_ionic(const LaunchCfg& L, const T* v, const T* w, const T* jstim, T*
 // Persistent CG kernels (L.pgrid blocks).  Each launch reduces the partials
 // `prev` of the launch before it (L.pgrid per component) into the solver
 // scalars read from `cin`, publishes them in `cout` and leaves its own
-// partials in `parts`.  init_kind: 0 after k_be_init, 1 after k_inner_init.
+// partials in `parts`.
+//
+// k_be_init: reaction + r0 = dt A v*, x0 = v*; optionally the activation
+// check of the previous step (x still holds v_prev).  Partials (b.b, r.r).
 template <typename T>
 void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v,
-                    const T* w, const T* jstim, const T* dinv, T* x, T* wout, T* r,
-                    IonicT<T> ion, T dt, CGScalars* cout, double* parts, double tol2,
-                    int maxit);
+                    const T* w, const T* jstim, T* x, T* wout, T* r, IonicT<T> ion, T dt,
+                    T* tact, T theta, double tprev, int check_prev, int* flags,
+                    CGScalars* cout, double* parts, double tol2, int maxit);
 
+// One launch of the one-reduction PCG for K = c0 I + c1 A (kind 0 set-up,
+// 1 first iteration, 2 general; init_kind 0 after k_be_init, 1 after
+// k_inner_init).  r, s, w are ping-pong pairs (read with halo, write own).
 template <typename T>
-void launch_spmv(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* r,
-                 const T* dinv, const T* pold, T* pnew, T* q, T c0, T c1, int first,
-                 int init_kind, const CGScalars* cin, CGScalars* cout, const double* prev,
-                 double* parts);
-
-template <typename T>
-void launch_cg_update(const LaunchCfg& L, T* x, T* r, const T* p, const T* q,
-                      const T* dinv, const CGScalars* cin, CGScalars* cout, const double* prev,
-                      double* parts);
+void launch_cgcg(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, const T* dinv,
+                 T* x, const T* r_in, T* r_out, T* p, const T* s_in, T* s_out, const T* w_in,
+                 T* w_out, int kind, int init_kind, const CGScalars* cin, CGScalars* cout,
+                 const double* prev, double* parts);
 
 // out[k] = sum of partials[k*nparts .. (k+1)*nparts) in a fixed order
 void launch_reduce_sum(hipStream_t s, const double* partials, int nparts, int K, double* out);
@@ -151,8 +154,8 @@ void launch_resid64(const LaunchCfg& L, const int* nbr, CoefSet<double> ci, Coef
                     const T* vs, const double* phi, double* r64, double* partials);
 
 void launch_inner_init(const LaunchCfg& L, const double* r64, const uint8_t* mask,
-                       const double* sums, double inv_count, const float* dinv, float* x,
-                       float* r, CGScalars* cout, double* parts, double tol2, int maxit);
+                       const double* sums, double inv_count, float* x, float* r,
+                       CGScalars* cout, double* parts, double tol2, int maxit);
 
 void launch_phi_correct(const LaunchCfg& L, double* phi, const float* d, const uint8_t* mask,
                         double* partials);

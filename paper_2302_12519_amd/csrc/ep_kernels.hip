@@ -375,18 +375,29 @@ __global__ __launch_bounds__(kBV) void k_ionic(int nb, const T* __restrict__ v,
 // the solver scalars from them, and block 0 publishes the scalars for the
 // host and the next launch.  Partials and scalars are double-buffered: a
 // launch reads `prev` / `cin` and writes `parts` / `cout`.
+//
+// The iteration is the one-reduction form of preconditioned CG (Chronopoulos
+// and Gear): with u = M^-1 r and w = K u it carries s = K p by recurrence,
+//   gamma = (r, u), delta = (u, w),  beta = gamma / gamma_old,
+//   alpha = gamma / (delta - beta gamma / alpha_old),
+//   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
+// so one stencil launch per iteration does both the vector updates and the
+// operator application, and its three dot products share one reduction.
 
-// Reaction fused with the initial residual r0 = b - (I - dt A) b = dt A v*.
-// Partials: (r.M^-1 r, b.b, r.r).
+// Reaction fused with the initial residual r0 = b - (I - dt A) b = dt A v*,
+// x0 = b.  When check_prev is set it also records activation for the
+// previous step (vprev -> v) before x0 overwrites vprev's buffer.
+// Partials: (b.b, r.r).
 template <typename T>
-__global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__ nbr,
+__global__ __launch_bounds__(kBV, sizeof(T) == 4 ? 6 : 4) void k_be_init(int nb, const int* __restrict__ nbr,
                                                  CoefSet<T> c, const T* __restrict__ v,
                                                  const T* __restrict__ w,
-                                                 const T* __restrict__ jstim,
-                                                 const T* __restrict__ dinv, T* __restrict__ x,
+                                                 const T* __restrict__ jstim, T* x,
                                                  T* __restrict__ wout, T* __restrict__ r,
-                                                 IonicT<T> ion, T dt, CGScalars* cout,
-                                                 double* parts, double tol2, int maxit) {
+                                                 IonicT<T> ion, T dt, T* __restrict__ tact,
+                                                 T theta, double tprev, int check_prev,
+                                                 int* flags, CGScalars* cout, double* parts,
+                                                 double tol2, int maxit) {
   __shared__ T s[kTile];
   __shared__ int nbs[kNbr];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -395,7 +406,7 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
     st.maxit = maxit;
     *cout = st;
   }
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[2] = {0.0, 0.0};
   for (int m = 0;; ++m) {
     const int brick = pbrick(m, nb);
     if (brick < 0) break;
@@ -404,7 +415,7 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
     const Cell q = cell_setup(nbs, brick);
     const T v0 = v[q.g], w0 = w[q.g];
     const T j0 = jstim ? jstim[q.g] : T(0);
-    const T dg = dinv[q.g];
+    const T vp = check_prev ? x[q.g] : T(0);
     T hv = T(0), hw = T(0), hj = T(0);
     if (q.has_halo) {
       hv = v[q.hg];
@@ -423,143 +434,142 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
     }
     __syncthreads();
     const T rr = dt * apply19(s, q.C, k18);
+    if (check_prev && vp < theta && theta <= v0) {
+      if (isinf(tact[q.g])) tact[q.g] = static_cast<T>(tprev) + dt * (theta - vp) / (v0 - vp);
+    }
+    if (!isfinite(v0)) flags[0] = 1;
     x[q.g] = vs;
     wout[q.g] = ws;
     r[q.g] = rr;
     const double rd = static_cast<double>(rr);
-    acc[0] += rd * static_cast<double>(dg) * rd;
-    acc[1] += static_cast<double>(vs) * static_cast<double>(vs);
-    acc[2] += rd * rd;
+    acc[0] += static_cast<double>(vs) * static_cast<double>(vs);
+    acc[1] += rd * rd;
   }
-  block_partials<3>(acc, parts);
+  block_partials<2>(acc, parts);
 }
 
-// Start or continue a solve from the previous launch's partials; returns the
-// scalars of this iteration (identical in every block).
-//  first, init_kind 0: partials (rz, bb, rr) of k_be_init
-//  first, init_kind 1: partials (rz, rr) of k_inner_init (tolerance relative
-//                      to the initial residual)
-//  otherwise:          partials (rr, rz) of k_cg_update -> beta, convergence
-__device__ __forceinline__ CGScalars cg_advance(const CGScalars& in, const double* prev,
-                                                int first, int init_kind) {
-  CGScalars st = in;
-  if (first) {
-    if (init_kind == 0) {
-      double S[3];
-      sum_prev<3>(prev, gridDim.x, S);
-      st.rz = S[0]; st.bb = S[1]; st.rr = S[2];
-      st.done = (S[1] == 0.0 || S[2] <= in.tol2 * S[1]) ? 1 : 0;
-    } else {
-      double S[2];
-      sum_prev<2>(prev, gridDim.x, S);
-      st.rz = S[0]; st.rr = S[1]; st.bb = S[1];
-      st.done = (S[1] == 0.0) ? 1 : 0;
-    }
-    st.it = 0; st.beta = 0.0; st.alpha = 0.0; st.fail = 0;
-  } else {
-    double S[2];
-    sum_prev<2>(prev, gridDim.x, S);
-    st.it = in.it + 1;
-    st.rr = S[0];
-    if (!isfinite(S[0])) { st.done = 1; st.fail = 1; }
-    else if (S[0] <= in.tol2 * in.bb) st.done = 1;
-    else if (st.it >= in.maxit) { st.done = 1; st.fail = 1; }
-    else { st.beta = S[1] / in.rz; st.rz = S[1]; }
-  }
-  return st;
-}
-
-// q = c0 p + c1 A p with the search direction p = M^-1 r + beta p_old formed
-// on the fly (also for halo cells), written once for the owned voxels.
-// Partial: (p.q).
+// One CG launch.  kind 0: set-up, u0 = M^-1 r0, w0 = K u0 (partials of the
+// init launch: (b.b, r.r) when init_kind == 0, or (r.r) with the tolerance
+// relative to it when init_kind == 1).  kind 1: first iteration (beta = 0,
+// no p / s history).  kind 2: general iteration.  K = c0 I + c1 A.
+// Partials: (gamma, delta, rho) = ((r, u), (u, w), (r, r)).
 template <typename T>
-__global__ __launch_bounds__(kBV) void k_spmv(int nb, const int* __restrict__ nbr, CoefSet<T> c,
-                                              const T* __restrict__ r,
-                                              const T* __restrict__ dinv,
-                                              const T* __restrict__ pold, T* __restrict__ pnew,
-                                              T* __restrict__ q, T c0, T c1, int first,
-                                              int init_kind, const CGScalars* __restrict__ cin,
-                                              CGScalars* cout, const double* __restrict__ prev,
-                                              double* parts) {
+__global__ __launch_bounds__(kBV) void k_cgcg(int nb, const int* __restrict__ nbr, CoefSet<T> c,
+                                              T c0, T c1, const T* __restrict__ dinv,
+                                              T* __restrict__ x, const T* __restrict__ r_in,
+                                              T* __restrict__ r_out, T* __restrict__ p,
+                                              const T* __restrict__ s_in, T* __restrict__ s_out,
+                                              const T* __restrict__ w_in,
+                                              T* __restrict__ w_out, int kind, int init_kind,
+                                              const CGScalars* __restrict__ cin, CGScalars* cout,
+                                              const double* __restrict__ prev, double* parts) {
   const CGScalars in = *cin;
   if (in.done) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *cout = in;
     return;
   }
-  const CGScalars st = cg_advance(in, prev, first, init_kind);
+  CGScalars st = in;
+  if (kind == 0) {
+    if (init_kind == 0) {
+      double S[2];
+      sum_prev<2>(prev, gridDim.x, S);
+      st.bb = S[0];
+      st.rr = S[1];
+      st.done = (S[0] == 0.0 || S[1] <= in.tol2 * S[0]) ? 1 : 0;
+    } else {
+      double S[1];
+      sum_prev<1>(prev, gridDim.x, S);
+      st.bb = S[0];
+      st.rr = S[0];
+      st.done = (S[0] == 0.0) ? 1 : 0;
+    }
+    st.it = 0;
+    st.fail = 0;
+  } else {
+    double S[3];
+    sum_prev<3>(prev, gridDim.x, S);
+    const double gam = S[0], del = S[1], rho = S[2];
+    st.rr = rho;
+    st.it = (kind == 1) ? 0 : in.it + 1;
+    if (!isfinite(rho)) { st.done = 1; st.fail = 1; }
+    else if (rho <= in.tol2 * in.bb) st.done = 1;
+    else if (st.it >= in.maxit) { st.done = 1; st.fail = 1; }
+    else {
+      const double beta = (kind == 1) ? 0.0 : gam / in.rz;
+      const double den = (kind == 1) ? del : del - beta * gam / in.alpha;
+      if (!(den > 0.0) || !isfinite(den)) { st.done = 1; st.fail = 1; }
+      else {
+        st.beta = beta;
+        st.alpha = gam / den;
+        st.rz = gam;
+      }
+    }
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) *cout = st;
   if (st.done) return;
   __shared__ T s[kTile];
   __shared__ int nbs[kNbr];
-  const T beta = static_cast<T>(st.beta);
-  double acc[1] = {0.0};
+  const T alpha = static_cast<T>(st.alpha), beta = static_cast<T>(st.beta);
+  double acc[3] = {0.0, 0.0, 0.0};
   for (int m = 0;; ++m) {
     const int brick = pbrick(m, nb);
     if (brick < 0) break;
     if (threadIdx.x < kNbr) nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
     __syncthreads();
     const Cell e = cell_setup(nbs, brick);
-    const T rg = r[e.g], dg = dinv[e.g];
-    const T po = first ? T(0) : pold[e.g];
-    T hr = T(0), hd = T(0), hp = T(0);
-    if (e.has_halo) {
-      hr = r[e.hg];
-      hd = dinv[e.hg];
-      hp = first ? T(0) : pold[e.hg];
+    T rn, un;
+    if (kind == 0) {
+      const T rg = r_in[e.g], dg = dinv[e.g];
+      T hr = T(0), hd = T(0);
+      if (e.has_halo) {
+        hr = r_in[e.hg];
+        hd = dinv[e.hg];
+      }
+      T k18[18];
+      gather18(c, nbs, brick, e.lx, e.ly, e.lz, k18);
+      rn = rg;
+      un = dg * rg;
+      s[e.C] = un;
+      if (e.has_halo) s[e.hC] = hd * hr;
+      __syncthreads();
+      const T wv = c0 * un + c1 * apply19(s, e.C, k18);
+      w_out[e.g] = wv;
+      acc[0] += static_cast<double>(rn) * static_cast<double>(un);
+      acc[1] += static_cast<double>(un) * static_cast<double>(wv);
+      acc[2] += static_cast<double>(rn) * static_cast<double>(rn);
+    } else {
+      const bool hist = kind != 1;
+      const T rg = r_in[e.g], dg = dinv[e.g], wg = w_in[e.g], xg = x[e.g];
+      const T sg = hist ? s_in[e.g] : T(0);
+      const T pg = hist ? p[e.g] : T(0);
+      T hr = T(0), hd = T(0), hw = T(0), hs = T(0);
+      if (e.has_halo) {
+        hr = r_in[e.hg];
+        hd = dinv[e.hg];
+        hw = w_in[e.hg];
+        hs = hist ? s_in[e.hg] : T(0);
+      }
+      T k18[18];
+      gather18(c, nbs, brick, e.lx, e.ly, e.lz, k18);
+      const T pn = dg * rg + beta * pg;
+      const T sn = wg + beta * sg;
+      rn = rg - alpha * sn;
+      un = dg * rn;
+      s[e.C] = un;
+      if (e.has_halo) s[e.hC] = hd * (hr - alpha * (hw + beta * hs));
+      __syncthreads();
+      const T wv = c0 * un + c1 * apply19(s, e.C, k18);
+      x[e.g] = xg + alpha * pn;
+      p[e.g] = pn;
+      s_out[e.g] = sn;
+      r_out[e.g] = rn;
+      w_out[e.g] = wv;
+      acc[0] += static_cast<double>(rn) * static_cast<double>(un);
+      acc[1] += static_cast<double>(un) * static_cast<double>(wv);
+      acc[2] += static_cast<double>(rn) * static_cast<double>(rn);
     }
-    T k18[18];
-    gather18(c, nbs, brick, e.lx, e.ly, e.lz, k18);
-    const T pn = dg * rg + beta * po;
-    s[e.C] = pn;
-    if (e.has_halo) s[e.hC] = hd * hr + beta * hp;
-    __syncthreads();
-    const T qv = c0 * pn + c1 * apply19(s, e.C, k18);
-    pnew[e.g] = pn;
-    q[e.g] = qv;
-    acc[0] += static_cast<double>(pn) * static_cast<double>(qv);
   }
-  block_partials<1>(acc, parts);
-}
-
-// alpha = (r, M^-1 r) / (p, q) from the SpMV partials; x += alpha p;
-// r -= alpha q.  Partials: (r.r, r.M^-1 r).
-template <typename T>
-__global__ __launch_bounds__(kBV) void k_cg_update(int nb, T* __restrict__ x, T* __restrict__ r,
-                                                   const T* __restrict__ p,
-                                                   const T* __restrict__ q,
-                                                   const T* __restrict__ dinv,
-                                                   const CGScalars* __restrict__ cin,
-                                                   CGScalars* cout,
-                                                   const double* __restrict__ prev,
-                                                   double* parts) {
-  const CGScalars in = *cin;
-  if (in.done) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *cout = in;
-    return;
-  }
-  double S[1];
-  sum_prev<1>(prev, gridDim.x, S);
-  CGScalars st = in;
-  st.pq = S[0];
-  if (!(S[0] > 0.0) || !isfinite(S[0])) { st.done = 1; st.fail = 1; }
-  else st.alpha = in.rz / S[0];
-  if (blockIdx.x == 0 && threadIdx.x == 0) *cout = st;
-  if (st.done) return;
-  const T alpha = static_cast<T>(st.alpha);
-  double acc[2] = {0.0, 0.0};
-  for (int m = 0;; ++m) {
-    const int brick = pbrick(m, nb);
-    if (brick < 0) break;
-    const int g = brick * kBV + threadIdx.x;
-    const T xg = x[g], pg = p[g], rg = r[g], qg = q[g], dg = dinv[g];
-    x[g] = xg + alpha * pg;
-    const T rn = rg - alpha * qg;
-    r[g] = rn;
-    const double rd = static_cast<double>(rn);
-    acc[0] += rd * rd;
-    acc[1] += rd * static_cast<double>(dg) * rd;
-  }
-  block_partials<2>(acc, parts);
+  block_partials<3>(acc, parts);
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict__ partials,
@@ -684,13 +694,11 @@ __global__ __launch_bounds__(kBV) void k_resid64(int nb, const int* __restrict__
 }
 
 // inner solve start: r32 = (r64 - mean) on tissue, x32 = 0.  Persistent
-// like the CG kernels; partials (r.M^-1 r, r.r).
+// like the CG kernels; partial (r.r).
 __global__ __launch_bounds__(kBV) void k_inner_init(int nb, const double* __restrict__ r64,
                                                     const uint8_t* __restrict__ mask,
                                                     const double* __restrict__ sums,
-                                                    double inv_count,
-                                                    const float* __restrict__ dinv,
-                                                    float* __restrict__ x,
+                                                    double inv_count, float* __restrict__ x,
                                                     float* __restrict__ r, CGScalars* cout,
                                                     double* parts, double tol2, int maxit) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -700,7 +708,7 @@ __global__ __launch_bounds__(kBV) void k_inner_init(int nb, const double* __rest
     *cout = st;
   }
   const double mean = sums[1] * inv_count;
-  double acc[2] = {0.0, 0.0};
+  double acc[1] = {0.0};
   for (int m = 0;; ++m) {
     const int brick = pbrick(m, nb);
     if (brick < 0) break;
@@ -709,10 +717,9 @@ __global__ __launch_bounds__(kBV) void k_inner_init(int nb, const double* __rest
     r[g] = rv;
     x[g] = 0.0f;
     const double rd = static_cast<double>(rv);
-    acc[0] += rd * static_cast<double>(dinv[g]) * rd;
-    acc[1] += rd * rd;
+    acc[0] += rd * rd;
   }
-  block_partials<2>(acc, parts);
+  block_partials<1>(acc, parts);
 }
 
 // phi += d (FP64); partial sum of phi
@@ -881,25 +888,22 @@ void launch_ionic(const LaunchCfg& L, const T* v, const T* w, const T* jstim, T*
 
 template <typename T>
 void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v, const T* w,
-                    const T* jstim, const T* dinv, T* x, T* wout, T* r, IonicT<T> ion, T dt,
-                    CGScalars* cout, double* parts, double tol2, int maxit) {
-  k_be_init<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, dinv, x, wout, r, ion,
-                                              dt, cout, parts, tol2, maxit);
+                    const T* jstim, T* x, T* wout, T* r, IonicT<T> ion, T dt, T* tact, T theta,
+                    double tprev, int check_prev, int* flags, CGScalars* cout, double* parts,
+                    double tol2, int maxit) {
+  k_be_init<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, x, wout, r, ion, dt,
+                                              tact, theta, tprev, check_prev, flags, cout, parts,
+                                              tol2, maxit);
 }
 
 template <typename T>
-void launch_spmv(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* r, const T* dinv,
-                 const T* pold, T* pnew, T* q, T c0, T c1, int first, int init_kind,
-                 const CGScalars* cin, CGScalars* cout, const double* prev, double* parts) {
-  k_spmv<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, r, dinv, pold, pnew, q, c0, c1, first,
-                                           init_kind, cin, cout, prev, parts);
-}
-
-template <typename T>
-void launch_cg_update(const LaunchCfg& L, T* x, T* r, const T* p, const T* q, const T* dinv,
-                      const CGScalars* cin, CGScalars* cout, const double* prev,
-                      double* parts) {
-  k_cg_update<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, x, r, p, q, dinv, cin, cout, prev, parts);
+void launch_cgcg(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, const T* dinv,
+                 T* x, const T* r_in, T* r_out, T* p, const T* s_in, T* s_out, const T* w_in,
+                 T* w_out, int kind, int init_kind, const CGScalars* cin, CGScalars* cout,
+                 const double* prev, double* parts) {
+  k_cgcg<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, c0, c1, dinv, x, r_in, r_out, p, s_in,
+                                           s_out, w_in, w_out, kind, init_kind, cin, cout, prev,
+                                           parts);
 }
 
 void launch_reduce_sum(hipStream_t s, const double* partials, int nparts, int K, double* out) {
@@ -939,9 +943,9 @@ void launch_resid64(const LaunchCfg& L, const int* nbr, CoefSet<double> ci, Coef
 }
 
 void launch_inner_init(const LaunchCfg& L, const double* r64, const uint8_t* mask,
-                       const double* sums, double inv_count, const float* dinv, float* x,
-                       float* r, CGScalars* cout, double* parts, double tol2, int maxit) {
-  k_inner_init<<<L.pgrid, kBV, 0, L.stream>>>(L.nb, r64, mask, sums, inv_count, dinv, x, r, cout,
+                       const double* sums, double inv_count, float* x, float* r,
+                       CGScalars* cout, double* parts, double tol2, int maxit) {
+  k_inner_init<<<L.pgrid, kBV, 0, L.stream>>>(L.nb, r64, mask, sums, inv_count, x, r, cout,
                                               parts, tol2, maxit);
 }
 
@@ -976,13 +980,11 @@ void launch_apply(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* x, 
   template void launch_ionic<T>(const LaunchCfg&, const T*, const T*, const T*, T*, T*,        \
                                 IonicT<T>, T);                                                 \
   template void launch_be_init<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*,          \
-                                  const T*, const T*, const T*, T*, T*, T*, IonicT<T>, T,      \
-                                  CGScalars*, double*, double, int);                           \
-  template void launch_spmv<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*, const T*,   \
-                               const T*, T*, T*, T, T, int, int, const CGScalars*, CGScalars*, \
-                               const double*, double*);                                        \
-  template void launch_cg_update<T>(const LaunchCfg&, T*, T*, const T*, const T*, const T*,    \
-                                    const CGScalars*, CGScalars*, const double*, double*);     \
+                                  const T*, const T*, T*, T*, T*, IonicT<T>, T, T*, T, double, \
+                                  int, int*, CGScalars*, double*, double, int);                \
+  template void launch_cgcg<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T, const T*, T*,   \
+                               const T*, T*, T*, const T*, T*, const T*, T*, int, int,         \
+                               const CGScalars*, CGScalars*, const double*, double*);          \
   template void launch_activation<T>(const LaunchCfg&, const T*, const T*, T*, T, T, double,   \
                                      int*);                                                    \
   template void launch_dinv<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T, T*);            \

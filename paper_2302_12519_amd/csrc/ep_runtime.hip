@@ -35,8 +35,12 @@ struct TimerPair {
   hipEvent_t a, b;
 };
 
-// kernel kinds that can be timed (ep_kernel_time ids)
-enum { KT_STENCIL = 0, KT_UPDATE = 1, KT_PARABOLIC = 2, KT_RESID = 3, kTimers = 4 };
+// kernel kinds that can be timed (ep_kernel_time ids): 0 the explicit step
+// or one full CG iteration, 1 the CG set-up launch, 2 the bidomain parabolic
+// stencil, 3 the FP64 elliptic residual, 4 CG launches that only detected
+// convergence (or skipped after it)
+enum { KT_STENCIL = 0, KT_CGSETUP = 1, KT_PARABOLIC = 2, KT_RESID = 3, KT_CGTAIL = 4,
+       kTimers = 5 };
 
 }  // namespace
 
@@ -77,17 +81,19 @@ struct ep_grid_s {
   double* d_ci64[6] = {};     // bidomain: A_i in FP64
   double* d_ck64[6] = {};     // bidomain: A_i + A_e in FP64
   float* d_ck32[6] = {};      // bidomain: A_i + A_e in FP32
-  void* d_r = nullptr;        // PCG vectors (state precision)
-  void* d_p[2] = {nullptr, nullptr};
-  void* d_q = nullptr;
+  void* d_cr[2] = {nullptr, nullptr};  // PCG vectors (state precision): r, s, w ping-pong
+  void* d_cs[2] = {nullptr, nullptr};
+  void* d_cw[2] = {nullptr, nullptr};
+  void* d_cp = nullptr;
   void* d_dinv = nullptr;
   void* d_vs = nullptr;       // bidomain v*
   double* d_phi = nullptr;
   double* d_r64 = nullptr;
-  float* d_x32 = nullptr;
-  float* d_r32 = nullptr;
-  float* d_p32[2] = {nullptr, nullptr};
-  float* d_q32 = nullptr;
+  float* d_x32 = nullptr;        // inner FP32 PCG of the elliptic refinement
+  float* d_r32[2] = {nullptr, nullptr};
+  float* d_s32[2] = {nullptr, nullptr};
+  float* d_w32[2] = {nullptr, nullptr};
+  float* d_p32 = nullptr;
   float* d_dinvk = nullptr;
   double* d_partials = nullptr;   // per-block partial sums of one-brick-per-block launches
   double* d_cgp[2] = {nullptr, nullptr};  // persistent CG launches: ping-pong partials
@@ -110,6 +116,7 @@ struct ep_grid_s {
   // state
   int cur = 0;
   int64_t step = 0;
+  bool have_prev = false;      // d_v[1-cur] holds the previous step's v
   bool has_cond = false;
   bool nonfinite = false;
   int last_iters = 4;
@@ -224,6 +231,21 @@ void timer_end(ep_grid g, TimerPair* tp) {
   if (tp) (void)hipEventRecord(tp->b, g->stream);
 }
 
+// move the last `count` pairs recorded under `from` to `to`
+void timer_retag(ep_grid g, int from, int to, int count) {
+  if (!g->timing) return;
+  for (int i = 0; i < count && g->tused[from] > 0; ++i) {
+    TimerPair tp = g->tk[from][--g->tused[from]];
+    g->tk[from].erase(g->tk[from].begin() + static_cast<long>(g->tused[from]));
+    if (g->tused[to] == g->tk[to].size()) {
+      g->tk[to].push_back(tp);
+    } else {
+      g->tk[to].insert(g->tk[to].begin() + static_cast<long>(g->tused[to]), tp);
+    }
+    ++g->tused[to];
+  }
+}
+
 void timer_collect(ep_grid g) {
   for (int id = 0; id < kTimers; ++id) {
     for (size_t i = 0; i < g->tused[id]; ++i) {
@@ -317,47 +339,44 @@ ep_status update_stimulus(ep_grid g, int64_t step, const T** jstim) {
 
 // ---- one CG solve (device-resident scalars; host polls `done` in chunks) ----
 // One CG solve after its init launch (scalars in d_cg[0], partials in
-// d_cgp[0]).  Launch order: SpMV(first), then pairs (update, SpMV); each SpMV
-// decides from the update before it whether the solve has converged.  The
-// host polls the scalars once per chunk of pairs (one round trip per solve
-// when the chunk matches the previous solve's iteration count).
+// d_cgp[0], r0 in r[0], x0 in x).  Launch j reads scalars / partials [j & 1]
+// and writes [(j + 1) & 1]; launch j >= 1 tests the residual left by launch
+// j - 1 before doing iteration j.  The host polls the scalars once per chunk
+// (one round trip per solve when the chunk matches the previous solve).
 template <typename T>
-ep_status pcg_loop(ep_grid g, CoefSet<T> c, T* x, T* r, T* p0, T* p1, T* q, const T* dinv,
-                   T c0, T c1, int init_kind, int maxit, int* chunk_hint, int* iters,
-                   bool* failed) {
-  CGScalars* A = g->d_cg;
-  CGScalars* B = g->d_cg + 1;
-  double* P0 = g->d_cgp[0];
-  double* P1 = g->d_cgp[1];
-  T* p[2] = {p0, p1};
-  int pa = 0;
-  auto spmv = [&](int first) {
-    TimerPair* t0 = timer_begin(g, KT_STENCIL);
-    launch_spmv<T>(g->L, g->d_nbr, c, r, dinv, p[pa], p[1 - pa], q, c0, c1, first, init_kind,
-                   A, B, P0, P1);
+ep_status cg_solve(ep_grid g, CoefSet<T> c, T c0, T c1, const T* dinv, T* x, T* const r[2],
+                   T* const sv[2], T* const wv[2], T* p, int init_kind, int maxit,
+                   int* chunk_hint, int* iters, bool* failed) {
+  CGScalars* cg = g->d_cg;
+  double* const* P = g->d_cgp;
+  // r_k lives in r[k & 1], w_k in wv[k & 1], s_k in sv[k & 1]; launch j >= 1
+  // reads r_{j-1}, s_{j-2}, w_{j-1} and writes r_j, s_{j-1}, w_j; launch 0
+  // reads r_0 and writes w_0.
+  auto launch = [&](int j) {
+    TimerPair* t0 = timer_begin(g, j == 0 ? KT_CGSETUP : KT_STENCIL);
+    const int kind = j == 0 ? 0 : (j == 1 ? 1 : 2);
+    const T* rin = (j == 0) ? r[0] : r[(j + 1) & 1];
+    launch_cgcg<T>(g->L, g->d_nbr, c, c0, c1, dinv, x, rin, r[j & 1], p, sv[j & 1],
+                   sv[(j + 1) & 1], wv[(j + 1) & 1], wv[j & 1], kind, init_kind, cg + (j & 1),
+                   cg + ((j + 1) & 1), P[j & 1], P[(j + 1) & 1]);
     timer_end(g, t0);
-    pa = 1 - pa;
   };
-  spmv(1);
-  int enq = 0;
-  int chunk = std::max(1, *chunk_hint);
+  int j = 0;
+  launch(j++);
+  int chunk = std::max(1, *chunk_hint) + 1;
   for (;;) {
-    for (int i = 0; i < chunk; ++i) {
-      TimerPair* t1 = timer_begin(g, KT_UPDATE);
-      launch_cg_update<T>(g->L, x, r, p[pa], q, dinv, B, A, P1, P0);
-      timer_end(g, t1);
-      spmv(0);
-    }
-    enq += chunk;
-    HIPCHK(g, hipMemcpyAsync(&g->hs->cg, B, sizeof(CGScalars), hipMemcpyDeviceToHost,
+    for (int i = 0; i < chunk; ++i) launch(j++);
+    HIPCHK(g, hipMemcpyAsync(&g->hs->cg, cg + (j & 1), sizeof(CGScalars), hipMemcpyDeviceToHost,
                              g->stream));
     HIPCHK(g, hipStreamSynchronize(g->stream));
-    if (g->hs->cg.done || enq > maxit) break;
-    chunk = std::min(4, std::max(1, maxit + 1 - enq));
+    if (g->hs->cg.done || j >= maxit + 2) break;
+    chunk = std::min(4, std::max(1, maxit + 2 - j));
   }
   *iters = g->hs->cg.it;
   *failed = g->hs->cg.fail != 0 || !g->hs->cg.done;
   *chunk_hint = std::max(1, g->hs->cg.it);
+  // launches 1..it did an iteration; the rest only detected convergence
+  timer_retag(g, KT_STENCIL, KT_CGTAIL, j - 1 - g->hs->cg.it);
   return EP_OK;
 }
 
@@ -379,20 +398,21 @@ template <typename T>
 ep_status step_be(ep_grid g, const T* jstim, ep_step_info* acc) {
   const int c = g->cur, n = 1 - c;
   T* x = static_cast<T*>(g->d_v[n]);
-  T* r = static_cast<T*>(g->d_r);
+  T* r[2] = {static_cast<T*>(g->d_cr[0]), static_cast<T*>(g->d_cr[1])};
+  T* sv[2] = {static_cast<T*>(g->d_cs[0]), static_cast<T*>(g->d_cs[1])};
+  T* wv[2] = {static_cast<T*>(g->d_cw[0]), static_cast<T*>(g->d_cw[1])};
   const T* dinv = static_cast<const T*>(g->d_dinv);
+  // x (= d_v[n]) still holds the previous step's v: check its activation here
   launch_be_init<T>(g->L, g->d_nbr, coefs<T>(g), static_cast<const T*>(g->d_v[c]),
-                    static_cast<const T*>(g->d_w[c]), jstim, dinv, x,
-                    static_cast<T*>(g->d_w[n]), r, ionic_t<T>(g), static_cast<T>(g->dt),
-                    g->d_cg, g->d_cgp[0], g->pcg_rtol * g->pcg_rtol, g->pcg_maxit);
+                    static_cast<const T*>(g->d_w[c]), jstim, x, static_cast<T*>(g->d_w[n]),
+                    r[0], ionic_t<T>(g), static_cast<T>(g->dt), static_cast<T*>(g->d_tact),
+                    static_cast<T>(g->theta), static_cast<double>(g->step - 1) * g->dt,
+                    g->have_prev ? 1 : 0, g->d_flags, g->d_cg, g->d_cgp[0],
+                    g->pcg_rtol * g->pcg_rtol, g->pcg_maxit);
   int iters = 0;
   bool failed = false;
-  TRY(pcg_loop<T>(g, coefs<T>(g), x, r, static_cast<T*>(g->d_p[0]), static_cast<T*>(g->d_p[1]),
-                  static_cast<T*>(g->d_q), dinv, T(1), static_cast<T>(-g->dt), 0, g->pcg_maxit,
-                  &g->last_iters, &iters, &failed));
-  launch_activation<T>(g->L, static_cast<const T*>(g->d_v[c]), x, static_cast<T*>(g->d_tact),
-                       static_cast<T>(g->dt), static_cast<T>(g->theta),
-                       static_cast<double>(g->step) * g->dt, g->d_flags);
+  TRY(cg_solve<T>(g, coefs<T>(g), T(1), static_cast<T>(-g->dt), dinv, x, r, sv, wv,
+                  static_cast<T*>(g->d_cp), 0, g->pcg_maxit, &g->last_iters, &iters, &failed));
   acc->cg_iters += iters;
   acc->cg_max = std::max(acc->cg_max, iters);
   if (g->hs->cg.bb > 0) acc->relres = std::sqrt(g->hs->cg.rr / g->hs->cg.bb);
@@ -432,14 +452,13 @@ ep_status elliptic(ep_grid g, const T* vsrc, double rtol, int max_outer, ep_solv
     relres = std::sqrt(rr / bb);
     if (relres <= rtol) { ok = true; break; }
     if (!std::isfinite(relres) || outer >= max_outer) break;
-    launch_inner_init(g->L, g->d_r64, g->d_mask, g->d_sums, inv_count, g->d_dinvk, g->d_x32,
-                      g->d_r32, g->d_cg, g->d_cgp[0], kInnerRtol * kInnerRtol,
-                      g->ell_inner_maxit);
+    launch_inner_init(g->L, g->d_r64, g->d_mask, g->d_sums, inv_count, g->d_x32, g->d_r32[0],
+                      g->d_cg, g->d_cgp[0], kInnerRtol * kInnerRtol, g->ell_inner_maxit);
     int iters = 0;
     bool failed = false;
-    TRY(pcg_loop<float>(g, cset32(g->d_ck32), g->d_x32, g->d_r32, g->d_p32[0], g->d_p32[1],
-                        g->d_q32, g->d_dinvk, 0.0f, -1.0f, 1, g->ell_inner_maxit,
-                        &g->last_inner, &iters, &failed));
+    TRY(cg_solve<float>(g, cset32(g->d_ck32), 0.0f, -1.0f, g->d_dinvk, g->d_x32, g->d_r32,
+                        g->d_s32, g->d_w32, g->d_p32, 1, g->ell_inner_maxit, &g->last_inner,
+                        &iters, &failed));
     inner_total += iters;
     launch_phi_correct(g->L, g->d_phi, g->d_x32, g->d_mask, g->d_partials);
     launch_reduce_sum(g->stream, g->d_partials, G, 1, g->d_sums + 4);
@@ -496,6 +515,15 @@ ep_status run_steps(ep_grid g, int32_t nsteps, ep_step_info* info) {
     }
     g->cur = 1 - g->cur;
     g->step += 1;
+    g->have_prev = true;
+  }
+  if (g->model == EP_MONO && g->diff == EP_DIFF_BE_PCG && nsteps > 0) {
+    // activation of the last step (the next step's init would check it too;
+    // the first-crossing rule makes that repeat harmless)
+    launch_activation<T>(g->L, static_cast<const T*>(g->d_v[1 - g->cur]),
+                         static_cast<const T*>(g->d_v[g->cur]), static_cast<T*>(g->d_tact),
+                         static_cast<T>(g->dt), static_cast<T>(g->theta),
+                         static_cast<double>(g->step - 1) * g->dt, g->d_flags);
   }
   const int noconv = g->hs->flags[1];
   launch_sum<T>(g->L, static_cast<const T*>(g->d_v[g->cur]), g->d_partials);
@@ -685,7 +713,7 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   g->grid = grid_for(nb);
   g->L.nb = nb;
   g->L.grid = g->grid;
-  g->L.pgrid = pgrid_for(nb);
+  g->L.pgrid = pgrid_for(nb, g->prec == EP_F64);
   g->L.stream = g->stream;
   if (g->model == EP_BIDO && tissue_components(boxmask, g->n) != 1)
     return fail(g, EP_ERR_ARG, "bidomain tissue must be one face-connected component");
@@ -733,10 +761,12 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   TRY(dalloc(g, &g->d_qstep, sizeof(double)));
   TRY(dalloc(g, &g->d_phi, static_cast<size_t>(g->nvox) * sizeof(double)));
   if (g->diff == EP_DIFF_BE_PCG) {
-    TRY(dalloc(g, &g->d_r, vb));
-    TRY(dalloc(g, &g->d_p[0], vb));
-    TRY(dalloc(g, &g->d_p[1], vb));
-    TRY(dalloc(g, &g->d_q, vb));
+    for (int k = 0; k < 2; ++k) {
+      TRY(dalloc(g, &g->d_cr[k], vb));
+      TRY(dalloc(g, &g->d_cs[k], vb));
+      TRY(dalloc(g, &g->d_cw[k], vb));
+    }
+    TRY(dalloc(g, &g->d_cp, vb));
     TRY(dalloc(g, &g->d_dinv, vb));
   }
   if (g->model == EP_BIDO) {
@@ -750,10 +780,12 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
       TRY(dalloc(g, &g->d_ck32[k], b32));
     }
     TRY(dalloc(g, &g->d_x32, b32));
-    TRY(dalloc(g, &g->d_r32, b32));
-    TRY(dalloc(g, &g->d_p32[0], b32));
-    TRY(dalloc(g, &g->d_p32[1], b32));
-    TRY(dalloc(g, &g->d_q32, b32));
+    for (int k = 0; k < 2; ++k) {
+      TRY(dalloc(g, &g->d_r32[k], b32));
+      TRY(dalloc(g, &g->d_s32[k], b32));
+      TRY(dalloc(g, &g->d_w32[k], b32));
+    }
+    TRY(dalloc(g, &g->d_p32, b32));
     TRY(dalloc(g, &g->d_dinvk, b32));
   }
   {
@@ -1044,6 +1076,7 @@ EP_API ep_status ep_write_state(ep_grid g, ep_field f, const double* host_in, si
     ep_status s = g->prec == EP_F64 ? write_field<double>(g, f, host_in)
                                     : write_field<float>(g, f, host_in);
     if (s == EP_OK) {
+      if (f == EP_V) g->have_prev = false;
       g->nonfinite = false;
       HIPCHK(g, hipMemsetAsync(g->d_flags, 0, 4 * sizeof(int), g->stream));
       HIPCHK(g, hipStreamSynchronize(g->stream));
@@ -1064,6 +1097,7 @@ EP_API ep_status ep_set_step(ep_grid g, int64_t step) {
   if (!g || step < 0) return EP_ERR_ARG;
   g->step = step;
   g->stim_built = false;
+  g->have_prev = false;
   return EP_OK;
 }
 
