@@ -190,6 +190,60 @@ EP_API ep_status ep_destroy_grid(ep_grid g);
 EP_API const char* ep_status_string(ep_status s);
 EP_API const char* ep_last_error(ep_grid g);
 
+/* ---- batched serving ----------------------------------------------------
+ * Many independent simulations (different grids, conductivities, ionic
+ * parameters and step counts) advanced together on one GPU.  The thesis
+ * proposes running many independent simulations in parallel (parameter
+ * estimation, patient fitting) instead of splitting one across devices
+ * (Abstract; Review & Outlook chapter, Assessment, "GPU Processing"); this
+ * is that mode, as continuous batching:
+ *  - ep_batch_submit queues a request (FP32, monodomain, explicit diffusion,
+ *    all stimuli of a request sharing one time window); host data is copied.
+ *  - ep_batch_advance admits queued requests in FIFO order while their
+ *    device memory fits the HBM budget and a slot is free (their grids,
+ *    coefficients and state are built on the device), then launches one
+ *    captured graph of K steps in which every admitted request advances by up
+ *    to K steps (a request never steps past its own count), and detects the
+ *    requests that have finished.  Requests admitted later join running
+ *    ones at the next graph boundary; their work shares each launch.
+ *  - finished requests stay resident until ep_batch_release; read their
+ *    fields with ep_batch_read (same layout and conventions as
+ *    ep_read_state).
+ * Each request's arithmetic is independent of the mix: a request gives the
+ * same bits alone, in any mix and through ep_step on an EP_F32 grid.
+ * Errors: EP_ERR_ARG (bad description / id), EP_ERR_UNSUPPORTED (model,
+ * precision, scheme or stimulus windows outside this mode), EP_ERR_OOM (a
+ * request larger than the whole budget), EP_ERR_HIP. */
+typedef struct ep_batch_s* ep_batch;
+
+typedef struct {
+  int64_t hbm_budget;         /* device bytes for admitted requests (arena) */
+  int32_t max_slots;          /* requests resident at once */
+  int32_t steps_per_launch;   /* K, steps per graph launch (>= 1) */
+  void* stream;               /* hipStream_t or NULL for the batch's own */
+} ep_batch_desc;
+
+typedef struct {
+  int64_t submitted, admitted, finished, released;
+  int32_t resident;           /* requests holding device memory */
+  int32_t queued;
+  int64_t arena_used, arena_peak;   /* bytes */
+  int64_t graph_launches;
+  double voxel_steps;         /* tissue voxel-steps advanced so far */
+} ep_batch_stats;
+
+EP_API ep_status ep_batch_create(const ep_batch_desc* d, ep_batch* out);
+EP_API ep_status ep_batch_submit(ep_batch b, const ep_grid_desc* d, const double* fibre,
+                                 const double* scale, double sig_l, double sig_t,
+                                 int64_t n_steps, int64_t* id);
+EP_API ep_status ep_batch_advance(ep_batch b, int32_t* n_finished);
+EP_API ep_status ep_batch_finished(ep_batch b, int64_t* ids, int32_t cap, int32_t* n);
+EP_API ep_status ep_batch_read(ep_batch b, int64_t id, ep_field f, double* host_out, size_t n);
+EP_API ep_status ep_batch_release(ep_batch b, int64_t id);
+EP_API ep_status ep_batch_get_stats(ep_batch b, ep_batch_stats* s);
+EP_API ep_status ep_batch_destroy(ep_batch b);
+EP_API const char* ep_batch_last_error(ep_batch b);
+
 #ifdef __cplusplus
 }
 #endif

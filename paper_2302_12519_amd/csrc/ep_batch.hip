@@ -1,0 +1,748 @@
+// Batched serving of many explicit-monodomain simulations on one GPU (the
+// ep_batch_* family of include/ep.h).
+//
+// Device side: every admitted request ("slot") owns a region of one arena
+// allocation holding its neighbour table, FP32 operator weights, ping-pong
+// v / w, activation times and stimulus amplitudes.  A work list of
+// (slot, brick) pairs lists every brick of every running request; one
+// persistent launch of k_batch_step advances all of them by one step, each
+// brick with exactly the per-grid explicit kernel's arithmetic (so a request
+// gives the same bits alone, in any mix, or through ep_step).  The state of
+// step s lives in buffer s & 1, and a launch for substep k skips slots whose
+// step + k has reached their own step count.  K substeps plus a counter
+// update are captured once in a hipGraph; admission and retirement only
+// rewrite the slot table and the work list between graph launches.
+//
+// Host side: FIFO admission by HBM budget (first-fit arena with coalescing)
+// and free slots, request bookkeeping and result read-back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <limits>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ep.h"
+#include "ep_device.h"
+#include "ep_layout.h"
+
+namespace ep {
+namespace {
+
+using namespace dev;
+
+struct SlotDev {
+  const int* nbr;
+  const float* c[6];
+  float* v[2];
+  float* w[2];
+  float* tact;
+  const float* jamp;      // stimulus current per voxel while the window is open
+  IonicT<float> ion;
+  float dt, theta;
+  double dtd, t_on, t_off;
+  long long step, n_steps;
+  int active, pad;
+};
+
+struct WorkItem {
+  int slot, brick;
+};
+
+constexpr int kBatchGrid = 1024;   // persistent: 4 blocks per CU on 256 CUs
+
+// One explicit step of every running request's bricks (substep k of the
+// current graph launch).
+__global__ __launch_bounds__(kBV) void k_batch_step(const SlotDev* __restrict__ slots,
+                                                    const WorkItem* __restrict__ work,
+                                                    const int* __restrict__ count, int k,
+                                                    int* flags) {
+  __shared__ float s[kTile];
+  __shared__ int nbs[kNbr];
+  const int n = *count;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const WorkItem it = work[i];
+    const SlotDev* sd = slots + it.slot;
+    const long long st = sd->step + k;
+    if (st >= sd->n_steps) continue;
+    const int brick = it.brick;
+    if (threadIdx.x < kNbr) nbs[threadIdx.x] = sd->nbr[brick * kNbr + threadIdx.x];
+    __syncthreads();
+    const int par = static_cast<int>(st & 1);
+    const float* __restrict__ v = sd->v[par];
+    const float* __restrict__ w = sd->w[par];
+    float* __restrict__ vout = sd->v[par ^ 1];
+    float* __restrict__ wout = sd->w[par ^ 1];
+    const double tn = static_cast<double>(st) * sd->dtd;
+    const float* __restrict__ jstim =
+        (sd->jamp && sd->t_on <= tn && tn < sd->t_off) ? sd->jamp : nullptr;
+    const IonicT<float> ion = sd->ion;
+    const float dt = sd->dt, theta = sd->theta;
+    CoefSet<float> c;
+    for (int q = 0; q < 6; ++q) c.c[q] = sd->c[q];
+    const Cell q = cell_setup(nbs, brick);
+    const float v0 = v[q.g], w0 = w[q.g];
+    const float j0 = jstim ? jstim[q.g] : 0.0f;
+    float hv = 0.0f, hw = 0.0f, hj = 0.0f;
+    if (q.has_halo) {
+      hv = v[q.hg];
+      hw = w[q.hg];
+      hj = jstim ? jstim[q.hg] : 0.0f;
+    }
+    float k18[18];
+    gather18(c, nbs, brick, q.lx, q.ly, q.lz, k18);
+    float vs, ws;
+    ms_step(v0, w0, j0, ion, dt, vs, ws);
+    s[q.C] = vs;
+    if (q.has_halo) {
+      float a, b;
+      ms_step(hv, hw, hj, ion, dt, a, b);
+      s[q.hC] = a;
+    }
+    __syncthreads();
+    const float vn = vs + dt * apply19(s, q.C, k18);
+    vout[q.g] = vn;
+    wout[q.g] = ws;
+    if (v0 < theta && theta <= vn) {
+      if (isinf(sd->tact[q.g]))
+        sd->tact[q.g] = static_cast<float>(tn) + dt * (theta - v0) / (vn - v0);
+    }
+    if (!isfinite(vn)) flags[0] = 1;
+  }
+}
+
+// after K substeps: step += K, clamped at the request's step count
+__global__ void k_batch_advance(SlotDev* slots, int nslots, int K) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nslots || !slots[i].active) return;
+  const long long s = slots[i].step + K;
+  slots[i].step = s < slots[i].n_steps ? s : slots[i].n_steps;
+}
+
+// first-fit allocator over one device allocation, coalescing on free
+class Arena {
+ public:
+  void reset(size_t size) {
+    size_ = size;
+    free_.clear();
+    free_[0] = size;
+    used_ = 0;
+  }
+  size_t alloc(size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        const size_t off = it->first, rest = it->second - bytes;
+        free_.erase(it);
+        if (rest) free_[off + bytes] = rest;
+        used_ += bytes;
+        return off;
+      }
+    }
+    return std::numeric_limits<size_t>::max();
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+  size_t size() const { return size_; }
+
+ private:
+  size_t size_ = 0, used_ = 0;
+  std::map<size_t, size_t> free_;
+};
+
+size_t region_bytes(const BrickMap& m) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return al(static_cast<size_t>(m.nb + 1) * kNbr * sizeof(int)) +
+         12 * al(static_cast<size_t>(m.nvox) * sizeof(float));
+}
+
+}  // namespace
+}  // namespace ep
+
+using namespace ep;
+
+struct ep_batch_request {
+  int64_t id = 0;
+  int n[3] = {0, 0, 0};
+  double h = 0, dt = 0, theta = 0.5;
+  ep_ionic ionic{};
+  std::vector<uint8_t> mask;
+  std::vector<double> fibre, scale;
+  double sig_l = 0, sig_t = 0;
+  std::vector<ep_stim> stims;
+  double t_on = 0, t_off = 0;
+  int64_t n_steps = 0;
+  BrickMap map;
+  size_t bytes = 0, off = 0;
+  int slot = -1;
+  bool finished = false;
+};
+
+struct ep_batch_s {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int64_t budget = 0;
+  int max_slots = 0;
+  int K = 1;
+  char* arena_base = nullptr;
+  Arena arena;
+  size_t arena_peak = 0;
+  SlotDev* d_slots = nullptr;
+  SlotDev* h_slots = nullptr;   // pinned read-back
+  WorkItem* d_work = nullptr;
+  int* d_count = nullptr;
+  int* d_flags = nullptr;
+  int work_cap = 0;
+  // coefficient-encoding scratch (grown on demand)
+  double* d_fib = nullptr;
+  double* d_scale = nullptr;
+  double* d_tens = nullptr;
+  uint8_t* d_mask = nullptr;
+  int64_t scratch_vox = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::deque<ep_batch_request*> queue;
+  std::map<int64_t, ep_batch_request*> all;
+  std::vector<int64_t> slot_owner;
+  std::vector<int64_t> finished_ids;
+  int64_t next_id = 1;
+  ep_batch_stats st{};
+  bool work_dirty = true;
+  std::string err;
+};
+
+namespace {
+
+ep_status bfail(ep_batch b, ep_status s, const std::string& msg) {
+  if (b) b->err = msg;
+  return s;
+}
+
+#define BHIP(b, expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return bfail((b), EP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+ep_status grow_scratch(ep_batch b, int64_t nvox) {
+  if (nvox <= b->scratch_vox) return EP_OK;
+  BHIP(b, hipStreamSynchronize(b->stream));
+  (void)hipFree(b->d_fib);
+  (void)hipFree(b->d_scale);
+  (void)hipFree(b->d_tens);
+  (void)hipFree(b->d_mask);
+  b->d_fib = b->d_scale = b->d_tens = nullptr;
+  b->d_mask = nullptr;
+  b->scratch_vox = 0;
+  const size_t n = static_cast<size_t>(nvox);
+  if (hipMalloc(&b->d_fib, 3 * n * sizeof(double)) != hipSuccess ||
+      hipMalloc(&b->d_scale, n * sizeof(double)) != hipSuccess ||
+      hipMalloc(&b->d_tens, 6 * n * sizeof(double)) != hipSuccess ||
+      hipMalloc(&b->d_mask, n) != hipSuccess) {
+    (void)hipGetLastError();
+    return bfail(b, EP_ERR_OOM, "coefficient scratch allocation failed");
+  }
+  b->scratch_vox = nvox;
+  return EP_OK;
+}
+
+// Build a request's device region: weights, initial state, stimulus field.
+ep_status admit(ep_batch b, ep_batch_request* r, int slot) {
+  const BrickMap& m = r->map;
+  const size_t nv = static_cast<size_t>(m.nvox);
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  char* base = b->arena_base + r->off;
+  int* d_nbr = reinterpret_cast<int*>(base);
+  char* p = base + al(static_cast<size_t>(m.nb + 1) * kNbr * sizeof(int));
+  float* arr[12];
+  for (int k = 0; k < 12; ++k) {
+    arr[k] = reinterpret_cast<float*>(p);
+    p += al(nv * sizeof(float));
+  }
+  // arr: 0-5 weights, 6-7 v, 8-9 w, 10 tact, 11 jamp
+  if (ep_status s = grow_scratch(b, m.nvox); s != EP_OK) return s;
+  BHIP(b, hipMemsetAsync(base, 0, r->bytes, b->stream));
+  // fibres / scale / mask in brick layout
+  std::vector<double> hf(3 * nv, 0.0), hs;
+  if (!r->scale.empty()) hs.assign(nv, 0.0);
+  std::vector<float> w0(nv, 0.0f), tact(nv, 0.0f), jamp(nv, 0.0f);
+  const int64_t nreal = static_cast<int64_t>(m.nb) * kBV;
+  for (int64_t i = 0; i < nreal; ++i) {
+    w0[i] = 1.0f;
+    tact[i] = std::numeric_limits<float>::infinity();
+  }
+  for (int x = 0; x < r->n[0]; ++x)
+    for (int y = 0; y < r->n[1]; ++y)
+      for (int z = 0; z < r->n[2]; ++z) {
+        const int64_t gi = m.brick_index(x, y, z);
+        if (gi < 0 || !m.mask[gi]) continue;
+        const int64_t bi = m.box_index(x, y, z);
+        hf[3 * gi] = r->fibre[3 * bi];
+        hf[3 * gi + 1] = r->fibre[3 * bi + 1];
+        hf[3 * gi + 2] = r->fibre[3 * bi + 2];
+        if (!hs.empty()) hs[gi] = r->scale[bi];
+      }
+  // stimulus amplitudes (same membership rule as the per-grid path)
+  std::vector<double> jv(nv, 0.0);
+  for (const ep_stim& s : r->stims)
+    for (int x = std::max(0, s.lo[0]); x < std::min(r->n[0], s.hi[0]); ++x)
+      for (int y = std::max(0, s.lo[1]); y < std::min(r->n[1], s.hi[1]); ++y)
+        for (int z = std::max(0, s.lo[2]); z < std::min(r->n[2], s.hi[2]); ++z) {
+          const int64_t gi = m.brick_index(x, y, z);
+          if (gi < 0 || !m.mask[gi]) continue;
+          if (s.radius > 0.0) {
+            const double dx = (x + 0.5) * r->h - s.center[0];
+            const double dy = (y + 0.5) * r->h - s.center[1];
+            const double dz = (z + 0.5) * r->h - s.center[2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (!(r2 <= s.radius * s.radius)) continue;
+          }
+          jv[gi] += s.amp;
+        }
+  for (size_t i = 0; i < nv; ++i) jamp[i] = static_cast<float>(jv[i]);
+  BHIP(b, hipMemcpyAsync(d_nbr, m.nbr.data(), m.nbr.size() * sizeof(int), hipMemcpyHostToDevice,
+                         b->stream));
+  BHIP(b, hipMemcpyAsync(b->d_mask, m.mask.data(), nv, hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(b->d_fib, hf.data(), 3 * nv * sizeof(double), hipMemcpyHostToDevice,
+                         b->stream));
+  if (!hs.empty())
+    BHIP(b, hipMemcpyAsync(b->d_scale, hs.data(), nv * sizeof(double), hipMemcpyHostToDevice,
+                           b->stream));
+  BHIP(b, hipMemsetAsync(b->d_tens, 0, 6 * nv * sizeof(double), b->stream));
+  BHIP(b, hipMemcpyAsync(arr[8], w0.data(), nv * sizeof(float), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(arr[10], tact.data(), nv * sizeof(float), hipMemcpyHostToDevice,
+                         b->stream));
+  BHIP(b, hipMemcpyAsync(arr[11], jamp.data(), nv * sizeof(float), hipMemcpyHostToDevice,
+                         b->stream));
+  LaunchCfg L;
+  L.nb = m.nb;
+  L.grid = grid_for(m.nb);
+  L.pgrid = L.grid;
+  L.stream = b->stream;
+  float* c32[6];
+  for (int k = 0; k < 6; ++k) c32[k] = arr[k];
+  launch_tensor_coefs(L, d_nbr, b->d_mask, b->d_fib, hs.empty() ? nullptr : b->d_scale,
+                      r->sig_l, r->sig_t, r->h, b->d_tens, nullptr, c32);
+  BHIP(b, hipGetLastError());
+  SlotDev sd{};
+  sd.nbr = d_nbr;
+  for (int k = 0; k < 6; ++k) sd.c[k] = arr[k];
+  sd.v[0] = arr[6];
+  sd.v[1] = arr[7];
+  sd.w[0] = arr[8];
+  sd.w[1] = arr[9];
+  sd.tact = arr[10];
+  sd.jamp = r->stims.empty() ? nullptr : arr[11];
+  sd.ion.inv_tau_in = static_cast<float>(1.0 / r->ionic.tau_in);
+  sd.ion.inv_tau_out = static_cast<float>(1.0 / r->ionic.tau_out);
+  sd.ion.inv_tau_open = static_cast<float>(1.0 / r->ionic.tau_open);
+  sd.ion.inv_tau_close = static_cast<float>(1.0 / r->ionic.tau_close);
+  sd.ion.v_gate = static_cast<float>(r->ionic.v_gate);
+  sd.ion.exc = static_cast<float>(r->ionic.exc);
+  sd.dt = static_cast<float>(r->dt);
+  sd.theta = static_cast<float>(r->theta);
+  sd.dtd = r->dt;
+  sd.t_on = r->t_on;
+  sd.t_off = r->t_off;
+  sd.step = 0;
+  sd.n_steps = r->n_steps;
+  sd.active = 1;
+  BHIP(b, hipMemcpyAsync(b->d_slots + slot, &sd, sizeof(SlotDev), hipMemcpyHostToDevice,
+                         b->stream));
+  // host buffers above must outlive the copies
+  BHIP(b, hipStreamSynchronize(b->stream));
+  b->h_slots[slot] = sd;
+  r->slot = slot;
+  b->slot_owner[slot] = r->id;
+  b->st.admitted += 1;
+  b->st.resident += 1;
+  b->work_dirty = true;
+  return EP_OK;
+}
+
+ep_status rebuild_work(ep_batch b) {
+  std::vector<WorkItem> items;
+  for (int s = 0; s < b->max_slots; ++s) {
+    const int64_t id = b->slot_owner[s];
+    if (id < 0) continue;
+    const ep_batch_request* r = b->all[id];
+    if (r->finished) continue;
+    for (int k = 0; k < r->map.nb; ++k) items.push_back({s, k});
+  }
+  if (static_cast<int>(items.size()) > b->work_cap) {
+    BHIP(b, hipStreamSynchronize(b->stream));
+    (void)hipFree(b->d_work);
+    b->d_work = nullptr;
+    b->work_cap = 0;
+    if (hipMalloc(&b->d_work, items.size() * sizeof(WorkItem)) != hipSuccess) {
+      (void)hipGetLastError();
+      return bfail(b, EP_ERR_OOM, "work list allocation failed");
+    }
+    b->work_cap = static_cast<int>(items.size());
+    // the captured graph holds the old pointer: capture again
+    if (b->exec) {
+      (void)hipGraphExecDestroy(b->exec);
+      b->exec = nullptr;
+    }
+    if (b->graph) {
+      (void)hipGraphDestroy(b->graph);
+      b->graph = nullptr;
+    }
+  }
+  const int n = static_cast<int>(items.size());
+  if (n) BHIP(b, hipMemcpyAsync(b->d_work, items.data(), n * sizeof(WorkItem),
+                                hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(b->d_count, &n, sizeof(int), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipStreamSynchronize(b->stream));
+  b->work_dirty = false;
+  return EP_OK;
+}
+
+ep_status capture(ep_batch b) {
+  if (b->exec) return EP_OK;
+  BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < b->K; ++k)
+    k_batch_step<<<kBatchGrid, kBV, 0, b->stream>>>(b->d_slots, b->d_work, b->d_count, k,
+                                                      b->d_flags);
+  k_batch_advance<<<(b->max_slots + 255) / 256, 256, 0, b->stream>>>(b->d_slots, b->max_slots,
+                                                                     b->K);
+  hipGraph_t gr = nullptr;
+  BHIP(b, hipStreamEndCapture(b->stream, &gr));
+  b->graph = gr;
+  BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return EP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+EP_API ep_status ep_batch_create(const ep_batch_desc* d, ep_batch* out) {
+  if (!out) return EP_ERR_ARG;
+  *out = nullptr;
+  if (!d || d->hbm_budget <= 0 || d->max_slots < 1 || d->steps_per_launch < 1)
+    return EP_ERR_ARG;
+  ep_batch b = new (std::nothrow) ep_batch_s();
+  if (!b) return EP_ERR_OOM;
+  b->budget = d->hbm_budget;
+  b->max_slots = d->max_slots;
+  b->K = d->steps_per_launch;
+  ep_status s = EP_OK;
+  do {
+    if (d->stream) {
+      b->stream = static_cast<hipStream_t>(d->stream);
+    } else if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess) {
+      b->own_stream = true;
+    } else {
+      s = EP_ERR_HIP;
+      break;
+    }
+    if (hipMalloc(&b->arena_base, static_cast<size_t>(b->budget)) != hipSuccess ||
+        hipMalloc(&b->d_slots, b->max_slots * sizeof(SlotDev)) != hipSuccess ||
+        hipMalloc(&b->d_count, sizeof(int)) != hipSuccess ||
+        hipMalloc(&b->d_flags, 4 * sizeof(int)) != hipSuccess) {
+      (void)hipGetLastError();
+      s = EP_ERR_OOM;
+      break;
+    }
+    void* hp = nullptr;
+    if (hipHostMalloc(&hp, b->max_slots * sizeof(SlotDev), hipHostMallocDefault) != hipSuccess) {
+      s = EP_ERR_OOM;
+      break;
+    }
+    b->h_slots = static_cast<SlotDev*>(hp);
+    std::memset(b->h_slots, 0, b->max_slots * sizeof(SlotDev));
+    if (hipMemsetAsync(b->d_slots, 0, b->max_slots * sizeof(SlotDev), b->stream) != hipSuccess ||
+        hipMemsetAsync(b->d_count, 0, sizeof(int), b->stream) != hipSuccess ||
+        hipMemsetAsync(b->d_flags, 0, 4 * sizeof(int), b->stream) != hipSuccess ||
+        hipStreamSynchronize(b->stream) != hipSuccess) {
+      s = EP_ERR_HIP;
+      break;
+    }
+    b->arena.reset(static_cast<size_t>(b->budget));
+    b->slot_owner.assign(b->max_slots, -1);
+    // every resident brick holds at least 12 arrays of 512 floats of arena,
+    // so this many work items always suffice
+    b->work_cap = static_cast<int>(b->budget / (12 * kBV * sizeof(float))) + b->max_slots;
+    if (hipMalloc(&b->d_work, static_cast<size_t>(b->work_cap) * sizeof(WorkItem)) != hipSuccess) {
+      (void)hipGetLastError();
+      s = EP_ERR_OOM;
+      break;
+    }
+  } while (false);
+  if (s != EP_OK) {
+    ep_batch_destroy(b);
+    return s;
+  }
+  *out = b;
+  return EP_OK;
+}
+
+EP_API ep_status ep_batch_submit(ep_batch b, const ep_grid_desc* d, const double* fibre,
+                                 const double* scale, double sig_l, double sig_t,
+                                 int64_t n_steps, int64_t* id) {
+  if (!b) return EP_ERR_ARG;
+  if (!d || !fibre || !id || n_steps < 0) return bfail(b, EP_ERR_ARG, "bad submit arguments");
+  if (d->model != EP_MONO || d->prec != EP_F32 || d->diff != EP_DIFF_EXPLICIT)
+    return bfail(b, EP_ERR_UNSUPPORTED, "batched serving runs FP32 explicit monodomain only");
+  for (int k = 0; k < 3; ++k)
+    if (d->n[k] < 1 || d->n[k] > 4096) return bfail(b, EP_ERR_ARG, "n must be in [1, 4096]");
+  if (!(d->h > 0) || !(d->dt > 0) || !(d->act_threshold > 0 && d->act_threshold < 1))
+    return bfail(b, EP_ERR_ARG, "bad h, dt or threshold");
+  const ep_ionic& io = d->ionic;
+  if (!(io.tau_in > 0) || !(io.tau_out > 0) || !(io.tau_open > 0) || !(io.tau_close > 0) ||
+      !(io.exc >= 0))
+    return bfail(b, EP_ERR_ARG, "ionic time constants must be > 0 and exc >= 0");
+  if (!(sig_l >= 0) || !(sig_t >= 0) || !std::isfinite(sig_l) || !std::isfinite(sig_t))
+    return bfail(b, EP_ERR_ARG, "conductivities must be finite and >= 0");
+  if (d->n_stim < 0 || (d->n_stim > 0 && !d->stim)) return bfail(b, EP_ERR_ARG, "bad stimuli");
+  try {
+    auto* r = new ep_batch_request();
+    std::unique_ptr<ep_batch_request> guard(r);
+    std::copy(d->n, d->n + 3, r->n);
+    r->h = d->h;
+    r->dt = d->dt;
+    r->theta = d->act_threshold;
+    r->ionic = d->ionic;
+    r->sig_l = sig_l;
+    r->sig_t = sig_t;
+    r->n_steps = n_steps;
+    r->stims.assign(d->stim, d->stim + d->n_stim);
+    for (size_t k = 0; k < r->stims.size(); ++k)
+      if (r->stims[k].t_on != r->stims[0].t_on || r->stims[k].t_off != r->stims[0].t_off)
+        return bfail(b, EP_ERR_UNSUPPORTED, "stimuli of a batched request share one window");
+    if (!r->stims.empty()) {
+      r->t_on = r->stims[0].t_on;
+      r->t_off = r->stims[0].t_off;
+    }
+    const int64_t N = static_cast<int64_t>(r->n[0]) * r->n[1] * r->n[2];
+    r->mask.assign(N, 1);
+    if (d->mask)
+      for (int64_t i = 0; i < N; ++i) r->mask[i] = d->mask[i] ? 1 : 0;
+    std::string merr;
+    if (!build_brick_map(r->n, r->mask.data(), r->map, merr)) return bfail(b, EP_ERR_ARG, merr);
+    r->fibre.assign(fibre, fibre + 3 * N);
+    double smax = 1.0;
+    if (scale) {
+      r->scale.assign(scale, scale + N);
+      smax = 0.0;
+    }
+    for (int64_t i = 0; i < N; ++i) {
+      if (!r->mask[i]) continue;
+      const double f0 = fibre[3 * i], f1 = fibre[3 * i + 1], f2 = fibre[3 * i + 2];
+      if (!(std::fabs(std::sqrt(f0 * f0 + f1 * f1 + f2 * f2) - 1.0) <= 1e-6))
+        return bfail(b, EP_ERR_ARG, "fibre is not a unit vector on a tissue voxel");
+      if (scale) {
+        if (!(scale[i] > 0) || !std::isfinite(scale[i]))
+          return bfail(b, EP_ERR_ARG, "scale must be finite and > 0 on tissue");
+        smax = std::max(smax, scale[i]);
+      }
+    }
+    // explicit stability, conservatively: |A_pp| + sum_q |A_pq| <=
+    // 4 smax (sig_l + 2 sig_t + |sig_l - sig_t|) / h^2 for unit fibres
+    const double gb = 4.0 * smax * (sig_l + 2.0 * sig_t + std::fabs(sig_l - sig_t)) / (r->h * r->h);
+    if (!(r->dt * gb < 2.0))
+      return bfail(b, EP_ERR_ARG, "explicit diffusion may be unstable for this dt (bound test)");
+    r->bytes = region_bytes(r->map);
+    if (static_cast<int64_t>(r->bytes) > b->budget)
+      return bfail(b, EP_ERR_OOM, "request larger than the batch's HBM budget");
+    r->id = b->next_id++;
+    guard.release();
+    b->all[r->id] = r;
+    b->queue.push_back(r);
+    b->st.submitted += 1;
+    b->st.queued = static_cast<int32_t>(b->queue.size());
+    *id = r->id;
+    return EP_OK;
+  } catch (const std::bad_alloc&) {
+    return bfail(b, EP_ERR_OOM, "host allocation failed");
+  }
+}
+
+EP_API ep_status ep_batch_advance(ep_batch b, int32_t* n_finished) {
+  if (!b) return EP_ERR_ARG;
+  try {
+    // admission: FIFO while memory and a slot are free
+    while (!b->queue.empty()) {
+      ep_batch_request* r = b->queue.front();
+      int slot = -1;
+      for (int s = 0; s < b->max_slots; ++s)
+        if (b->slot_owner[s] < 0) { slot = s; break; }
+      if (slot < 0) break;
+      const size_t off = b->arena.alloc(r->bytes);
+      if (off == std::numeric_limits<size_t>::max()) break;
+      r->off = off;
+      b->queue.pop_front();
+      if (ep_status s = admit(b, r, slot); s != EP_OK) return s;
+      b->arena_peak = std::max(b->arena_peak, b->arena.used());
+    }
+    b->st.queued = static_cast<int32_t>(b->queue.size());
+    if (b->work_dirty)
+      if (ep_status s = rebuild_work(b); s != EP_OK) return s;
+    if (ep_status s = capture(b); s != EP_OK) return s;
+    // one graph launch of K steps for every running request
+    std::vector<long long> before(b->max_slots, 0);
+    bool any = false;
+    for (int s = 0; s < b->max_slots; ++s) {
+      const int64_t id = b->slot_owner[s];
+      if (id >= 0 && !b->all[id]->finished) {
+        before[s] = b->h_slots[s].step;
+        any = true;
+      }
+    }
+    int nfin = 0;
+    if (any) {
+      BHIP(b, hipGraphLaunch(b->exec, b->stream));
+      b->st.graph_launches += 1;
+      BHIP(b, hipMemcpyAsync(b->h_slots, b->d_slots, b->max_slots * sizeof(SlotDev),
+                             hipMemcpyDeviceToHost, b->stream));
+      BHIP(b, hipStreamSynchronize(b->stream));
+      for (int s = 0; s < b->max_slots; ++s) {
+        const int64_t id = b->slot_owner[s];
+        if (id < 0) continue;
+        ep_batch_request* r = b->all[id];
+        if (r->finished) continue;
+        b->st.voxel_steps +=
+            static_cast<double>(b->h_slots[s].step - before[s]) * static_cast<double>(r->map.n_tissue);
+        if (b->h_slots[s].step >= r->n_steps) {
+          r->finished = true;
+          b->finished_ids.push_back(id);
+          b->st.finished += 1;
+          b->work_dirty = true;
+          ++nfin;
+        }
+      }
+    }
+    if (n_finished) *n_finished = nfin;
+    return EP_OK;
+  } catch (const std::bad_alloc&) {
+    return bfail(b, EP_ERR_OOM, "host allocation failed");
+  }
+}
+
+EP_API ep_status ep_batch_finished(ep_batch b, int64_t* ids, int32_t cap, int32_t* n) {
+  if (!b || !n || (cap > 0 && !ids)) return EP_ERR_ARG;
+  const int32_t k = static_cast<int32_t>(std::min<size_t>(cap, b->finished_ids.size()));
+  for (int32_t i = 0; i < k; ++i) ids[i] = b->finished_ids[i];
+  b->finished_ids.erase(b->finished_ids.begin(), b->finished_ids.begin() + k);
+  *n = k;
+  return EP_OK;
+}
+
+EP_API ep_status ep_batch_read(ep_batch b, int64_t id, ep_field f, double* host_out, size_t n) {
+  if (!b || !host_out) return EP_ERR_ARG;
+  auto it = b->all.find(id);
+  if (it == b->all.end()) return bfail(b, EP_ERR_ARG, "unknown request id");
+  ep_batch_request* r = it->second;
+  if (r->slot < 0) return bfail(b, EP_ERR_STATE, "request not admitted yet");
+  if (f != EP_V && f != EP_W && f != EP_TACT) return bfail(b, EP_ERR_ARG, "bad field");
+  const BrickMap& m = r->map;
+  const size_t N = static_cast<size_t>(r->n[0]) * r->n[1] * r->n[2];
+  if (n < N) return bfail(b, EP_ERR_ARG, "output buffer too small");
+  try {
+    BHIP(b, hipMemcpyAsync(&b->h_slots[r->slot], b->d_slots + r->slot, sizeof(SlotDev),
+                           hipMemcpyDeviceToHost, b->stream));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    const SlotDev& sd = b->h_slots[r->slot];
+    const int par = static_cast<int>(sd.step & 1);
+    const float* src = f == EP_V ? sd.v[par] : (f == EP_W ? sd.w[par] : sd.tact);
+    std::vector<float> buf(m.nvox);
+    BHIP(b, hipMemcpyAsync(buf.data(), src, m.nvox * sizeof(float), hipMemcpyDeviceToHost,
+                           b->stream));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    const double off = f == EP_TACT ? std::numeric_limits<double>::infinity() : 0.0;
+    for (int x = 0; x < r->n[0]; ++x)
+      for (int y = 0; y < r->n[1]; ++y)
+        for (int z = 0; z < r->n[2]; ++z) {
+          const int64_t gi = m.brick_index(x, y, z);
+          host_out[m.box_index(x, y, z)] =
+              (gi >= 0 && m.mask[gi]) ? static_cast<double>(buf[gi]) : off;
+        }
+    return EP_OK;
+  } catch (const std::bad_alloc&) {
+    return bfail(b, EP_ERR_OOM, "host allocation failed");
+  }
+}
+
+EP_API ep_status ep_batch_release(ep_batch b, int64_t id) {
+  if (!b) return EP_ERR_ARG;
+  auto it = b->all.find(id);
+  if (it == b->all.end()) return bfail(b, EP_ERR_ARG, "unknown request id");
+  ep_batch_request* r = it->second;
+  if (r->slot >= 0) {
+    SlotDev off{};
+    BHIP(b, hipMemcpyAsync(b->d_slots + r->slot, &off, sizeof(SlotDev), hipMemcpyHostToDevice,
+                           b->stream));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    std::memset(&b->h_slots[r->slot], 0, sizeof(SlotDev));
+    b->arena.release(r->off, r->bytes);
+    b->slot_owner[r->slot] = -1;
+    b->st.resident -= 1;
+    b->work_dirty = true;
+  } else {
+    b->queue.erase(std::remove(b->queue.begin(), b->queue.end(), r), b->queue.end());
+    b->st.queued = static_cast<int32_t>(b->queue.size());
+  }
+  b->finished_ids.erase(std::remove(b->finished_ids.begin(), b->finished_ids.end(), id),
+                        b->finished_ids.end());
+  b->st.released += 1;
+  b->all.erase(it);
+  delete r;
+  return EP_OK;
+}
+
+EP_API ep_status ep_batch_get_stats(ep_batch b, ep_batch_stats* s) {
+  if (!b || !s) return EP_ERR_ARG;
+  *s = b->st;
+  s->arena_used = static_cast<int64_t>(b->arena.used());
+  s->arena_peak = static_cast<int64_t>(b->arena_peak);
+  return EP_OK;
+}
+
+EP_API ep_status ep_batch_destroy(ep_batch b) {
+  if (!b) return EP_ERR_ARG;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (auto& kv : b->all) delete kv.second;
+  (void)hipFree(b->arena_base);
+  (void)hipFree(b->d_slots);
+  (void)hipFree(b->d_work);
+  (void)hipFree(b->d_count);
+  (void)hipFree(b->d_flags);
+  (void)hipFree(b->d_fib);
+  (void)hipFree(b->d_scale);
+  (void)hipFree(b->d_tens);
+  (void)hipFree(b->d_mask);
+  if (b->h_slots) (void)hipHostFree(b->h_slots);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+  return EP_OK;
+}
+
+EP_API const char* ep_batch_last_error(ep_batch b) { return b ? b->err.c_str() : ""; }
+
+}  // extern "C"

@@ -1,0 +1,192 @@
+// Device helpers shared by the per-grid kernels and the batched serving
+// kernel: brick/tile indexing, the 19-point operator on an LDS tile, the
+// Mitchell-Schaeffer update and block-level partial sums.  See
+// ep_internal.h for the data layout.
+#pragma once
+
+#include <cmath>
+
+#include "ep_internal.h"
+
+namespace ep {
+namespace dev {
+
+
+__device__ __forceinline__ int tidx(int x, int y, int z) { return (x * kH + y) * kH + z; }
+
+// Workgroups are dealt round-robin to the 8 XCDs; hand each XCD a contiguous
+// run of bricks so that halo neighbours tend to sit in the same L2.
+__device__ __forceinline__ int block_brick() {
+  const int per = gridDim.x / kXcd;
+  const int b = blockIdx.x;
+  return (b % kXcd) * per + b / kXcd;
+}
+
+// Halo cell k in [0, 480): 6 faces x 64 cells, then 12 edges x 8 cells.
+// Coordinates are tile coordinates in [0, 10) (0 and 9 are the halo).
+__device__ __forceinline__ void halo_cell(int k, int& hx, int& hy, int& hz) {
+  if (k < 384) {
+    const int f = k >> 6, m = k & 63;
+    const int d = f >> 1, side = (f & 1) ? 9 : 0;
+    const int i = (m >> 3) + 1, j = (m & 7) + 1;
+    if (d == 0) { hx = side; hy = i; hz = j; }
+    else if (d == 1) { hx = i; hy = side; hz = j; }
+    else { hx = i; hy = j; hz = side; }
+  } else {
+    const int k2 = k - 384;
+    const int e = k2 >> 3, t = (k2 & 7) + 1;
+    const int pair = e >> 2;
+    const int s1 = (e & 2) ? 9 : 0, s2 = (e & 1) ? 9 : 0;
+    if (pair == 0) { hx = s1; hy = s2; hz = t; }
+    else if (pair == 1) { hx = s1; hy = t; hz = s2; }
+    else { hx = t; hy = s1; hz = s2; }
+  }
+}
+
+// global index of tile cell (hx, hy, hz) of the brick whose neighbour row is nbs
+__device__ __forceinline__ int tile_global(const int* nbs, int hx, int hy, int hz) {
+  const int ox = (hx == 0) ? 0 : (hx == 9 ? 2 : 1);
+  const int oy = (hy == 0) ? 0 : (hy == 9 ? 2 : 1);
+  const int oz = (hz == 0) ? 0 : (hz == 9 ? 2 : 1);
+  const int bk = nbs[ox * 9 + oy * 3 + oz];
+  return bk * kBV + ((((hx + 7) & 7) * 8 + ((hy + 7) & 7)) * 8 + ((hz + 7) & 7));
+}
+
+// global index of voxel (lx+dx, ly+dy, lz+dz), d in {-1, 0, 1}
+__device__ __forceinline__ int nb_global(const int* nbs, int brick, int lx, int ly, int lz,
+                                         int dx, int dy, int dz) {
+  const int tx = lx + dx, ty = ly + dy, tz = lz + dz;
+  const int ox = tx < 0 ? 0 : (tx > 7 ? 2 : 1);
+  const int oy = ty < 0 ? 0 : (ty > 7 ? 2 : 1);
+  const int oz = tz < 0 ? 0 : (tz > 7 ? 2 : 1);
+  const int slot = ox * 9 + oy * 3 + oz;
+  const int bk = (slot == 13) ? brick : nbs[slot];
+  return bk * kBV + (((tx & 7) * 8 + (ty & 7)) * 8 + (tz & 7));
+}
+
+// The 18 off-centre weights of voxel p of the 19-point operator, in the order
+//  0 ax(p)   1 ax(p-x)  2 ay(p)   3 ay(p-y)  4 az(p)   5 az(p-z)
+//  6 bxy(p)  7 bxy(p-x-y)  8 bxy(p-y)  9 bxy(p-x)
+// 10 bxz(p) 11 bxz(p-x-z) 12 bxz(p-z) 13 bxz(p-x)
+// 14 byz(p) 15 byz(p-y-z) 16 byz(p-z) 17 byz(p-y)
+template <typename T>
+__device__ __forceinline__ void gather18(const CoefSet<T>& c, const int* nbs, int brick, int lx,
+                                         int ly, int lz, T k[18]) {
+  const int g = brick * kBV + (lx * 8 + ly) * 8 + lz;
+  const int gx = nb_global(nbs, brick, lx, ly, lz, -1, 0, 0);
+  const int gy = nb_global(nbs, brick, lx, ly, lz, 0, -1, 0);
+  const int gz = nb_global(nbs, brick, lx, ly, lz, 0, 0, -1);
+  const int gxy = nb_global(nbs, brick, lx, ly, lz, -1, -1, 0);
+  const int gxz = nb_global(nbs, brick, lx, ly, lz, -1, 0, -1);
+  const int gyz = nb_global(nbs, brick, lx, ly, lz, 0, -1, -1);
+  k[0] = c.c[CX][g];
+  k[1] = c.c[CX][gx];
+  k[2] = c.c[CY][g];
+  k[3] = c.c[CY][gy];
+  k[4] = c.c[CZ][g];
+  k[5] = c.c[CZ][gz];
+  k[6] = c.c[CXY][g];
+  k[7] = c.c[CXY][gxy];
+  k[8] = c.c[CXY][gy];
+  k[9] = c.c[CXY][gx];
+  k[10] = c.c[CXZ][g];
+  k[11] = c.c[CXZ][gxz];
+  k[12] = c.c[CXZ][gz];
+  k[13] = c.c[CXZ][gx];
+  k[14] = c.c[CYZ][g];
+  k[15] = c.c[CYZ][gyz];
+  k[16] = c.c[CYZ][gz];
+  k[17] = c.c[CYZ][gy];
+}
+
+// (A u)_p from the LDS tile s at tile cell C.  Faces: a (u_q - u_p).  Each
+// 2x2 block in plane (d, d') couples p with its diagonal partner: +b along
+// (+d,+d') / (-d,-d') and -b along (+d,-d') / (-d,+d').
+template <typename T>
+__device__ __forceinline__ T apply19(const T* s, int C, const T k[18]) {
+  const T u = s[C];
+  T a = k[0] * (s[C + 100] - u) + k[1] * (s[C - 100] - u) + k[2] * (s[C + 10] - u) +
+        k[3] * (s[C - 10] - u) + k[4] * (s[C + 1] - u) + k[5] * (s[C - 1] - u);
+  a += k[6] * (s[C + 110] - u) + k[7] * (s[C - 110] - u) - k[8] * (s[C + 90] - u) -
+       k[9] * (s[C - 90] - u);
+  a += k[10] * (s[C + 101] - u) + k[11] * (s[C - 101] - u) - k[12] * (s[C + 99] - u) -
+       k[13] * (s[C - 99] - u);
+  a += k[14] * (s[C + 11] - u) + k[15] * (s[C - 11] - u) - k[16] * (s[C + 9] - u) -
+       k[17] * (s[C - 9] - u);
+  return a;
+}
+
+template <typename T>
+__device__ __forceinline__ T diag19(const T k[18]) {
+  return -(k[0] + k[1] + k[2] + k[3] + k[4] + k[5]) - (k[6] + k[7]) + (k[8] + k[9]) -
+         (k[10] + k[11]) + (k[12] + k[13]) - (k[14] + k[15]) + (k[16] + k[17]);
+}
+
+// One explicit Euler step of Mitchell-Schaeffer; the gate branch is decided
+// on the pre-step v and taken as a select.
+template <typename T>
+__device__ __forceinline__ void ms_step(T v, T w, T js, const IonicT<T>& p, T dt, T& vs,
+                                        T& ws) {
+  const T jin = p.exc * v * v * (T(1) - v) * w * p.inv_tau_in;
+  const T jout = -v * p.inv_tau_out;
+  const T dw = (v < p.v_gate) ? (T(1) - w) * p.inv_tau_open : -w * p.inv_tau_close;
+  vs = v + dt * (jin + jout + js);
+  ws = w + dt * dw;
+}
+
+// Sum K per-thread doubles over the block; thread k < K writes slot k.
+template <int K>
+__device__ __forceinline__ void block_partials(double (&v)[K], double* partials) {
+  __shared__ double red[K][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double x = v[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[k][wave] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += red[threadIdx.x][w];
+    partials[threadIdx.x * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void idle_partials(double* partials) {
+  if (partials && threadIdx.x < K) partials[threadIdx.x * gridDim.x + blockIdx.x] = 0.0;
+}
+
+// Common prologue of the stencil kernels: the thread's own voxel, its halo
+// cell (threads < 480) and their tile cells.
+struct Cell {
+  int lx, ly, lz, g, C;     // own voxel
+  bool has_halo;
+  int hg, hC;               // halo cell: global index and tile cell
+};
+
+__device__ __forceinline__ Cell cell_setup(const int* nbs, int brick) {
+  Cell c;
+  const int t = threadIdx.x;
+  c.lx = t >> 6;
+  c.ly = (t >> 3) & 7;
+  c.lz = t & 7;
+  c.g = brick * kBV + t;
+  c.C = tidx(c.lx + 1, c.ly + 1, c.lz + 1);
+  c.has_halo = t < kHalo;
+  c.hg = 0;
+  c.hC = 0;
+  if (c.has_halo) {
+    int hx, hy, hz;
+    halo_cell(t, hx, hy, hz);
+    c.hg = tile_global(nbs, hx, hy, hz);
+    c.hC = tidx(hx, hy, hz);
+  }
+  return c;
+}
+
+}  // namespace dev
+}  // namespace ep

@@ -15,6 +15,7 @@
 
 #include "../../include/ep.h"
 #include "ep_internal.h"
+#include "ep_layout.h"
 
 using namespace ep;
 
@@ -683,33 +684,19 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   std::vector<uint8_t> boxmask(N, 1);
   if (d->mask)
     for (int64_t i = 0; i < N; ++i) boxmask[i] = d->mask[i] ? 1 : 0;
-  g->nbx = (g->n[0] + 7) / 8;
-  g->nby = (g->n[1] + 7) / 8;
-  g->nbz = (g->n[2] + 7) / 8;
-  const int64_t NB = static_cast<int64_t>(g->nbx) * g->nby * g->nbz;
-  g->brick_id.assign(NB, -1);
-  int64_t tissue = 0;
-  for (int x = 0; x < g->n[0]; ++x)
-    for (int y = 0; y < g->n[1]; ++y)
-      for (int z = 0; z < g->n[2]; ++z)
-        if (boxmask[box_index(g, x, y, z)]) {
-          ++tissue;
-          g->brick_id[(static_cast<int64_t>(x >> 3) * g->nby + (y >> 3)) * g->nbz + (z >> 3)] = 0;
-        }
-  if (tissue == 0) return fail(g, EP_ERR_ARG, "mask holds no tissue");
-  int nb = 0;
-  for (int64_t b = 0; b < NB; ++b)
-    if (g->brick_id[b] >= 0) {
-      g->brick_id[b] = nb++;
-      g->brick_pos.push_back(static_cast<int>(b / (static_cast<int64_t>(g->nby) * g->nbz)));
-      g->brick_pos.push_back(static_cast<int>((b / g->nbz) % g->nby));
-      g->brick_pos.push_back(static_cast<int>(b % g->nbz));
-    }
-  if (static_cast<int64_t>(nb + 1) * kBV >= (int64_t(1) << 31))
-    return fail(g, EP_ERR_ARG, "grid too large for 32-bit brick indexing");
+  BrickMap bm;
+  std::string merr;
+  if (!build_brick_map(g->n, boxmask.data(), bm, merr)) return fail(g, EP_ERR_ARG, merr);
+  g->nbx = bm.nbx;
+  g->nby = bm.nby;
+  g->nbz = bm.nbz;
+  g->brick_id = std::move(bm.brick_id);
+  g->brick_pos = std::move(bm.brick_pos);
+  g->hmask = std::move(bm.mask);
+  const int nb = bm.nb;
   g->nb = nb;
-  g->n_tissue = tissue;
-  g->nvox = static_cast<int64_t>(nb + 1) * kBV;
+  g->n_tissue = bm.n_tissue;
+  g->nvox = bm.nvox;
   g->grid = grid_for(nb);
   g->L.nb = nb;
   g->L.grid = g->grid;
@@ -717,27 +704,7 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   g->L.stream = g->stream;
   if (g->model == EP_BIDO && tissue_components(boxmask, g->n) != 1)
     return fail(g, EP_ERR_ARG, "bidomain tissue must be one face-connected component");
-
-  std::vector<int> hnbr(static_cast<size_t>(nb + 1) * kNbr, nb);
-  for (int id = 0; id < nb; ++id) {
-    const int bx = g->brick_pos[3 * id], by = g->brick_pos[3 * id + 1], bz = g->brick_pos[3 * id + 2];
-    for (int dx = -1; dx <= 1; ++dx)
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dz = -1; dz <= 1; ++dz) {
-          const int x = bx + dx, y = by + dy, z = bz + dz;
-          int v = nb;
-          if (x >= 0 && y >= 0 && z >= 0 && x < g->nbx && y < g->nby && z < g->nbz) {
-            const int id2 = g->brick_id[(static_cast<int64_t>(x) * g->nby + y) * g->nbz + z];
-            if (id2 >= 0) v = id2;
-          }
-          hnbr[static_cast<size_t>(id) * kNbr + (dx + 1) * 9 + (dy + 1) * 3 + (dz + 1)] = v;
-        }
-  }
-  g->hmask.assign(g->nvox, 0);
-  for (int x = 0; x < g->n[0]; ++x)
-    for (int y = 0; y < g->n[1]; ++y)
-      for (int z = 0; z < g->n[2]; ++z)
-        if (boxmask[box_index(g, x, y, z)]) g->hmask[brick_index(g, x, y, z)] = 1;
+  const std::vector<int>& hnbr = bm.nbr;
 
   // device buffers
   const size_t es = elem_size(g->prec);

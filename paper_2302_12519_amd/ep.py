@@ -60,6 +60,18 @@ class SolveInfo(C.Structure):
     _fields_ = [("outer", C.c_int32), ("inner_iters", C.c_int64), ("relres", C.c_double)]
 
 
+class BatchDesc(C.Structure):
+    _fields_ = [("hbm_budget", C.c_int64), ("max_slots", C.c_int32),
+                ("steps_per_launch", C.c_int32), ("stream", C.c_void_p)]
+
+
+class BatchStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("finished", C.c_int64),
+                ("released", C.c_int64), ("resident", C.c_int32), ("queued", C.c_int32),
+                ("arena_used", C.c_int64), ("arena_peak", C.c_int64),
+                ("graph_launches", C.c_int64), ("voxel_steps", C.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
@@ -83,9 +95,23 @@ def _load():
     lib.ep_status_string.restype = C.c_char_p
     lib.ep_last_error.argtypes = [vp]
     lib.ep_last_error.restype = C.c_char_p
+    lib.ep_batch_create.argtypes = [C.POINTER(BatchDesc), C.POINTER(vp)]
+    lib.ep_batch_submit.argtypes = [vp, C.POINTER(GridDesc), vp, vp, C.c_double, C.c_double,
+                                    C.c_int64, C.POINTER(C.c_int64)]
+    lib.ep_batch_advance.argtypes = [vp, C.POINTER(C.c_int32)]
+    lib.ep_batch_finished.argtypes = [vp, C.POINTER(C.c_int64), C.c_int32,
+                                      C.POINTER(C.c_int32)]
+    lib.ep_batch_read.argtypes = [vp, C.c_int64, C.c_int, vp, C.c_size_t]
+    lib.ep_batch_release.argtypes = [vp, C.c_int64]
+    lib.ep_batch_get_stats.argtypes = [vp, C.POINTER(BatchStats)]
+    lib.ep_batch_destroy.argtypes = [vp]
+    lib.ep_batch_last_error.argtypes = [vp]
+    lib.ep_batch_last_error.restype = C.c_char_p
     for name in ("ep_create_grid", "ep_set_conductivity_fibres", "ep_step", "ep_solve_elliptic",
                  "ep_read_state", "ep_write_state", "ep_get_step", "ep_set_step",
-                 "ep_grid_stats", "ep_kernel_timing", "ep_kernel_time", "ep_destroy_grid"):
+                 "ep_grid_stats", "ep_kernel_timing", "ep_kernel_time", "ep_destroy_grid",
+                 "ep_batch_create", "ep_batch_submit", "ep_batch_advance", "ep_batch_finished",
+                 "ep_batch_read", "ep_batch_release", "ep_batch_get_stats", "ep_batch_destroy"):
         getattr(lib, name).restype = C.c_int
     return lib
 
@@ -97,50 +123,65 @@ def _p(a):
     return a.ctypes.data_as(C.c_void_p)
 
 
+def make_desc(n, h, dt, mask=None, model="mono", prec="f32", diff="explicit", ionic=None,
+              stims=(), theta=0.5, pcg_rtol=1e-6, pcg_maxit=50, ell_rtol=1e-8,
+              ell_max_outer=8, ell_inner_maxit=4000, stream=None):
+    """Fill an ep_grid_desc; returns it and the arrays it points into (keep
+    them alive while the descriptor is used)."""
+    n = tuple(int(k) for k in n)
+    N = int(np.prod(n))
+    d = GridDesc()
+    d.n[:] = list(n)
+    d.h = float(h)
+    keep = []
+    if mask is not None:
+        m = np.ascontiguousarray(mask, dtype=np.uint8).ravel()
+        if m.size != N:
+            raise ValueError("mask size does not match n")
+        keep.append(m)
+        d.mask = _p(m)
+    d.model = EP_BIDO if model == "bido" else EP_MONO
+    d.prec = EP_F64 if prec == "f64" else EP_F32
+    d.diff = EP_DIFF_BE_PCG if diff == "be_pcg" else EP_DIFF_EXPLICIT
+    d.dt = float(dt)
+    io = ionic or {}
+    for k in ("tau_in", "tau_out", "tau_open", "tau_close", "v_gate", "exc"):
+        setattr(d.ionic, k, float(io[k]))
+    stims = list(stims)
+    arr = (Stim * max(1, len(stims)))()
+    for k, s in enumerate(stims):
+        arr[k].lo[:] = [int(v) for v in s.lo]
+        arr[k].hi[:] = [int(v) for v in s.hi]
+        arr[k].center[:] = [float(v) for v in s.center]
+        arr[k].radius = float(s.radius)
+        arr[k].amp = float(s.amp)
+        arr[k].t_on = float(s.t_on)
+        arr[k].t_off = float(s.t_off)
+    keep.append(arr)
+    d.stim = C.cast(arr, C.POINTER(Stim))
+    d.n_stim = len(stims)
+    d.act_threshold = float(theta)
+    d.pcg_rtol, d.pcg_maxit = float(pcg_rtol), int(pcg_maxit)
+    d.ell_rtol, d.ell_max_outer = float(ell_rtol), int(ell_max_outer)
+    d.ell_inner_maxit = int(ell_inner_maxit)
+    d.stream = stream
+    return d, keep
+
+
 class Grid:
     """One simulation grid on the GPU (see include/ep.h for the semantics)."""
 
     def __init__(self, n, h, dt, mask=None, model="mono", prec="f32", diff="explicit",
                  ionic=None, stims=(), theta=0.5, pcg_rtol=1e-6, pcg_maxit=50,
                  ell_rtol=1e-8, ell_max_outer=8, ell_inner_maxit=4000, stream=None):
+        self._desc, keep = make_desc(n, h, dt, mask, model, prec, diff, ionic, stims, theta,
+                                     pcg_rtol, pcg_maxit, ell_rtol, ell_max_outer,
+                                     ell_inner_maxit, stream)
+        self._keep = keep
         self.n = tuple(int(k) for k in n)
         self.N = int(np.prod(self.n))
-        d = GridDesc()
-        d.n[:] = list(self.n)
-        d.h = float(h)
-        self._mask = None
-        if mask is not None:
-            self._mask = np.ascontiguousarray(mask, dtype=np.uint8).ravel()
-            if self._mask.size != self.N:
-                raise ValueError("mask size does not match n")
-            d.mask = _p(self._mask)
-        d.model = EP_BIDO if model == "bido" else EP_MONO
-        d.prec = EP_F64 if prec == "f64" else EP_F32
-        d.diff = EP_DIFF_BE_PCG if diff == "be_pcg" else EP_DIFF_EXPLICIT
-        d.dt = float(dt)
-        io = ionic or {}
-        for k in ("tau_in", "tau_out", "tau_open", "tau_close", "v_gate", "exc"):
-            setattr(d.ionic, k, float(io[k]))
-        stims = list(stims)
-        self._stims = (Stim * max(1, len(stims)))()
-        for k, s in enumerate(stims):
-            self._stims[k].lo[:] = [int(v) for v in s.lo]
-            self._stims[k].hi[:] = [int(v) for v in s.hi]
-            self._stims[k].center[:] = [float(v) for v in s.center]
-            self._stims[k].radius = float(s.radius)
-            self._stims[k].amp = float(s.amp)
-            self._stims[k].t_on = float(s.t_on)
-            self._stims[k].t_off = float(s.t_off)
-        d.stim = C.cast(self._stims, C.POINTER(Stim))
-        d.n_stim = len(stims)
-        d.act_threshold = float(theta)
-        d.pcg_rtol, d.pcg_maxit = float(pcg_rtol), int(pcg_maxit)
-        d.ell_rtol, d.ell_max_outer = float(ell_rtol), int(ell_max_outer)
-        d.ell_inner_maxit = int(ell_inner_maxit)
-        d.stream = stream
-        self._desc = d
         self._h = C.c_void_p()
-        self._check(lib.ep_create_grid(C.byref(d), C.byref(self._h)), "ep_create_grid",
+        self._check(lib.ep_create_grid(C.byref(self._desc), C.byref(self._h)), "ep_create_grid",
                     handle=False)
 
     @classmethod
@@ -239,3 +280,75 @@ class Grid:
 
     def __exit__(self, *a):
         self.close()
+
+
+class Batch:
+    """Continuous-batching server state on the GPU (ep_batch_* of include/ep.h)."""
+
+    def __init__(self, hbm_budget, max_slots=64, steps_per_launch=16, stream=None):
+        d = BatchDesc(int(hbm_budget), int(max_slots), int(steps_per_launch), stream)
+        self._b = C.c_void_p()
+        st = lib.ep_batch_create(C.byref(d), C.byref(self._b))
+        if st != EP_OK:
+            raise EPError(st, f"ep_batch_create: {lib.ep_status_string(st).decode()}")
+        self._sizes = {}
+
+    def _check(self, st, what):
+        if st != EP_OK:
+            raise EPError(st, f"{what}: {lib.ep_status_string(st).decode()} "
+                              f"{lib.ep_batch_last_error(self._b).decode()}".strip())
+
+    def submit(self, n, h, dt, mask, ionic, stims, theta, fibre, scale, sig_l, sig_t, n_steps):
+        d, keep = make_desc(n, h, dt, mask, "mono", "f32", "explicit", ionic, stims, theta)
+        N = int(np.prod(n))
+        f = np.ascontiguousarray(fibre, dtype=np.float64).reshape(N * 3)
+        sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64).ravel()
+        rid = C.c_int64()
+        self._check(lib.ep_batch_submit(self._b, C.byref(d), _p(f), None if sc is None else _p(sc),
+                                        float(sig_l), float(sig_t), int(n_steps), C.byref(rid)),
+                    "ep_batch_submit")
+        self._sizes[rid.value] = tuple(int(k) for k in n)
+        return rid.value
+
+    def submit_instance(self, inst, n_steps=None):
+        return self.submit(inst.n, inst.h, inst.dt, inst.mask, inst.ionic, inst.stims, inst.theta,
+                           inst.fibre, inst.scale, inst.sigma_l, inst.sigma_t,
+                           inst.steps if n_steps is None else n_steps)
+
+    def advance(self):
+        nf = C.c_int32()
+        self._check(lib.ep_batch_advance(self._b, C.byref(nf)), "ep_batch_advance")
+        return nf.value
+
+    def finished(self, cap=1024):
+        ids = (C.c_int64 * cap)()
+        n = C.c_int32()
+        self._check(lib.ep_batch_finished(self._b, ids, cap, C.byref(n)), "ep_batch_finished")
+        return [ids[i] for i in range(n.value)]
+
+    def read(self, rid, field):
+        n = self._sizes[rid]
+        out = np.empty(int(np.prod(n)), dtype=np.float64)
+        self._check(lib.ep_batch_read(self._b, int(rid), FIELDS[field], _p(out), out.size),
+                    "ep_batch_read")
+        return out.reshape(n)
+
+    def release(self, rid):
+        self._check(lib.ep_batch_release(self._b, int(rid)), "ep_batch_release")
+        self._sizes.pop(rid, None)
+
+    def stats(self):
+        s = BatchStats()
+        self._check(lib.ep_batch_get_stats(self._b, C.byref(s)), "ep_batch_get_stats")
+        return {k: getattr(s, k) for k, _ in BatchStats._fields_}
+
+    def close(self):
+        if self._b:
+            lib.ep_batch_destroy(self._b)
+            self._b = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
