@@ -47,10 +47,13 @@ def parse():
                     help="budget for the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--serving", type=int, default=64,
+                    help="requests of the serving measurement (0 skips it)")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-box FP64 line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (for HBM counter scaling)")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles",
-                                                           "traffic_spmv_aniso_be_256.txt"))
+                                                           "traffic_cgcg_aniso_be_256.txt"))
     return ap.parse_args()
 
 
@@ -93,6 +96,71 @@ def cpu_baseline(inst, budget_s):
             "kind": "oracle",
             "sample": f"first {steps} step(s) of the same {inst.n[0]}^3 workload from rest, "
                       f"FP64, CG to 1e-13, {dt:.1f} s wall"}
+
+
+def bench_serving(count):
+    """Serving workload: `count` requests (grids 48^3..160^3 shells, sigma x
+    U[0.5,1.5], excitability U[0.8,1.2], 200..1000 FP32 explicit steps).  A
+    burst run measures capacity; a Poisson stream at 0.9 x capacity gives
+    p50/p99 latency.  The same requests one at a time on the plain FP64
+    per-grid path give the comparison throughput."""
+    import ep_inputs as E
+    from paper_2302_12519_amd import Grid, serve
+    from paper_2302_12519_amd.ep import Batch
+
+    t = time.perf_counter()
+    reqs = E.serving_stream(count=count, burst=True)
+    gen_s = time.perf_counter() - t
+    work = sum(r.inst.nt * r.inst.steps for r in reqs)
+    budget, slots, K = 16 << 30, count, 16
+
+    def run(rs):
+        b = Batch(budget, max_slots=slots, steps_per_launch=K)
+        out = serve.serve(b, rs, fields=("tact",))
+        b.close()
+        return out
+
+    burst = run([serve.InstanceRequest(r.rid, 0.0, r.inst) for r in reqs])
+    capacity = count / burst["makespan"]
+    rate = 0.9 * capacity
+    arrivals = E.serving_stream(count=count, rate=rate, burst=False)
+    poisson = run([serve.InstanceRequest(r.rid, a.arrival, r.inst)
+                   for r, a in zip(reqs, arrivals)])
+    # the plain one-request-at-a-time FP64 GPU path on the same requests
+    t = time.perf_counter()
+    for r in reqs:
+        g = Grid.from_instance(r.inst, prec="f64")
+        g.step(r.inst.steps)
+        g.read("tact")
+        g.close()
+    t64 = time.perf_counter() - t
+    return {"requests": count, "voxel_steps": work, "steps_per_graph": K,
+            "burst": {"makespan_s": burst["makespan"], "voxel_steps_per_s": work / burst["makespan"],
+                      "p50_s": burst["p50"], "p99_s": burst["p99"]},
+            "poisson": {"rate_per_s": rate, "makespan_s": poisson["makespan"],
+                        "voxel_steps_per_s": work / poisson["makespan"],
+                        "p50_s": poisson["p50"], "p99_s": poisson["p99"]},
+            "fp64_one_at_a_time": {"seconds": t64, "voxel_steps_per_s": work / t64},
+            "speedup_vs_fp64": (work / burst["makespan"]) / (work / t64),
+            "generation_s": gen_s}
+
+
+def bench_plain_fp64(steps=1000):
+    """Plain monodomain 32^3 FP64 box (dt 0.01, 1000 steps): microseconds per
+    step of the fused explicit kernel; this size is launch-bound."""
+    import ep_inputs as E
+    import torch
+    from paper_2302_12519_amd import Grid
+    inst = E.plain_box(32, steps=steps, prec="f64")
+    g = Grid.from_instance(inst)
+    g.step(10)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    g.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    g.close()
+    return {"us_per_step": 1e6 * dt / steps, "voxel_steps_per_s": inst.nt * steps / dt}
 
 
 def main():
@@ -181,9 +249,13 @@ def main():
         o.run(1)
         v, ref = g.read("v"), o.field("v")
         out["parity_one_step"] = float(np.abs(v - ref).max() / np.abs(ref).max())
+    g.close()
+    if a.serving:
+        out["serving"] = bench_serving(a.serving)
+    if not a.no_plain:
+        out["plain_box_32_fp64"] = bench_plain_fp64()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, a.cpu_seconds)
-    g.close()
     print(json.dumps(out), flush=True)
 
 

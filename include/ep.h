@@ -157,6 +157,36 @@ EP_API ep_status ep_step(ep_grid g, int32_t nsteps, ep_step_info* info);
 EP_API ep_status ep_solve_elliptic(ep_grid g, double rel_tol, int32_t max_outer,
                                    ep_solve_info* info);
 
+/* Gradient of an activation-time misfit with respect to the per-voxel
+ * conductivity scale s (the `scale` of ep_set_conductivity_fibres, D = s D0),
+ * by the discrete adjoint of the explicit monodomain step.  The thesis offers
+ * the simulation as the objective function of parameter estimation and
+ * patient fitting (Abstract; Cardiac Simulation chapter, Results,
+ * "Electrophysiology"); this call differentiates that objective:
+ *   L = sum over tissue voxels activated during the run with a finite
+ *       target of (T_act - T*)^2,
+ * T_act as ep_step records it (first crossing of act_threshold, linear
+ * interpolation inside the step).
+ *  - Runs nsteps explicit steps from the current state, with T_act reset to
+ *    +inf at the start; the grid ends in the run's final state (v, w, T_act,
+ *    step), as ep_step would leave it.
+ *  - tstar: host, box layout, n0*n1*n2 entries in ms; non-finite = no target.
+ *  - grad: host output, box layout, dL/ds per voxel (0 off tissue), in the
+ *    state precision of the grid, accumulated in FP64.
+ *  - loss, n_used: L and the number of voxels in the sum.
+ *  - ckpt_every K >= 1: the forward run keeps (v, w) every K steps; the
+ *    backward pass recomputes one K-step segment at a time.  Device memory:
+ *    about (3 ceil(nsteps / K) + 2 K + 7) state-precision fields of the
+ *    padded grid.  K = 0 picks K = round(sqrt(1.5 nsteps)).
+ *  - The gate-switch derivative at v = v_gate (a Dirac) is dropped: the
+ *    gradient is that of the piecewise-smooth map with the branch held.
+ * Errors: EP_ERR_UNSUPPORTED (not explicit monodomain), EP_ERR_STATE (no
+ * conductivity), EP_ERR_ARG (NULL, nsteps < 1, ckpt_every < 0), EP_ERR_OOM
+ * (work block does not fit), EP_ERR_NONFINITE, EP_ERR_HIP. */
+EP_API ep_status ep_adjoint_scale(ep_grid g, int32_t nsteps, int32_t ckpt_every,
+                                  const double* tstar, double* loss, double* grad,
+                                  int64_t* n_used);
+
 /* Copy a field to host FP64 in box layout (n0*n1*n2 entries); non-tissue
  * voxels read 0 (v, w, phi) or +inf (T_act).  Synchronises the stream.
  * Errors: EP_ERR_ARG (NULL, n too small, bad field), EP_ERR_HIP. */

@@ -95,10 +95,11 @@ void launch_tensor_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask
                          double h, double* tens /*6 arrays, scratch*/, double* c64[6],
                          float* c32[6]);
 
+// cross (nullable): records the step index where T_act is first set
 template <typename T>
 void launch_explicit(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v,
                      const T* w, const T* jstim, T* vout, T* wout, T* tact,
-                     IonicT<T> ion, T dt, T theta, double tn, int* flags);
+                     IonicT<T> ion, T dt, T theta, double tn, int* flags, int* cross, int step);
 
 template <typename T>
 void launch_ionic(const LaunchCfg& L, const T* v, const T* w, const T* jstim, T* vs,
@@ -171,5 +172,24 @@ void launch_parabolic(const LaunchCfg& L, const int* nbr, CoefSet<T> ci, const T
 template <typename T>
 void launch_apply(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* x, T* y,
                   double* partials);
+
+// discrete adjoint of the explicit monodomain step (reverse mode)
+template <typename T>
+void launch_adj_init(const LaunchCfg& L, const uint8_t* mask, const T* vlast, const T* vprev,
+                     const int* cross, const T* tact, const T* tstar, T* lv, T* lw, T dt,
+                     T theta, int nlast);
+template <typename T>
+void launch_adj_step(const LaunchCfg& L, const int* nbr, CoefSet<T> c, CoefSet<T> d0,
+                     const uint8_t* mask, const T* lv_in, const T* lw_in, T* lv_out, T* lw_out,
+                     const T* v, const T* w, const T* jstim, const T* vnext, const T* vprev,
+                     const int* cross, const T* tact, const T* tstar, double* grad,
+                     IonicT<T> ion, T dt, T theta, T inv_h2, int n);
+// unscaled voxel tensors D0 (6 component arrays) from unit fibres
+template <typename T>
+void launch_unit_tensors(const LaunchCfg& L, const uint8_t* mask, const double* fib,
+                         double sig_l, double sig_t, T* out[6]);
+template <typename T>
+void launch_loss(const LaunchCfg& L, const uint8_t* mask, const int* cross, const T* tact,
+                 const T* tstar, double* partials);
 
 }  // namespace ep

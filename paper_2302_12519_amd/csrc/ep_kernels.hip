@@ -84,6 +84,23 @@ __global__ __launch_bounds__(kBV) void k_tensor(int nb, const uint8_t* __restric
   tens[5 * stride + g] = t ? s * (a * f1 * f2) : 0.0;
 }
 
+// unscaled voxel tensors (scale 1) in state precision, 6 component arrays
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_unit_tensor(int nb, const uint8_t* __restrict__ mask,
+                                                     const double* __restrict__ fib, double sig_l,
+                                                     double sig_t, CoefOut<T> out) {
+  const int brick = block_brick();
+  if (brick >= nb) return;
+  const int g = brick * kBV + threadIdx.x;
+  const bool t = mask[g] != 0;
+  const double f0 = fib[3 * (int64_t)g], f1 = fib[3 * (int64_t)g + 1], f2 = fib[3 * (int64_t)g + 2];
+  const double a = sig_l - sig_t;
+  const double d[6] = {sig_t + a * f0 * f0, sig_t + a * f1 * f1, sig_t + a * f2 * f2,
+                       a * f0 * f1,         a * f0 * f2,         a * f1 * f2};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) out.c[k][g] = t ? static_cast<T>(d[k]) : T(0);
+}
+
 // Face weight: mean of the two voxel tensors / h^2 when both are tissue.
 // Edge weight: mean of the four voxel tensors of the 2x2 block / (2 h^2)
 // when all four are tissue.  Terms touching non-tissue are dropped (no flux).
@@ -141,7 +158,8 @@ __global__ __launch_bounds__(kBV) void k_explicit(int nb, const int* __restrict_
                                                   const T* __restrict__ jstim,
                                                   T* __restrict__ vout, T* __restrict__ wout,
                                                   T* __restrict__ tact, IonicT<T> ion, T dt,
-                                                  T theta, double tn, int* flags) {
+                                                  T theta, double tn, int* flags,
+                                                  int* __restrict__ cross, int step) {
   __shared__ T s[kTile];
   __shared__ int nbs[kNbr];
   const int brick = block_brick();
@@ -172,7 +190,10 @@ __global__ __launch_bounds__(kBV) void k_explicit(int nb, const int* __restrict_
   vout[q.g] = vn;
   wout[q.g] = ws;
   if (v0 < theta && theta <= vn) {
-    if (isinf(tact[q.g])) tact[q.g] = static_cast<T>(tn) + dt * (theta - v0) / (vn - v0);
+    if (isinf(tact[q.g])) {
+      tact[q.g] = static_cast<T>(tn) + dt * (theta - v0) / (vn - v0);
+      if (cross) cross[q.g] = step;
+    }
   }
   if (!isfinite(vn)) flags[0] = 1;
 }
@@ -670,6 +691,174 @@ __global__ __launch_bounds__(kBV) void k_scale(int nb, double* __restrict__ x,
   x[g] = n2 > 0.0 ? y[g] / sqrt(n2) : 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// discrete adjoint of the explicit monodomain step (reverse mode)
+// ---------------------------------------------------------------------------
+// Forward step n: v* = v + dt f(v, w) (+ J_stim), w' = w + dt g(v, w),
+// v_{n+1} = (I + dt A(s)) v*, with A symmetric and the voxel tensors
+// s_q D0_q.  Activation times T enter the loss sum (T - T*)^2.
+//
+// Adjoint step n maps (lv, lw) = dL/d(v_{n+1}, w_{n+1}) to dL/d(v_n, w_n):
+//   nu   = lv + dt A lv                                   ((I + dt A)^T)
+//   grad_q += -dt dB(lv, v*)/ds_q   (B: bilinear form of the energy; faces
+//             touching q carry D0_q / 2, 2x2 blocks D0_q / 4)
+//   lv_n = nu dv*/dv + (direct dT/dv_n of crossings at steps n and n-1)
+//   lw_n = nu dv*/dw + lw dw'/dw  (the gate switch is a Dirac, dropped)
+
+// dB(mu, u)/ds_q at tile cell C for voxel tensor d0 (xx, yy, zz, xy, xz, yz)
+template <typename T>
+__device__ __forceinline__ T dB_ds(const T* sm, const T* su, const uint8_t* mk, int C,
+                                   const T d0[6], T inv_h2) {
+  T acc = T(0);
+  const int off[3] = {100, 10, 1};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+#pragma unroll
+    for (int sg = -1; sg <= 1; sg += 2) {
+      const int Q = C + sg * off[d];
+      if (mk[C] && mk[Q])
+        acc += T(0.5) * d0[d] * (sm[Q] - sm[C]) * (su[Q] - su[C]) * inv_h2;
+    }
+  }
+  const int pd[3] = {0, 0, 1}, pe[3] = {1, 2, 2};
+#pragma unroll
+  for (int pl = 0; pl < 3; ++pl) {
+    const int od = off[pd[pl]], oe = off[pe[pl]];
+#pragma unroll
+    for (int ad = 0; ad <= 1; ++ad) {
+#pragma unroll
+      for (int ae = 0; ae <= 1; ++ae) {
+        const int b0 = C - ad * od - ae * oe;
+        const int b1 = b0 + od, b2 = b0 + oe, b3 = b0 + od + oe;
+        if (!(mk[b0] && mk[b1] && mk[b2] && mk[b3])) continue;
+        const T gdm = sm[b1] + sm[b3] - sm[b0] - sm[b2];
+        const T gem = sm[b2] + sm[b3] - sm[b0] - sm[b1];
+        const T gdu = su[b1] + su[b3] - su[b0] - su[b2];
+        const T geu = su[b2] + su[b3] - su[b0] - su[b1];
+        acc += T(0.25) * d0[3 + pl] * (gdm * geu + gdu * gem) * (T(0.25) * inv_h2);
+      }
+    }
+  }
+  return acc;
+}
+
+// dT/dv seed of a voxel that crossed theta at step `cs`: T depends on
+// v_cs (before) and v_cs+1 (after).
+template <typename T>
+__device__ __forceinline__ T cross_seed(T vb, T va, T theta, T dt, T dl, bool before) {
+  const T del = va - vb;
+  return before ? dl * (dt * (theta - va) / (del * del))
+                : dl * (-dt * (theta - vb) / (del * del));
+}
+
+// lv_N = seeds of crossings at step N-1 (dT/dv_N), lw_N = 0
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_adj_init(int nb, const uint8_t* __restrict__ mask,
+                                                  const T* __restrict__ vlast,
+                                                  const T* __restrict__ vprev,
+                                                  const int* __restrict__ cross,
+                                                  const T* __restrict__ tact,
+                                                  const T* __restrict__ tstar, T* __restrict__ lv,
+                                                  T* __restrict__ lw, T dt, T theta, int nlast) {
+  const int brick = block_brick();
+  if (brick >= nb) return;
+  const int g = brick * kBV + threadIdx.x;
+  T a = T(0);
+  if (mask[g] && cross[g] == nlast && isfinite(tstar[g]))
+    a = cross_seed(vprev[g], vlast[g], theta, dt, T(2) * (tact[g] - tstar[g]), false);
+  lv[g] = a;
+  lw[g] = T(0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_adj_step(
+    int nb, const int* __restrict__ nbr, CoefSet<T> c, CoefSet<T> d0,
+    const uint8_t* __restrict__ mask, const T* __restrict__ lv_in, const T* __restrict__ lw_in,
+    T* __restrict__ lv_out, T* __restrict__ lw_out, const T* __restrict__ v,
+    const T* __restrict__ w, const T* __restrict__ jstim, const T* __restrict__ vnext,
+    const T* __restrict__ vprev, const int* __restrict__ cross, const T* __restrict__ tact,
+    const T* __restrict__ tstar, double* __restrict__ grad, IonicT<T> ion, T dt, T theta,
+    T inv_h2, int n) {
+  __shared__ T sm[kTile];
+  __shared__ T su[kTile];
+  __shared__ uint8_t mk[kTile];
+  __shared__ int nbs[kNbr];
+  const int brick = block_brick();
+  if (brick >= nb) return;
+  if (threadIdx.x < kNbr) nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
+  __syncthreads();
+  const Cell q = cell_setup(nbs, brick);
+  const T mu = lv_in[q.g], v0 = v[q.g], w0 = w[q.g];
+  const T j0 = jstim ? jstim[q.g] : T(0);
+  const uint8_t m0 = mask[q.g];
+  T hm = T(0), hv = T(0), hw = T(0), hj = T(0);
+  uint8_t hk = 0;
+  if (q.has_halo) {
+    hm = lv_in[q.hg];
+    hv = v[q.hg];
+    hw = w[q.hg];
+    hj = jstim ? jstim[q.hg] : T(0);
+    hk = mask[q.hg];
+  }
+  T k18[18];
+  gather18(c, nbs, brick, q.lx, q.ly, q.lz, k18);
+  T dq[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) dq[k] = d0.c[k][q.g];
+  T vs, ws;
+  ms_step(v0, w0, j0, ion, dt, vs, ws);
+  sm[q.C] = mu;
+  su[q.C] = vs;
+  mk[q.C] = m0;
+  if (q.has_halo) {
+    T a, b;
+    ms_step(hv, hw, hj, ion, dt, a, b);
+    sm[q.hC] = hm;
+    su[q.hC] = a;
+    mk[q.hC] = hk;
+  }
+  __syncthreads();
+  if (!m0) {
+    lv_out[q.g] = T(0);
+    lw_out[q.g] = T(0);
+    return;
+  }
+  const T nu = mu + dt * apply19(sm, q.C, k18);
+  grad[q.g] -= static_cast<double>(dt * dB_ds(sm, su, mk, q.C, dq, inv_h2));
+  const T dvs_dv = T(1) + dt * (ion.exc * (T(2) * v0 - T(3) * v0 * v0) * w0 * ion.inv_tau_in -
+                                ion.inv_tau_out);
+  const T dvs_dw = dt * ion.exc * v0 * v0 * (T(1) - v0) * ion.inv_tau_in;
+  const T dws_dw = (v0 < ion.v_gate) ? T(1) - dt * ion.inv_tau_open : T(1) - dt * ion.inv_tau_close;
+  T lvn = nu * dvs_dv;
+  const int cs = cross[q.g];
+  if ((cs == n || (vprev && cs == n - 1)) && isfinite(tstar[q.g])) {
+    const T dl = T(2) * (tact[q.g] - tstar[q.g]);
+    if (cs == n) lvn += cross_seed(v0, vnext[q.g], theta, dt, dl, true);
+    else lvn += cross_seed(vprev[q.g], v0, theta, dt, dl, false);
+  }
+  lv_out[q.g] = lvn;
+  lw_out[q.g] = nu * dvs_dw + lw_in[q.g] * dws_dw;
+}
+
+// loss partials over voxels activated in the run and in the target:
+// ((T - T*)^2, count)
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_loss(int nb, const uint8_t* __restrict__ mask,
+                                              const int* __restrict__ cross,
+                                              const T* __restrict__ tact,
+                                              const T* __restrict__ tstar, double* partials) {
+  const int brick = block_brick();
+  if (brick >= nb) { idle_partials<2>(partials); return; }
+  const int g = brick * kBV + threadIdx.x;
+  double acc[2] = {0.0, 0.0};
+  if (mask[g] && cross[g] >= 0 && isfinite(tstar[g])) {
+    const double d = static_cast<double>(tact[g]) - static_cast<double>(tstar[g]);
+    acc[0] = d * d;
+    acc[1] = 1.0;
+  }
+  block_partials<2>(acc, partials);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -699,11 +888,19 @@ void launch_tensor_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask
 }
 
 template <typename T>
+void launch_unit_tensors(const LaunchCfg& L, const uint8_t* mask, const double* fib,
+                         double sig_l, double sig_t, T* out[6]) {
+  CoefOut<T> o;
+  for (int k = 0; k < 6; ++k) o.c[k] = out[k];
+  k_unit_tensor<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, mask, fib, sig_l, sig_t, o);
+}
+
+template <typename T>
 void launch_explicit(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v, const T* w,
                      const T* jstim, T* vout, T* wout, T* tact, IonicT<T> ion, T dt, T theta,
-                     double tn, int* flags) {
+                     double tn, int* flags, int* cross, int step) {
   k_explicit<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, vout, wout, tact, ion,
-                                              dt, theta, tn, flags);
+                                              dt, theta, tn, flags, cross, step);
 }
 
 template <typename T>
@@ -799,10 +996,35 @@ void launch_apply(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* x, 
   k_apply<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, c, x, y, partials);
 }
 
+template <typename T>
+void launch_adj_init(const LaunchCfg& L, const uint8_t* mask, const T* vlast, const T* vprev,
+                     const int* cross, const T* tact, const T* tstar, T* lv, T* lw, T dt,
+                     T theta, int nlast) {
+  k_adj_init<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, mask, vlast, vprev, cross, tact, tstar, lv,
+                                              lw, dt, theta, nlast);
+}
+
+template <typename T>
+void launch_adj_step(const LaunchCfg& L, const int* nbr, CoefSet<T> c, CoefSet<T> d0,
+                     const uint8_t* mask, const T* lv_in, const T* lw_in, T* lv_out, T* lw_out,
+                     const T* v, const T* w, const T* jstim, const T* vnext, const T* vprev,
+                     const int* cross, const T* tact, const T* tstar, double* grad,
+                     IonicT<T> ion, T dt, T theta, T inv_h2, int n) {
+  k_adj_step<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, c, d0, mask, lv_in, lw_in, lv_out,
+                                              lw_out, v, w, jstim, vnext, vprev, cross, tact,
+                                              tstar, grad, ion, dt, theta, inv_h2, n);
+}
+
+template <typename T>
+void launch_loss(const LaunchCfg& L, const uint8_t* mask, const int* cross, const T* tact,
+                 const T* tstar, double* partials) {
+  k_loss<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, mask, cross, tact, tstar, partials);
+}
+
 #define EP_INST(T)                                                                             \
   template void launch_explicit<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*,         \
                                    const T*, const T*, T*, T*, T*, IonicT<T>, T, T, double,    \
-                                   int*);                                                      \
+                                   int*, int*, int);                                           \
   template void launch_ionic<T>(const LaunchCfg&, const T*, const T*, const T*, T*, T*,        \
                                 IonicT<T>, T);                                                 \
   template void launch_be_init<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*,          \
@@ -822,7 +1044,17 @@ void launch_apply(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* x, 
   template void launch_parabolic<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*,        \
                                     const double*, const T*, T*, T*, T, T, double, int*);      \
   template void launch_apply<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*, T*,        \
-                                double*);
+                                double*);                                                      \
+  template void launch_adj_init<T>(const LaunchCfg&, const uint8_t*, const T*, const T*,       \
+                                   const int*, const T*, const T*, T*, T*, T, T, int);         \
+  template void launch_adj_step<T>(const LaunchCfg&, const int*, CoefSet<T>, CoefSet<T>,       \
+                                   const uint8_t*, const T*, const T*, T*, T*, const T*,       \
+                                   const T*, const T*, const T*, const T*, const int*,         \
+                                   const T*, const T*, double*, IonicT<T>, T, T, T, int);      \
+  template void launch_unit_tensors<T>(const LaunchCfg&, const uint8_t*, const double*, double, \
+                                       double, T*[6]);                                         \
+  template void launch_loss<T>(const LaunchCfg&, const uint8_t*, const int*, const T*,         \
+                               const T*, double*);
 
 EP_INST(float)
 EP_INST(double)

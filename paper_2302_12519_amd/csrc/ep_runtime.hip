@@ -96,6 +96,9 @@ struct ep_grid_s {
   float* d_w32[2] = {nullptr, nullptr};
   float* d_p32 = nullptr;
   float* d_dinvk = nullptr;
+  void* d_d0[6] = {};         // explicit monodomain: unscaled voxel tensors (adjoint)
+  void* d_adj = nullptr;      // adjoint work block (cached, grown on demand)
+  size_t adj_cap = 0;
   double* d_partials = nullptr;   // per-block partial sums of one-brick-per-block launches
   double* d_cgp[2] = {nullptr, nullptr};  // persistent CG launches: ping-pong partials
   CGScalars* d_cg = nullptr;      // two solver-scalar records, ping-pong
@@ -390,7 +393,7 @@ ep_status step_explicit(ep_grid g, const T* jstim) {
                      static_cast<const T*>(g->d_w[c]), jstim, static_cast<T*>(g->d_v[n]),
                      static_cast<T*>(g->d_w[n]), static_cast<T*>(g->d_tact), ionic_t<T>(g),
                      static_cast<T>(g->dt), static_cast<T>(g->theta),
-                     static_cast<double>(g->step) * g->dt, g->d_flags);
+                     static_cast<double>(g->step) * g->dt, g->d_flags, nullptr, 0);
   timer_end(g, t0);
   return EP_OK;
 }
@@ -548,6 +551,174 @@ ep_status run_steps(ep_grid g, int32_t nsteps, ep_step_info* info) {
   if (g->hs->flags[0]) g->nonfinite = true;
   if (g->nonfinite) return fail(g, EP_ERR_NONFINITE, "non-finite potential");
   if (noconv) return fail(g, EP_ERR_NOCONV, "a linear solve hit its iteration limit");
+  return EP_OK;
+}
+
+// ---- adjoint of the explicit monodomain run (checkpointed) ------------------
+// Forward: nsteps explicit steps from the current state with a fresh T_act,
+// recording each voxel's crossing step and, every K steps, a checkpoint
+// (v, w at the segment start and v one step earlier).  Backward: per segment,
+// last first, the segment's states are recomputed from its checkpoint (the
+// forward kernel is deterministic, so they are bitwise the forward's) and the
+// adjoint kernel runs once per step, last step first.
+template <typename T>
+ep_status adjoint_impl(ep_grid g, int32_t nsteps, int32_t K, const double* tstar_box,
+                       double* loss, double* grad_box, int64_t* n_used) {
+  const int64_t nv = g->nvox;
+  const size_t vb = static_cast<size_t>(nv) * sizeof(T);
+  const int S = (nsteps + K - 1) / K;
+  // work block: grad (FP64), cross, T*, lv/lw ping-pong, checkpoints, segment
+  const size_t n_arr = 1 + 4 + 3 * static_cast<size_t>(S) + 2 * (static_cast<size_t>(K) + 1);
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t need = al(nv * sizeof(double)) + al(nv * sizeof(int)) + n_arr * al(vb);
+  if (need > g->adj_cap) {
+    if (g->d_adj) {
+      HIPCHK(g, hipStreamSynchronize(g->stream));
+      (void)hipFree(g->d_adj);
+      g->d_adj = nullptr;
+      g->adj_cap = 0;
+    }
+    if (hipMalloc(&g->d_adj, need) != hipSuccess) {
+      (void)hipGetLastError();
+      g->d_adj = nullptr;
+      return fail(g, EP_ERR_OOM, "adjoint work block of " + std::to_string(need) +
+                                     " bytes does not fit; raise ckpt_every or lower nsteps");
+    }
+    g->adj_cap = need;
+  }
+  char* base = static_cast<char*>(g->d_adj);
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    void* p = base + off;
+    off += al(b);
+    return p;
+  };
+  double* d_grad = static_cast<double*>(take(nv * sizeof(double)));
+  int* d_cross = static_cast<int*>(take(nv * sizeof(int)));
+  T* d_tstar = static_cast<T*>(take(vb));
+  T* lv[2] = {static_cast<T*>(take(vb)), static_cast<T*>(take(vb))};
+  T* lw[2] = {static_cast<T*>(take(vb)), static_cast<T*>(take(vb))};
+  std::vector<T*> ck_v(S), ck_w(S), ck_vp(S), seg_v(K + 1), seg_w(K + 1);
+  for (int c = 0; c < S; ++c) {
+    ck_v[c] = static_cast<T*>(take(vb));
+    ck_w[c] = static_cast<T*>(take(vb));
+    ck_vp[c] = static_cast<T*>(take(vb));
+  }
+  for (int i = 0; i <= K; ++i) {
+    seg_v[i] = static_cast<T*>(take(vb));
+    seg_w[i] = static_cast<T*>(take(vb));
+  }
+
+  // targets to brick layout (non-finite = no target; non-tissue = no target)
+  {
+    std::vector<T> ht(nv, std::numeric_limits<T>::infinity());
+    for (int x = 0; x < g->n[0]; ++x)
+      for (int y = 0; y < g->n[1]; ++y)
+        for (int z = 0; z < g->n[2]; ++z) {
+          const int64_t gi = brick_index(g, x, y, z);
+          if (gi < 0 || !g->hmask[gi]) continue;
+          const double t = tstar_box[box_index(g, x, y, z)];
+          ht[gi] = std::isfinite(t) ? static_cast<T>(t) : std::numeric_limits<T>::infinity();
+        }
+    HIPCHK(g, hipMemcpyAsync(d_tstar, ht.data(), vb, hipMemcpyHostToDevice, g->stream));
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+  }
+  HIPCHK(g, hipMemsetAsync(d_grad, 0, nv * sizeof(double), g->stream));
+  HIPCHK(g, hipMemsetAsync(d_cross, 0xff, nv * sizeof(int), g->stream));  // -1
+  {
+    std::vector<T> inf(nv, std::numeric_limits<T>::infinity());
+    HIPCHK(g, hipMemcpyAsync(g->d_tact, inf.data(), vb, hipMemcpyHostToDevice, g->stream));
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+  }
+  HIPCHK(g, hipMemsetAsync(g->d_qacc, 0, sizeof(double), g->stream));
+
+  const CoefSet<T> c = coefs<T>(g);
+  CoefSet<T> d0;
+  for (int k = 0; k < 6; ++k) d0.c[k] = static_cast<const T*>(g->d_d0[k]);
+  const IonicT<T> ion = ionic_t<T>(g);
+  const T dt = static_cast<T>(g->dt), theta = static_cast<T>(g->theta);
+  const int64_t step0 = g->step;
+  T* tact = static_cast<T*>(g->d_tact);
+
+  // forward
+  for (int32_t s = 0; s < nsteps; ++s) {
+    const int cu = g->cur, nx = 1 - cu;
+    if (s % K == 0) {
+      const int ci = s / K;
+      HIPCHK(g, hipMemcpyAsync(ck_v[ci], g->d_v[cu], vb, hipMemcpyDeviceToDevice, g->stream));
+      HIPCHK(g, hipMemcpyAsync(ck_w[ci], g->d_w[cu], vb, hipMemcpyDeviceToDevice, g->stream));
+      if (s > 0)
+        HIPCHK(g, hipMemcpyAsync(ck_vp[ci], g->d_v[nx], vb, hipMemcpyDeviceToDevice, g->stream));
+    }
+    const T* jstim = nullptr;
+    TRY(update_stimulus<T>(g, step0 + s, &jstim));
+    launch_explicit<T>(g->L, g->d_nbr, c, static_cast<const T*>(g->d_v[cu]),
+                       static_cast<const T*>(g->d_w[cu]), jstim, static_cast<T*>(g->d_v[nx]),
+                       static_cast<T*>(g->d_w[nx]), tact, ion, dt, theta,
+                       static_cast<double>(step0 + s) * g->dt, g->d_flags, d_cross, s);
+    g->cur = nx;
+    g->step += 1;
+    g->have_prev = true;
+  }
+  HIPCHK(g, hipGetLastError());
+
+  // loss over voxels activated in the run with a finite target
+  launch_loss<T>(g->L, g->d_mask, d_cross, tact, d_tstar, g->d_partials);
+  launch_reduce_sum(g->stream, g->d_partials, g->grid, 2, g->d_sums + 4);
+  HIPCHK(g, hipMemcpyAsync(g->hs->sums, g->d_sums + 4, 2 * sizeof(double),
+                           hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(g, hipMemcpyAsync(g->hs->flags, g->d_flags, sizeof(int), hipMemcpyDeviceToHost,
+                           g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  if (g->hs->flags[0]) {
+    g->nonfinite = true;
+    return fail(g, EP_ERR_NONFINITE, "non-finite potential in the forward run");
+  }
+  *loss = g->hs->sums[0];
+  *n_used = static_cast<int64_t>(g->hs->sums[1] + 0.5);
+
+  // backward: lambda_N from the crossings of the last step
+  int a = 0;
+  launch_adj_init<T>(g->L, g->d_mask, static_cast<const T*>(g->d_v[g->cur]),
+                     static_cast<const T*>(g->d_v[1 - g->cur]), d_cross, tact, d_tstar, lv[0],
+                     lw[0], dt, theta, nsteps - 1);
+  const T inv_h2 = static_cast<T>(1.0 / (g->h * g->h));
+  for (int ci = S - 1; ci >= 0; --ci) {
+    const int s0 = ci * K, s1 = std::min(nsteps, s0 + K);
+    HIPCHK(g, hipMemcpyAsync(seg_v[0], ck_v[ci], vb, hipMemcpyDeviceToDevice, g->stream));
+    HIPCHK(g, hipMemcpyAsync(seg_w[0], ck_w[ci], vb, hipMemcpyDeviceToDevice, g->stream));
+    // recompute v_{s0+1..s1}, w_{s0+1..s1}; T_act is already set wherever a
+    // crossing happens, so the kernel leaves it (and the crossing steps) alone
+    for (int s = s0; s < s1; ++s) {
+      const T* jstim = nullptr;
+      TRY(update_stimulus<T>(g, step0 + s, &jstim));
+      const int i = s - s0;
+      launch_explicit<T>(g->L, g->d_nbr, c, seg_v[i], seg_w[i], jstim, seg_v[i + 1],
+                         seg_w[i + 1], tact, ion, dt, theta,
+                         static_cast<double>(step0 + s) * g->dt, g->d_flags, nullptr, 0);
+    }
+    for (int s = s1 - 1; s >= s0; --s) {
+      const T* jstim = nullptr;
+      TRY(update_stimulus<T>(g, step0 + s, &jstim));
+      const int i = s - s0;
+      const T* vprev = (i > 0) ? seg_v[i - 1] : (ci > 0 ? ck_vp[ci] : nullptr);
+      launch_adj_step<T>(g->L, g->d_nbr, c, d0, g->d_mask, lv[a], lw[a], lv[1 - a], lw[1 - a],
+                         seg_v[i], seg_w[i], jstim, seg_v[i + 1], vprev, d_cross, tact, d_tstar,
+                         d_grad, ion, dt, theta, inv_h2, s);
+      a = 1 - a;
+    }
+  }
+  HIPCHK(g, hipGetLastError());
+  std::vector<double> hg(nv);
+  HIPCHK(g, hipMemcpyAsync(hg.data(), d_grad, nv * sizeof(double), hipMemcpyDeviceToHost,
+                           g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  for (int x = 0; x < g->n[0]; ++x)
+    for (int y = 0; y < g->n[1]; ++y)
+      for (int z = 0; z < g->n[2]; ++z) {
+        const int64_t gi = brick_index(g, x, y, z);
+        grad_box[box_index(g, x, y, z)] = (gi < 0 || !g->hmask[gi]) ? 0.0 : hg[gi];
+      }
   return EP_OK;
 }
 
@@ -736,6 +907,8 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
     TRY(dalloc(g, &g->d_cp, vb));
     TRY(dalloc(g, &g->d_dinv, vb));
   }
+  if (g->model == EP_MONO && g->diff == EP_DIFF_EXPLICIT)
+    for (int k = 0; k < 6; ++k) TRY(dalloc(g, &g->d_d0[k], vb));
   if (g->model == EP_BIDO) {
     const size_t b64 = static_cast<size_t>(g->nvox) * sizeof(double);
     const size_t b32 = static_cast<size_t>(g->nvox) * sizeof(float);
@@ -916,6 +1089,14 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
       for (int k = 0; k < 6; ++k) c64[k] = static_cast<double*>(g->d_c[k]);
     launch_tensor_coefs(g->L, g->d_nbr, g->d_mask, dfib, dsc, sl, st, g->h, tens,
                         need64 ? c64 : nullptr, g->prec == EP_F32 ? c32 : nullptr);
+    if (g->model == EP_MONO && g->diff == EP_DIFF_EXPLICIT) {
+      if (g->prec == EP_F64)
+        launch_unit_tensors<double>(g->L, g->d_mask, dfib, sl, st,
+                                    reinterpret_cast<double**>(g->d_d0));
+      else
+        launch_unit_tensors<float>(g->L, g->d_mask, dfib, sl, st,
+                                   reinterpret_cast<float**>(g->d_d0));
+    }
     if (g->model == EP_BIDO) {
       if (g->prec == EP_F64) {
         // FP64 state: d_c already holds A_i in FP64; copy it into the FP64 twin
@@ -1000,6 +1181,28 @@ EP_API ep_status ep_step(ep_grid g, int32_t nsteps, ep_step_info* info) {
   try {
     return g->prec == EP_F64 ? run_steps<double>(g, nsteps, info)
                              : run_steps<float>(g, nsteps, info);
+  } catch (const std::bad_alloc&) {
+    return fail(g, EP_ERR_OOM, "host allocation failed");
+  }
+}
+
+EP_API ep_status ep_adjoint_scale(ep_grid g, int32_t nsteps, int32_t ckpt_every,
+                                  const double* tstar, double* loss, double* grad,
+                                  int64_t* n_used) {
+  if (!g) return EP_ERR_ARG;
+  if (!tstar || !loss || !grad || !n_used) return fail(g, EP_ERR_ARG, "NULL argument");
+  if (nsteps < 1) return fail(g, EP_ERR_ARG, "nsteps must be >= 1");
+  if (ckpt_every < 0) return fail(g, EP_ERR_ARG, "ckpt_every must be >= 0");
+  if (g->model != EP_MONO || g->diff != EP_DIFF_EXPLICIT)
+    return fail(g, EP_ERR_UNSUPPORTED, "the adjoint covers the explicit monodomain step only");
+  if (!g->has_cond) return fail(g, EP_ERR_STATE, "ep_set_conductivity_fibres not called");
+  if (g->nonfinite) return fail(g, EP_ERR_NONFINITE, "state is non-finite; write a new state");
+  int32_t K = ckpt_every;
+  if (K == 0) K = std::max(1, static_cast<int32_t>(std::lround(std::sqrt(1.5 * nsteps))));
+  K = std::min(K, nsteps);
+  try {
+    return g->prec == EP_F64 ? adjoint_impl<double>(g, nsteps, K, tstar, loss, grad, n_used)
+                             : adjoint_impl<float>(g, nsteps, K, tstar, loss, grad, n_used);
   } catch (const std::bad_alloc&) {
     return fail(g, EP_ERR_OOM, "host allocation failed");
   }
@@ -1100,6 +1303,7 @@ EP_API ep_status ep_destroy_grid(ep_grid g) {
   if (!g) return EP_ERR_ARG;
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   for (void* p : g->allocs) (void)hipFree(p);
+  if (g->d_adj) (void)hipFree(g->d_adj);
   for (int k = 0; k < kTimers; ++k)
     for (auto& tp : g->tk[k]) {
       (void)hipEventDestroy(tp.a);

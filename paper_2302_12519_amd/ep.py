@@ -90,6 +90,8 @@ def _load():
                                   C.POINTER(C.c_int64)]
     lib.ep_kernel_timing.argtypes = [vp, C.c_int32]
     lib.ep_kernel_time.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.ep_adjoint_scale.argtypes = [vp, C.c_int32, C.c_int32, vp, C.POINTER(C.c_double), vp,
+                                     C.POINTER(C.c_int64)]
     lib.ep_destroy_grid.argtypes = [vp]
     lib.ep_status_string.argtypes = [C.c_int]
     lib.ep_status_string.restype = C.c_char_p
@@ -110,6 +112,7 @@ def _load():
     for name in ("ep_create_grid", "ep_set_conductivity_fibres", "ep_step", "ep_solve_elliptic",
                  "ep_read_state", "ep_write_state", "ep_get_step", "ep_set_step",
                  "ep_grid_stats", "ep_kernel_timing", "ep_kernel_time", "ep_destroy_grid",
+                 "ep_adjoint_scale",
                  "ep_batch_create", "ep_batch_submit", "ep_batch_advance", "ep_batch_finished",
                  "ep_batch_read", "ep_batch_release", "ep_batch_get_stats", "ep_batch_destroy"):
         getattr(lib, name).restype = C.c_int
@@ -227,6 +230,19 @@ class Grid:
         out = {k: getattr(info, k) for k, _ in SolveInfo._fields_}
         out["status"] = st
         return out
+
+    def adjoint_scale(self, tstar, nsteps, ckpt_every=0):
+        """Run ``nsteps`` explicit steps with a fresh T_act and return
+        (loss, dL/dscale in box layout, voxels in the loss)."""
+        t = np.ascontiguousarray(tstar, dtype=np.float64).ravel()
+        if t.size != self.N:
+            raise ValueError("tstar size does not match n")
+        grad = np.empty(self.N, dtype=np.float64)
+        loss, used = C.c_double(), C.c_int64()
+        self._check(lib.ep_adjoint_scale(self._h, int(nsteps), int(ckpt_every), _p(t),
+                                         C.byref(loss), _p(grad), C.byref(used)),
+                    "ep_adjoint_scale")
+        return loss.value, grad.reshape(self.n), used.value
 
     def read(self, field):
         out = np.empty(self.N, dtype=np.float64)
