@@ -33,23 +33,31 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 #             (20 B)                                                   -> 68 B
 #   CG set-up u0 = M^-1 r0, w0 = K u0: reads r, M^-1, weights, writes w -> 36 B
 #   explicit fused step: reads v, w (8 B) + 24 B weights, writes v, w   -> 40 B
-ALGO_BYTES = {"cg_iter": 68, "cg_setup": 36, "stencil_explicit": 40}
+#   adjoint step: reads lambda_v, lambda_w, v, w, v_next, crossing step (24 B),
+#             weights and unscaled tensors (48 B), mask (1 B), gradient (8 B,
+#             FP64); writes lambda_v, lambda_w (8 B) and gradient (8 B)  -> 97 B
+ALGO_BYTES = {"cg_iter": 68, "cg_setup": 36, "stencil_explicit": 40, "adjoint_step": 97}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="grid edge of the shell workload")
     ap.add_argument("--rtol", type=float, default=1e-7)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget for the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--bidomain", type=int, default=192,
+                    help="grid edge of the bidomain line (0 = skip)")
+    ap.add_argument("--adjoint", type=int, default=128,
+                    help="grid edge of the adjoint line (0 = skip)")
     ap.add_argument("--serving", type=int, default=64,
                     help="requests of the serving measurement (0 skips it)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-box FP64 line")
+    ap.add_argument("--only", choices=["serving", "plain", "bidomain", "adjoint"],
+                    help="run one side workload alone and print its JSON (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (for HBM counter scaling)")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles",
@@ -163,6 +171,76 @@ def bench_plain_fp64(steps=1000):
     return {"us_per_step": 1e6 * dt / steps, "voxel_steps_per_s": inst.nt * steps / dt}
 
 
+def bench_bidomain(n, steps=20, warmup=3):
+    """Bidomain n^3 shell (sigma_i 0.17/0.019, sigma_e 0.62/0.24, dt 0.05):
+    per-step time of the full step (ionic, elliptic FP32 PCG inside FP64
+    refinement to 1e-8, parabolic update), timed on `steps` steps after
+    `warmup` from rest, with per-kernel averages."""
+    import ep_inputs as E
+    import torch
+    from paper_2302_12519_amd import Grid
+    inst = E.bidomain(n, steps=warmup + steps)
+    g = Grid.from_instance(inst)
+    g.step(warmup)
+    torch.cuda.synchronize()
+    g.kernel_timing(True)
+    t = time.perf_counter()
+    info = g.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    it_ms, it_n = g.kernel_time("stencil")
+    rs_ms, rs_n = g.kernel_time("resid")
+    pb_ms, pb_n = g.kernel_time("parabolic")
+    g.kernel_timing(False)
+    g.close()
+    avg_it = it_ms / max(it_n, 1)
+    return {"workload": f"bidomain_{n}: {inst.nt} tissue voxels, {steps} steps after {warmup}",
+            "voxel_steps_per_s": inst.nt * steps / dt, "ms_per_step": 1e3 * dt / steps,
+            "inner_iters_per_step": info["cg_iters"] / steps,
+            "outer_per_step": info["ell_outer"] / steps, "relres_last": info["relres"],
+            "inner_iter_avg_us": 1e3 * avg_it,
+            "inner_iter_achieved_gbs": ALGO_BYTES["cg_iter"] * inst.nt / (avg_it * 1e-3) / 1e9,
+            "resid64_avg_us": 1e3 * rs_ms / max(rs_n, 1),
+            "parabolic_avg_us": 1e3 * pb_ms / max(pb_n, 1)}
+
+
+def bench_adjoint(n, steps=500, K=50):
+    """Activation-time adjoint on the n^3 shell (smooth scale in [0.5, 1.5],
+    8 stimuli, FP32 explicit, dt 0.04): one ep_adjoint_scale call (forward
+    with checkpoints every K, per-segment recompute, adjoint steps); the
+    target comes from a GPU forward run with the second scale field."""
+    import ep_inputs as E
+    import torch
+    from paper_2302_12519_amd import Grid
+    inst = E.adjoint_shell(n, steps=steps)
+    gt = Grid.from_instance(E.adjoint_shell(n, steps=steps, target=True))
+    gt.step(steps)
+    tstar = gt.read("tact")
+    gt.close()
+    g = Grid.from_instance(inst)
+    g.adjoint_scale(tstar, steps, K)          # warm-up (allocates the work block)
+    g.write("v", np.zeros(inst.n))
+    g.write("w", np.ones(inst.n))
+    g.step_index = 0
+    torch.cuda.synchronize()
+    g.kernel_timing(True)
+    t = time.perf_counter()
+    loss, grad, used = g.adjoint_scale(tstar, steps, K)
+    dt = time.perf_counter() - t
+    st_ms, st_n = g.kernel_time("stencil")
+    ad_ms, ad_n = g.kernel_time("adjoint")
+    g.kernel_timing(False)
+    g.close()
+    avg_ad = ad_ms / max(ad_n, 1)
+    return {"workload": f"adjoint_{n}: {inst.nt} tissue voxels, {steps} FP32 steps, "
+                        f"checkpoints every {K}",
+            "voxel_steps_per_s": inst.nt * steps / dt, "seconds": dt,
+            "loss": loss, "n_used": used,
+            "forward_recompute_avg_us": 1e3 * st_ms / max(st_n, 1), "forward_launches": st_n,
+            "adjoint_avg_us": 1e3 * avg_ad, "adjoint_launches": ad_n,
+            "adjoint_achieved_gbs": ALGO_BYTES["adjoint_step"] * inst.nt / (avg_ad * 1e-3) / 1e9}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -174,6 +252,14 @@ def main():
     torch.cuda.set_device(0)
     import ep_inputs as E
     from paper_2302_12519_amd import Grid
+
+    if a.only:
+        side = {"serving": lambda: bench_serving(a.serving or 64),
+                "plain": bench_plain_fp64,
+                "bidomain": lambda: bench_bidomain(a.bidomain or 192),
+                "adjoint": lambda: bench_adjoint(a.adjoint or 128)}[a.only]
+        print(json.dumps({a.only: side()}), flush=True)
+        return
 
     if a.copy_calibration:
         # plain copy of known size: 1 GiB read + 1 GiB written
@@ -240,20 +326,15 @@ def main():
                "setup_avg_us": 1e3 * set_ms / max(set_n, 1),
                "tail_avg_us": 1e3 * tail_ms / max(tail_n, 1), "tail_launches": tail_n},
     }
-    if not a.no_parity:
-        # one-step parity from the GPU's current state against the FP64 oracle
-        import oracle
-        o = oracle.Oracle(inst)
-        o.set_state(v=g.read("v"), w=g.read("w"), step=g.step_index)
-        g.step(1)
-        o.run(1)
-        v, ref = g.read("v"), o.field("v")
-        out["parity_one_step"] = float(np.abs(v - ref).max() / np.abs(ref).max())
     g.close()
     if a.serving:
         out["serving"] = bench_serving(a.serving)
     if not a.no_plain:
         out["plain_box_32_fp64"] = bench_plain_fp64()
+    if a.bidomain:
+        out["bidomain"] = bench_bidomain(a.bidomain)
+    if a.adjoint:
+        out["adjoint"] = bench_adjoint(a.adjoint)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, a.cpu_seconds)
     print(json.dumps(out), flush=True)

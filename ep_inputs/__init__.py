@@ -7,8 +7,8 @@ constants of each workload.  It holds none of the method's arithmetic (no ionic
 model, no conductivity tensor, no stencil, no solver); each side computes those
 itself from these inputs.
 
-Geometry follows the thesis's signed-distance encoding (Geometry chapter,
-"Primitives" and the set operations after them): an ellipsoid primitive
+Geometry follows the thesis's signed-distance encoding (Geometry section of
+the Discretization and Solver chapter, "Primitives" and the set operations after them): an ellipsoid primitive
 ``|p/r| - 1`` and the complement ``max(s1, -s2)`` carve a hollow, ventricle-like
 shell out of the voxel box; a voxel is tissue when the SDF at its centre is
 <= 0 (volume pass of the two-pass encoding).  The thesis's schematic heart is
@@ -28,9 +28,9 @@ from typing import List, Optional, Sequence
 
 import numpy as np
 
-# Mitchell-Schaeffer constants (Electrophysiology chapter, MS model).  The
-# thesis prints none; these are the values of the original 2003 model it
-# cites.  Times in ms, v dimensionless.
+# Mitchell-Schaeffer constants (Cardiac Multiphysics chapter,
+# Mitchell-Schaeffer Model subsection).  The thesis prints none; these are
+# the values of the original 2003 model it cites.  Times in ms, v dimensionless.
 MS_DEFAULT = dict(tau_in=0.3, tau_out=6.0, tau_open=120.0, tau_close=150.0,
                   v_gate=0.13, exc=1.0)
 
@@ -173,14 +173,16 @@ def smooth_scale(n, seed, sigma_vox=8.0, amp=0.5):
 # the five workloads
 # --------------------------------------------------------------------------
 def plain_box(n=32, steps=1000, prec="f64"):
-    """Plain monodomain: n^3 all-tissue box, h = 0.25 mm, isotropic 0.1
-    mm^2/ms, stimulus on the x = 0 layer for 1 ms, explicit Euler dt 0.01."""
-    shape = (n, n, n)
+    """Plain monodomain: n^3 all-tissue box (or an (nx, ny, nz) box), h = 0.25
+    mm, isotropic 0.1 mm^2/ms, stimulus on the x = 0 layer for 1 ms, explicit
+    Euler dt 0.01."""
+    shape = (n, n, n) if np.isscalar(n) else tuple(int(k) for k in n)
     mask = np.ones(shape, np.uint8)
     fib = np.zeros(shape + (3,))
     fib[..., 0] = 1.0
-    stims = [Stim(lo=(0, 0, 0), hi=(1, n, n), amp=1.0, t_on=0.0, t_off=1.0)]
-    return Instance(name=f"plain_box_{n}", n=shape, h=0.25, dt=0.01, steps=steps,
+    stims = [Stim(lo=(0, 0, 0), hi=(1,) + shape[1:], amp=1.0, t_on=0.0, t_off=1.0)]
+    tag = str(n) if np.isscalar(n) else "x".join(str(k) for k in shape)
+    return Instance(name=f"plain_box_{tag}", n=shape, h=0.25, dt=0.01, steps=steps,
                     mask=mask, fibre=fib, scale=None, sigma_l=0.1, sigma_t=0.1,
                     stims=stims, model="mono", diff="explicit", prec=prec)
 

@@ -3,14 +3,14 @@
  *
  * The library advances the operator-split, matrix-free finite-volume
  * monodomain / bidomain equations on a voxel grid (thesis "Computational
- * Tools for Cardiac Simulation", Algorithm chapter, section
+ * Tools for Cardiac Simulation", Algorithm Details chapter, section
  * "Electrophysiology"): a pointwise Mitchell-Schaeffer update by explicit
  * Euler (Reaction subsection; eqn:ms1, eqn:ms2), then diffusion through the
  * conductivity tensor field (eqn:sigma1) either explicitly or by implicit
- * Euler solved with Jacobi-preconditioned CG (Linear Solver chapter,
- * "Implicit Euler"), and for the bidomain model the elliptic extracellular
- * equation (second line of eqn:bidomain1) by FP32 PCG inside FP64 iterative
- * refinement.
+ * Euler solved with Jacobi-preconditioned CG (Discretization and Solver
+ * chapter, Linear Solver section, "Implicit Euler"), and for the bidomain
+ * model the elliptic extracellular equation (second line of
+ * eqn:bidomain1) by FP32 PCG inside FP64 iterative refinement.
  *
  * Conventions shared by every call:
  *  - Every call returns an ep_status; EP_OK is 0.  No C++ exception crosses
@@ -117,7 +117,7 @@ typedef struct {
 } ep_solve_info;
 
 /* Create a grid.  Validates the description, builds the brick map of the
- * tissue mask (voxel geometry as in the Geometry chapter: tissue voxels are
+ * tissue mask (voxel geometry as in the Geometry section: tissue voxels are
  * the volume pass of the SDF encoding), allocates device state (v = 0,
  * w = 1 on tissue, phi = 0, T_act = +inf) and copies stimuli.  On failure
  * *out is NULL.  Errors: EP_ERR_ARG (bad sizes/values, NULL desc or out,
@@ -211,7 +211,8 @@ EP_API ep_status ep_grid_stats(ep_grid g, int64_t* n_tissue, int64_t* n_bricks,
  * the last enable.  kernel_id 0: the fused explicit step, or one full
  * implicit-Euler / inner PCG iteration (the dominant kernel); 1: the CG
  * set-up launch; 2: the bidomain parabolic stencil; 3: the FP64 elliptic
- * residual; 4: CG launches that only detected convergence. */
+ * residual; 4: CG launches that only detected convergence; 5: the adjoint
+ * step of ep_adjoint_scale (its forward and recompute launches count as 0). */
 EP_API ep_status ep_kernel_timing(ep_grid g, int32_t enable);
 EP_API ep_status ep_kernel_time(ep_grid g, int32_t kernel_id, double* total_ms,
                                 int64_t* launches);

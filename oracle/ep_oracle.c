@@ -10,8 +10,8 @@
  * Everything is double precision, written for clarity, not speed: each
  * function follows the definition it cites, with no blocking or fusion.
  *
- * Model (thesis, Electrophysiology chapter; Algorithm chapter, section
- * "Electrophysiology"):
+ * Model (thesis, Cardiac Multiphysics chapter, Electrophysiology section;
+ * Algorithm Details chapter, Electrophysiology section):
  *   - Mitchell-Schaeffer ionic model, eqn:ms1 / eqn:ms2, integrated by one
  *     explicit Euler step per time step (Reaction subsection).  Readings: the
  *     gate relaxes as -w/tau_close above v_gate (the printed (1-w)/tau_close
@@ -24,10 +24,10 @@
  *     cell-centred 7-point Neumann Laplacian.  Face tensors are the mean of
  *     the two voxel tensors, edge tensors the mean of the four voxel tensors
  *     of the 2x2 block (the thesis interpolates the conductivity to the
- *     gradient points, Algorithm chapter, Diffusion subsection).
+ *     gradient points, Algorithm Details chapter, Diffusion subsection).
  *   - Monodomain (eqn:monodomain1, chi_m*C_m = 1, lambda/(1+lambda) folded
  *     into D): v_{n+1} = v* + dt A v* (explicit) or (I - dt A) v_{n+1} = v*
- *     (implicit Euler, Linear Solver chapter, "Implicit Euler"), solved here
+ *     (implicit Euler: Linear Solver section, "Implicit Euler"), solved here
  *     by Jacobi-preconditioned CG.
  *   - Bidomain (eqn:bidomain1, heart only, v_i = v + phi_e):
  *     -(A_i + A_e) phi = A_i v*, sum_tissue phi = 0;  v_{n+1} = v* + dt A_i(v* + phi).

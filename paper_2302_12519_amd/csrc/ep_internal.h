@@ -65,14 +65,6 @@ struct CGScalars {
   int it, maxit, done, fail;
 };
 
-enum RedOp {
-  RED_BE_INIT = 0,    // partials (rz, bb, rr) -> start a solve
-  RED_ALPHA = 1,      // partial pq -> alpha
-  RED_BETA = 2,       // partials (rr, rz) -> beta, convergence
-  RED_SUM = 3,        // generic: sum K partials into out[0..K)
-  RED_INNER_INIT = 4  // partials (rz, rr) -> start an inner solve (bb := rr)
-};
-
 struct LaunchCfg {
   int nb;       // active bricks
   int grid;     // blocks of a one-brick-per-block launch (multiple of kXcd, >= nb)

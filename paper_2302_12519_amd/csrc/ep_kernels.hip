@@ -11,10 +11,29 @@
 // a brick overlap instead of forming dependent round trips.  Nothing here is
 // a dense contraction, so there is no MFMA: every kernel is HBM-bound.
 //
-// Reductions are deterministic: each block writes its partial sums (FP64) to
-// a fixed slot; the last block to finish (device-scope counter) sums the
-// slots in block order and updates the solver scalars, so a CG iteration
-// needs no separate reduction launch.
+// Reductions are deterministic and need no atomics: each block writes its
+// FP64 partial sums to a fixed slot, and the next launch (every one of its
+// blocks, redundantly) sums the previous launch's slots in a fixed order
+// before using the totals.  The CG kernels are persistent (a fixed grid that
+// strides over the bricks), so that sum costs a few hundred loads per block,
+// and one CG iteration is one launch.
+//
+// What each kernel computes, with the passage it follows (thesis):
+//   k_tensor, k_coefs, k_unit_tensor: voxel conductivity tensors (eqn:sigma1)
+//     and the face / edge weights of the 19-point finite-volume operator
+//     (matrix-free assembly, Linear Solver section, "Matrix-Free Assembly";
+//     conductivity interpolated to the gradient points, Algorithm Details
+//     chapter, Diffusion subsection).
+//   k_explicit, k_ionic: Mitchell-Schaeffer reaction by explicit Euler
+//     (eqn:ms1, eqn:ms2; Reaction subsection) fused with explicit diffusion;
+//     activation time at the first threshold crossing.
+//   k_be_init, k_cgcg: implicit-Euler diffusion step (Linear Solver section,
+//     "Implicit Euler") solved by Jacobi-preconditioned CG.
+//   k_resid64, k_inner_init, k_phi_correct, k_phi_shift, k_parabolic: the
+//     bidomain step (eqn:bidomain1): elliptic solve for phi_e by FP32 PCG
+//     inside FP64 refinement, then the parabolic update.
+//   k_adj_init, k_adj_step, k_loss: discrete adjoint of the explicit step
+//     for the activation-time loss.
 #include <cmath>
 
 #include "ep_device.h"

@@ -41,7 +41,7 @@ struct TimerPair {
 // stencil, 3 the FP64 elliptic residual, 4 CG launches that only detected
 // convergence (or skipped after it)
 enum { KT_STENCIL = 0, KT_CGSETUP = 1, KT_PARABOLIC = 2, KT_RESID = 3, KT_CGTAIL = 4,
-       kTimers = 5 };
+       KT_ADJ = 5, kTimers = 6 };
 
 }  // namespace
 
@@ -652,10 +652,12 @@ ep_status adjoint_impl(ep_grid g, int32_t nsteps, int32_t K, const double* tstar
     }
     const T* jstim = nullptr;
     TRY(update_stimulus<T>(g, step0 + s, &jstim));
+    TimerPair* t0 = timer_begin(g, KT_STENCIL);
     launch_explicit<T>(g->L, g->d_nbr, c, static_cast<const T*>(g->d_v[cu]),
                        static_cast<const T*>(g->d_w[cu]), jstim, static_cast<T*>(g->d_v[nx]),
                        static_cast<T*>(g->d_w[nx]), tact, ion, dt, theta,
                        static_cast<double>(step0 + s) * g->dt, g->d_flags, d_cross, s);
+    timer_end(g, t0);
     g->cur = nx;
     g->step += 1;
     g->have_prev = true;
@@ -693,18 +695,22 @@ ep_status adjoint_impl(ep_grid g, int32_t nsteps, int32_t K, const double* tstar
       const T* jstim = nullptr;
       TRY(update_stimulus<T>(g, step0 + s, &jstim));
       const int i = s - s0;
+      TimerPair* t0 = timer_begin(g, KT_STENCIL);
       launch_explicit<T>(g->L, g->d_nbr, c, seg_v[i], seg_w[i], jstim, seg_v[i + 1],
                          seg_w[i + 1], tact, ion, dt, theta,
                          static_cast<double>(step0 + s) * g->dt, g->d_flags, nullptr, 0);
+      timer_end(g, t0);
     }
     for (int s = s1 - 1; s >= s0; --s) {
       const T* jstim = nullptr;
       TRY(update_stimulus<T>(g, step0 + s, &jstim));
       const int i = s - s0;
       const T* vprev = (i > 0) ? seg_v[i - 1] : (ci > 0 ? ck_vp[ci] : nullptr);
+      TimerPair* t0 = timer_begin(g, KT_ADJ);
       launch_adj_step<T>(g->L, g->d_nbr, c, d0, g->d_mask, lv[a], lw[a], lv[1 - a], lw[1 - a],
                          seg_v[i], seg_w[i], jstim, seg_v[i + 1], vprev, d_cross, tact, d_tstar,
                          d_grad, ion, dt, theta, inv_h2, s);
+      timer_end(g, t0);
       a = 1 - a;
     }
   }
@@ -713,6 +719,7 @@ ep_status adjoint_impl(ep_grid g, int32_t nsteps, int32_t K, const double* tstar
   HIPCHK(g, hipMemcpyAsync(hg.data(), d_grad, nv * sizeof(double), hipMemcpyDeviceToHost,
                            g->stream));
   HIPCHK(g, hipStreamSynchronize(g->stream));
+  timer_collect(g);
   for (int x = 0; x < g->n[0]; ++x)
     for (int y = 0; y < g->n[1]; ++y)
       for (int z = 0; z < g->n[2]; ++z) {

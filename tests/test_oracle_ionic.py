@@ -1,5 +1,5 @@
 """Pins for the oracle's Mitchell-Schaeffer update (eqn:ms1, eqn:ms2, explicit
-Euler as in the Reaction subsection of the Algorithm chapter)."""
+Euler as in the Reaction subsection of the Algorithm Details chapter)."""
 import math
 
 import numpy as np
