@@ -250,15 +250,20 @@ __global__ __launch_bounds__(kBV) void k_ionic(int nb, const T* __restrict__ v,
 // so one stencil launch per iteration does both the vector updates and the
 // operator application, and its three dot products share one reduction.
 
-// Reaction fused with the initial residual r0 = b - (I - dt A) b = dt A v*,
-// x0 = b.  When check_prev is set it also records activation for the
-// previous step (vprev -> v) before x0 overwrites vprev's buffer.
+// Reaction fused with the initial guess and residual of the implicit solve
+// (I - dt A) x = b, b = v*.  The guess adds the previous step's diffusion
+// increment to b, x0 = b + (v_n - b_{n-1}), when b_{n-1} is given (bprev),
+// else x0 = b; r0 = b - (I - dt A) x0.  b is stored in bout for the next
+// step.  When check_prev is set it also records activation for the previous
+// step (vprev -> v) before x0 overwrites vprev's buffer.
 // Partials: (b.b, r.r).
 template <typename T>
 __global__ __launch_bounds__(kBV, sizeof(T) == 4 ? 6 : 4) void k_be_init(int nb, const int* __restrict__ nbr,
                                                  CoefSet<T> c, const T* __restrict__ v,
                                                  const T* __restrict__ w,
-                                                 const T* __restrict__ jstim, T* x,
+                                                 const T* __restrict__ jstim,
+                                                 const T* __restrict__ bprev,
+                                                 T* __restrict__ bout, T* x,
                                                  T* __restrict__ wout, T* __restrict__ r,
                                                  IonicT<T> ion, T dt, T* __restrict__ tact,
                                                  T theta, double tprev, int check_prev,
@@ -282,29 +287,33 @@ __global__ __launch_bounds__(kBV, sizeof(T) == 4 ? 6 : 4) void k_be_init(int nb,
     const T v0 = v[q.g], w0 = w[q.g];
     const T j0 = jstim ? jstim[q.g] : T(0);
     const T vp = check_prev ? x[q.g] : T(0);
-    T hv = T(0), hw = T(0), hj = T(0);
+    const T b0 = bprev ? bprev[q.g] : T(0);
+    T hv = T(0), hw = T(0), hj = T(0), hb = T(0);
     if (q.has_halo) {
       hv = v[q.hg];
       hw = w[q.hg];
       hj = jstim ? jstim[q.hg] : T(0);
+      hb = bprev ? bprev[q.hg] : T(0);
     }
     T k18[18];
     gather18(c, nbs, brick, q.lx, q.ly, q.lz, k18);
     T vs, ws;
     ms_step(v0, w0, j0, ion, dt, vs, ws);
-    s[q.C] = vs;
+    const T x0 = bprev ? vs + (v0 - b0) : vs;
+    s[q.C] = x0;
     if (q.has_halo) {
       T a, b;
       ms_step(hv, hw, hj, ion, dt, a, b);
-      s[q.hC] = a;
+      s[q.hC] = bprev ? a + (hv - hb) : a;
     }
     __syncthreads();
-    const T rr = dt * apply19(s, q.C, k18);
+    const T rr = (vs - x0) + dt * apply19(s, q.C, k18);
     if (check_prev && vp < theta && theta <= v0) {
       if (isinf(tact[q.g])) tact[q.g] = static_cast<T>(tprev) + dt * (theta - vp) / (v0 - vp);
     }
     if (!isfinite(v0)) flags[0] = 1;
-    x[q.g] = vs;
+    x[q.g] = x0;
+    bout[q.g] = vs;
     wout[q.g] = ws;
     r[q.g] = rr;
     const double rd = static_cast<double>(rr);
@@ -930,10 +939,11 @@ void launch_ionic(const LaunchCfg& L, const T* v, const T* w, const T* jstim, T*
 
 template <typename T>
 void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v, const T* w,
-                    const T* jstim, T* x, T* wout, T* r, IonicT<T> ion, T dt, T* tact, T theta,
-                    double tprev, int check_prev, int* flags, CGScalars* cout, double* parts,
-                    double tol2, int maxit) {
-  k_be_init<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, x, wout, r, ion, dt,
+                    const T* jstim, const T* bprev, T* bout, T* x, T* wout, T* r, IonicT<T> ion,
+                    T dt, T* tact, T theta, double tprev, int check_prev, int* flags,
+                    CGScalars* cout, double* parts, double tol2, int maxit) {
+  k_be_init<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, bprev, bout, x, wout,
+                                              r, ion, dt,
                                               tact, theta, tprev, check_prev, flags, cout, parts,
                                               tol2, maxit);
 }
@@ -1047,8 +1057,8 @@ void launch_loss(const LaunchCfg& L, const uint8_t* mask, const int* cross, cons
   template void launch_ionic<T>(const LaunchCfg&, const T*, const T*, const T*, T*, T*,        \
                                 IonicT<T>, T);                                                 \
   template void launch_be_init<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*,          \
-                                  const T*, const T*, T*, T*, T*, IonicT<T>, T, T*, T, double, \
-                                  int, int*, CGScalars*, double*, double, int);                \
+                                  const T*, const T*, const T*, T*, T*, T*, T*, IonicT<T>, T,  \
+                                  T*, T, double, int, int*, CGScalars*, double*, double, int); \
   template void launch_cgcg<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T, const T*, T*,   \
                                const T*, T*, T*, const T*, T*, const T*, T*, int, int,         \
                                const CGScalars*, CGScalars*, const double*, double*);          \

@@ -87,6 +87,7 @@ struct ep_grid_s {
   void* d_cw[2] = {nullptr, nullptr};
   void* d_cp = nullptr;
   void* d_dinv = nullptr;
+  void* d_bprev[2] = {nullptr, nullptr};  // implicit solve: b of the last two steps
   void* d_vs = nullptr;       // bidomain v*
   double* d_phi = nullptr;
   double* d_r64 = nullptr;
@@ -121,6 +122,8 @@ struct ep_grid_s {
   int cur = 0;
   int64_t step = 0;
   bool have_prev = false;      // d_v[1-cur] holds the previous step's v
+  bool have_bprev = false;     // d_bprev[1-bsel] holds the previous step's b
+  int bsel = 0;
   bool has_cond = false;
   bool nonfinite = false;
   int last_iters = 4;
@@ -407,8 +410,11 @@ ep_status step_be(ep_grid g, const T* jstim, ep_step_info* acc) {
   T* wv[2] = {static_cast<T*>(g->d_cw[0]), static_cast<T*>(g->d_cw[1])};
   const T* dinv = static_cast<const T*>(g->d_dinv);
   // x (= d_v[n]) still holds the previous step's v: check its activation here
+  // initial guess from the previous step's diffusion increment (v_n - b_{n-1})
+  const T* bprev = g->have_bprev ? static_cast<const T*>(g->d_bprev[1 - g->bsel]) : nullptr;
   launch_be_init<T>(g->L, g->d_nbr, coefs<T>(g), static_cast<const T*>(g->d_v[c]),
-                    static_cast<const T*>(g->d_w[c]), jstim, x, static_cast<T*>(g->d_w[n]),
+                    static_cast<const T*>(g->d_w[c]), jstim, bprev,
+                    static_cast<T*>(g->d_bprev[g->bsel]), x, static_cast<T*>(g->d_w[n]),
                     r[0], ionic_t<T>(g), static_cast<T>(g->dt), static_cast<T*>(g->d_tact),
                     static_cast<T>(g->theta), static_cast<double>(g->step - 1) * g->dt,
                     g->have_prev ? 1 : 0, g->d_flags, g->d_cg, g->d_cgp[0],
@@ -514,6 +520,8 @@ ep_status run_steps(ep_grid g, int32_t nsteps, ep_step_info* info) {
       TRY(step_bido<T>(g, jstim, &acc));
     } else if (g->diff == EP_DIFF_BE_PCG) {
       TRY(step_be<T>(g, jstim, &acc));
+      g->bsel = 1 - g->bsel;
+      g->have_bprev = true;
     } else {
       TRY(step_explicit<T>(g, jstim));
     }
@@ -913,6 +921,7 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
     }
     TRY(dalloc(g, &g->d_cp, vb));
     TRY(dalloc(g, &g->d_dinv, vb));
+    for (int k = 0; k < 2; ++k) TRY(dalloc(g, &g->d_bprev[k], vb));
   }
   if (g->model == EP_MONO && g->diff == EP_DIFF_EXPLICIT)
     for (int k = 0; k < 6; ++k) TRY(dalloc(g, &g->d_d0[k], vb));
@@ -1138,6 +1147,7 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
   (void)hipStreamSynchronize(g->stream);
   cleanup();
   if (rc == EP_OK) g->has_cond = true;
+  g->have_bprev = false;
   return rc;
 }
 
@@ -1254,6 +1264,7 @@ EP_API ep_status ep_write_state(ep_grid g, ep_field f, const double* host_in, si
                                     : write_field<float>(g, f, host_in);
     if (s == EP_OK) {
       if (f == EP_V) g->have_prev = false;
+      g->have_bprev = false;
       g->nonfinite = false;
       HIPCHK(g, hipMemsetAsync(g->d_flags, 0, 4 * sizeof(int), g->stream));
       HIPCHK(g, hipStreamSynchronize(g->stream));
@@ -1275,6 +1286,7 @@ EP_API ep_status ep_set_step(ep_grid g, int64_t step) {
   g->step = step;
   g->stim_built = false;
   g->have_prev = false;
+  g->have_bprev = false;
   return EP_OK;
 }
 
