@@ -293,6 +293,7 @@ def main():
     it_ms, it_n = g.kernel_time("stencil")
     set_ms, set_n = g.kernel_time("cg_setup")
     tail_ms, tail_n = g.kernel_time("cg_tail")
+    init_ms, init_n = g.kernel_time("be_init")
     g.kernel_timing(False)
 
     value = inst.nt * a.steps / elapsed
@@ -324,7 +325,9 @@ def main():
         "cg": {"iters_total": info["cg_iters"], "iters_per_step": info["cg_iters"] / a.steps,
                "iters_max": info["cg_max"],
                "setup_avg_us": 1e3 * set_ms / max(set_n, 1),
-               "tail_avg_us": 1e3 * tail_ms / max(tail_n, 1), "tail_launches": tail_n},
+               "tail_avg_us": 1e3 * tail_ms / max(tail_n, 1), "tail_launches": tail_n,
+               "init_avg_us": 1e3 * init_ms / max(init_n, 1),
+               "kernel_ms_per_step": (it_ms + set_ms + tail_ms + init_ms) / a.steps},
     }
     g.close()
     if a.serving:

@@ -14,7 +14,9 @@
  *
  * Conventions shared by every call:
  *  - Every call returns an ep_status; EP_OK is 0.  No C++ exception crosses
- *    the ABI.  ep_last_error(g) gives a message for the last failure on g.
+ *    the ABI.  ep_last_error(g) gives a message for the last failure on g;
+ *    ep_last_error(NULL) gives the calling thread's last failed
+ *    ep_create_grid message.
  *  - Box layout: flat index (x*ny + y)*nz + z, z fastest, n = {nx, ny, nz}.
  *  - Units: lengths mm, times ms, diffusivities mm^2/ms, v dimensionless.
  *    chi_m*C_m = 1; the monodomain factor lambda/(1+lambda) is folded into
@@ -212,7 +214,8 @@ EP_API ep_status ep_grid_stats(ep_grid g, int64_t* n_tissue, int64_t* n_bricks,
  * implicit-Euler / inner PCG iteration (the dominant kernel); 1: the CG
  * set-up launch; 2: the bidomain parabolic stencil; 3: the FP64 elliptic
  * residual; 4: CG launches that only detected convergence; 5: the adjoint
- * step of ep_adjoint_scale (its forward and recompute launches count as 0). */
+ * step of ep_adjoint_scale (its forward and recompute launches count as 0);
+ * 6: the reaction + initial-residual launch of an implicit-Euler step. */
 EP_API ep_status ep_kernel_timing(ep_grid g, int32_t enable);
 EP_API ep_status ep_kernel_time(ep_grid g, int32_t kernel_id, double* total_ms,
                                 int64_t* launches);

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -188,8 +189,10 @@ struct ep_batch_request {
   int n[3] = {0, 0, 0};
   double h = 0, dt = 0, theta = 0.5;
   ep_ionic ionic{};
-  std::vector<uint8_t> mask;
-  std::vector<double> fibre, scale;
+  std::vector<double> fib_b;     // 3 per voxel, brick layout, zero off tissue
+  std::vector<double> scale_b;   // brick layout (empty: scale 1)
+  std::vector<int64_t> stim_idx; // stimulated voxels (brick layout) and their
+  std::vector<double> stim_amp;  // summed amplitudes, same rule as the per-grid path
   double sig_l = 0, sig_t = 0;
   std::vector<ep_stim> stims;
   double t_on = 0, t_off = 0;
@@ -221,6 +224,12 @@ struct ep_batch_s {
   double* d_tens = nullptr;
   uint8_t* d_mask = nullptr;
   int64_t scratch_vox = 0;
+  int64_t* d_stim_idx = nullptr;  // stimulus scatter scratch (grown on demand)
+  double* d_stim_amp = nullptr;
+  double* d_qstep = nullptr;
+  size_t stim_cap = 0;
+  WorkItem* h_work = nullptr;     // pinned staging of the work list (work_cap entries)
+  int* h_count = nullptr;         // pinned staging of the work count
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::deque<ep_batch_request*> queue;
@@ -266,13 +275,37 @@ ep_status grow_scratch(ep_batch b, int64_t nvox) {
     return bfail(b, EP_ERR_OOM, "coefficient scratch allocation failed");
   }
   b->scratch_vox = nvox;
+  if (!b->d_qstep && hipMalloc(&b->d_qstep, sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return bfail(b, EP_ERR_OOM, "coefficient scratch allocation failed");
+  }
+  return EP_OK;
+}
+
+ep_status grow_stim(ep_batch b, size_t n) {
+  if (n <= b->stim_cap) return EP_OK;
+  BHIP(b, hipStreamSynchronize(b->stream));
+  (void)hipFree(b->d_stim_idx);
+  (void)hipFree(b->d_stim_amp);
+  b->d_stim_idx = nullptr;
+  b->d_stim_amp = nullptr;
+  b->stim_cap = 0;
+  if (hipMalloc(&b->d_stim_idx, n * sizeof(int64_t)) != hipSuccess ||
+      hipMalloc(&b->d_stim_amp, n * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return bfail(b, EP_ERR_OOM, "stimulus scratch allocation failed");
+  }
+  b->stim_cap = n;
   return EP_OK;
 }
 
 // Build a request's device region: weights, initial state, stimulus field.
+// Everything is enqueued on the batch stream without waiting: the host
+// sources are owned by the request (alive until its release) or pinned.
 ep_status admit(ep_batch b, ep_batch_request* r, int slot) {
   const BrickMap& m = r->map;
   const size_t nv = static_cast<size_t>(m.nvox);
+  const size_t nreal = static_cast<size_t>(m.nb) * kBV;
   auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
   char* base = b->arena_base + r->off;
   int* d_nbr = reinterpret_cast<int*>(base);
@@ -284,70 +317,44 @@ ep_status admit(ep_batch b, ep_batch_request* r, int slot) {
   }
   // arr: 0-5 weights, 6-7 v, 8-9 w, 10 tact, 11 jamp
   if (ep_status s = grow_scratch(b, m.nvox); s != EP_OK) return s;
+  if (ep_status s = grow_stim(b, r->stim_idx.size()); s != EP_OK) return s;
   BHIP(b, hipMemsetAsync(base, 0, r->bytes, b->stream));
-  // fibres / scale / mask in brick layout
-  std::vector<double> hf(3 * nv, 0.0), hs;
-  if (!r->scale.empty()) hs.assign(nv, 0.0);
-  std::vector<float> w0(nv, 0.0f), tact(nv, 0.0f), jamp(nv, 0.0f);
-  const int64_t nreal = static_cast<int64_t>(m.nb) * kBV;
-  for (int64_t i = 0; i < nreal; ++i) {
-    w0[i] = 1.0f;
-    tact[i] = std::numeric_limits<float>::infinity();
-  }
-  for (int x = 0; x < r->n[0]; ++x)
-    for (int y = 0; y < r->n[1]; ++y)
-      for (int z = 0; z < r->n[2]; ++z) {
-        const int64_t gi = m.brick_index(x, y, z);
-        if (gi < 0 || !m.mask[gi]) continue;
-        const int64_t bi = m.box_index(x, y, z);
-        hf[3 * gi] = r->fibre[3 * bi];
-        hf[3 * gi + 1] = r->fibre[3 * bi + 1];
-        hf[3 * gi + 2] = r->fibre[3 * bi + 2];
-        if (!hs.empty()) hs[gi] = r->scale[bi];
-      }
-  // stimulus amplitudes (same membership rule as the per-grid path)
-  std::vector<double> jv(nv, 0.0);
-  for (const ep_stim& s : r->stims)
-    for (int x = std::max(0, s.lo[0]); x < std::min(r->n[0], s.hi[0]); ++x)
-      for (int y = std::max(0, s.lo[1]); y < std::min(r->n[1], s.hi[1]); ++y)
-        for (int z = std::max(0, s.lo[2]); z < std::min(r->n[2], s.hi[2]); ++z) {
-          const int64_t gi = m.brick_index(x, y, z);
-          if (gi < 0 || !m.mask[gi]) continue;
-          if (s.radius > 0.0) {
-            const double dx = (x + 0.5) * r->h - s.center[0];
-            const double dy = (y + 0.5) * r->h - s.center[1];
-            const double dz = (z + 0.5) * r->h - s.center[2];
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (!(r2 <= s.radius * s.radius)) continue;
-          }
-          jv[gi] += s.amp;
-        }
-  for (size_t i = 0; i < nv; ++i) jamp[i] = static_cast<float>(jv[i]);
+  // rest state on the real bricks (the ghost brick stays zero): w = 1,
+  // T_act = +inf
+  BHIP(b, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(arr[8]), 0x3f800000u, nreal,
+                            b->stream));
+  BHIP(b, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(arr[10]), 0x7f800000u, nreal,
+                            b->stream));
   BHIP(b, hipMemcpyAsync(d_nbr, m.nbr.data(), m.nbr.size() * sizeof(int), hipMemcpyHostToDevice,
                          b->stream));
   BHIP(b, hipMemcpyAsync(b->d_mask, m.mask.data(), nv, hipMemcpyHostToDevice, b->stream));
-  BHIP(b, hipMemcpyAsync(b->d_fib, hf.data(), 3 * nv * sizeof(double), hipMemcpyHostToDevice,
-                         b->stream));
-  if (!hs.empty())
-    BHIP(b, hipMemcpyAsync(b->d_scale, hs.data(), nv * sizeof(double), hipMemcpyHostToDevice,
-                           b->stream));
+  BHIP(b, hipMemcpyAsync(b->d_fib, r->fib_b.data(), 3 * nv * sizeof(double),
+                         hipMemcpyHostToDevice, b->stream));
+  if (!r->scale_b.empty())
+    BHIP(b, hipMemcpyAsync(b->d_scale, r->scale_b.data(), nv * sizeof(double),
+                           hipMemcpyHostToDevice, b->stream));
   BHIP(b, hipMemsetAsync(b->d_tens, 0, 6 * nv * sizeof(double), b->stream));
-  BHIP(b, hipMemcpyAsync(arr[8], w0.data(), nv * sizeof(float), hipMemcpyHostToDevice, b->stream));
-  BHIP(b, hipMemcpyAsync(arr[10], tact.data(), nv * sizeof(float), hipMemcpyHostToDevice,
-                         b->stream));
-  BHIP(b, hipMemcpyAsync(arr[11], jamp.data(), nv * sizeof(float), hipMemcpyHostToDevice,
-                         b->stream));
+  if (!r->stim_idx.empty()) {
+    BHIP(b, hipMemcpyAsync(b->d_stim_idx, r->stim_idx.data(), r->stim_idx.size() * sizeof(int64_t),
+                           hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->d_stim_amp, r->stim_amp.data(), r->stim_amp.size() * sizeof(double),
+                           hipMemcpyHostToDevice, b->stream));
+    launch_stim_scatter<float>(b->stream, b->d_stim_idx, b->d_stim_amp,
+                               static_cast<int>(r->stim_idx.size()), arr[11], b->d_qstep);
+  }
   LaunchCfg L;
   L.nb = m.nb;
   L.grid = grid_for(m.nb);
   L.pgrid = L.grid;
   L.stream = b->stream;
+  L.rowsn = nullptr;
   float* c32[6];
   for (int k = 0; k < 6; ++k) c32[k] = arr[k];
-  launch_tensor_coefs(L, d_nbr, b->d_mask, b->d_fib, hs.empty() ? nullptr : b->d_scale,
+  launch_tensor_coefs(L, d_nbr, b->d_mask, b->d_fib, r->scale_b.empty() ? nullptr : b->d_scale,
                       r->sig_l, r->sig_t, r->h, b->d_tens, nullptr, c32);
   BHIP(b, hipGetLastError());
-  SlotDev sd{};
+  SlotDev& sd = b->h_slots[slot];
+  sd = SlotDev{};
   sd.nbr = d_nbr;
   for (int k = 0; k < 6; ++k) sd.c[k] = arr[k];
   sd.v[0] = arr[6];
@@ -370,11 +377,10 @@ ep_status admit(ep_batch b, ep_batch_request* r, int slot) {
   sd.step = 0;
   sd.n_steps = r->n_steps;
   sd.active = 1;
+  // from pinned memory; the next read-back of the slot table follows it on
+  // the same stream
   BHIP(b, hipMemcpyAsync(b->d_slots + slot, &sd, sizeof(SlotDev), hipMemcpyHostToDevice,
                          b->stream));
-  // host buffers above must outlive the copies
-  BHIP(b, hipStreamSynchronize(b->stream));
-  b->h_slots[slot] = sd;
   r->slot = slot;
   b->slot_owner[slot] = r->id;
   b->st.admitted += 1;
@@ -383,25 +389,34 @@ ep_status admit(ep_batch b, ep_batch_request* r, int slot) {
   return EP_OK;
 }
 
+// Work list of every running request's bricks.  Staged through pinned host
+// memory and enqueued without waiting: the previous graph launch, which
+// still reads the old list, runs first on the same stream, and the host
+// never rewrites the staging area before the end of an advance, which
+// waits for the stream.
 ep_status rebuild_work(ep_batch b) {
-  std::vector<WorkItem> items;
+  int64_t total = 0;
   for (int s = 0; s < b->max_slots; ++s) {
     const int64_t id = b->slot_owner[s];
     if (id < 0) continue;
     const ep_batch_request* r = b->all[id];
-    if (r->finished) continue;
-    for (int k = 0; k < r->map.nb; ++k) items.push_back({s, k});
+    if (!r->finished) total += r->map.nb;
   }
-  if (static_cast<int>(items.size()) > b->work_cap) {
+  if (total > b->work_cap) {
     BHIP(b, hipStreamSynchronize(b->stream));
     (void)hipFree(b->d_work);
+    (void)hipHostFree(b->h_work);
     b->d_work = nullptr;
+    b->h_work = nullptr;
     b->work_cap = 0;
-    if (hipMalloc(&b->d_work, items.size() * sizeof(WorkItem)) != hipSuccess) {
+    void* hp = nullptr;
+    if (hipMalloc(&b->d_work, total * sizeof(WorkItem)) != hipSuccess ||
+        hipHostMalloc(&hp, total * sizeof(WorkItem), hipHostMallocDefault) != hipSuccess) {
       (void)hipGetLastError();
       return bfail(b, EP_ERR_OOM, "work list allocation failed");
     }
-    b->work_cap = static_cast<int>(items.size());
+    b->h_work = static_cast<WorkItem*>(hp);
+    b->work_cap = static_cast<int>(total);
     // the captured graph holds the old pointer: capture again
     if (b->exec) {
       (void)hipGraphExecDestroy(b->exec);
@@ -412,11 +427,18 @@ ep_status rebuild_work(ep_batch b) {
       b->graph = nullptr;
     }
   }
-  const int n = static_cast<int>(items.size());
-  if (n) BHIP(b, hipMemcpyAsync(b->d_work, items.data(), n * sizeof(WorkItem),
+  int n = 0;
+  for (int s = 0; s < b->max_slots; ++s) {
+    const int64_t id = b->slot_owner[s];
+    if (id < 0) continue;
+    const ep_batch_request* r = b->all[id];
+    if (r->finished) continue;
+    for (int k = 0; k < r->map.nb; ++k) b->h_work[n++] = WorkItem{s, k};
+  }
+  *b->h_count = n;
+  if (n) BHIP(b, hipMemcpyAsync(b->d_work, b->h_work, n * sizeof(WorkItem),
                                 hipMemcpyHostToDevice, b->stream));
-  BHIP(b, hipMemcpyAsync(b->d_count, &n, sizeof(int), hipMemcpyHostToDevice, b->stream));
-  BHIP(b, hipStreamSynchronize(b->stream));
+  BHIP(b, hipMemcpyAsync(b->d_count, b->h_count, sizeof(int), hipMemcpyHostToDevice, b->stream));
   b->work_dirty = false;
   return EP_OK;
 }
@@ -487,11 +509,18 @@ EP_API ep_status ep_batch_create(const ep_batch_desc* d, ep_batch* out) {
     // every resident brick holds at least 12 arrays of 512 floats of arena,
     // so this many work items always suffice
     b->work_cap = static_cast<int>(b->budget / (12 * kBV * sizeof(float))) + b->max_slots;
-    if (hipMalloc(&b->d_work, static_cast<size_t>(b->work_cap) * sizeof(WorkItem)) != hipSuccess) {
+    void* hw = nullptr;
+    void* hc = nullptr;
+    if (hipMalloc(&b->d_work, static_cast<size_t>(b->work_cap) * sizeof(WorkItem)) != hipSuccess ||
+        hipHostMalloc(&hw, static_cast<size_t>(b->work_cap) * sizeof(WorkItem),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&hc, sizeof(int), hipHostMallocDefault) != hipSuccess) {
       (void)hipGetLastError();
       s = EP_ERR_OOM;
       break;
     }
+    b->h_work = static_cast<WorkItem*>(hw);
+    b->h_count = static_cast<int*>(hc);
   } while (false);
   if (s != EP_OK) {
     ep_batch_destroy(b);
@@ -538,28 +567,67 @@ EP_API ep_status ep_batch_submit(ep_batch b, const ep_grid_desc* d, const double
       r->t_on = r->stims[0].t_on;
       r->t_off = r->stims[0].t_off;
     }
-    const int64_t N = static_cast<int64_t>(r->n[0]) * r->n[1] * r->n[2];
-    r->mask.assign(N, 1);
-    if (d->mask)
-      for (int64_t i = 0; i < N; ++i) r->mask[i] = d->mask[i] ? 1 : 0;
     std::string merr;
-    if (!build_brick_map(r->n, r->mask.data(), r->map, merr)) return bfail(b, EP_ERR_ARG, merr);
-    r->fibre.assign(fibre, fibre + 3 * N);
+    if (!build_brick_map(r->n, d->mask, r->map, merr)) return bfail(b, EP_ERR_ARG, merr);
+    const BrickMap& m = r->map;
+    const size_t nv = static_cast<size_t>(m.nvox);
+    // fibres (and scale) to brick layout, validated on tissue
+    r->fib_b.assign(3 * nv, 0.0);
+    if (scale) r->scale_b.assign(nv, 0.0);
+    std::atomic<int> bad{0};   // 1: non-unit fibre, 2: bad scale
+    std::vector<double> smax_x(r->n[0], 0.0);
+    parallel_for(r->n[0], [&](int64_t xx) {
+      const int x = static_cast<int>(xx);
+      double sm = 0.0;
+      for (int y = 0; y < r->n[1]; ++y)
+        for (int z = 0; z < r->n[2]; ++z) {
+          const int64_t gi = m.brick_index(x, y, z);
+          if (gi < 0 || !m.mask[gi]) continue;
+          const int64_t bi = m.box_index(x, y, z);
+          const double f0 = fibre[3 * bi], f1 = fibre[3 * bi + 1], f2 = fibre[3 * bi + 2];
+          if (!(std::fabs(std::sqrt(f0 * f0 + f1 * f1 + f2 * f2) - 1.0) <= 1e-6)) bad.store(1);
+          r->fib_b[3 * gi] = f0;
+          r->fib_b[3 * gi + 1] = f1;
+          r->fib_b[3 * gi + 2] = f2;
+          if (scale) {
+            if (!(scale[bi] > 0) || !std::isfinite(scale[bi])) bad.store(2);
+            r->scale_b[gi] = scale[bi];
+            sm = std::max(sm, scale[bi]);
+          }
+        }
+      smax_x[x] = sm;
+    });
+    if (bad.load() == 1) return bfail(b, EP_ERR_ARG, "fibre is not a unit vector on a tissue voxel");
+    if (bad.load() == 2) return bfail(b, EP_ERR_ARG, "scale must be finite and > 0 on tissue");
     double smax = 1.0;
-    if (scale) {
-      r->scale.assign(scale, scale + N);
-      smax = 0.0;
-    }
-    for (int64_t i = 0; i < N; ++i) {
-      if (!r->mask[i]) continue;
-      const double f0 = fibre[3 * i], f1 = fibre[3 * i + 1], f2 = fibre[3 * i + 2];
-      if (!(std::fabs(std::sqrt(f0 * f0 + f1 * f1 + f2 * f2) - 1.0) <= 1e-6))
-        return bfail(b, EP_ERR_ARG, "fibre is not a unit vector on a tissue voxel");
-      if (scale) {
-        if (!(scale[i] > 0) || !std::isfinite(scale[i]))
-          return bfail(b, EP_ERR_ARG, "scale must be finite and > 0 on tissue");
-        smax = std::max(smax, scale[i]);
-      }
+    if (scale) smax = *std::max_element(smax_x.begin(), smax_x.end());
+    // stimulated voxels with their summed amplitudes (stimuli in order, as
+    // the per-grid path sums them)
+    std::vector<std::pair<int64_t, double>> sv;
+    for (const ep_stim& st : r->stims)
+      for (int x = std::max(0, st.lo[0]); x < std::min(r->n[0], st.hi[0]); ++x)
+        for (int y = std::max(0, st.lo[1]); y < std::min(r->n[1], st.hi[1]); ++y)
+          for (int z = std::max(0, st.lo[2]); z < std::min(r->n[2], st.hi[2]); ++z) {
+            const int64_t gi = m.brick_index(x, y, z);
+            if (gi < 0 || !m.mask[gi]) continue;
+            if (st.radius > 0.0) {
+              const double dx = (x + 0.5) * r->h - st.center[0];
+              const double dy = (y + 0.5) * r->h - st.center[1];
+              const double dz = (z + 0.5) * r->h - st.center[2];
+              const double r2 = dx * dx + dy * dy + dz * dz;
+              if (!(r2 <= st.radius * st.radius)) continue;
+            }
+            sv.emplace_back(gi, st.amp);
+          }
+    std::stable_sort(sv.begin(), sv.end(),
+                     [](const auto& a, const auto& c) { return a.first < c.first; });
+    for (size_t k = 0; k < sv.size();) {
+      double acc = 0.0;
+      size_t e = k;
+      for (; e < sv.size() && sv[e].first == sv[k].first; ++e) acc += sv[e].second;
+      r->stim_idx.push_back(sv[k].first);
+      r->stim_amp.push_back(acc);
+      k = e;
     }
     // explicit stability, conservatively: |A_pp| + sum_q |A_pq| <=
     // 4 smax (sig_l + 2 sig_t + |sig_l - sig_t|) / h^2 for unit fibres
@@ -674,13 +742,15 @@ EP_API ep_status ep_batch_read(ep_batch b, int64_t id, ep_field f, double* host_
                            b->stream));
     BHIP(b, hipStreamSynchronize(b->stream));
     const double off = f == EP_TACT ? std::numeric_limits<double>::infinity() : 0.0;
-    for (int x = 0; x < r->n[0]; ++x)
+    parallel_for(r->n[0], [&](int64_t xx) {
+      const int x = static_cast<int>(xx);
       for (int y = 0; y < r->n[1]; ++y)
         for (int z = 0; z < r->n[2]; ++z) {
           const int64_t gi = m.brick_index(x, y, z);
           host_out[m.box_index(x, y, z)] =
               (gi >= 0 && m.mask[gi]) ? static_cast<double>(buf[gi]) : off;
         }
+    });
     return EP_OK;
   } catch (const std::bad_alloc&) {
     return bfail(b, EP_ERR_OOM, "host allocation failed");
@@ -737,7 +807,12 @@ EP_API ep_status ep_batch_destroy(ep_batch b) {
   (void)hipFree(b->d_scale);
   (void)hipFree(b->d_tens);
   (void)hipFree(b->d_mask);
+  (void)hipFree(b->d_stim_idx);
+  (void)hipFree(b->d_stim_amp);
+  (void)hipFree(b->d_qstep);
   if (b->h_slots) (void)hipHostFree(b->h_slots);
+  if (b->h_work) (void)hipHostFree(b->h_work);
+  if (b->h_count) (void)hipHostFree(b->h_count);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return EP_OK;

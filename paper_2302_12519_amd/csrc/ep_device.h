@@ -64,21 +64,52 @@ __device__ __forceinline__ int nb_global(const int* nbs, int brick, int lx, int 
   return bk * kBV + (((tx & 7) * 8 + (ty & 7)) * 8 + (tz & 7));
 }
 
+// Row liveness.  A brick row is the 8 voxels (lx, ly, 0..7), 32 contiguous
+// bytes in FP32; bit lx*8 + ly of a brick's row mask is set when the row
+// holds tissue.  rowm[27] holds the masks of a brick's 3x3x3 neighbourhood
+// (same slots as nbs).  A voxel of an empty row carries nothing the
+// operator uses (its weights are zero, and the kernels that skip rows never
+// store there), so its loads are redirected to the same offset in the ghost
+// brick, which is all zeros and stays in L2: the loads remain unconditional
+// (no branch, no wait) and the row's HBM traffic disappears.
+__device__ __forceinline__ bool vox_live(const uint64_t* rowm, int tx, int ty, int tz) {
+  const int ox = tx < 0 ? 0 : (tx > 7 ? 2 : 1);
+  const int oy = ty < 0 ? 0 : (ty > 7 ? 2 : 1);
+  const int oz = tz < 0 ? 0 : (tz > 7 ? 2 : 1);
+  return (rowm[ox * 9 + oy * 3 + oz] >> ((((tx & 7) << 3) | (ty & 7)))) & 1;
+}
+
 // The 18 off-centre weights of voxel p of the 19-point operator, in the order
 //  0 ax(p)   1 ax(p-x)  2 ay(p)   3 ay(p-y)  4 az(p)   5 az(p-z)
 //  6 bxy(p)  7 bxy(p-x-y)  8 bxy(p-y)  9 bxy(p-x)
 // 10 bxz(p) 11 bxz(p-x-z) 12 bxz(p-z) 13 bxz(p-x)
 // 14 byz(p) 15 byz(p-y-z) 16 byz(p-z) 17 byz(p-y)
+// With rowm, weights stored in empty rows are read as zero without a load
+// (and a voxel in an empty row gets all zeros).
+// With rowm, a weight stored in an empty row is loaded from the ghost brick
+// (nb is the ghost brick id), so it reads zero.
 template <typename T>
 __device__ __forceinline__ void gather18(const CoefSet<T>& c, const int* nbs, int brick, int lx,
-                                         int ly, int lz, T k[18]) {
-  const int g = brick * kBV + (lx * 8 + ly) * 8 + lz;
-  const int gx = nb_global(nbs, brick, lx, ly, lz, -1, 0, 0);
-  const int gy = nb_global(nbs, brick, lx, ly, lz, 0, -1, 0);
-  const int gz = nb_global(nbs, brick, lx, ly, lz, 0, 0, -1);
-  const int gxy = nb_global(nbs, brick, lx, ly, lz, -1, -1, 0);
-  const int gxz = nb_global(nbs, brick, lx, ly, lz, -1, 0, -1);
-  const int gyz = nb_global(nbs, brick, lx, ly, lz, 0, -1, -1);
+                                         int ly, int lz, T k[18],
+                                         const uint64_t* rowm = nullptr, int nb = 0) {
+  int g = brick * kBV + (lx * 8 + ly) * 8 + lz;
+  int gx = nb_global(nbs, brick, lx, ly, lz, -1, 0, 0);
+  int gy = nb_global(nbs, brick, lx, ly, lz, 0, -1, 0);
+  int gz = nb_global(nbs, brick, lx, ly, lz, 0, 0, -1);
+  int gxy = nb_global(nbs, brick, lx, ly, lz, -1, -1, 0);
+  int gxz = nb_global(nbs, brick, lx, ly, lz, -1, 0, -1);
+  int gyz = nb_global(nbs, brick, lx, ly, lz, 0, -1, -1);
+  if (rowm) {
+    const int gh = nb * kBV + (lx * 8 + ly) * 8 + lz;
+    const bool l0 = vox_live(rowm, lx, ly, lz);
+    g = l0 ? g : gh;
+    gx = (l0 && vox_live(rowm, lx - 1, ly, lz)) ? gx : gh;
+    gy = (l0 && vox_live(rowm, lx, ly - 1, lz)) ? gy : gh;
+    gz = (l0 && vox_live(rowm, lx, ly, lz - 1)) ? gz : gh;
+    gxy = (l0 && vox_live(rowm, lx - 1, ly - 1, lz)) ? gxy : gh;
+    gxz = (l0 && vox_live(rowm, lx - 1, ly, lz - 1)) ? gxz : gh;
+    gyz = (l0 && vox_live(rowm, lx, ly - 1, lz - 1)) ? gyz : gh;
+  }
   k[0] = c.c[CX][g];
   k[1] = c.c[CX][gx];
   k[2] = c.c[CY][g];
@@ -162,13 +193,20 @@ __device__ __forceinline__ void idle_partials(double* partials) {
 
 // Common prologue of the stencil kernels: the thread's own voxel, its halo
 // cell (threads < 480) and their tile cells.
+// With rowm (and the ghost brick id nb), live tells whether the own voxel
+// lies in a row holding tissue; gl / hgl are the indices to load the own
+// voxel / the halo cell from: the real ones for live rows, the same offset
+// in the ghost brick otherwise.  Without rowm, gl = g, hgl = hg, live = true.
 struct Cell {
   int lx, ly, lz, g, C;     // own voxel
   bool has_halo;
   int hg, hC;               // halo cell: global index and tile cell
+  bool live;
+  int gl, hgl;
 };
 
-__device__ __forceinline__ Cell cell_setup(const int* nbs, int brick) {
+__device__ __forceinline__ Cell cell_setup(const int* nbs, int brick,
+                                           const uint64_t* rowm = nullptr, int nb = 0) {
   Cell c;
   const int t = threadIdx.x;
   c.lx = t >> 6;
@@ -179,11 +217,15 @@ __device__ __forceinline__ Cell cell_setup(const int* nbs, int brick) {
   c.has_halo = t < kHalo;
   c.hg = 0;
   c.hC = 0;
+  c.live = rowm ? vox_live(rowm, c.lx, c.ly, c.lz) : true;
+  c.gl = c.live ? c.g : nb * kBV + t;
+  c.hgl = 0;
   if (c.has_halo) {
     int hx, hy, hz;
     halo_cell(t, hx, hy, hz);
     c.hg = tile_global(nbs, hx, hy, hz);
     c.hC = tidx(hx, hy, hz);
+    c.hgl = (!rowm || vox_live(rowm, hx - 1, hy - 1, hz - 1)) ? c.hg : nb * kBV + t;
   }
   return c;
 }

@@ -70,6 +70,7 @@ struct LaunchCfg {
   int grid;     // blocks of a one-brick-per-block launch (multiple of kXcd, >= nb)
   int pgrid;    // blocks of a persistent launch (multiple of kXcd, <= grid)
   hipStream_t stream;
+  const uint64_t* rowsn;   // (nb+1)*27 row masks of each brick's neighbourhood
 };
 
 inline int grid_for(int nb) { return ((nb + kXcd - 1) / kXcd) * kXcd; }
@@ -151,6 +152,8 @@ void launch_inner_init(const LaunchCfg& L, const double* r64, const uint8_t* mas
 
 void launch_phi_correct(const LaunchCfg& L, double* phi, const float* d, const uint8_t* mask,
                         double* partials);
+
+void launch_phi_extrap(const LaunchCfg& L, double* phi, double* phi_prev);
 
 void launch_phi_shift(const LaunchCfg& L, double* phi, const uint8_t* mask, const double* sum,
                       double inv_count);

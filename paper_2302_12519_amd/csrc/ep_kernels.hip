@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kBV) void k_ionic(int nb, const T* __restrict__ v,
 // step (vprev -> v) before x0 overwrites vprev's buffer.
 // Partials: (b.b, r.r).
 template <typename T>
-__global__ __launch_bounds__(kBV, sizeof(T) == 4 ? 6 : 4) void k_be_init(int nb, const int* __restrict__ nbr,
+__global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__ nbr,
                                                  CoefSet<T> c, const T* __restrict__ v,
                                                  const T* __restrict__ w,
                                                  const T* __restrict__ jstim,
@@ -268,9 +268,11 @@ __global__ __launch_bounds__(kBV, sizeof(T) == 4 ? 6 : 4) void k_be_init(int nb,
                                                  IonicT<T> ion, T dt, T* __restrict__ tact,
                                                  T theta, double tprev, int check_prev,
                                                  int* flags, CGScalars* cout, double* parts,
-                                                 double tol2, int maxit) {
+                                                 double tol2, int maxit,
+                                                 const uint64_t* __restrict__ rowsn) {
   __shared__ T s[kTile];
   __shared__ int nbs[kNbr];
+  __shared__ uint64_t rowm[kNbr];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     CGScalars st = {};
     st.tol2 = tol2;
@@ -281,22 +283,25 @@ __global__ __launch_bounds__(kBV, sizeof(T) == 4 ? 6 : 4) void k_be_init(int nb,
   for (int m = 0;; ++m) {
     const int brick = pbrick(m, nb);
     if (brick < 0) break;
-    if (threadIdx.x < kNbr) nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
+    if (threadIdx.x < kNbr) {
+      nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
+      rowm[threadIdx.x] = rowsn[brick * kNbr + threadIdx.x];
+    }
     __syncthreads();
-    const Cell q = cell_setup(nbs, brick);
-    const T v0 = v[q.g], w0 = w[q.g];
-    const T j0 = jstim ? jstim[q.g] : T(0);
-    const T vp = check_prev ? x[q.g] : T(0);
-    const T b0 = bprev ? bprev[q.g] : T(0);
+    const Cell q = cell_setup(nbs, brick, rowm, nb);
+    const T v0 = v[q.gl], w0 = w[q.gl];
+    const T j0 = jstim ? jstim[q.gl] : T(0);
+    const T vp = check_prev ? x[q.gl] : T(0);
+    const T b0 = bprev ? bprev[q.gl] : T(0);
     T hv = T(0), hw = T(0), hj = T(0), hb = T(0);
     if (q.has_halo) {
-      hv = v[q.hg];
-      hw = w[q.hg];
-      hj = jstim ? jstim[q.hg] : T(0);
-      hb = bprev ? bprev[q.hg] : T(0);
+      hv = v[q.hgl];
+      hw = w[q.hgl];
+      hj = jstim ? jstim[q.hgl] : T(0);
+      hb = bprev ? bprev[q.hgl] : T(0);
     }
     T k18[18];
-    gather18(c, nbs, brick, q.lx, q.ly, q.lz, k18);
+    gather18(c, nbs, brick, q.lx, q.ly, q.lz, k18, rowm, nb);
     T vs, ws;
     ms_step(v0, w0, j0, ion, dt, vs, ws);
     const T x0 = bprev ? vs + (v0 - b0) : vs;
@@ -312,10 +317,12 @@ __global__ __launch_bounds__(kBV, sizeof(T) == 4 ? 6 : 4) void k_be_init(int nb,
       if (isinf(tact[q.g])) tact[q.g] = static_cast<T>(tprev) + dt * (theta - vp) / (v0 - vp);
     }
     if (!isfinite(v0)) flags[0] = 1;
-    x[q.g] = x0;
-    bout[q.g] = vs;
-    wout[q.g] = ws;
-    r[q.g] = rr;
+    if (q.live) {
+      x[q.g] = x0;
+      bout[q.g] = vs;
+      wout[q.g] = ws;
+      r[q.g] = rr;
+    }
     const double rd = static_cast<double>(rr);
     acc[0] += static_cast<double>(vs) * static_cast<double>(vs);
     acc[1] += rd * rd;
@@ -337,7 +344,8 @@ __global__ __launch_bounds__(kBV) void k_cgcg(int nb, const int* __restrict__ nb
                                               const T* __restrict__ w_in,
                                               T* __restrict__ w_out, int kind, int init_kind,
                                               const CGScalars* __restrict__ cin, CGScalars* cout,
-                                              const double* __restrict__ prev, double* parts) {
+                                              const double* __restrict__ prev, double* parts,
+                                              const uint64_t* __restrict__ rowsn) {
   const CGScalars in = *cin;
   if (in.done) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *cout = in;
@@ -384,48 +392,52 @@ __global__ __launch_bounds__(kBV) void k_cgcg(int nb, const int* __restrict__ nb
   if (st.done) return;
   __shared__ T s[kTile];
   __shared__ int nbs[kNbr];
+  __shared__ uint64_t rowm[kNbr];
   const T alpha = static_cast<T>(st.alpha), beta = static_cast<T>(st.beta);
   double acc[3] = {0.0, 0.0, 0.0};
   for (int m = 0;; ++m) {
     const int brick = pbrick(m, nb);
     if (brick < 0) break;
-    if (threadIdx.x < kNbr) nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
+    if (threadIdx.x < kNbr) {
+      nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
+      rowm[threadIdx.x] = rowsn[brick * kNbr + threadIdx.x];
+    }
     __syncthreads();
-    const Cell e = cell_setup(nbs, brick);
+    const Cell e = cell_setup(nbs, brick, rowm, nb);
     T rn, un;
     if (kind == 0) {
-      const T rg = r_in[e.g], dg = dinv[e.g];
+      const T rg = r_in[e.gl], dg = dinv[e.gl];
       T hr = T(0), hd = T(0);
       if (e.has_halo) {
-        hr = r_in[e.hg];
-        hd = dinv[e.hg];
+        hr = r_in[e.hgl];
+        hd = dinv[e.hgl];
       }
       T k18[18];
-      gather18(c, nbs, brick, e.lx, e.ly, e.lz, k18);
+      gather18(c, nbs, brick, e.lx, e.ly, e.lz, k18, rowm, nb);
       rn = rg;
       un = dg * rg;
       s[e.C] = un;
       if (e.has_halo) s[e.hC] = hd * hr;
       __syncthreads();
       const T wv = c0 * un + c1 * apply19(s, e.C, k18);
-      w_out[e.g] = wv;
+      if (e.live) w_out[e.g] = wv;
       acc[0] += static_cast<double>(rn) * static_cast<double>(un);
       acc[1] += static_cast<double>(un) * static_cast<double>(wv);
       acc[2] += static_cast<double>(rn) * static_cast<double>(rn);
     } else {
       const bool hist = kind != 1;
-      const T rg = r_in[e.g], dg = dinv[e.g], wg = w_in[e.g], xg = x[e.g];
-      const T sg = hist ? s_in[e.g] : T(0);
-      const T pg = hist ? p[e.g] : T(0);
+      const T rg = r_in[e.gl], dg = dinv[e.gl], wg = w_in[e.gl], xg = x[e.gl];
+      const T sg = hist ? s_in[e.gl] : T(0);
+      const T pg = hist ? p[e.gl] : T(0);
       T hr = T(0), hd = T(0), hw = T(0), hs = T(0);
       if (e.has_halo) {
-        hr = r_in[e.hg];
-        hd = dinv[e.hg];
-        hw = w_in[e.hg];
-        hs = hist ? s_in[e.hg] : T(0);
+        hr = r_in[e.hgl];
+        hd = dinv[e.hgl];
+        hw = w_in[e.hgl];
+        hs = hist ? s_in[e.hgl] : T(0);
       }
       T k18[18];
-      gather18(c, nbs, brick, e.lx, e.ly, e.lz, k18);
+      gather18(c, nbs, brick, e.lx, e.ly, e.lz, k18, rowm, nb);
       const T pn = dg * rg + beta * pg;
       const T sn = wg + beta * sg;
       rn = rg - alpha * sn;
@@ -434,11 +446,13 @@ __global__ __launch_bounds__(kBV) void k_cgcg(int nb, const int* __restrict__ nb
       if (e.has_halo) s[e.hC] = hd * (hr - alpha * (hw + beta * hs));
       __syncthreads();
       const T wv = c0 * un + c1 * apply19(s, e.C, k18);
-      x[e.g] = xg + alpha * pn;
-      p[e.g] = pn;
-      s_out[e.g] = sn;
-      r_out[e.g] = rn;
-      w_out[e.g] = wv;
+      if (e.live) {
+        x[e.g] = xg + alpha * pn;
+        p[e.g] = pn;
+        s_out[e.g] = sn;
+        r_out[e.g] = rn;
+        w_out[e.g] = wv;
+      }
       acc[0] += static_cast<double>(rn) * static_cast<double>(un);
       acc[1] += static_cast<double>(un) * static_cast<double>(wv);
       acc[2] += static_cast<double>(rn) * static_cast<double>(rn);
@@ -620,6 +634,18 @@ __global__ __launch_bounds__(kBV) void k_phi_shift(int nb, double* __restrict__ 
   const int g = brick * kBV + threadIdx.x;
   const double mean = sum[0] * inv_count;
   phi[g] = mask[g] ? phi[g] - mean : 0.0;
+}
+
+// Initial guess of the next elliptic solve by linear extrapolation in time:
+// phi <- 2 phi - phi_prev, phi_prev <- the old phi (both keep sum = 0).
+__global__ __launch_bounds__(kBV) void k_phi_extrap(int nb, double* __restrict__ phi,
+                                                    double* __restrict__ phi_prev) {
+  const int brick = block_brick();
+  if (brick >= nb) return;
+  const int g = brick * kBV + threadIdx.x;
+  const double p = phi[g];
+  phi[g] = 2.0 * p - phi_prev[g];
+  phi_prev[g] = p;
 }
 
 // v_{n+1} = v* + dt A_i (v* + phi), with the activation check
@@ -945,7 +971,7 @@ void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v
   k_be_init<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, bprev, bout, x, wout,
                                               r, ion, dt,
                                               tact, theta, tprev, check_prev, flags, cout, parts,
-                                              tol2, maxit);
+                                              tol2, maxit, L.rowsn);
 }
 
 template <typename T>
@@ -955,7 +981,7 @@ void launch_cgcg(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, c
                  const double* prev, double* parts) {
   k_cgcg<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, c0, c1, dinv, x, r_in, r_out, p, s_in,
                                            s_out, w_in, w_out, kind, init_kind, cin, cout, prev,
-                                           parts);
+                                           parts, L.rowsn);
 }
 
 void launch_reduce_sum(hipStream_t s, const double* partials, int nparts, int K, double* out) {
@@ -1004,6 +1030,10 @@ void launch_inner_init(const LaunchCfg& L, const double* r64, const uint8_t* mas
 void launch_phi_correct(const LaunchCfg& L, double* phi, const float* d, const uint8_t* mask,
                         double* partials) {
   k_phi_correct<<<L.grid, kBV, 0, L.stream>>>(L.nb, phi, d, mask, partials);
+}
+
+void launch_phi_extrap(const LaunchCfg& L, double* phi, double* phi_prev) {
+  k_phi_extrap<<<L.grid, kBV, 0, L.stream>>>(L.nb, phi, phi_prev);
 }
 
 void launch_phi_shift(const LaunchCfg& L, double* phi, const uint8_t* mask, const double* sum,

@@ -41,7 +41,7 @@ struct TimerPair {
 // stencil, 3 the FP64 elliptic residual, 4 CG launches that only detected
 // convergence (or skipped after it)
 enum { KT_STENCIL = 0, KT_CGSETUP = 1, KT_PARABOLIC = 2, KT_RESID = 3, KT_CGTAIL = 4,
-       KT_ADJ = 5, kTimers = 6 };
+       KT_ADJ = 5, KT_INIT = 6, kTimers = 7 };
 
 }  // namespace
 
@@ -73,6 +73,7 @@ struct ep_grid_s {
   std::vector<void*> allocs;
   int64_t dev_bytes = 0;
   int* d_nbr = nullptr;
+  uint64_t* d_rowsn = nullptr;
   uint8_t* d_mask = nullptr;
   void* d_v[2] = {nullptr, nullptr};
   void* d_w[2] = {nullptr, nullptr};
@@ -90,6 +91,7 @@ struct ep_grid_s {
   void* d_bprev[2] = {nullptr, nullptr};  // implicit solve: b of the last two steps
   void* d_vs = nullptr;       // bidomain v*
   double* d_phi = nullptr;
+  double* d_phi_prev = nullptr;   // bidomain: phi of the step before (extrapolated guess)
   double* d_r64 = nullptr;
   float* d_x32 = nullptr;        // inner FP32 PCG of the elliptic refinement
   float* d_r32[2] = {nullptr, nullptr};
@@ -123,6 +125,7 @@ struct ep_grid_s {
   int64_t step = 0;
   bool have_prev = false;      // d_v[1-cur] holds the previous step's v
   bool have_bprev = false;     // d_bprev[1-bsel] holds the previous step's b
+  int phi_hist = 0;            // solved phi of past steps: 1 = d_phi, 2 = also d_phi_prev
   int bsel = 0;
   bool has_cond = false;
   bool nonfinite = false;
@@ -139,6 +142,12 @@ struct ep_grid_s {
 };
 
 namespace {
+
+// message of this thread's last failed ep_create_grid
+std::string& create_error() {
+  static thread_local std::string last;
+  return last;
+}
 
 ep_status fail(ep_grid g, ep_status s, const std::string& msg) {
   if (g) g->err = msg;
@@ -412,6 +421,7 @@ ep_status step_be(ep_grid g, const T* jstim, ep_step_info* acc) {
   // x (= d_v[n]) still holds the previous step's v: check its activation here
   // initial guess from the previous step's diffusion increment (v_n - b_{n-1})
   const T* bprev = g->have_bprev ? static_cast<const T*>(g->d_bprev[1 - g->bsel]) : nullptr;
+  TimerPair* ti = timer_begin(g, KT_INIT);
   launch_be_init<T>(g->L, g->d_nbr, coefs<T>(g), static_cast<const T*>(g->d_v[c]),
                     static_cast<const T*>(g->d_w[c]), jstim, bprev,
                     static_cast<T*>(g->d_bprev[g->bsel]), x, static_cast<T*>(g->d_w[n]),
@@ -419,6 +429,7 @@ ep_status step_be(ep_grid g, const T* jstim, ep_step_info* acc) {
                     static_cast<T>(g->theta), static_cast<double>(g->step - 1) * g->dt,
                     g->have_prev ? 1 : 0, g->d_flags, g->d_cg, g->d_cgp[0],
                     g->pcg_rtol * g->pcg_rtol, g->pcg_maxit);
+  timer_end(g, ti);
   int iters = 0;
   bool failed = false;
   TRY(cg_solve<T>(g, coefs<T>(g), T(1), static_cast<T>(-g->dt), dinv, x, r, sv, wv,
@@ -490,8 +501,16 @@ ep_status step_bido(ep_grid g, const T* jstim, ep_step_info* acc) {
   T* vs = static_cast<T*>(g->d_vs);
   launch_ionic<T>(g->L, static_cast<const T*>(g->d_v[c]), static_cast<const T*>(g->d_w[c]), jstim,
                   vs, static_cast<T*>(g->d_w[n]), ionic_t<T>(g), static_cast<T>(g->dt));
+  // warm start: phi of the last step, linearly extrapolated once two exist
+  if (g->phi_hist >= 2) {
+    launch_phi_extrap(g->L, g->d_phi, g->d_phi_prev);
+  } else if (g->phi_hist == 1) {
+    HIPCHK(g, hipMemcpyAsync(g->d_phi_prev, g->d_phi, static_cast<size_t>(g->nvox) * sizeof(double),
+                             hipMemcpyDeviceToDevice, g->stream));
+  }
   ep_solve_info si{};
   ep_status s = elliptic<T>(g, vs, g->ell_rtol, g->ell_max_outer, &si);
+  g->phi_hist = std::min(2, g->phi_hist + 1);
   if (s == EP_ERR_NOCONV) g->hs->flags[1] = 1;
   else if (s != EP_OK) return s;
   acc->cg_iters += si.inner_iters;
@@ -620,7 +639,8 @@ ep_status adjoint_impl(ep_grid g, int32_t nsteps, int32_t K, const double* tstar
   // targets to brick layout (non-finite = no target; non-tissue = no target)
   {
     std::vector<T> ht(nv, std::numeric_limits<T>::infinity());
-    for (int x = 0; x < g->n[0]; ++x)
+    parallel_for(g->n[0], [&](int64_t xx) {
+      const int x = static_cast<int>(xx);
       for (int y = 0; y < g->n[1]; ++y)
         for (int z = 0; z < g->n[2]; ++z) {
           const int64_t gi = brick_index(g, x, y, z);
@@ -628,6 +648,7 @@ ep_status adjoint_impl(ep_grid g, int32_t nsteps, int32_t K, const double* tstar
           const double t = tstar_box[box_index(g, x, y, z)];
           ht[gi] = std::isfinite(t) ? static_cast<T>(t) : std::numeric_limits<T>::infinity();
         }
+    });
     HIPCHK(g, hipMemcpyAsync(d_tstar, ht.data(), vb, hipMemcpyHostToDevice, g->stream));
     HIPCHK(g, hipStreamSynchronize(g->stream));
   }
@@ -728,12 +749,14 @@ ep_status adjoint_impl(ep_grid g, int32_t nsteps, int32_t K, const double* tstar
                            g->stream));
   HIPCHK(g, hipStreamSynchronize(g->stream));
   timer_collect(g);
-  for (int x = 0; x < g->n[0]; ++x)
+  parallel_for(g->n[0], [&](int64_t xx) {
+    const int x = static_cast<int>(xx);
     for (int y = 0; y < g->n[1]; ++y)
       for (int z = 0; z < g->n[2]; ++z) {
         const int64_t gi = brick_index(g, x, y, z);
         grad_box[box_index(g, x, y, z)] = (gi < 0 || !g->hmask[gi]) ? 0.0 : hg[gi];
       }
+  });
   return EP_OK;
 }
 
@@ -896,6 +919,8 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   const size_t es = elem_size(g->prec);
   const size_t vb = static_cast<size_t>(g->nvox) * es;
   TRY(dalloc(g, &g->d_nbr, hnbr.size() * sizeof(int)));
+  TRY(dalloc(g, &g->d_rowsn, bm.rowsn.size() * sizeof(uint64_t)));
+  g->L.rowsn = g->d_rowsn;
   TRY(dalloc(g, &g->d_mask, static_cast<size_t>(g->nvox)));
   for (int k = 0; k < 2; ++k) {
     TRY(dalloc(g, &g->d_v[k], vb));
@@ -929,6 +954,7 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
     const size_t b64 = static_cast<size_t>(g->nvox) * sizeof(double);
     const size_t b32 = static_cast<size_t>(g->nvox) * sizeof(float);
     TRY(dalloc(g, &g->d_vs, vb));
+    TRY(dalloc(g, &g->d_phi_prev, b64));
     TRY(dalloc(g, &g->d_r64, b64));
     for (int k = 0; k < 6; ++k) {
       TRY(dalloc(g, &g->d_ci64[k], b64));
@@ -951,6 +977,8 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
     std::memset(g->hs, 0, sizeof(HostSync));
   }
   HIPCHK(g, hipMemcpyAsync(g->d_nbr, hnbr.data(), hnbr.size() * sizeof(int),
+                           hipMemcpyHostToDevice, g->stream));
+  HIPCHK(g, hipMemcpyAsync(g->d_rowsn, bm.rowsn.data(), bm.rowsn.size() * sizeof(uint64_t),
                            hipMemcpyHostToDevice, g->stream));
   HIPCHK(g, hipMemcpyAsync(g->d_mask, g->hmask.data(), g->hmask.size(), hipMemcpyHostToDevice,
                            g->stream));
@@ -976,19 +1004,20 @@ ep_status write_field(ep_grid g, ep_field f, const double* in) {
   double* bd = reinterpret_cast<double*>(buf.data());
   const int64_t nreal = static_cast<int64_t>(g->nb) * kBV;
   // defaults for non-tissue voxels of active bricks (the ghost brick stays 0)
-  for (int64_t i = 0; i < nreal; ++i) {
-    if (f == EP_W) bt[i] = T(1);
-    else if (f == EP_TACT) bt[i] = static_cast<T>(kInf);
+  if (f == EP_W || f == EP_TACT) {
+    const T fill = f == EP_W ? T(1) : static_cast<T>(kInf);
+    std::fill(bt, bt + nreal, fill);
   }
-  for (int x = 0; x < g->n[0]; ++x)
+  parallel_for(g->n[0], [&](int64_t x) {
     for (int y = 0; y < g->n[1]; ++y)
       for (int z = 0; z < g->n[2]; ++z) {
-        const int64_t gi = brick_index(g, x, y, z);
+        const int64_t gi = brick_index(g, static_cast<int>(x), y, z);
         if (gi < 0 || !g->hmask[gi]) continue;
-        const double v = in[box_index(g, x, y, z)];
+        const double v = in[box_index(g, static_cast<int>(x), y, z)];
         if (f == EP_PHIE) bd[gi] = v;
         else bt[gi] = static_cast<T>(v);
       }
+  });
   void* dst = nullptr;
   switch (f) {
     case EP_V: dst = g->d_v[g->cur]; break;
@@ -1017,14 +1046,15 @@ ep_status read_field(ep_grid g, ep_field f, double* out) {
   const T* bt = reinterpret_cast<const T*>(buf.data());
   const double* bd = reinterpret_cast<const double*>(buf.data());
   const double off = (f == EP_TACT) ? kInf : 0.0;
-  for (int x = 0; x < g->n[0]; ++x)
+  parallel_for(g->n[0], [&](int64_t x) {
     for (int y = 0; y < g->n[1]; ++y)
       for (int z = 0; z < g->n[2]; ++z) {
-        const int64_t gi = brick_index(g, x, y, z);
+        const int64_t gi = brick_index(g, static_cast<int>(x), y, z);
         double v = off;
         if (gi >= 0 && g->hmask[gi]) v = (f == EP_PHIE) ? bd[gi] : static_cast<double>(bt[gi]);
-        out[box_index(g, x, y, z)] = v;
+        out[box_index(g, static_cast<int>(x), y, z)] = v;
       }
+  });
   return EP_OK;
 }
 
@@ -1039,7 +1069,9 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
   // fibres / scale to brick layout, validated on tissue
   std::vector<double> hf(static_cast<size_t>(g->nvox) * 3, 0.0), hsc;
   if (scale) hsc.assign(g->nvox, 0.0);
-  for (int x = 0; x < g->n[0]; ++x)
+  std::atomic<int> bad{0};   // 1: non-unit fibre, 2: bad scale
+  parallel_for(g->n[0], [&](int64_t xx) {
+    const int x = static_cast<int>(xx);
     for (int y = 0; y < g->n[1]; ++y)
       for (int z = 0; z < g->n[2]; ++z) {
         const int64_t gi = brick_index(g, x, y, z);
@@ -1047,18 +1079,19 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
         const int64_t bi = box_index(g, x, y, z);
         const double f0 = fibre[3 * bi], f1 = fibre[3 * bi + 1], f2 = fibre[3 * bi + 2];
         const double nrm = std::sqrt(f0 * f0 + f1 * f1 + f2 * f2);
-        if (!(std::fabs(nrm - 1.0) <= 1e-6))
-          return fail(g, EP_ERR_ARG, "fibre is not a unit vector on a tissue voxel");
+        if (!(std::fabs(nrm - 1.0) <= 1e-6)) bad.store(1);
         hf[3 * gi] = f0;
         hf[3 * gi + 1] = f1;
         hf[3 * gi + 2] = f2;
         if (scale) {
           const double s = scale[bi];
-          if (!(s > 0) || !std::isfinite(s))
-            return fail(g, EP_ERR_ARG, "scale must be finite and > 0 on tissue");
+          if (!(s > 0) || !std::isfinite(s)) bad.store(2);
           hsc[gi] = s;
         }
       }
+  });
+  if (bad.load() == 1) return fail(g, EP_ERR_ARG, "fibre is not a unit vector on a tissue voxel");
+  if (bad.load() == 2) return fail(g, EP_ERR_ARG, "scale must be finite and > 0 on tissue");
   double *dfib = nullptr, *dsc = nullptr, *tens = nullptr;
   const size_t b64 = static_cast<size_t>(g->nvox) * sizeof(double);
   hipError_t e = hipMalloc(&dfib, 3 * b64);
@@ -1170,8 +1203,7 @@ EP_API ep_status ep_create_grid(const ep_grid_desc* d, ep_grid* out) {
     s = fail(g, EP_ERR_HIP, "unexpected exception");
   }
   if (s != EP_OK) {
-    static thread_local std::string last;
-    last = g->err;
+    create_error() = g->err;
     ep_destroy_grid(g);
     return s;
   }
@@ -1231,6 +1263,7 @@ EP_API ep_status ep_solve_elliptic(ep_grid g, double rel_tol, int32_t max_outer,
   if (g->model != EP_BIDO) return fail(g, EP_ERR_UNSUPPORTED, "monodomain grid");
   if (!g->has_cond) return fail(g, EP_ERR_STATE, "ep_set_conductivity_fibres not called");
   if (!(rel_tol > 0) || max_outer < 1) return fail(g, EP_ERR_ARG, "rel_tol > 0, max_outer >= 1");
+  g->phi_hist = 0;   // this phi belongs to no step
   ep_status s = g->prec == EP_F64
                     ? elliptic<double>(g, static_cast<const double*>(g->d_v[g->cur]), rel_tol,
                                        max_outer, info)
@@ -1265,6 +1298,7 @@ EP_API ep_status ep_write_state(ep_grid g, ep_field f, const double* host_in, si
     if (s == EP_OK) {
       if (f == EP_V) g->have_prev = false;
       g->have_bprev = false;
+      g->phi_hist = 0;
       g->nonfinite = false;
       HIPCHK(g, hipMemsetAsync(g->d_flags, 0, 4 * sizeof(int), g->stream));
       HIPCHK(g, hipStreamSynchronize(g->stream));
@@ -1287,6 +1321,7 @@ EP_API ep_status ep_set_step(ep_grid g, int64_t step) {
   g->stim_built = false;
   g->have_prev = false;
   g->have_bprev = false;
+  g->phi_hist = 0;
   return EP_OK;
 }
 
@@ -1349,7 +1384,7 @@ EP_API const char* ep_status_string(ep_status s) {
 }
 
 EP_API const char* ep_last_error(ep_grid g) {
-  return g ? g->err.c_str() : "";
+  return g ? g->err.c_str() : create_error().c_str();
 }
 
 }  // extern "C"

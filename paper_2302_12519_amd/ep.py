@@ -11,6 +11,15 @@ import os
 
 import numpy as np
 
+# torch ships its own HIP runtime.  When this library's runtime (ROCm from
+# /opt/rocm) is loaded into a process before torch's, and torch then
+# initialises the device, this library's first HIP call finds no device; in
+# the opposite order both work.  Load torch first whenever it is installed.
+try:
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover - torch is optional for the binding
+    pass
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libep_hip.so")
 
@@ -20,7 +29,8 @@ EP_F64, EP_F32 = 0, 1
 EP_MONO, EP_BIDO = 0, 1
 EP_DIFF_EXPLICIT, EP_DIFF_BE_PCG = 0, 1
 FIELDS = {"v": 0, "w": 1, "phi": 2, "tact": 3}
-KERNELS = {"stencil": 0, "cg_setup": 1, "parabolic": 2, "resid": 3, "cg_tail": 4, "adjoint": 5}
+KERNELS = {"stencil": 0, "cg_setup": 1, "parabolic": 2, "resid": 3, "cg_tail": 4, "adjoint": 5,
+           "be_init": 6}
 
 
 class EPError(RuntimeError):
@@ -202,7 +212,7 @@ class Grid:
 
     def _check(self, st, what, handle=True):
         if st != EP_OK:
-            msg = lib.ep_last_error(self._h).decode() if handle and self._h else ""
+            msg = lib.ep_last_error(self._h if handle else None).decode()
             name = lib.ep_status_string(st).decode()
             raise EPError(st, f"{what}: {name} {msg}".strip())
 
