@@ -106,9 +106,10 @@ void launch_ionic(const LaunchCfg& L, const T* v, const T* w, const T* jstim, T*
 // check of the previous step (x still holds v_prev).  Partials (b.b, r.r).
 template <typename T>
 void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v,
-                    const T* w, const T* jstim, const T* bprev, T* bout, T* x, T* wout, T* r,
-                    IonicT<T> ion, T dt, T* tact, T theta, double tprev, int check_prev,
-                    int* flags, CGScalars* cout, double* parts, double tol2, int maxit);
+                    const T* w, const T* jstim, const T* bprev, const T* dprev2, T* bout,
+                    T* dout, T* x, T* wout, T* r, IonicT<T> ion, T dt, T* tact, T theta,
+                    double tprev, int check_prev, int* flags, CGScalars* cout, double* parts,
+                    double tol2, int maxit);
 
 // One launch of the one-reduction PCG for K = c0 I + c1 A (kind 0 set-up,
 // 1 first iteration, 2 general; init_kind 0 after k_be_init, 1 after
