@@ -89,7 +89,7 @@ struct ep_grid_s {
   void* d_cp = nullptr;
   void* d_dinv = nullptr;
   void* d_bprev[2] = {nullptr, nullptr};  // implicit solve: b of the last two steps
-  void* d_dprev[2] = {nullptr, nullptr};  // and diffusion increments d = v_{k+1} - b_k
+  void* d_dprev[3] = {nullptr, nullptr, nullptr};  // ring of increments d = v_{k+1} - b_k
   void* d_vs = nullptr;       // bidomain v*
   double* d_phi = nullptr;
   double* d_phi_prev = nullptr;   // bidomain: phi of the step before (extrapolated guess)
@@ -126,7 +126,8 @@ struct ep_grid_s {
   int64_t step = 0;
   bool have_prev = false;      // d_v[1-cur] holds the previous step's v
   bool have_bprev = false;     // d_bprev[1-bsel] holds the previous step's b
-  bool have_dprev = false;     // d_dprev[1-bsel] holds d of the step before that
+  int dhist = 0;               // increments held in the d ring (0..2)
+  int dsel = 0;                // ring slot of the next increment
   int phi_hist = 0;            // solved phi of past steps: 1 = d_phi, 2 = also d_phi_prev
   int bsel = 0;
   bool has_cond = false;
@@ -423,11 +424,12 @@ ep_status step_be(ep_grid g, const T* jstim, ep_step_info* acc) {
   // x (= d_v[n]) still holds the previous step's v: check its activation here
   // initial guess from the previous step's diffusion increment (v_n - b_{n-1})
   const T* bprev = g->have_bprev ? static_cast<const T*>(g->d_bprev[1 - g->bsel]) : nullptr;
-  const T* dprev2 = g->have_dprev ? static_cast<const T*>(g->d_dprev[1 - g->bsel]) : nullptr;
+  const T* dprev2 = g->dhist >= 1 ? static_cast<const T*>(g->d_dprev[(g->dsel + 2) % 3]) : nullptr;
+  const T* dprev3 = g->dhist >= 2 ? static_cast<const T*>(g->d_dprev[(g->dsel + 1) % 3]) : nullptr;
   TimerPair* ti = timer_begin(g, KT_INIT);
   launch_be_init<T>(g->L, g->d_nbr, coefs<T>(g), static_cast<const T*>(g->d_v[c]),
-                    static_cast<const T*>(g->d_w[c]), jstim, bprev, dprev2,
-                    static_cast<T*>(g->d_bprev[g->bsel]), static_cast<T*>(g->d_dprev[g->bsel]),
+                    static_cast<const T*>(g->d_w[c]), jstim, bprev, dprev2, dprev3,
+                    static_cast<T*>(g->d_bprev[g->bsel]), static_cast<T*>(g->d_dprev[g->dsel]),
                     x, static_cast<T*>(g->d_w[n]),
                     r[0], ionic_t<T>(g), static_cast<T>(g->dt), static_cast<T*>(g->d_tact),
                     static_cast<T>(g->theta), static_cast<double>(g->step - 1) * g->dt,
@@ -544,7 +546,10 @@ ep_status run_steps(ep_grid g, int32_t nsteps, ep_step_info* info) {
     } else if (g->diff == EP_DIFF_BE_PCG) {
       TRY(step_be<T>(g, jstim, &acc));
       g->bsel = 1 - g->bsel;
-      g->have_dprev = g->have_bprev;   // d was written when b_{n-1} existed
+      if (g->have_bprev) {   // this step wrote d_{n-1} into the ring
+        g->dsel = (g->dsel + 1) % 3;
+        g->dhist = std::min(2, g->dhist + 1);
+      }
       g->have_bprev = true;
     } else {
       TRY(step_explicit<T>(g, jstim));
@@ -951,10 +956,8 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
     }
     TRY(dalloc(g, &g->d_cp, vb));
     TRY(dalloc(g, &g->d_dinv, vb));
-    for (int k = 0; k < 2; ++k) {
-      TRY(dalloc(g, &g->d_bprev[k], vb));
-      TRY(dalloc(g, &g->d_dprev[k], vb));
-    }
+    for (int k = 0; k < 2; ++k) TRY(dalloc(g, &g->d_bprev[k], vb));
+    for (int k = 0; k < 3; ++k) TRY(dalloc(g, &g->d_dprev[k], vb));
   }
   if (g->model == EP_MONO && g->diff == EP_DIFF_EXPLICIT)
     for (int k = 0; k < 6; ++k) TRY(dalloc(g, &g->d_d0[k], vb));
@@ -1189,7 +1192,7 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
   cleanup();
   if (rc == EP_OK) g->has_cond = true;
   g->have_bprev = false;
-  g->have_dprev = false;
+  g->dhist = 0;
   return rc;
 }
 
@@ -1307,7 +1310,7 @@ EP_API ep_status ep_write_state(ep_grid g, ep_field f, const double* host_in, si
     if (s == EP_OK) {
       if (f == EP_V) g->have_prev = false;
       g->have_bprev = false;
-      g->have_dprev = false;
+      g->dhist = 0;
       g->phi_hist = 0;
       g->nonfinite = false;
       HIPCHK(g, hipMemsetAsync(g->d_flags, 0, 4 * sizeof(int), g->stream));
@@ -1331,7 +1334,7 @@ EP_API ep_status ep_set_step(ep_grid g, int64_t step) {
   g->stim_built = false;
   g->have_prev = false;
   g->have_bprev = false;
-  g->have_dprev = false;
+  g->dhist = 0;
   g->phi_hist = 0;
   return EP_OK;
 }
