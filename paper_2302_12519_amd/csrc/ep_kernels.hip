@@ -252,10 +252,10 @@ __global__ __launch_bounds__(kBV) void k_ionic(int nb, const T* __restrict__ v,
 
 // Reaction fused with the initial guess and residual of the implicit solve
 // (I - dt A) x = b, b = v*.  The guess extrapolates the diffusion increment
-// d_k = v_{k+1} - b_k of the past steps: x0 = b + d_{n-1} when b_{n-1} is
-// given (bprev), x0 = b + 2 d_{n-1} - d_{n-2} when d_{n-2} is given too
-// (dprev2), x0 = b + 3 d_{n-1} - 3 d_{n-2} + d_{n-3} when d_{n-3} is given
-// too (dprev3), else x0 = b.  r0 = b - (I - dt A) x0.  b is stored in bout and
+// d_k = v_{k+1} - b_k of the past steps by the polynomial through the last
+// 1..4 of them: x0 = b + d_{n-1} (bprev given), + 2 d_{n-1} - d_{n-2}
+// (dprev2 too), + 3 d_{n-1} - 3 d_{n-2} + d_{n-3} (dprev3 too), or
+// + 4 d_{n-1} - 6 d_{n-2} + 4 d_{n-3} - d_{n-4} (dprev4 too); else x0 = b.  r0 = b - (I - dt A) x0.  b is stored in bout and
 // d_{n-1} in dout (when bprev is given) for the next step; neither buffer is
 // read in the same launch, so halo reads never race with other blocks'
 // writes.  When check_prev is set it also records activation for the
@@ -269,6 +269,7 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
                                                  const T* __restrict__ bprev,
                                                  const T* __restrict__ dprev2,
                                                  const T* __restrict__ dprev3,
+                                                 const T* __restrict__ dprev4,
                                                  T* __restrict__ bout, T* __restrict__ dout,
                                                  T* x,
                                                  T* __restrict__ wout, T* __restrict__ r,
@@ -302,7 +303,8 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
     const T b1 = bprev ? bprev[q.gl] : T(0);
     const T d2 = dprev2 ? dprev2[q.gl] : T(0);
     const T d3 = dprev3 ? dprev3[q.gl] : T(0);
-    T hv = T(0), hw = T(0), hj = T(0), hb1 = T(0), hd2 = T(0), hd3 = T(0);
+    const T d4 = dprev4 ? dprev4[q.gl] : T(0);
+    T hv = T(0), hw = T(0), hj = T(0), hb1 = T(0), hd2 = T(0), hd3 = T(0), hd4 = T(0);
     if (q.has_halo) {
       hv = v[q.hgl];
       hw = w[q.hgl];
@@ -310,6 +312,7 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
       hb1 = bprev ? bprev[q.hgl] : T(0);
       hd2 = dprev2 ? dprev2[q.hgl] : T(0);
       hd3 = dprev3 ? dprev3[q.hgl] : T(0);
+      hd4 = dprev4 ? dprev4[q.hgl] : T(0);
     }
     T k18[18];
     gather18(c, nbs, brick, q.lx, q.ly, q.lz, k18, rowm, nb);
@@ -317,7 +320,8 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
     ms_step(v0, w0, j0, ion, dt, vs, ws);
     const T d1 = v0 - b1;
     T x0 = vs;
-    if (dprev3) x0 = vs + (T(3) * (d1 - d2) + d3);
+    if (dprev4) x0 = vs + (T(4) * (d1 + d3) - T(6) * d2 - d4);
+    else if (dprev3) x0 = vs + (T(3) * (d1 - d2) + d3);
     else if (dprev2) x0 = vs + (T(2) * d1 - d2);
     else if (bprev) x0 = vs + d1;
     s[q.C] = x0;
@@ -326,7 +330,8 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
       ms_step(hv, hw, hj, ion, dt, a, b);
       const T hd1 = hv - hb1;
       T hx0 = a;
-      if (dprev3) hx0 = a + (T(3) * (hd1 - hd2) + hd3);
+      if (dprev4) hx0 = a + (T(4) * (hd1 + hd3) - T(6) * hd2 - hd4);
+      else if (dprev3) hx0 = a + (T(3) * (hd1 - hd2) + hd3);
       else if (dprev2) hx0 = a + (T(2) * hd1 - hd2);
       else if (bprev) hx0 = a + hd1;
       s[q.hC] = hx0;
@@ -986,12 +991,12 @@ void launch_ionic(const LaunchCfg& L, const T* v, const T* w, const T* jstim, T*
 
 template <typename T>
 void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v, const T* w,
-                    const T* jstim, const T* bprev, const T* dprev2, const T* dprev3, T* bout,
-                    T* dout, T* x, T* wout, T* r, IonicT<T> ion, T dt, T* tact, T theta,
-                    double tprev, int check_prev, int* flags, CGScalars* cout, double* parts,
-                    double tol2, int maxit) {
+                    const T* jstim, const T* bprev, const T* dprev2, const T* dprev3,
+                    const T* dprev4, T* bout, T* dout, T* x, T* wout, T* r, IonicT<T> ion, T dt,
+                    T* tact, T theta, double tprev, int check_prev, int* flags, CGScalars* cout,
+                    double* parts, double tol2, int maxit) {
   k_be_init<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, bprev, dprev2, dprev3,
-                                              bout, dout, x, wout, r, ion, dt,
+                                              dprev4, bout, dout, x, wout, r, ion, dt,
                                               tact, theta, tprev, check_prev, flags, cout, parts,
                                               tol2, maxit, L.rowsn);
 }
@@ -1109,8 +1114,8 @@ void launch_loss(const LaunchCfg& L, const uint8_t* mask, const int* cross, cons
   template void launch_ionic<T>(const LaunchCfg&, const T*, const T*, const T*, T*, T*,        \
                                 IonicT<T>, T);                                                 \
   template void launch_be_init<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*,          \
-                                  const T*, const T*, const T*, const T*, const T*, T*, T*,    \
-                                  T*, T*, T*, IonicT<T>, T, T*, T, double, int, int*,          \
+                                  const T*, const T*, const T*, const T*, const T*, const T*,  \
+                                  T*, T*, T*, T*, T*, IonicT<T>, T, T*, T, double, int, int*,  \
                                   CGScalars*, double*, double, int);                           \
   template void launch_cgcg<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T, const T*, T*,   \
                                const T*, T*, T*, const T*, T*, const T*, T*, int, int,         \

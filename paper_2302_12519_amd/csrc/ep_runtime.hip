@@ -40,6 +40,10 @@ struct TimerPair {
 // or one full CG iteration, 1 the CG set-up launch, 2 the bidomain parabolic
 // stencil, 3 the FP64 elliptic residual, 4 CG launches that only detected
 // convergence (or skipped after it)
+// ring of past diffusion increments kept for the implicit solve's initial
+// guess (the newest written each step plus kDRing - 1 older ones)
+constexpr int kDRing = 4;
+
 enum { KT_STENCIL = 0, KT_CGSETUP = 1, KT_PARABOLIC = 2, KT_RESID = 3, KT_CGTAIL = 4,
        KT_ADJ = 5, KT_INIT = 6, kTimers = 7 };
 
@@ -89,7 +93,7 @@ struct ep_grid_s {
   void* d_cp = nullptr;
   void* d_dinv = nullptr;
   void* d_bprev[2] = {nullptr, nullptr};  // implicit solve: b of the last two steps
-  void* d_dprev[3] = {nullptr, nullptr, nullptr};  // ring of increments d = v_{k+1} - b_k
+  void* d_dprev[kDRing] = {};  // ring of increments d = v_{k+1} - b_k
   void* d_vs = nullptr;       // bidomain v*
   double* d_phi = nullptr;
   double* d_phi_prev = nullptr;   // bidomain: phi of the step before (extrapolated guess)
@@ -126,7 +130,7 @@ struct ep_grid_s {
   int64_t step = 0;
   bool have_prev = false;      // d_v[1-cur] holds the previous step's v
   bool have_bprev = false;     // d_bprev[1-bsel] holds the previous step's b
-  int dhist = 0;               // increments held in the d ring (0..2)
+  int dhist = 0;               // increments held in the d ring (0..kDRing-1)
   int dsel = 0;                // ring slot of the next increment
   int phi_hist = 0;            // solved phi of past steps: 1 = d_phi, 2 = also d_phi_prev
   int bsel = 0;
@@ -424,11 +428,16 @@ ep_status step_be(ep_grid g, const T* jstim, ep_step_info* acc) {
   // x (= d_v[n]) still holds the previous step's v: check its activation here
   // initial guess from the previous step's diffusion increment (v_n - b_{n-1})
   const T* bprev = g->have_bprev ? static_cast<const T*>(g->d_bprev[1 - g->bsel]) : nullptr;
-  const T* dprev2 = g->dhist >= 1 ? static_cast<const T*>(g->d_dprev[(g->dsel + 2) % 3]) : nullptr;
-  const T* dprev3 = g->dhist >= 2 ? static_cast<const T*>(g->d_dprev[(g->dsel + 1) % 3]) : nullptr;
+  auto dback = [&](int k) {   // d_{n-1-k}, k = 1.. (written k steps ago)
+    return g->dhist >= k ? static_cast<const T*>(g->d_dprev[(g->dsel + kDRing - k) % kDRing])
+                         : nullptr;
+  };
+  const T* dprev2 = dback(1);
+  const T* dprev3 = dback(2);
+  const T* dprev4 = dback(3);
   TimerPair* ti = timer_begin(g, KT_INIT);
   launch_be_init<T>(g->L, g->d_nbr, coefs<T>(g), static_cast<const T*>(g->d_v[c]),
-                    static_cast<const T*>(g->d_w[c]), jstim, bprev, dprev2, dprev3,
+                    static_cast<const T*>(g->d_w[c]), jstim, bprev, dprev2, dprev3, dprev4,
                     static_cast<T*>(g->d_bprev[g->bsel]), static_cast<T*>(g->d_dprev[g->dsel]),
                     x, static_cast<T*>(g->d_w[n]),
                     r[0], ionic_t<T>(g), static_cast<T>(g->dt), static_cast<T*>(g->d_tact),
@@ -547,8 +556,8 @@ ep_status run_steps(ep_grid g, int32_t nsteps, ep_step_info* info) {
       TRY(step_be<T>(g, jstim, &acc));
       g->bsel = 1 - g->bsel;
       if (g->have_bprev) {   // this step wrote d_{n-1} into the ring
-        g->dsel = (g->dsel + 1) % 3;
-        g->dhist = std::min(2, g->dhist + 1);
+        g->dsel = (g->dsel + 1) % kDRing;
+        g->dhist = std::min(kDRing - 1, g->dhist + 1);
       }
       g->have_bprev = true;
     } else {
@@ -957,7 +966,7 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
     TRY(dalloc(g, &g->d_cp, vb));
     TRY(dalloc(g, &g->d_dinv, vb));
     for (int k = 0; k < 2; ++k) TRY(dalloc(g, &g->d_bprev[k], vb));
-    for (int k = 0; k < 3; ++k) TRY(dalloc(g, &g->d_dprev[k], vb));
+    for (int k = 0; k < kDRing; ++k) TRY(dalloc(g, &g->d_dprev[k], vb));
   }
   if (g->model == EP_MONO && g->diff == EP_DIFF_EXPLICIT)
     for (int k = 0; k < 6; ++k) TRY(dalloc(g, &g->d_d0[k], vb));
