@@ -156,7 +156,9 @@ void launch_inner_init(const LaunchCfg& L, const double* r64, const uint8_t* mas
 void launch_phi_correct(const LaunchCfg& L, double* phi, const float* d, const uint8_t* mask,
                         double* partials);
 
-void launch_phi_extrap(const LaunchCfg& L, double* phi, double* phi_prev);
+// phi = polynomial extrapolation (order 2 or 3) of the past solutions h1, h2, h3
+void launch_phi_extrap(const LaunchCfg& L, double* phi, const double* h1, const double* h2,
+                       const double* h3, int order);
 
 void launch_phi_shift(const LaunchCfg& L, double* phi, const uint8_t* mask, const double* sum,
                       double inv_count);

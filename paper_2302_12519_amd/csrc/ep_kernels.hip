@@ -662,16 +662,17 @@ __global__ __launch_bounds__(kBV) void k_phi_shift(int nb, double* __restrict__ 
   phi[g] = mask[g] ? phi[g] - mean : 0.0;
 }
 
-// Initial guess of the next elliptic solve by linear extrapolation in time:
-// phi <- 2 phi - phi_prev, phi_prev <- the old phi (both keep sum = 0).
+// Initial guess of the next elliptic solve: the polynomial in time through
+// the last solutions h1 (newest), h2, h3: phi = 2 h1 - h2 (order 2) or
+// 3 h1 - 3 h2 + h3 (order 3).  The weights sum to 1, so sum phi = 0 holds.
 __global__ __launch_bounds__(kBV) void k_phi_extrap(int nb, double* __restrict__ phi,
-                                                    double* __restrict__ phi_prev) {
+                                                    const double* __restrict__ h1,
+                                                    const double* __restrict__ h2,
+                                                    const double* __restrict__ h3, int order) {
   const int brick = block_brick();
   if (brick >= nb) return;
   const int g = brick * kBV + threadIdx.x;
-  const double p = phi[g];
-  phi[g] = 2.0 * p - phi_prev[g];
-  phi_prev[g] = p;
+  phi[g] = order >= 3 ? 3.0 * (h1[g] - h2[g]) + h3[g] : 2.0 * h1[g] - h2[g];
 }
 
 // v_{n+1} = v* + dt A_i (v* + phi), with the activation check
@@ -1059,8 +1060,9 @@ void launch_phi_correct(const LaunchCfg& L, double* phi, const float* d, const u
   k_phi_correct<<<L.grid, kBV, 0, L.stream>>>(L.nb, phi, d, mask, partials);
 }
 
-void launch_phi_extrap(const LaunchCfg& L, double* phi, double* phi_prev) {
-  k_phi_extrap<<<L.grid, kBV, 0, L.stream>>>(L.nb, phi, phi_prev);
+void launch_phi_extrap(const LaunchCfg& L, double* phi, const double* h1, const double* h2,
+                       const double* h3, int order) {
+  k_phi_extrap<<<L.grid, kBV, 0, L.stream>>>(L.nb, phi, h1, h2, h3, order);
 }
 
 void launch_phi_shift(const LaunchCfg& L, double* phi, const uint8_t* mask, const double* sum,

@@ -22,7 +22,9 @@ using namespace ep;
 namespace {
 
 constexpr double kInf = std::numeric_limits<double>::infinity();
-// Inner FP32 PCG of the elliptic refinement: relative reduction per outer step.
+// Inner FP32 PCG of the elliptic refinement: relative reduction per outer
+// step (asking one pass for more costs more iterations than it saves: FP32
+// rounding of the operator limits what a pass gains in FP64 terms).
 constexpr double kInnerRtol = 1e-3;
 
 struct HostSync {          // pinned read-back block
@@ -96,7 +98,8 @@ struct ep_grid_s {
   void* d_dprev[kDRing] = {};  // ring of increments d = v_{k+1} - b_k
   void* d_vs = nullptr;       // bidomain v*
   double* d_phi = nullptr;
-  double* d_phi_prev = nullptr;   // bidomain: phi of the step before (extrapolated guess)
+  double* d_phi_hist[3] = {};     // bidomain: ring of past solutions (extrapolated guess)
+  int phi_sel = 0;                // ring slot of the next solution
   double* d_r64 = nullptr;
   float* d_x32 = nullptr;        // inner FP32 PCG of the elliptic refinement
   float* d_r32[2] = {nullptr, nullptr};
@@ -132,7 +135,7 @@ struct ep_grid_s {
   bool have_bprev = false;     // d_bprev[1-bsel] holds the previous step's b
   int dhist = 0;               // increments held in the d ring (0..kDRing-1)
   int dsel = 0;                // ring slot of the next increment
-  int phi_hist = 0;            // solved phi of past steps: 1 = d_phi, 2 = also d_phi_prev
+  int phi_hist = 0;            // solved phi of past steps held in the ring (0..3)
   int bsel = 0;
   bool has_cond = false;
   bool nonfinite = false;
@@ -488,8 +491,9 @@ ep_status elliptic(ep_grid g, const T* vsrc, double rtol, int max_outer, ep_solv
     relres = std::sqrt(rr / bb);
     if (relres <= rtol) { ok = true; break; }
     if (!std::isfinite(relres) || outer >= max_outer) break;
+    const double tin = kInnerRtol;
     launch_inner_init(g->L, g->d_r64, g->d_mask, g->d_sums, inv_count, g->d_x32, g->d_r32[0],
-                      g->d_cg, g->d_cgp[0], kInnerRtol * kInnerRtol, g->ell_inner_maxit);
+                      g->d_cg, g->d_cgp[0], tin * tin, g->ell_inner_maxit);
     int iters = 0;
     bool failed = false;
     TRY(cg_solve<float>(g, cset32(g->d_ck32), 0.0f, -1.0f, g->d_dinvk, g->d_x32, g->d_r32,
@@ -516,16 +520,18 @@ ep_status step_bido(ep_grid g, const T* jstim, ep_step_info* acc) {
   T* vs = static_cast<T*>(g->d_vs);
   launch_ionic<T>(g->L, static_cast<const T*>(g->d_v[c]), static_cast<const T*>(g->d_w[c]), jstim,
                   vs, static_cast<T*>(g->d_w[n]), ionic_t<T>(g), static_cast<T>(g->dt));
-  // warm start: phi of the last step, linearly extrapolated once two exist
-  if (g->phi_hist >= 2) {
-    launch_phi_extrap(g->L, g->d_phi, g->d_phi_prev);
-  } else if (g->phi_hist == 1) {
-    HIPCHK(g, hipMemcpyAsync(g->d_phi_prev, g->d_phi, static_cast<size_t>(g->nvox) * sizeof(double),
-                             hipMemcpyDeviceToDevice, g->stream));
-  }
+  // warm start: the last solution (still in d_phi), or the polynomial
+  // through the last two or three
+  auto hist = [&](int k) { return g->d_phi_hist[(g->phi_sel + 3 - k) % 3]; };   // k = 1 newest
+  if (g->phi_hist >= 2)
+    launch_phi_extrap(g->L, g->d_phi, hist(1), hist(2), hist(3), std::min(3, g->phi_hist));
   ep_solve_info si{};
   ep_status s = elliptic<T>(g, vs, g->ell_rtol, g->ell_max_outer, &si);
-  g->phi_hist = std::min(2, g->phi_hist + 1);
+  HIPCHK(g, hipMemcpyAsync(g->d_phi_hist[g->phi_sel], g->d_phi,
+                           static_cast<size_t>(g->nvox) * sizeof(double), hipMemcpyDeviceToDevice,
+                           g->stream));
+  g->phi_sel = (g->phi_sel + 1) % 3;
+  g->phi_hist = std::min(3, g->phi_hist + 1);
   if (s == EP_ERR_NOCONV) g->hs->flags[1] = 1;
   else if (s != EP_OK) return s;
   acc->cg_iters += si.inner_iters;
@@ -974,7 +980,7 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
     const size_t b64 = static_cast<size_t>(g->nvox) * sizeof(double);
     const size_t b32 = static_cast<size_t>(g->nvox) * sizeof(float);
     TRY(dalloc(g, &g->d_vs, vb));
-    TRY(dalloc(g, &g->d_phi_prev, b64));
+    for (int k = 0; k < 3; ++k) TRY(dalloc(g, &g->d_phi_hist[k], b64));
     TRY(dalloc(g, &g->d_r64, b64));
     for (int k = 0; k < 6; ++k) {
       TRY(dalloc(g, &g->d_ci64[k], b64));
