@@ -106,10 +106,9 @@ void launch_ionic(const LaunchCfg& L, const T* v, const T* w, const T* jstim, T*
 // check of the previous step (x still holds v_prev).  Partials (b.b, r.r).
 template <typename T>
 void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v,
-                    const T* w, const T* jstim, const T* bprev, const T* dprev2,
-                    const T* dprev3, const T* dprev4, T* bout, T* dout, T* x, T* wout, T* r,
-                    IonicT<T> ion, T dt,
-                    T* tact, T theta,
+                    const T* w, const T* jstim, const T* bprev, const T* qin, T kd,
+                    const T* d2, const T* d3, T q2, T q3, T q4, T* bout, T* dout, T* qout,
+                    T* x, T* wout, T* r, IonicT<T> ion, T dt, T* tact, T theta,
                     double tprev, int check_prev, int* flags, CGScalars* cout, double* parts,
                     double tol2, int maxit);
 

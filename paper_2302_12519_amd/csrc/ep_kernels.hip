@@ -253,13 +253,15 @@ __global__ __launch_bounds__(kBV) void k_ionic(int nb, const T* __restrict__ v,
 // Reaction fused with the initial guess and residual of the implicit solve
 // (I - dt A) x = b, b = v*.  The guess extrapolates the diffusion increment
 // d_k = v_{k+1} - b_k of the past steps by the polynomial through the last
-// 1..4 of them: x0 = b + d_{n-1} (bprev given), + 2 d_{n-1} - d_{n-2}
-// (dprev2 too), + 3 d_{n-1} - 3 d_{n-2} + d_{n-3} (dprev3 too), or
-// + 4 d_{n-1} - 6 d_{n-2} + 4 d_{n-3} - d_{n-4} (dprev4 too); else x0 = b.  r0 = b - (I - dt A) x0.  b is stored in bout and
-// d_{n-1} in dout (when bprev is given) for the next step; neither buffer is
-// read in the same launch, so halo reads never race with other blocks'
-// writes.  When check_prev is set it also records activation for the
-// previous step (vprev -> v) before x0 overwrites vprev's buffer.
+// K <= 4 of them (binomial weights): x0 = b + K d_{n-1} + Q_n, where
+// d_{n-1} = v_n - b_{n-1} (bprev) and Q_n, the part that holds only older
+// increments, was stored by the previous step (qin; none for K <= 1).  This
+// step stores b (bout), d_{n-1} (dout) and
+//   Q_{n+1} = q2 d_{n-1} + q3 d_{n-2} + q4 d_{n-3}   (qout; d2, d3 older ones)
+// for the next one.  No buffer read here is written in the same launch, so
+// halo reads never race with other blocks' writes.  r0 = b - (I - dt A) x0.
+// When check_prev is set it also records activation for the previous step
+// (vprev -> v) before x0 overwrites vprev's buffer.
 // Partials: (b.b, r.r).
 template <typename T>
 __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__ nbr,
@@ -267,11 +269,11 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
                                                  const T* __restrict__ w,
                                                  const T* __restrict__ jstim,
                                                  const T* __restrict__ bprev,
-                                                 const T* __restrict__ dprev2,
-                                                 const T* __restrict__ dprev3,
-                                                 const T* __restrict__ dprev4,
+                                                 const T* __restrict__ qin, T kd,
+                                                 const T* __restrict__ d2in,
+                                                 const T* __restrict__ d3in, T q2, T q3, T q4,
                                                  T* __restrict__ bout, T* __restrict__ dout,
-                                                 T* x,
+                                                 T* __restrict__ qout, T* x,
                                                  T* __restrict__ wout, T* __restrict__ r,
                                                  IonicT<T> ion, T dt, T* __restrict__ tact,
                                                  T theta, double tprev, int check_prev,
@@ -301,40 +303,28 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
     const T j0 = jstim ? jstim[q.gl] : T(0);
     const T vp = check_prev ? x[q.gl] : T(0);
     const T b1 = bprev ? bprev[q.gl] : T(0);
-    const T d2 = dprev2 ? dprev2[q.gl] : T(0);
-    const T d3 = dprev3 ? dprev3[q.gl] : T(0);
-    const T d4 = dprev4 ? dprev4[q.gl] : T(0);
-    T hv = T(0), hw = T(0), hj = T(0), hb1 = T(0), hd2 = T(0), hd3 = T(0), hd4 = T(0);
+    const T q0 = qin ? qin[q.gl] : T(0);
+    const T d2 = d2in ? d2in[q.gl] : T(0);
+    const T d3 = d3in ? d3in[q.gl] : T(0);
+    T hv = T(0), hw = T(0), hj = T(0), hb1 = T(0), hq = T(0);
     if (q.has_halo) {
       hv = v[q.hgl];
       hw = w[q.hgl];
       hj = jstim ? jstim[q.hgl] : T(0);
       hb1 = bprev ? bprev[q.hgl] : T(0);
-      hd2 = dprev2 ? dprev2[q.hgl] : T(0);
-      hd3 = dprev3 ? dprev3[q.hgl] : T(0);
-      hd4 = dprev4 ? dprev4[q.hgl] : T(0);
+      hq = qin ? qin[q.hgl] : T(0);
     }
     T k18[18];
     gather18(c, nbs, brick, q.lx, q.ly, q.lz, k18, rowm, nb);
     T vs, ws;
     ms_step(v0, w0, j0, ion, dt, vs, ws);
     const T d1 = v0 - b1;
-    T x0 = vs;
-    if (dprev4) x0 = vs + (T(4) * (d1 + d3) - T(6) * d2 - d4);
-    else if (dprev3) x0 = vs + (T(3) * (d1 - d2) + d3);
-    else if (dprev2) x0 = vs + (T(2) * d1 - d2);
-    else if (bprev) x0 = vs + d1;
+    const T x0 = bprev ? vs + (kd * d1 + q0) : vs;
     s[q.C] = x0;
     if (q.has_halo) {
       T a, b;
       ms_step(hv, hw, hj, ion, dt, a, b);
-      const T hd1 = hv - hb1;
-      T hx0 = a;
-      if (dprev4) hx0 = a + (T(4) * (hd1 + hd3) - T(6) * hd2 - hd4);
-      else if (dprev3) hx0 = a + (T(3) * (hd1 - hd2) + hd3);
-      else if (dprev2) hx0 = a + (T(2) * hd1 - hd2);
-      else if (bprev) hx0 = a + hd1;
-      s[q.hC] = hx0;
+      s[q.hC] = bprev ? a + (kd * (hv - hb1) + hq) : a;
     }
     __syncthreads();
     const T rr = (vs - x0) + dt * apply19(s, q.C, k18);
@@ -345,7 +335,10 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
     if (q.live) {
       x[q.g] = x0;
       bout[q.g] = vs;
-      if (bprev) dout[q.g] = d1;
+      if (bprev) {
+        dout[q.g] = d1;
+        qout[q.g] = q2 * d1 + q3 * d2 + q4 * d3;
+      }
       wout[q.g] = ws;
       r[q.g] = rr;
     }
@@ -992,12 +985,12 @@ void launch_ionic(const LaunchCfg& L, const T* v, const T* w, const T* jstim, T*
 
 template <typename T>
 void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v, const T* w,
-                    const T* jstim, const T* bprev, const T* dprev2, const T* dprev3,
-                    const T* dprev4, T* bout, T* dout, T* x, T* wout, T* r, IonicT<T> ion, T dt,
-                    T* tact, T theta, double tprev, int check_prev, int* flags, CGScalars* cout,
-                    double* parts, double tol2, int maxit) {
-  k_be_init<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, bprev, dprev2, dprev3,
-                                              dprev4, bout, dout, x, wout, r, ion, dt,
+                    const T* jstim, const T* bprev, const T* qin, T kd, const T* d2,
+                    const T* d3, T q2, T q3, T q4, T* bout, T* dout, T* qout, T* x, T* wout,
+                    T* r, IonicT<T> ion, T dt, T* tact, T theta, double tprev, int check_prev,
+                    int* flags, CGScalars* cout, double* parts, double tol2, int maxit) {
+  k_be_init<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, bprev, qin, kd, d2, d3,
+                                              q2, q3, q4, bout, dout, qout, x, wout, r, ion, dt,
                                               tact, theta, tprev, check_prev, flags, cout, parts,
                                               tol2, maxit, L.rowsn);
 }
@@ -1116,9 +1109,9 @@ void launch_loss(const LaunchCfg& L, const uint8_t* mask, const int* cross, cons
   template void launch_ionic<T>(const LaunchCfg&, const T*, const T*, const T*, T*, T*,        \
                                 IonicT<T>, T);                                                 \
   template void launch_be_init<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*,          \
-                                  const T*, const T*, const T*, const T*, const T*, const T*,  \
-                                  T*, T*, T*, T*, T*, IonicT<T>, T, T*, T, double, int, int*,  \
-                                  CGScalars*, double*, double, int);                           \
+                                  const T*, const T*, const T*, const T*, T, const T*,         \
+                                  const T*, T, T, T, T*, T*, T*, T*, T*, T*, IonicT<T>, T, T*, \
+                                  T, double, int, int*, CGScalars*, double*, double, int);     \
   template void launch_cgcg<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T, const T*, T*,   \
                                const T*, T*, T*, const T*, T*, const T*, T*, int, int,         \
                                const CGScalars*, CGScalars*, const double*, double*);          \

@@ -42,9 +42,12 @@ struct TimerPair {
 // or one full CG iteration, 1 the CG set-up launch, 2 the bidomain parabolic
 // stencil, 3 the FP64 elliptic residual, 4 CG launches that only detected
 // convergence (or skipped after it)
-// ring of past diffusion increments kept for the implicit solve's initial
-// guess (the newest written each step plus kDRing - 1 older ones)
-constexpr int kDRing = 4;
+// Initial guess of the implicit solve: polynomial extrapolation of the
+// diffusion increments of at most kPredOrder past steps.  A ring of three
+// increments (the newest written each step, two older ones read) and a
+// ping-pong pair for the precomputed history term Q.
+constexpr int kPredOrder = 4;
+constexpr int kDRing = 3;
 
 enum { KT_STENCIL = 0, KT_CGSETUP = 1, KT_PARABOLIC = 2, KT_RESID = 3, KT_CGTAIL = 4,
        KT_ADJ = 5, KT_INIT = 6, kTimers = 7 };
@@ -96,6 +99,7 @@ struct ep_grid_s {
   void* d_dinv = nullptr;
   void* d_bprev[2] = {nullptr, nullptr};  // implicit solve: b of the last two steps
   void* d_dprev[kDRing] = {};  // ring of increments d = v_{k+1} - b_k
+  void* d_q[2] = {nullptr, nullptr};  // history term of the next guess, ping-pong
   void* d_vs = nullptr;       // bidomain v*
   double* d_phi = nullptr;
   double* d_phi_hist[3] = {};     // bidomain: ring of past solutions (extrapolated guess)
@@ -133,7 +137,7 @@ struct ep_grid_s {
   int64_t step = 0;
   bool have_prev = false;      // d_v[1-cur] holds the previous step's v
   bool have_bprev = false;     // d_bprev[1-bsel] holds the previous step's b
-  int dhist = 0;               // increments held in the d ring (0..kDRing-1)
+  int pred_len = 0;            // consecutive implicit steps behind the current one
   int dsel = 0;                // ring slot of the next increment
   int phi_hist = 0;            // solved phi of past steps held in the ring (0..3)
   int bsel = 0;
@@ -429,19 +433,30 @@ ep_status step_be(ep_grid g, const T* jstim, ep_step_info* acc) {
   T* wv[2] = {static_cast<T*>(g->d_cw[0]), static_cast<T*>(g->d_cw[1])};
   const T* dinv = static_cast<const T*>(g->d_dinv);
   // x (= d_v[n]) still holds the previous step's v: check its activation here
-  // initial guess from the previous step's diffusion increment (v_n - b_{n-1})
-  const T* bprev = g->have_bprev ? static_cast<const T*>(g->d_bprev[1 - g->bsel]) : nullptr;
-  auto dback = [&](int k) {   // d_{n-1-k}, k = 1.. (written k steps ago)
-    return g->dhist >= k ? static_cast<const T*>(g->d_dprev[(g->dsel + kDRing - k) % kDRing])
-                         : nullptr;
+  // initial guess: polynomial through the last K = min(pred_len, 4) diffusion
+  // increments; Q_n came from the previous step, Q_{n+1} is written now
+  auto binom = [](int k, int j) {
+    static const int t[5][5] = {{1, 0, 0, 0, 0}, {1, 1, 0, 0, 0}, {1, 2, 1, 0, 0},
+                                {1, 3, 3, 1, 0}, {1, 4, 6, 4, 1}};
+    return (k >= 0 && k <= 4 && j >= 0 && j <= 4) ? t[k][j] : 0;
   };
-  const T* dprev2 = dback(1);
-  const T* dprev3 = dback(2);
-  const T* dprev4 = dback(3);
+  const int m = g->have_bprev ? g->pred_len : 0;
+  const int K = std::min(kPredOrder, m);            // order of this step's guess
+  const int K1 = std::min(kPredOrder, m + 1);       // order of the next step's guess
+  const T* bprev = m >= 1 ? static_cast<const T*>(g->d_bprev[1 - g->bsel]) : nullptr;
+  const T* qin = K >= 2 ? static_cast<const T*>(g->d_q[1 - g->bsel]) : nullptr;
+  auto dback = [&](int k) {   // increment written k steps before this one's (k = 1, 2)
+    return static_cast<const T*>(g->d_dprev[(g->dsel + kDRing - k) % kDRing]);
+  };
+  const T* d2 = m >= 2 ? dback(1) : nullptr;
+  const T* d3 = m >= 3 ? dback(2) : nullptr;
+  const T q2 = static_cast<T>(-binom(K1, 2)), q3 = static_cast<T>(binom(K1, 3));
+  const T q4 = static_cast<T>(-binom(K1, 4));
   TimerPair* ti = timer_begin(g, KT_INIT);
   launch_be_init<T>(g->L, g->d_nbr, coefs<T>(g), static_cast<const T*>(g->d_v[c]),
-                    static_cast<const T*>(g->d_w[c]), jstim, bprev, dprev2, dprev3, dprev4,
-                    static_cast<T*>(g->d_bprev[g->bsel]), static_cast<T*>(g->d_dprev[g->dsel]),
+                    static_cast<const T*>(g->d_w[c]), jstim, bprev, qin, static_cast<T>(K), d2,
+                    d3, q2, q3, q4, static_cast<T*>(g->d_bprev[g->bsel]),
+                    static_cast<T*>(g->d_dprev[g->dsel]), static_cast<T*>(g->d_q[g->bsel]),
                     x, static_cast<T*>(g->d_w[n]),
                     r[0], ionic_t<T>(g), static_cast<T>(g->dt), static_cast<T*>(g->d_tact),
                     static_cast<T>(g->theta), static_cast<double>(g->step - 1) * g->dt,
@@ -561,10 +576,8 @@ ep_status run_steps(ep_grid g, int32_t nsteps, ep_step_info* info) {
     } else if (g->diff == EP_DIFF_BE_PCG) {
       TRY(step_be<T>(g, jstim, &acc));
       g->bsel = 1 - g->bsel;
-      if (g->have_bprev) {   // this step wrote d_{n-1} into the ring
-        g->dsel = (g->dsel + 1) % kDRing;
-        g->dhist = std::min(kDRing - 1, g->dhist + 1);
-      }
+      if (g->have_bprev) g->dsel = (g->dsel + 1) % kDRing;   // d_{n-1} went into the ring
+      g->pred_len = g->have_bprev ? g->pred_len + 1 : 1;
       g->have_bprev = true;
     } else {
       TRY(step_explicit<T>(g, jstim));
@@ -973,6 +986,7 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
     TRY(dalloc(g, &g->d_dinv, vb));
     for (int k = 0; k < 2; ++k) TRY(dalloc(g, &g->d_bprev[k], vb));
     for (int k = 0; k < kDRing; ++k) TRY(dalloc(g, &g->d_dprev[k], vb));
+    for (int k = 0; k < 2; ++k) TRY(dalloc(g, &g->d_q[k], vb));
   }
   if (g->model == EP_MONO && g->diff == EP_DIFF_EXPLICIT)
     for (int k = 0; k < 6; ++k) TRY(dalloc(g, &g->d_d0[k], vb));
@@ -1207,7 +1221,7 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
   cleanup();
   if (rc == EP_OK) g->has_cond = true;
   g->have_bprev = false;
-  g->dhist = 0;
+  g->pred_len = 0;
   return rc;
 }
 
@@ -1325,7 +1339,7 @@ EP_API ep_status ep_write_state(ep_grid g, ep_field f, const double* host_in, si
     if (s == EP_OK) {
       if (f == EP_V) g->have_prev = false;
       g->have_bprev = false;
-      g->dhist = 0;
+      g->pred_len = 0;
       g->phi_hist = 0;
       g->nonfinite = false;
       HIPCHK(g, hipMemsetAsync(g->d_flags, 0, 4 * sizeof(int), g->stream));
@@ -1349,7 +1363,7 @@ EP_API ep_status ep_set_step(ep_grid g, int64_t step) {
   g->stim_built = false;
   g->have_prev = false;
   g->have_bprev = false;
-  g->dhist = 0;
+  g->pred_len = 0;
   g->phi_hist = 0;
   return EP_OK;
 }
