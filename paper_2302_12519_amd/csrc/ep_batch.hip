@@ -213,7 +213,12 @@ struct ep_batch_s {
   Arena arena;
   size_t arena_peak = 0;
   SlotDev* d_slots = nullptr;
-  SlotDev* h_slots = nullptr;   // pinned read-back
+  SlotDev* h_slots = nullptr;   // pinned read-back of the slot table
+  SlotDev* h_up = nullptr;      // pinned staging of slot uploads (one per slot, and a zero entry)
+  hipStream_t rstream = nullptr;  // result reads (finished requests only)
+  hipEvent_t ev_done = nullptr;   // end of the graph launch in flight
+  bool inflight = false;
+  std::vector<long long> launch_before;  // per slot: step at the launch in flight, -1 = not in it
   WorkItem* d_work = nullptr;
   int* d_count = nullptr;
   int* d_flags = nullptr;
@@ -353,7 +358,7 @@ ep_status admit(ep_batch b, ep_batch_request* r, int slot) {
   launch_tensor_coefs(L, d_nbr, b->d_mask, b->d_fib, r->scale_b.empty() ? nullptr : b->d_scale,
                       r->sig_l, r->sig_t, r->h, b->d_tens, nullptr, c32);
   BHIP(b, hipGetLastError());
-  SlotDev& sd = b->h_slots[slot];
+  SlotDev& sd = b->h_up[slot];
   sd = SlotDev{};
   sd.nbr = d_nbr;
   for (int k = 0; k < 6; ++k) sd.c[k] = arr[k];
@@ -377,10 +382,10 @@ ep_status admit(ep_batch b, ep_batch_request* r, int slot) {
   sd.step = 0;
   sd.n_steps = r->n_steps;
   sd.active = 1;
-  // from pinned memory; the next read-back of the slot table follows it on
-  // the same stream
+  // from pinned staging that nothing rewrites before the copy has run
   BHIP(b, hipMemcpyAsync(b->d_slots + slot, &sd, sizeof(SlotDev), hipMemcpyHostToDevice,
                          b->stream));
+  b->h_slots[slot] = sd;
   r->slot = slot;
   b->slot_owner[slot] = r->id;
   b->st.admitted += 1;
@@ -497,6 +502,20 @@ EP_API ep_status ep_batch_create(const ep_batch_desc* d, ep_batch* out) {
     }
     b->h_slots = static_cast<SlotDev*>(hp);
     std::memset(b->h_slots, 0, b->max_slots * sizeof(SlotDev));
+    void* hu = nullptr;
+    if (hipHostMalloc(&hu, (b->max_slots + 1) * sizeof(SlotDev), hipHostMallocDefault) !=
+        hipSuccess) {
+      s = EP_ERR_OOM;
+      break;
+    }
+    b->h_up = static_cast<SlotDev*>(hu);
+    std::memset(b->h_up, 0, (b->max_slots + 1) * sizeof(SlotDev));
+    if (hipStreamCreateWithFlags(&b->rstream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming) != hipSuccess) {
+      s = EP_ERR_HIP;
+      break;
+    }
+    b->launch_before.assign(b->max_slots, -1);
     if (hipMemsetAsync(b->d_slots, 0, b->max_slots * sizeof(SlotDev), b->stream) != hipSuccess ||
         hipMemsetAsync(b->d_count, 0, sizeof(int), b->stream) != hipSuccess ||
         hipMemsetAsync(b->d_flags, 0, 4 * sizeof(int), b->stream) != hipSuccess ||
@@ -653,6 +672,27 @@ EP_API ep_status ep_batch_submit(ep_batch b, const ep_grid_desc* d, const double
 EP_API ep_status ep_batch_advance(ep_batch b, int32_t* n_finished) {
   if (!b) return EP_ERR_ARG;
   try {
+    // results of the graph launch in flight: wait for it, read the slot table
+    int nfin = 0;
+    if (b->inflight) {
+      BHIP(b, hipEventSynchronize(b->ev_done));
+      b->inflight = false;
+      for (int s = 0; s < b->max_slots; ++s) {
+        if (b->launch_before[s] < 0) continue;
+        const int64_t id = b->slot_owner[s];
+        ep_batch_request* r = b->all[id];
+        b->st.voxel_steps += static_cast<double>(b->h_slots[s].step - b->launch_before[s]) *
+                             static_cast<double>(r->map.n_tissue);
+        b->launch_before[s] = -1;
+        if (b->h_slots[s].step >= r->n_steps) {
+          r->finished = true;
+          b->finished_ids.push_back(id);
+          b->st.finished += 1;
+          b->work_dirty = true;
+          ++nfin;
+        }
+      }
+    }
     // admission: FIFO while memory and a slot are free
     while (!b->queue.empty()) {
       ep_batch_request* r = b->queue.front();
@@ -671,38 +711,23 @@ EP_API ep_status ep_batch_advance(ep_batch b, int32_t* n_finished) {
     if (b->work_dirty)
       if (ep_status s = rebuild_work(b); s != EP_OK) return s;
     if (ep_status s = capture(b); s != EP_OK) return s;
-    // one graph launch of K steps for every running request
-    std::vector<long long> before(b->max_slots, 0);
+    // one graph launch of K steps for every running request; the host
+    // returns at once and collects the results at the next call
     bool any = false;
     for (int s = 0; s < b->max_slots; ++s) {
       const int64_t id = b->slot_owner[s];
       if (id >= 0 && !b->all[id]->finished) {
-        before[s] = b->h_slots[s].step;
+        b->launch_before[s] = b->h_slots[s].step;
         any = true;
       }
     }
-    int nfin = 0;
     if (any) {
       BHIP(b, hipGraphLaunch(b->exec, b->stream));
       b->st.graph_launches += 1;
       BHIP(b, hipMemcpyAsync(b->h_slots, b->d_slots, b->max_slots * sizeof(SlotDev),
                              hipMemcpyDeviceToHost, b->stream));
-      BHIP(b, hipStreamSynchronize(b->stream));
-      for (int s = 0; s < b->max_slots; ++s) {
-        const int64_t id = b->slot_owner[s];
-        if (id < 0) continue;
-        ep_batch_request* r = b->all[id];
-        if (r->finished) continue;
-        b->st.voxel_steps +=
-            static_cast<double>(b->h_slots[s].step - before[s]) * static_cast<double>(r->map.n_tissue);
-        if (b->h_slots[s].step >= r->n_steps) {
-          r->finished = true;
-          b->finished_ids.push_back(id);
-          b->st.finished += 1;
-          b->work_dirty = true;
-          ++nfin;
-        }
-      }
+      BHIP(b, hipEventRecord(b->ev_done, b->stream));
+      b->inflight = true;
     }
     if (n_finished) *n_finished = nfin;
     return EP_OK;
@@ -731,16 +756,25 @@ EP_API ep_status ep_batch_read(ep_batch b, int64_t id, ep_field f, double* host_
   const size_t N = static_cast<size_t>(r->n[0]) * r->n[1] * r->n[2];
   if (n < N) return bfail(b, EP_ERR_ARG, "output buffer too small");
   try {
-    BHIP(b, hipMemcpyAsync(&b->h_slots[r->slot], b->d_slots + r->slot, sizeof(SlotDev),
-                           hipMemcpyDeviceToHost, b->stream));
-    BHIP(b, hipStreamSynchronize(b->stream));
-    const SlotDev& sd = b->h_slots[r->slot];
-    const int par = static_cast<int>(sd.step & 1);
+    // A finished request's buffers are no longer touched by any launch (it
+    // left the work list before the launch in flight): read them on the
+    // read stream, concurrently with that launch.  A running request is read
+    // after the launch in flight.
+    int64_t step = r->n_steps;
+    hipStream_t rs = b->rstream;
+    if (!r->finished) {
+      BHIP(b, hipStreamSynchronize(b->stream));
+      SlotDev cur{};
+      BHIP(b, hipMemcpy(&cur, b->d_slots + r->slot, sizeof(SlotDev), hipMemcpyDeviceToHost));
+      step = cur.step;
+      rs = b->stream;
+    }
+    const SlotDev& sd = b->h_up[r->slot];   // the request's buffer pointers
+    const int par = static_cast<int>(step & 1);
     const float* src = f == EP_V ? sd.v[par] : (f == EP_W ? sd.w[par] : sd.tact);
     std::vector<float> buf(m.nvox);
-    BHIP(b, hipMemcpyAsync(buf.data(), src, m.nvox * sizeof(float), hipMemcpyDeviceToHost,
-                           b->stream));
-    BHIP(b, hipStreamSynchronize(b->stream));
+    BHIP(b, hipMemcpyAsync(buf.data(), src, m.nvox * sizeof(float), hipMemcpyDeviceToHost, rs));
+    BHIP(b, hipStreamSynchronize(rs));
     const double off = f == EP_TACT ? std::numeric_limits<double>::infinity() : 0.0;
     parallel_for(r->n[0], [&](int64_t xx) {
       const int x = static_cast<int>(xx);
@@ -763,11 +797,15 @@ EP_API ep_status ep_batch_release(ep_batch b, int64_t id) {
   if (it == b->all.end()) return bfail(b, EP_ERR_ARG, "unknown request id");
   ep_batch_request* r = it->second;
   if (r->slot >= 0) {
-    SlotDev off{};
-    BHIP(b, hipMemcpyAsync(b->d_slots + r->slot, &off, sizeof(SlotDev), hipMemcpyHostToDevice,
-                           b->stream));
-    BHIP(b, hipStreamSynchronize(b->stream));
-    std::memset(&b->h_slots[r->slot], 0, sizeof(SlotDev));
+    if (!r->finished) {
+      // still in the work list of the launch in flight: let it end first
+      BHIP(b, hipStreamSynchronize(b->stream));
+      b->launch_before[r->slot] = -1;
+    }
+    // clear the slot after the launch in flight (the zero entry of the
+    // pinned staging area is never written)
+    BHIP(b, hipMemcpyAsync(b->d_slots + r->slot, b->h_up + b->max_slots, sizeof(SlotDev),
+                           hipMemcpyHostToDevice, b->stream));
     b->arena.release(r->off, r->bytes);
     b->slot_owner[r->slot] = -1;
     b->st.resident -= 1;
@@ -811,6 +849,9 @@ EP_API ep_status ep_batch_destroy(ep_batch b) {
   (void)hipFree(b->d_stim_amp);
   (void)hipFree(b->d_qstep);
   if (b->h_slots) (void)hipHostFree(b->h_slots);
+  if (b->h_up) (void)hipHostFree(b->h_up);
+  if (b->ev_done) (void)hipEventDestroy(b->ev_done);
+  if (b->rstream) (void)hipStreamDestroy(b->rstream);
   if (b->h_work) (void)hipHostFree(b->h_work);
   if (b->h_count) (void)hipHostFree(b->h_count);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);

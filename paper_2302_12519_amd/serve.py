@@ -21,11 +21,16 @@ def percentile(xs, q):
     return s[lo] + (s[hi] - s[lo]) * (k - lo)
 
 
-def serve(batch, requests, fields=("tact",), clock=time.perf_counter, sleep=time.sleep):
+def serve(batch, requests, fields=("tact",), clock=time.perf_counter, sleep=time.sleep,
+          submit_per_advance=1):
     """Run a request stream to completion.
 
     requests: iterable of objects with ``arrival`` (s from stream start),
     ``rid`` (caller id) and ``submit(batch) -> batch id``.
+    At most ``submit_per_advance`` arrived requests are submitted between two
+    advances, so the host work of submission overlaps the launch in flight
+    (an advance returns as soon as its launch is queued and reports the
+    requests that the previous launch finished).
     Returns a dict with per-request latency, results (the requested fields)
     and aggregate figures (makespan, p50/p99 latency, voxel-steps/s)."""
     pending = sorted(requests, key=lambda r: r.arrival)
@@ -36,7 +41,9 @@ def serve(batch, requests, fields=("tact",), clock=time.perf_counter, sleep=time
     i = 0
     while i < len(pending) or outstanding:
         now = clock() - t0
-        while i < len(pending) and pending[i].arrival <= now:
+        n_sub = 0
+        while i < len(pending) and pending[i].arrival <= now and n_sub < submit_per_advance:
+            n_sub += 1
             r = pending[i]
             bid = r.submit(batch)
             bid_of[r.rid] = bid

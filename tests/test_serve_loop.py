@@ -59,7 +59,7 @@ def test_all_requests_complete_with_latency():
     fb = FakeBatch(slots=2, K=10)
     clock = lambda: fb.t
     reqs = [Req(k, 0.0, 10 * (k + 1)) for k in range(5)]
-    out = serve.serve(fb, reqs, clock=clock, sleep=lambda s: None)
+    out = serve.serve(fb, reqs, clock=clock, sleep=lambda s: None, submit_per_advance=5)
     assert sorted(out["latency"]) == list(range(5))
     # with 2 slots: r0 (1 launch), r1 (2) run first; r2 enters after r0 ...
     assert out["latency"][0] == 1.0
@@ -86,3 +86,16 @@ def test_idle_until_next_arrival():
 def test_percentile_interpolates():
     assert serve.percentile([1, 2, 3, 4], 50) == 2.5
     assert serve.percentile([5], 99) == 5
+
+
+def test_one_submission_per_advance():
+    """A burst is fed one request per advance: every request still
+    completes, the first starts after one launch, and no launch is idle."""
+    fb = FakeBatch(slots=8, K=10)
+    clock = lambda: fb.t
+    reqs = [Req(k, 0.0, 20) for k in range(4)]
+    out = serve.serve(fb, reqs, clock=clock, sleep=lambda s: None, submit_per_advance=1)
+    assert sorted(out["latency"]) == list(range(4))
+    assert out["latency"][0] == 2.0
+    assert out["latency"][3] == 5.0
+    assert out["voxel_steps"] == 80
