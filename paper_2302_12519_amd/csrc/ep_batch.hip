@@ -56,10 +56,11 @@ struct WorkItem {
   int slot, brick;
 };
 
-constexpr int kBatchGrid = 1024;   // persistent: 4 blocks per CU on 256 CUs
-
 // One explicit step of every running request's bricks (substep k of the
-// current graph launch).
+// current graph launch): one block per work item.  The grid size of the
+// captured launches is set to the work-list length whenever the list is
+// rebuilt, so the hardware keeps many bricks' dependent metadata loads
+// (work item, slot, neighbour row) in flight at once.
 __global__ __launch_bounds__(kBV) void k_batch_step(const SlotDev* __restrict__ slots,
                                                     const WorkItem* __restrict__ work,
                                                     const int* __restrict__ count, int k,
@@ -67,11 +68,13 @@ __global__ __launch_bounds__(kBV) void k_batch_step(const SlotDev* __restrict__ 
   __shared__ float s[kTile];
   __shared__ int nbs[kNbr];
   const int n = *count;
-  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+  {
+    const int i = blockIdx.x;
+    if (i >= n) return;
     const WorkItem it = work[i];
     const SlotDev* sd = slots + it.slot;
     const long long st = sd->step + k;
-    if (st >= sd->n_steps) continue;
+    if (st >= sd->n_steps) return;
     const int brick = it.brick;
     if (threadIdx.x < kNbr) nbs[threadIdx.x] = sd->nbr[brick * kNbr + threadIdx.x];
     __syncthreads();
@@ -237,6 +240,9 @@ struct ep_batch_s {
   int* h_count = nullptr;         // pinned staging of the work count
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  std::vector<hipGraphNode_t> step_nodes;  // the K k_batch_step nodes of the graph
+  int graph_blocks = 0;                    // their current grid size
+  int work_count = 0;                      // length of the current work list
   std::deque<ep_batch_request*> queue;
   std::map<int64_t, ep_batch_request*> all;
   std::vector<int64_t> slot_owner;
@@ -394,6 +400,8 @@ ep_status admit(ep_batch b, ep_batch_request* r, int slot) {
   return EP_OK;
 }
 
+ep_status set_step_grid(ep_batch b);
+
 // Work list of every running request's bricks.  Staged through pinned host
 // memory and enqueued without waiting: the previous graph launch, which
 // still reads the old list, runs first on the same stream, and the host
@@ -444,22 +452,56 @@ ep_status rebuild_work(ep_batch b) {
   if (n) BHIP(b, hipMemcpyAsync(b->d_work, b->h_work, n * sizeof(WorkItem),
                                 hipMemcpyHostToDevice, b->stream));
   BHIP(b, hipMemcpyAsync(b->d_count, b->h_count, sizeof(int), hipMemcpyHostToDevice, b->stream));
+  b->work_count = n;
   b->work_dirty = false;
+  // no launch is in flight here (the advance waited for it): resize the grid
+  if (b->exec && b->graph_blocks != std::max(1, n))
+    if (ep_status s = set_step_grid(b); s != EP_OK) return s;
+  return EP_OK;
+}
+
+// Grid of the captured step launches: one block per work item.
+ep_status set_step_grid(ep_batch b) {
+  const unsigned blocks = static_cast<unsigned>(std::max(1, b->work_count));
+  for (hipGraphNode_t node : b->step_nodes) {
+    hipKernelNodeParams kp{};
+    BHIP(b, hipGraphKernelNodeGetParams(node, &kp));
+    kp.gridDim = dim3(blocks);
+    BHIP(b, hipGraphExecKernelNodeSetParams(b->exec, node, &kp));
+  }
+  b->graph_blocks = static_cast<int>(blocks);
   return EP_OK;
 }
 
 ep_status capture(ep_batch b) {
   if (b->exec) return EP_OK;
   BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  const unsigned blocks = static_cast<unsigned>(std::max(1, b->work_count));
   for (int k = 0; k < b->K; ++k)
-    k_batch_step<<<kBatchGrid, kBV, 0, b->stream>>>(b->d_slots, b->d_work, b->d_count, k,
-                                                      b->d_flags);
+    k_batch_step<<<blocks, kBV, 0, b->stream>>>(b->d_slots, b->d_work, b->d_count, k, b->d_flags);
   k_batch_advance<<<(b->max_slots + 255) / 256, 256, 0, b->stream>>>(b->d_slots, b->max_slots,
                                                                      b->K);
   hipGraph_t gr = nullptr;
   BHIP(b, hipStreamEndCapture(b->stream, &gr));
   b->graph = gr;
   BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  b->graph_blocks = static_cast<int>(blocks);
+  // the K step-kernel nodes, for later grid updates
+  size_t nn = 0;
+  BHIP(b, hipGraphGetNodes(b->graph, nullptr, &nn));
+  std::vector<hipGraphNode_t> nodes(nn);
+  BHIP(b, hipGraphGetNodes(b->graph, nodes.data(), &nn));
+  b->step_nodes.clear();
+  for (hipGraphNode_t node : nodes) {
+    hipGraphNodeType ty;
+    BHIP(b, hipGraphNodeGetType(node, &ty));
+    if (ty != hipGraphNodeTypeKernel) continue;
+    hipKernelNodeParams kp{};
+    BHIP(b, hipGraphKernelNodeGetParams(node, &kp));
+    if (kp.func == reinterpret_cast<void*>(&k_batch_step)) b->step_nodes.push_back(node);
+  }
+  if (static_cast<int>(b->step_nodes.size()) != b->K)
+    return bfail(b, EP_ERR_HIP, "captured graph does not hold the expected step launches");
   return EP_OK;
 }
 
