@@ -119,7 +119,7 @@ template <typename T>
 void launch_cgcg(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, const T* dinv,
                  T* x, const T* r_in, T* r_out, T* p, const T* s_in, T* s_out, const T* w_in,
                  T* w_out, int kind, int init_kind, const CGScalars* cin, CGScalars* cout,
-                 const double* prev, double* parts);
+                 const double* prev, double* parts, unsigned long long* mirror, unsigned seq);
 
 // out[k] = sum of partials[k*nparts .. (k+1)*nparts) in a fixed order
 void launch_reduce_sum(hipStream_t s, const double* partials, int nparts, int K, double* out);

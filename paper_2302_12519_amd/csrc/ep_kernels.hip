@@ -349,6 +349,19 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
   block_partials<2>(acc, parts);
 }
 
+// Status word of a CG launch for the host, written with one 8-byte store to
+// coherent pinned host memory (so the host reads it whole without waiting
+// for the stream): launch number (high 32 bits), iteration count, fail, done.
+__device__ __forceinline__ void publish_status(unsigned long long* mirror, unsigned seq,
+                                               const CGScalars& st) {
+  if (!mirror) return;
+  const unsigned long long v = (static_cast<unsigned long long>(seq) << 32) |
+                               (static_cast<unsigned long long>(st.it & 0x3fffffff) << 2) |
+                               (static_cast<unsigned long long>(st.fail ? 1 : 0) << 1) |
+                               static_cast<unsigned long long>(st.done ? 1 : 0);
+  *reinterpret_cast<volatile unsigned long long*>(mirror) = v;
+}
+
 // One CG launch.  kind 0: set-up, u0 = M^-1 r0, w0 = K u0 (partials of the
 // init launch: (b.b, r.r) when init_kind == 0, or (r.r) with the tolerance
 // relative to it when init_kind == 1).  kind 1: first iteration (beta = 0,
@@ -364,10 +377,14 @@ __global__ __launch_bounds__(kBV) void k_cgcg(int nb, const int* __restrict__ nb
                                               T* __restrict__ w_out, int kind, int init_kind,
                                               const CGScalars* __restrict__ cin, CGScalars* cout,
                                               const double* __restrict__ prev, double* parts,
-                                              const uint64_t* __restrict__ rowsn) {
+                                              const uint64_t* __restrict__ rowsn,
+                                              unsigned long long* mirror, unsigned seq) {
   const CGScalars in = *cin;
   if (in.done) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *cout = in;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      *cout = in;
+      publish_status(mirror, seq, in);
+    }
     return;
   }
   CGScalars st = in;
@@ -407,7 +424,10 @@ __global__ __launch_bounds__(kBV) void k_cgcg(int nb, const int* __restrict__ nb
       }
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *cout = st;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *cout = st;
+    publish_status(mirror, seq, st);
+  }
   if (st.done) return;
   __shared__ T s[kTile];
   __shared__ int nbs[kNbr];
@@ -999,10 +1019,10 @@ template <typename T>
 void launch_cgcg(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, const T* dinv,
                  T* x, const T* r_in, T* r_out, T* p, const T* s_in, T* s_out, const T* w_in,
                  T* w_out, int kind, int init_kind, const CGScalars* cin, CGScalars* cout,
-                 const double* prev, double* parts) {
+                 const double* prev, double* parts, unsigned long long* mirror, unsigned seq) {
   k_cgcg<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, c0, c1, dinv, x, r_in, r_out, p, s_in,
                                            s_out, w_in, w_out, kind, init_kind, cin, cout, prev,
-                                           parts, L.rowsn);
+                                           parts, L.rowsn, mirror, seq);
 }
 
 void launch_reduce_sum(hipStream_t s, const double* partials, int nparts, int K, double* out) {
@@ -1114,7 +1134,8 @@ void launch_loss(const LaunchCfg& L, const uint8_t* mask, const int* cross, cons
                                   T, double, int, int*, CGScalars*, double*, double, int);     \
   template void launch_cgcg<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T, const T*, T*,   \
                                const T*, T*, T*, const T*, T*, const T*, T*, int, int,         \
-                               const CGScalars*, CGScalars*, const double*, double*);          \
+                               const CGScalars*, CGScalars*, const double*, double*,           \
+                               unsigned long long*, unsigned);                                 \
   template void launch_activation<T>(const LaunchCfg&, const T*, const T*, T*, T, T, double,   \
                                      int*);                                                    \
   template void launch_dinv<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T, T*);            \

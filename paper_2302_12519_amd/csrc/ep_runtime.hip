@@ -124,6 +124,12 @@ struct ep_grid_s {
   int64_t* d_stim_idx = nullptr;
   double* d_stim_val = nullptr;
   HostSync* hs = nullptr;      // pinned
+  // CG status word: coherent pinned host memory the CG kernels write (one
+  // 8-byte store per launch), polled by the host instead of a copy + wait
+  volatile unsigned long long* hmirror = nullptr;
+  unsigned long long* dmirror = nullptr;
+  unsigned seq = 0;            // launch number of the last CG launch issued
+  const CGScalars* last_cg = nullptr;   // device scalars of the last implicit solve
 
   // stimulus bookkeeping
   std::vector<int64_t> stim_u;                 // unique stimulated voxels (global index)
@@ -367,6 +373,37 @@ ep_status update_stimulus(ep_grid g, int64_t step, const T** jstim) {
   return EP_OK;
 }
 
+// Wait until the CG status word shows launch `seq` and return it.  Spins on
+// the coherent host word; every 1024 spins it checks the stream, and should
+// the stream drain without the word (it never should), the device copy of
+// the scalars (`dev`) is read instead.
+ep_status wait_status(ep_grid g, unsigned seq, const CGScalars* dev, unsigned long long* out) {
+  for (uint64_t spin = 1;; ++spin) {
+    const unsigned long long v = *g->hmirror;
+    if (static_cast<unsigned>(v >> 32) == seq) {
+      *out = v;
+      return EP_OK;
+    }
+    if ((spin & 1023) == 0) {
+      const hipError_t e = hipStreamQuery(g->stream);
+      if (e == hipErrorNotReady) continue;
+      if (e != hipSuccess) return fail(g, EP_ERR_HIP, std::string("CG wait: ") + hipGetErrorString(e));
+      const unsigned long long w = *g->hmirror;
+      if (static_cast<unsigned>(w >> 32) == seq) {
+        *out = w;
+        return EP_OK;
+      }
+      CGScalars c{};
+      HIPCHK(g, hipMemcpy(&c, dev, sizeof(CGScalars), hipMemcpyDeviceToHost));
+      *out = (static_cast<unsigned long long>(seq) << 32) |
+             (static_cast<unsigned long long>(c.it & 0x3fffffff) << 2) |
+             (static_cast<unsigned long long>(c.fail ? 1 : 0) << 1) |
+             static_cast<unsigned long long>(c.done ? 1 : 0);
+      return EP_OK;
+    }
+  }
+}
+
 // ---- one CG solve (device-resident scalars; host polls `done` in chunks) ----
 // One CG solve after its init launch (scalars in d_cg[0], partials in
 // d_cgp[0], r0 in r[0], x0 in x).  Launch j reads scalars / partials [j & 1]
@@ -388,25 +425,28 @@ ep_status cg_solve(ep_grid g, CoefSet<T> c, T c0, T c1, const T* dinv, T* x, T* 
     const T* rin = (j == 0) ? r[0] : r[(j + 1) & 1];
     launch_cgcg<T>(g->L, g->d_nbr, c, c0, c1, dinv, x, rin, r[j & 1], p, sv[j & 1],
                    sv[(j + 1) & 1], wv[(j + 1) & 1], wv[j & 1], kind, init_kind, cg + (j & 1),
-                   cg + ((j + 1) & 1), P[j & 1], P[(j + 1) & 1]);
+                   cg + ((j + 1) & 1), P[j & 1], P[(j + 1) & 1], g->dmirror, ++g->seq);
     timer_end(g, t0);
   };
   int j = 0;
   launch(j++);
   int chunk = std::max(1, *chunk_hint) + 1;
+  unsigned long long st = 0;
   for (;;) {
     for (int i = 0; i < chunk; ++i) launch(j++);
-    HIPCHK(g, hipMemcpyAsync(&g->hs->cg, cg + (j & 1), sizeof(CGScalars), hipMemcpyDeviceToHost,
-                             g->stream));
-    HIPCHK(g, hipStreamSynchronize(g->stream));
-    if (g->hs->cg.done || j >= maxit + 2) break;
+    // the last launch of the chunk publishes its convergence test as soon as
+    // it starts; the next launches can be queued while it still runs
+    TRY(wait_status(g, g->seq, cg + (j & 1), &st));
+    if ((st & 1) || j >= maxit + 2) break;
     chunk = std::min(4, std::max(1, maxit + 2 - j));
   }
-  *iters = g->hs->cg.it;
-  *failed = g->hs->cg.fail != 0 || !g->hs->cg.done;
-  *chunk_hint = std::max(1, g->hs->cg.it);
+  const int it = static_cast<int>((st >> 2) & 0x3fffffff);
+  *iters = it;
+  *failed = ((st >> 1) & 1) != 0 || !(st & 1);
+  *chunk_hint = std::max(1, it);
+  g->last_cg = cg + (j & 1);
   // launches 1..it did an iteration; the rest only detected convergence
-  timer_retag(g, KT_STENCIL, KT_CGTAIL, j - 1 - g->hs->cg.it);
+  timer_retag(g, KT_STENCIL, KT_CGTAIL, j - 1 - it);
   return EP_OK;
 }
 
@@ -469,7 +509,6 @@ ep_status step_be(ep_grid g, const T* jstim, ep_step_info* acc) {
                   static_cast<T*>(g->d_cp), 0, g->pcg_maxit, &g->last_iters, &iters, &failed));
   acc->cg_iters += iters;
   acc->cg_max = std::max(acc->cg_max, iters);
-  if (g->hs->cg.bb > 0) acc->relres = std::sqrt(g->hs->cg.rr / g->hs->cg.bb);
   if (failed) g->hs->flags[1] = 1;
   return EP_OK;
 }
@@ -604,7 +643,12 @@ ep_status run_steps(ep_grid g, int32_t nsteps, ep_step_info* info) {
                            g->stream));
   HIPCHK(g, hipMemcpyAsync(g->hs->flags, g->d_flags, sizeof(int), hipMemcpyDeviceToHost,
                            g->stream));
+  const bool be = g->model == EP_MONO && g->diff == EP_DIFF_BE_PCG && nsteps > 0 && g->last_cg;
+  if (be)
+    HIPCHK(g, hipMemcpyAsync(&g->hs->cg, g->last_cg, sizeof(CGScalars), hipMemcpyDeviceToHost,
+                             g->stream));
   HIPCHK(g, hipStreamSynchronize(g->stream));
+  if (be && g->hs->cg.bb > 0) acc.relres = std::sqrt(g->hs->cg.rr / g->hs->cg.bb);
   timer_collect(g);
   const double h3 = g->h * g->h * g->h;
   acc.steps = nsteps;
@@ -1015,6 +1059,13 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
     HIPCHK(g, hipHostMalloc(&p, sizeof(HostSync), hipHostMallocDefault));
     g->hs = static_cast<HostSync*>(p);
     std::memset(g->hs, 0, sizeof(HostSync));
+    void* m = nullptr;
+    HIPCHK(g, hipHostMalloc(&m, 64, hipHostMallocMapped | hipHostMallocCoherent));
+    g->hmirror = static_cast<volatile unsigned long long*>(m);
+    *g->hmirror = 0;
+    void* dm = nullptr;
+    HIPCHK(g, hipHostGetDevicePointer(&dm, m, 0));
+    g->dmirror = static_cast<unsigned long long*>(dm);
   }
   HIPCHK(g, hipMemcpyAsync(g->d_nbr, hnbr.data(), hnbr.size() * sizeof(int),
                            hipMemcpyHostToDevice, g->stream));
@@ -1407,6 +1458,7 @@ EP_API ep_status ep_destroy_grid(ep_grid g) {
       (void)hipEventDestroy(tp.b);
     }
   if (g->hs) (void)hipHostFree(g->hs);
+  if (g->hmirror) (void)hipHostFree(const_cast<unsigned long long*>(g->hmirror));
   if (g->own_stream && g->stream) (void)hipStreamDestroy(g->stream);
   delete g;
   return EP_OK;
