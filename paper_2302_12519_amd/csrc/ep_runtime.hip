@@ -428,17 +428,19 @@ ep_status cg_solve(ep_grid g, CoefSet<T> c, T c0, T c1, const T* dinv, T* x, T* 
                    cg + ((j + 1) & 1), P[j & 1], P[(j + 1) & 1], g->dmirror, ++g->seq);
     timer_end(g, t0);
   };
+  // The last launch of a chunk publishes its convergence test as soon as it
+  // starts, so while it still runs an iteration the host has already queued
+  // the next launch: the first chunk holds as many launches as the previous
+  // solve needed iterations, and every later chunk one.
   int j = 0;
   launch(j++);
-  int chunk = std::max(1, *chunk_hint) + 1;
+  int chunk = std::max(1, *chunk_hint);
   unsigned long long st = 0;
   for (;;) {
     for (int i = 0; i < chunk; ++i) launch(j++);
-    // the last launch of the chunk publishes its convergence test as soon as
-    // it starts; the next launches can be queued while it still runs
     TRY(wait_status(g, g->seq, cg + (j & 1), &st));
     if ((st & 1) || j >= maxit + 2) break;
-    chunk = std::min(4, std::max(1, maxit + 2 - j));
+    chunk = 1;
   }
   const int it = static_cast<int>((st >> 2) & 0x3fffffff);
   *iters = it;
