@@ -28,15 +28,24 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 
 # Algorithmic HBM bytes per tissue voxel for one launch of each kernel
 # (FP32 state; each array read or written once):
-#   one PCG iteration (one-reduction form, k_cgcg): reads x, r, M^-1, p, s, w
-#             (24 B) and the 6 operator weights (24 B), writes x, r, p, s, w
-#             (20 B)                                                   -> 68 B
-#   CG set-up u0 = M^-1 r0, w0 = K u0: reads r, M^-1, weights, writes w -> 36 B
+#   implicit-step init (k_be_init): reads v, w, the previous step's v, b and
+#             Q, two older increments d (28 B) and the 6 operator weights
+#             (24 B); writes x0, b, d, Q, w, r0 (24 B)                  -> 76 B
+#   PCG direction + operator (k_pcg_dir): reads r, M^-1, p (12 B) and the
+#             weights (24 B), writes p, q (8 B)                          -> 44 B
+#   PCG update (k_pcg_upd): reads x, p, q, r, M^-1 (20 B), writes x, r  -> 28 B
+#   one-reduction PCG iteration (k_cgcg, elliptic solves): reads x, r,
+#             M^-1, p, s, w (24 B) and the weights (24 B), writes x, r, p,
+#             s, w (20 B)                                               -> 68 B
 #   explicit fused step: reads v, w (8 B) + 24 B weights, writes v, w   -> 40 B
 #   adjoint step: reads lambda_v, lambda_w, v, w, v_next, crossing step (24 B),
 #             weights and unscaled tensors (48 B), mask (1 B), gradient (8 B,
 #             FP64); writes lambda_v, lambda_w (8 B) and gradient (8 B)  -> 97 B
-ALGO_BYTES = {"cg_iter": 68, "cg_setup": 36, "stencil_explicit": 40, "adjoint_step": 97}
+ALGO_BYTES = {"be_init": 76, "pcg_dir": 44, "pcg_upd": 28, "cg_iter": 68,
+              "stencil_explicit": 40, "adjoint_step": 97}
+STEP_KERNELS = {"be_init": ("k_be_init<float>", "be_init"),
+                "stencil": ("k_pcg_dir<float>", "pcg_dir"),
+                "cg_update": ("k_pcg_upd<float>", "pcg_upd")}
 
 
 def parse():
@@ -65,10 +74,11 @@ def parse():
     return ap.parse_args()
 
 
-def read_traffic(path):
-    """Per-launch HBM bytes of the SpMV from the committed counter summary
-    (line 'traffic_bytes_per_launch: X' and 'kernel_source_sha: S'); None if
-    absent or taken on another kernel version."""
+def read_traffic(path, kernel):
+    """Per-launch HBM bytes of `kernel` from the committed counter summary
+    (lines 'kernel: K', 'traffic_bytes_per_launch: X' and
+    'kernel_source_sha: S'); None if absent, taken on another kernel, or on
+    another version of the kernel source."""
     if not os.path.exists(path):
         return None
     vals = {}
@@ -80,6 +90,8 @@ def read_traffic(path):
         import hashlib
         src = open(os.path.join(ROOT, "paper_2302_12519_amd", "csrc", "ep_kernels.hip"), "rb").read()
         if vals.get("kernel_source_sha") != hashlib.sha256(src).hexdigest()[:16]:
+            return None
+        if vals.get("kernel") != kernel:
             return None
         return float(vals["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -290,16 +302,17 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
-    it_ms, it_n = g.kernel_time("stencil")
-    set_ms, set_n = g.kernel_time("cg_setup")
-    tail_ms, tail_n = g.kernel_time("cg_tail")
-    init_ms, init_n = g.kernel_time("be_init")
+    times = {k: g.kernel_time(k) for k in ("be_init", "stencil", "cg_update", "cg_tail")}
     g.kernel_timing(False)
 
     value = inst.nt * a.steps / elapsed
-    avg_it = it_ms / max(it_n, 1)
-    achieved = ALGO_BYTES["cg_iter"] * inst.nt / (avg_it * 1e-3) / 1e9
-    traffic = read_traffic(a.traffic_file)
+    # the dominant kernel: the largest share of the step's kernel time
+    dom = max(STEP_KERNELS, key=lambda k: times[k][0])
+    dom_name, dom_bytes = STEP_KERNELS[dom]
+    dom_ms, dom_n = times[dom]
+    avg_it = dom_ms / max(dom_n, 1)
+    achieved = ALGO_BYTES[dom_bytes] * inst.nt / (avg_it * 1e-3) / 1e9
+    traffic = read_traffic(a.traffic_file, dom_name)
     out = {
         "metric": "voxel-steps/s",
         "value": value,
@@ -317,17 +330,22 @@ def main():
                                f"({inst.nt} tissue voxels), 19-point anisotropic stencil, "
                                f"implicit Euler by Jacobi-PCG rtol {a.rtol:g}, dt {inst.dt} ms",
                    "n_tissue": inst.nt, "grid": list(inst.n), "dt_ms": inst.dt},
-        "roofline": {"bound": "hbm", "kernel": "k_cgcg<float> (one PCG iteration)",
+        "roofline": {"bound": "hbm", "kernel": dom_name,
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algo_bytes_per_launch": ALGO_BYTES["cg_iter"] * inst.nt,
-                     "avg_launch_us": 1e3 * avg_it, "launches": it_n},
+                     "algo_bytes_per_launch": ALGO_BYTES[dom_bytes] * inst.nt,
+                     "avg_launch_us": 1e3 * avg_it, "launches": dom_n},
         "cg": {"iters_total": info["cg_iters"], "iters_per_step": info["cg_iters"] / a.steps,
                "iters_max": info["cg_max"],
-               "setup_avg_us": 1e3 * set_ms / max(set_n, 1),
-               "tail_avg_us": 1e3 * tail_ms / max(tail_n, 1), "tail_launches": tail_n,
-               "init_avg_us": 1e3 * init_ms / max(init_n, 1),
-               "kernel_ms_per_step": (it_ms + set_ms + tail_ms + init_ms) / a.steps},
+               "kernels": {STEP_KERNELS[k][0]: {
+                   "avg_us": 1e3 * times[k][0] / max(times[k][1], 1),
+                   "launches": times[k][1], "ms_per_step": times[k][0] / a.steps,
+                   "achieved_gbs": ALGO_BYTES[STEP_KERNELS[k][1]] * inst.nt
+                   / max(1e-3 * times[k][0] / max(times[k][1], 1), 1e-12) / 1e9}
+                   for k in STEP_KERNELS},
+               "tail_avg_us": 1e3 * times["cg_tail"][0] / max(times["cg_tail"][1], 1),
+               "tail_launches": times["cg_tail"][1],
+               "kernel_ms_per_step": sum(t[0] for t in times.values()) / a.steps},
     }
     g.close()
     if a.serving:

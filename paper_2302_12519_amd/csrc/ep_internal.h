@@ -69,6 +69,7 @@ struct LaunchCfg {
   int nb;       // active bricks
   int grid;     // blocks of a one-brick-per-block launch (multiple of kXcd, >= nb)
   int pgrid;    // blocks of a persistent launch (multiple of kXcd, <= grid)
+  int ugrid;    // blocks of the persistent streaming PCG update (multiple of kXcd, <= grid)
   hipStream_t stream;
   const uint64_t* rowsn;   // (nb+1)*27 row masks of each brick's neighbourhood
 };
@@ -79,6 +80,11 @@ inline int grid_for(int nb) { return ((nb + kXcd - 1) / kXcd) * kXcd; }
 inline int pgrid_for(int nb, bool /*fp64*/) {
   const int g = grid_for(nb);
   return g < 512 ? g : 512;
+}
+// the pointwise PCG update needs few registers: 4 blocks per CU
+inline int ugrid_for(int nb) {
+  const int g = grid_for(nb);
+  return g < 1024 ? g : 1024;
 }
 
 // ---- kernel launchers (ep_kernels.hip) ----------------------------------
@@ -120,6 +126,20 @@ void launch_cgcg(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, c
                  T* x, const T* r_in, T* r_out, T* p, const T* s_in, T* s_out, const T* w_in,
                  T* w_out, int kind, int init_kind, const CGScalars* cin, CGScalars* cout,
                  const double* prev, double* parts, unsigned long long* mirror, unsigned seq);
+
+// Two-launch PCG (textbook recurrences): direction + operator launch
+// (L.pgrid blocks; the launch before it left nprev partials per component),
+// then the x / r update (L.ugrid blocks).  Each tests the scalars of the
+// launch before it.
+template <typename T>
+void launch_pcg_dir(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, const T* dinv,
+                    const T* r, const T* p_in, T* p_out, T* q, int first, const CGScalars* cin,
+                    CGScalars* cout, const double* prev, int nprev, double* parts,
+                    unsigned long long* mirror, unsigned seq);
+template <typename T>
+void launch_pcg_upd(const LaunchCfg& L, const T* dinv, T* x, T* r, const T* p, const T* q,
+                    const CGScalars* cin, CGScalars* cout, const double* prev, double* parts,
+                    unsigned long long* mirror, unsigned seq);   // L.ugrid blocks
 
 // out[k] = sum of partials[k*nparts .. (k+1)*nparts) in a fixed order
 void launch_reduce_sum(hipStream_t s, const double* partials, int nparts, int K, double* out);

@@ -27,8 +27,9 @@
 //   k_explicit, k_ionic: Mitchell-Schaeffer reaction by explicit Euler
 //     (eqn:ms1, eqn:ms2; Reaction subsection) fused with explicit diffusion;
 //     activation time at the first threshold crossing.
-//   k_be_init, k_cgcg: implicit-Euler diffusion step (Linear Solver section,
-//     "Implicit Euler") solved by Jacobi-preconditioned CG.
+//   k_be_init, k_pcg_dir, k_pcg_upd: implicit-Euler diffusion step (Linear
+//     Solver section, "Implicit Euler") solved by Jacobi-preconditioned CG;
+//     k_cgcg: the same CG in one-reduction form for the elliptic solves.
 //   k_resid64, k_inner_init, k_phi_correct, k_phi_shift, k_parabolic: the
 //     bidomain step (eqn:bidomain1): elliptic solve for phi_e by FP32 PCG
 //     inside FP64 refinement, then the parabolic update.
@@ -53,6 +54,32 @@ __device__ __forceinline__ int pbrick(int m, int nb) {
   const int b = x * per + j + m * gper;
   return (b < (x + 1) * per && b < nb) ? b : -1;
 }
+
+// Neighbour row and row masks of a persistent block's next brick, loaded into
+// registers of threads < 27 one brick ahead.  The loads for brick m+1 are
+// issued as brick m starts and written to the other half of a double-buffered
+// LDS table once brick m's own loads have landed (so no wait is added), before
+// brick m's second barrier; brick m+1's data loads then follow its first
+// barrier directly instead of waiting for a table load.
+struct NbrAhead {
+  int nbv = 0;
+  uint64_t rmv = 0;
+  __device__ __forceinline__ void fetch(const int* __restrict__ nbr,
+                                        const uint64_t* __restrict__ rowsn, int brick) {
+    // Unconditional and always in bounds (the tables hold at least the ghost
+    // brick's row): a load under a branch would make the compiler wait for
+    // every outstanding store before reissuing it.
+    const int i = (brick < 0 ? 0 : brick) * kNbr + (threadIdx.x < kNbr ? threadIdx.x : 0);
+    nbv = nbr[i];
+    rmv = rowsn[i];
+  }
+  __device__ __forceinline__ void stage(int* nbs, uint64_t* rowm) const {
+    if (threadIdx.x < kNbr) {
+      nbs[threadIdx.x] = nbv;
+      rowm[threadIdx.x] = rmv;
+    }
+  }
+};
 
 // Sum the K partial sums the previous launch left (n per component) in a
 // fixed order.  Every block computes the identical totals, so no block has
@@ -281,8 +308,8 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
                                                  double tol2, int maxit,
                                                  const uint64_t* __restrict__ rowsn) {
   __shared__ T s[kTile];
-  __shared__ int nbs[kNbr];
-  __shared__ uint64_t rowm[kNbr];
+  __shared__ int nbt[2][kNbr];
+  __shared__ uint64_t rowt[2][kNbr];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     CGScalars st = {};
     st.tol2 = tol2;
@@ -290,13 +317,16 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
     *cout = st;
   }
   double acc[2] = {0.0, 0.0};
-  for (int m = 0;; ++m) {
-    const int brick = pbrick(m, nb);
-    if (brick < 0) break;
-    if (threadIdx.x < kNbr) {
-      nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
-      rowm[threadIdx.x] = rowsn[brick * kNbr + threadIdx.x];
-    }
+  NbrAhead ahead;
+  int nxt = pbrick(0, nb);
+  ahead.fetch(nbr, rowsn, nxt);
+  ahead.stage(nbt[0], rowt[0]);
+  for (int m = 0; nxt >= 0; ++m) {
+    const int brick = nxt;
+    const int* nbs = nbt[m & 1];
+    const uint64_t* rowm = rowt[m & 1];
+    nxt = pbrick(m + 1, nb);
+    ahead.fetch(nbr, rowsn, nxt);
     __syncthreads();
     const Cell q = cell_setup(nbs, brick, rowm, nb);
     const T v0 = v[q.gl], w0 = w[q.gl];
@@ -326,6 +356,7 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
       ms_step(hv, hw, hj, ion, dt, a, b);
       s[q.hC] = bprev ? a + (kd * (hv - hb1) + hq) : a;
     }
+    ahead.stage(nbt[(m + 1) & 1], rowt[(m + 1) & 1]);
     __syncthreads();
     const T rr = (vs - x0) + dt * apply19(s, q.C, k18);
     if (check_prev && vp < theta && theta <= v0) {
@@ -430,17 +461,20 @@ __global__ __launch_bounds__(kBV) void k_cgcg(int nb, const int* __restrict__ nb
   }
   if (st.done) return;
   __shared__ T s[kTile];
-  __shared__ int nbs[kNbr];
-  __shared__ uint64_t rowm[kNbr];
+  __shared__ int nbt[2][kNbr];
+  __shared__ uint64_t rowt[2][kNbr];
   const T alpha = static_cast<T>(st.alpha), beta = static_cast<T>(st.beta);
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int m = 0;; ++m) {
-    const int brick = pbrick(m, nb);
-    if (brick < 0) break;
-    if (threadIdx.x < kNbr) {
-      nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
-      rowm[threadIdx.x] = rowsn[brick * kNbr + threadIdx.x];
-    }
+  NbrAhead ahead;
+  int nxt = pbrick(0, nb);
+  ahead.fetch(nbr, rowsn, nxt);
+  ahead.stage(nbt[0], rowt[0]);
+  for (int m = 0; nxt >= 0; ++m) {
+    const int brick = nxt;
+    const int* nbs = nbt[m & 1];
+    const uint64_t* rowm = rowt[m & 1];
+    nxt = pbrick(m + 1, nb);
+    ahead.fetch(nbr, rowsn, nxt);
     __syncthreads();
     const Cell e = cell_setup(nbs, brick, rowm, nb);
     T rn, un;
@@ -457,6 +491,7 @@ __global__ __launch_bounds__(kBV) void k_cgcg(int nb, const int* __restrict__ nb
       un = dg * rg;
       s[e.C] = un;
       if (e.has_halo) s[e.hC] = hd * hr;
+      ahead.stage(nbt[(m + 1) & 1], rowt[(m + 1) & 1]);
       __syncthreads();
       const T wv = c0 * un + c1 * apply19(s, e.C, k18);
       if (e.live) w_out[e.g] = wv;
@@ -483,6 +518,7 @@ __global__ __launch_bounds__(kBV) void k_cgcg(int nb, const int* __restrict__ nb
       un = dg * rn;
       s[e.C] = un;
       if (e.has_halo) s[e.hC] = hd * (hr - alpha * (hw + beta * hs));
+      ahead.stage(nbt[(m + 1) & 1], rowt[(m + 1) & 1]);
       __syncthreads();
       const T wv = c0 * un + c1 * apply19(s, e.C, k18);
       if (e.live) {
@@ -498,6 +534,180 @@ __global__ __launch_bounds__(kBV) void k_cgcg(int nb, const int* __restrict__ nb
     }
   }
   block_partials<3>(acc, parts);
+}
+
+// Jacobi-PCG in its textbook two-recurrence form, two launches per
+// iteration.  Used for the implicit-Euler step, whose extrapolated guess
+// leaves one or two iterations to do: this form needs one operator apply per
+// iteration, where the one-reduction form above also needs a set-up apply
+// (w0 = K u0) per solve.  K = c0 I + c1 A, z = M^-1 r.
+//
+// k_pcg_dir, launch k: p_k = z_k + beta_k p_{k-1} (beta_0 = 0, no p_{-1}
+// read), q_k = K p_k.  It first tests the residual of the launch before
+// (the init launch's (b.b, r.r) for k = 0, else the update's (gamma, rho);
+// nprev partials per component).
+// Partials: (delta, gamma) = ((p_k, q_k), (r_k, z_k)).  p_{k-1} is read at
+// the halo, so p_k goes to the other buffer of a pair.
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_pcg_dir(int nb, const int* __restrict__ nbr,
+                                                 CoefSet<T> c, T c0, T c1,
+                                                 const T* __restrict__ dinv,
+                                                 const T* __restrict__ r,
+                                                 const T* __restrict__ p_in,
+                                                 T* __restrict__ p_out, T* __restrict__ q,
+                                                 int first, const CGScalars* __restrict__ cin,
+                                                 CGScalars* cout, const double* __restrict__ prev,
+                                                 int nprev, double* parts,
+                                                 const uint64_t* __restrict__ rowsn,
+                                                 unsigned long long* mirror, unsigned seq) {
+  const CGScalars in = *cin;
+  if (in.done) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      *cout = in;
+      publish_status(mirror, seq, in);
+    }
+    return;
+  }
+  CGScalars st = in;
+  {
+    double S[2];
+    sum_prev<2>(prev, nprev, S);
+    if (first) {
+      st.bb = S[0];
+      st.rr = S[1];
+      st.it = 0;
+      st.fail = 0;
+      st.beta = 0.0;
+      st.done = (S[0] == 0.0 || S[1] <= in.tol2 * S[0]) ? 1 : 0;
+    } else {
+      const double gam = S[0], rho = S[1];
+      st.rr = rho;
+      st.it = in.it + 1;
+      if (!isfinite(rho) || !isfinite(gam)) { st.done = 1; st.fail = 1; }
+      else if (rho <= in.tol2 * in.bb) st.done = 1;
+      else if (st.it >= in.maxit) { st.done = 1; st.fail = 1; }
+      else if (!(in.rz > 0.0)) { st.done = 1; st.fail = 1; }
+      else {
+        st.beta = gam / in.rz;
+        st.rz = gam;
+      }
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *cout = st;
+    publish_status(mirror, seq, st);
+  }
+  if (st.done) return;
+  __shared__ T s[kTile];
+  __shared__ int nbt[2][kNbr];
+  __shared__ uint64_t rowt[2][kNbr];
+  const T beta = static_cast<T>(st.beta);
+  double acc[2] = {0.0, 0.0};
+  NbrAhead ahead;
+  int nxt = pbrick(0, nb);
+  ahead.fetch(nbr, rowsn, nxt);
+  ahead.stage(nbt[0], rowt[0]);
+  for (int m = 0; nxt >= 0; ++m) {
+    const int brick = nxt;
+    const int* nbs = nbt[m & 1];
+    const uint64_t* rowm = rowt[m & 1];
+    nxt = pbrick(m + 1, nb);
+    ahead.fetch(nbr, rowsn, nxt);
+    __syncthreads();
+    const Cell e = cell_setup(nbs, brick, rowm, nb);
+    const T rg = r[e.gl], dg = dinv[e.gl];
+    const T pg = first ? T(0) : p_in[e.gl];
+    T hr = T(0), hd = T(0), hp = T(0);
+    if (e.has_halo) {
+      hr = r[e.hgl];
+      hd = dinv[e.hgl];
+      hp = first ? T(0) : p_in[e.hgl];
+    }
+    T k18[18];
+    gather18(c, nbs, brick, e.lx, e.ly, e.lz, k18, rowm, nb);
+    const T zg = dg * rg;
+    const T pn = zg + beta * pg;
+    s[e.C] = pn;
+    if (e.has_halo) s[e.hC] = hd * hr + beta * hp;
+    ahead.stage(nbt[(m + 1) & 1], rowt[(m + 1) & 1]);
+    __syncthreads();
+    const T qv = c0 * pn + c1 * apply19(s, e.C, k18);
+    if (e.live) {
+      p_out[e.g] = pn;
+      q[e.g] = qv;
+    }
+    acc[0] += static_cast<double>(pn) * static_cast<double>(qv);
+    acc[1] += static_cast<double>(rg) * static_cast<double>(zg);
+  }
+  block_partials<2>(acc, parts);
+}
+
+// k_pcg_upd, launch k: alpha_k = gamma_k / delta_k from the direction
+// launch's partials; x += alpha p_k, r -= alpha q_k, in place (no halo).
+// Partials: (gamma_{k+1}, rho_{k+1}) = ((r, z), (r, r)).  Voxels of rows
+// without tissue are neither loaded (their loads read the ghost brick) nor
+// stored; the own brick's row mask is fetched one brick ahead.  Launched
+// on more blocks than the stencil kernels (it needs few registers), so its
+// partials count differs from theirs (nprev of the next direction launch).
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_pcg_upd(int nb, const T* __restrict__ dinv,
+                                                 T* __restrict__ x, T* __restrict__ r,
+                                                 const T* __restrict__ p,
+                                                 const T* __restrict__ q,
+                                                 const CGScalars* __restrict__ cin,
+                                                 CGScalars* cout, const double* __restrict__ prev,
+                                                 int nprev, double* parts,
+                                                 const uint64_t* __restrict__ rowsn,
+                                                 unsigned long long* mirror, unsigned seq) {
+  const CGScalars in = *cin;
+  if (in.done) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      *cout = in;
+      publish_status(mirror, seq, in);
+    }
+    return;
+  }
+  CGScalars st = in;
+  {
+    double S[2];
+    sum_prev<2>(prev, nprev, S);
+    const double del = S[0], gam = S[1];
+    if (!(del > 0.0) || !isfinite(del) || !isfinite(gam)) { st.done = 1; st.fail = 1; }
+    else {
+      st.alpha = gam / del;
+      st.rz = gam;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *cout = st;
+    publish_status(mirror, seq, st);
+  }
+  if (st.done) return;
+  const T alpha = static_cast<T>(st.alpha);
+  const int t = threadIdx.x;
+  const int bit = t >> 3;   // row (lx, ly) of voxel t: bit lx*8 + ly
+  double acc[2] = {0.0, 0.0};
+  int nxt = pbrick(0, nb);
+  uint64_t rm_next = rowsn[(nxt < 0 ? 0 : nxt) * kNbr + 13];
+  for (int m = 0; nxt >= 0; ++m) {
+    const int brick = nxt;
+    const uint64_t rm = rm_next;
+    nxt = pbrick(m + 1, nb);
+    rm_next = rowsn[(nxt < 0 ? 0 : nxt) * kNbr + 13];
+    const bool live = (rm >> bit) & 1;
+    const int g = brick * kBV + t;
+    const int gl = live ? g : nb * kBV + t;
+    const T xg = x[gl], pg = p[gl], qg = q[gl], rg = r[gl], dg = dinv[gl];
+    const T rn = rg - alpha * qg;
+    if (live) {
+      x[g] = xg + alpha * pg;
+      r[g] = rn;
+    }
+    const double rd = static_cast<double>(rn);
+    acc[0] += rd * static_cast<double>(dg * rn);
+    acc[1] += rd * rd;
+  }
+  block_partials<2>(acc, parts);
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict__ partials,
@@ -1025,6 +1235,24 @@ void launch_cgcg(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, c
                                            parts, L.rowsn, mirror, seq);
 }
 
+template <typename T>
+void launch_pcg_dir(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, const T* dinv,
+                    const T* r, const T* p_in, T* p_out, T* q, int first, const CGScalars* cin,
+                    CGScalars* cout, const double* prev, int nprev, double* parts,
+                    unsigned long long* mirror, unsigned seq) {
+  k_pcg_dir<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, c0, c1, dinv, r, p_in, p_out, q,
+                                              first, cin, cout, prev, nprev, parts, L.rowsn,
+                                              mirror, seq);
+}
+
+template <typename T>
+void launch_pcg_upd(const LaunchCfg& L, const T* dinv, T* x, T* r, const T* p, const T* q,
+                    const CGScalars* cin, CGScalars* cout, const double* prev, double* parts,
+                    unsigned long long* mirror, unsigned seq) {
+  k_pcg_upd<T><<<L.ugrid, kBV, 0, L.stream>>>(L.nb, dinv, x, r, p, q, cin, cout, prev, L.pgrid,
+                                              parts, L.rowsn, mirror, seq);
+}
+
 void launch_reduce_sum(hipStream_t s, const double* partials, int nparts, int K, double* out) {
   k_reduce<<<1, kRedThreads, 0, s>>>(partials, nparts, K, out);
 }
@@ -1136,6 +1364,13 @@ void launch_loss(const LaunchCfg& L, const uint8_t* mask, const int* cross, cons
                                const T*, T*, T*, const T*, T*, const T*, T*, int, int,         \
                                const CGScalars*, CGScalars*, const double*, double*,           \
                                unsigned long long*, unsigned);                                 \
+  template void launch_pcg_dir<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T, const T*,   \
+                                  const T*, const T*, T*, T*, int, const CGScalars*,           \
+                                  CGScalars*, const double*, int, double*,                     \
+                                  unsigned long long*, unsigned);                              \
+  template void launch_pcg_upd<T>(const LaunchCfg&, const T*, T*, T*, const T*, const T*,      \
+                                  const CGScalars*, CGScalars*, const double*, double*,        \
+                                  unsigned long long*, unsigned);                              \
   template void launch_activation<T>(const LaunchCfg&, const T*, const T*, T*, T, T, double,   \
                                      int*);                                                    \
   template void launch_dinv<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T, T*);            \

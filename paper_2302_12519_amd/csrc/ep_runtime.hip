@@ -50,7 +50,7 @@ constexpr int kPredOrder = 4;
 constexpr int kDRing = 3;
 
 enum { KT_STENCIL = 0, KT_CGSETUP = 1, KT_PARABOLIC = 2, KT_RESID = 3, KT_CGTAIL = 4,
-       KT_ADJ = 5, KT_INIT = 6, kTimers = 7 };
+       KT_ADJ = 5, KT_INIT = 6, KT_UPDATE = 7, kTimers = 8 };
 
 }  // namespace
 
@@ -149,7 +149,6 @@ struct ep_grid_s {
   int bsel = 0;
   bool has_cond = false;
   bool nonfinite = false;
-  int last_iters = 4;
   int last_inner = 50;
   std::string err;
 
@@ -452,6 +451,58 @@ ep_status cg_solve(ep_grid g, CoefSet<T> c, T c0, T c1, const T* dinv, T* x, T* 
   return EP_OK;
 }
 
+// Two-launch PCG solve after its init launch (scalars in d_cg[0], the init's
+// (b.b, r.r) partials in d_cgp[0], r0 in r, x0 in x).  Launches alternate
+// direction (even j) and update (odd j); launch j reads scalars / partials
+// [j & 1] and writes [(j + 1) & 1].  Direction k writes p_k to pv[k & 1] and
+// reads p_{k-1} from pv[(k + 1) & 1].  The host queues one iteration (update,
+// direction) at a time: a direction launch publishes the convergence test of
+// the update before it as it starts, so the next pair is queued while it
+// still runs its stencil, and at most one launch per solve only finds the
+// solve done.
+template <typename T>
+ep_status pcg_split_solve(ep_grid g, CoefSet<T> c, T c0, T c1, const T* dinv, T* x, T* r,
+                          T* const pv[2], T* q, int maxit, int* iters, bool* failed) {
+  CGScalars* cg = g->d_cg;
+  double* const* P = g->d_cgp;
+  int ndir = 0, nupd = 0;
+  auto dir = [&](int j) {
+    const int k = j >> 1;
+    TimerPair* t0 = timer_begin(g, KT_STENCIL);
+    launch_pcg_dir<T>(g->L, g->d_nbr, c, c0, c1, dinv, r, pv[(k + 1) & 1], pv[k & 1], q,
+                      k == 0 ? 1 : 0, cg + (j & 1), cg + ((j + 1) & 1), P[j & 1],
+                      k == 0 ? g->L.pgrid : g->L.ugrid, P[(j + 1) & 1], g->dmirror, ++g->seq);
+    timer_end(g, t0);
+    ++ndir;
+  };
+  auto upd = [&](int j) {
+    const int k = j >> 1;
+    TimerPair* t0 = timer_begin(g, KT_UPDATE);
+    launch_pcg_upd<T>(g->L, dinv, x, r, pv[k & 1], q, cg + (j & 1), cg + ((j + 1) & 1),
+                      P[j & 1], P[(j + 1) & 1], g->dmirror, ++g->seq);
+    timer_end(g, t0);
+    ++nupd;
+  };
+  int j = 0;
+  dir(j++);
+  unsigned long long st = 0;
+  for (;;) {
+    upd(j++);
+    dir(j++);
+    TRY(wait_status(g, g->seq, cg + (j & 1), &st));
+    if ((st & 1) || j >= 2 * maxit + 3) break;
+  }
+  const int it = static_cast<int>((st >> 2) & 0x3fffffff);
+  *iters = it;
+  *failed = ((st >> 1) & 1) != 0 || !(st & 1);
+  g->last_cg = cg + (j & 1);
+  // directions 0..it-1 and updates 0..it-1 did work; the rest found the
+  // solve done
+  timer_retag(g, KT_STENCIL, KT_CGTAIL, ndir - it);
+  timer_retag(g, KT_UPDATE, KT_CGTAIL, nupd - it);
+  return EP_OK;
+}
+
 // ---- step drivers -----------------------------------------------------------
 template <typename T>
 ep_status step_explicit(ep_grid g, const T* jstim) {
@@ -507,8 +558,8 @@ ep_status step_be(ep_grid g, const T* jstim, ep_step_info* acc) {
   timer_end(g, ti);
   int iters = 0;
   bool failed = false;
-  TRY(cg_solve<T>(g, coefs<T>(g), T(1), static_cast<T>(-g->dt), dinv, x, r, sv, wv,
-                  static_cast<T*>(g->d_cp), 0, g->pcg_maxit, &g->last_iters, &iters, &failed));
+  TRY(pcg_split_solve<T>(g, coefs<T>(g), T(1), static_cast<T>(-g->dt), dinv, x, r[0], sv,
+                         wv[0], g->pcg_maxit, &iters, &failed));
   acc->cg_iters += iters;
   acc->cg_max = std::max(acc->cg_max, iters);
   if (failed) g->hs->flags[1] = 1;
@@ -994,6 +1045,7 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   g->L.nb = nb;
   g->L.grid = g->grid;
   g->L.pgrid = pgrid_for(nb, g->prec == EP_F64);
+  g->L.ugrid = ugrid_for(nb);
   g->L.stream = g->stream;
   if (g->model == EP_BIDO && tissue_components(boxmask, g->n) != 1)
     return fail(g, EP_ERR_ARG, "bidomain tissue must be one face-connected component");
@@ -1016,7 +1068,8 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   TRY(dalloc(g, &g->d_partials, static_cast<size_t>(g->grid) * 4 * sizeof(double)));
   TRY(dalloc(g, &g->d_cg, 2 * sizeof(CGScalars)));
   for (int k = 0; k < 2; ++k)
-    TRY(dalloc(g, &g->d_cgp[k], static_cast<size_t>(g->L.pgrid) * 3 * sizeof(double)));
+    TRY(dalloc(g, &g->d_cgp[k], static_cast<size_t>(std::max(g->L.pgrid, g->L.ugrid)) * 3 *
+                                   sizeof(double)));
   TRY(dalloc(g, &g->d_flags, 4 * sizeof(int)));
   TRY(dalloc(g, &g->d_sums, 8 * sizeof(double)));
   TRY(dalloc(g, &g->d_qacc, sizeof(double)));
