@@ -207,15 +207,20 @@ EP_API ep_status ep_set_step(ep_grid g, int64_t step);
 EP_API ep_status ep_grid_stats(ep_grid g, int64_t* n_tissue, int64_t* n_bricks,
                                int64_t* device_bytes);
 
-/* Kernel timing for measurement: when enabled, the library records HIP
- * events around every launch of the timed kernels on the grid's stream;
+/* Kernel timing for measurement: `enable` is a bit mask of kernel ids
+ * (bit k times kernel id k; -1 times all, 0 none).  The library records HIP
+ * events on the grid's stream around every launch of the selected kernels;
  * ep_kernel_time returns the summed milliseconds and the launch count since
- * the last enable.  kernel_id 0: the fused explicit step, or one full
- * implicit-Euler / inner PCG iteration (the dominant kernel); 1: the CG
- * set-up launch; 2: the bidomain parabolic stencil; 3: the FP64 elliptic
- * residual; 4: CG launches that only detected convergence; 5: the adjoint
- * step of ep_adjoint_scale (its forward and recompute launches count as 0);
- * 6: the reaction + initial-residual launch of an implicit-Euler step. */
+ * the last ep_kernel_timing call.  Events between launches cost time, so
+ * timing only the kernel of interest disturbs a run least.  kernel_id 0: the
+ * fused explicit step, the direction + operator launch of the implicit-Euler
+ * PCG, or one one-reduction PCG iteration of the elliptic solve; 1: the
+ * one-reduction PCG set-up launch; 2: the bidomain parabolic stencil; 3: the
+ * FP64 elliptic residual; 4: PCG launches that only found the solve done
+ * (recorded under a timed id 0 or 7 and moved here); 5: the adjoint step of
+ * ep_adjoint_scale (its forward and recompute launches count as 0); 6: the
+ * reaction + initial-residual launch of an implicit-Euler step; 7: the x / r
+ * update launch of the implicit-Euler PCG. */
 EP_API ep_status ep_kernel_timing(ep_grid g, int32_t enable);
 EP_API ep_status ep_kernel_time(ep_grid g, int32_t kernel_id, double* total_ms,
                                 int64_t* launches);

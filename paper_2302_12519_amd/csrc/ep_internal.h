@@ -81,10 +81,14 @@ inline int pgrid_for(int nb, bool /*fp64*/) {
   const int g = grid_for(nb);
   return g < 512 ? g : 512;
 }
-// the pointwise PCG update needs few registers: 4 blocks per CU
+// the pointwise PCG update: a block covers kUpdBricks bricks at a time, and
+// the launch has one block per kUpdBricks bricks up to 4096 blocks (then it
+// loops)
+constexpr int kUpdBricks = 4;
 inline int ugrid_for(int nb) {
-  const int g = grid_for(nb);
-  return g < 1024 ? g : 1024;
+  const int b = (nb + kUpdBricks - 1) / kUpdBricks;
+  const int g = ((b + kXcd - 1) / kXcd) * kXcd;
+  return g < 4096 ? g : 4096;
 }
 
 // ---- kernel launchers (ep_kernels.hip) ----------------------------------

@@ -642,13 +642,21 @@ __global__ __launch_bounds__(kBV) void k_pcg_dir(int nb, const int* __restrict__
   block_partials<2>(acc, parts);
 }
 
+// Four consecutive voxels of a brick row (16 B in FP32), loaded and stored
+// as one vector access.
+template <typename T> struct Quad;
+template <> struct Quad<float> { using V = float4; };
+template <> struct Quad<double> { using V = double4; };
+
 // k_pcg_upd, launch k: alpha_k = gamma_k / delta_k from the direction
 // launch's partials; x += alpha p_k, r -= alpha q_k, in place (no halo).
-// Partials: (gamma_{k+1}, rho_{k+1}) = ((r, z), (r, r)).  Voxels of rows
+// Partials: (gamma_{k+1}, rho_{k+1}) = ((r, z), (r, r)).  Each thread takes
+// half a brick row (4 voxels, vector loads), so a 512-thread block covers 4
+// bricks at a time (slot = thread / 128); the launch has about one block per
+// 4 bricks (kUpdBricks), left to the hardware to balance.  Voxels of rows
 // without tissue are neither loaded (their loads read the ghost brick) nor
-// stored; the own brick's row mask is fetched one brick ahead.  Launched
-// on more blocks than the stencil kernels (it needs few registers), so its
-// partials count differs from theirs (nprev of the next direction launch).
+// stored.  Its partials count (gridDim.x) differs from the stencil kernels'
+// (nprev of the next direction launch).
 template <typename T>
 __global__ __launch_bounds__(kBV) void k_pcg_upd(int nb, const T* __restrict__ dinv,
                                                  T* __restrict__ x, T* __restrict__ r,
@@ -659,6 +667,7 @@ __global__ __launch_bounds__(kBV) void k_pcg_upd(int nb, const T* __restrict__ d
                                                  int nprev, double* parts,
                                                  const uint64_t* __restrict__ rowsn,
                                                  unsigned long long* mirror, unsigned seq) {
+  using V = typename Quad<T>::V;
   const CGScalars in = *cin;
   if (in.done) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -684,28 +693,38 @@ __global__ __launch_bounds__(kBV) void k_pcg_upd(int nb, const T* __restrict__ d
   }
   if (st.done) return;
   const T alpha = static_cast<T>(st.alpha);
-  const int t = threadIdx.x;
-  const int bit = t >> 3;   // row (lx, ly) of voxel t: bit lx*8 + ly
+  const int slot = threadIdx.x >> 7;              // brick slot 0..3
+  const int e = (threadIdx.x & 127) * 4;          // first of the thread's 4 voxels
+  const int bit = e >> 3;                         // its row lx*8 + ly
   double acc[2] = {0.0, 0.0};
-  int nxt = pbrick(0, nb);
-  uint64_t rm_next = rowsn[(nxt < 0 ? 0 : nxt) * kNbr + 13];
-  for (int m = 0; nxt >= 0; ++m) {
-    const int brick = nxt;
-    const uint64_t rm = rm_next;
-    nxt = pbrick(m + 1, nb);
-    rm_next = rowsn[(nxt < 0 ? 0 : nxt) * kNbr + 13];
-    const bool live = (rm >> bit) & 1;
-    const int g = brick * kBV + t;
-    const int gl = live ? g : nb * kBV + t;
-    const T xg = x[gl], pg = p[gl], qg = q[gl], rg = r[gl], dg = dinv[gl];
-    const T rn = rg - alpha * qg;
+  for (int m = slot;; m += kUpdBricks) {
+    const int brick = pbrick(m, nb);
+    if (brick < 0) break;
+    const bool live = (rowsn[brick * kNbr + 13] >> bit) & 1;
+    const int g = brick * kBV + e;
+    const int gl = live ? g : nb * kBV + e;
+    const V xv = *reinterpret_cast<const V*>(x + gl);
+    const V pv = *reinterpret_cast<const V*>(p + gl);
+    const V qv = *reinterpret_cast<const V*>(q + gl);
+    const V rv = *reinterpret_cast<const V*>(r + gl);
+    const V dv = *reinterpret_cast<const V*>(dinv + gl);
+    V xn, rn;
+    xn.x = xv.x + alpha * pv.x;
+    xn.y = xv.y + alpha * pv.y;
+    xn.z = xv.z + alpha * pv.z;
+    xn.w = xv.w + alpha * pv.w;
+    rn.x = rv.x - alpha * qv.x;
+    rn.y = rv.y - alpha * qv.y;
+    rn.z = rv.z - alpha * qv.z;
+    rn.w = rv.w - alpha * qv.w;
     if (live) {
-      x[g] = xg + alpha * pg;
-      r[g] = rn;
+      *reinterpret_cast<V*>(x + g) = xn;
+      *reinterpret_cast<V*>(r + g) = rn;
     }
-    const double rd = static_cast<double>(rn);
-    acc[0] += rd * static_cast<double>(dg * rn);
-    acc[1] += rd * rd;
+    const double r0 = rn.x, r1 = rn.y, r2 = rn.z, r3 = rn.w;
+    acc[0] += r0 * static_cast<double>(dv.x * rn.x) + r1 * static_cast<double>(dv.y * rn.y) +
+              r2 * static_cast<double>(dv.z * rn.z) + r3 * static_cast<double>(dv.w * rn.w);
+    acc[1] += r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3;
   }
   block_partials<2>(acc, parts);
 }

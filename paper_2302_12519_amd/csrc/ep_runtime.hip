@@ -152,8 +152,8 @@ struct ep_grid_s {
   int last_inner = 50;
   std::string err;
 
-  // timing
-  bool timing = false;
+  // timing: bit k set = launches of kernel id k are bracketed by events
+  uint32_t timing = 0;
   size_t tused[kTimers] = {};
   std::vector<TimerPair> tk[kTimers];
   double tms[kTimers] = {};
@@ -251,7 +251,7 @@ IonicT<T> ionic_t(const ep_grid g) {
 
 // ---- timing ---------------------------------------------------------------
 TimerPair* timer_begin(ep_grid g, int id) {
-  if (!g->timing) return nullptr;
+  if (!((g->timing >> id) & 1u)) return nullptr;
   if (g->tused[id] == g->tk[id].size()) {
     TimerPair tp;
     if (hipEventCreate(&tp.a) != hipSuccess || hipEventCreate(&tp.b) != hipSuccess) return nullptr;
@@ -1485,7 +1485,7 @@ EP_API ep_status ep_grid_stats(ep_grid g, int64_t* n_tissue, int64_t* n_bricks,
 
 EP_API ep_status ep_kernel_timing(ep_grid g, int32_t enable) {
   if (!g) return EP_ERR_ARG;
-  g->timing = enable != 0;
+  g->timing = static_cast<uint32_t>(enable) & ((1u << kTimers) - 1u);
   for (int k = 0; k < kTimers; ++k) {
     g->tms[k] = 0;
     g->tcount[k] = 0;

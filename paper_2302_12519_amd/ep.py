@@ -281,8 +281,18 @@ class Grid:
                     "ep_grid_stats")
         return {"n_tissue": a.value, "n_bricks": b.value, "device_bytes": c.value}
 
-    def kernel_timing(self, enable=True):
-        self._check(lib.ep_kernel_timing(self._h, 1 if enable else 0), "ep_kernel_timing")
+    def kernel_timing(self, enable=True, kernels=None):
+        """Time launches with HIP events: all kernels, or only those named in
+        `kernels` (keys of KERNELS); resets the totals."""
+        if not enable:
+            mask = 0
+        elif kernels is None:
+            mask = -1
+        else:
+            mask = 0
+            for k in kernels:
+                mask |= 1 << KERNELS[k]
+        self._check(lib.ep_kernel_timing(self._h, mask), "ep_kernel_timing")
 
     def kernel_time(self, kernel):
         ms, cnt = C.c_double(), C.c_int64()
