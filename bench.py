@@ -31,9 +31,11 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 #   implicit-step init (k_be_init): reads v, w, the previous step's v, b and
 #             Q, two older increments d (28 B) and the 6 operator weights
 #             (24 B); writes x0, b, d, Q, w, r0 (24 B)                  -> 76 B
-#   PCG direction + operator (k_pcg_dir): reads r, M^-1, p (12 B) and the
-#             weights (24 B), writes p, q (8 B)                          -> 44 B
-#   PCG update (k_pcg_upd): reads x, p, q, r, M^-1 (20 B), writes x, r  -> 28 B
+#   PCG launch 0 (k_pcg_step, first): reads r, M^-1 (8 B) and the weights
+#             (24 B), writes p, q (8 B)                                 -> 40 B
+#   PCG iteration (k_pcg_step): reads x, r, q, p, M^-1 (20 B) and the
+#             weights (24 B), writes x, r, p, q (16 B)                  -> 60 B
+#   PCG last x update (k_pcg_step, solve done): reads x, p, writes x    -> 12 B
 #   one-reduction PCG iteration (k_cgcg, elliptic solves): reads x, r,
 #             M^-1, p, s, w (24 B) and the weights (24 B), writes x, r, p,
 #             s, w (20 B)                                               -> 68 B
@@ -41,11 +43,12 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 #   adjoint step: reads lambda_v, lambda_w, v, w, v_next, crossing step (24 B),
 #             weights and unscaled tensors (48 B), mask (1 B), gradient (8 B,
 #             FP64); writes lambda_v, lambda_w (8 B) and gradient (8 B)  -> 97 B
-ALGO_BYTES = {"be_init": 76, "pcg_dir": 44, "pcg_upd": 28, "cg_iter": 68,
+ALGO_BYTES = {"be_init": 76, "pcg_first": 40, "pcg_iter": 60, "pcg_final": 12, "cg_iter": 68,
               "stencil_explicit": 40, "adjoint_step": 97}
 STEP_KERNELS = {"be_init": ("k_be_init<float>", "be_init"),
-                "stencil": ("k_pcg_dir<float>", "pcg_dir"),
-                "cg_update": ("k_pcg_upd<float>", "pcg_upd")}
+                "cg_setup": ("k_pcg_step<float> (launch 0: p0 = z0, q0 = K p0)", "pcg_first"),
+                "stencil": ("k_pcg_step<float> (iteration)", "pcg_iter"),
+                "cg_update": ("k_pcg_step<float> (last x update)", "pcg_final")}
 
 
 def parse():
@@ -292,13 +295,17 @@ def main():
           f"device {st['device_bytes'] / 2**20:.0f} MiB, generated in {gen_s:.1f} s",
           file=sys.stderr, flush=True)
 
-    # warm-up with every kernel timed, to find the dominant one (the largest
-    # share of the step's kernel time)
+    if a.warmup:
+        g.step(a.warmup)
+    # per-kernel breakdown, every kernel timed, on the steps after the
+    # warm-up; it also names the dominant kernel (the largest share of the
+    # step's kernel time)
+    n_diag = min(a.steps, 200)
     g.kernel_timing(True)
-    g.step(max(a.warmup, 1))
+    g.step(n_diag)
     torch.cuda.synchronize()
-    warm = {k: g.kernel_time(k) for k in STEP_KERNELS}
-    dom = max(STEP_KERNELS, key=lambda k: warm[k][0])
+    times = {k: g.kernel_time(k) for k in list(STEP_KERNELS) + ["cg_tail"]}
+    dom = max(STEP_KERNELS, key=lambda k: times[k][0])
     dom_name, dom_bytes = STEP_KERNELS[dom]
     # timed region: events around the dominant kernel's launches only (events
     # between launches cost time)
@@ -310,13 +317,6 @@ def main():
     t1 = time.perf_counter()
     elapsed = t1 - t0
     dom_ms, dom_n = g.kernel_time(dom)
-    # per-kernel breakdown, every kernel timed, on further steps after the
-    # timed region
-    n_diag = min(a.steps, 200)
-    g.kernel_timing(True)
-    g.step(n_diag)
-    torch.cuda.synchronize()
-    times = {k: g.kernel_time(k) for k in ("be_init", "stencil", "cg_update", "cg_tail")}
     g.kernel_timing(False)
 
     value = inst.nt * a.steps / elapsed

@@ -357,7 +357,6 @@ ep_status admit(ep_batch b, ep_batch_request* r, int slot) {
   L.nb = m.nb;
   L.grid = grid_for(m.nb);
   L.pgrid = L.grid;
-  L.ugrid = L.grid;
   L.stream = b->stream;
   L.rowsn = nullptr;
   float* c32[6];

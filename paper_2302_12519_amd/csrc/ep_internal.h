@@ -69,7 +69,6 @@ struct LaunchCfg {
   int nb;       // active bricks
   int grid;     // blocks of a one-brick-per-block launch (multiple of kXcd, >= nb)
   int pgrid;    // blocks of a persistent launch (multiple of kXcd, <= grid)
-  int ugrid;    // blocks of the persistent streaming PCG update (multiple of kXcd, <= grid)
   hipStream_t stream;
   const uint64_t* rowsn;   // (nb+1)*27 row masks of each brick's neighbourhood
 };
@@ -81,16 +80,6 @@ inline int pgrid_for(int nb, bool /*fp64*/) {
   const int g = grid_for(nb);
   return g < 512 ? g : 512;
 }
-// the pointwise PCG update: a block covers kUpdBricks bricks at a time, and
-// the launch has one block per kUpdBricks bricks up to 4096 blocks (then it
-// loops)
-constexpr int kUpdBricks = 4;
-inline int ugrid_for(int nb) {
-  const int b = (nb + kUpdBricks - 1) / kUpdBricks;
-  const int g = ((b + kXcd - 1) / kXcd) * kXcd;
-  return g < 4096 ? g : 4096;
-}
-
 // ---- kernel launchers (ep_kernels.hip) ----------------------------------
 void launch_tensor_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask,
                          const double* fib, const double* scale, double sig_l, double sig_t,
@@ -131,19 +120,16 @@ void launch_cgcg(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, c
                  T* w_out, int kind, int init_kind, const CGScalars* cin, CGScalars* cout,
                  const double* prev, double* parts, unsigned long long* mirror, unsigned seq);
 
-// Two-launch PCG (textbook recurrences): direction + operator launch
-// (L.pgrid blocks; the launch before it left nprev partials per component),
-// then the x / r update (L.ugrid blocks).  Each tests the scalars of the
-// launch before it.
+// One-launch-per-iteration PCG (textbook recurrences with the next
+// residual norms expanded in the previous launch's dots; 7 partials per
+// block).  first: launch 0 of a solve (tests the init's (b.b, r.r)).
 template <typename T>
-void launch_pcg_dir(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, const T* dinv,
-                    const T* r, const T* p_in, T* p_out, T* q, int first, const CGScalars* cin,
-                    CGScalars* cout, const double* prev, int nprev, double* parts,
-                    unsigned long long* mirror, unsigned seq);
-template <typename T>
-void launch_pcg_upd(const LaunchCfg& L, const T* dinv, T* x, T* r, const T* p, const T* q,
-                    const CGScalars* cin, CGScalars* cout, const double* prev, double* parts,
-                    unsigned long long* mirror, unsigned seq);   // L.ugrid blocks
+void launch_pcg_step(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, const T* dinv,
+                     T* x, const T* r_in, T* r_out, const T* p_in, T* p_out, const T* q_in,
+                     T* q_out, int first, const CGScalars* cin, CGScalars* cout,
+                     const double* prev, double* parts, unsigned long long* mirror,
+                     unsigned seq);
+constexpr int kMaxPartials = 7;   // partial sums per block of any CG launch
 
 // out[k] = sum of partials[k*nparts .. (k+1)*nparts) in a fixed order
 void launch_reduce_sum(hipStream_t s, const double* partials, int nparts, int K, double* out);

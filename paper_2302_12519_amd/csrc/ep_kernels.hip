@@ -27,8 +27,8 @@
 //   k_explicit, k_ionic: Mitchell-Schaeffer reaction by explicit Euler
 //     (eqn:ms1, eqn:ms2; Reaction subsection) fused with explicit diffusion;
 //     activation time at the first threshold crossing.
-//   k_be_init, k_pcg_dir, k_pcg_upd: implicit-Euler diffusion step (Linear
-//     Solver section, "Implicit Euler") solved by Jacobi-preconditioned CG;
+//   k_be_init, k_pcg_step: implicit-Euler diffusion step (Linear Solver
+//     section, "Implicit Euler") solved by Jacobi-preconditioned CG;
 //     k_cgcg: the same CG in one-reduction form for the elliptic solves.
 //   k_resid64, k_inner_init, k_phi_correct, k_phi_shift, k_parabolic: the
 //     bidomain step (eqn:bidomain1): elliptic solve for phi_e by FP32 PCG
@@ -536,30 +536,39 @@ __global__ __launch_bounds__(kBV) void k_cgcg(int nb, const int* __restrict__ nb
   block_partials<3>(acc, parts);
 }
 
-// Jacobi-PCG in its textbook two-recurrence form, two launches per
-// iteration.  Used for the implicit-Euler step, whose extrapolated guess
-// leaves one or two iterations to do: this form needs one operator apply per
-// iteration, where the one-reduction form above also needs a set-up apply
-// (w0 = K u0) per solve.  K = c0 I + c1 A, z = M^-1 r.
-//
-// k_pcg_dir, launch k: p_k = z_k + beta_k p_{k-1} (beta_0 = 0, no p_{-1}
-// read), q_k = K p_k.  It first tests the residual of the launch before
-// (the init launch's (b.b, r.r) for k = 0, else the update's (gamma, rho);
-// nprev partials per component).
-// Partials: (delta, gamma) = ((p_k, q_k), (r_k, z_k)).  p_{k-1} is read at
-// the halo, so p_k goes to the other buffer of a pair.
+// Four consecutive voxels of a brick row (16 B in FP32), loaded and stored
+// as one vector access.
+template <typename T> struct Quad;
+template <> struct Quad<float> { using V = float4; };
+template <> struct Quad<double> { using V = double4; };
+
+// Jacobi-PCG with one launch per iteration and no set-up apply: the
+// textbook recurrences, with the next residual's two norms, (r, z) and
+// (r, r), expanded in dot products of the previous launch's own vectors, so
+// that the x / r update, the new direction and the operator apply of one
+// iteration share a launch.  K = c0 I + c1 A, z = M^-1 r.
+//   launch 0: tests the init's residual ((b.b, r.r) partials), then
+//     p_0 = z_0, q_0 = K p_0 (r_0 stays where the init left it);
+//   launch k >= 1: from launch k-1's dots, alpha = gamma / delta,
+//     gamma' = gamma - 2 alpha (q, z) + alpha^2 (q, M^-1 q),
+//     rho'   = rho   - 2 alpha (q, r) + alpha^2 (q, q).
+//     If rho' <= tol^2 (b, b) the solve is done and only x += alpha p is
+//     left: a pointwise pass (also taken when maxit is reached, flagged as
+//     failed).  Otherwise r' = r - alpha q, x += alpha p, z' = M^-1 r',
+//     beta = gamma' / gamma, p' = z' + beta p, q' = K p'.
+// The dots are accumulated in FP64 from the FP32 vectors, so the expansion
+// loses nothing that matters next to the FP32 rounding of r' itself.
+// Partials: (delta, gamma, (q, z), (q, M^-1 q), rho, (q, r), (q, q)) of the
+// launch's own p, q, r.  r, p and q are read at the halo, so a launch writes
+// the other buffer of each pair; x is updated in place.
 template <typename T>
-__global__ __launch_bounds__(kBV) void k_pcg_dir(int nb, const int* __restrict__ nbr,
-                                                 CoefSet<T> c, T c0, T c1,
-                                                 const T* __restrict__ dinv,
-                                                 const T* __restrict__ r,
-                                                 const T* __restrict__ p_in,
-                                                 T* __restrict__ p_out, T* __restrict__ q,
-                                                 int first, const CGScalars* __restrict__ cin,
-                                                 CGScalars* cout, const double* __restrict__ prev,
-                                                 int nprev, double* parts,
-                                                 const uint64_t* __restrict__ rowsn,
-                                                 unsigned long long* mirror, unsigned seq) {
+__global__ __launch_bounds__(kBV) void k_pcg_step(
+    int nb, const int* __restrict__ nbr, CoefSet<T> c, T c0, T c1, const T* __restrict__ dinv,
+    T* __restrict__ x, const T* __restrict__ r_in, T* __restrict__ r_out,
+    const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restrict__ q_in,
+    T* __restrict__ q_out, int first, const CGScalars* __restrict__ cin, CGScalars* cout,
+    const double* __restrict__ prev, double* parts, const uint64_t* __restrict__ rowsn,
+    unsigned long long* mirror, unsigned seq) {
   const CGScalars in = *cin;
   if (in.done) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -569,27 +578,45 @@ __global__ __launch_bounds__(kBV) void k_pcg_dir(int nb, const int* __restrict__
     return;
   }
   CGScalars st = in;
-  {
+  bool final_x = false;
+  if (first) {
     double S[2];
-    sum_prev<2>(prev, nprev, S);
-    if (first) {
-      st.bb = S[0];
-      st.rr = S[1];
-      st.it = 0;
-      st.fail = 0;
-      st.beta = 0.0;
-      st.done = (S[0] == 0.0 || S[1] <= in.tol2 * S[0]) ? 1 : 0;
+    sum_prev<2>(prev, gridDim.x, S);
+    st.bb = S[0];
+    st.rr = S[1];
+    st.it = 0;
+    st.fail = 0;
+    st.alpha = 0.0;
+    st.beta = 0.0;
+    st.done = (S[0] == 0.0 || S[1] <= in.tol2 * S[0]) ? 1 : 0;
+  } else {
+    double S[7];
+    sum_prev<7>(prev, gridDim.x, S);
+    const double del = S[0], gam = S[1], qz = S[2], qmq = S[3], rho = S[4], qr = S[5],
+                 qq = S[6];
+    st.it = in.it + 1;
+    if (!(del > 0.0) || !isfinite(del) || !isfinite(gam)) {
+      st.done = 1;
+      st.fail = 1;
     } else {
-      const double gam = S[0], rho = S[1];
-      st.rr = rho;
-      st.it = in.it + 1;
-      if (!isfinite(rho) || !isfinite(gam)) { st.done = 1; st.fail = 1; }
-      else if (rho <= in.tol2 * in.bb) st.done = 1;
-      else if (st.it >= in.maxit) { st.done = 1; st.fail = 1; }
-      else if (!(in.rz > 0.0)) { st.done = 1; st.fail = 1; }
-      else {
-        st.beta = gam / in.rz;
-        st.rz = gam;
+      const double alpha = gam / del;
+      const double gam1 = gam - 2.0 * alpha * qz + alpha * alpha * qmq;
+      const double rho1 = rho - 2.0 * alpha * qr + alpha * alpha * qq;
+      st.alpha = alpha;
+      st.rr = rho1;
+      if (!isfinite(rho1) || !isfinite(gam1)) {
+        st.done = 1;
+        st.fail = 1;
+      } else if (rho1 <= in.tol2 * in.bb) {
+        st.done = 1;
+        final_x = true;
+      } else if (st.it >= in.maxit || !(gam1 > 0.0)) {
+        st.done = 1;
+        st.fail = 1;
+        final_x = true;
+      } else {
+        st.beta = gam1 / gam;
+        st.rz = gam1;
       }
     }
   }
@@ -597,12 +624,35 @@ __global__ __launch_bounds__(kBV) void k_pcg_dir(int nb, const int* __restrict__
     *cout = st;
     publish_status(mirror, seq, st);
   }
+  const T alpha = static_cast<T>(st.alpha), beta = static_cast<T>(st.beta);
+  if (final_x) {
+    // the last x update, pointwise over the rows holding tissue: half a row
+    // (4 voxels, vector accesses) per thread, 4 bricks per block at a time
+    using V = typename Quad<T>::V;
+    const int slot = threadIdx.x >> 7;
+    const int e = (threadIdx.x & 127) * 4;
+    const int bit = e >> 3;
+    for (int m = slot;; m += 4) {
+      const int brick = pbrick(m, nb);
+      if (brick < 0) break;
+      if ((rowsn[brick * kNbr + 13] >> bit) & 1) {
+        const int g = brick * kBV + e;
+        V xv = *reinterpret_cast<const V*>(x + g);
+        const V pv = *reinterpret_cast<const V*>(p_in + g);
+        xv.x += alpha * pv.x;
+        xv.y += alpha * pv.y;
+        xv.z += alpha * pv.z;
+        xv.w += alpha * pv.w;
+        *reinterpret_cast<V*>(x + g) = xv;
+      }
+    }
+    return;
+  }
   if (st.done) return;
   __shared__ T s[kTile];
   __shared__ int nbt[2][kNbr];
   __shared__ uint64_t rowt[2][kNbr];
-  const T beta = static_cast<T>(st.beta);
-  double acc[2] = {0.0, 0.0};
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   NbrAhead ahead;
   int nxt = pbrick(0, nb);
   ahead.fetch(nbr, rowsn, nxt);
@@ -615,118 +665,45 @@ __global__ __launch_bounds__(kBV) void k_pcg_dir(int nb, const int* __restrict__
     ahead.fetch(nbr, rowsn, nxt);
     __syncthreads();
     const Cell e = cell_setup(nbs, brick, rowm, nb);
-    const T rg = r[e.gl], dg = dinv[e.gl];
+    const T rg = r_in[e.gl], dg = dinv[e.gl];
+    const T qg = first ? T(0) : q_in[e.gl];
     const T pg = first ? T(0) : p_in[e.gl];
-    T hr = T(0), hd = T(0), hp = T(0);
+    const T xg = first ? T(0) : x[e.gl];
+    T hr = T(0), hd = T(0), hq = T(0), hp = T(0);
     if (e.has_halo) {
-      hr = r[e.hgl];
+      hr = r_in[e.hgl];
       hd = dinv[e.hgl];
+      hq = first ? T(0) : q_in[e.hgl];
       hp = first ? T(0) : p_in[e.hgl];
     }
     T k18[18];
     gather18(c, nbs, brick, e.lx, e.ly, e.lz, k18, rowm, nb);
-    const T zg = dg * rg;
-    const T pn = zg + beta * pg;
+    const T rn = rg - alpha * qg;
+    const T zn = dg * rn;
+    const T pn = zn + beta * pg;
     s[e.C] = pn;
-    if (e.has_halo) s[e.hC] = hd * hr + beta * hp;
+    if (e.has_halo) s[e.hC] = hd * (hr - alpha * hq) + beta * hp;
     ahead.stage(nbt[(m + 1) & 1], rowt[(m + 1) & 1]);
     __syncthreads();
     const T qv = c0 * pn + c1 * apply19(s, e.C, k18);
     if (e.live) {
+      if (!first) {
+        x[e.g] = xg + alpha * pg;
+        r_out[e.g] = rn;
+      }
       p_out[e.g] = pn;
-      q[e.g] = qv;
+      q_out[e.g] = qv;
     }
-    acc[0] += static_cast<double>(pn) * static_cast<double>(qv);
-    acc[1] += static_cast<double>(rg) * static_cast<double>(zg);
+    const double dr = rn, dz = zn, dp = pn, dq = qv;
+    acc[0] += dp * dq;
+    acc[1] += dr * dz;
+    acc[2] += dq * dz;
+    acc[3] += dq * static_cast<double>(dg * qv);
+    acc[4] += dr * dr;
+    acc[5] += dq * dr;
+    acc[6] += dq * dq;
   }
-  block_partials<2>(acc, parts);
-}
-
-// Four consecutive voxels of a brick row (16 B in FP32), loaded and stored
-// as one vector access.
-template <typename T> struct Quad;
-template <> struct Quad<float> { using V = float4; };
-template <> struct Quad<double> { using V = double4; };
-
-// k_pcg_upd, launch k: alpha_k = gamma_k / delta_k from the direction
-// launch's partials; x += alpha p_k, r -= alpha q_k, in place (no halo).
-// Partials: (gamma_{k+1}, rho_{k+1}) = ((r, z), (r, r)).  Each thread takes
-// half a brick row (4 voxels, vector loads), so a 512-thread block covers 4
-// bricks at a time (slot = thread / 128); the launch has about one block per
-// 4 bricks (kUpdBricks), left to the hardware to balance.  Voxels of rows
-// without tissue are neither loaded (their loads read the ghost brick) nor
-// stored.  Its partials count (gridDim.x) differs from the stencil kernels'
-// (nprev of the next direction launch).
-template <typename T>
-__global__ __launch_bounds__(kBV) void k_pcg_upd(int nb, const T* __restrict__ dinv,
-                                                 T* __restrict__ x, T* __restrict__ r,
-                                                 const T* __restrict__ p,
-                                                 const T* __restrict__ q,
-                                                 const CGScalars* __restrict__ cin,
-                                                 CGScalars* cout, const double* __restrict__ prev,
-                                                 int nprev, double* parts,
-                                                 const uint64_t* __restrict__ rowsn,
-                                                 unsigned long long* mirror, unsigned seq) {
-  using V = typename Quad<T>::V;
-  const CGScalars in = *cin;
-  if (in.done) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      *cout = in;
-      publish_status(mirror, seq, in);
-    }
-    return;
-  }
-  CGScalars st = in;
-  {
-    double S[2];
-    sum_prev<2>(prev, nprev, S);
-    const double del = S[0], gam = S[1];
-    if (!(del > 0.0) || !isfinite(del) || !isfinite(gam)) { st.done = 1; st.fail = 1; }
-    else {
-      st.alpha = gam / del;
-      st.rz = gam;
-    }
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    *cout = st;
-    publish_status(mirror, seq, st);
-  }
-  if (st.done) return;
-  const T alpha = static_cast<T>(st.alpha);
-  const int slot = threadIdx.x >> 7;              // brick slot 0..3
-  const int e = (threadIdx.x & 127) * 4;          // first of the thread's 4 voxels
-  const int bit = e >> 3;                         // its row lx*8 + ly
-  double acc[2] = {0.0, 0.0};
-  for (int m = slot;; m += kUpdBricks) {
-    const int brick = pbrick(m, nb);
-    if (brick < 0) break;
-    const bool live = (rowsn[brick * kNbr + 13] >> bit) & 1;
-    const int g = brick * kBV + e;
-    const int gl = live ? g : nb * kBV + e;
-    const V xv = *reinterpret_cast<const V*>(x + gl);
-    const V pv = *reinterpret_cast<const V*>(p + gl);
-    const V qv = *reinterpret_cast<const V*>(q + gl);
-    const V rv = *reinterpret_cast<const V*>(r + gl);
-    const V dv = *reinterpret_cast<const V*>(dinv + gl);
-    V xn, rn;
-    xn.x = xv.x + alpha * pv.x;
-    xn.y = xv.y + alpha * pv.y;
-    xn.z = xv.z + alpha * pv.z;
-    xn.w = xv.w + alpha * pv.w;
-    rn.x = rv.x - alpha * qv.x;
-    rn.y = rv.y - alpha * qv.y;
-    rn.z = rv.z - alpha * qv.z;
-    rn.w = rv.w - alpha * qv.w;
-    if (live) {
-      *reinterpret_cast<V*>(x + g) = xn;
-      *reinterpret_cast<V*>(r + g) = rn;
-    }
-    const double r0 = rn.x, r1 = rn.y, r2 = rn.z, r3 = rn.w;
-    acc[0] += r0 * static_cast<double>(dv.x * rn.x) + r1 * static_cast<double>(dv.y * rn.y) +
-              r2 * static_cast<double>(dv.z * rn.z) + r3 * static_cast<double>(dv.w * rn.w);
-    acc[1] += r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3;
-  }
-  block_partials<2>(acc, parts);
+  block_partials<7>(acc, parts);
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict__ partials,
@@ -1255,21 +1232,14 @@ void launch_cgcg(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, c
 }
 
 template <typename T>
-void launch_pcg_dir(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, const T* dinv,
-                    const T* r, const T* p_in, T* p_out, T* q, int first, const CGScalars* cin,
-                    CGScalars* cout, const double* prev, int nprev, double* parts,
-                    unsigned long long* mirror, unsigned seq) {
-  k_pcg_dir<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, c0, c1, dinv, r, p_in, p_out, q,
-                                              first, cin, cout, prev, nprev, parts, L.rowsn,
-                                              mirror, seq);
-}
-
-template <typename T>
-void launch_pcg_upd(const LaunchCfg& L, const T* dinv, T* x, T* r, const T* p, const T* q,
-                    const CGScalars* cin, CGScalars* cout, const double* prev, double* parts,
-                    unsigned long long* mirror, unsigned seq) {
-  k_pcg_upd<T><<<L.ugrid, kBV, 0, L.stream>>>(L.nb, dinv, x, r, p, q, cin, cout, prev, L.pgrid,
-                                              parts, L.rowsn, mirror, seq);
+void launch_pcg_step(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, const T* dinv,
+                     T* x, const T* r_in, T* r_out, const T* p_in, T* p_out, const T* q_in,
+                     T* q_out, int first, const CGScalars* cin, CGScalars* cout,
+                     const double* prev, double* parts, unsigned long long* mirror,
+                     unsigned seq) {
+  k_pcg_step<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, c0, c1, dinv, x, r_in, r_out, p_in,
+                                               p_out, q_in, q_out, first, cin, cout, prev, parts,
+                                               L.rowsn, mirror, seq);
 }
 
 void launch_reduce_sum(hipStream_t s, const double* partials, int nparts, int K, double* out) {
@@ -1383,13 +1353,10 @@ void launch_loss(const LaunchCfg& L, const uint8_t* mask, const int* cross, cons
                                const T*, T*, T*, const T*, T*, const T*, T*, int, int,         \
                                const CGScalars*, CGScalars*, const double*, double*,           \
                                unsigned long long*, unsigned);                                 \
-  template void launch_pcg_dir<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T, const T*,   \
-                                  const T*, const T*, T*, T*, int, const CGScalars*,           \
-                                  CGScalars*, const double*, int, double*,                     \
-                                  unsigned long long*, unsigned);                              \
-  template void launch_pcg_upd<T>(const LaunchCfg&, const T*, T*, T*, const T*, const T*,      \
-                                  const CGScalars*, CGScalars*, const double*, double*,        \
-                                  unsigned long long*, unsigned);                              \
+  template void launch_pcg_step<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T, const T*,  \
+                                   T*, const T*, T*, const T*, T*, const T*, T*, int,          \
+                                   const CGScalars*, CGScalars*, const double*, double*,       \
+                                   unsigned long long*, unsigned);                             \
   template void launch_activation<T>(const LaunchCfg&, const T*, const T*, T*, T, T, double,   \
                                      int*);                                                    \
   template void launch_dinv<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T, T*);            \

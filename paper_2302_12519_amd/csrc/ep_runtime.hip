@@ -92,10 +92,9 @@ struct ep_grid_s {
   double* d_ci64[6] = {};     // bidomain: A_i in FP64
   double* d_ck64[6] = {};     // bidomain: A_i + A_e in FP64
   float* d_ck32[6] = {};      // bidomain: A_i + A_e in FP32
-  void* d_cr[2] = {nullptr, nullptr};  // PCG vectors (state precision): r, s, w ping-pong
-  void* d_cs[2] = {nullptr, nullptr};
+  void* d_cr[2] = {nullptr, nullptr};  // implicit-step PCG vectors (state precision):
+  void* d_cs[2] = {nullptr, nullptr};  // r, p, q, each a ping-pong pair
   void* d_cw[2] = {nullptr, nullptr};
-  void* d_cp = nullptr;
   void* d_dinv = nullptr;
   void* d_bprev[2] = {nullptr, nullptr};  // implicit solve: b of the last two steps
   void* d_dprev[kDRing] = {};  // ring of increments d = v_{k+1} - b_k
@@ -451,55 +450,51 @@ ep_status cg_solve(ep_grid g, CoefSet<T> c, T c0, T c1, const T* dinv, T* x, T* 
   return EP_OK;
 }
 
-// Two-launch PCG solve after its init launch (scalars in d_cg[0], the init's
-// (b.b, r.r) partials in d_cgp[0], r0 in r, x0 in x).  Launches alternate
-// direction (even j) and update (odd j); launch j reads scalars / partials
-// [j & 1] and writes [(j + 1) & 1].  Direction k writes p_k to pv[k & 1] and
-// reads p_{k-1} from pv[(k + 1) & 1].  The host queues one iteration (update,
-// direction) at a time: a direction launch publishes the convergence test of
-// the update before it as it starts, so the next pair is queued while it
-// still runs its stencil, and at most one launch per solve only finds the
-// solve done.
+// One-launch-per-iteration PCG solve after its init launch (scalars in
+// d_cg[0], the init's (b.b, r.r) partials in d_cgp[0], r0 in rb[0], x0 in x).
+// Launch k reads scalars / partials [k & 1] and writes [(k + 1) & 1]; it
+// reads r_{k-1} from rb[(k - 1) & 1] (r_0 from rb[0]) and writes r_k to
+// rb[k & 1], and p_k, q_k to pb[k & 1], qb[k & 1].  Each launch publishes its
+// convergence test as it starts, so after launches 0 and 1 the host queues
+// one launch at a time while the last one runs its stencil; the launch that
+// finds the solve done does only the last x update.
 template <typename T>
-ep_status pcg_split_solve(ep_grid g, CoefSet<T> c, T c0, T c1, const T* dinv, T* x, T* r,
-                          T* const pv[2], T* q, int maxit, int* iters, bool* failed) {
+ep_status pcg_step_solve(ep_grid g, CoefSet<T> c, T c0, T c1, const T* dinv, T* x,
+                         T* const rb[2], T* const pb[2], T* const qb[2], int maxit, int* iters,
+                         bool* failed) {
   CGScalars* cg = g->d_cg;
   double* const* P = g->d_cgp;
-  int ndir = 0, nupd = 0;
-  auto dir = [&](int j) {
-    const int k = j >> 1;
-    TimerPair* t0 = timer_begin(g, KT_STENCIL);
-    launch_pcg_dir<T>(g->L, g->d_nbr, c, c0, c1, dinv, r, pv[(k + 1) & 1], pv[k & 1], q,
-                      k == 0 ? 1 : 0, cg + (j & 1), cg + ((j + 1) & 1), P[j & 1],
-                      k == 0 ? g->L.pgrid : g->L.ugrid, P[(j + 1) & 1], g->dmirror, ++g->seq);
+  int n = 0;
+  auto launch = [&](int k) {
+    TimerPair* t0 = timer_begin(g, k == 0 ? KT_CGSETUP : KT_STENCIL);
+    launch_pcg_step<T>(g->L, g->d_nbr, c, c0, c1, dinv, x, rb[k == 0 ? 0 : (k - 1) & 1],
+                       rb[k & 1], pb[(k + 1) & 1], pb[k & 1], qb[(k + 1) & 1], qb[k & 1],
+                       k == 0 ? 1 : 0, cg + (k & 1), cg + ((k + 1) & 1), P[k & 1],
+                       P[(k + 1) & 1], g->dmirror, ++g->seq);
     timer_end(g, t0);
-    ++ndir;
+    ++n;
   };
-  auto upd = [&](int j) {
-    const int k = j >> 1;
-    TimerPair* t0 = timer_begin(g, KT_UPDATE);
-    launch_pcg_upd<T>(g->L, dinv, x, r, pv[k & 1], q, cg + (j & 1), cg + ((j + 1) & 1),
-                      P[j & 1], P[(j + 1) & 1], g->dmirror, ++g->seq);
-    timer_end(g, t0);
-    ++nupd;
-  };
-  int j = 0;
-  dir(j++);
+  int k = 0;
+  launch(k++);
   unsigned long long st = 0;
   for (;;) {
-    upd(j++);
-    dir(j++);
-    TRY(wait_status(g, g->seq, cg + (j & 1), &st));
-    if ((st & 1) || j >= 2 * maxit + 3) break;
+    launch(k++);
+    TRY(wait_status(g, g->seq, cg + (k & 1), &st));
+    if ((st & 1) || k >= maxit + 2) break;
   }
   const int it = static_cast<int>((st >> 2) & 0x3fffffff);
   *iters = it;
   *failed = ((st >> 1) & 1) != 0 || !(st & 1);
-  g->last_cg = cg + (j & 1);
-  // directions 0..it-1 and updates 0..it-1 did work; the rest found the
-  // solve done
-  timer_retag(g, KT_STENCIL, KT_CGTAIL, ndir - it);
-  timer_retag(g, KT_UPDATE, KT_CGTAIL, nupd - it);
+  g->last_cg = cg + (k & 1);
+  // launch 0 and launches 1..it-1 applied the operator; launch it (it >= 1)
+  // did the last x update; launches after it found the solve done
+  if (it == 0) {
+    timer_retag(g, KT_STENCIL, KT_CGTAIL, n - 1);
+    timer_retag(g, KT_CGSETUP, KT_CGTAIL, 1);
+  } else {
+    timer_retag(g, KT_STENCIL, KT_CGTAIL, n - 1 - it);
+    timer_retag(g, KT_STENCIL, KT_UPDATE, 1);
+  }
   return EP_OK;
 }
 
@@ -522,8 +517,8 @@ ep_status step_be(ep_grid g, const T* jstim, ep_step_info* acc) {
   const int c = g->cur, n = 1 - c;
   T* x = static_cast<T*>(g->d_v[n]);
   T* r[2] = {static_cast<T*>(g->d_cr[0]), static_cast<T*>(g->d_cr[1])};
-  T* sv[2] = {static_cast<T*>(g->d_cs[0]), static_cast<T*>(g->d_cs[1])};
-  T* wv[2] = {static_cast<T*>(g->d_cw[0]), static_cast<T*>(g->d_cw[1])};
+  T* pv[2] = {static_cast<T*>(g->d_cs[0]), static_cast<T*>(g->d_cs[1])};
+  T* qv[2] = {static_cast<T*>(g->d_cw[0]), static_cast<T*>(g->d_cw[1])};
   const T* dinv = static_cast<const T*>(g->d_dinv);
   // x (= d_v[n]) still holds the previous step's v: check its activation here
   // initial guess: polynomial through the last K = min(pred_len, 4) diffusion
@@ -558,8 +553,8 @@ ep_status step_be(ep_grid g, const T* jstim, ep_step_info* acc) {
   timer_end(g, ti);
   int iters = 0;
   bool failed = false;
-  TRY(pcg_split_solve<T>(g, coefs<T>(g), T(1), static_cast<T>(-g->dt), dinv, x, r[0], sv,
-                         wv[0], g->pcg_maxit, &iters, &failed));
+  TRY(pcg_step_solve<T>(g, coefs<T>(g), T(1), static_cast<T>(-g->dt), dinv, x, r, pv, qv,
+                        g->pcg_maxit, &iters, &failed));
   acc->cg_iters += iters;
   acc->cg_max = std::max(acc->cg_max, iters);
   if (failed) g->hs->flags[1] = 1;
@@ -1045,7 +1040,6 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   g->L.nb = nb;
   g->L.grid = g->grid;
   g->L.pgrid = pgrid_for(nb, g->prec == EP_F64);
-  g->L.ugrid = ugrid_for(nb);
   g->L.stream = g->stream;
   if (g->model == EP_BIDO && tissue_components(boxmask, g->n) != 1)
     return fail(g, EP_ERR_ARG, "bidomain tissue must be one face-connected component");
@@ -1068,7 +1062,7 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   TRY(dalloc(g, &g->d_partials, static_cast<size_t>(g->grid) * 4 * sizeof(double)));
   TRY(dalloc(g, &g->d_cg, 2 * sizeof(CGScalars)));
   for (int k = 0; k < 2; ++k)
-    TRY(dalloc(g, &g->d_cgp[k], static_cast<size_t>(std::max(g->L.pgrid, g->L.ugrid)) * 3 *
+    TRY(dalloc(g, &g->d_cgp[k], static_cast<size_t>(g->L.pgrid) * kMaxPartials *
                                    sizeof(double)));
   TRY(dalloc(g, &g->d_flags, 4 * sizeof(int)));
   TRY(dalloc(g, &g->d_sums, 8 * sizeof(double)));
@@ -1081,7 +1075,6 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
       TRY(dalloc(g, &g->d_cs[k], vb));
       TRY(dalloc(g, &g->d_cw[k], vb));
     }
-    TRY(dalloc(g, &g->d_cp, vb));
     TRY(dalloc(g, &g->d_dinv, vb));
     for (int k = 0; k < 2; ++k) TRY(dalloc(g, &g->d_bprev[k], vb));
     for (int k = 0; k < kDRing; ++k) TRY(dalloc(g, &g->d_dprev[k], vb));
