@@ -72,8 +72,9 @@ def parse():
                     help="run one side workload alone and print its JSON (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (for HBM counter scaling)")
-    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles",
-                                                           "traffic_cgcg_aniso_be_256.txt"))
+    ap.add_argument("--traffic-file", default=None,
+                    help="counter summary of the dominant kernel (default: "
+                         "profiles/traffic_<kernel>_aniso_be_<n>.txt)")
     return ap.parse_args()
 
 
@@ -322,7 +323,9 @@ def main():
     value = inst.nt * a.steps / elapsed
     avg_it = dom_ms / max(dom_n, 1)
     achieved = ALGO_BYTES[dom_bytes] * inst.nt / (avg_it * 1e-3) / 1e9
-    traffic = read_traffic(a.traffic_file, dom_name)
+    tfile = a.traffic_file or os.path.join(
+        ROOT, "profiles", f"traffic_{dom_name.split('<')[0]}_aniso_be_{a.n}.txt")
+    traffic = read_traffic(tfile, dom_name)
     out = {
         "metric": "voxel-steps/s",
         "value": value,
