@@ -71,7 +71,14 @@ struct LaunchCfg {
   int pgrid;    // blocks of a persistent launch (multiple of kXcd, <= grid)
   hipStream_t stream;
   const uint64_t* rowsn;   // (nb+1)*27 row masks of each brick's neighbourhood
+  bool stream_nt = false;  // implicit-step kernels: non-temporal own-voxel streams
 };
+
+// The implicit step touches about 24 state-precision arrays per step.  Once
+// they exceed the last-level cache (256 MB on MI355X), the kernels mark the
+// accesses no other brick reads as non-temporal.
+constexpr int kBeArrays = 24;
+constexpr long long kLlcBytes = 256ll << 20;
 
 inline int grid_for(int nb) { return ((nb + kXcd - 1) / kXcd) * kXcd; }
 // persistent launches: as many 512-thread blocks as stay resident on the

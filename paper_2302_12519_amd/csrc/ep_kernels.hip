@@ -81,6 +81,22 @@ struct NbrAhead {
   }
 };
 
+// Loads and stores of data no other brick of the launch reads (own-voxel
+// streams, outputs).  With NT they carry the non-temporal hint, so that on
+// grids whose working set exceeds the last-level cache they do not evict the
+// halo and neighbour-weight lines the next bricks read; on grids that fit,
+// plain accesses keep them cached for the next launch.
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_stream(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 // Sum the K partial sums the previous launch left (n per component) in a
 // fixed order.  Every block computes the identical totals, so no block has
 // to wait for another and nothing is communicated within the launch.
@@ -290,7 +306,7 @@ __global__ __launch_bounds__(kBV) void k_ionic(int nb, const T* __restrict__ v,
 // When check_prev is set it also records activation for the previous step
 // (vprev -> v) before x0 overwrites vprev's buffer.
 // Partials: (b.b, r.r).
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__ nbr,
                                                  CoefSet<T> c, const T* __restrict__ v,
                                                  const T* __restrict__ w,
@@ -331,11 +347,11 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
     const Cell q = cell_setup(nbs, brick, rowm, nb);
     const T v0 = v[q.gl], w0 = w[q.gl];
     const T j0 = jstim ? jstim[q.gl] : T(0);
-    const T vp = check_prev ? x[q.gl] : T(0);
+    const T vp = check_prev ? ld_stream<NT>(x + q.gl) : T(0);
     const T b1 = bprev ? bprev[q.gl] : T(0);
     const T q0 = qin ? qin[q.gl] : T(0);
-    const T d2 = d2in ? d2in[q.gl] : T(0);
-    const T d3 = d3in ? d3in[q.gl] : T(0);
+    const T d2 = d2in ? ld_stream<NT>(d2in + q.gl) : T(0);
+    const T d3 = d3in ? ld_stream<NT>(d3in + q.gl) : T(0);
     T hv = T(0), hw = T(0), hj = T(0), hb1 = T(0), hq = T(0);
     if (q.has_halo) {
       hv = v[q.hgl];
@@ -364,14 +380,14 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
     }
     if (!isfinite(v0)) flags[0] = 1;
     if (q.live) {
-      x[q.g] = x0;
-      bout[q.g] = vs;
+      st_stream<NT>(x + q.g, x0);
+      st_stream<NT>(bout + q.g, vs);
       if (bprev) {
-        dout[q.g] = d1;
-        qout[q.g] = q2 * d1 + q3 * d2 + q4 * d3;
+        st_stream<NT>(dout + q.g, d1);
+        st_stream<NT>(qout + q.g, q2 * d1 + q3 * d2 + q4 * d3);
       }
-      wout[q.g] = ws;
-      r[q.g] = rr;
+      st_stream<NT>(wout + q.g, ws);
+      st_stream<NT>(r + q.g, rr);
     }
     const double rd = static_cast<double>(rr);
     acc[0] += static_cast<double>(vs) * static_cast<double>(vs);
@@ -538,9 +554,9 @@ __global__ __launch_bounds__(kBV) void k_cgcg(int nb, const int* __restrict__ nb
 
 // Four consecutive voxels of a brick row (16 B in FP32), loaded and stored
 // as one vector access.
-template <typename T> struct Quad;
-template <> struct Quad<float> { using V = float4; };
-template <> struct Quad<double> { using V = double4; };
+template <typename T> struct Quad {
+  typedef T V __attribute__((ext_vector_type(4)));
+};
 
 // Jacobi-PCG with one launch per iteration and no set-up apply: the
 // textbook recurrences, with the next residual's two norms, (r, z) and
@@ -561,7 +577,7 @@ template <> struct Quad<double> { using V = double4; };
 // Partials: (delta, gamma, (q, z), (q, M^-1 q), rho, (q, r), (q, q)) of the
 // launch's own p, q, r.  r, p and q are read at the halo, so a launch writes
 // the other buffer of each pair; x is updated in place.
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(kBV) void k_pcg_step(
     int nb, const int* __restrict__ nbr, CoefSet<T> c, T c0, T c1, const T* __restrict__ dinv,
     T* __restrict__ x, const T* __restrict__ r_in, T* __restrict__ r_out,
@@ -637,13 +653,9 @@ __global__ __launch_bounds__(kBV) void k_pcg_step(
       if (brick < 0) break;
       if ((rowsn[brick * kNbr + 13] >> bit) & 1) {
         const int g = brick * kBV + e;
-        V xv = *reinterpret_cast<const V*>(x + g);
-        const V pv = *reinterpret_cast<const V*>(p_in + g);
-        xv.x += alpha * pv.x;
-        xv.y += alpha * pv.y;
-        xv.z += alpha * pv.z;
-        xv.w += alpha * pv.w;
-        *reinterpret_cast<V*>(x + g) = xv;
+        const V xv = ld_stream<NT>(reinterpret_cast<const V*>(x + g));
+        const V pv = ld_stream<NT>(reinterpret_cast<const V*>(p_in + g));
+        st_stream<NT>(reinterpret_cast<V*>(x + g), xv + alpha * pv);
       }
     }
     return;
@@ -668,7 +680,7 @@ __global__ __launch_bounds__(kBV) void k_pcg_step(
     const T rg = r_in[e.gl], dg = dinv[e.gl];
     const T qg = first ? T(0) : q_in[e.gl];
     const T pg = first ? T(0) : p_in[e.gl];
-    const T xg = first ? T(0) : x[e.gl];
+    const T xg = first ? T(0) : ld_stream<NT>(x + e.gl);
     T hr = T(0), hd = T(0), hq = T(0), hp = T(0);
     if (e.has_halo) {
       hr = r_in[e.hgl];
@@ -688,11 +700,11 @@ __global__ __launch_bounds__(kBV) void k_pcg_step(
     const T qv = c0 * pn + c1 * apply19(s, e.C, k18);
     if (e.live) {
       if (!first) {
-        x[e.g] = xg + alpha * pg;
-        r_out[e.g] = rn;
+        st_stream<NT>(x + e.g, xg + alpha * pg);
+        st_stream<NT>(r_out + e.g, rn);
       }
-      p_out[e.g] = pn;
-      q_out[e.g] = qv;
+      st_stream<NT>(p_out + e.g, pn);
+      st_stream<NT>(q_out + e.g, qv);
     }
     const double dr = rn, dz = zn, dp = pn, dq = qv;
     acc[0] += dp * dq;
@@ -1215,10 +1227,10 @@ void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v
                     const T* d3, T q2, T q3, T q4, T* bout, T* dout, T* qout, T* x, T* wout,
                     T* r, IonicT<T> ion, T dt, T* tact, T theta, double tprev, int check_prev,
                     int* flags, CGScalars* cout, double* parts, double tol2, int maxit) {
-  k_be_init<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, bprev, qin, kd, d2, d3,
-                                              q2, q3, q4, bout, dout, qout, x, wout, r, ion, dt,
-                                              tact, theta, tprev, check_prev, flags, cout, parts,
-                                              tol2, maxit, L.rowsn);
+  auto k = L.stream_nt ? k_be_init<T, true> : k_be_init<T, false>;
+  k<<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, bprev, qin, kd, d2, d3, q2, q3, q4,
+                                   bout, dout, qout, x, wout, r, ion, dt, tact, theta, tprev,
+                                   check_prev, flags, cout, parts, tol2, maxit, L.rowsn);
 }
 
 template <typename T>
@@ -1237,9 +1249,9 @@ void launch_pcg_step(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c
                      T* q_out, int first, const CGScalars* cin, CGScalars* cout,
                      const double* prev, double* parts, unsigned long long* mirror,
                      unsigned seq) {
-  k_pcg_step<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, c0, c1, dinv, x, r_in, r_out, p_in,
-                                               p_out, q_in, q_out, first, cin, cout, prev, parts,
-                                               L.rowsn, mirror, seq);
+  auto k = L.stream_nt ? k_pcg_step<T, true> : k_pcg_step<T, false>;
+  k<<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, c0, c1, dinv, x, r_in, r_out, p_in, p_out, q_in,
+                                   q_out, first, cin, cout, prev, parts, L.rowsn, mirror, seq);
 }
 
 void launch_reduce_sum(hipStream_t s, const double* partials, int nparts, int K, double* out) {

@@ -1040,6 +1040,8 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   g->L.nb = nb;
   g->L.grid = g->grid;
   g->L.pgrid = pgrid_for(nb, g->prec == EP_F64);
+  g->L.stream_nt = static_cast<long long>(kBeArrays) * (nb + 1) * kBV *
+                       (g->prec == EP_F64 ? 8 : 4) > kLlcBytes;
   g->L.stream = g->stream;
   if (g->model == EP_BIDO && tissue_components(boxmask, g->n) != 1)
     return fail(g, EP_ERR_ARG, "bidomain tissue must be one face-connected component");
