@@ -194,6 +194,20 @@ EP_API ep_status ep_adjoint_scale(ep_grid g, int32_t nsteps, int32_t ckpt_every,
  * Errors: EP_ERR_ARG (NULL, n too small, bad field), EP_ERR_HIP. */
 EP_API ep_status ep_read_state(ep_grid g, ep_field f, double* host_out, size_t n);
 
+/* Copy a field into caller-owned device memory in box layout (n0*n1*n2
+ * entries, z fastest) as FP64 (dtype 0) or FP32 (dtype 1); non-tissue
+ * voxels read 0 (v, w, phi) or +inf (T_act).  The state stays on the GPU:
+ * the thesis keeps all allocation and arithmetic on the device and moves
+ * buffers only to produce output (GPU Computation chapter, PCI Bus
+ * subsection); this hands a field to device-side consumers (e.g. a torch
+ * tensor) without the host round trip.  dptr must be device memory of this
+ * GPU holding n0*n1*n2 elements of the dtype; it is borrowed for the call.
+ * The copy is enqueued on the grid's stream and the call returns without
+ * waiting: order later reads after that stream (or create the grid on the
+ * consumer's stream).  Errors: EP_ERR_ARG (NULL, bad field or dtype),
+ * EP_ERR_HIP. */
+EP_API ep_status ep_read_state_device(ep_grid g, ep_field f, void* dptr, int32_t dtype);
+
 /* Overwrite a field from host FP64 in box layout; values at non-tissue
  * voxels are ignored.  Clears the sticky non-finite flag.  For EP_TACT,
  * +inf marks "not yet activated". */

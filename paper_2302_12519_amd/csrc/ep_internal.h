@@ -138,6 +138,12 @@ void launch_pcg_step(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c
                      unsigned seq);
 constexpr int kMaxPartials = 7;   // partial sums per block of any CG launch
 
+// field (brick layout, T) -> caller's device buffer in box layout (O);
+// brick_id: box brick -> brick id or -1; fill for non-tissue voxels
+template <typename T, typename O>
+void launch_box_gather(hipStream_t s, const int n[3], int nby, int nbz, const int* brick_id,
+                       const T* src, const uint8_t* mask, O* out, O fill);
+
 // out[k] = sum of partials[k*nparts .. (k+1)*nparts) in a fixed order
 void launch_reduce_sum(hipStream_t s, const double* partials, int nparts, int K, double* out);
 void launch_block_max(const LaunchCfg& L, const int* nbr, CoefSet<double> c,

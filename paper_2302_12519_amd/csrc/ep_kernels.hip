@@ -123,6 +123,31 @@ __device__ __forceinline__ void sum_prev(const double* __restrict__ parts, int n
   __syncthreads();
 }
 
+// A field in brick layout -> box layout (z fastest) in a caller's device
+// buffer, converted to O; voxels that are not tissue get `fill`.
+template <typename T, typename O>
+__global__ __launch_bounds__(256) void k_box_gather(int n0, int n1, int n2, int nby, int nbz,
+                                                    const int* __restrict__ brick_id,
+                                                    const T* __restrict__ src,
+                                                    const uint8_t* __restrict__ mask,
+                                                    O* __restrict__ out, O fill) {
+  const int64_t N = static_cast<int64_t>(n0) * n1 * n2;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < N;
+       i += stride) {
+    const int z = static_cast<int>(i % n2);
+    const int64_t t = i / n2;
+    const int y = static_cast<int>(t % n1), x = static_cast<int>(t / n1);
+    const int b = brick_id[(static_cast<int64_t>(x >> 3) * nby + (y >> 3)) * nbz + (z >> 3)];
+    O v = fill;
+    if (b >= 0) {
+      const int64_t g = static_cast<int64_t>(b) * kBV + (((x & 7) * 8 + (y & 7)) * 8 + (z & 7));
+      if (mask[g]) v = static_cast<O>(src[g]);
+    }
+    out[i] = v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // coefficient encoding (once per conductivity change)
 // ---------------------------------------------------------------------------
@@ -1253,6 +1278,24 @@ void launch_pcg_step(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c
   k<<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, c0, c1, dinv, x, r_in, r_out, p_in, p_out, q_in,
                                    q_out, first, cin, cout, prev, parts, L.rowsn, mirror, seq);
 }
+
+template <typename T, typename O>
+void launch_box_gather(hipStream_t s, const int n[3], int nby, int nbz, const int* brick_id,
+                       const T* src, const uint8_t* mask, O* out, O fill) {
+  const int64_t N = static_cast<int64_t>(n[0]) * n[1] * n[2];
+  const int64_t want = (N + 255) / 256;
+  const int blocks = static_cast<int>(want < 8192 ? want : 8192);
+  k_box_gather<T, O><<<blocks, 256, 0, s>>>(n[0], n[1], n[2], nby, nbz, brick_id, src, mask, out,
+                                            fill);
+}
+template void launch_box_gather<float, float>(hipStream_t, const int*, int, int, const int*,
+                                              const float*, const uint8_t*, float*, float);
+template void launch_box_gather<float, double>(hipStream_t, const int*, int, int, const int*,
+                                               const float*, const uint8_t*, double*, double);
+template void launch_box_gather<double, float>(hipStream_t, const int*, int, int, const int*,
+                                               const double*, const uint8_t*, float*, float);
+template void launch_box_gather<double, double>(hipStream_t, const int*, int, int, const int*,
+                                                const double*, const uint8_t*, double*, double);
 
 void launch_reduce_sum(hipStream_t s, const double* partials, int nparts, int K, double* out) {
   k_reduce<<<1, kRedThreads, 0, s>>>(partials, nparts, K, out);

@@ -84,6 +84,7 @@ struct ep_grid_s {
   int* d_nbr = nullptr;
   uint64_t* d_rowsn = nullptr;
   uint8_t* d_mask = nullptr;
+  int* d_brick_id = nullptr;   // box brick -> brick id or -1 (device reads into box layout)
   void* d_v[2] = {nullptr, nullptr};
   void* d_w[2] = {nullptr, nullptr};
   void* d_tact = nullptr;
@@ -1054,6 +1055,7 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   TRY(dalloc(g, &g->d_rowsn, bm.rowsn.size() * sizeof(uint64_t)));
   g->L.rowsn = g->d_rowsn;
   TRY(dalloc(g, &g->d_mask, static_cast<size_t>(g->nvox)));
+  TRY(dalloc(g, &g->d_brick_id, g->brick_id.size() * sizeof(int)));
   for (int k = 0; k < 2; ++k) {
     TRY(dalloc(g, &g->d_v[k], vb));
     TRY(dalloc(g, &g->d_w[k], vb));
@@ -1120,6 +1122,8 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   HIPCHK(g, hipMemcpyAsync(g->d_nbr, hnbr.data(), hnbr.size() * sizeof(int),
                            hipMemcpyHostToDevice, g->stream));
   HIPCHK(g, hipMemcpyAsync(g->d_rowsn, bm.rowsn.data(), bm.rowsn.size() * sizeof(uint64_t),
+                           hipMemcpyHostToDevice, g->stream));
+  HIPCHK(g, hipMemcpyAsync(g->d_brick_id, g->brick_id.data(), g->brick_id.size() * sizeof(int),
                            hipMemcpyHostToDevice, g->stream));
   HIPCHK(g, hipMemcpyAsync(g->d_mask, g->hmask.data(), g->hmask.size(), hipMemcpyHostToDevice,
                            g->stream));
@@ -1427,6 +1431,39 @@ EP_API ep_status ep_read_state(ep_grid g, ep_field f, double* host_out, size_t n
   } catch (const std::bad_alloc&) {
     return fail(g, EP_ERR_OOM, "host allocation failed");
   }
+}
+
+EP_API ep_status ep_read_state_device(ep_grid g, ep_field f, void* dptr, int32_t dtype) {
+  if (!g || !dptr) return EP_ERR_ARG;
+  if (f < EP_V || f > EP_TACT) return fail(g, EP_ERR_ARG, "bad field");
+  if (dtype != 0 && dtype != 1) return fail(g, EP_ERR_ARG, "dtype must be 0 (FP64) or 1 (FP32)");
+  const void* src = nullptr;
+  switch (f) {
+    case EP_V: src = g->d_v[g->cur]; break;
+    case EP_W: src = g->d_w[g->cur]; break;
+    case EP_PHIE: src = g->d_phi; break;
+    case EP_TACT: src = g->d_tact; break;
+  }
+  const double fill = (f == EP_TACT) ? kInf : 0.0;
+  const bool src64 = (f == EP_PHIE) || g->prec == EP_F64;
+  if (src64 && dtype == 0)
+    launch_box_gather<double, double>(g->stream, g->n, g->nby, g->nbz, g->d_brick_id,
+                                      static_cast<const double*>(src), g->d_mask,
+                                      static_cast<double*>(dptr), fill);
+  else if (src64)
+    launch_box_gather<double, float>(g->stream, g->n, g->nby, g->nbz, g->d_brick_id,
+                                     static_cast<const double*>(src), g->d_mask,
+                                     static_cast<float*>(dptr), static_cast<float>(fill));
+  else if (dtype == 0)
+    launch_box_gather<float, double>(g->stream, g->n, g->nby, g->nbz, g->d_brick_id,
+                                     static_cast<const float*>(src), g->d_mask,
+                                     static_cast<double*>(dptr), fill);
+  else
+    launch_box_gather<float, float>(g->stream, g->n, g->nby, g->nbz, g->d_brick_id,
+                                    static_cast<const float*>(src), g->d_mask,
+                                    static_cast<float*>(dptr), static_cast<float>(fill));
+  HIPCHK(g, hipGetLastError());
+  return EP_OK;
 }
 
 EP_API ep_status ep_write_state(ep_grid g, ep_field f, const double* host_in, size_t n) {

@@ -93,6 +93,7 @@ def _load():
     lib.ep_step.argtypes = [vp, C.c_int32, C.POINTER(StepInfo)]
     lib.ep_solve_elliptic.argtypes = [vp, C.c_double, C.c_int32, C.POINTER(SolveInfo)]
     lib.ep_read_state.argtypes = [vp, C.c_int, vp, C.c_size_t]
+    lib.ep_read_state_device.argtypes = [vp, C.c_int, vp, C.c_int32]
     lib.ep_write_state.argtypes = [vp, C.c_int, vp, C.c_size_t]
     lib.ep_get_step.argtypes = [vp, C.POINTER(C.c_int64)]
     lib.ep_set_step.argtypes = [vp, C.c_int64]
@@ -120,7 +121,8 @@ def _load():
     lib.ep_batch_last_error.argtypes = [vp]
     lib.ep_batch_last_error.restype = C.c_char_p
     for name in ("ep_create_grid", "ep_set_conductivity_fibres", "ep_step", "ep_solve_elliptic",
-                 "ep_read_state", "ep_write_state", "ep_get_step", "ep_set_step",
+                 "ep_read_state", "ep_read_state_device", "ep_write_state", "ep_get_step",
+                 "ep_set_step",
                  "ep_grid_stats", "ep_kernel_timing", "ep_kernel_time", "ep_destroy_grid",
                  "ep_adjoint_scale",
                  "ep_batch_create", "ep_batch_submit", "ep_batch_advance", "ep_batch_finished",
@@ -258,6 +260,21 @@ class Grid:
         out = np.empty(self.N, dtype=np.float64)
         self._check(lib.ep_read_state(self._h, FIELDS[field], _p(out), self.N), "ep_read_state")
         return out.reshape(self.n)
+
+    def read_tensor(self, field, dtype=None):
+        """The field as a torch tensor on the GPU (box layout, shape n),
+        copied device to device by the library; FP32 unless dtype is
+        torch.float64.  Waits for the copy before returning."""
+        import torch
+        dtype = torch.float32 if dtype is None else dtype
+        if dtype not in (torch.float32, torch.float64):
+            raise ValueError("dtype must be torch.float32 or torch.float64")
+        out = torch.empty(self.n, dtype=dtype, device="cuda")
+        self._check(lib.ep_read_state_device(self._h, FIELDS[field], C.c_void_p(out.data_ptr()),
+                                             0 if dtype == torch.float64 else 1),
+                    "ep_read_state_device")
+        torch.cuda.synchronize()
+        return out
 
     def write(self, field, values):
         a = np.ascontiguousarray(values, dtype=np.float64).ravel()

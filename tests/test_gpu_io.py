@@ -1,0 +1,50 @@
+"""GPU test of ep_read_state_device: fields written in box layout straight
+into device memory (a torch tensor) agree with the host read."""
+import numpy as np
+import pytest
+
+import ep_inputs as E
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2302_12519_amd as P
+    return P
+
+
+def be_shell(n, n_stim=3, prec="f64", seed=9):
+    shape, mask, fib, stims = E.shell(n, seed, n_stim)
+    return E.Instance(name=f"shell{n}", n=shape, h=0.25, dt=0.05, steps=0, mask=mask, fibre=fib,
+                      scale=None, sigma_l=0.2, sigma_t=0.05, sigma_el=0.0, sigma_et=0.0,
+                      stims=stims, model="mono", diff="be_pcg", prec=prec)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_read_state_device_matches_host_read(P, prec):
+    """ep_read_state_device writes every field in box layout into a torch
+    tensor: the same values as ep_read_state (FP64 output bitwise, FP32
+    output the rounded values), 0 / +inf outside tissue."""
+    import torch
+    inst = be_shell(17, prec=prec) if prec == "f64" else E.aniso_be(24, steps=20)
+    say(f"case device read {prec}")
+    g = P.Grid.from_instance(inst)
+    g.step(15)
+    for f in ("v", "w", "tact", "phi"):
+        host = g.read(f)
+        d64 = g.read_tensor(f, torch.float64).cpu().numpy()
+        d32 = g.read_tensor(f, torch.float32).cpu().numpy()
+        assert d64.shape == tuple(inst.n)
+        assert np.array_equal(d64, host, equal_nan=True), f
+        assert np.array_equal(d32, host.astype(np.float32), equal_nan=True), f
+        outside = inst.mask == 0
+        fill = np.inf if f == "tact" else 0.0
+        assert np.all(d64[outside] == fill), f
+    g.close()

@@ -114,3 +114,4 @@ def test_be_pcg_fp32_bitwise_reproducible(P):
     assert i1 == i2
     assert np.array_equal(v1, v2) and np.array_equal(w1, w2)
     assert np.array_equal(t1, t2, equal_nan=True)
+
