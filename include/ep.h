@@ -98,6 +98,16 @@ typedef struct {
   int32_t ell_inner_maxit;   /* max inner FP32 PCG iterations per outer */
   void* stream;              /* hipStream_t (e.g. a torch stream) or NULL for
                                 the library's own stream */
+  void* arena;               /* optional caller-owned device memory (e.g. a
+                                torch tensor): when not NULL every device
+                                array of the grid, the adjoint work block
+                                included, is carved from it and nothing is
+                                allocated; the caller keeps it alive until
+                                ep_destroy_grid.  NULL: the grid allocates */
+  int64_t arena_bytes;       /* size of arena; too small -> EP_ERR_OOM (a grid
+                                created without an arena reports its size in
+                                ep_grid_stats' device_bytes).  Ignored by
+                                ep_batch_submit */
 } ep_grid_desc;
 
 typedef struct {
@@ -217,7 +227,10 @@ EP_API ep_status ep_write_state(ep_grid g, ep_field f, const double* host_in, si
 EP_API ep_status ep_get_step(ep_grid g, int64_t* step);
 EP_API ep_status ep_set_step(ep_grid g, int64_t step);
 
-/* Counts: tissue voxels, active 8x8x8 bricks, device bytes held. */
+/* Counts: tissue voxels, active 8x8x8 bricks, and device_bytes: the most
+ * device memory the grid has held at once, the temporaries of earlier calls
+ * (conductivity encoding, adjoint work block) included -- an arena of that
+ * size serves the same sequence of calls. */
 EP_API ep_status ep_grid_stats(ep_grid g, int64_t* n_tissue, int64_t* n_bricks,
                                int64_t* device_bytes);
 

@@ -80,7 +80,12 @@ struct ep_grid_s {
 
   // device
   std::vector<void*> allocs;
-  int64_t dev_bytes = 0;
+  int64_t dev_bytes = 0;       // device bytes held now (256-byte granules)
+  int64_t dev_peak = 0;        // the most held at once, call temporaries included
+  // caller-owned arena (nullptr: the grid allocates)
+  char* arena = nullptr;
+  int64_t arena_bytes = 0, arena_used = 0;
+  bool adj_in_arena = false;
   int* d_nbr = nullptr;
   uint64_t* d_rowsn = nullptr;
   uint8_t* d_mask = nullptr;
@@ -184,22 +189,68 @@ size_t elem_size(ep_prec p) { return p == EP_F64 ? sizeof(double) : sizeof(float
 
 template <typename P>
 ep_status dalloc(ep_grid g, P** out, size_t bytes) {
+  const size_t rb = (bytes + 255) & ~static_cast<size_t>(255);
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(g, EP_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  if (g->arena) {
+    if (g->arena_used + static_cast<int64_t>(rb) > g->arena_bytes)
+      return fail(g, EP_ERR_OOM, "arena of " + std::to_string(g->arena_bytes) +
+                                     " bytes is too small (" +
+                                     std::to_string(g->arena_used + static_cast<int64_t>(rb)) +
+                                     " bytes needed so far)");
+    p = g->arena + g->arena_used;
+  } else {
+    hipError_t e = hipMalloc(&p, rb);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(g, EP_ERR_OOM, "hipMalloc of " + std::to_string(rb) + " bytes failed");
+    }
   }
-  e = hipMemsetAsync(p, 0, bytes, g->stream);
+  hipError_t e = hipMemsetAsync(p, 0, rb, g->stream);
   if (e != hipSuccess) {
-    (void)hipFree(p);
+    if (!g->arena) (void)hipFree(p);
     return fail(g, EP_ERR_HIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e));
   }
-  g->allocs.push_back(p);
-  g->dev_bytes += static_cast<int64_t>(bytes);
+  if (g->arena) g->arena_used += static_cast<int64_t>(rb);
+  else g->allocs.push_back(p);
+  g->dev_bytes += static_cast<int64_t>(rb);
+  g->dev_peak = std::max(g->dev_peak, g->dev_bytes);
   *out = static_cast<P*>(p);
   return EP_OK;
 }
+
+// Device temporaries of one call: carved from the arena above its current
+// use and given back when the call ends, or hipMalloc'd and freed.  The
+// owner synchronises the grid's stream before they go.
+struct Temps {
+  ep_grid g;
+  int64_t mark, held = 0;
+  std::vector<void*> mine;
+  explicit Temps(ep_grid gg) : g(gg), mark(gg->arena_used) {}
+  Temps(const Temps&) = delete;
+  Temps& operator=(const Temps&) = delete;
+  template <typename P>
+  hipError_t get(P** out, size_t bytes) {
+    const size_t rb = (bytes + 255) & ~static_cast<size_t>(255);
+    void* p = nullptr;
+    if (g->arena) {
+      if (g->arena_used + static_cast<int64_t>(rb) > g->arena_bytes) return hipErrorOutOfMemory;
+      p = g->arena + g->arena_used;
+      g->arena_used += static_cast<int64_t>(rb);
+    } else {
+      const hipError_t e = hipMalloc(&p, rb);
+      if (e != hipSuccess) return e;
+      mine.push_back(p);
+    }
+    held += static_cast<int64_t>(rb);
+    g->dev_peak = std::max(g->dev_peak, g->dev_bytes + held);
+    *out = static_cast<P*>(p);
+    return hipSuccess;
+  }
+  ~Temps() {
+    if (g->arena) g->arena_used = mark;
+    for (void* p : mine) (void)hipFree(p);
+  }
+};
 
 #define TRY(expr)                     \
   do {                                \
@@ -730,19 +781,31 @@ ep_status adjoint_impl(ep_grid g, int32_t nsteps, int32_t K, const double* tstar
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t need = al(nv * sizeof(double)) + al(nv * sizeof(int)) + n_arr * al(vb);
   if (need > g->adj_cap) {
-    if (g->d_adj) {
+    if (g->d_adj && !g->adj_in_arena) {
       HIPCHK(g, hipStreamSynchronize(g->stream));
       (void)hipFree(g->d_adj);
-      g->d_adj = nullptr;
-      g->adj_cap = 0;
+      g->dev_bytes -= static_cast<int64_t>(g->adj_cap);
     }
-    if (hipMalloc(&g->d_adj, need) != hipSuccess) {
+    g->d_adj = nullptr;
+    g->adj_cap = 0;
+    if (g->arena) {
+      // carved for good: a later, larger call takes a new block above it
+      const int64_t rb = static_cast<int64_t>(al(need));
+      if (g->arena_used + rb > g->arena_bytes)
+        return fail(g, EP_ERR_OOM, "adjoint work block of " + std::to_string(need) +
+                                       " bytes does not fit in the arena");
+      g->d_adj = g->arena + g->arena_used;
+      g->arena_used += rb;
+      g->adj_in_arena = true;
+    } else if (hipMalloc(&g->d_adj, need) != hipSuccess) {
       (void)hipGetLastError();
       g->d_adj = nullptr;
       return fail(g, EP_ERR_OOM, "adjoint work block of " + std::to_string(need) +
                                      " bytes does not fit; raise ckpt_every or lower nsteps");
     }
     g->adj_cap = need;
+    g->dev_bytes += static_cast<int64_t>(al(need));
+    g->dev_peak = std::max(g->dev_peak, g->dev_bytes);
   }
   char* base = static_cast<char*>(g->d_adj);
   size_t off = 0;
@@ -906,8 +969,11 @@ ep_status check_explicit_stability(ep_grid g, double* const c64[6]) {
   if (g->dt * gersh < 2.0) return EP_OK;
   double *x = nullptr, *y = nullptr;
   const size_t bytes = static_cast<size_t>(g->nvox) * sizeof(double);
-  TRY(dalloc(g, &x, bytes));
-  TRY(dalloc(g, &y, bytes));
+  Temps tmp(g);
+  if (tmp.get(&x, bytes) != hipSuccess || tmp.get(&y, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(g, EP_ERR_OOM, "no device memory for the stability estimate");
+  }
   std::vector<double> hx(g->nvox, 0.0);
   uint64_t st = 0x9E3779B97F4A7C15ull;
   for (int64_t i = 0; i < g->nb * (int64_t)kBV; ++i) {
@@ -979,6 +1045,8 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   if (d->model == EP_BIDO && d->diff != EP_DIFF_EXPLICIT)
     return fail(g, EP_ERR_UNSUPPORTED, "bidomain parabolic part is explicit only");
   if (d->n_stim < 0 || (d->n_stim > 0 && !d->stim)) return fail(g, EP_ERR_ARG, "bad stimuli");
+  if (d->arena && (d->arena_bytes <= 0 || reinterpret_cast<uintptr_t>(d->arena) % 256 != 0))
+    return fail(g, EP_ERR_ARG, "arena must be 256-byte aligned with arena_bytes > 0");
   const ep_ionic& io = d->ionic;
   if (!(io.tau_in > 0) || !(io.tau_out > 0) || !(io.tau_open > 0) || !(io.tau_close > 0) ||
       !std::isfinite(io.v_gate) || !std::isfinite(io.exc) || io.exc < 0)
@@ -998,6 +1066,8 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   }
 
   std::copy(d->n, d->n + 3, g->n);
+  g->arena = static_cast<char*>(d->arena);
+  g->arena_bytes = d->arena ? d->arena_bytes : 0;
   g->h = d->h;
   g->dt = d->dt;
   g->model = d->model;
@@ -1239,23 +1309,19 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
   if (bad.load() == 2) return fail(g, EP_ERR_ARG, "scale must be finite and > 0 on tissue");
   double *dfib = nullptr, *dsc = nullptr, *tens = nullptr;
   const size_t b64 = static_cast<size_t>(g->nvox) * sizeof(double);
-  hipError_t e = hipMalloc(&dfib, 3 * b64);
-  if (e == hipSuccess && scale) e = hipMalloc(&dsc, b64);
-  if (e == hipSuccess) e = hipMalloc(&tens, 6 * b64);
+  Temps tmp(g);
+  hipError_t e = tmp.get(&dfib, 3 * b64);
+  if (e == hipSuccess && scale) e = tmp.get(&dsc, b64);
+  if (e == hipSuccess) e = tmp.get(&tens, 6 * b64);
   double* tmp64[6] = {};
   const bool need64 = (g->prec == EP_F64) || g->model == EP_BIDO || g->diff == EP_DIFF_EXPLICIT;
   if (e == hipSuccess && need64)
-    for (int k = 0; k < 6 && e == hipSuccess; ++k) e = hipMalloc(&tmp64[k], b64);
-  auto cleanup = [&]() {
-    (void)hipFree(dfib);
-    (void)hipFree(dsc);
-    (void)hipFree(tens);
-    for (int k = 0; k < 6; ++k) (void)hipFree(tmp64[k]);
-  };
+    for (int k = 0; k < 6 && e == hipSuccess; ++k) e = tmp.get(&tmp64[k], b64);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    cleanup();
-    return fail(g, EP_ERR_OOM, "temporary allocation for coefficient encoding failed");
+    return fail(g, EP_ERR_OOM, g->arena ? "arena too small for the coefficient-encoding "
+                                          "temporaries (ep_grid_stats reports the peak)"
+                                        : "temporary allocation for coefficient encoding failed");
   }
   ep_status rc = EP_OK;
   do {
@@ -1323,7 +1389,6 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
     }
   } while (false);
   (void)hipStreamSynchronize(g->stream);
-  cleanup();
   if (rc == EP_OK) g->has_cond = true;
   g->have_bprev = false;
   g->pred_len = 0;
@@ -1511,7 +1576,7 @@ EP_API ep_status ep_grid_stats(ep_grid g, int64_t* n_tissue, int64_t* n_bricks,
   if (!g) return EP_ERR_ARG;
   if (n_tissue) *n_tissue = g->n_tissue;
   if (n_bricks) *n_bricks = g->nb;
-  if (device_bytes) *device_bytes = g->dev_bytes;
+  if (device_bytes) *device_bytes = g->dev_peak;
   return EP_OK;
 }
 
@@ -1538,7 +1603,7 @@ EP_API ep_status ep_destroy_grid(ep_grid g) {
   if (!g) return EP_ERR_ARG;
   if (g->stream) (void)hipStreamSynchronize(g->stream);
   for (void* p : g->allocs) (void)hipFree(p);
-  if (g->d_adj) (void)hipFree(g->d_adj);
+  if (g->d_adj && !g->adj_in_arena) (void)hipFree(g->d_adj);
   for (int k = 0; k < kTimers; ++k)
     for (auto& tp : g->tk[k]) {
       (void)hipEventDestroy(tp.a);

@@ -57,7 +57,7 @@ class GridDesc(C.Structure):
                 ("act_threshold", C.c_double), ("pcg_rtol", C.c_double),
                 ("pcg_maxit", C.c_int32), ("ell_rtol", C.c_double),
                 ("ell_max_outer", C.c_int32), ("ell_inner_maxit", C.c_int32),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("arena", C.c_void_p), ("arena_bytes", C.c_int64)]
 
 
 class StepInfo(C.Structure):
@@ -140,9 +140,11 @@ def _p(a):
 
 def make_desc(n, h, dt, mask=None, model="mono", prec="f32", diff="explicit", ionic=None,
               stims=(), theta=0.5, pcg_rtol=1e-6, pcg_maxit=50, ell_rtol=1e-8,
-              ell_max_outer=8, ell_inner_maxit=4000, stream=None):
+              ell_max_outer=8, ell_inner_maxit=4000, stream=None, arena=None):
     """Fill an ep_grid_desc; returns it and the arrays it points into (keep
-    them alive while the descriptor is used)."""
+    them alive while the descriptor is used).  arena: optional caller-owned
+    device memory, a torch CUDA tensor whose bytes the grid carves its
+    arrays from (kept alive by the returned list)."""
     n = tuple(int(k) for k in n)
     N = int(np.prod(n))
     d = GridDesc()
@@ -180,6 +182,12 @@ def make_desc(n, h, dt, mask=None, model="mono", prec="f32", diff="explicit", io
     d.ell_rtol, d.ell_max_outer = float(ell_rtol), int(ell_max_outer)
     d.ell_inner_maxit = int(ell_inner_maxit)
     d.stream = stream
+    if arena is not None:
+        if not getattr(arena, "is_cuda", False) or not arena.is_contiguous():
+            raise ValueError("arena must be a contiguous CUDA tensor")
+        keep.append(arena)
+        d.arena = C.c_void_p(arena.data_ptr())
+        d.arena_bytes = int(arena.numel() * arena.element_size())
     return d, keep
 
 
@@ -188,10 +196,11 @@ class Grid:
 
     def __init__(self, n, h, dt, mask=None, model="mono", prec="f32", diff="explicit",
                  ionic=None, stims=(), theta=0.5, pcg_rtol=1e-6, pcg_maxit=50,
-                 ell_rtol=1e-8, ell_max_outer=8, ell_inner_maxit=4000, stream=None):
+                 ell_rtol=1e-8, ell_max_outer=8, ell_inner_maxit=4000, stream=None,
+                 arena=None):
         self._desc, keep = make_desc(n, h, dt, mask, model, prec, diff, ionic, stims, theta,
                                      pcg_rtol, pcg_maxit, ell_rtol, ell_max_outer,
-                                     ell_inner_maxit, stream)
+                                     ell_inner_maxit, stream, arena)
         self._keep = keep
         self.n = tuple(int(k) for k in n)
         self.N = int(np.prod(self.n))

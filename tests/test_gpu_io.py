@@ -48,3 +48,28 @@ def test_read_state_device_matches_host_read(P, prec):
         fill = np.inf if f == "tact" else 0.0
         assert np.all(d64[outside] == fill), f
     g.close()
+
+
+def test_grid_in_caller_arena_matches_own_allocation(P):
+    """A grid built inside a caller-owned torch buffer (ep_grid_desc.arena)
+    gives bitwise the same run as one that allocates, takes no more than the
+    peak ep_grid_stats reported, and a too-small arena is EP_ERR_OOM."""
+    import torch
+    inst = E.aniso_be(32, steps=60)
+    say("case arena grid aniso_be_32 fp32")
+    ref = P.Grid.from_instance(inst)
+    ref.step(60)
+    v_ref, t_ref = ref.read("v"), ref.read("tact")
+    need = ref.stats()["device_bytes"]
+    ref.close()
+    arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+    g = P.Grid.from_instance(inst, arena=arena)
+    g.step(60)
+    assert np.array_equal(g.read("v"), v_ref)
+    assert np.array_equal(g.read("tact"), t_ref, equal_nan=True)
+    assert g.stats()["device_bytes"] <= need
+    g.close()
+    small = torch.empty(need // 2, dtype=torch.uint8, device="cuda")
+    with pytest.raises(P.EPError) as e:
+        P.Grid.from_instance(inst, arena=small)
+    assert e.value.status == P.ep.EP_ERR_OOM
