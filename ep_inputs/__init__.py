@@ -68,13 +68,14 @@ class Instance:
     sigma_et: float = 0.0
     stims: List[Stim] = dataclasses.field(default_factory=list)
     model: str = "mono"           # "mono" | "bido"
-    diff: str = "explicit"        # "explicit" | "be_pcg"
+    diff: str = "explicit"        # "explicit" | "be_pcg" | "be_jacobi"
     prec: str = "f32"             # "f32" | "f64"
     ionic: dict = dataclasses.field(default_factory=lambda: dict(MS_DEFAULT))
     theta: float = 0.5
     pcg_rtol: float = 1e-6
     pcg_maxit: int = 50
     ell_rtol: float = 1e-8
+    jacobi_sweeps: int = 10       # "be_jacobi": fixed Jacobi sweeps per step
 
     @property
     def nb(self) -> int:

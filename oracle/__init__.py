@@ -41,7 +41,7 @@ class Problem(C.Structure):
                 ("exc", C.c_double), ("model", C.c_int32), ("diff", C.c_int32),
                 ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32), ("n_stim", C.c_int32),
                 ("stim", C.POINTER(Stim)), ("mask", C.c_void_p), ("Di", C.c_void_p),
-                ("De", C.c_void_p)]
+                ("De", C.c_void_p), ("jacobi_sweeps", C.c_int32)]
 
 
 class State(C.Structure):
@@ -160,7 +160,8 @@ class Oracle:
         self.P.tau_open, self.P.tau_close = io["tau_open"], io["tau_close"]
         self.P.v_gate, self.P.exc = io["v_gate"], io["exc"]
         self.P.model = 1 if inst.model == "bido" else 0
-        self.P.diff = 1 if inst.diff == "be_pcg" else 0
+        self.P.diff = {"explicit": 0, "be_pcg": 1, "be_jacobi": 2}[inst.diff]
+        self.P.jacobi_sweeps = int(getattr(inst, "jacobi_sweeps", 0))
         self.P.cg_rtol, self.P.cg_maxit = cg_rtol, cg_maxit
         self.P.n_stim = len(st)
         self.P.stim = C.cast(self._stims, C.POINTER(Stim))

@@ -28,7 +28,8 @@
  *   - Monodomain (eqn:monodomain1, chi_m*C_m = 1, lambda/(1+lambda) folded
  *     into D): v_{n+1} = v* + dt A v* (explicit) or (I - dt A) v_{n+1} = v*
  *     (implicit Euler: Linear Solver section, "Implicit Euler"), solved here
- *     by Jacobi-preconditioned CG.
+ *     by Jacobi-preconditioned CG to a tolerance, or by the thesis's own fixed
+ *     number of Jacobi sweeps (eqn:iejac1).
  *   - Bidomain (eqn:bidomain1, heart only, v_i = v + phi_e):
  *     -(A_i + A_e) phi = A_i v*, sum_tissue phi = 0;  v_{n+1} = v* + dt A_i(v* + phi).
  *   - Activation time: first step with v_n < theta <= v_{n+1}; linear
@@ -69,7 +70,8 @@ typedef struct {
   double h, dt, theta;
   double tau_in, tau_out, tau_open, tau_close, v_gate, exc;
   int32_t model;      /* 0 monodomain, 1 bidomain */
-  int32_t diff;       /* 0 explicit, 1 implicit Euler by PCG (monodomain) */
+  int32_t diff;       /* 0 explicit, 1 implicit Euler by PCG, 2 implicit Euler
+                         by a fixed number of Jacobi sweeps (monodomain) */
   double cg_rtol;
   int32_t cg_maxit;
   int32_t n_stim;
@@ -77,6 +79,7 @@ typedef struct {
   const uint8_t* mask;
   const double* Di;   /* 6*N voxel tensors (monodomain D, or intracellular) */
   const double* De;   /* 6*N extracellular tensors (bidomain) */
+  int32_t jacobi_sweeps;  /* diff 2: sweeps per step */
 } orc_problem;
 
 typedef struct {
@@ -461,6 +464,11 @@ int orc_run(const orc_problem* P, orc_state* S, int32_t nsteps, orc_info* info) 
     orc_diag(P->n, P->h, P->mask, P->Di, dinv);
     for (int64_t p = 0; p < N; ++p) dinv[p] = 1.0 / (1.0 - P->dt * dinv[p]);
   }
+  double* dA = NULL;   /* diagonal of A, for the Jacobi sweeps */
+  if (P->model == 0 && P->diff == 2) {
+    dA = (double*)malloc((size_t)N * sizeof(double));
+    orc_diag(P->n, P->h, P->mask, P->Di, dA);
+  }
   for (int32_t s = 0; s < nsteps; ++s) {
     const int64_t step = S->step;
     /* reaction: one explicit Euler step of the ionic model */
@@ -473,6 +481,22 @@ int orc_run(const orc_problem* P, orc_state* S, int32_t nsteps, orc_info* info) 
     if (P->model == 0 && P->diff == 0) {
       orc_apply(P->n, P->h, P->mask, P->Di, vs, a);
       for (int64_t p = 0; p < N; ++p) vn[p] = vs[p] + P->dt * a[p];
+    } else if (P->model == 0 && P->diff == 2) {
+      /* implicit Euler by a fixed number of Jacobi sweeps (Linear Solver
+       * section, "Implicit Euler", eqn:iejac1): with D the diagonal of A and
+       * L + U the rest, u^{k+1} = [I - dt D]^-1 [u^t + dt (L + U) u^k],
+       * starting from u^0 = u^t, which under operator splitting is v*. */
+      memcpy(vn, vs, (size_t)N * sizeof(double));
+      for (int32_t k = 0; k < P->jacobi_sweeps; ++k) {
+        orc_apply(P->n, P->h, P->mask, P->Di, vn, a);
+        for (int64_t p = 0; p < N; ++p) {
+          const double lu = a[p] - dA[p] * vn[p];
+          tmp[p] = (vs[p] + P->dt * lu) / (1.0 - P->dt * dA[p]);
+        }
+        memcpy(vn, tmp, (size_t)N * sizeof(double));
+      }
+      inf.cg_iters += P->jacobi_sweeps;
+      if (P->jacobi_sweeps > inf.cg_max) inf.cg_max = P->jacobi_sweeps;
     } else if (P->model == 0) {
       memcpy(vn, vs, (size_t)N * sizeof(double));
       orc_op o = {P, P->Di, NULL, P->dt, 0, tmp};
@@ -501,7 +525,7 @@ int orc_run(const orc_problem* P, orc_state* S, int32_t nsteps, orc_info* info) 
   inf.mass = h3 * m;
   if (info) *info = inf;
   free(j); free(vs); free(ws); free(a); free(vn); free(tmp);
-  free(dinv);
+  free(dinv); free(dA);
   return rc;
 }
 

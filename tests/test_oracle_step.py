@@ -227,3 +227,52 @@ def test_adjoint_matches_central_differences(orc):
         fd = (Lp - Lm) / (2 * eps)
         ad = float(np.sum(g * d))
         assert abs(fd - ad) <= 1e-5 * abs(fd), (fd, ad)
+
+
+def jacobi_shell(n, sweeps):
+    inst = small_shell(n)
+    inst.diff = "be_jacobi"
+    inst.jacobi_sweeps = sweeps
+    return inst
+
+
+@pytest.mark.parametrize("sweeps", [1, 2, 5])
+def test_jacobi_step_matches_dense_recurrence(orc, sweeps):
+    """The fixed-sweep implicit step (eqn:iejac1) against the same recurrence
+    on the dense matrix: M = I - dt A split into its diagonal and the rest,
+    u^0 = v*, u^{k+1} = diag(M)^-1 (v* - (M - diag(M)) u^k)."""
+    inst = jacobi_shell(12, sweeps)
+    o = orc.Oracle(inst)
+    v0, w0 = E.random_state(inst, 5)
+    o.set_state(v=v0, w=w0, step=100)
+    vs, _ = o.ionic(o.field("v"), o.field("w"))
+    rc, info = o.run(1)
+    A = orc.dense_matrix(inst.n, inst.h, inst.mask, o.Di)
+    M = np.eye(A.shape[0]) - inst.dt * A
+    d = np.diag(M)
+    R = M - np.diag(d)
+    b = vs.ravel()
+    u = b.copy()
+    for _ in range(sweeps):
+        u = (b - R @ u) / d
+    u = np.where(inst.mask.ravel() > 0, u, 0.0)
+    assert rc == 0 and info.cg_iters == sweeps
+    assert np.abs(o.v - u).max() <= 1e-13 * np.abs(u).max()
+
+
+def test_jacobi_step_converges_to_the_implicit_solve(orc):
+    """Enough sweeps reach the backward-Euler solution (dense solve), and the
+    error shrinks monotonically with the sweep count."""
+    errs = []
+    for sweeps in (2, 8, 32):
+        inst = jacobi_shell(12, sweeps)
+        o = orc.Oracle(inst)
+        v0, w0 = E.random_state(inst, 3)
+        o.set_state(v=v0, w=w0, step=100)
+        vs, _ = o.ionic(o.field("v"), o.field("w"))
+        o.run(1)
+        A = orc.dense_matrix(inst.n, inst.h, inst.mask, o.Di)
+        x = np.linalg.solve(np.eye(A.shape[0]) - inst.dt * A, vs.ravel())
+        errs.append(np.abs(o.v - x).max() / np.abs(x).max())
+    assert all(b < a for a, b in zip(errs, errs[1:]))
+    assert errs[-1] <= 1e-12
