@@ -57,7 +57,11 @@ typedef enum {
 
 typedef enum { EP_F64 = 0, EP_F32 = 1 } ep_prec;       /* bulk state + stencil */
 typedef enum { EP_MONO = 0, EP_BIDO = 1 } ep_model;
-typedef enum { EP_DIFF_EXPLICIT = 0, EP_DIFF_BE_PCG = 1 } ep_diff;
+/* Monodomain diffusion: explicit Euler; implicit Euler by Jacobi-PCG to
+ * pcg_rtol; or implicit Euler by the thesis's own fixed number of Jacobi
+ * sweeps from the current potential (Linear Solver section, "Implicit
+ * Euler", eqn:iejac1), jacobi_sweeps per step, with no stopping test. */
+typedef enum { EP_DIFF_EXPLICIT = 0, EP_DIFF_BE_PCG = 1, EP_DIFF_BE_JACOBI = 2 } ep_diff;
 typedef enum { EP_V = 0, EP_W = 1, EP_PHIE = 2, EP_TACT = 3 } ep_field;
 
 /* Mitchell-Schaeffer constants (eqn:ms1, eqn:ms2).  exc multiplies J_in
@@ -93,6 +97,7 @@ typedef struct {
   double act_threshold;      /* activation threshold theta (0 < theta < 1) */
   double pcg_rtol;           /* implicit-Euler PCG: stop at ||r|| <= rtol ||b|| */
   int32_t pcg_maxit;
+  int32_t jacobi_sweeps;     /* EP_DIFF_BE_JACOBI: sweeps per step (>= 1) */
   double ell_rtol;           /* bidomain elliptic refinement tolerance */
   int32_t ell_max_outer;     /* max refinement (outer) iterations */
   int32_t ell_inner_maxit;   /* max inner FP32 PCG iterations per outer */

@@ -144,6 +144,11 @@ template <typename T, typename O>
 void launch_box_gather(hipStream_t s, const int n[3], int nby, int nbz, const int* brick_id,
                        const T* src, const uint8_t* mask, O* out, O fill);
 
+// one Jacobi sweep x_out = x_in + M^-1 (b - (I - dt A) x_in) (L.grid blocks)
+template <typename T>
+void launch_jacobi(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T dt, const T* dinv,
+                   const T* b, const T* x_in, T* x_out);
+
 // out[k] = sum of partials[k*nparts .. (k+1)*nparts) in a fixed order
 void launch_reduce_sum(hipStream_t s, const double* partials, int nparts, int K, double* out);
 void launch_block_max(const LaunchCfg& L, const int* nbr, CoefSet<double> c,

@@ -29,6 +29,7 @@
 //     activation time at the first threshold crossing.
 //   k_be_init, k_pcg_step: implicit-Euler diffusion step (Linear Solver
 //     section, "Implicit Euler") solved by Jacobi-preconditioned CG;
+//     k_jacobi: the same step by the thesis's fixed Jacobi sweeps (eqn:iejac1);
 //     k_cgcg: the same CG in one-reduction form for the elliptic solves.
 //   k_resid64, k_inner_init, k_phi_correct, k_phi_shift, k_parabolic: the
 //     bidomain step (eqn:bidomain1): elliptic solve for phi_e by FP32 PCG
@@ -777,6 +778,40 @@ __global__ __launch_bounds__(kBV) void k_activation(int nb, const T* __restrict_
   if (!isfinite(vn)) flags[0] = 1;
 }
 
+// One Jacobi sweep of the implicit-Euler system (I - dt A) x = b, the
+// thesis's own solver (Linear Solver section, "Implicit Euler",
+// eqn:iejac1): x_out = x + M^-1 (b - (I - dt A) x) with M = diag(I - dt A),
+// which is [I - dt D]^-1 [b + dt (L + U) x] rewritten.  One brick per block,
+// no reductions; rows without tissue read the ghost brick and are not
+// stored.
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_jacobi(int nb, const int* __restrict__ nbr,
+                                                CoefSet<T> c, T dt, const T* __restrict__ dinv,
+                                                const T* __restrict__ b,
+                                                const T* __restrict__ x_in,
+                                                T* __restrict__ x_out,
+                                                const uint64_t* __restrict__ rowsn) {
+  __shared__ T s[kTile];
+  __shared__ int nbs[kNbr];
+  __shared__ uint64_t rowm[kNbr];
+  const int brick = block_brick();
+  if (brick >= nb) return;
+  if (threadIdx.x < kNbr) {
+    nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
+    rowm[threadIdx.x] = rowsn[brick * kNbr + threadIdx.x];
+  }
+  __syncthreads();
+  const Cell e = cell_setup(nbs, brick, rowm, nb);
+  const T xg = x_in[e.gl], bg = b[e.gl], dg = dinv[e.gl];
+  s[e.C] = xg;
+  if (e.has_halo) s[e.hC] = x_in[e.hgl];
+  T k18[18];
+  gather18(c, nbs, brick, e.lx, e.ly, e.lz, k18, rowm, nb);
+  __syncthreads();
+  const T r = (bg - xg) + dt * apply19(s, e.C, k18);
+  if (e.live) x_out[e.g] = xg + dg * r;
+}
+
 // Jacobi: dinv = 1 / (c0 + c1 A_pp) where positive, else 0.
 template <typename T>
 __global__ __launch_bounds__(kBV) void k_dinv(int nb, const int* __restrict__ nbr, CoefSet<T> c,
@@ -1297,6 +1332,12 @@ template void launch_box_gather<double, float>(hipStream_t, const int*, int, int
 template void launch_box_gather<double, double>(hipStream_t, const int*, int, int, const int*,
                                                 const double*, const uint8_t*, double*, double);
 
+template <typename T>
+void launch_jacobi(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T dt, const T* dinv,
+                   const T* b, const T* x_in, T* x_out) {
+  k_jacobi<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, c, dt, dinv, b, x_in, x_out, L.rowsn);
+}
+
 void launch_reduce_sum(hipStream_t s, const double* partials, int nparts, int K, double* out) {
   k_reduce<<<1, kRedThreads, 0, s>>>(partials, nparts, K, out);
 }
@@ -1412,6 +1453,8 @@ void launch_loss(const LaunchCfg& L, const uint8_t* mask, const int* cross, cons
                                    T*, const T*, T*, const T*, T*, const T*, T*, int,          \
                                    const CGScalars*, CGScalars*, const double*, double*,       \
                                    unsigned long long*, unsigned);                             \
+  template void launch_jacobi<T>(const LaunchCfg&, const int*, CoefSet<T>, T, const T*,       \
+                                 const T*, const T*, T*);                                      \
   template void launch_activation<T>(const LaunchCfg&, const T*, const T*, T*, T, T, double,   \
                                      int*);                                                    \
   template void launch_dinv<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T, T*);            \

@@ -64,6 +64,7 @@ struct ep_grid_s {
   ep_ionic ionic{};
   double pcg_rtol = 1e-6, ell_rtol = 1e-8;
   int pcg_maxit = 50, ell_max_outer = 8, ell_inner_maxit = 2000;
+  int jacobi_sweeps = 0;
   std::vector<ep_stim> stims;
   hipStream_t stream = nullptr;
   bool own_stream = false;
@@ -105,7 +106,7 @@ struct ep_grid_s {
   void* d_bprev[2] = {nullptr, nullptr};  // implicit solve: b of the last two steps
   void* d_dprev[kDRing] = {};  // ring of increments d = v_{k+1} - b_k
   void* d_q[2] = {nullptr, nullptr};  // history term of the next guess, ping-pong
-  void* d_vs = nullptr;       // bidomain v*
+  void* d_vs = nullptr;       // v* (bidomain; Jacobi implicit step: its right-hand side)
   double* d_phi = nullptr;
   double* d_phi_hist[3] = {};     // bidomain: ring of past solutions (extrapolated guess)
   int phi_sel = 0;                // ring slot of the next solution
@@ -613,6 +614,37 @@ ep_status step_be(ep_grid g, const T* jstim, ep_step_info* acc) {
   return EP_OK;
 }
 
+// Implicit Euler by the thesis's fixed number of Jacobi sweeps from the
+// current potential: reaction into v*, then jacobi_sweeps sweeps of
+// (I - dt A) v = v* starting from v*, the last one written to the new
+// state, then the activation check of this step.
+template <typename T>
+ep_status step_jacobi(ep_grid g, const T* jstim, ep_step_info* acc) {
+  const int c = g->cur, n = 1 - c;
+  T* vs = static_cast<T*>(g->d_vs);
+  T* out = static_cast<T*>(g->d_v[n]);
+  T* scratch = static_cast<T*>(g->d_cr[0]);
+  launch_ionic<T>(g->L, static_cast<const T*>(g->d_v[c]), static_cast<const T*>(g->d_w[c]), jstim,
+                  vs, static_cast<T*>(g->d_w[n]), ionic_t<T>(g), static_cast<T>(g->dt));
+  const int K = g->jacobi_sweeps;
+  const T* in = vs;
+  for (int j = 0; j < K; ++j) {
+    // alternate so that sweep K - 1 writes the new state
+    T* dst = ((K - 1 - j) % 2 == 0) ? out : scratch;
+    TimerPair* t0 = timer_begin(g, KT_STENCIL);
+    launch_jacobi<T>(g->L, g->d_nbr, coefs<T>(g), static_cast<T>(g->dt),
+                     static_cast<const T*>(g->d_dinv), vs, in, dst);
+    timer_end(g, t0);
+    in = dst;
+  }
+  launch_activation<T>(g->L, static_cast<const T*>(g->d_v[c]), out, static_cast<T*>(g->d_tact),
+                       static_cast<T>(g->dt), static_cast<T>(g->theta),
+                       static_cast<double>(g->step) * g->dt, g->d_flags);
+  acc->cg_iters += K;
+  acc->cg_max = std::max(acc->cg_max, K);
+  return EP_OK;
+}
+
 // Mixed-precision elliptic solve for phi given the source potential vsrc
 // (FP64 refinement around FP32 Jacobi-PCG inner solves).
 template <typename T>
@@ -712,6 +744,8 @@ ep_status run_steps(ep_grid g, int32_t nsteps, ep_step_info* info) {
     TRY(update_stimulus<T>(g, g->step, &jstim));
     if (g->model == EP_BIDO) {
       TRY(step_bido<T>(g, jstim, &acc));
+    } else if (g->diff == EP_DIFF_BE_JACOBI) {
+      TRY(step_jacobi<T>(g, jstim, &acc));
     } else if (g->diff == EP_DIFF_BE_PCG) {
       TRY(step_be<T>(g, jstim, &acc));
       g->bsel = 1 - g->bsel;
@@ -1040,8 +1074,10 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   if (!(d->dt > 0) || !std::isfinite(d->dt)) return fail(g, EP_ERR_ARG, "dt must be > 0");
   if (d->model != EP_MONO && d->model != EP_BIDO) return fail(g, EP_ERR_ARG, "bad model");
   if (d->prec != EP_F64 && d->prec != EP_F32) return fail(g, EP_ERR_ARG, "bad precision");
-  if (d->diff != EP_DIFF_EXPLICIT && d->diff != EP_DIFF_BE_PCG)
+  if (d->diff != EP_DIFF_EXPLICIT && d->diff != EP_DIFF_BE_PCG && d->diff != EP_DIFF_BE_JACOBI)
     return fail(g, EP_ERR_ARG, "bad diffusion scheme");
+  if (d->diff == EP_DIFF_BE_JACOBI && d->jacobi_sweeps < 1)
+    return fail(g, EP_ERR_ARG, "jacobi_sweeps >= 1 required");
   if (d->model == EP_BIDO && d->diff != EP_DIFF_EXPLICIT)
     return fail(g, EP_ERR_UNSUPPORTED, "bidomain parabolic part is explicit only");
   if (d->n_stim < 0 || (d->n_stim > 0 && !d->stim)) return fail(g, EP_ERR_ARG, "bad stimuli");
@@ -1077,6 +1113,7 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   g->theta = d->act_threshold;
   g->pcg_rtol = d->pcg_rtol;
   g->pcg_maxit = d->pcg_maxit;
+  g->jacobi_sweeps = d->jacobi_sweeps;
   g->ell_rtol = d->ell_rtol;
   g->ell_max_outer = d->ell_max_outer;
   g->ell_inner_maxit = d->ell_inner_maxit;
@@ -1153,6 +1190,11 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
     for (int k = 0; k < 2; ++k) TRY(dalloc(g, &g->d_bprev[k], vb));
     for (int k = 0; k < kDRing; ++k) TRY(dalloc(g, &g->d_dprev[k], vb));
     for (int k = 0; k < 2; ++k) TRY(dalloc(g, &g->d_q[k], vb));
+  }
+  if (g->diff == EP_DIFF_BE_JACOBI) {
+    TRY(dalloc(g, &g->d_dinv, vb));
+    TRY(dalloc(g, &g->d_vs, vb));
+    TRY(dalloc(g, &g->d_cr[0], vb));
   }
   if (g->model == EP_MONO && g->diff == EP_DIFF_EXPLICIT)
     for (int k = 0; k < 6; ++k) TRY(dalloc(g, &g->d_d0[k], vb));
@@ -1370,7 +1412,7 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
                           g->d_ck64, g->d_ck32);
       launch_dinv<float>(g->L, g->d_nbr, cset32(g->d_ck32), 0.0f, -1.0f, g->d_dinvk);
     }
-    if (g->diff == EP_DIFF_BE_PCG) {
+    if (g->diff == EP_DIFF_BE_PCG || g->diff == EP_DIFF_BE_JACOBI) {
       if (g->prec == EP_F64)
         launch_dinv<double>(g->L, g->d_nbr, coefs<double>(g), 1.0, -g->dt,
                             static_cast<double*>(g->d_dinv));

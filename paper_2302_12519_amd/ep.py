@@ -27,7 +27,7 @@ EP_OK, EP_ERR_ARG, EP_ERR_OOM, EP_ERR_HIP, EP_ERR_NOCONV, EP_ERR_NONFINITE, EP_E
     EP_ERR_UNSUPPORTED = range(8)
 EP_F64, EP_F32 = 0, 1
 EP_MONO, EP_BIDO = 0, 1
-EP_DIFF_EXPLICIT, EP_DIFF_BE_PCG = 0, 1
+EP_DIFF_EXPLICIT, EP_DIFF_BE_PCG, EP_DIFF_BE_JACOBI = 0, 1, 2
 FIELDS = {"v": 0, "w": 1, "phi": 2, "tact": 3}
 KERNELS = {"stencil": 0, "cg_setup": 1, "parabolic": 2, "resid": 3, "cg_tail": 4, "adjoint": 5,
            "be_init": 6, "cg_update": 7}
@@ -55,7 +55,7 @@ class GridDesc(C.Structure):
                 ("model", C.c_int), ("prec", C.c_int), ("diff", C.c_int), ("dt", C.c_double),
                 ("ionic", Ionic), ("stim", C.POINTER(Stim)), ("n_stim", C.c_int32),
                 ("act_threshold", C.c_double), ("pcg_rtol", C.c_double),
-                ("pcg_maxit", C.c_int32), ("ell_rtol", C.c_double),
+                ("pcg_maxit", C.c_int32), ("jacobi_sweeps", C.c_int32), ("ell_rtol", C.c_double),
                 ("ell_max_outer", C.c_int32), ("ell_inner_maxit", C.c_int32),
                 ("stream", C.c_void_p), ("arena", C.c_void_p), ("arena_bytes", C.c_int64)]
 
@@ -140,7 +140,8 @@ def _p(a):
 
 def make_desc(n, h, dt, mask=None, model="mono", prec="f32", diff="explicit", ionic=None,
               stims=(), theta=0.5, pcg_rtol=1e-6, pcg_maxit=50, ell_rtol=1e-8,
-              ell_max_outer=8, ell_inner_maxit=4000, stream=None, arena=None):
+              ell_max_outer=8, ell_inner_maxit=4000, stream=None, arena=None,
+              jacobi_sweeps=10):
     """Fill an ep_grid_desc; returns it and the arrays it points into (keep
     them alive while the descriptor is used).  arena: optional caller-owned
     device memory, a torch CUDA tensor whose bytes the grid carves its
@@ -159,7 +160,8 @@ def make_desc(n, h, dt, mask=None, model="mono", prec="f32", diff="explicit", io
         d.mask = _p(m)
     d.model = EP_BIDO if model == "bido" else EP_MONO
     d.prec = EP_F64 if prec == "f64" else EP_F32
-    d.diff = EP_DIFF_BE_PCG if diff == "be_pcg" else EP_DIFF_EXPLICIT
+    d.diff = {"explicit": EP_DIFF_EXPLICIT, "be_pcg": EP_DIFF_BE_PCG,
+              "be_jacobi": EP_DIFF_BE_JACOBI}[diff]
     d.dt = float(dt)
     io = ionic or {}
     for k in ("tau_in", "tau_out", "tau_open", "tau_close", "v_gate", "exc"):
@@ -179,6 +181,7 @@ def make_desc(n, h, dt, mask=None, model="mono", prec="f32", diff="explicit", io
     d.n_stim = len(stims)
     d.act_threshold = float(theta)
     d.pcg_rtol, d.pcg_maxit = float(pcg_rtol), int(pcg_maxit)
+    d.jacobi_sweeps = int(jacobi_sweeps)
     d.ell_rtol, d.ell_max_outer = float(ell_rtol), int(ell_max_outer)
     d.ell_inner_maxit = int(ell_inner_maxit)
     d.stream = stream
@@ -197,10 +200,10 @@ class Grid:
     def __init__(self, n, h, dt, mask=None, model="mono", prec="f32", diff="explicit",
                  ionic=None, stims=(), theta=0.5, pcg_rtol=1e-6, pcg_maxit=50,
                  ell_rtol=1e-8, ell_max_outer=8, ell_inner_maxit=4000, stream=None,
-                 arena=None):
+                 arena=None, jacobi_sweeps=10):
         self._desc, keep = make_desc(n, h, dt, mask, model, prec, diff, ionic, stims, theta,
                                      pcg_rtol, pcg_maxit, ell_rtol, ell_max_outer,
-                                     ell_inner_maxit, stream, arena)
+                                     ell_inner_maxit, stream, arena, jacobi_sweeps)
         self._keep = keep
         self.n = tuple(int(k) for k in n)
         self.N = int(np.prod(self.n))
@@ -216,7 +219,8 @@ class Grid:
         g = cls(inst.n, inst.h, inst.dt, mask=inst.mask, model=inst.model,
                 prec=prec or inst.prec, diff=inst.diff, ionic=inst.ionic, stims=inst.stims,
                 theta=inst.theta, pcg_rtol=inst.pcg_rtol, pcg_maxit=inst.pcg_maxit,
-                ell_rtol=inst.ell_rtol, **kw)
+                ell_rtol=inst.ell_rtol,
+                jacobi_sweeps=getattr(inst, "jacobi_sweeps", 10), **kw)
         g.set_conductivity(inst.fibre, inst.scale, inst.sigma_l, inst.sigma_t,
                            inst.sigma_el, inst.sigma_et)
         return g
