@@ -68,7 +68,9 @@ def parse():
     ap.add_argument("--serving", type=int, default=64,
                     help="requests of the serving measurement (0 skips it)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-box FP64 line")
-    ap.add_argument("--only", choices=["serving", "plain", "bidomain", "adjoint"],
+    ap.add_argument("--jacobi", type=int, default=256,
+                    help="grid edge of the fixed-sweep Jacobi line (0 = skip)")
+    ap.add_argument("--only", choices=["serving", "plain", "bidomain", "adjoint", "jacobi"],
                     help="run one side workload alone and print its JSON (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (for HBM counter scaling)")
@@ -187,6 +189,39 @@ def bench_plain_fp64(steps=1000):
     return {"us_per_step": 1e6 * dt / steps, "voxel_steps_per_s": inst.nt * steps / dt}
 
 
+def bench_jacobi(n, steps=200, sweeps=(4, 10)):
+    """The thesis's own implicit solver on the same shell as the headline:
+    a fixed number of Jacobi sweeps per step from the current potential
+    (no stopping test).  For each sweep count: voxel-steps/s over `steps`
+    steps from rest, and the largest difference of v from the PCG solve
+    (rtol 1e-7) after the same steps, relative to max |v|."""
+    import ep_inputs as E
+    import torch
+    from paper_2302_12519_amd import Grid
+    inst = E.aniso_be(n, steps=steps)
+    inst.pcg_rtol = 1e-7
+    ref = Grid.from_instance(inst)
+    ref.step(steps)
+    v_ref = ref.read("v")
+    ref.close()
+    out = {"workload": f"aniso_be_{n}: {inst.nt} tissue voxels, {steps} FP32 steps from rest"}
+    for k in sweeps:
+        inst.diff, inst.jacobi_sweeps = "be_jacobi", k
+        g = Grid.from_instance(inst)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        v = g.read("v")
+        g.close()
+        out[f"sweeps_{k}"] = {"voxel_steps_per_s": inst.nt * steps / dt,
+                              "ms_per_step": 1e3 * dt / steps,
+                              "max_rel_diff_vs_pcg": float(np.abs(v - v_ref).max()
+                                                           / np.abs(v_ref).max())}
+    return out
+
+
 def bench_bidomain(n, steps=20, warmup=3):
     """Bidomain n^3 shell (sigma_i 0.17/0.019, sigma_e 0.62/0.24, dt 0.05):
     per-step time of the full step (ionic, elliptic FP32 PCG inside FP64
@@ -284,7 +319,8 @@ def main():
         side = {"serving": lambda: bench_serving(a.serving or 64),
                 "plain": bench_plain_fp64,
                 "bidomain": lambda: bench_bidomain(a.bidomain or 192),
-                "adjoint": lambda: bench_adjoint(a.adjoint or 128)}[a.only]
+                "adjoint": lambda: bench_adjoint(a.adjoint or 128),
+                "jacobi": lambda: bench_jacobi(a.jacobi or 256)}[a.only]
         print(json.dumps({a.only: side()}), flush=True)
         return
 
@@ -381,6 +417,8 @@ def main():
         out["bidomain"] = bench_bidomain(a.bidomain)
     if a.adjoint:
         out["adjoint"] = bench_adjoint(a.adjoint)
+    if a.jacobi:
+        out["jacobi"] = bench_jacobi(a.jacobi)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, a.cpu_seconds)
     print(json.dumps(out), flush=True)
