@@ -70,7 +70,10 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-box FP64 line")
     ap.add_argument("--jacobi", type=int, default=256,
                     help="grid edge of the fixed-sweep Jacobi line (0 = skip)")
-    ap.add_argument("--only", choices=["serving", "plain", "bidomain", "adjoint", "jacobi"],
+    ap.add_argument("--no-cuboid", action="store_true",
+                    help="skip the benchmark-geometry cuboid line")
+    ap.add_argument("--only", choices=["serving", "plain", "bidomain", "adjoint", "jacobi",
+                                       "cuboid"],
                     help="run one side workload alone and print its JSON (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (for HBM counter scaling)")
@@ -222,6 +225,35 @@ def bench_jacobi(n, steps=200, sweeps=(4, 10)):
     return out
 
 
+def bench_cuboid(dxs=(0.5, 0.2, 0.1), dt=0.005, t_end=60.0):
+    """The thesis's benchmark geometry (20 x 7 x 3 mm cuboid, 1.5 mm corner
+    stimulus) at each voxel width, FP32 explicit, dt 0.005 ms: activation
+    time (ms) at points along the long diagonal and at the far corner, and
+    the GPU time of the run."""
+    import ep_inputs as E
+    import torch
+    from paper_2302_12519_amd import Grid
+    out = {"dt_ms": dt, "t_end_ms": t_end, "diagonal_fractions": [0.25, 0.5, 0.75, 1.0]}
+    for dx in dxs:
+        inst = E.cuboid(dx, dt, t_end=t_end)
+        g = Grid.from_instance(inst)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        g.step(inst.steps)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t
+        T = g.read("tact")
+        g.close()
+        n = inst.n
+        diag = [float(T[int(f * (n[0] - 1)), int(f * (n[1] - 1)), int(f * (n[2] - 1))])
+                for f in out["diagonal_fractions"]]
+        out[f"dx_{dx:g}"] = {"grid": list(n), "steps": inst.steps, "seconds": sec,
+                             "voxel_steps_per_s": inst.nt * inst.steps / sec,
+                             "t_act_diagonal_ms": diag,
+                             "t_act_far_corner_ms": float(T[-1, -1, -1])}
+    return out
+
+
 def bench_bidomain(n, steps=20, warmup=3):
     """Bidomain n^3 shell (sigma_i 0.17/0.019, sigma_e 0.62/0.24, dt 0.05):
     per-step time of the full step (ionic, elliptic FP32 PCG inside FP64
@@ -320,7 +352,8 @@ def main():
                 "plain": bench_plain_fp64,
                 "bidomain": lambda: bench_bidomain(a.bidomain or 192),
                 "adjoint": lambda: bench_adjoint(a.adjoint or 128),
-                "jacobi": lambda: bench_jacobi(a.jacobi or 256)}[a.only]
+                "jacobi": lambda: bench_jacobi(a.jacobi or 256),
+                "cuboid": bench_cuboid}[a.only]
         print(json.dumps({a.only: side()}), flush=True)
         return
 
@@ -419,6 +452,8 @@ def main():
         out["adjoint"] = bench_adjoint(a.adjoint)
     if a.jacobi:
         out["jacobi"] = bench_jacobi(a.jacobi)
+    if not a.no_cuboid:
+        out["cuboid"] = bench_cuboid()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, a.cpu_seconds)
     print(json.dumps(out), flush=True)

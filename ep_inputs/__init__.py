@@ -188,6 +188,26 @@ def plain_box(n=32, steps=1000, prec="f64"):
                     stims=stims, model="mono", diff="explicit", prec=prec)
 
 
+def cuboid(dx, dt, t_end=60.0, prec="f32", diff="explicit", sigma=(0.2, 0.05)):
+    """The thesis's electrophysiology benchmark geometry (Benchmark Studies
+    section): a 20 x 7 x 3 mm all-tissue cuboid at voxel width dx (mm),
+    fibres along its long axis, stimulated in the 1.5 mm cube at one corner
+    for the first 1 ms.  The benchmark's own cell model and conductivities
+    are not in the thesis; this stands in with Mitchell-Schaeffer and
+    sigma = (0.2, 0.05) mm^2/ms (the shell workloads' values).  Steps cover
+    t_end ms at dt."""
+    shape = tuple(int(round(L / dx)) for L in (20.0, 7.0, 3.0))
+    mask = np.ones(shape, np.uint8)
+    fib = np.zeros(shape + (3,))
+    fib[..., 0] = 1.0
+    k = int(math.ceil(1.5 / dx - 1e-9))
+    stims = [Stim(lo=(0, 0, 0), hi=(k, k, k), amp=1.0, t_on=0.0, t_off=1.0)]
+    return Instance(name=f"cuboid_dx{dx:g}_dt{dt:g}", n=shape, h=float(dx), dt=float(dt),
+                    steps=int(round(t_end / dt)), mask=mask, fibre=fib, scale=None,
+                    sigma_l=sigma[0], sigma_t=sigma[1], stims=stims, model="mono", diff=diff,
+                    prec=prec)
+
+
 def shell(n, seed, n_stim, h=0.25, rout_frac=SHELL_ROUT, rho=SHELL_RHO):
     shape = (n, n, n) if np.isscalar(n) else tuple(n)
     mask, R = shell_mask(shape, h, rout_frac, rho)
