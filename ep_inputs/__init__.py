@@ -68,7 +68,7 @@ class Instance:
     sigma_et: float = 0.0
     stims: List[Stim] = dataclasses.field(default_factory=list)
     model: str = "mono"           # "mono" | "bido"
-    diff: str = "explicit"        # "explicit" | "be_pcg" | "be_jacobi"
+    diff: str = "explicit"        # "explicit" | "be_pcg" | "be_jacobi" | "explicit27"
     prec: str = "f32"             # "f32" | "f64"
     ionic: dict = dataclasses.field(default_factory=lambda: dict(MS_DEFAULT))
     theta: float = 0.5

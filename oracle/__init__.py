@@ -102,6 +102,15 @@ def apply(n, h, mask, D, v):
     return out.reshape(np.shape(v))
 
 
+def apply27(n, h, mask, D, v):
+    """(A27 v) with the thesis's corner-gradient operator."""
+    m = np.ascontiguousarray(mask, dtype=np.uint8).ravel()
+    vv = _f64(v).ravel()
+    out = np.zeros_like(vv)
+    lib().orc_apply27(_n3(n), C.c_double(h), _p(m), _p(_f64(D)), _p(vv), _p(out))
+    return out.reshape(np.shape(v))
+
+
 def diag(n, h, mask, D):
     m = np.ascontiguousarray(mask, dtype=np.uint8).ravel()
     out = np.zeros(int(np.prod(n)))
@@ -118,14 +127,16 @@ def dA_ds(n, h, mask, D0, mu, v):
     return out.reshape(tuple(n))
 
 
-def dense_matrix(n, h, mask, D):
-    """Dense A by applying the operator to unit vectors (tiny grids only)."""
+def dense_matrix(n, h, mask, D, op=None):
+    """Dense A (or of op, e.g. apply27) by applying the operator to unit
+    vectors (tiny grids only)."""
+    op = apply if op is None else op
     N = int(np.prod(n))
     A = np.zeros((N, N))
     e = np.zeros(N)
     for j in range(N):
         e[j] = 1.0
-        A[:, j] = apply(n, h, mask, D, e.reshape(tuple(n))).ravel()
+        A[:, j] = op(n, h, mask, D, e.reshape(tuple(n))).ravel()
         e[j] = 0.0
     return A
 
@@ -160,7 +171,8 @@ class Oracle:
         self.P.tau_open, self.P.tau_close = io["tau_open"], io["tau_close"]
         self.P.v_gate, self.P.exc = io["v_gate"], io["exc"]
         self.P.model = 1 if inst.model == "bido" else 0
-        self.P.diff = {"explicit": 0, "be_pcg": 1, "be_jacobi": 2}[inst.diff]
+        self.P.diff = {"explicit": 0, "be_pcg": 1, "be_jacobi": 2,
+                       "explicit27": 3}[inst.diff]
         self.P.jacobi_sweeps = int(getattr(inst, "jacobi_sweeps", 0))
         self.P.cg_rtol, self.P.cg_maxit = cg_rtol, cg_maxit
         self.P.n_stim = len(st)

@@ -32,6 +32,8 @@
  *     number of Jacobi sweeps (eqn:iejac1).
  *   - Bidomain (eqn:bidomain1, heart only, v_i = v + phi_e):
  *     -(A_i + A_e) phi = A_i v*, sum_tissue phi = 0;  v_{n+1} = v* + dt A_i(v* + phi).
+ *   - Optionally (diff 3, monodomain, explicit only) the thesis's own
+ *     corner-gradient operator A27 (orc_apply27), for comparison.
  *   - Activation time: first step with v_n < theta <= v_{n+1}; linear
  *     interpolation T = t_n + dt (theta - v_n)/(v_{n+1} - v_n).
  *
@@ -71,7 +73,9 @@ typedef struct {
   double tau_in, tau_out, tau_open, tau_close, v_gate, exc;
   int32_t model;      /* 0 monodomain, 1 bidomain */
   int32_t diff;       /* 0 explicit, 1 implicit Euler by PCG, 2 implicit Euler
-                         by a fixed number of Jacobi sweeps (monodomain) */
+                         by a fixed number of Jacobi sweeps (monodomain),
+                         3 explicit with the corner-gradient operator A27
+                         (monodomain) */
   double cg_rtol;
   int32_t cg_maxit;
   int32_t n_stim;
@@ -264,6 +268,82 @@ void orc_diag(const int32_t n[3], double h, const uint8_t* mask, const double* D
         }
         diag[p] = acc;
       }
+}
+
+/* ------------------------------------------------------------------------ */
+/* the thesis's corner-gradient operator (Matrix-Free Assembly section,     */
+/* eqn:ass1 - eqn:ass3; Algorithm Details chapter, Diffusion subsection)    */
+/* ------------------------------------------------------------------------ */
+
+/* (A27 v)_p from the 27 values around p, taken through the thesis's chain of
+ * small matrices in order:
+ *   D1  reference gradient at each of the 8 corners of p's volume, from the
+ *       2x2x2 block of voxels meeting at that corner: per axis, the mean of
+ *       the block's four differences along it (unit reference spacing);
+ *   S1  the conductivity tensor at the corner: the mean of the block's eight
+ *       voxel tensors (the thesis interpolates the fibre field to the
+ *       gradient points; averaging tensors keeps f and -f equivalent);
+ *   F1  inverse deformation gradient: I/h on the undeformed grid;
+ *   D2  the flux at each face midpoint: the mean over the face's 4 corners;
+ *   F2 N1  outward unit normal dotted with each face flux, summed over the 6
+ *       faces, times face area over volume (1/h undeformed).
+ * Reading (no flux): a corner whose block leaves the grid or holds a
+ * non-tissue voxel carries no flux. */
+static double apply27_at(const int32_t n[3], double h, const uint8_t* mask,
+                         const double* D, const double* v, int x, int y, int z) {
+  const int64_t N = nvox(n);
+  const int64_t p = idx3(n, x, y, z);
+  if (!mask[p]) return 0.0;
+  double face[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};   /* [axis][- side, + side] */
+  for (int a = 0; a <= 1; ++a)
+    for (int b = 0; b <= 1; ++b)
+      for (int c = 0; c <= 1; ++c) {
+        /* corner at p + (a - 1/2, b - 1/2, c - 1/2) h; its block's lowest voxel */
+        const int bx = x + a - 1, by = y + b - 1, bz = z + c - 1;
+        double val[2][2][2];
+        double S[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int ok = 1;
+        for (int i = 0; i <= 1 && ok; ++i)
+          for (int j = 0; j <= 1 && ok; ++j)
+            for (int k = 0; k <= 1 && ok; ++k) {
+              if (!inside(n, bx + i, by + j, bz + k)) { ok = 0; break; }
+              const int64_t q = idx3(n, bx + i, by + j, bz + k);
+              if (!mask[q]) { ok = 0; break; }
+              val[i][j][k] = v[q];
+              for (int m = 0; m < 6; ++m) S[m] += D[m * N + q] / 8.0;
+            }
+        if (!ok) continue;
+        /* D1 */
+        double gr[3] = {0.0, 0.0, 0.0};
+        for (int j = 0; j <= 1; ++j)
+          for (int k = 0; k <= 1; ++k) {
+            gr[0] += 0.25 * (val[1][j][k] - val[0][j][k]);
+            gr[1] += 0.25 * (val[j][1][k] - val[j][0][k]);
+            gr[2] += 0.25 * (val[j][k][1] - val[j][k][0]);
+          }
+        /* S1 */
+        const double fl[3] = {S[ORC_XX] * gr[0] + S[ORC_XY] * gr[1] + S[ORC_XZ] * gr[2],
+                              S[ORC_XY] * gr[0] + S[ORC_YY] * gr[1] + S[ORC_YZ] * gr[2],
+                              S[ORC_XZ] * gr[0] + S[ORC_YZ] * gr[1] + S[ORC_ZZ] * gr[2]};
+        /* F1, then D2: the corner is one of the 4 corners of the faces on
+         * its side of each axis */
+        face[0][a] += 0.25 * fl[0] / h;
+        face[1][b] += 0.25 * fl[1] / h;
+        face[2][c] += 0.25 * fl[2] / h;
+      }
+  /* F2 N1 */
+  double acc = 0.0;
+  for (int d = 0; d < 3; ++d) acc += (face[d][1] - face[d][0]) / h;
+  return acc;
+}
+
+void orc_apply27(const int32_t n[3], double h, const uint8_t* mask, const double* D,
+                 const double* v, double* out) {
+#pragma omp parallel for schedule(static)
+  for (int x = 0; x < n[0]; ++x)
+    for (int y = 0; y < n[1]; ++y)
+      for (int z = 0; z < n[2]; ++z)
+        out[idx3(n, x, y, z)] = apply27_at(n, h, mask, D, v, x, y, z);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -478,8 +558,9 @@ int orc_run(const orc_problem* P, orc_state* S, int32_t nsteps, orc_info* info) 
     inf.q_stim += P->dt * h3 * qs;
     orc_ionic(P, S->v, S->w, j, vs, ws);
     /* diffusion */
-    if (P->model == 0 && P->diff == 0) {
-      orc_apply(P->n, P->h, P->mask, P->Di, vs, a);
+    if (P->model == 0 && (P->diff == 0 || P->diff == 3)) {
+      if (P->diff == 0) orc_apply(P->n, P->h, P->mask, P->Di, vs, a);
+      else orc_apply27(P->n, P->h, P->mask, P->Di, vs, a);
       for (int64_t p = 0; p < N; ++p) vn[p] = vs[p] + P->dt * a[p];
     } else if (P->model == 0 && P->diff == 2) {
       /* implicit Euler by a fixed number of Jacobi sweeps (Linear Solver
