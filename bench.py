@@ -70,10 +70,12 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-box FP64 line")
     ap.add_argument("--jacobi", type=int, default=256,
                     help="grid edge of the fixed-sweep Jacobi line (0 = skip)")
+    ap.add_argument("--explicit27", type=int, default=256,
+                    help="shell size of the A27 vs 19-point explicit line (0: skip)")
     ap.add_argument("--no-cuboid", action="store_true",
                     help="skip the benchmark-geometry cuboid line")
     ap.add_argument("--only", choices=["serving", "plain", "bidomain", "adjoint", "jacobi",
-                                       "cuboid"],
+                                       "cuboid", "explicit27"],
                     help="run one side workload alone and print its JSON (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (for HBM counter scaling)")
@@ -225,6 +227,52 @@ def bench_jacobi(n, steps=200, sweeps=(4, 10)):
     return out
 
 
+def bench_explicit27(n, steps=200):
+    """The thesis's corner-gradient operator A27 beside the 19-point operator
+    on the headline shell: FP32 explicit steps (dt 0.05 ms) from rest.  For
+    each: voxel-steps/s over `steps` untimed-event steps, then the fused
+    kernel's mean duration from a second pass with events on it, its
+    algorithmic rate (40 B per tissue voxel), and how far the two operators'
+    activation times lie apart after the same steps (v itself differs by
+    O(1) wherever the fronts are a voxel apart)."""
+    import ep_inputs as E
+    import torch
+    from paper_2302_12519_amd import Grid
+    inst = E.aniso_be(n, steps=steps)
+    out = {"workload": f"aniso_{n}: {inst.nt} tissue voxels, {steps} FP32 explicit steps "
+                       f"of dt {inst.dt} from rest"}
+    vs, ts = {}, {}
+    for diff in ("explicit", "explicit27"):
+        inst.diff = diff
+        g = Grid.from_instance(inst)
+        g.step(5)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t
+        vs[diff] = g.read("v")
+        ts[diff] = g.read("tact")
+        g.kernel_timing(True, kernels=["stencil"])
+        g.step(50)
+        ms, cnt = g.kernel_time("stencil")
+        g.kernel_timing(False)
+        g.close()
+        k_us = 1e3 * ms / max(cnt, 1)
+        out[diff] = {"voxel_steps_per_s": inst.nt * steps / sec, "ms_per_step": 1e3 * sec / steps,
+                     "kernel_us": k_us,
+                     "kernel_GBps": ALGO_BYTES["stencil_explicit"] * inst.nt / (k_us * 1e-6) / 1e9}
+    a, b = vs["explicit27"], vs["explicit"]
+    out["max_rel_diff_v_27_vs_19"] = float(np.abs(a - b).max() / np.abs(b).max())
+    ta, tb = ts["explicit27"], ts["explicit"]
+    both = np.isfinite(ta) & np.isfinite(tb)
+    d = ta[both] - tb[both]
+    out["activated"] = {"explicit": int(np.isfinite(tb).sum()),
+                        "explicit27": int(np.isfinite(ta).sum())}
+    out["t_act_27_minus_19_ms"] = {"mean": float(d.mean()), "max_abs": float(np.abs(d).max())}
+    return out
+
+
 def bench_cuboid(dxs=(0.5, 0.2, 0.1), dt=0.005, t_end=60.0):
     """The thesis's benchmark geometry (20 x 7 x 3 mm cuboid, 1.5 mm corner
     stimulus) at each voxel width, FP32 explicit, dt 0.005 ms: activation
@@ -353,7 +401,8 @@ def main():
                 "bidomain": lambda: bench_bidomain(a.bidomain or 192),
                 "adjoint": lambda: bench_adjoint(a.adjoint or 128),
                 "jacobi": lambda: bench_jacobi(a.jacobi or 256),
-                "cuboid": bench_cuboid}[a.only]
+                "cuboid": bench_cuboid,
+                "explicit27": lambda: bench_explicit27(a.explicit27 or 256)}[a.only]
         print(json.dumps({a.only: side()}), flush=True)
         return
 
@@ -454,6 +503,8 @@ def main():
         out["jacobi"] = bench_jacobi(a.jacobi)
     if not a.no_cuboid:
         out["cuboid"] = bench_cuboid()
+    if a.explicit27:
+        out["explicit27"] = bench_explicit27(a.explicit27)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -60,8 +60,28 @@ typedef enum { EP_MONO = 0, EP_BIDO = 1 } ep_model;
 /* Monodomain diffusion: explicit Euler; implicit Euler by Jacobi-PCG to
  * pcg_rtol; or implicit Euler by the thesis's own fixed number of Jacobi
  * sweeps from the current potential (Linear Solver section, "Implicit
- * Euler", eqn:iejac1), jacobi_sweeps per step, with no stopping test. */
-typedef enum { EP_DIFF_EXPLICIT = 0, EP_DIFF_BE_PCG = 1, EP_DIFF_BE_JACOBI = 2 } ep_diff;
+ * Euler", eqn:iejac1), jacobi_sweeps per step, with no stopping test.
+ * EP_DIFF_EXPLICIT27: explicit Euler with the thesis's own corner-gradient
+ * operator (Matrix-Free Assembly section, eqn:ass1 - eqn:ass3, with the
+ * conductivity block of the Algorithm Details chapter's Diffusion
+ * subsection): gradients at the 8 corners of each voxel from the 2x2x2
+ * blocks meeting there, the corner tensor the mean of the block's 8 voxel
+ * tensors, fluxes averaged to the face midpoints and summed through the
+ * faces; a corner whose block holds non-tissue carries no flux.  It reads
+ * the same 3x3x3 neighbourhood and the same 24 B (FP32) of coefficients
+ * per voxel as the 19-point operator, is symmetric and negative
+ * semidefinite, but has hourglass null modes ((-1)^(i+j), (-1)^(i+k),
+ * (-1)^(j+k), (-1)^(i+j+k)), so it is offered for the explicit monodomain
+ * step only (not for the implicit solvers, the bidomain, the adjoint or
+ * batched serving).  ep_set_conductivity_fibres rejects dt unless
+ * dt * 4 max_p(s_p) max(sigma_l, sigma_t) / h^2 < 2, a bound on
+ * dt * lambda_max(-A27) that uniform tissue nearly reaches. */
+typedef enum {
+  EP_DIFF_EXPLICIT = 0,
+  EP_DIFF_BE_PCG = 1,
+  EP_DIFF_BE_JACOBI = 2,
+  EP_DIFF_EXPLICIT27 = 3
+} ep_diff;
 typedef enum { EP_V = 0, EP_W = 1, EP_PHIE = 2, EP_TACT = 3 } ep_field;
 
 /* Mitchell-Schaeffer constants (eqn:ms1, eqn:ms2).  exc multiplies J_in

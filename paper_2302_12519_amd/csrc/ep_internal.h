@@ -93,6 +93,19 @@ void launch_tensor_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask
                          double h, double* tens /*6 arrays, scratch*/, double* c64[6],
                          float* c32[6]);
 
+// corner tensors of the corner-gradient operator A27 (one corner per voxel,
+// the six entries in the slots CX..CYZ read as xx, yy, zz, xy, xz, yz)
+void launch_corner_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask,
+                         const double* fib, const double* scale, double sig_l, double sig_t,
+                         double h, double* tens /*6 arrays, scratch*/, double* c64[6],
+                         float* c32[6]);
+
+// explicit step with A27 (ionic + diffusion + activation)
+template <typename T>
+void launch_explicit27(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v,
+                       const T* w, const T* jstim, T* vout, T* wout, T* tact, IonicT<T> ion,
+                       T dt, T theta, double tn, int* flags);
+
 // cross (nullable): records the step index where T_act is first set
 template <typename T>
 void launch_explicit(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v,

@@ -236,6 +236,46 @@ __global__ __launch_bounds__(kBV) void k_coefs(int nb, const int* __restrict__ n
   }
 }
 
+// Corner tensors of the corner-gradient operator A27 (Matrix-Free Assembly
+// section with the conductivity block of the Diffusion subsection).  Voxel p
+// owns the corner at p + (1/2, 1/2, 1/2) h, where the 2x2x2 block p + {0,1}^3
+// meets.  Its six tensor entries (xx, yy, zz, xy, xz, yz) are the mean of the
+// block's eight voxel tensors over 16 h^2, or zero when the block holds a
+// non-tissue voxel (no flux through that corner).  With these weights
+//   (A27 v)_p = sum over p's 8 corners c of sigma_c . (K_c u_c),
+// sigma_c the sign vector of c - p and u_c the block's signed sums
+// (sum over the block of sign(q - c)_d v_q for each axis d).
+__global__ __launch_bounds__(kBV) void k_coefs27(int nb, const int* __restrict__ nbr,
+                                                 const uint8_t* __restrict__ mask,
+                                                 const double* __restrict__ tens, int64_t stride,
+                                                 double inv_16h2, CoefOut<double> out64,
+                                                 CoefOut<float> out32) {
+  __shared__ int nbs[kNbr];
+  const int brick = block_brick();
+  if (brick >= nb) return;
+  const int t = threadIdx.x;
+  if (t < kNbr) nbs[t] = nbr[brick * kNbr + t];
+  __syncthreads();
+  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
+  int gq[8];
+  bool full = true;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    gq[k] = nb_global(nbs, brick, lx, ly, lz, k >> 2, (k >> 1) & 1, k & 1);
+    full = full && mask[gq[k]] != 0;
+  }
+  const int g = brick * kBV + t;
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    double a = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a += tens[m * stride + gq[k]];
+    const double cval = full ? a * 0.125 * inv_16h2 : 0.0;
+    if (out64.c[m]) out64.c[m][g] = cval;
+    if (out32.c[m]) out32.c[m][g] = static_cast<float>(cval);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // explicit monodomain step: ionic + 19-point diffusion + activation, fused
 // ---------------------------------------------------------------------------
@@ -283,6 +323,132 @@ __global__ __launch_bounds__(kBV) void k_explicit(int nb, const int* __restrict_
       if (cross) cross[q.g] = step;
     }
   }
+  if (!isfinite(vn)) flags[0] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// explicit monodomain step with the corner-gradient operator A27: ionic +
+// diffusion + activation, fused.  Two phases over the brick's LDS tile:
+// every corner of the brick's voxels (9^3 of them, lower voxel at tile
+// coordinates [0, 8]^3) gets its flux K_c u_c once, then each voxel sums the
+// signed fluxes of its 8 corners.  Thread t takes the corner its own voxel
+// owns (tile coordinates in [1, 8]^3, so its six weights are plain
+// coalesced loads), and threads < 217 also take one corner owned by the
+// -x / -y / -z halo (a tile coordinate of 0).
+// ---------------------------------------------------------------------------
+constexpr int kCorners = 729;            // 9^3 corners per brick
+constexpr int kCornersExtra = 729 - 512; // corners with a tile coordinate of 0
+
+__device__ __forceinline__ int corner_id(int cx, int cy, int cz) { return (cx * 9 + cy) * 9 + cz; }
+
+// the k-th corner (k < 217) with a lower-voxel tile coordinate equal to 0
+__device__ __forceinline__ void extra_corner(int k, int& cx, int& cy, int& cz) {
+  if (k < 81) { cx = 0; cy = k / 9; cz = k % 9; }
+  else if (k < 153) { k -= 81; cx = (k / 9) + 1; cy = 0; cz = k % 9; }
+  else { k -= 153; cx = (k >> 3) + 1; cy = (k & 7) + 1; cz = 0; }
+}
+
+template <typename T>
+__device__ __forceinline__ void corner_flux(const T* s, int cx, int cy, int cz, const T k[6],
+                                            T* qx, T* qy, T* qz) {
+  const int b = tidx(cx, cy, cz);
+  // block values v[i][j][l] at tile (cx+i, cy+j, cz+l)
+  const T v000 = s[b], v001 = s[b + 1], v010 = s[b + 10], v011 = s[b + 11];
+  const T v100 = s[b + 100], v101 = s[b + 101], v110 = s[b + 110], v111 = s[b + 111];
+  const T ux = (v100 - v000) + (v101 - v001) + (v110 - v010) + (v111 - v011);
+  const T uy = (v010 - v000) + (v011 - v001) + (v110 - v100) + (v111 - v101);
+  const T uz = (v001 - v000) + (v011 - v010) + (v101 - v100) + (v111 - v110);
+  const int ci = corner_id(cx, cy, cz);
+  qx[ci] = k[CX] * ux + k[CXY] * uy + k[CXZ] * uz;
+  qy[ci] = k[CXY] * ux + k[CY] * uy + k[CYZ] * uz;
+  qz[ci] = k[CXZ] * ux + k[CYZ] * uy + k[CZ] * uz;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBV) void k_explicit27(int nb, const int* __restrict__ nbr,
+                                                    CoefSet<T> c, const T* __restrict__ v,
+                                                    const T* __restrict__ w,
+                                                    const T* __restrict__ jstim,
+                                                    T* __restrict__ vout, T* __restrict__ wout,
+                                                    T* __restrict__ tact, IonicT<T> ion, T dt,
+                                                    T theta, double tn, int* flags) {
+  __shared__ T s[kTile];
+  __shared__ T qx[kCorners], qy[kCorners], qz[kCorners];
+  __shared__ int nbs[kNbr];
+  const int brick = block_brick();
+  if (brick >= nb) return;
+  if (threadIdx.x < kNbr) nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
+  __syncthreads();
+  const Cell q = cell_setup(nbs, brick);
+  const T v0 = v[q.g], w0 = w[q.g];
+  const T j0 = jstim ? jstim[q.g] : T(0);
+  T hv = T(0), hw = T(0), hj = T(0);
+  if (q.has_halo) {
+    hv = v[q.hg];
+    hw = w[q.hg];
+    hj = jstim ? jstim[q.hg] : T(0);
+  }
+  // the 8 corner cells of the tile, which the 19-point halo leaves out
+  const bool tcorner = threadIdx.x >= kHalo && threadIdx.x < kHalo + 8;
+  int cC = 0;
+  T cv = T(0), cw = T(0), cj = T(0);
+  if (tcorner) {
+    const int k = threadIdx.x - kHalo;
+    const int hx = (k & 4) ? 9 : 0, hy = (k & 2) ? 9 : 0, hz = (k & 1) ? 9 : 0;
+    const int cg = tile_global(nbs, hx, hy, hz);
+    cC = tidx(hx, hy, hz);
+    cv = v[cg];
+    cw = w[cg];
+    cj = jstim ? jstim[cg] : T(0);
+  }
+  // this thread's corners: the one its own voxel owns, and for threads < 217
+  // one with a tile coordinate of 0
+  T k1[6], k2[6];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) k1[m] = c.c[m][q.g];
+  const bool two = threadIdx.x < kCornersExtra;
+  int cx2 = 0, cy2 = 0, cz2 = 0;
+  if (two) {
+    extra_corner(threadIdx.x, cx2, cy2, cz2);
+    const int g2 = nb_global(nbs, brick, cx2 - 1, cy2 - 1, cz2 - 1, 0, 0, 0);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) k2[m] = c.c[m][g2];
+  }
+  T vs, ws;
+  ms_step(v0, w0, j0, ion, dt, vs, ws);
+  s[q.C] = vs;
+  if (q.has_halo) {
+    T a, b;
+    ms_step(hv, hw, hj, ion, dt, a, b);
+    s[q.hC] = a;
+  }
+  if (tcorner) {
+    T a, b;
+    ms_step(cv, cw, cj, ion, dt, a, b);
+    s[cC] = a;
+  }
+  __syncthreads();
+  corner_flux(s, q.lx + 1, q.ly + 1, q.lz + 1, k1, qx, qy, qz);
+  if (two) corner_flux(s, cx2, cy2, cz2, k2, qx, qy, qz);
+  __syncthreads();
+  T a = T(0);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int l = 0; l < 2; ++l) {
+        const int ci = corner_id(q.lx + i, q.ly + j, q.lz + l);
+        const T fx = i ? qx[ci] : -qx[ci];
+        const T fy = j ? qy[ci] : -qy[ci];
+        const T fz = l ? qz[ci] : -qz[ci];
+        a += fx + fy + fz;
+      }
+  const T vn = vs + dt * a;
+  vout[q.g] = vn;
+  wout[q.g] = ws;
+  if (v0 < theta && theta <= vn && isinf(tact[q.g]))
+    tact[q.g] = static_cast<T>(tn) + dt * (theta - v0) / (vn - v0);
   if (!isfinite(vn)) flags[0] = 1;
 }
 
@@ -1259,6 +1425,21 @@ void launch_tensor_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask
   k_coefs<<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, mask, tens, stride, 1.0 / (h * h), o64, o32);
 }
 
+void launch_corner_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask,
+                         const double* fib, const double* scale, double sig_l, double sig_t,
+                         double h, double* tens, double* c64[6], float* c32[6]) {
+  const int64_t stride = (int64_t)(L.nb + 1) * kBV;
+  k_tensor<<<L.grid, kBV, 0, L.stream>>>(L.nb, mask, fib, scale, sig_l, sig_t, tens, stride);
+  CoefOut<double> o64;
+  CoefOut<float> o32;
+  for (int k = 0; k < 6; ++k) {
+    o64.c[k] = c64 ? c64[k] : nullptr;
+    o32.c[k] = c32 ? c32[k] : nullptr;
+  }
+  k_coefs27<<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, mask, tens, stride, 1.0 / (16.0 * h * h),
+                                          o64, o32);
+}
+
 template <typename T>
 void launch_unit_tensors(const LaunchCfg& L, const uint8_t* mask, const double* fib,
                          double sig_l, double sig_t, T* out[6]) {
@@ -1273,6 +1454,14 @@ void launch_explicit(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* 
                      double tn, int* flags, int* cross, int step) {
   k_explicit<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, vout, wout, tact, ion,
                                               dt, theta, tn, flags, cross, step);
+}
+
+template <typename T>
+void launch_explicit27(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v, const T* w,
+                       const T* jstim, T* vout, T* wout, T* tact, IonicT<T> ion, T dt, T theta,
+                       double tn, int* flags) {
+  k_explicit27<T><<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, vout, wout, tact,
+                                                ion, dt, theta, tn, flags);
 }
 
 template <typename T>
@@ -1439,6 +1628,9 @@ void launch_loss(const LaunchCfg& L, const uint8_t* mask, const int* cross, cons
   template void launch_explicit<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*,         \
                                    const T*, const T*, T*, T*, T*, IonicT<T>, T, T, double,    \
                                    int*, int*, int);                                           \
+  template void launch_explicit27<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*,       \
+                                     const T*, const T*, T*, T*, T*, IonicT<T>, T, T, double,  \
+                                     int*);                                                    \
   template void launch_ionic<T>(const LaunchCfg&, const T*, const T*, const T*, T*, T*,        \
                                 IonicT<T>, T);                                                 \
   template void launch_be_init<T>(const LaunchCfg&, const int*, CoefSet<T>, const T*,          \

@@ -566,6 +566,19 @@ ep_status step_explicit(ep_grid g, const T* jstim) {
 }
 
 template <typename T>
+ep_status step_explicit27(ep_grid g, const T* jstim) {
+  const int c = g->cur, n = 1 - c;
+  TimerPair* t0 = timer_begin(g, KT_STENCIL);
+  launch_explicit27<T>(g->L, g->d_nbr, coefs<T>(g), static_cast<const T*>(g->d_v[c]),
+                       static_cast<const T*>(g->d_w[c]), jstim, static_cast<T*>(g->d_v[n]),
+                       static_cast<T*>(g->d_w[n]), static_cast<T*>(g->d_tact), ionic_t<T>(g),
+                       static_cast<T>(g->dt), static_cast<T>(g->theta),
+                       static_cast<double>(g->step) * g->dt, g->d_flags);
+  timer_end(g, t0);
+  return EP_OK;
+}
+
+template <typename T>
 ep_status step_be(ep_grid g, const T* jstim, ep_step_info* acc) {
   const int c = g->cur, n = 1 - c;
   T* x = static_cast<T*>(g->d_v[n]);
@@ -752,6 +765,8 @@ ep_status run_steps(ep_grid g, int32_t nsteps, ep_step_info* info) {
       if (g->have_bprev) g->dsel = (g->dsel + 1) % kDRing;   // d_{n-1} went into the ring
       g->pred_len = g->have_bprev ? g->pred_len + 1 : 1;
       g->have_bprev = true;
+    } else if (g->diff == EP_DIFF_EXPLICIT27) {
+      TRY(step_explicit27<T>(g, jstim));
     } else {
       TRY(step_explicit<T>(g, jstim));
     }
@@ -1074,12 +1089,13 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   if (!(d->dt > 0) || !std::isfinite(d->dt)) return fail(g, EP_ERR_ARG, "dt must be > 0");
   if (d->model != EP_MONO && d->model != EP_BIDO) return fail(g, EP_ERR_ARG, "bad model");
   if (d->prec != EP_F64 && d->prec != EP_F32) return fail(g, EP_ERR_ARG, "bad precision");
-  if (d->diff != EP_DIFF_EXPLICIT && d->diff != EP_DIFF_BE_PCG && d->diff != EP_DIFF_BE_JACOBI)
+  if (d->diff != EP_DIFF_EXPLICIT && d->diff != EP_DIFF_BE_PCG && d->diff != EP_DIFF_BE_JACOBI &&
+      d->diff != EP_DIFF_EXPLICIT27)
     return fail(g, EP_ERR_ARG, "bad diffusion scheme");
   if (d->diff == EP_DIFF_BE_JACOBI && d->jacobi_sweeps < 1)
     return fail(g, EP_ERR_ARG, "jacobi_sweeps >= 1 required");
   if (d->model == EP_BIDO && d->diff != EP_DIFF_EXPLICIT)
-    return fail(g, EP_ERR_UNSUPPORTED, "bidomain parabolic part is explicit only");
+    return fail(g, EP_ERR_UNSUPPORTED, "bidomain takes the explicit 19-point step only");
   if (d->n_stim < 0 || (d->n_stim > 0 && !d->stim)) return fail(g, EP_ERR_ARG, "bad stimuli");
   if (d->arena && (d->arena_bytes <= 0 || reinterpret_cast<uintptr_t>(d->arena) % 256 != 0))
     return fail(g, EP_ERR_ARG, "arena must be 256-byte aligned with arena_bytes > 0");
@@ -1389,8 +1405,12 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
     }
     if (g->prec == EP_F64)
       for (int k = 0; k < 6; ++k) c64[k] = static_cast<double*>(g->d_c[k]);
-    launch_tensor_coefs(g->L, g->d_nbr, g->d_mask, dfib, dsc, sl, st, g->h, tens,
-                        need64 ? c64 : nullptr, g->prec == EP_F32 ? c32 : nullptr);
+    if (g->diff == EP_DIFF_EXPLICIT27)
+      launch_corner_coefs(g->L, g->d_nbr, g->d_mask, dfib, dsc, sl, st, g->h, tens,
+                          need64 ? c64 : nullptr, g->prec == EP_F32 ? c32 : nullptr);
+    else
+      launch_tensor_coefs(g->L, g->d_nbr, g->d_mask, dfib, dsc, sl, st, g->h, tens,
+                          need64 ? c64 : nullptr, g->prec == EP_F32 ? c32 : nullptr);
     if (g->model == EP_MONO && g->diff == EP_DIFF_EXPLICIT) {
       if (g->prec == EP_F64)
         launch_unit_tensors<double>(g->L, g->d_mask, dfib, sl, st,
@@ -1428,6 +1448,25 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
       double* const* cc = (g->prec == EP_F64) ? reinterpret_cast<double* const*>(g->d_c)
                                               : (g->model == EP_BIDO ? g->d_ci64 : tmp64);
       rc = check_explicit_stability(g, cc);
+    } else if (g->diff == EP_DIFF_EXPLICIT27) {
+      // lambda_max(-A27) <= 4 max_p lambda_max(D_p) / h^2: each of a voxel's 8
+      // corners adds a term of norm lambda_max(D_c) / (2 h^2), and D_c is a mean
+      // of voxel tensors whose largest eigenvalue is s_p max(sL, sT) (unit
+      // fibres, to the 1e-6 checked above).  Uniform tissue comes within a
+      // few per cent of it, so the bound is the test.
+      double smax = 1.0;
+      if (scale) {
+        smax = 0.0;
+        for (int64_t i = 0; i < g->nvox; ++i)
+          if (g->hmask[i]) smax = std::max(smax, hsc[i]);
+      }
+      const double lam = 4.0 * smax * std::max(sl, st) * (1.0 + 1e-5) / (g->h * g->h);
+      if (!(g->dt * lam < 2.0)) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "explicit diffusion unstable: dt*lambda_max(-A27) <= %.3f "
+                 "is not below 2", g->dt * lam);
+        rc = fail(g, EP_ERR_ARG, buf);
+      }
     }
   } while (false);
   (void)hipStreamSynchronize(g->stream);

@@ -27,7 +27,7 @@ EP_OK, EP_ERR_ARG, EP_ERR_OOM, EP_ERR_HIP, EP_ERR_NOCONV, EP_ERR_NONFINITE, EP_E
     EP_ERR_UNSUPPORTED = range(8)
 EP_F64, EP_F32 = 0, 1
 EP_MONO, EP_BIDO = 0, 1
-EP_DIFF_EXPLICIT, EP_DIFF_BE_PCG, EP_DIFF_BE_JACOBI = 0, 1, 2
+EP_DIFF_EXPLICIT, EP_DIFF_BE_PCG, EP_DIFF_BE_JACOBI, EP_DIFF_EXPLICIT27 = 0, 1, 2, 3
 FIELDS = {"v": 0, "w": 1, "phi": 2, "tact": 3}
 KERNELS = {"stencil": 0, "cg_setup": 1, "parabolic": 2, "resid": 3, "cg_tail": 4, "adjoint": 5,
            "be_init": 6, "cg_update": 7}
@@ -161,11 +161,13 @@ def make_desc(n, h, dt, mask=None, model="mono", prec="f32", diff="explicit", io
     d.model = EP_BIDO if model == "bido" else EP_MONO
     d.prec = EP_F64 if prec == "f64" else EP_F32
     d.diff = {"explicit": EP_DIFF_EXPLICIT, "be_pcg": EP_DIFF_BE_PCG,
-              "be_jacobi": EP_DIFF_BE_JACOBI}[diff]
+              "be_jacobi": EP_DIFF_BE_JACOBI, "explicit27": EP_DIFF_EXPLICIT27}[diff]
     d.dt = float(dt)
-    io = ionic or {}
-    for k in ("tau_in", "tau_out", "tau_open", "tau_close", "v_gate", "exc"):
-        setattr(d.ionic, k, float(io[k]))
+    keys = ("tau_in", "tau_out", "tau_open", "tau_close", "v_gate", "exc")
+    if ionic is None or any(k not in ionic for k in keys):
+        raise ValueError(f"ionic must give {', '.join(keys)}")
+    for k in keys:
+        setattr(d.ionic, k, float(ionic[k]))
     stims = list(stims)
     arr = (Stim * max(1, len(stims)))()
     for k, s in enumerate(stims):
