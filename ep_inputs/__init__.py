@@ -76,6 +76,9 @@ class Instance:
     pcg_maxit: int = 50
     ell_rtol: float = 1e-8
     jacobi_sweeps: int = 10       # "be_jacobi": fixed Jacobi sweeps per step
+    bath: Optional[np.ndarray] = None   # uint8, 1 on conducting bath voxels (bidomain)
+    sigma_bath: float = 0.0       # isotropic bath conductivity
+    electrodes: Optional[tuple] = None  # voxel coordinates of RA, LA, LL
 
     @property
     def nb(self) -> int:
@@ -235,6 +238,23 @@ def bidomain(n=192, steps=500):
                     mask=mask, fibre=fib, scale=None, sigma_l=0.17, sigma_t=0.019,
                     sigma_el=0.62, sigma_et=0.24, stims=stims, model="bido",
                     diff="explicit", prec="f32", ell_rtol=1e-8)
+
+
+def bidomain_bath(n=128, steps=200, sigma_bath=1.0, rout_frac=(0.30, 0.30, 0.32)):
+    """Bidomain with a conducting bath for the ECG: a smaller shell (the
+    heart) inside an n^3 box whose every other voxel (cavity and
+    surroundings) is bath of isotropic conductivity sigma_bath.  Electrodes
+    at box corners: RA (0, 0, n-1) and LL (n-1, n-1, 0) diametrically
+    opposite, LA (n-1, 0, n-1).  Heart conductivities and stimuli as in
+    bidomain(); dt 0.05."""
+    shape, mask, fib, stims = shell(n, 3001, 8, rout_frac=rout_frac)
+    bath = (mask == 0).astype(np.uint8)
+    e = ((0, 0, n - 1), (n - 1, 0, n - 1), (n - 1, n - 1, 0))
+    return Instance(name=f"bidomain_bath_{n}", n=shape, h=0.25, dt=0.05, steps=steps,
+                    mask=mask, fibre=fib, scale=None, sigma_l=0.17, sigma_t=0.019,
+                    sigma_el=0.62, sigma_et=0.24, stims=stims, model="bido",
+                    diff="explicit", prec="f32", ell_rtol=1e-8, bath=bath,
+                    sigma_bath=float(sigma_bath), electrodes=e)
 
 
 def adjoint_shell(n=128, steps=500, target=False):

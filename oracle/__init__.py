@@ -41,7 +41,8 @@ class Problem(C.Structure):
                 ("exc", C.c_double), ("model", C.c_int32), ("diff", C.c_int32),
                 ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32), ("n_stim", C.c_int32),
                 ("stim", C.POINTER(Stim)), ("mask", C.c_void_p), ("Di", C.c_void_p),
-                ("De", C.c_void_p), ("jacobi_sweeps", C.c_int32)]
+                ("De", C.c_void_p), ("jacobi_sweeps", C.c_int32), ("bath", C.c_void_p),
+                ("sig_bath", C.c_double)]
 
 
 class State(C.Structure):
@@ -180,6 +181,11 @@ class Oracle:
         self.P.mask = _p(self.mask)
         self.P.Di = _p(self.Di)
         self.P.De = _p(self.De) if self.De is not None else None
+        bath = getattr(inst, "bath", None)
+        self.bath = (None if bath is None
+                     else np.ascontiguousarray(bath, dtype=np.uint8).ravel())
+        self.P.bath = _p(self.bath) if self.bath is not None else None
+        self.P.sig_bath = float(getattr(inst, "sigma_bath", 0.0))
         m = inst.mask.astype(bool)
         self.v = np.zeros(self.N)
         self.w = np.where(m.ravel(), 1.0, 0.0)
@@ -225,6 +231,15 @@ class Oracle:
         it = lib().orc_solve_elliptic(C.byref(self.P), _p(_f64(b).ravel()), _p(phi),
                                       C.c_double(rtol), C.c_int(maxit))
         return phi.reshape(self.n), it
+
+    def ecg(self, electrodes=None):
+        """The six limb leads (I, II, III, aVR, aVL, aVF) from phi at the
+        RA, LA, LL voxels."""
+        e = self.inst.electrodes if electrodes is None else electrodes
+        ee = (C.c_int32 * 9)(*[int(k) for xyz in e for k in xyz])
+        out = np.zeros(6)
+        lib().orc_ecg(_n3(self.n), _p(self.phi), ee, _p(out))
+        return out
 
     def adjoint(self, D0, nsteps, tstar, v0=None, w0=None, step0=0):
         """Loss and gradient wrt the per-voxel scale (explicit monodomain)."""

@@ -30,8 +30,10 @@
  *     (implicit Euler: Linear Solver section, "Implicit Euler"), solved here
  *     by Jacobi-preconditioned CG to a tolerance, or by the thesis's own fixed
  *     number of Jacobi sweeps (eqn:iejac1).
- *   - Bidomain (eqn:bidomain1, heart only, v_i = v + phi_e):
- *     -(A_i + A_e) phi = A_i v*, sum_tissue phi = 0;  v_{n+1} = v* + dt A_i(v* + phi).
+ *   - Bidomain (eqn:bidomain1, v_i = v + phi_e):
+ *     -(A_i + A_e) phi = A_i v*, sum_tissue phi = 0;  v_{n+1} = v* + dt A_i(v* + phi),
+ *     optionally with a conducting bath around the heart for the ECG
+ *     (orc_solve_elliptic), and the six limb leads (orc_ecg).
  *   - Optionally (diff 3, monodomain, explicit only) the thesis's own
  *     corner-gradient operator A27 (orc_apply27), for comparison.
  *   - Activation time: first step with v_n < theta <= v_{n+1}; linear
@@ -84,6 +86,9 @@ typedef struct {
   const double* Di;   /* 6*N voxel tensors (monodomain D, or intracellular) */
   const double* De;   /* 6*N extracellular tensors (bidomain) */
   int32_t jacobi_sweeps;  /* diff 2: sweeps per step */
+  const uint8_t* bath;    /* bidomain: NULL, or 1 on conducting body-tissue
+                             (bath / torso) voxels outside the heart */
+  double sig_bath;        /* isotropic bath conductivity */
 } orc_problem;
 
 typedef struct {
@@ -416,10 +421,11 @@ static double dot(const int32_t n[3], const double* a, const double* b) {
 
 typedef struct {
   const orc_problem* P;
+  const uint8_t* mask;  /* the operator's domain */
   const double* D1;
   const double* D2;   /* second tensor set (bidomain) or NULL */
   double alpha;       /* operator is  I - alpha A  (alpha != 0)  or  -(A1 + A2) */
-  int kind;           /* 0: I - alpha A(D1);  1: -(A(D1) + A(D2)) */
+  int kind;           /* 0: I - alpha A(D1);  1: -(A(D1) + A(D2));  2: -A(D1) */
   double* tmp;
 } orc_op;
 
@@ -427,12 +433,15 @@ static void op_apply(const orc_op* o, const double* x, double* y) {
   const orc_problem* P = o->P;
   const int64_t N = nvox(P->n);
   if (o->kind == 0) {
-    orc_apply(P->n, P->h, P->mask, o->D1, x, y);
+    orc_apply(P->n, P->h, o->mask, o->D1, x, y);
     for (int64_t p = 0; p < N; ++p) y[p] = x[p] - o->alpha * y[p];
-  } else {
-    orc_apply(P->n, P->h, P->mask, o->D1, x, y);
-    orc_apply(P->n, P->h, P->mask, o->D2, x, o->tmp);
+  } else if (o->kind == 1) {
+    orc_apply(P->n, P->h, o->mask, o->D1, x, y);
+    orc_apply(P->n, P->h, o->mask, o->D2, x, o->tmp);
     for (int64_t p = 0; p < N; ++p) y[p] = -(y[p] + o->tmp[p]);
+  } else {
+    orc_apply(P->n, P->h, o->mask, o->D1, x, y);
+    for (int64_t p = 0; p < N; ++p) y[p] = -y[p];
   }
 }
 
@@ -476,17 +485,27 @@ static int pcg(const orc_op* o, const double* dinv, const double* b, double* x,
   return it;
 }
 
-static void project_mean_zero(const orc_problem* P, double* x) {
-  const int64_t N = nvox(P->n);
+static void project_mean_zero(const int32_t n[3], const uint8_t* m, double* x) {
+  const int64_t N = nvox(n);
   double s = 0.0;
   int64_t cnt = 0;
-  for (int64_t p = 0; p < N; ++p) if (P->mask[p]) { s += x[p]; ++cnt; }
-  const double m = cnt ? s / (double)cnt : 0.0;
-  for (int64_t p = 0; p < N; ++p) x[p] = P->mask[p] ? x[p] - m : 0.0;
+  for (int64_t p = 0; p < N; ++p) if (m[p]) { s += x[p]; ++cnt; }
+  const double mean = cnt ? s / (double)cnt : 0.0;
+  for (int64_t p = 0; p < N; ++p) x[p] = m[p] ? x[p] - mean : 0.0;
 }
 
-/* Solve -(A_i + A_e) phi = b on the tissue with sum phi = 0 (pure Neumann,
- * heart only).  phi holds the warm start on entry.  Returns iterations. */
+/* The elliptic part of eqn:bidomain1, pure Neumann, with sum phi = 0 over its
+ * domain:
+ *  - heart only:  -(A_i + A_e) phi = b on the heart;
+ *  - with a bath (Bidomain Model subsection, Boundary Conditions: the body
+ *    tissue conducts with Sigma_o = sig_bath I, phi is continuous and the
+ *    normal current is continuous across the heart's boundary, no current
+ *    leaves the body, the intracellular current stays in the heart):
+ *    -A_K phi = b on heart + bath, where A_K is the operator of the voxel
+ *    tensor D_i + D_e on the heart and sig_bath I on the bath.  Faces and
+ *    blocks that straddle the two take the mean of the voxel tensors, as
+ *    everywhere else.  b = A_i v* vanishes off the heart.
+ * phi holds the warm start on entry.  Returns iterations (-1: maxit). */
 int orc_solve_elliptic(const orc_problem* P, const double* b_in, double* phi,
                        double rtol, int maxit) {
   const int64_t N = nvox(P->n);
@@ -494,20 +513,58 @@ int orc_solve_elliptic(const orc_problem* P, const double* b_in, double* phi,
   double* di = (double*)malloc((size_t)N * sizeof(double));
   double* de = (double*)malloc((size_t)N * sizeof(double));
   double* tmp = (double*)malloc((size_t)N * sizeof(double));
+  uint8_t* dom = (uint8_t*)malloc((size_t)N);
+  double* Dk = NULL;
+  for (int64_t p = 0; p < N; ++p) dom[p] = P->mask[p] || (P->bath && P->bath[p]);
+  if (P->bath) {
+    Dk = (double*)calloc((size_t)6 * (size_t)N, sizeof(double));
+    for (int64_t p = 0; p < N; ++p) {
+      if (P->mask[p]) {
+        for (int c = 0; c < 6; ++c) Dk[c * N + p] = P->Di[c * N + p] + P->De[c * N + p];
+      } else if (P->bath[p]) {
+        Dk[ORC_XX * N + p] = P->sig_bath;
+        Dk[ORC_YY * N + p] = P->sig_bath;
+        Dk[ORC_ZZ * N + p] = P->sig_bath;
+      }
+    }
+  }
   memcpy(b, b_in, (size_t)N * sizeof(double));
-  project_mean_zero(P, b);
-  orc_diag(P->n, P->h, P->mask, P->Di, di);
-  orc_diag(P->n, P->h, P->mask, P->De, de);
+  project_mean_zero(P->n, dom, b);
+  if (Dk) {
+    orc_diag(P->n, P->h, dom, Dk, di);
+    memset(de, 0, (size_t)N * sizeof(double));
+  } else {
+    orc_diag(P->n, P->h, dom, P->Di, di);
+    orc_diag(P->n, P->h, dom, P->De, de);
+  }
   for (int64_t p = 0; p < N; ++p) {
     const double k = -(di[p] + de[p]);
-    di[p] = (P->mask[p] && k > 0.0) ? 1.0 / k : 0.0;
+    di[p] = (dom[p] && k > 0.0) ? 1.0 / k : 0.0;
   }
-  project_mean_zero(P, phi);
-  orc_op o = {P, P->Di, P->De, 0.0, 1, tmp};
+  project_mean_zero(P->n, dom, phi);
+  orc_op o = Dk ? (orc_op){P, dom, Dk, NULL, 0.0, 2, tmp}
+                : (orc_op){P, dom, P->Di, P->De, 0.0, 1, tmp};
   const int it = pcg(&o, di, b, phi, rtol, maxit);
-  project_mean_zero(P, phi);
-  free(b); free(di); free(de); free(tmp);
+  project_mean_zero(P->n, dom, phi);
+  free(b); free(di); free(de); free(tmp); free(dom); free(Dk);
   return it;
+}
+
+/* The six limb leads from the extracellular potential at the right-arm,
+ * left-arm and left-leg electrodes (Cardiac Simulation chapter, Results,
+ * ECG): Einthoven's I = LA - RA, II = LL - RA, III = LL - LA and Goldberger's
+ * augmented leads aVR = RA - (LA + LL)/2, aVL = LA - (RA + LL)/2,
+ * aVF = LL - (RA + LA)/2.  e holds the voxel coordinates of RA, LA, LL. */
+void orc_ecg(const int32_t n[3], const double* phi, const int32_t e[9], double out[6]) {
+  const double ra = phi[idx3(n, e[0], e[1], e[2])];
+  const double la = phi[idx3(n, e[3], e[4], e[5])];
+  const double ll = phi[idx3(n, e[6], e[7], e[8])];
+  out[0] = la - ra;
+  out[1] = ll - ra;
+  out[2] = ll - la;
+  out[3] = ra - 0.5 * (la + ll);
+  out[4] = la - 0.5 * (ra + ll);
+  out[5] = ll - 0.5 * (ra + la);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -580,7 +637,7 @@ int orc_run(const orc_problem* P, orc_state* S, int32_t nsteps, orc_info* info) 
       if (P->jacobi_sweeps > inf.cg_max) inf.cg_max = P->jacobi_sweeps;
     } else if (P->model == 0) {
       memcpy(vn, vs, (size_t)N * sizeof(double));
-      orc_op o = {P, P->Di, NULL, P->dt, 0, tmp};
+      orc_op o = {P, P->mask, P->Di, NULL, P->dt, 0, tmp};
       const int it = pcg(&o, dinv, vs, vn, P->cg_rtol, P->cg_maxit);
       if (it < 0) { rc = 1; inf.cg_fail++; inf.cg_iters += P->cg_maxit; }
       else { inf.cg_iters += it; if (it > inf.cg_max) inf.cg_max = it; }
