@@ -72,10 +72,12 @@ def parse():
                     help="grid edge of the fixed-sweep Jacobi line (0 = skip)")
     ap.add_argument("--explicit27", type=int, default=256,
                     help="shell size of the A27 vs 19-point explicit line (0: skip)")
+    ap.add_argument("--bath", type=int, default=128,
+                    help="box size of the bidomain-with-bath (ECG) line (0: skip)")
     ap.add_argument("--no-cuboid", action="store_true",
                     help="skip the benchmark-geometry cuboid line")
     ap.add_argument("--only", choices=["serving", "plain", "bidomain", "adjoint", "jacobi",
-                                       "cuboid", "explicit27"],
+                                       "cuboid", "explicit27", "bath"],
                     help="run one side workload alone and print its JSON (profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (for HBM counter scaling)")
@@ -273,6 +275,34 @@ def bench_explicit27(n, steps=200):
     return out
 
 
+def bench_bath(n, steps=40, every=10):
+    """Bidomain with a conducting bath (the ECG configuration): an n^3 box,
+    a shell heart inside it, every other voxel bath.  FP32 steps of dt 0.05
+    ms from rest: ms per step, the elliptic solve's inner iterations per
+    step, and the six leads every `every` steps."""
+    import ep_inputs as E
+    import torch
+    from paper_2302_12519_amd import Grid
+    inst = E.bidomain_bath(n, steps=steps)
+    g = Grid.from_instance(inst)
+    leads, sec, inner = [], 0.0, 0
+    for k in range(steps // every):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = g.step(every)
+        torch.cuda.synchronize()
+        sec += time.perf_counter() - t
+        inner += info["cg_iters"]
+        leads.append([float(x) for x in g.ecg(inst.electrodes)])
+    g.close()
+    done = every * (steps // every)
+    return {"workload": f"bidomain_bath_{n}: {inst.nt} heart voxels, {int(inst.bath.sum())} "
+                        f"bath voxels, {done} FP32 steps of dt {inst.dt} from rest",
+            "ms_per_step": 1e3 * sec / done, "inner_iters_per_step": inner / done,
+            "heart_voxel_steps_per_s": inst.nt * done / sec,
+            "leads_every_ms": every * inst.dt, "leads_I_II_III_aVR_aVL_aVF": leads}
+
+
 def bench_cuboid(dxs=(0.5, 0.2, 0.1), dt=0.005, t_end=60.0):
     """The thesis's benchmark geometry (20 x 7 x 3 mm cuboid, 1.5 mm corner
     stimulus) at each voxel width, FP32 explicit, dt 0.005 ms: activation
@@ -402,7 +432,8 @@ def main():
                 "adjoint": lambda: bench_adjoint(a.adjoint or 128),
                 "jacobi": lambda: bench_jacobi(a.jacobi or 256),
                 "cuboid": bench_cuboid,
-                "explicit27": lambda: bench_explicit27(a.explicit27 or 256)}[a.only]
+                "explicit27": lambda: bench_explicit27(a.explicit27 or 256),
+                "bath": lambda: bench_bath(a.bath or 128)}[a.only]
         print(json.dumps({a.only: side()}), flush=True)
         return
 
@@ -505,6 +536,8 @@ def main():
         out["cuboid"] = bench_cuboid()
     if a.explicit27:
         out["explicit27"] = bench_explicit27(a.explicit27)
+    if a.bath:
+        out["bath"] = bench_bath(a.bath)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -133,6 +133,24 @@ typedef struct {
                                 created without an arena reports its size in
                                 ep_grid_stats' device_bytes).  Ignored by
                                 ep_batch_submit */
+  const uint8_t* bath;       /* bidomain only (else EP_ERR_UNSUPPORTED): NULL,
+                                or host n0*n1*n2 box layout, nonzero on
+                                conducting body-tissue (bath / torso) voxels
+                                around the heart (Bidomain Model subsection,
+                                Boundary Conditions of eqn:bidomain1).  It
+                                must not overlap mask (EP_ERR_ARG).  The
+                                extracellular potential is then solved on
+                                heart + bath: the voxel tensor D_i + D_e on
+                                the heart, sig_bath I on the bath, faces that
+                                straddle the two taking the mean of their
+                                tensors; phi and the normal current are
+                                continuous across the heart's boundary, no
+                                current leaves heart + bath, and the
+                                intracellular current stays in the heart
+                                (v, w and T_act live on the heart only).
+                                Heart + bath must be one face-connected
+                                component; the gauge is sum phi = 0 over it */
+  double sig_bath;           /* bath conductivity (mm^2/ms), > 0 with a bath */
 } ep_grid_desc;
 
 typedef struct {
@@ -225,7 +243,8 @@ EP_API ep_status ep_adjoint_scale(ep_grid g, int32_t nsteps, int32_t ckpt_every,
                                   int64_t* n_used);
 
 /* Copy a field to host FP64 in box layout (n0*n1*n2 entries); non-tissue
- * voxels read 0 (v, w, phi) or +inf (T_act).  Synchronises the stream.
+ * voxels read 0 (v, w, phi) or +inf (T_act).  With a bath, phi is read
+ * (and written by ep_write_state) on heart + bath.  Synchronises the stream.
  * Errors: EP_ERR_ARG (NULL, n too small, bad field), EP_ERR_HIP. */
 EP_API ep_status ep_read_state(ep_grid g, ep_field f, double* host_out, size_t n);
 
@@ -242,6 +261,18 @@ EP_API ep_status ep_read_state(ep_grid g, ep_field f, double* host_out, size_t n
  * consumer's stream).  Errors: EP_ERR_ARG (NULL, bad field or dtype),
  * EP_ERR_HIP. */
 EP_API ep_status ep_read_state_device(ep_grid g, ep_field f, void* dptr, int32_t dtype);
+
+/* The six limb leads of the electrocardiogram from the extracellular
+ * potential (Cardiac Simulation chapter, Results, ECG subsection): with
+ * RA, LA, LL the potential at the right-arm, left-arm and left-leg
+ * electrodes, out[0..5] = I = LA - RA, II = LL - RA, III = LL - LA,
+ * aVR = RA - (LA + LL)/2, aVL = LA - (RA + LL)/2, aVF = LL - (RA + LA)/2.
+ * electrodes: host, 9 int32, the (x, y, z) voxel of RA, LA, LL; each must
+ * lie in the elliptic domain (heart, or bath with one).  phi is the one the
+ * last ep_step (or ep_solve_elliptic) left.  Synchronises the grid's
+ * stream.  Errors: EP_ERR_ARG (NULL, electrode outside the box or the
+ * domain), EP_ERR_UNSUPPORTED (monodomain grid), EP_ERR_HIP. */
+EP_API ep_status ep_ecg_leads(ep_grid g, const int32_t* electrodes, double* out);
 
 /* Overwrite a field from host FP64 in box layout; values at non-tissue
  * voxels are ignored.  Clears the sticky non-finite flag.  For EP_TACT,

@@ -88,10 +88,13 @@ inline int pgrid_for(int nb, bool /*fp64*/) {
   return g < 512 ? g : 512;
 }
 // ---- kernel launchers (ep_kernels.hip) ----------------------------------
+// 19-point weights of the voxel tensors on mask; with body (elliptic domain
+// with a bath, nullable) the weights cover body, whose non-tissue voxels
+// carry sig_body I
 void launch_tensor_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask,
                          const double* fib, const double* scale, double sig_l, double sig_t,
                          double h, double* tens /*6 arrays, scratch*/, double* c64[6],
-                         float* c32[6]);
+                         float* c32[6], const uint8_t* body = nullptr, double sig_body = 0.0);
 
 // corner tensors of the corner-gradient operator A27 (one corner per voxel,
 // the six entries in the slots CX..CYZ read as xx, yy, zz, xy, xz, yz)

@@ -152,21 +152,26 @@ __global__ __launch_bounds__(256) void k_box_gather(int n0, int n1, int n2, int 
 // ---------------------------------------------------------------------------
 // coefficient encoding (once per conductivity change)
 // ---------------------------------------------------------------------------
+// Voxel tensors s (sT I + (sL - sT) f f^T) on the tissue (eqn:sigma1).  With
+// body (the elliptic domain with a bath), voxels of the body outside the
+// tissue get the isotropic bath tensor sig_body I.
 __global__ __launch_bounds__(kBV) void k_tensor(int nb, const uint8_t* __restrict__ mask,
                                                 const double* __restrict__ fib,
                                                 const double* __restrict__ scale, double sig_l,
                                                 double sig_t, double* __restrict__ tens,
-                                                int64_t stride) {
+                                                int64_t stride, const uint8_t* __restrict__ body,
+                                                double sig_body) {
   const int brick = block_brick();
   if (brick >= nb) return;
   const int g = brick * kBV + threadIdx.x;
   const bool t = mask[g] != 0;
+  const double iso = (!t && body && body[g]) ? sig_body : 0.0;
   const double s = scale ? scale[g] : 1.0;
   const double f0 = fib[3 * (int64_t)g], f1 = fib[3 * (int64_t)g + 1], f2 = fib[3 * (int64_t)g + 2];
   const double a = sig_l - sig_t;
-  tens[0 * stride + g] = t ? s * (sig_t + a * f0 * f0) : 0.0;
-  tens[1 * stride + g] = t ? s * (sig_t + a * f1 * f1) : 0.0;
-  tens[2 * stride + g] = t ? s * (sig_t + a * f2 * f2) : 0.0;
+  tens[0 * stride + g] = t ? s * (sig_t + a * f0 * f0) : iso;
+  tens[1 * stride + g] = t ? s * (sig_t + a * f1 * f1) : iso;
+  tens[2 * stride + g] = t ? s * (sig_t + a * f2 * f2) : iso;
   tens[3 * stride + g] = t ? s * (a * f0 * f1) : 0.0;
   tens[4 * stride + g] = t ? s * (a * f0 * f2) : 0.0;
   tens[5 * stride + g] = t ? s * (a * f1 * f2) : 0.0;
@@ -1413,23 +1418,27 @@ void launch_scale(const LaunchCfg& L, double* x, const double* y, const double* 
 
 void launch_tensor_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask,
                          const double* fib, const double* scale, double sig_l, double sig_t,
-                         double h, double* tens, double* c64[6], float* c32[6]) {
+                         double h, double* tens, double* c64[6], float* c32[6],
+                         const uint8_t* body, double sig_body) {
   const int64_t stride = (int64_t)(L.nb + 1) * kBV;
-  k_tensor<<<L.grid, kBV, 0, L.stream>>>(L.nb, mask, fib, scale, sig_l, sig_t, tens, stride);
+  k_tensor<<<L.grid, kBV, 0, L.stream>>>(L.nb, mask, fib, scale, sig_l, sig_t, tens, stride,
+                                         body, sig_body);
   CoefOut<double> o64;
   CoefOut<float> o32;
   for (int k = 0; k < 6; ++k) {
     o64.c[k] = c64 ? c64[k] : nullptr;
     o32.c[k] = c32 ? c32[k] : nullptr;
   }
-  k_coefs<<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, mask, tens, stride, 1.0 / (h * h), o64, o32);
+  k_coefs<<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, body ? body : mask, tens, stride,
+                                        1.0 / (h * h), o64, o32);
 }
 
 void launch_corner_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask,
                          const double* fib, const double* scale, double sig_l, double sig_t,
                          double h, double* tens, double* c64[6], float* c32[6]) {
   const int64_t stride = (int64_t)(L.nb + 1) * kBV;
-  k_tensor<<<L.grid, kBV, 0, L.stream>>>(L.nb, mask, fib, scale, sig_l, sig_t, tens, stride);
+  k_tensor<<<L.grid, kBV, 0, L.stream>>>(L.nb, mask, fib, scale, sig_l, sig_t, tens, stride,
+                                         nullptr, 0.0);
   CoefOut<double> o64;
   CoefOut<float> o32;
   for (int k = 0; k < 6; ++k) {

@@ -75,6 +75,12 @@ struct ep_grid_s {
   std::vector<int> brick_pos;  // id -> (bx, by, bz)
   std::vector<uint8_t> hmask;  // (nb+1)*512 brick layout
   int64_t n_tissue = 0;
+  // bidomain bath: conducting body tissue around the heart, part of the
+  // elliptic domain only.  hbody = heart or bath (== hmask without a bath).
+  bool bath = false;
+  double sig_bath = 0.0;
+  std::vector<uint8_t> hbody;
+  int64_t n_body = 0;
   int64_t nvox = 0;            // (nb+1)*512
   LaunchCfg L{};
   int grid = 0;
@@ -90,6 +96,7 @@ struct ep_grid_s {
   int* d_nbr = nullptr;
   uint64_t* d_rowsn = nullptr;
   uint8_t* d_mask = nullptr;
+  uint8_t* d_body = nullptr;   // elliptic domain (aliases d_mask without a bath)
   int* d_brick_id = nullptr;   // box brick -> brick id or -1 (device reads into box layout)
   void* d_v[2] = {nullptr, nullptr};
   void* d_w[2] = {nullptr, nullptr};
@@ -663,7 +670,7 @@ ep_status step_jacobi(ep_grid g, const T* jstim, ep_step_info* acc) {
 template <typename T>
 ep_status elliptic(ep_grid g, const T* vsrc, double rtol, int max_outer, ep_solve_info* out) {
   const int G = g->grid;
-  const double inv_count = 1.0 / static_cast<double>(g->n_tissue);
+  const double inv_count = 1.0 / static_cast<double>(g->n_body);
   int outer = 0;
   int64_t inner_total = 0;
   double relres = 0.0;
@@ -691,7 +698,7 @@ ep_status elliptic(ep_grid g, const T* vsrc, double rtol, int max_outer, ep_solv
     if (relres <= rtol) { ok = true; break; }
     if (!std::isfinite(relres) || outer >= max_outer) break;
     const double tin = kInnerRtol;
-    launch_inner_init(g->L, g->d_r64, g->d_mask, g->d_sums, inv_count, g->d_x32, g->d_r32[0],
+    launch_inner_init(g->L, g->d_r64, g->d_body, g->d_sums, inv_count, g->d_x32, g->d_r32[0],
                       g->d_cg, g->d_cgp[0], tin * tin, g->ell_inner_maxit);
     int iters = 0;
     bool failed = false;
@@ -699,12 +706,12 @@ ep_status elliptic(ep_grid g, const T* vsrc, double rtol, int max_outer, ep_solv
                         g->d_s32, g->d_w32, g->d_p32, 1, g->ell_inner_maxit, &g->last_inner,
                         &iters, &failed));
     inner_total += iters;
-    launch_phi_correct(g->L, g->d_phi, g->d_x32, g->d_mask, g->d_partials);
+    launch_phi_correct(g->L, g->d_phi, g->d_x32, g->d_body, g->d_partials);
     launch_reduce_sum(g->stream, g->d_partials, G, 1, g->d_sums + 4);
     corrected = true;
     ++outer;
   }
-  if (corrected) launch_phi_shift(g->L, g->d_phi, g->d_mask, g->d_sums + 4, inv_count);
+  if (corrected) launch_phi_shift(g->L, g->d_phi, g->d_body, g->d_sums + 4, inv_count);
   if (out) {
     out->outer = outer;
     out->inner_iters = inner_total;
@@ -1097,6 +1104,10 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   if (d->model == EP_BIDO && d->diff != EP_DIFF_EXPLICIT)
     return fail(g, EP_ERR_UNSUPPORTED, "bidomain takes the explicit 19-point step only");
   if (d->n_stim < 0 || (d->n_stim > 0 && !d->stim)) return fail(g, EP_ERR_ARG, "bad stimuli");
+  if (d->bath && d->model != EP_BIDO)
+    return fail(g, EP_ERR_UNSUPPORTED, "a bath belongs to the bidomain elliptic solve");
+  if (d->bath && (!(d->sig_bath > 0) || !std::isfinite(d->sig_bath)))
+    return fail(g, EP_ERR_ARG, "sig_bath must be finite and > 0");
   if (d->arena && (d->arena_bytes <= 0 || reinterpret_cast<uintptr_t>(d->arena) % 256 != 0))
     return fail(g, EP_ERR_ARG, "arena must be 256-byte aligned with arena_bytes > 0");
   const ep_ionic& io = d->ionic;
@@ -1142,11 +1153,20 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
     g->own_stream = true;
   }
 
-  // brick map
+  // brick map, over the heart and the bath
   const int64_t N = static_cast<int64_t>(g->n[0]) * g->n[1] * g->n[2];
   std::vector<uint8_t> boxmask(N, 1);
   if (d->mask)
     for (int64_t i = 0; i < N; ++i) boxmask[i] = d->mask[i] ? 1 : 0;
+  g->bath = d->bath != nullptr;
+  g->sig_bath = g->bath ? d->sig_bath : 0.0;
+  if (g->bath) {
+    for (int64_t i = 0; i < N; ++i) {
+      if (!d->bath[i]) continue;
+      if (boxmask[i]) return fail(g, EP_ERR_ARG, "bath voxels must lie outside the heart");
+      boxmask[i] = 2;
+    }
+  }
   BrickMap bm;
   std::string merr;
   if (!build_brick_map(g->n, boxmask.data(), bm, merr)) return fail(g, EP_ERR_ARG, merr);
@@ -1155,11 +1175,26 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   g->nbz = bm.nbz;
   g->brick_id = std::move(bm.brick_id);
   g->brick_pos = std::move(bm.brick_pos);
-  g->hmask = std::move(bm.mask);
+  g->hbody = std::move(bm.mask);
   const int nb = bm.nb;
   g->nb = nb;
-  g->n_tissue = bm.n_tissue;
+  g->n_body = bm.n_tissue;
   g->nvox = bm.nvox;
+  if (g->bath) {
+    // the heart alone, in brick layout
+    g->hmask.assign(g->hbody.size(), 0);
+    g->n_tissue = 0;
+    for (int x = 0; x < g->n[0]; ++x)
+      for (int y = 0; y < g->n[1]; ++y)
+        for (int z = 0; z < g->n[2]; ++z)
+          if (boxmask[(static_cast<int64_t>(x) * g->n[1] + y) * g->n[2] + z] == 1) {
+            g->hmask[brick_index(g, x, y, z)] = 1;
+            ++g->n_tissue;
+          }
+  } else {
+    g->hmask = g->hbody;
+    g->n_tissue = g->n_body;
+  }
   g->grid = grid_for(nb);
   g->L.nb = nb;
   g->L.grid = g->grid;
@@ -1168,7 +1203,8 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
                        (g->prec == EP_F64 ? 8 : 4) > kLlcBytes;
   g->L.stream = g->stream;
   if (g->model == EP_BIDO && tissue_components(boxmask, g->n) != 1)
-    return fail(g, EP_ERR_ARG, "bidomain tissue must be one face-connected component");
+    return fail(g, EP_ERR_ARG, g->bath ? "heart and bath must be one face-connected component"
+                                       : "bidomain tissue must be one face-connected component");
   const std::vector<int>& hnbr = bm.nbr;
 
   // device buffers
@@ -1178,6 +1214,8 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   TRY(dalloc(g, &g->d_rowsn, bm.rowsn.size() * sizeof(uint64_t)));
   g->L.rowsn = g->d_rowsn;
   TRY(dalloc(g, &g->d_mask, static_cast<size_t>(g->nvox)));
+  if (g->bath) TRY(dalloc(g, &g->d_body, static_cast<size_t>(g->nvox)));
+  else g->d_body = g->d_mask;
   TRY(dalloc(g, &g->d_brick_id, g->brick_id.size() * sizeof(int)));
   for (int k = 0; k < 2; ++k) {
     TRY(dalloc(g, &g->d_v[k], vb));
@@ -1255,6 +1293,9 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
                            hipMemcpyHostToDevice, g->stream));
   HIPCHK(g, hipMemcpyAsync(g->d_mask, g->hmask.data(), g->hmask.size(), hipMemcpyHostToDevice,
                            g->stream));
+  if (g->bath)
+    HIPCHK(g, hipMemcpyAsync(g->d_body, g->hbody.data(), g->hbody.size(), hipMemcpyHostToDevice,
+                             g->stream));
   HIPCHK(g, hipStreamSynchronize(g->stream));
   TRY(build_stimuli(g));
   // initial state: v = 0, w = 1 (tissue and non-tissue of active bricks), T_act = +inf
@@ -1285,7 +1326,8 @@ ep_status write_field(ep_grid g, ep_field f, const double* in) {
     for (int y = 0; y < g->n[1]; ++y)
       for (int z = 0; z < g->n[2]; ++z) {
         const int64_t gi = brick_index(g, static_cast<int>(x), y, z);
-        if (gi < 0 || !g->hmask[gi]) continue;
+        const std::vector<uint8_t>& m = (f == EP_PHIE) ? g->hbody : g->hmask;
+        if (gi < 0 || !m[gi]) continue;
         const double v = in[box_index(g, static_cast<int>(x), y, z)];
         if (f == EP_PHIE) bd[gi] = v;
         else bt[gi] = static_cast<T>(v);
@@ -1324,7 +1366,8 @@ ep_status read_field(ep_grid g, ep_field f, double* out) {
       for (int z = 0; z < g->n[2]; ++z) {
         const int64_t gi = brick_index(g, static_cast<int>(x), y, z);
         double v = off;
-        if (gi >= 0 && g->hmask[gi]) v = (f == EP_PHIE) ? bd[gi] : static_cast<double>(bt[gi]);
+        const std::vector<uint8_t>& m = (f == EP_PHIE) ? g->hbody : g->hmask;
+        if (gi >= 0 && m[gi]) v = (f == EP_PHIE) ? bd[gi] : static_cast<double>(bt[gi]);
         out[box_index(g, static_cast<int>(x), y, z)] = v;
       }
   });
@@ -1428,8 +1471,9 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
       // A_i + A_e: both tensors share the fibre field and scale, and the
       // operator is linear in the tensor, so the sum is the operator of
       // D_i + D_e = s((sT_i + sT_e) I + ((sL_i - sT_i) + (sL_e - sT_e)) f f^T).
+      // with a bath: D_i + D_e on the heart, sig_bath I on the bath
       launch_tensor_coefs(g->L, g->d_nbr, g->d_mask, dfib, dsc, sl + sel, st + set_, g->h, tens,
-                          g->d_ck64, g->d_ck32);
+                          g->d_ck64, g->d_ck32, g->bath ? g->d_body : nullptr, g->sig_bath);
       launch_dinv<float>(g->L, g->d_nbr, cset32(g->d_ck32), 0.0f, -1.0f, g->d_dinvk);
     }
     if (g->diff == EP_DIFF_BE_PCG || g->diff == EP_DIFF_BE_JACOBI) {
@@ -1591,24 +1635,52 @@ EP_API ep_status ep_read_state_device(ep_grid g, ep_field f, void* dptr, int32_t
     case EP_TACT: src = g->d_tact; break;
   }
   const double fill = (f == EP_TACT) ? kInf : 0.0;
+  const uint8_t* fm = (f == EP_PHIE) ? g->d_body : g->d_mask;
   const bool src64 = (f == EP_PHIE) || g->prec == EP_F64;
   if (src64 && dtype == 0)
     launch_box_gather<double, double>(g->stream, g->n, g->nby, g->nbz, g->d_brick_id,
-                                      static_cast<const double*>(src), g->d_mask,
+                                      static_cast<const double*>(src), fm,
                                       static_cast<double*>(dptr), fill);
   else if (src64)
     launch_box_gather<double, float>(g->stream, g->n, g->nby, g->nbz, g->d_brick_id,
-                                     static_cast<const double*>(src), g->d_mask,
+                                     static_cast<const double*>(src), fm,
                                      static_cast<float*>(dptr), static_cast<float>(fill));
   else if (dtype == 0)
     launch_box_gather<float, double>(g->stream, g->n, g->nby, g->nbz, g->d_brick_id,
-                                     static_cast<const float*>(src), g->d_mask,
+                                     static_cast<const float*>(src), fm,
                                      static_cast<double*>(dptr), fill);
   else
     launch_box_gather<float, float>(g->stream, g->n, g->nby, g->nbz, g->d_brick_id,
-                                    static_cast<const float*>(src), g->d_mask,
+                                    static_cast<const float*>(src), fm,
                                     static_cast<float*>(dptr), static_cast<float>(fill));
   HIPCHK(g, hipGetLastError());
+  return EP_OK;
+}
+
+EP_API ep_status ep_ecg_leads(ep_grid g, const int32_t* electrodes, double* out) {
+  if (!g || !electrodes || !out) return EP_ERR_ARG;
+  if (g->model != EP_BIDO)
+    return fail(g, EP_ERR_UNSUPPORTED, "ECG leads need the bidomain extracellular potential");
+  int64_t gi[3];
+  for (int k = 0; k < 3; ++k) {
+    const int x = electrodes[3 * k], y = electrodes[3 * k + 1], z = electrodes[3 * k + 2];
+    if (x < 0 || y < 0 || z < 0 || x >= g->n[0] || y >= g->n[1] || z >= g->n[2])
+      return fail(g, EP_ERR_ARG, "electrode outside the box");
+    gi[k] = brick_index(g, x, y, z);
+    if (gi[k] < 0 || !g->hbody[gi[k]])
+      return fail(g, EP_ERR_ARG, "electrode outside the elliptic domain (heart or bath)");
+  }
+  for (int k = 0; k < 3; ++k)
+    HIPCHK(g, hipMemcpyAsync(&g->hs->sums[k], g->d_phi + gi[k], sizeof(double),
+                             hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  const double ra = g->hs->sums[0], la = g->hs->sums[1], ll = g->hs->sums[2];
+  out[0] = la - ra;
+  out[1] = ll - ra;
+  out[2] = ll - la;
+  out[3] = ra - 0.5 * (la + ll);
+  out[4] = la - 0.5 * (ra + ll);
+  out[5] = ll - 0.5 * (ra + la);
   return EP_OK;
 }
 

@@ -57,7 +57,8 @@ class GridDesc(C.Structure):
                 ("act_threshold", C.c_double), ("pcg_rtol", C.c_double),
                 ("pcg_maxit", C.c_int32), ("jacobi_sweeps", C.c_int32), ("ell_rtol", C.c_double),
                 ("ell_max_outer", C.c_int32), ("ell_inner_maxit", C.c_int32),
-                ("stream", C.c_void_p), ("arena", C.c_void_p), ("arena_bytes", C.c_int64)]
+                ("stream", C.c_void_p), ("arena", C.c_void_p), ("arena_bytes", C.c_int64),
+                ("bath", C.c_void_p), ("sig_bath", C.c_double)]
 
 
 class StepInfo(C.Structure):
@@ -95,6 +96,7 @@ def _load():
     lib.ep_read_state.argtypes = [vp, C.c_int, vp, C.c_size_t]
     lib.ep_read_state_device.argtypes = [vp, C.c_int, vp, C.c_int32]
     lib.ep_write_state.argtypes = [vp, C.c_int, vp, C.c_size_t]
+    lib.ep_ecg_leads.argtypes = [vp, vp, vp]
     lib.ep_get_step.argtypes = [vp, C.POINTER(C.c_int64)]
     lib.ep_set_step.argtypes = [vp, C.c_int64]
     lib.ep_grid_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
@@ -121,7 +123,8 @@ def _load():
     lib.ep_batch_last_error.argtypes = [vp]
     lib.ep_batch_last_error.restype = C.c_char_p
     for name in ("ep_create_grid", "ep_set_conductivity_fibres", "ep_step", "ep_solve_elliptic",
-                 "ep_read_state", "ep_read_state_device", "ep_write_state", "ep_get_step",
+                 "ep_read_state", "ep_read_state_device", "ep_write_state", "ep_ecg_leads",
+                 "ep_get_step",
                  "ep_set_step",
                  "ep_grid_stats", "ep_kernel_timing", "ep_kernel_time", "ep_destroy_grid",
                  "ep_adjoint_scale",
@@ -141,7 +144,7 @@ def _p(a):
 def make_desc(n, h, dt, mask=None, model="mono", prec="f32", diff="explicit", ionic=None,
               stims=(), theta=0.5, pcg_rtol=1e-6, pcg_maxit=50, ell_rtol=1e-8,
               ell_max_outer=8, ell_inner_maxit=4000, stream=None, arena=None,
-              jacobi_sweeps=10):
+              jacobi_sweeps=10, bath=None, sig_bath=0.0):
     """Fill an ep_grid_desc; returns it and the arrays it points into (keep
     them alive while the descriptor is used).  arena: optional caller-owned
     device memory, a torch CUDA tensor whose bytes the grid carves its
@@ -193,6 +196,13 @@ def make_desc(n, h, dt, mask=None, model="mono", prec="f32", diff="explicit", io
         keep.append(arena)
         d.arena = C.c_void_p(arena.data_ptr())
         d.arena_bytes = int(arena.numel() * arena.element_size())
+    if bath is not None:
+        b = np.ascontiguousarray(bath, dtype=np.uint8).ravel()
+        if b.size != N:
+            raise ValueError("bath size does not match n")
+        keep.append(b)
+        d.bath = _p(b)
+        d.sig_bath = float(sig_bath)
     return d, keep
 
 
@@ -202,10 +212,11 @@ class Grid:
     def __init__(self, n, h, dt, mask=None, model="mono", prec="f32", diff="explicit",
                  ionic=None, stims=(), theta=0.5, pcg_rtol=1e-6, pcg_maxit=50,
                  ell_rtol=1e-8, ell_max_outer=8, ell_inner_maxit=4000, stream=None,
-                 arena=None, jacobi_sweeps=10):
+                 arena=None, jacobi_sweeps=10, bath=None, sig_bath=0.0):
         self._desc, keep = make_desc(n, h, dt, mask, model, prec, diff, ionic, stims, theta,
                                      pcg_rtol, pcg_maxit, ell_rtol, ell_max_outer,
-                                     ell_inner_maxit, stream, arena, jacobi_sweeps)
+                                     ell_inner_maxit, stream, arena, jacobi_sweeps, bath,
+                                     sig_bath)
         self._keep = keep
         self.n = tuple(int(k) for k in n)
         self.N = int(np.prod(self.n))
@@ -222,7 +233,9 @@ class Grid:
                 prec=prec or inst.prec, diff=inst.diff, ionic=inst.ionic, stims=inst.stims,
                 theta=inst.theta, pcg_rtol=inst.pcg_rtol, pcg_maxit=inst.pcg_maxit,
                 ell_rtol=inst.ell_rtol,
-                jacobi_sweeps=getattr(inst, "jacobi_sweeps", 10), **kw)
+                jacobi_sweeps=getattr(inst, "jacobi_sweeps", 10),
+                bath=getattr(inst, "bath", None), sig_bath=getattr(inst, "sigma_bath", 0.0),
+                **kw)
         g.set_conductivity(inst.fibre, inst.scale, inst.sigma_l, inst.sigma_t,
                            inst.sigma_el, inst.sigma_et)
         return g
@@ -312,6 +325,14 @@ class Grid:
         self._check(lib.ep_grid_stats(self._h, C.byref(a), C.byref(b), C.byref(c)),
                     "ep_grid_stats")
         return {"n_tissue": a.value, "n_bricks": b.value, "device_bytes": c.value}
+
+    def ecg(self, electrodes):
+        """Leads I, II, III, aVR, aVL, aVF from phi at the RA, LA, LL voxels
+        (three (x, y, z) triples)."""
+        e = np.ascontiguousarray(np.asarray(electrodes, dtype=np.int32).reshape(9))
+        out = np.zeros(6)
+        self._check(lib.ep_ecg_leads(self._h, _p(e), _p(out)), "ep_ecg_leads")
+        return out
 
     def kernel_timing(self, enable=True, kernels=None):
         """Time launches with HIP events: all kernels, or only those named in

@@ -1,0 +1,133 @@
+"""GPU parity of the bidomain step with a conducting bath around the heart
+(Boundary Conditions of eqn:bidomain1) and of the six ECG leads (Results,
+ECG) against the oracle:
+
+- the elliptic solve on heart + bath meets its FP64 residual bound measured
+  with the oracle's operators, in the sum-zero gauge, at 32^3 and 128^3;
+- FP32 and FP64 runs: v, phi on heart + bath and the leads;
+- refused inputs (bath on a monodomain grid, overlapping the heart, zero
+  conductivity; electrodes outside the domain).
+"""
+import numpy as np
+import pytest
+
+import ep_inputs as E
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2302_12519_amd as P
+    return P
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def bath_operator(orc, inst, o):
+    """-A_K on heart + bath, with the tensor field built here in numpy."""
+    N = inst.nb
+    m, bt = inst.mask.ravel() > 0, inst.bath.ravel() > 0
+    Dk = np.zeros((6, N))
+    Dk[:, m] = (o.Di + o.De)[:, m]
+    Dk[:3, bt] = inst.sigma_bath
+    dom = (m | bt).reshape(inst.n).astype(np.uint8)
+    return (lambda phi: -orc.apply(inst.n, inst.h, dom, Dk, phi)), dom
+
+
+@pytest.mark.parametrize("n", [32, 128])
+def test_bath_elliptic_residual_in_fp64(P, orc, n):
+    inst = E.bidomain_bath(n, steps=0)
+    say(f"case bidomain_bath_{n} elliptic")
+    g = P.Grid.from_instance(inst)
+    o = orc.Oracle(inst)
+    X, Y, Z = np.meshgrid(*[np.arange(k) for k in inst.n], indexing="ij")
+    v = (0.5 + 0.5 * np.sin(0.31 * X + 0.17 * Y) * np.cos(0.23 * Z)) * inst.mask
+    g.write("v", v)
+    vg = g.read("v")
+    info = g.solve_elliptic(1e-8, 10)
+    phi = g.read("phi")
+    g.close()
+    K, dom = bath_operator(orc, inst, o)
+    b = orc.apply(inst.n, inst.h, inst.mask, o.Di, vg)
+    relres = np.linalg.norm(b - K(phi)) / np.linalg.norm(b)
+    say(f"bath_{n} elliptic: outer {info['outer']} inner {info['inner_iters']} "
+        f"relres(gpu) {info['relres']:.2e} relres(oracle) {relres:.2e}")
+    assert relres <= 2e-8
+    assert abs(phi[dom > 0].sum()) <= 1e-9 * np.abs(phi).sum()
+    assert np.abs(phi[inst.bath > 0]).max() > 0.0
+    if n <= 32:
+        ref, _ = o.solve_elliptic(b)
+        assert rel(phi, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_bath_steps_and_leads(P, orc, prec):
+    """60 steps of dt 0.05 from rest on a 24^3 box (heart shell inside a
+    bath): v, phi and the six leads against the oracle.  Bars: FP32 as the
+    heart-only bidomain run (v 1e-4, phi 1e-3); FP64 with the elliptic
+    solve refined to 1e-11: 1e-8."""
+    inst = E.bidomain_bath(24, steps=60)
+    inst.prec = prec
+    inst.ell_rtol = 1e-8 if prec == "f32" else 1e-11
+    say(f"case bidomain_bath_24 {prec} 60 steps")
+    g = P.Grid.from_instance(inst)
+    o = orc.Oracle(inst)
+    leads, leads_o = [], []
+    for _ in range(3):
+        g.step(20)
+        o.run(20)
+        leads.append(g.ecg(inst.electrodes))
+        leads_o.append(o.ecg())
+    err = rel(g.read("v"), o.field("v"))
+    perr = rel(g.read("phi"), o.field("phi"))
+    g.close()
+    L, Lo = np.array(leads), np.array(leads_o)
+    lerr = np.abs(L - Lo).max() / np.abs(Lo).max()
+    say(f"bath_24 {prec}: v err {err:.2e} phi err {perr:.2e} lead err {lerr:.2e}; "
+        f"leads at 3 ms {np.array2string(L[-1], precision=4)}")
+    assert np.abs(Lo).max() > 0.0
+    assert np.allclose(L[:, 0] + L[:, 2], L[:, 1], rtol=0, atol=1e-12 * np.abs(L).max())
+    if prec == "f32":
+        assert err <= 1e-4 and perr <= 1e-3 and lerr <= 1e-3
+    else:
+        assert err <= 1e-8 and perr <= 1e-8 and lerr <= 1e-8
+
+
+def test_bath_refused_inputs(P):
+    inst = E.bidomain_bath(16, steps=0)
+    say("case bath refused inputs")
+    kw = dict(mask=inst.mask, model="bido", ionic=inst.ionic, stims=inst.stims)
+    with pytest.raises(P.ep.EPError) as e:
+        P.Grid(inst.n, inst.h, inst.dt, mask=inst.mask, model="mono", ionic=inst.ionic,
+               bath=inst.bath, sig_bath=1.0)
+    assert e.value.status == P.ep.EP_ERR_UNSUPPORTED
+    overlap = inst.bath.copy()
+    overlap[inst.mask > 0] = 1
+    for bath, sb in ((overlap, 1.0), (inst.bath, 0.0)):
+        with pytest.raises(P.ep.EPError) as e:
+            P.Grid(inst.n, inst.h, inst.dt, bath=bath, sig_bath=sb, **kw)
+        assert e.value.status == P.ep.EP_ERR_ARG
+    # a bath that leaves one corner out: an electrode there is refused
+    part = inst.bath.copy()
+    part[0, 0, -1] = 0
+    g = P.Grid(inst.n, inst.h, inst.dt, bath=part, sig_bath=1.0, **kw)
+    g.set_conductivity(inst.fibre, None, inst.sigma_l, inst.sigma_t, inst.sigma_el,
+                       inst.sigma_et)
+    with pytest.raises(P.ep.EPError) as e:
+        g.ecg(inst.electrodes)
+    assert e.value.status == P.ep.EP_ERR_ARG
+    g.close()
+    m = P.Grid(inst.n, inst.h, inst.dt, mask=inst.mask, ionic=inst.ionic)
+    with pytest.raises(P.ep.EPError) as e:
+        m.ecg(inst.electrodes)
+    assert e.value.status == P.ep.EP_ERR_UNSUPPORTED
+    m.close()
