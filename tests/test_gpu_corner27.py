@@ -119,6 +119,38 @@ def test_explicit27_256_one_step_every_voxel(P, orc):
     assert (np.isfinite(Tg) != np.isfinite(To)).sum() <= 2
 
 
+@pytest.mark.parametrize("shape", [(8, 9, 1), (1, 1, 1), (12, 2, 11)])
+def test_explicit27_degenerate_grids(P, orc, shape):
+    """A grid one voxel thick has no 2x2x2 block, so A27 has no corner and
+    the step is the reaction alone; a two-voxel-thick slab has one layer of
+    corners.  FP64 against the oracle, 20 steps from a random state."""
+    rng = np.random.default_rng(sum(shape))
+    fib = rng.normal(size=shape + (3,))
+    fib /= np.linalg.norm(fib, axis=-1, keepdims=True)
+    inst = E.Instance(name="c27_thin", n=shape, h=0.25, dt=0.02, steps=0,
+                      mask=np.ones(shape, np.uint8), fibre=fib, scale=None, sigma_l=0.2,
+                      sigma_t=0.05, stims=[], diff="explicit27", prec="f64")
+    say(f"case A27 degenerate grid {shape}")
+    g = P.Grid.from_instance(inst)
+    o = orc.Oracle(inst)
+    v0, w0 = E.random_state(inst, 3)
+    g.write("v", v0)
+    g.write("w", w0)
+    o.set_state(v=v0, w=w0)
+    g.step(20)
+    o.run(20)
+    err = rel(g.read("v"), o.field("v"))
+    g.close()
+    assert err <= 1e-13
+    if min(shape) == 1:
+        bare = orc.Oracle(inst)
+        bare.set_state(v=v0, w=w0)
+        for _ in range(20):
+            vs, ws = bare.ionic(bare.field("v"), bare.field("w"))
+            bare.set_state(v=vs, w=ws)
+        assert rel(o.field("v"), bare.field("v")) <= 1e-15
+
+
 def test_explicit27_stability_bound(P):
     """h 0.25, sigma_l 0.2: A27 needs dt * 12.8 / ms < 2, so dt 0.155 is
     accepted (where the 19-point operator, lambda_max ~ 19.5 / ms, is not)
