@@ -296,16 +296,18 @@ EP_API ep_status ep_grid_stats(ep_grid g, int64_t* n_tissue, int64_t* n_bricks,
  * ep_kernel_time returns the summed milliseconds and the launch count since
  * the last ep_kernel_timing call.  Events between launches cost time, so
  * timing only the kernel of interest disturbs a run least.  kernel_id 0: the
- * fused explicit step, or one PCG iteration (x / r update, new direction and
- * operator apply in one launch, implicit-Euler or elliptic); 1: the first
- * launch of a PCG solve (implicit-Euler: p0 = z0, q0 = K p0; elliptic:
- * w0 = K u0); 2: the bidomain parabolic stencil; 3: the FP64 elliptic
- * residual; 4: PCG launches that only found the solve done (recorded under
- * a timed id 0, 1 or 7 and moved here); 5: the adjoint step of
- * ep_adjoint_scale (its forward and recompute launches count as 0); 6: the
- * reaction + initial-residual launch of an implicit-Euler step; 7: the
- * implicit-Euler solve's last launch, which only applies the last x
- * update. */
+ * fused explicit step, one implicit-Euler PCG iteration (x / r update, new
+ * direction and operator apply in one launch), or the apply launch of an
+ * elliptic inner iteration (z = M^-1 r, w = K z); 1: the first launch of an
+ * implicit-Euler PCG solve (p0 = z0, q0 = K p0); 2: the bidomain parabolic
+ * stencil; 3: the FP64 elliptic residual; 4: launches that only found the
+ * solve done (recorded under a timed id 0 or 1 and moved here); 5: the
+ * adjoint step of ep_adjoint_scale (its forward and recompute launches count
+ * as 0); 6: the reaction + initial-residual launch of an implicit-Euler
+ * step; 7: the implicit-Euler solve's last launch, which only applies the
+ * last x update, or the update launch of an elliptic inner iteration (x, r,
+ * p, s and the brick sums of r); 8: the coarse correction of an elliptic
+ * inner iteration (aggregate sums and the GEMV with the coarse inverse). */
 EP_API ep_status ep_kernel_timing(ep_grid g, int32_t enable);
 EP_API ep_status ep_kernel_time(ep_grid g, int32_t kernel_id, double* total_ms,
                                 int64_t* launches);

@@ -82,7 +82,7 @@ constexpr long long kLlcBytes = 256ll << 20;
 
 inline int grid_for(int nb) { return ((nb + kXcd - 1) / kXcd) * kXcd; }
 // persistent launches: as many 512-thread blocks as stay resident on the
-// 256 CUs (the one-reduction CG kernel needs 65-128 VGPRs: 2 blocks per CU)
+// 256 CUs (the persistent CG kernels need 100-115 VGPRs: 2 blocks per CU)
 inline int pgrid_for(int nb, bool /*fp64*/) {
   const int g = grid_for(nb);
   return g < 512 ? g : 512;
@@ -102,6 +102,28 @@ void launch_corner_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask
                          const double* fib, const double* scale, double sig_l, double sig_t,
                          double h, double* tens /*6 arrays, scratch*/, double* c64[6],
                          float* c32[6]);
+
+// two-level preconditioner of the bidomain inner solve (aggregates of
+// bricks; see ep_kernels.hip): Kc = P^T K P into the zeroed dense kc (n x n,
+// FP64) from the FP64 weights, K = c0 I + c1 A; kb: nb * 27 scratch
+void launch_coarse_setup(const LaunchCfg& L, const int* nbr, double* const ck64[6], double c0,
+                         double c1, int n, const int* agg_ptr, const int* agg_brk, const int* agg,
+                         double* kb, double* kc);
+// kc += shift (every entry), then kc^-1 in place (Gauss-Jordan, FP64) and
+// its FP32 copy in kinv, rows padded to ld; rowk, colk: n doubles each
+void launch_coarse_invert(hipStream_t st, int n, int ld, double* kc, double shift, double* rowk,
+                          double* colk, float* kinv);
+void launch_cg2_update(const LaunchCfg& L, float* x, float* r, float* p, float* s, const float* z,
+                       const float* w, float* rb, int kind, const CGScalars* cin, CGScalars* cout,
+                       const double* prev, unsigned long long* mirror, unsigned seq);
+// cc = kinv (aggregate sums of rb); with single-brick aggregates rb holds
+// them already (rb and rc hold ld entries, zero beyond n)
+void launch_coarse_apply(hipStream_t st, int n, int ld, bool brick_aggs, const int* agg_ptr,
+                         const int* agg_brk, const float* rb, float* rc, const float* kinv,
+                         float* cc, const CGScalars* sc);
+void launch_cg2_apply(const LaunchCfg& L, const int* nbr, CoefSet<float> c, float c0, float c1,
+                      const float* dinv, const float* r, const float* cc, const int* agg, float* z,
+                      float* w, const CGScalars* cin, double* parts);
 
 // explicit step with A27 (ionic + diffusion + activation)
 template <typename T>
@@ -134,14 +156,6 @@ void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v
                     double tprev, int check_prev, int* flags, CGScalars* cout, double* parts,
                     double tol2, int maxit);
 
-// One launch of the one-reduction PCG for K = c0 I + c1 A (kind 0 set-up,
-// 1 first iteration, 2 general; init_kind 0 after k_be_init, 1 after
-// k_inner_init).  r, s, w are ping-pong pairs (read with halo, write own).
-template <typename T>
-void launch_cgcg(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, const T* dinv,
-                 T* x, const T* r_in, T* r_out, T* p, const T* s_in, T* s_out, const T* w_in,
-                 T* w_out, int kind, int init_kind, const CGScalars* cin, CGScalars* cout,
-                 const double* prev, double* parts, unsigned long long* mirror, unsigned seq);
 
 // One-launch-per-iteration PCG (textbook recurrences with the next
 // residual norms expanded in the previous launch's dots; 7 partials per

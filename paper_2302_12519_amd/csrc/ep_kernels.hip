@@ -30,7 +30,9 @@
 //   k_be_init, k_pcg_step: implicit-Euler diffusion step (Linear Solver
 //     section, "Implicit Euler") solved by Jacobi-preconditioned CG;
 //     k_jacobi: the same step by the thesis's fixed Jacobi sweeps (eqn:iejac1);
-//     k_cgcg: the same CG in one-reduction form for the elliptic solves.
+//     k_cg2_update, k_coarse_gemv, k_cg2_apply (with k_coarse_brick and the
+//     Gauss-Jordan set-up): the elliptic inner solve, one-reduction PCG with
+//     a two-level (Jacobi + aggregate coarse space) preconditioner.
 //   k_resid64, k_inner_init, k_phi_correct, k_phi_shift, k_parabolic: the
 //     bidomain step (eqn:bidomain1): elliptic solve for phi_e by FP32 PCG
 //     inside FP64 refinement, then the parabolic update.
@@ -482,13 +484,13 @@ __global__ __launch_bounds__(kBV) void k_ionic(int nb, const T* __restrict__ v,
 // host and the next launch.  Partials and scalars are double-buffered: a
 // launch reads `prev` / `cin` and writes `parts` / `cout`.
 //
-// The iteration is the one-reduction form of preconditioned CG (Chronopoulos
-// and Gear): with u = M^-1 r and w = K u it carries s = K p by recurrence,
+// The elliptic inner solve uses the one-reduction form of preconditioned CG
+// (Chronopoulos and Gear): with u = M^-1 r and w = K u it carries s = K p by
+// recurrence,
 //   gamma = (r, u), delta = (u, w),  beta = gamma / gamma_old,
 //   alpha = gamma / (delta - beta gamma / alpha_old),
 //   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
-// so one stencil launch per iteration does both the vector updates and the
-// operator application, and its three dot products share one reduction.
+// so its three dot products share one reduction.
 
 // Reaction fused with the initial guess and residual of the implicit solve
 // (I - dt A) x = b, b = v*.  The guess extrapolates the diffusion increment
@@ -611,18 +613,145 @@ __device__ __forceinline__ void publish_status(unsigned long long* mirror, unsig
 // relative to it when init_kind == 1).  kind 1: first iteration (beta = 0,
 // no p / s history).  kind 2: general iteration.  K = c0 I + c1 A.
 // Partials: (gamma, delta, rho) = ((r, u), (u, w), (r, r)).
-template <typename T>
-__global__ __launch_bounds__(kBV) void k_cgcg(int nb, const int* __restrict__ nbr, CoefSet<T> c,
-                                              T c0, T c1, const T* __restrict__ dinv,
-                                              T* __restrict__ x, const T* __restrict__ r_in,
-                                              T* __restrict__ r_out, T* __restrict__ p,
-                                              const T* __restrict__ s_in, T* __restrict__ s_out,
-                                              const T* __restrict__ w_in,
-                                              T* __restrict__ w_out, int kind, int init_kind,
-                                              const CGScalars* __restrict__ cin, CGScalars* cout,
-                                              const double* __restrict__ prev, double* parts,
-                                              const uint64_t* __restrict__ rowsn,
-                                              unsigned long long* mirror, unsigned seq) {
+// ---------------------------------------------------------------------------
+// Two-level preconditioner of the bidomain inner solve:
+//   M^-1 = D^-1 + P Kc^-1 P^T,
+// D the diagonal of K, P piecewise constant on aggregates of bricks (a voxel
+// of the elliptic domain belongs to its brick's aggregate), Kc = P^T K P with
+// s/n_c added to every entry so that it is invertible (K is singular only on
+// constants, and the inner solve sees sum-zero residuals, whose restriction
+// sums to zero).  Kc^-1 is formed once per conductivity and applied as a
+// dense GEMV.  The inner iteration is the one-reduction (Chronopoulos-Gear)
+// PCG split over four launches: update (x, r, p, s and the brick sums of r),
+// aggregate sums, coarse GEMV, apply (z = M^-1 r, w = K z and the dots).
+// Every sum is taken in a fixed order.
+// ---------------------------------------------------------------------------
+
+// The 18 off-diagonal entries of the 19-point operator as (offset, sign of
+// the weight in gather18's order), apply19's layout.
+__device__ __forceinline__ void off18(int i, int& dx, int& dy, int& dz, int& sg) {
+  const int o[18][4] = {{1, 0, 0, 1},   {-1, 0, 0, 1},  {0, 1, 0, 1},  {0, -1, 0, 1},
+                        {0, 0, 1, 1},   {0, 0, -1, 1},  {1, 1, 0, 1},  {-1, -1, 0, 1},
+                        {1, -1, 0, -1}, {-1, 1, 0, -1}, {1, 0, 1, 1},  {-1, 0, -1, 1},
+                        {1, 0, -1, -1}, {-1, 0, 1, -1}, {0, 1, 1, 1},  {0, -1, -1, 1},
+                        {0, 1, -1, -1}, {0, -1, 1, -1}};
+  dx = o[i][0];
+  dy = o[i][1];
+  dz = o[i][2];
+  sg = o[i][3];
+}
+
+// Per brick, the 27 sums over the brick's voxels p and the voxels q of
+// neighbour slot s of K_pq, K = c0 I + c1 A (FP64 weights).  Block sums in a
+// fixed order; kb[brick * 27 + s].
+__global__ __launch_bounds__(kBV) void k_coarse_brick(int nb, const int* __restrict__ nbr,
+                                                      CoefSet<double> c, double c0, double c1,
+                                                      double* __restrict__ kb) {
+  __shared__ int nbs[kNbr];
+  __shared__ double red[kBV / 64];
+  const int brick = block_brick();
+  if (brick >= nb) return;
+  const int t = threadIdx.x;
+  if (t < kNbr) nbs[t] = nbr[brick * kNbr + t];
+  __syncthreads();
+  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
+  double k18[18];
+  gather18(c, nbs, brick, lx, ly, lz, k18);
+  int slot[18];
+  double val[18];
+#pragma unroll
+  for (int i = 0; i < 18; ++i) {
+    int dx, dy, dz, sg;
+    off18(i, dx, dy, dz, sg);
+    const int tx = lx + dx, ty = ly + dy, tz = lz + dz;
+    slot[i] = (tx < 0 ? 0 : (tx > 7 ? 2 : 1)) * 9 + (ty < 0 ? 0 : (ty > 7 ? 2 : 1)) * 3 +
+              (tz < 0 ? 0 : (tz > 7 ? 2 : 1));
+    val[i] = c1 * static_cast<double>(sg) * k18[i];
+  }
+  const double dg = c0 + c1 * diag19(k18);
+  const int lane = t & 63, wave = t >> 6;
+  for (int s2 = 0; s2 < kNbr; ++s2) {
+    double v = (s2 == 13) ? dg : 0.0;
+#pragma unroll
+    for (int i = 0; i < 18; ++i) v += (slot[i] == s2) ? val[i] : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (t == 0) {
+      double a = 0.0;
+      for (int w = 0; w < kBV / 64; ++w) a += red[w];
+      kb[static_cast<int64_t>(brick) * kNbr + s2] = a;
+    }
+    __syncthreads();
+  }
+}
+
+// Row I of the dense Kc (n x n, zeroed before): the brick rows of aggregate
+// I, its bricks in list order, their 27 slots in order.  One thread per row.
+__global__ void k_coarse_rows(int n, const int* __restrict__ agg_ptr,
+                              const int* __restrict__ agg_brk, const int* __restrict__ nbr,
+                              const int* __restrict__ agg, int nb, const double* __restrict__ kb,
+                              double* __restrict__ kc) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= n) return;
+  for (int e = agg_ptr[I]; e < agg_ptr[I + 1]; ++e) {
+    const int b = agg_brk[e];
+    for (int s2 = 0; s2 < kNbr; ++s2) {
+      const int q = nbr[b * kNbr + s2];
+      if (q >= nb) continue;
+      kc[static_cast<int64_t>(I) * n + agg[q]] += kb[static_cast<int64_t>(b) * kNbr + s2];
+    }
+  }
+}
+
+// a[i] += v for i < len
+__global__ void k_add_const(int64_t len, double* __restrict__ a, double v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < len) a[i] += v;
+}
+
+// Gauss-Jordan inversion in place, no pivoting (Kc is symmetric positive
+// definite), step k: the scaled pivot row and the pivot column ...
+__global__ void k_gj_pivot(int n, const double* __restrict__ a, int k, double* __restrict__ rowk,
+                           double* __restrict__ colk) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double piv = a[static_cast<int64_t>(k) * n + k];
+  rowk[j] = (j == k ? 1.0 : a[static_cast<int64_t>(k) * n + j]) / piv;
+  colk[j] = (j == k) ? 0.0 : a[static_cast<int64_t>(j) * n + k];
+}
+
+// ... then every entry: row k becomes the scaled pivot row; row i != k
+// loses colk[i] times it (its column k starting from 0).
+__global__ void k_gj_update(int n, double* __restrict__ a, int k, const double* __restrict__ rowk,
+                            const double* __restrict__ colk) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(n) * n) return;
+  const int i = static_cast<int>(idx / n), j = static_cast<int>(idx % n);
+  if (i == k) a[idx] = rowk[j];
+  else a[idx] = (j == k ? 0.0 : a[idx]) - colk[i] * rowk[j];
+}
+
+// FP32 copy of the n x n inverse with rows padded to ld (a multiple of 4)
+__global__ void k_to_f32(int n, int ld, const double* __restrict__ a, float* __restrict__ o) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= static_cast<int64_t>(n) * ld) return;
+  const int i = static_cast<int>(idx / ld), j = static_cast<int>(idx % ld);
+  o[idx] = j < n ? static_cast<float>(a[static_cast<int64_t>(i) * n + j]) : 0.0f;
+}
+
+// Update launch of the two-level inner PCG.  kind 0 (first): the scalars
+// from the inner init's (r, r) partials, no vector update.  kind 1: the
+// convergence test on (r, r) of the last apply, then alpha, beta from its
+// (r, z) and (z, w) and
+//   p = z + beta p, s = w + beta s, x += alpha p, r -= alpha s.
+// Both write the brick sums of r for the restriction.
+__global__ __launch_bounds__(kBV) void k_cg2_update(
+    int nb, float* __restrict__ x, float* __restrict__ r, float* __restrict__ p,
+    float* __restrict__ s, const float* __restrict__ z, const float* __restrict__ w,
+    float* __restrict__ rb, int kind, const CGScalars* __restrict__ cin, CGScalars* cout,
+    const double* __restrict__ prev, unsigned long long* mirror, unsigned seq) {
   const CGScalars in = *cin;
   if (in.done) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -632,39 +761,34 @@ __global__ __launch_bounds__(kBV) void k_cgcg(int nb, const int* __restrict__ nb
     return;
   }
   CGScalars st = in;
+  bool upd = false;
   if (kind == 0) {
-    if (init_kind == 0) {
-      double S[2];
-      sum_prev<2>(prev, gridDim.x, S);
-      st.bb = S[0];
-      st.rr = S[1];
-      st.done = (S[0] == 0.0 || S[1] <= in.tol2 * S[0]) ? 1 : 0;
-    } else {
-      double S[1];
-      sum_prev<1>(prev, gridDim.x, S);
-      st.bb = S[0];
-      st.rr = S[0];
-      st.done = (S[0] == 0.0) ? 1 : 0;
-    }
+    double S[1];
+    sum_prev<1>(prev, gridDim.x, S);
+    st.bb = S[0];
+    st.rr = S[0];
     st.it = 0;
     st.fail = 0;
+    st.alpha = st.beta = st.rz = 0.0;
+    st.done = (S[0] == 0.0) ? 1 : 0;
   } else {
     double S[3];
     sum_prev<3>(prev, gridDim.x, S);
     const double gam = S[0], del = S[1], rho = S[2];
     st.rr = rho;
-    st.it = (kind == 1) ? 0 : in.it + 1;
     if (!isfinite(rho)) { st.done = 1; st.fail = 1; }
     else if (rho <= in.tol2 * in.bb) st.done = 1;
-    else if (st.it >= in.maxit) { st.done = 1; st.fail = 1; }
+    else if (in.it >= in.maxit) { st.done = 1; st.fail = 1; }
     else {
-      const double beta = (kind == 1) ? 0.0 : gam / in.rz;
-      const double den = (kind == 1) ? del : del - beta * gam / in.alpha;
+      const double beta = (in.it == 0) ? 0.0 : gam / in.rz;
+      const double den = (in.it == 0) ? del : del - beta * gam / in.alpha;
       if (!(den > 0.0) || !isfinite(den)) { st.done = 1; st.fail = 1; }
       else {
         st.beta = beta;
         st.alpha = gam / den;
         st.rz = gam;
+        st.it = in.it + 1;
+        upd = true;
       }
     }
   }
@@ -673,10 +797,86 @@ __global__ __launch_bounds__(kBV) void k_cgcg(int nb, const int* __restrict__ nb
     publish_status(mirror, seq, st);
   }
   if (st.done) return;
-  __shared__ T s[kTile];
+  __shared__ float red[kBV / 64];
+  const float alpha = static_cast<float>(st.alpha), beta = static_cast<float>(st.beta);
+  const bool first = in.it == 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int m = 0;; ++m) {
+    const int brick = pbrick(m, nb);
+    if (brick < 0) break;
+    const int g = brick * kBV + threadIdx.x;
+    float rn = r[g];
+    if (upd) {
+      const float pn = first ? z[g] : z[g] + beta * p[g];
+      const float sn = first ? w[g] : w[g] + beta * s[g];
+      p[g] = pn;
+      s[g] = sn;
+      x[g] += alpha * pn;
+      rn -= alpha * sn;
+      r[g] = rn;
+    }
+    float v = rn;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float a = 0.0f;
+      for (int k = 0; k < kBV / 64; ++k) a += red[k];
+      rb[brick] = a;
+    }
+    __syncthreads();
+  }
+}
+
+// rc[I] = sum of the brick sums of aggregate I, in list order
+__global__ void k_agg_sum(int n, const int* __restrict__ agg_ptr, const int* __restrict__ agg_brk,
+                          const float* __restrict__ rb, float* __restrict__ rc,
+                          const CGScalars* __restrict__ st) {
+  if (st->done) return;
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= n) return;
+  float a = 0.0f;
+  for (int e = agg_ptr[I]; e < agg_ptr[I + 1]; ++e) a += rb[agg_brk[e]];
+  rc[I] = a;
+}
+
+// cc[I] = sum_J kinv[I][J] rc[J]: one block per row, rows padded to ld
+// (rc zero beyond n), 16-byte loads, FP64 accumulation
+__global__ __launch_bounds__(256) void k_coarse_gemv(int ld, const float* __restrict__ kinv,
+                                                     const float* __restrict__ rc,
+                                                     float* __restrict__ cc,
+                                                     const CGScalars* __restrict__ st) {
+  if (st->done) return;
+  __shared__ double red[4];
+  typedef float F4 __attribute__((ext_vector_type(4)));
+  const int I = blockIdx.x;
+  const F4* row = reinterpret_cast<const F4*>(kinv + static_cast<int64_t>(I) * ld);
+  const F4* v = reinterpret_cast<const F4*>(rc);
+  double a = 0.0;
+  for (int j = threadIdx.x; j < ld / 4; j += 256) {
+    const F4 m = row[j], x = v[j];
+    a += static_cast<double>(m.x * x.x + m.y * x.y) + static_cast<double>(m.z * x.z + m.w * x.w);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) cc[I] = static_cast<float>(red[0] + red[1] + red[2] + red[3]);
+}
+
+// Apply launch: z = D^-1 r + P cc on the elliptic domain (where D^-1 > 0),
+// w = c0 z + c1 A z, and the partials (r, z), (z, w), (r, r).  Every voxel
+// of the brick is written.
+__global__ __launch_bounds__(kBV) void k_cg2_apply(
+    int nb, const int* __restrict__ nbr, CoefSet<float> c, float c0, float c1,
+    const float* __restrict__ dinv, const float* __restrict__ r, const float* __restrict__ cc,
+    const int* __restrict__ agg, float* __restrict__ z, float* __restrict__ w,
+    const CGScalars* __restrict__ cin, double* parts, const uint64_t* __restrict__ rowsn) {
+  if (cin->done) return;
+  __shared__ float s[kTile];
   __shared__ int nbt[2][kNbr];
   __shared__ uint64_t rowt[2][kNbr];
-  const T alpha = static_cast<T>(st.alpha), beta = static_cast<T>(st.beta);
   double acc[3] = {0.0, 0.0, 0.0};
   NbrAhead ahead;
   int nxt = pbrick(0, nb);
@@ -685,66 +885,31 @@ __global__ __launch_bounds__(kBV) void k_cgcg(int nb, const int* __restrict__ nb
   for (int m = 0; nxt >= 0; ++m) {
     const int brick = nxt;
     const int* nbs = nbt[m & 1];
-    const uint64_t* rowm = rowt[m & 1];
     nxt = pbrick(m + 1, nb);
     ahead.fetch(nbr, rowsn, nxt);
     __syncthreads();
-    const Cell e = cell_setup(nbs, brick, rowm, nb);
-    T rn, un;
-    if (kind == 0) {
-      const T rg = r_in[e.gl], dg = dinv[e.gl];
-      T hr = T(0), hd = T(0);
-      if (e.has_halo) {
-        hr = r_in[e.hgl];
-        hd = dinv[e.hgl];
-      }
-      T k18[18];
-      gather18(c, nbs, brick, e.lx, e.ly, e.lz, k18, rowm, nb);
-      rn = rg;
-      un = dg * rg;
-      s[e.C] = un;
-      if (e.has_halo) s[e.hC] = hd * hr;
-      ahead.stage(nbt[(m + 1) & 1], rowt[(m + 1) & 1]);
-      __syncthreads();
-      const T wv = c0 * un + c1 * apply19(s, e.C, k18);
-      if (e.live) w_out[e.g] = wv;
-      acc[0] += static_cast<double>(rn) * static_cast<double>(un);
-      acc[1] += static_cast<double>(un) * static_cast<double>(wv);
-      acc[2] += static_cast<double>(rn) * static_cast<double>(rn);
-    } else {
-      const bool hist = kind != 1;
-      const T rg = r_in[e.gl], dg = dinv[e.gl], wg = w_in[e.gl], xg = x[e.gl];
-      const T sg = hist ? s_in[e.gl] : T(0);
-      const T pg = hist ? p[e.gl] : T(0);
-      T hr = T(0), hd = T(0), hw = T(0), hs = T(0);
-      if (e.has_halo) {
-        hr = r_in[e.hgl];
-        hd = dinv[e.hgl];
-        hw = w_in[e.hgl];
-        hs = hist ? s_in[e.hgl] : T(0);
-      }
-      T k18[18];
-      gather18(c, nbs, brick, e.lx, e.ly, e.lz, k18, rowm, nb);
-      const T pn = dg * rg + beta * pg;
-      const T sn = wg + beta * sg;
-      rn = rg - alpha * sn;
-      un = dg * rn;
-      s[e.C] = un;
-      if (e.has_halo) s[e.hC] = hd * (hr - alpha * (hw + beta * hs));
-      ahead.stage(nbt[(m + 1) & 1], rowt[(m + 1) & 1]);
-      __syncthreads();
-      const T wv = c0 * un + c1 * apply19(s, e.C, k18);
-      if (e.live) {
-        x[e.g] = xg + alpha * pn;
-        p[e.g] = pn;
-        s_out[e.g] = sn;
-        r_out[e.g] = rn;
-        w_out[e.g] = wv;
-      }
-      acc[0] += static_cast<double>(rn) * static_cast<double>(un);
-      acc[1] += static_cast<double>(un) * static_cast<double>(wv);
-      acc[2] += static_cast<double>(rn) * static_cast<double>(rn);
+    const Cell e = cell_setup(nbs, brick);
+    const float rg = r[e.g], dg = dinv[e.g];
+    const float cown = cc[agg[brick]];
+    float hr = 0.0f, hd = 0.0f, hc = 0.0f;
+    if (e.has_halo) {
+      hr = r[e.hg];
+      hd = dinv[e.hg];
+      hc = cc[agg[e.hg / kBV]];
     }
+    float k18[18];
+    gather18(c, nbs, brick, e.lx, e.ly, e.lz, k18);
+    const float zn = dg > 0.0f ? dg * rg + cown : 0.0f;
+    s[e.C] = zn;
+    if (e.has_halo) s[e.hC] = hd > 0.0f ? hd * hr + hc : 0.0f;
+    ahead.stage(nbt[(m + 1) & 1], rowt[(m + 1) & 1]);
+    __syncthreads();
+    const float wv = c0 * zn + c1 * apply19(s, e.C, k18);
+    z[e.g] = zn;
+    w[e.g] = wv;
+    acc[0] += static_cast<double>(rg) * static_cast<double>(zn);
+    acc[1] += static_cast<double>(zn) * static_cast<double>(wv);
+    acc[2] += static_cast<double>(rg) * static_cast<double>(rg);
   }
   block_partials<3>(acc, parts);
 }
@@ -1473,6 +1638,51 @@ void launch_explicit27(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T
                                                 ion, dt, theta, tn, flags);
 }
 
+// ---- two-level preconditioner of the bidomain inner solve ----------------
+void launch_coarse_setup(const LaunchCfg& L, const int* nbr, double* const ck64[6], double c0,
+                         double c1, int n, const int* agg_ptr, const int* agg_brk, const int* agg,
+                         double* kb, double* kc) {
+  CoefSet<double> c;
+  for (int k = 0; k < 6; ++k) c.c[k] = ck64[k];
+  k_coarse_brick<<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, c, c0, c1, kb);
+  k_coarse_rows<<<(n + 127) / 128, 128, 0, L.stream>>>(n, agg_ptr, agg_brk, nbr, agg, L.nb, kb,
+                                                      kc);
+}
+
+void launch_coarse_invert(hipStream_t st, int n, int ld, double* kc, double shift, double* rowk,
+                          double* colk, float* kinv) {
+  const int64_t nn = static_cast<int64_t>(n) * n;
+  const int64_t blocks = (nn + 255) / 256;
+  k_add_const<<<blocks, 256, 0, st>>>(nn, kc, shift);
+  for (int k = 0; k < n; ++k) {
+    k_gj_pivot<<<(n + 255) / 256, 256, 0, st>>>(n, kc, k, rowk, colk);
+    k_gj_update<<<blocks, 256, 0, st>>>(n, kc, k, rowk, colk);
+  }
+  k_to_f32<<<(static_cast<int64_t>(n) * ld + 255) / 256, 256, 0, st>>>(n, ld, kc, kinv);
+}
+
+void launch_cg2_update(const LaunchCfg& L, float* x, float* r, float* p, float* s, const float* z,
+                       const float* w, float* rb, int kind, const CGScalars* cin, CGScalars* cout,
+                       const double* prev, unsigned long long* mirror, unsigned seq) {
+  k_cg2_update<<<L.pgrid, kBV, 0, L.stream>>>(L.nb, x, r, p, s, z, w, rb, kind, cin, cout, prev,
+                                               mirror, seq);
+}
+
+void launch_coarse_apply(hipStream_t st, int n, int ld, bool brick_aggs, const int* agg_ptr,
+                         const int* agg_brk, const float* rb, float* rc, const float* kinv,
+                         float* cc, const CGScalars* sc) {
+  // single-brick aggregates: the brick sums are the aggregate sums
+  if (!brick_aggs) k_agg_sum<<<(n + 127) / 128, 128, 0, st>>>(n, agg_ptr, agg_brk, rb, rc, sc);
+  k_coarse_gemv<<<n, 256, 0, st>>>(ld, kinv, brick_aggs ? rb : rc, cc, sc);
+}
+
+void launch_cg2_apply(const LaunchCfg& L, const int* nbr, CoefSet<float> c, float c0, float c1,
+                      const float* dinv, const float* r, const float* cc, const int* agg, float* z,
+                      float* w, const CGScalars* cin, double* parts) {
+  k_cg2_apply<<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, c0, c1, dinv, r, cc, agg, z, w, cin,
+                                              parts, L.rowsn);
+}
+
 template <typename T>
 void launch_ionic(const LaunchCfg& L, const T* v, const T* w, const T* jstim, T* vs, T* wout,
                   IonicT<T> ion, T dt) {
@@ -1491,15 +1701,6 @@ void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v
                                    check_prev, flags, cout, parts, tol2, maxit, L.rowsn);
 }
 
-template <typename T>
-void launch_cgcg(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, const T* dinv,
-                 T* x, const T* r_in, T* r_out, T* p, const T* s_in, T* s_out, const T* w_in,
-                 T* w_out, int kind, int init_kind, const CGScalars* cin, CGScalars* cout,
-                 const double* prev, double* parts, unsigned long long* mirror, unsigned seq) {
-  k_cgcg<T><<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, c0, c1, dinv, x, r_in, r_out, p, s_in,
-                                           s_out, w_in, w_out, kind, init_kind, cin, cout, prev,
-                                           parts, L.rowsn, mirror, seq);
-}
 
 template <typename T>
 void launch_pcg_step(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, const T* dinv,
@@ -1646,10 +1847,6 @@ void launch_loss(const LaunchCfg& L, const uint8_t* mask, const int* cross, cons
                                   const T*, const T*, const T*, const T*, T, const T*,         \
                                   const T*, T, T, T, T*, T*, T*, T*, T*, T*, IonicT<T>, T, T*, \
                                   T, double, int, int*, CGScalars*, double*, double, int);     \
-  template void launch_cgcg<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T, const T*, T*,   \
-                               const T*, T*, T*, const T*, T*, const T*, T*, int, int,         \
-                               const CGScalars*, CGScalars*, const double*, double*,           \
-                               unsigned long long*, unsigned);                                 \
   template void launch_pcg_step<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T, const T*,  \
                                    T*, const T*, T*, const T*, T*, const T*, T*, int,          \
                                    const CGScalars*, CGScalars*, const double*, double*,       \

@@ -50,7 +50,10 @@ constexpr int kPredOrder = 4;
 constexpr int kDRing = 3;
 
 enum { KT_STENCIL = 0, KT_CGSETUP = 1, KT_PARABOLIC = 2, KT_RESID = 3, KT_CGTAIL = 4,
-       KT_ADJ = 5, KT_INIT = 6, KT_UPDATE = 7, kTimers = 8 };
+       KT_ADJ = 5, KT_INIT = 6, KT_UPDATE = 7, KT_COARSE = 8, kTimers = 9 };
+// the two-level preconditioner keeps at most this many aggregates (the dense
+// inverse is kMaxAgg^2 FP32); aggregates are cubes of 1, 2, 4, ... bricks
+constexpr int kMaxAgg = 8192;
 
 }  // namespace
 
@@ -118,11 +121,21 @@ struct ep_grid_s {
   double* d_phi_hist[3] = {};     // bidomain: ring of past solutions (extrapolated guess)
   int phi_sel = 0;                // ring slot of the next solution
   double* d_r64 = nullptr;
-  float* d_x32 = nullptr;        // inner FP32 PCG of the elliptic refinement
-  float* d_r32[2] = {nullptr, nullptr};
-  float* d_s32[2] = {nullptr, nullptr};
-  float* d_w32[2] = {nullptr, nullptr};
-  float* d_p32 = nullptr;
+  float* d_x32 = nullptr;        // inner FP32 PCG of the elliptic refinement: x,
+  float* d_r32[2] = {nullptr, nullptr};   // r and z,
+  float* d_s32 = nullptr;                 // s = K p,
+  float* d_w32 = nullptr;                 // w = K z,
+  float* d_p32 = nullptr;                 // p
+  // two-level preconditioner of the inner solve (aggregates of bricks)
+  int n_agg = 0, agg_edge = 1;   // aggregates; bricks per aggregate edge
+  int agg_ld = 0;                // n_agg rounded up to a multiple of 4 (row pitch)
+  int* d_agg = nullptr;          // nb + 1: brick -> aggregate (ghost -> n_agg)
+  int* d_agg_ptr = nullptr;      // n_agg + 1: CSR of each aggregate's bricks
+  int* d_agg_brk = nullptr;      // nb
+  float* d_rb = nullptr;         // max(nb, agg_ld): brick sums of r (zero beyond nb)
+  float* d_rc = nullptr;         // agg_ld: aggregate sums of r (zero beyond n_agg)
+  float* d_cc = nullptr;         // n_agg + 1: coarse correction (last: 0, the ghost's)
+  float* d_kinv = nullptr;       // n_agg x agg_ld: (Kc + s/n_agg)^-1, FP32
   float* d_dinvk = nullptr;
   void* d_d0[6] = {};         // explicit monodomain: unscaled voxel tensors (adjoint)
   void* d_adj = nullptr;      // adjoint work block (cached, grown on demand)
@@ -462,54 +475,6 @@ ep_status wait_status(ep_grid g, unsigned seq, const CGScalars* dev, unsigned lo
   }
 }
 
-// ---- one CG solve (device-resident scalars; host polls `done` in chunks) ----
-// One CG solve after its init launch (scalars in d_cg[0], partials in
-// d_cgp[0], r0 in r[0], x0 in x).  Launch j reads scalars / partials [j & 1]
-// and writes [(j + 1) & 1]; launch j >= 1 tests the residual left by launch
-// j - 1 before doing iteration j.  The host polls the scalars once per chunk
-// (one round trip per solve when the chunk matches the previous solve).
-template <typename T>
-ep_status cg_solve(ep_grid g, CoefSet<T> c, T c0, T c1, const T* dinv, T* x, T* const r[2],
-                   T* const sv[2], T* const wv[2], T* p, int init_kind, int maxit,
-                   int* chunk_hint, int* iters, bool* failed) {
-  CGScalars* cg = g->d_cg;
-  double* const* P = g->d_cgp;
-  // r_k lives in r[k & 1], w_k in wv[k & 1], s_k in sv[k & 1]; launch j >= 1
-  // reads r_{j-1}, s_{j-2}, w_{j-1} and writes r_j, s_{j-1}, w_j; launch 0
-  // reads r_0 and writes w_0.
-  auto launch = [&](int j) {
-    TimerPair* t0 = timer_begin(g, j == 0 ? KT_CGSETUP : KT_STENCIL);
-    const int kind = j == 0 ? 0 : (j == 1 ? 1 : 2);
-    const T* rin = (j == 0) ? r[0] : r[(j + 1) & 1];
-    launch_cgcg<T>(g->L, g->d_nbr, c, c0, c1, dinv, x, rin, r[j & 1], p, sv[j & 1],
-                   sv[(j + 1) & 1], wv[(j + 1) & 1], wv[j & 1], kind, init_kind, cg + (j & 1),
-                   cg + ((j + 1) & 1), P[j & 1], P[(j + 1) & 1], g->dmirror, ++g->seq);
-    timer_end(g, t0);
-  };
-  // The last launch of a chunk publishes its convergence test as soon as it
-  // starts, so while it still runs an iteration the host has already queued
-  // the next launch: the first chunk holds as many launches as the previous
-  // solve needed iterations, and every later chunk one.
-  int j = 0;
-  launch(j++);
-  int chunk = std::max(1, *chunk_hint);
-  unsigned long long st = 0;
-  for (;;) {
-    for (int i = 0; i < chunk; ++i) launch(j++);
-    TRY(wait_status(g, g->seq, cg + (j & 1), &st));
-    if ((st & 1) || j >= maxit + 2) break;
-    chunk = 1;
-  }
-  const int it = static_cast<int>((st >> 2) & 0x3fffffff);
-  *iters = it;
-  *failed = ((st >> 1) & 1) != 0 || !(st & 1);
-  *chunk_hint = std::max(1, it);
-  g->last_cg = cg + (j & 1);
-  // launches 1..it did an iteration; the rest only detected convergence
-  timer_retag(g, KT_STENCIL, KT_CGTAIL, j - 1 - it);
-  return EP_OK;
-}
-
 // One-launch-per-iteration PCG solve after its init launch (scalars in
 // d_cg[0], the init's (b.b, r.r) partials in d_cgp[0], r0 in rb[0], x0 in x).
 // Launch k reads scalars / partials [k & 1] and writes [(k + 1) & 1]; it
@@ -665,6 +630,94 @@ ep_status step_jacobi(ep_grid g, const T* jstim, ep_step_info* acc) {
   return EP_OK;
 }
 
+// Coarse operator of the two-level preconditioner: Kc = P^T K P over the
+// aggregates (K = -(A_i + A_e), with a bath its body operator), from the FP64
+// weights; every entry raised by s/n_agg, s the mean diagonal, so that the
+// constants (K's null space) get eigenvalue s; then its inverse in FP64 and
+// an FP32 copy for the inner solve.
+ep_status coarse_setup(ep_grid g, Temps& tmp) {
+  const int n = g->n_agg;
+  const size_t nn = static_cast<size_t>(n) * n;
+  double *kb = nullptr, *kc = nullptr, *rowk = nullptr, *colk = nullptr;
+  if (tmp.get(&kb, static_cast<size_t>(g->nb) * kNbr * sizeof(double)) != hipSuccess ||
+      tmp.get(&kc, nn * sizeof(double)) != hipSuccess ||
+      tmp.get(&rowk, n * sizeof(double)) != hipSuccess ||
+      tmp.get(&colk, n * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(g, EP_ERR_OOM, "no device memory for the coarse operator");
+  }
+  HIPCHK(g, hipMemsetAsync(kc, 0, nn * sizeof(double), g->stream));
+  launch_coarse_setup(g->L, g->d_nbr, g->d_ck64, 0.0, -1.0, n, g->d_agg_ptr, g->d_agg_brk,
+                      g->d_agg, kb, kc);
+  std::vector<double> dg(n);
+  HIPCHK(g, hipMemcpy2DAsync(dg.data(), sizeof(double), kc, (n + 1) * sizeof(double),
+                             sizeof(double), n, hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  double mean = 0.0;
+  for (double d : dg) mean += d;
+  mean /= n;
+  if (!(mean > 0.0) || !std::isfinite(mean))
+    return fail(g, EP_ERR_ARG, "coarse operator has no positive diagonal");
+  launch_coarse_invert(g->stream, n, g->agg_ld, kc, mean / n, rowk, colk, g->d_kinv);
+  HIPCHK(g, hipGetLastError());
+  HIPCHK(g, hipMemcpy2DAsync(dg.data(), sizeof(double), kc, (n + 1) * sizeof(double),
+                             sizeof(double), n, hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  for (double d : dg)
+    if (!(d > 0.0) || !std::isfinite(d))
+      return fail(g, EP_ERR_HIP, "coarse operator inverse is not positive definite");
+  return EP_OK;
+}
+
+// Inner solve of the elliptic refinement: PCG with the two-level
+// preconditioner, one-reduction form, four launches per iteration (update;
+// aggregate sums and coarse GEMV; apply).  The update launch publishes its
+// convergence test as it starts; the host keeps `chunk` iterations queued
+// ahead like the one-launch solvers.  Scalars ping-pong in d_cg[0/1]; the
+// init's partials are in d_cgp[0], the apply's in d_cgp[1].
+ep_status cg2_solve(ep_grid g, int maxit, int* chunk_hint, int* iters, bool* failed) {
+  CGScalars* cg = g->d_cg;
+  float* x = g->d_x32;
+  float* r = g->d_r32[0];
+  float* z = g->d_r32[1];
+  float* p = g->d_p32;
+  float* sv = g->d_s32;
+  float* w = g->d_w32;
+  const CoefSet<float> c = cset32(g->d_ck32);
+  auto iter = [&](int j) {
+    CGScalars* cout = cg + ((j + 1) & 1);
+    TimerPair* tu = timer_begin(g, KT_UPDATE);
+    launch_cg2_update(g->L, x, r, p, sv, z, w, g->d_rb, j == 0 ? 0 : 1, cg + (j & 1), cout,
+                      j == 0 ? g->d_cgp[0] : g->d_cgp[1], g->dmirror, ++g->seq);
+    timer_end(g, tu);
+    TimerPair* tc = timer_begin(g, KT_COARSE);
+    launch_coarse_apply(g->stream, g->n_agg, g->agg_ld, g->agg_edge == 1, g->d_agg_ptr,
+                        g->d_agg_brk, g->d_rb, g->d_rc, g->d_kinv, g->d_cc, cout);
+    timer_end(g, tc);
+    TimerPair* ta = timer_begin(g, KT_STENCIL);
+    launch_cg2_apply(g->L, g->d_nbr, c, 0.0f, -1.0f, g->d_dinvk, r, g->d_cc, g->d_agg, z, w,
+                     cout, g->d_cgp[1]);
+    timer_end(g, ta);
+  };
+  int j = 0;
+  iter(j++);
+  int chunk = std::max(1, *chunk_hint);
+  unsigned long long st = 0;
+  for (;;) {
+    for (int i = 0; i < chunk; ++i) iter(j++);
+    TRY(wait_status(g, g->seq, cg + (j & 1), &st));
+    if ((st & 1) || j >= maxit + 2) break;
+    chunk = 1;
+  }
+  const int it = static_cast<int>((st >> 2) & 0x3fffffff);
+  *iters = it;
+  *failed = ((st >> 1) & 1) != 0 || !(st & 1);
+  *chunk_hint = std::max(1, it);
+  // applies after the update that found the solve done only returned
+  timer_retag(g, KT_STENCIL, KT_CGTAIL, std::max(0, j - 1 - it));
+  return EP_OK;
+}
+
 // Mixed-precision elliptic solve for phi given the source potential vsrc
 // (FP64 refinement around FP32 Jacobi-PCG inner solves).
 template <typename T>
@@ -702,9 +755,7 @@ ep_status elliptic(ep_grid g, const T* vsrc, double rtol, int max_outer, ep_solv
                       g->d_cg, g->d_cgp[0], tin * tin, g->ell_inner_maxit);
     int iters = 0;
     bool failed = false;
-    TRY(cg_solve<float>(g, cset32(g->d_ck32), 0.0f, -1.0f, g->d_dinvk, g->d_x32, g->d_r32,
-                        g->d_s32, g->d_w32, g->d_p32, 1, g->ell_inner_maxit, &g->last_inner,
-                        &iters, &failed));
+    TRY(cg2_solve(g, g->ell_inner_maxit, &g->last_inner, &iters, &failed));
     inner_total += iters;
     launch_phi_correct(g->L, g->d_phi, g->d_x32, g->d_body, g->d_partials);
     launch_reduce_sum(g->stream, g->d_partials, G, 1, g->d_sums + 4);
@@ -1264,12 +1315,55 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
       TRY(dalloc(g, &g->d_ck32[k], b32));
     }
     TRY(dalloc(g, &g->d_x32, b32));
-    for (int k = 0; k < 2; ++k) {
-      TRY(dalloc(g, &g->d_r32[k], b32));
-      TRY(dalloc(g, &g->d_s32[k], b32));
-      TRY(dalloc(g, &g->d_w32[k], b32));
-    }
+    for (int k = 0; k < 2; ++k) TRY(dalloc(g, &g->d_r32[k], b32));
+    TRY(dalloc(g, &g->d_s32, b32));
+    TRY(dalloc(g, &g->d_w32, b32));
     TRY(dalloc(g, &g->d_p32, b32));
+    // aggregates: cubes of agg_edge^3 bricks, the smallest edge that keeps
+    // their number within kMaxAgg; numbered in brick order
+    for (g->agg_edge = 1;; g->agg_edge *= 2) {
+      const int e = g->agg_edge;
+      const int ax = (g->nbx + e - 1) / e, ay = (g->nby + e - 1) / e, az = (g->nbz + e - 1) / e;
+      std::vector<int> id(static_cast<size_t>(ax) * ay * az, -1);
+      std::vector<int> agg(nb + 1, 0);
+      int na = 0;
+      for (int b = 0; b < nb; ++b) {
+        const int* bp = &g->brick_pos[3 * static_cast<size_t>(b)];
+        int& a = id[(static_cast<size_t>(bp[0] / e) * ay + bp[1] / e) * az + bp[2] / e];
+        if (a < 0) a = na++;
+        agg[b] = a;
+      }
+      if (na > kMaxAgg) continue;
+      agg[nb] = na;
+      std::vector<int> ptr(na + 1, 0), brk(nb);
+      for (int b = 0; b < nb; ++b) ++ptr[agg[b] + 1];
+      for (int a = 0; a < na; ++a) ptr[a + 1] += ptr[a];
+      std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+      for (int b = 0; b < nb; ++b) brk[fill[agg[b]]++] = b;
+      g->n_agg = na;
+      TRY(dalloc(g, &g->d_agg, agg.size() * sizeof(int)));
+      TRY(dalloc(g, &g->d_agg_ptr, ptr.size() * sizeof(int)));
+      TRY(dalloc(g, &g->d_agg_brk, brk.size() * sizeof(int)));
+      HIPCHK(g, hipMemcpyAsync(g->d_agg, agg.data(), agg.size() * sizeof(int),
+                               hipMemcpyHostToDevice, g->stream));
+      HIPCHK(g, hipMemcpyAsync(g->d_agg_ptr, ptr.data(), ptr.size() * sizeof(int),
+                               hipMemcpyHostToDevice, g->stream));
+      HIPCHK(g, hipMemcpyAsync(g->d_agg_brk, brk.data(), brk.size() * sizeof(int),
+                               hipMemcpyHostToDevice, g->stream));
+      HIPCHK(g, hipStreamSynchronize(g->stream));
+      break;
+    }
+    g->agg_ld = (g->n_agg + 3) & ~3;
+    const size_t nrb = static_cast<size_t>(std::max(nb, g->agg_ld));
+    TRY(dalloc(g, &g->d_rb, nrb * sizeof(float)));
+    TRY(dalloc(g, &g->d_rc, static_cast<size_t>(g->agg_ld) * sizeof(float)));
+    TRY(dalloc(g, &g->d_cc, static_cast<size_t>(g->n_agg + 1) * sizeof(float)));
+    TRY(dalloc(g, &g->d_kinv, static_cast<size_t>(g->n_agg) * g->agg_ld * sizeof(float)));
+    HIPCHK(g, hipMemsetAsync(g->d_rb, 0, nrb * sizeof(float), g->stream));
+    HIPCHK(g, hipMemsetAsync(g->d_rc, 0, static_cast<size_t>(g->agg_ld) * sizeof(float),
+                             g->stream));
+    HIPCHK(g, hipMemsetAsync(g->d_cc, 0, static_cast<size_t>(g->n_agg + 1) * sizeof(float),
+                             g->stream));
     TRY(dalloc(g, &g->d_dinvk, b32));
   }
   {
@@ -1475,6 +1569,8 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
       launch_tensor_coefs(g->L, g->d_nbr, g->d_mask, dfib, dsc, sl + sel, st + set_, g->h, tens,
                           g->d_ck64, g->d_ck32, g->bath ? g->d_body : nullptr, g->sig_bath);
       launch_dinv<float>(g->L, g->d_nbr, cset32(g->d_ck32), 0.0f, -1.0f, g->d_dinvk);
+      rc = coarse_setup(g, tmp);
+      if (rc != EP_OK) break;
     }
     if (g->diff == EP_DIFF_BE_PCG || g->diff == EP_DIFF_BE_JACOBI) {
       if (g->prec == EP_F64)

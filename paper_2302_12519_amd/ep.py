@@ -30,7 +30,7 @@ EP_MONO, EP_BIDO = 0, 1
 EP_DIFF_EXPLICIT, EP_DIFF_BE_PCG, EP_DIFF_BE_JACOBI, EP_DIFF_EXPLICIT27 = 0, 1, 2, 3
 FIELDS = {"v": 0, "w": 1, "phi": 2, "tact": 3}
 KERNELS = {"stencil": 0, "cg_setup": 1, "parabolic": 2, "resid": 3, "cg_tail": 4, "adjoint": 5,
-           "be_init": 6, "cg_update": 7}
+           "be_init": 6, "cg_update": 7, "coarse": 8}
 
 
 class EPError(RuntimeError):
