@@ -109,10 +109,12 @@ void launch_corner_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask
 void launch_coarse_setup(const LaunchCfg& L, const int* nbr, double* const ck64[6], double c0,
                          double c1, int n, const int* agg_ptr, const int* agg_brk, const int* agg,
                          double* kb, double* kc);
-// kc += shift (every entry), then kc^-1 in place (Gauss-Jordan, FP64) and
-// its FP32 copy in kinv, rows padded to ld; rowk, colk: n doubles each
-void launch_coarse_invert(hipStream_t st, int n, int ld, double* kc, double shift, double* rowk,
-                          double* colk, float* kinv);
+// kc += shift (every entry), then kc^-1 in place (blocked Gauss-Jordan,
+// FP64, 32 columns per step) and its FP32 copy in kinv, rows padded to ld;
+// scratch: pinv 32 x 32, rp 32 x n, cp n x 32 doubles
+constexpr int kGjPanel = 32;
+void launch_coarse_invert(hipStream_t st, int n, int ld, double* kc, double shift, double* pinv,
+                          double* rp, double* cp, float* kinv);
 void launch_cg2_update(const LaunchCfg& L, float* x, float* r, float* p, float* s, const float* z,
                        const float* w, float* rb, int kind, const CGScalars* cin, CGScalars* cout,
                        const double* prev, unsigned long long* mirror, unsigned seq);

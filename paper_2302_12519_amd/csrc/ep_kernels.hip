@@ -711,26 +711,86 @@ __global__ void k_add_const(int64_t len, double* __restrict__ a, double v) {
   if (i < len) a[i] += v;
 }
 
-// Gauss-Jordan inversion in place, no pivoting (Kc is symmetric positive
-// definite), step k: the scaled pivot row and the pivot column ...
-__global__ void k_gj_pivot(int n, const double* __restrict__ a, int k, double* __restrict__ rowk,
-                           double* __restrict__ colk) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const double piv = a[static_cast<int64_t>(k) * n + k];
-  rowk[j] = (j == k ? 1.0 : a[static_cast<int64_t>(k) * n + j]) / piv;
-  colk[j] = (j == k) ? 0.0 : a[static_cast<int64_t>(j) * n + k];
+// Blocked Gauss-Jordan inversion in place, no pivoting (Kc is symmetric
+// positive definite), kGjPanel columns per step.  With K the step's pivot rows
+// and columns, P = A[K,K]:
+//   rows K:          A[K,:] <- P^-1 A[K,:],  and A[K,K] <- P^-1;
+//   every other row: A[i,:] <- A[i,:] - A[i,K] (P^-1 A[K,:]),  with A[i,K]
+//                    taken as 0 on the left, so A[i,K] <- -A[i,K] P^-1.
+// Each step reads and writes the matrix once for kGjPanel eliminations.
+
+// P^-1 of the bs x bs pivot block (bs <= kGjPanel) by unblocked Gauss-Jordan in
+// LDS, one block of kGjPanel * kGjPanel threads
+__global__ __launch_bounds__(kGjPanel * kGjPanel) void k_gj_pivot(int n, const double* __restrict__ a,
+                                                          int k0, int bs,
+                                                          double* __restrict__ pinv) {
+  __shared__ double m[kGjPanel][kGjPanel + 1];
+  __shared__ double rowp[kGjPanel], colp[kGjPanel];
+  const int r = threadIdx.x / kGjPanel, c = threadIdx.x % kGjPanel;
+  const bool in = r < bs && c < bs;
+  if (in) m[r][c] = a[static_cast<int64_t>(k0 + r) * n + k0 + c];
+  __syncthreads();
+  for (int k = 0; k < bs; ++k) {
+    if (threadIdx.x < bs) {
+      const int t = threadIdx.x;
+      const double piv = m[k][k];
+      rowp[t] = (t == k ? 1.0 : m[k][t]) / piv;
+      colp[t] = (t == k) ? 0.0 : m[t][k];
+    }
+    __syncthreads();
+    if (in) m[r][c] = (r == k) ? rowp[c] : (c == k ? 0.0 : m[r][c]) - colp[r] * rowp[c];
+    __syncthreads();
+  }
+  if (in) pinv[r * kGjPanel + c] = m[r][c];
 }
 
-// ... then every entry: row k becomes the scaled pivot row; row i != k
-// loses colk[i] times it (its column k starting from 0).
-__global__ void k_gj_update(int n, double* __restrict__ a, int k, const double* __restrict__ rowk,
-                            const double* __restrict__ colk) {
+// Row panel rp[t][j] = (P^-1 A[K,:])[t][j] for j outside K, P^-1[t][j - k0]
+// inside; column panel cp[i][t] = A[i][k0 + t] (i outside K; 0 inside)
+__global__ void k_gj_panels(int n, const double* __restrict__ a, int k0, int bs,
+                            const double* __restrict__ pinv, double* __restrict__ rp,
+                            double* __restrict__ cp) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= static_cast<int64_t>(n) * n) return;
-  const int i = static_cast<int>(idx / n), j = static_cast<int>(idx % n);
-  if (i == k) a[idx] = rowk[j];
-  else a[idx] = (j == k ? 0.0 : a[idx]) - colk[i] * rowk[j];
+  if (idx >= static_cast<int64_t>(kGjPanel) * n) return;
+  const int t = static_cast<int>(idx / n), j = static_cast<int>(idx % n);
+  if (t < bs) {
+    double v;
+    if (j >= k0 && j < k0 + bs) {
+      v = pinv[t * kGjPanel + (j - k0)];
+    } else {
+      v = 0.0;
+      for (int u = 0; u < bs; ++u) v += pinv[t * kGjPanel + u] * a[static_cast<int64_t>(k0 + u) * n + j];
+    }
+    rp[static_cast<int64_t>(t) * n + j] = v;
+    // the same thread grid also copies column t of the pivot columns (row j)
+    cp[static_cast<int64_t>(j) * kGjPanel + t] =
+        (j >= k0 && j < k0 + bs) ? 0.0 : a[static_cast<int64_t>(j) * n + k0 + t];
+  }
+}
+
+// The rank-bs update of one 16 x 16 tile of A per block: panel slices in LDS
+__global__ __launch_bounds__(256) void k_gj_update(int n, double* __restrict__ a, int k0, int bs,
+                                                   const double* __restrict__ rp,
+                                                   const double* __restrict__ cp) {
+  __shared__ double cs[16][kGjPanel + 1], rs[kGjPanel][17];
+  const int ti = threadIdx.x / 16, tj = threadIdx.x % 16;
+  const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+  for (int e = threadIdx.x; e < 16 * kGjPanel; e += 256) {
+    const int r = e / kGjPanel, t = e % kGjPanel;
+    cs[r][t] = (i0 + r < n && t < bs) ? cp[static_cast<int64_t>(i0 + r) * kGjPanel + t] : 0.0;
+    const int t2 = e / 16, c2 = e % 16;
+    rs[t2][c2] = (j0 + c2 < n && t2 < bs) ? rp[static_cast<int64_t>(t2) * n + j0 + c2] : 0.0;
+  }
+  __syncthreads();
+  const int i = i0 + ti, j = j0 + tj;
+  if (i >= n || j >= n) return;
+  const int64_t idx = static_cast<int64_t>(i) * n + j;
+  if (i >= k0 && i < k0 + bs) {
+    a[idx] = rs[i - k0][tj];
+    return;
+  }
+  double acc = 0.0;
+  for (int t = 0; t < bs; ++t) acc += cs[ti][t] * rs[t][tj];
+  a[idx] = ((j >= k0 && j < k0 + bs) ? 0.0 : a[idx]) - acc;
 }
 
 // FP32 copy of the n x n inverse with rows padded to ld (a multiple of 4)
@@ -1649,14 +1709,18 @@ void launch_coarse_setup(const LaunchCfg& L, const int* nbr, double* const ck64[
                                                       kc);
 }
 
-void launch_coarse_invert(hipStream_t st, int n, int ld, double* kc, double shift, double* rowk,
-                          double* colk, float* kinv) {
+void launch_coarse_invert(hipStream_t st, int n, int ld, double* kc, double shift, double* pinv,
+                          double* rp, double* cp, float* kinv) {
   const int64_t nn = static_cast<int64_t>(n) * n;
   const int64_t blocks = (nn + 255) / 256;
   k_add_const<<<blocks, 256, 0, st>>>(nn, kc, shift);
-  for (int k = 0; k < n; ++k) {
-    k_gj_pivot<<<(n + 255) / 256, 256, 0, st>>>(n, kc, k, rowk, colk);
-    k_gj_update<<<blocks, 256, 0, st>>>(n, kc, k, rowk, colk);
+  const dim3 tiles((n + 15) / 16, (n + 15) / 16);
+  for (int k0 = 0; k0 < n; k0 += kGjPanel) {
+    const int bs = std::min(kGjPanel, n - k0);
+    k_gj_pivot<<<1, kGjPanel * kGjPanel, 0, st>>>(n, kc, k0, bs, pinv);
+    k_gj_panels<<<(static_cast<int64_t>(kGjPanel) * n + 255) / 256, 256, 0, st>>>(n, kc, k0, bs, pinv,
+                                                                          rp, cp);
+    k_gj_update<<<tiles, 256, 0, st>>>(n, kc, k0, bs, rp, cp);
   }
   k_to_f32<<<(static_cast<int64_t>(n) * ld + 255) / 256, 256, 0, st>>>(n, ld, kc, kinv);
 }

@@ -638,11 +638,12 @@ ep_status step_jacobi(ep_grid g, const T* jstim, ep_step_info* acc) {
 ep_status coarse_setup(ep_grid g, Temps& tmp) {
   const int n = g->n_agg;
   const size_t nn = static_cast<size_t>(n) * n;
-  double *kb = nullptr, *kc = nullptr, *rowk = nullptr, *colk = nullptr;
+  double *kb = nullptr, *kc = nullptr, *pinv = nullptr, *rp = nullptr, *cp = nullptr;
+  const size_t panel = static_cast<size_t>(kGjPanel) * n * sizeof(double);
   if (tmp.get(&kb, static_cast<size_t>(g->nb) * kNbr * sizeof(double)) != hipSuccess ||
       tmp.get(&kc, nn * sizeof(double)) != hipSuccess ||
-      tmp.get(&rowk, n * sizeof(double)) != hipSuccess ||
-      tmp.get(&colk, n * sizeof(double)) != hipSuccess) {
+      tmp.get(&pinv, static_cast<size_t>(kGjPanel) * kGjPanel * sizeof(double)) != hipSuccess ||
+      tmp.get(&rp, panel) != hipSuccess || tmp.get(&cp, panel) != hipSuccess) {
     (void)hipGetLastError();
     return fail(g, EP_ERR_OOM, "no device memory for the coarse operator");
   }
@@ -658,7 +659,7 @@ ep_status coarse_setup(ep_grid g, Temps& tmp) {
   mean /= n;
   if (!(mean > 0.0) || !std::isfinite(mean))
     return fail(g, EP_ERR_ARG, "coarse operator has no positive diagonal");
-  launch_coarse_invert(g->stream, n, g->agg_ld, kc, mean / n, rowk, colk, g->d_kinv);
+  launch_coarse_invert(g->stream, n, g->agg_ld, kc, mean / n, pinv, rp, cp, g->d_kinv);
   HIPCHK(g, hipGetLastError());
   HIPCHK(g, hipMemcpy2DAsync(dg.data(), sizeof(double), kc, (n + 1) * sizeof(double),
                              sizeof(double), n, hipMemcpyDeviceToHost, g->stream));
