@@ -105,7 +105,9 @@ void launch_corner_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask
 
 // two-level preconditioner of the bidomain inner solve (aggregates of
 // bricks; see ep_kernels.hip): Kc = P^T K P into the zeroed dense kc (n x n,
-// FP64) from the FP64 weights, K = c0 I + c1 A; kb: nb * 27 scratch
+// FP64) from the FP64 weights, K = c0 I + c1 A; kb: nb * kCoarseRow scratch,
+// per brick its 27 neighbour-slot sums and (last) the sum of K's diagonal
+constexpr int kCoarseRow = kNbr + 1;
 void launch_coarse_setup(const LaunchCfg& L, const int* nbr, double* const ck64[6], double c0,
                          double c1, int n, const int* agg_ptr, const int* agg_brk, const int* agg,
                          double* kb, double* kc);

@@ -642,8 +642,9 @@ __device__ __forceinline__ void off18(int i, int& dx, int& dy, int& dz, int& sg)
 }
 
 // Per brick, the 27 sums over the brick's voxels p and the voxels q of
-// neighbour slot s of K_pq, K = c0 I + c1 A (FP64 weights).  Block sums in a
-// fixed order; kb[brick * 27 + s].
+// neighbour slot s of K_pq, K = c0 I + c1 A (FP64 weights), and as a 28th
+// value the sum of K's diagonal over the brick.  Block sums in a fixed
+// order; kb[brick * kCoarseRow + s].
 __global__ __launch_bounds__(kBV) void k_coarse_brick(int nb, const int* __restrict__ nbr,
                                                       CoefSet<double> c, double c0, double c1,
                                                       double* __restrict__ kb) {
@@ -670,10 +671,12 @@ __global__ __launch_bounds__(kBV) void k_coarse_brick(int nb, const int* __restr
   }
   const double dg = c0 + c1 * diag19(k18);
   const int lane = t & 63, wave = t >> 6;
-  for (int s2 = 0; s2 < kNbr; ++s2) {
-    double v = (s2 == 13) ? dg : 0.0;
+  for (int s2 = 0; s2 < kCoarseRow; ++s2) {
+    double v = (s2 == 13 || s2 == kNbr) ? dg : 0.0;
+    if (s2 < kNbr) {
 #pragma unroll
-    for (int i = 0; i < 18; ++i) v += (slot[i] == s2) ? val[i] : 0.0;
+      for (int i = 0; i < 18; ++i) v += (slot[i] == s2) ? val[i] : 0.0;
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     if (lane == 0) red[wave] = v;
@@ -681,7 +684,7 @@ __global__ __launch_bounds__(kBV) void k_coarse_brick(int nb, const int* __restr
     if (t == 0) {
       double a = 0.0;
       for (int w = 0; w < kBV / 64; ++w) a += red[w];
-      kb[static_cast<int64_t>(brick) * kNbr + s2] = a;
+      kb[static_cast<int64_t>(brick) * kCoarseRow + s2] = a;
     }
     __syncthreads();
   }
@@ -700,7 +703,7 @@ __global__ void k_coarse_rows(int n, const int* __restrict__ agg_ptr,
     for (int s2 = 0; s2 < kNbr; ++s2) {
       const int q = nbr[b * kNbr + s2];
       if (q >= nb) continue;
-      kc[static_cast<int64_t>(I) * n + agg[q]] += kb[static_cast<int64_t>(b) * kNbr + s2];
+      kc[static_cast<int64_t>(I) * n + agg[q]] += kb[static_cast<int64_t>(b) * kCoarseRow + s2];
     }
   }
 }

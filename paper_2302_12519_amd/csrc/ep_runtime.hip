@@ -632,15 +632,17 @@ ep_status step_jacobi(ep_grid g, const T* jstim, ep_step_info* acc) {
 
 // Coarse operator of the two-level preconditioner: Kc = P^T K P over the
 // aggregates (K = -(A_i + A_e), with a bath its body operator), from the FP64
-// weights; every entry raised by s/n_agg, s the mean diagonal, so that the
-// constants (K's null space) get eigenvalue s; then its inverse in FP64 and
-// an FP32 copy for the inner solve.
+// weights; every entry raised by s/n_agg with s = trace(K)/n_agg (each
+// aggregate's summed diagonal, always positive, bounds its Kc entry), so the
+// constants, K's null space, get an eigenvalue of K's own scale -- also when
+// one aggregate makes Kc zero up to rounding; then its inverse in FP64 and an
+// FP32 copy for the inner solve.
 ep_status coarse_setup(ep_grid g, Temps& tmp) {
   const int n = g->n_agg;
   const size_t nn = static_cast<size_t>(n) * n;
   double *kb = nullptr, *kc = nullptr, *pinv = nullptr, *rp = nullptr, *cp = nullptr;
   const size_t panel = static_cast<size_t>(kGjPanel) * n * sizeof(double);
-  if (tmp.get(&kb, static_cast<size_t>(g->nb) * kNbr * sizeof(double)) != hipSuccess ||
+  if (tmp.get(&kb, static_cast<size_t>(g->nb) * kCoarseRow * sizeof(double)) != hipSuccess ||
       tmp.get(&kc, nn * sizeof(double)) != hipSuccess ||
       tmp.get(&pinv, static_cast<size_t>(kGjPanel) * kGjPanel * sizeof(double)) != hipSuccess ||
       tmp.get(&rp, panel) != hipSuccess || tmp.get(&cp, panel) != hipSuccess) {
@@ -650,22 +652,22 @@ ep_status coarse_setup(ep_grid g, Temps& tmp) {
   HIPCHK(g, hipMemsetAsync(kc, 0, nn * sizeof(double), g->stream));
   launch_coarse_setup(g->L, g->d_nbr, g->d_ck64, 0.0, -1.0, n, g->d_agg_ptr, g->d_agg_brk,
                       g->d_agg, kb, kc);
-  std::vector<double> dg(n);
-  HIPCHK(g, hipMemcpy2DAsync(dg.data(), sizeof(double), kc, (n + 1) * sizeof(double),
-                             sizeof(double), n, hipMemcpyDeviceToHost, g->stream));
+  std::vector<double> dg(std::max(n, g->nb));
+  HIPCHK(g, hipMemcpy2DAsync(dg.data(), sizeof(double), kb + kNbr, kCoarseRow * sizeof(double),
+                             sizeof(double), g->nb, hipMemcpyDeviceToHost, g->stream));
   HIPCHK(g, hipStreamSynchronize(g->stream));
-  double mean = 0.0;
-  for (double d : dg) mean += d;
-  mean /= n;
-  if (!(mean > 0.0) || !std::isfinite(mean))
-    return fail(g, EP_ERR_ARG, "coarse operator has no positive diagonal");
-  launch_coarse_invert(g->stream, n, g->agg_ld, kc, mean / n, pinv, rp, cp, g->d_kinv);
+  double trace = 0.0;
+  for (int b = 0; b < g->nb; ++b) trace += dg[b];
+  const double s = trace / n;
+  if (!(s > 0.0) || !std::isfinite(s))
+    return fail(g, EP_ERR_ARG, "the elliptic operator has no positive diagonal");
+  launch_coarse_invert(g->stream, n, g->agg_ld, kc, s / n, pinv, rp, cp, g->d_kinv);
   HIPCHK(g, hipGetLastError());
   HIPCHK(g, hipMemcpy2DAsync(dg.data(), sizeof(double), kc, (n + 1) * sizeof(double),
                              sizeof(double), n, hipMemcpyDeviceToHost, g->stream));
   HIPCHK(g, hipStreamSynchronize(g->stream));
-  for (double d : dg)
-    if (!(d > 0.0) || !std::isfinite(d))
+  for (int i = 0; i < n; ++i)
+    if (!(dg[i] > 0.0) || !std::isfinite(dg[i]))
       return fail(g, EP_ERR_HIP, "coarse operator inverse is not positive definite");
   return EP_OK;
 }

@@ -148,3 +148,29 @@ def test_bidomain_bitwise_reproducible(P):
     (v1, p1, i1), (v2, p2, i2) = out
     assert i1 == i2
     assert np.array_equal(v1, v2) and np.array_equal(p1, p2)
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (6, 5, 4), (12, 3, 9)])
+def test_bidomain_small_grids(P, orc, shape):
+    """Bidomain grids of one or a few bricks (a single aggregate makes the
+    coarse operator zero: only the constants, which the sum-zero residuals
+    never excite): 20 FP64 steps against the oracle."""
+    rng = np.random.default_rng(sum(shape))
+    fib = rng.normal(size=shape + (3,))
+    fib /= np.linalg.norm(fib, axis=-1, keepdims=True)
+    k = max(1, shape[0] // 3)
+    st = [E.Stim(lo=(0, 0, 0), hi=(k, shape[1], shape[2]), amp=1.0, t_on=0.0, t_off=1.0)]
+    inst = E.Instance(name="bido_small", n=shape, h=0.25, dt=0.02, steps=0,
+                      mask=np.ones(shape, np.uint8), fibre=fib, scale=None, sigma_l=0.17,
+                      sigma_t=0.019, sigma_el=0.62, sigma_et=0.24, stims=st, model="bido",
+                      prec="f64", ell_rtol=1e-11)
+    say(f"case bidomain small grid {shape}")
+    g = P.Grid.from_instance(inst)
+    o = orc.Oracle(inst)
+    g.step(20)
+    o.run(20)
+    err = rel(g.read("v"), o.field("v"))
+    perr = rel(g.read("phi"), o.field("phi"))
+    g.close()
+    say(f"bidomain small {shape}: v err {err:.2e} phi err {perr:.2e}")
+    assert err <= 1e-9 and perr <= 1e-7
