@@ -43,8 +43,10 @@ def bath_operator(orc, inst, o):
     return (lambda phi: -orc.apply(inst.n, inst.h, dom, Dk, phi)), dom
 
 
-@pytest.mark.parametrize("n", [32, 128])
+@pytest.mark.parametrize("n", [32, 128, 256])
 def test_bath_elliptic_residual_in_fp64(P, orc, n):
+    """256^3 is 32768 bricks: the coarse space takes 2x2x2-brick aggregates
+    (4096 of them) and the aggregate-sum launch."""
     inst = E.bidomain_bath(n, steps=0)
     say(f"case bidomain_bath_{n} elliptic")
     g = P.Grid.from_instance(inst)
