@@ -435,8 +435,8 @@ def bench_adjoint(n, steps=500, K=50):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
-              "(the grid is not sharded across GPUs)", file=sys.stderr)
+        print(f"bench.py: the library runs each grid on one GPU; --gpus {a.gpus} is not "
+              "supported (grids are not sharded across GPUs)", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench needs a GPU"
