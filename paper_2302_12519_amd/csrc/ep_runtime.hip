@@ -86,6 +86,7 @@ struct ep_grid_s {
   int64_t n_body = 0;
   int64_t nvox = 0;            // (nb+1)*512
   LaunchCfg L{};
+  LaunchCfg Le{};              // the elliptic inner solve's kernels (larger persistent grid)
   int grid = 0;
 
   // device
@@ -690,7 +691,7 @@ ep_status cg2_solve(ep_grid g, int maxit, int* chunk_hint, int* iters, bool* fai
   auto iter = [&](int j) {
     CGScalars* cout = cg + ((j + 1) & 1);
     TimerPair* tu = timer_begin(g, KT_UPDATE);
-    launch_cg2_update(g->L, x, r, p, sv, z, w, g->d_rb, j == 0 ? 0 : 1, cg + (j & 1), cout,
+    launch_cg2_update(g->Le, x, r, p, sv, z, w, g->d_rb, j == 0 ? 0 : 1, cg + (j & 1), cout,
                       j == 0 ? g->d_cgp[0] : g->d_cgp[1], g->dmirror, ++g->seq);
     timer_end(g, tu);
     TimerPair* tc = timer_begin(g, KT_COARSE);
@@ -698,7 +699,7 @@ ep_status cg2_solve(ep_grid g, int maxit, int* chunk_hint, int* iters, bool* fai
                         g->d_agg_brk, g->d_rb, g->d_rc, g->d_kinv, g->d_cc, cout);
     timer_end(g, tc);
     TimerPair* ta = timer_begin(g, KT_STENCIL);
-    launch_cg2_apply(g->L, g->d_nbr, c, 0.0f, -1.0f, g->d_dinvk, r, g->d_cc, g->d_agg, z, w,
+    launch_cg2_apply(g->Le, g->d_nbr, c, 0.0f, -1.0f, g->d_dinvk, r, g->d_cc, g->d_agg, z, w,
                      cout, g->d_cgp[1]);
     timer_end(g, ta);
   };
@@ -754,7 +755,7 @@ ep_status elliptic(ep_grid g, const T* vsrc, double rtol, int max_outer, ep_solv
     if (relres <= rtol) { ok = true; break; }
     if (!std::isfinite(relres) || outer >= max_outer) break;
     const double tin = kInnerRtol;
-    launch_inner_init(g->L, g->d_r64, g->d_body, g->d_sums, inv_count, g->d_x32, g->d_r32[0],
+    launch_inner_init(g->Le, g->d_r64, g->d_body, g->d_sums, inv_count, g->d_x32, g->d_r32[0],
                       g->d_cg, g->d_cgp[0], tin * tin, g->ell_inner_maxit);
     int iters = 0;
     bool failed = false;
@@ -1256,6 +1257,10 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   g->L.stream_nt = static_cast<long long>(kBeArrays) * (nb + 1) * kBV *
                        (g->prec == EP_F64 ? 8 : 4) > kLlcBytes;
   g->L.stream = g->stream;
+  // the elliptic inner solve's kernels need at most 74 VGPRs: three
+  // 512-thread blocks fit per CU
+  g->Le = g->L;
+  g->Le.pgrid = std::min(g->grid, 3 * 256);
   if (g->model == EP_BIDO && tissue_components(boxmask, g->n) != 1)
     return fail(g, EP_ERR_ARG, g->bath ? "heart and bath must be one face-connected component"
                                        : "bidomain tissue must be one face-connected component");
@@ -1267,6 +1272,7 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   TRY(dalloc(g, &g->d_nbr, hnbr.size() * sizeof(int)));
   TRY(dalloc(g, &g->d_rowsn, bm.rowsn.size() * sizeof(uint64_t)));
   g->L.rowsn = g->d_rowsn;
+  g->Le.rowsn = g->d_rowsn;
   TRY(dalloc(g, &g->d_mask, static_cast<size_t>(g->nvox)));
   if (g->bath) TRY(dalloc(g, &g->d_body, static_cast<size_t>(g->nvox)));
   else g->d_body = g->d_mask;
@@ -1281,7 +1287,8 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   TRY(dalloc(g, &g->d_partials, static_cast<size_t>(g->grid) * 4 * sizeof(double)));
   TRY(dalloc(g, &g->d_cg, 2 * sizeof(CGScalars)));
   for (int k = 0; k < 2; ++k)
-    TRY(dalloc(g, &g->d_cgp[k], static_cast<size_t>(g->L.pgrid) * kMaxPartials *
+    TRY(dalloc(g, &g->d_cgp[k], static_cast<size_t>(std::max(g->L.pgrid, g->Le.pgrid)) *
+                                   kMaxPartials *
                                    sizeof(double)));
   TRY(dalloc(g, &g->d_flags, 4 * sizeof(int)));
   TRY(dalloc(g, &g->d_sums, 8 * sizeof(double)));
