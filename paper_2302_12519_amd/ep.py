@@ -236,8 +236,12 @@ class Grid:
                 jacobi_sweeps=getattr(inst, "jacobi_sweeps", 10),
                 bath=getattr(inst, "bath", None), sig_bath=getattr(inst, "sigma_bath", 0.0),
                 **kw)
-        g.set_conductivity(inst.fibre, inst.scale, inst.sigma_l, inst.sigma_t,
-                           inst.sigma_el, inst.sigma_et)
+        try:
+            g.set_conductivity(inst.fibre, inst.scale, inst.sigma_l, inst.sigma_t,
+                               inst.sigma_el, inst.sigma_et)
+        except Exception:
+            g.close()
+            raise
         return g
 
     def _check(self, st, what, handle=True):

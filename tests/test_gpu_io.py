@@ -73,3 +73,27 @@ def test_grid_in_caller_arena_matches_own_allocation(P):
     with pytest.raises(P.EPError) as e:
         P.Grid.from_instance(inst, arena=small)
     assert e.value.status == P.ep.EP_ERR_OOM
+
+
+def test_bidomain_bath_grid_in_caller_arena(P):
+    """The bidomain grid with a bath, whose conductivity set-up builds the
+    coarse operator in large temporaries (the FP64 matrix and its panels),
+    runs bitwise the same inside an arena of the reported peak size."""
+    import torch
+    inst = E.bidomain_bath(24, steps=20)
+    say("case arena grid bidomain_bath_24 fp32")
+    ref = P.Grid.from_instance(inst)
+    ref.step(20)
+    v_ref, p_ref = ref.read("v"), ref.read("phi")
+    need = ref.stats()["device_bytes"]
+    ref.close()
+    arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+    g = P.Grid.from_instance(inst, arena=arena)
+    g.step(20)
+    assert np.array_equal(g.read("v"), v_ref) and np.array_equal(g.read("phi"), p_ref)
+    assert g.stats()["device_bytes"] <= need
+    g.close()
+    small = torch.empty(need // 2, dtype=torch.uint8, device="cuda")
+    with pytest.raises(P.EPError) as e:
+        P.Grid.from_instance(inst, arena=small)
+    assert e.value.status == P.ep.EP_ERR_OOM
