@@ -64,6 +64,47 @@ def test_aniso_be_256_one_step_every_voxel(P, orc):
     assert (np.isfinite(Tg) != np.isfinite(To)).sum() <= max(2, new.sum() // 1000)
 
 
+def _one_step_from_gpu_state(P, orc, inst, warm):
+    g = P.Grid.from_instance(inst)
+    g.step(warm)
+    v, w, T = g.read("v"), g.read("w"), g.read("tact")
+    o = orc.Oracle(inst)
+    o.set_state(v=v, w=w, tact=T, step=warm)
+    o.run(1)
+    g.step(1)
+    err = np.abs(g.read("v") - o.field("v")).max() / np.abs(o.field("v")).max()
+    Tg, To = g.read("tact"), o.field("tact")
+    g.close()
+    both = np.isfinite(Tg) & np.isfinite(To)
+    dT = np.abs(Tg[both] - To[both]).max() if both.any() else 0.0
+    return err, dT, (np.isfinite(Tg) != np.isfinite(To)).sum(), int(both.sum())
+
+
+def test_cuboid_dx01_one_step(P, orc):
+    """The benchmark cuboid at its finest width (200 x 70 x 30, dt 0.005 ms)
+    as the bench line runs it: 4000 GPU steps (the front mid-slab), then one
+    step against the oracle's from the same state.  FP32, one step of 19
+    terms: bar 1e-6 of max |v|."""
+    inst = E.cuboid(0.1, 0.005, t_end=20.005)
+    say("case cuboid dx 0.1: 4000 GPU steps, then one oracle step")
+    err, dT, mism, nact = _one_step_from_gpu_state(P, orc, inst, 4000)
+    say(f"cuboid dx 0.1 one step: v err {err:.2e}, dT {dT:.2e}, activated {nact}")
+    assert nact > 1000
+    assert err <= 1e-6 and dT <= inst.dt and mism <= 2
+
+
+def test_jacobi_256_one_step(P, orc):
+    """The fixed-sweep implicit step on the 256^3 shell (10 sweeps), as the
+    Jacobi bench line runs it: 40 GPU steps, then one step against the
+    oracle's.  FP32, 10 sweeps of a 19-term update: bar 1e-5 of max |v|."""
+    inst = E.aniso_be(256, steps=41)
+    inst.diff, inst.jacobi_sweeps = "be_jacobi", 10
+    say("case aniso_256 Jacobi 10 sweeps: 40 GPU steps, then one oracle step")
+    err, dT, mism, nact = _one_step_from_gpu_state(P, orc, inst, 40)
+    say(f"aniso_256 Jacobi one step: v err {err:.2e}, dT {dT:.2e}, activated {nact}")
+    assert err <= 1e-5 and dT <= inst.dt and mism <= 2
+
+
 def test_bidomain_192_elliptic_residual(P, orc):
     """The mixed-precision elliptic solve at 192^3 meets ||b - K phi|| <=
     1e-8 ||b|| measured in FP64 by the oracle's operators, with the gauge
