@@ -72,6 +72,8 @@ def parse():
     ap.add_argument("--serving", type=int, default=64,
                     help="requests of the serving measurement (0 skips it)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-box FP64 line")
+    ap.add_argument("--serving-k", type=int, default=16,
+                    help="steps per captured graph launch of the serving line")
     ap.add_argument("--jacobi", type=int, default=256,
                     help="grid edge of the fixed-sweep Jacobi line (0 = skip)")
     ap.add_argument("--explicit27", type=int, default=256,
@@ -135,7 +137,7 @@ def cpu_baseline(inst, budget_s):
                       f"FP64, CG to 1e-13, {dt:.1f} s wall"}
 
 
-def bench_serving(count):
+def bench_serving(count, K=16):
     """Serving workload: `count` requests (grids 48^3..160^3 shells, sigma x
     U[0.5,1.5], excitability U[0.8,1.2], 200..1000 FP32 explicit steps).  A
     burst run measures capacity; a Poisson stream at 0.9 x capacity gives
@@ -149,7 +151,7 @@ def bench_serving(count):
     reqs = E.serving_stream(count=count, burst=True)
     gen_s = time.perf_counter() - t
     work = sum(r.inst.nt * r.inst.steps for r in reqs)
-    budget, slots, K = 16 << 30, count, 16
+    budget, slots = 16 << 30, count
 
     def run(rs):
         b = Batch(budget, max_slots=slots, steps_per_launch=K)
@@ -445,7 +447,7 @@ def main():
     from paper_2302_12519_amd import Grid
 
     if a.only:
-        side = {"serving": lambda: bench_serving(a.serving or 64),
+        side = {"serving": lambda: bench_serving(a.serving or 64, a.serving_k),
                 "plain": bench_plain_fp64,
                 "bidomain": lambda: bench_bidomain(a.bidomain or 192),
                 "adjoint": lambda: bench_adjoint(a.adjoint or 128),
@@ -542,7 +544,7 @@ def main():
     }
     g.close()
     if a.serving:
-        out["serving"] = bench_serving(a.serving)
+        out["serving"] = bench_serving(a.serving, a.serving_k)
     if not a.no_plain:
         out["plain_box_32_fp64"] = bench_plain_fp64()
     if a.bidomain:
