@@ -146,3 +146,38 @@ def test_run_step_is_ionic_plus_explicit27(orc):
     o.run(1)
     want = vs + inst.dt * orc.apply27(shape, inst.h, mask, o.Di, vs)
     assert np.abs(o.field("v") - np.where(mask > 0, want, 0.0)).max() <= 1e-15
+
+
+@pytest.mark.parametrize("diff", ["explicit", "explicit27"])
+def test_second_moment_tensor_grows_by_2D(orc, diff):
+    """Ionic currents off, a blob far from the walls, uniform anisotropic D:
+    one explicit step changes sum v x_i x_j h^3 by exactly 2 D_ij dt mass,
+    off-diagonal moments included (both operators are symmetric and exact on
+    quadratics)."""
+    import math
+    shape, h, dt, sl, st = (24, 26, 22), 0.25, 0.01, 0.2, 0.05
+    f = np.array([1.0, 2.0, 2.0]) / 3.0
+    fib = np.broadcast_to(f, shape + (3,)).copy()
+    ionic = dict(E.MS_DEFAULT, exc=0.0, tau_out=math.inf)
+    inst = E.Instance(name="mom", n=shape, h=h, dt=dt, steps=0, mask=np.ones(shape, np.uint8),
+                      fibre=fib, scale=None, sigma_l=sl, sigma_t=st, stims=[], diff=diff,
+                      prec="f64", ionic=ionic)
+    X = np.stack(np.meshgrid(*[h * (np.arange(k) + 0.5) for k in shape], indexing="ij"), -1)
+    c = np.array([k * h / 2 for k in shape]) + np.array([0.1, -0.2, 0.15])
+    r2 = ((X - c) ** 2).sum(-1)
+    v0 = np.exp(-r2 / (2 * 0.3 ** 2))   # the walls at > 8.7 sigma
+    o = orc.Oracle(inst)
+    o.set_state(v=v0, w=np.ones(shape))
+    o.run(1)
+    v1 = o.field("v")
+
+    Y = X - c        # about the blob centre (the first moment does not move)
+
+    def moments(v):
+        return np.einsum("xyz,xyzi,xyzj->ij", v, Y, Y) * h**3, v.sum() * h**3
+
+    M0, m0 = moments(v0)
+    M1, m1 = moments(v1)
+    D = st * np.eye(3) + (sl - st) * np.outer(f, f)
+    assert abs(m1 - m0) <= 1e-13 * m0
+    assert np.abs((M1 - M0) - 2 * D * dt * m0).max() <= 1e-9 * np.abs(2 * D * dt * m0).max()
