@@ -1,0 +1,70 @@
+"""Host logic of bench.py that runs without a GPU: the refusal of several
+GPUs and the rule that a committed HBM-traffic counter summary is used only
+for the kernel and the kernel source it was taken on."""
+import hashlib
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+@pytest.mark.parametrize("n", [2, 8])
+def test_several_gpus_refused_with_message(n):
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", str(n)],
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr and f"--gpus {n}" in p.stderr
+    assert p.stdout == ""
+
+
+def _source_sha():
+    src = os.path.join(ROOT, "paper_2302_12519_amd", "csrc", "ep_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def _summary(tmp_path, sha, kernel="k_be_init<float>", traffic="557791271"):
+    p = tmp_path / "traffic.txt"
+    p.write_text("command: (not run)\n"
+                 f"kernel: {kernel}\n"
+                 f"traffic_bytes_per_launch: {traffic}\n"
+                 f"kernel_source_sha: {sha}\n")
+    return str(p)
+
+
+def test_traffic_used_for_matching_kernel_and_source(tmp_path):
+    assert bench.read_traffic(_summary(tmp_path, _source_sha()),
+                              "k_be_init<float>") == 557791271.0
+
+
+def test_traffic_dropped_for_other_source(tmp_path):
+    other = "0" * 16 if _source_sha() != "0" * 16 else "1" * 16
+    assert bench.read_traffic(_summary(tmp_path, other), "k_be_init<float>") is None
+
+
+def test_traffic_dropped_for_other_kernel(tmp_path):
+    assert bench.read_traffic(_summary(tmp_path, _source_sha(), kernel="k_pcg_step<float>"),
+                              "k_be_init<float>") is None
+
+
+def test_traffic_absent_or_malformed(tmp_path):
+    assert bench.read_traffic(str(tmp_path / "missing.txt"), "k_be_init<float>") is None
+    assert bench.read_traffic(_summary(tmp_path, _source_sha(), traffic="n/a"),
+                              "k_be_init<float>") is None
+
+
+def test_committed_summary_names_its_kernel_and_source():
+    path = os.path.join(ROOT, "profiles", "traffic_k_be_init_aniso_be_256.txt")
+    keys = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            keys[k.strip()] = v.strip()
+    assert keys["kernel"] == "k_be_init<float>"
+    assert len(keys["kernel_source_sha"]) == 16
+    assert float(keys["traffic_bytes_per_launch"]) > 0
