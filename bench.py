@@ -130,7 +130,7 @@ def cpu_baseline(inst, budget_s):
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = oracle.threads()
     return {"value": inst.nt * steps / dt, "unit": "voxel-steps/s", "cores": cores,
             "kind": "oracle",
             "sample": f"first {steps} step(s) of the same {inst.n[0]}^3 workload from rest, "

@@ -67,7 +67,13 @@ def lib():
         _lib.orc_run.restype = C.c_int
         _lib.orc_solve_elliptic.restype = C.c_int
         _lib.orc_adjoint.restype = C.c_int
+        _lib.orc_threads.restype = C.c_int
     return _lib
+
+
+def threads() -> int:
+    """Threads the oracle's OpenMP loops run with."""
+    return int(lib().orc_threads())
 
 
 def _p(a):

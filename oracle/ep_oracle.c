@@ -51,6 +51,7 @@
  * Tensor storage: D[c*N + p], c = 0..5 for xx, yy, zz, xy, xz, yz.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -838,3 +839,7 @@ int orc_adjoint(const orc_problem* P, const double* D0, const double* v0,
   free(av); free(aw); free(nu); free(gs);
   return 0;
 }
+
+/* Number of threads the oracle's OpenMP loops run with (the CPU baseline
+ * reports it as the cores it used). */
+int orc_threads(void) { return omp_get_max_threads(); }

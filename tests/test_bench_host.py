@@ -68,3 +68,12 @@ def test_committed_summary_names_its_kernel_and_source():
     assert keys["kernel"] == "k_be_init<float>"
     assert len(keys["kernel_source_sha"]) == 16
     assert float(keys["traffic_bytes_per_launch"]) > 0
+
+
+def test_cpu_baseline_reports_the_oracle_threads():
+    import ep_inputs as E
+    import oracle
+    out = bench.cpu_baseline(E.aniso_be(16, steps=2), 0.0)
+    assert out["kind"] == "oracle" and out["unit"] == "voxel-steps/s"
+    assert out["cores"] == oracle.threads() >= 1
+    assert out["value"] > 0 and "first 1 step(s)" in out["sample"]
