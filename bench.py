@@ -41,8 +41,8 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 #             x, r (16 B)                                               -> 40 B
 #     apply (k_cg2_apply): reads r, D^-1 (8 B) and the weights (24 B),
 #             writes z, w (8 B)                                         -> 40 B
-#     coarse correction: the FP32 coarse inverse, 4 B per entry (not per
-#             voxel)
+#     coarse correction: the scaled FP16 coarse inverse, 2 B per entry (not
+#             per voxel)
 #   explicit fused step: reads v, w (8 B) + 24 B weights, writes v, w   -> 40 B
 #   adjoint step: reads lambda_v, lambda_w, v, w, v_next, crossing step (24 B),
 #             weights and unscaled tensors (48 B), mask (1 B), gradient (8 B,

@@ -112,19 +112,23 @@ void launch_coarse_setup(const LaunchCfg& L, const int* nbr, double* const ck64[
                          double c1, int n, const int* agg_ptr, const int* agg_brk, const int* agg,
                          double* kb, double* kc);
 // kc += shift (every entry), then kc^-1 in place (blocked Gauss-Jordan,
-// FP64, 32 columns per step) and its FP32 copy in kinv, rows padded to ld;
-// scratch: pinv 32 x 32, rp 32 x n, cp n x 32 doubles
+// FP64, 32 columns per step); scratch: pinv 32 x 32, rp 32 x n, cp n x 32
+// doubles
 constexpr int kGjPanel = 32;
 void launch_coarse_invert(hipStream_t st, int n, int ld, double* kc, double shift, double* pinv,
-                          double* rp, double* cp, float* kinv);
+                          double* rp, double* cp);
+// FP16 copy of kc * scale into kinv (n rows of ld entries, zero beyond n)
+void launch_coarse_pack(hipStream_t st, int n, int ld, const double* kc, double scale,
+                        void* kinv);
 void launch_cg2_update(const LaunchCfg& L, float* x, float* r, float* p, float* s, const float* z,
                        const float* w, float* rb, int kind, const CGScalars* cin, CGScalars* cout,
                        const double* prev, unsigned long long* mirror, unsigned seq);
-// cc = kinv (aggregate sums of rb); with single-brick aggregates rb holds
-// them already (rb and rc hold ld entries, zero beyond n)
+// cc = unscale * kinv (aggregate sums of rb), kinv the FP16 copy of
+// launch_coarse_pack; with single-brick aggregates rb holds the sums already
+// (rb and rc hold ld entries, zero beyond n)
 void launch_coarse_apply(hipStream_t st, int n, int ld, bool brick_aggs, const int* agg_ptr,
-                         const int* agg_brk, const float* rb, float* rc, const float* kinv,
-                         float* cc, const CGScalars* sc);
+                         const int* agg_brk, const float* rb, float* rc, const void* kinv,
+                         float unscale, float* cc, const CGScalars* sc);
 void launch_cg2_apply(const LaunchCfg& L, const int* nbr, CoefSet<float> c, float c0, float c1,
                       const float* dinv, const float* r, const float* cc, const int* agg, float* z,
                       float* w, const CGScalars* cin, double* parts);

@@ -797,11 +797,17 @@ __global__ __launch_bounds__(256) void k_gj_update(int n, double* __restrict__ a
 }
 
 // FP32 copy of the n x n inverse with rows padded to ld (a multiple of 4)
-__global__ void k_to_f32(int n, int ld, const double* __restrict__ a, float* __restrict__ o) {
+// FP16 copy of the coarse inverse for the GEMV, scaled by `scale` (chosen so
+// that the largest entry, on the diagonal of this SPD matrix, maps to 2^14),
+// rows padded to ld with zeros
+__global__ void k_to_f16(int n, int ld, const double* __restrict__ a, double scale,
+                         _Float16* __restrict__ o) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (idx >= static_cast<int64_t>(n) * ld) return;
   const int i = static_cast<int>(idx / ld), j = static_cast<int>(idx % ld);
-  o[idx] = j < n ? static_cast<float>(a[static_cast<int64_t>(i) * n + j]) : 0.0f;
+  o[idx] = j < n ? static_cast<_Float16>(static_cast<float>(a[static_cast<int64_t>(i) * n + j] *
+                                                            scale))
+                 : static_cast<_Float16>(0.0f);
 }
 
 // Update launch of the two-level inner PCG.  kind 0 (first): the scalars
@@ -904,28 +910,35 @@ __global__ void k_agg_sum(int n, const int* __restrict__ agg_ptr, const int* __r
   rc[I] = a;
 }
 
-// cc[I] = sum_J kinv[I][J] rc[J]: one block per row, rows padded to ld
-// (rc zero beyond n), 16-byte loads, FP64 accumulation
-__global__ __launch_bounds__(256) void k_coarse_gemv(int ld, const float* __restrict__ kinv,
+// cc[I] = unscale * sum_J kinv[I][J] rc[J] from the scaled FP16 inverse:
+// one block per row, rows padded to ld (rc zero beyond n), 8-byte loads of
+// four entries, FP64 accumulation
+__global__ __launch_bounds__(256) void k_coarse_gemv(int ld, const _Float16* __restrict__ kinv,
+                                                     float unscale,
                                                      const float* __restrict__ rc,
                                                      float* __restrict__ cc,
                                                      const CGScalars* __restrict__ st) {
   if (st->done) return;
   __shared__ double red[4];
   typedef float F4 __attribute__((ext_vector_type(4)));
+  typedef _Float16 H4 __attribute__((ext_vector_type(4)));
   const int I = blockIdx.x;
-  const F4* row = reinterpret_cast<const F4*>(kinv + static_cast<int64_t>(I) * ld);
+  const H4* row = reinterpret_cast<const H4*>(kinv + static_cast<int64_t>(I) * ld);
   const F4* v = reinterpret_cast<const F4*>(rc);
   double a = 0.0;
   for (int j = threadIdx.x; j < ld / 4; j += 256) {
-    const F4 m = row[j], x = v[j];
-    a += static_cast<double>(m.x * x.x + m.y * x.y) + static_cast<double>(m.z * x.z + m.w * x.w);
+    const H4 h = row[j];
+    const F4 x = v[j];
+    const float m0 = static_cast<float>(h.x), m1 = static_cast<float>(h.y);
+    const float m2 = static_cast<float>(h.z), m3 = static_cast<float>(h.w);
+    a += static_cast<double>(m0 * x.x + m1 * x.y) + static_cast<double>(m2 * x.z + m3 * x.w);
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
   __syncthreads();
-  if (threadIdx.x == 0) cc[I] = static_cast<float>(red[0] + red[1] + red[2] + red[3]);
+  if (threadIdx.x == 0)
+    cc[I] = static_cast<float>((red[0] + red[1] + red[2] + red[3]) * static_cast<double>(unscale));
 }
 
 // Apply launch: z = D^-1 r + P cc on the elliptic domain (where D^-1 > 0),
@@ -1713,7 +1726,7 @@ void launch_coarse_setup(const LaunchCfg& L, const int* nbr, double* const ck64[
 }
 
 void launch_coarse_invert(hipStream_t st, int n, int ld, double* kc, double shift, double* pinv,
-                          double* rp, double* cp, float* kinv) {
+                          double* rp, double* cp) {
   const int64_t nn = static_cast<int64_t>(n) * n;
   const int64_t blocks = (nn + 255) / 256;
   k_add_const<<<blocks, 256, 0, st>>>(nn, kc, shift);
@@ -1725,7 +1738,12 @@ void launch_coarse_invert(hipStream_t st, int n, int ld, double* kc, double shif
                                                                           rp, cp);
     k_gj_update<<<tiles, 256, 0, st>>>(n, kc, k0, bs, rp, cp);
   }
-  k_to_f32<<<(static_cast<int64_t>(n) * ld + 255) / 256, 256, 0, st>>>(n, ld, kc, kinv);
+}
+
+void launch_coarse_pack(hipStream_t st, int n, int ld, const double* kc, double scale,
+                        void* kinv) {
+  k_to_f16<<<(static_cast<int64_t>(n) * ld + 255) / 256, 256, 0, st>>>(
+      n, ld, kc, scale, static_cast<_Float16*>(kinv));
 }
 
 void launch_cg2_update(const LaunchCfg& L, float* x, float* r, float* p, float* s, const float* z,
@@ -1736,11 +1754,12 @@ void launch_cg2_update(const LaunchCfg& L, float* x, float* r, float* p, float* 
 }
 
 void launch_coarse_apply(hipStream_t st, int n, int ld, bool brick_aggs, const int* agg_ptr,
-                         const int* agg_brk, const float* rb, float* rc, const float* kinv,
-                         float* cc, const CGScalars* sc) {
+                         const int* agg_brk, const float* rb, float* rc, const void* kinv,
+                         float unscale, float* cc, const CGScalars* sc) {
   // single-brick aggregates: the brick sums are the aggregate sums
   if (!brick_aggs) k_agg_sum<<<(n + 127) / 128, 128, 0, st>>>(n, agg_ptr, agg_brk, rb, rc, sc);
-  k_coarse_gemv<<<n, 256, 0, st>>>(ld, kinv, brick_aggs ? rb : rc, cc, sc);
+  k_coarse_gemv<<<n, 256, 0, st>>>(ld, static_cast<const _Float16*>(kinv), unscale,
+                                   brick_aggs ? rb : rc, cc, sc);
 }
 
 void launch_cg2_apply(const LaunchCfg& L, const int* nbr, CoefSet<float> c, float c0, float c1,

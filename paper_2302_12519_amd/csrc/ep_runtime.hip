@@ -136,7 +136,8 @@ struct ep_grid_s {
   float* d_rb = nullptr;         // max(nb, agg_ld): brick sums of r (zero beyond nb)
   float* d_rc = nullptr;         // agg_ld: aggregate sums of r (zero beyond n_agg)
   float* d_cc = nullptr;         // n_agg + 1: coarse correction (last: 0, the ghost's)
-  float* d_kinv = nullptr;       // n_agg x agg_ld: (Kc + s/n_agg)^-1, FP32
+  void* d_kinv = nullptr;        // n_agg x agg_ld: (Kc + s/n_agg)^-1 in FP16,
+  float kinv_unscale = 1.0f;     //   scaled; times kinv_unscale gives the inverse
   float* d_dinvk = nullptr;
   void* d_d0[6] = {};         // explicit monodomain: unscaled voxel tensors (adjoint)
   void* d_adj = nullptr;      // adjoint work block (cached, grown on demand)
@@ -662,14 +663,24 @@ ep_status coarse_setup(ep_grid g, Temps& tmp) {
   const double s = trace / n;
   if (!(s > 0.0) || !std::isfinite(s))
     return fail(g, EP_ERR_ARG, "the elliptic operator has no positive diagonal");
-  launch_coarse_invert(g->stream, n, g->agg_ld, kc, s / n, pinv, rp, cp, g->d_kinv);
+  launch_coarse_invert(g->stream, n, g->agg_ld, kc, s / n, pinv, rp, cp);
   HIPCHK(g, hipGetLastError());
   HIPCHK(g, hipMemcpy2DAsync(dg.data(), sizeof(double), kc, (n + 1) * sizeof(double),
                              sizeof(double), n, hipMemcpyDeviceToHost, g->stream));
   HIPCHK(g, hipStreamSynchronize(g->stream));
-  for (int i = 0; i < n; ++i)
+  double dmax = 0.0;
+  for (int i = 0; i < n; ++i) {
     if (!(dg[i] > 0.0) || !std::isfinite(dg[i]))
       return fail(g, EP_ERR_HIP, "coarse operator inverse is not positive definite");
+    dmax = std::max(dmax, dg[i]);
+  }
+  // an SPD matrix's largest entry lies on its diagonal: scale it to 2^14,
+  // well inside FP16's range
+  const double scale = 16384.0 / dmax;
+  launch_coarse_pack(g->stream, n, g->agg_ld, kc, scale, g->d_kinv);
+  HIPCHK(g, hipGetLastError());
+  HIPCHK(g, hipStreamSynchronize(g->stream));
+  g->kinv_unscale = static_cast<float>(dmax / 16384.0);
   return EP_OK;
 }
 
@@ -696,7 +707,8 @@ ep_status cg2_solve(ep_grid g, int maxit, int* chunk_hint, int* iters, bool* fai
     timer_end(g, tu);
     TimerPair* tc = timer_begin(g, KT_COARSE);
     launch_coarse_apply(g->stream, g->n_agg, g->agg_ld, g->agg_edge == 1, g->d_agg_ptr,
-                        g->d_agg_brk, g->d_rb, g->d_rc, g->d_kinv, g->d_cc, cout);
+                        g->d_agg_brk, g->d_rb, g->d_rc, g->d_kinv, g->kinv_unscale, g->d_cc,
+                        cout);
     timer_end(g, tc);
     TimerPair* ta = timer_begin(g, KT_STENCIL);
     launch_cg2_apply(g->Le, g->d_nbr, c, 0.0f, -1.0f, g->d_dinvk, r, g->d_cc, g->d_agg, z, w,
@@ -1368,7 +1380,9 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
     TRY(dalloc(g, &g->d_rb, nrb * sizeof(float)));
     TRY(dalloc(g, &g->d_rc, static_cast<size_t>(g->agg_ld) * sizeof(float)));
     TRY(dalloc(g, &g->d_cc, static_cast<size_t>(g->n_agg + 1) * sizeof(float)));
-    TRY(dalloc(g, &g->d_kinv, static_cast<size_t>(g->n_agg) * g->agg_ld * sizeof(float)));
+    _Float16* kinv16 = nullptr;
+    TRY(dalloc(g, &kinv16, static_cast<size_t>(g->n_agg) * g->agg_ld * sizeof(_Float16)));
+    g->d_kinv = kinv16;
     HIPCHK(g, hipMemsetAsync(g->d_rb, 0, nrb * sizeof(float), g->stream));
     HIPCHK(g, hipMemsetAsync(g->d_rc, 0, static_cast<size_t>(g->agg_ld) * sizeof(float),
                              g->stream));
