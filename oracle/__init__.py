@@ -207,7 +207,8 @@ class Oracle:
         if w is not None:
             self.w = np.where(m, _f64(w).ravel(), 0.0)
         if phi is not None:
-            self.phi = np.where(m, _f64(phi).ravel(), 0.0)
+            dom = m if self.bath is None else (m | (self.bath > 0))
+            self.phi = np.where(dom, _f64(phi).ravel(), 0.0)
         if tact is not None:
             self.tact = _f64(tact).ravel().copy()
         if step is not None:

@@ -422,11 +422,12 @@ static double dot(const int32_t n[3], const double* a, const double* b) {
 
 typedef struct {
   const orc_problem* P;
-  const uint8_t* mask;  /* the operator's domain */
+  const uint8_t* mask;  /* domain of the D1 operator */
   const double* D1;
-  const double* D2;   /* second tensor set (bidomain) or NULL */
-  double alpha;       /* operator is  I - alpha A  (alpha != 0)  or  -(A1 + A2) */
-  int kind;           /* 0: I - alpha A(D1);  1: -(A(D1) + A(D2));  2: -A(D1) */
+  const uint8_t* mask2; /* domain of the D2 operator (kind 1) */
+  const double* D2;     /* second tensor field (kind 1) */
+  double alpha;         /* kind 0: the operator is I - alpha A(D1) */
+  int kind;             /* 0: I - alpha A(D1);  1: -(A(D1) + A(D2)), each over its own domain */
   double* tmp;
 } orc_op;
 
@@ -436,13 +437,10 @@ static void op_apply(const orc_op* o, const double* x, double* y) {
   if (o->kind == 0) {
     orc_apply(P->n, P->h, o->mask, o->D1, x, y);
     for (int64_t p = 0; p < N; ++p) y[p] = x[p] - o->alpha * y[p];
-  } else if (o->kind == 1) {
-    orc_apply(P->n, P->h, o->mask, o->D1, x, y);
-    orc_apply(P->n, P->h, o->mask, o->D2, x, o->tmp);
-    for (int64_t p = 0; p < N; ++p) y[p] = -(y[p] + o->tmp[p]);
   } else {
     orc_apply(P->n, P->h, o->mask, o->D1, x, y);
-    for (int64_t p = 0; p < N; ++p) y[p] = -y[p];
+    orc_apply(P->n, P->h, o->mask2, o->D2, x, o->tmp);
+    for (int64_t p = 0; p < N; ++p) y[p] = -(y[p] + o->tmp[p]);
   }
 }
 
@@ -496,16 +494,21 @@ static void project_mean_zero(const int32_t n[3], const uint8_t* m, double* x) {
 }
 
 /* The elliptic part of eqn:bidomain1, pure Neumann, with sum phi = 0 over its
- * domain:
- *  - heart only:  -(A_i + A_e) phi = b on the heart;
- *  - with a bath (Bidomain Model subsection, Boundary Conditions: the body
- *    tissue conducts with Sigma_o = sig_bath I, phi is continuous and the
- *    normal current is continuous across the heart's boundary, no current
- *    leaves the body, the intracellular current stays in the heart):
- *    -A_K phi = b on heart + bath, where A_K is the operator of the voxel
- *    tensor D_i + D_e on the heart and sig_bath I on the bath.  Faces and
- *    blocks that straddle the two take the mean of the voxel tensors, as
- *    everywhere else.  b = A_i v* vanishes off the heart.
+ * domain.  phi is the extracellular potential on the heart and, with a bath,
+ * the body-tissue potential v_o on the bath (continuous across the heart's
+ * boundary).  The equation is the sum of the intracellular and extracellular
+ * current balances, so its operator is the sum of two operators, each on
+ * its own domain:
+ *  - A_i: the intracellular tensor on the heart only.  Faces and blocks
+ *    that touch a non-heart voxel are dropped, so no intracellular current
+ *    crosses the heart's boundary (last line of eqn:bidomain1);
+ *  - A_e: over heart + bath, the extracellular tensor D_e on heart voxels
+ *    and sig_bath I on bath voxels (Boundary Conditions: the body tissue
+ *    conducts with Sigma_o, the normal extracellular current equals the
+ *    body current on the heart's boundary, and none leaves the body).  A
+ *    face or block that straddles the two takes the mean of its voxel
+ *    tensors, like every other face.  Without a bath it is D_e on the heart.
+ * The system is -(A_i + A_e) phi = b with b = A_i v* (zero off the heart).
  * phi holds the warm start on entry.  Returns iterations (-1: maxit). */
 int orc_solve_elliptic(const orc_problem* P, const double* b_in, double* phi,
                        double rtol, int maxit) {
@@ -515,39 +518,34 @@ int orc_solve_elliptic(const orc_problem* P, const double* b_in, double* phi,
   double* de = (double*)malloc((size_t)N * sizeof(double));
   double* tmp = (double*)malloc((size_t)N * sizeof(double));
   uint8_t* dom = (uint8_t*)malloc((size_t)N);
-  double* Dk = NULL;
+  double* Deo = NULL;   /* extracellular + bath tensor field */
   for (int64_t p = 0; p < N; ++p) dom[p] = P->mask[p] || (P->bath && P->bath[p]);
   if (P->bath) {
-    Dk = (double*)calloc((size_t)6 * (size_t)N, sizeof(double));
+    Deo = (double*)calloc((size_t)6 * (size_t)N, sizeof(double));
     for (int64_t p = 0; p < N; ++p) {
       if (P->mask[p]) {
-        for (int c = 0; c < 6; ++c) Dk[c * N + p] = P->Di[c * N + p] + P->De[c * N + p];
+        for (int c = 0; c < 6; ++c) Deo[c * N + p] = P->De[c * N + p];
       } else if (P->bath[p]) {
-        Dk[ORC_XX * N + p] = P->sig_bath;
-        Dk[ORC_YY * N + p] = P->sig_bath;
-        Dk[ORC_ZZ * N + p] = P->sig_bath;
+        Deo[ORC_XX * N + p] = P->sig_bath;
+        Deo[ORC_YY * N + p] = P->sig_bath;
+        Deo[ORC_ZZ * N + p] = P->sig_bath;
       }
     }
   }
+  const double* De = Deo ? Deo : P->De;
   memcpy(b, b_in, (size_t)N * sizeof(double));
   project_mean_zero(P->n, dom, b);
-  if (Dk) {
-    orc_diag(P->n, P->h, dom, Dk, di);
-    memset(de, 0, (size_t)N * sizeof(double));
-  } else {
-    orc_diag(P->n, P->h, dom, P->Di, di);
-    orc_diag(P->n, P->h, dom, P->De, de);
-  }
+  orc_diag(P->n, P->h, P->mask, P->Di, di);
+  orc_diag(P->n, P->h, dom, De, de);
   for (int64_t p = 0; p < N; ++p) {
     const double k = -(di[p] + de[p]);
     di[p] = (dom[p] && k > 0.0) ? 1.0 / k : 0.0;
   }
   project_mean_zero(P->n, dom, phi);
-  orc_op o = Dk ? (orc_op){P, dom, Dk, NULL, 0.0, 2, tmp}
-                : (orc_op){P, dom, P->Di, P->De, 0.0, 1, tmp};
+  const orc_op o = {P, P->mask, P->Di, dom, De, 0.0, 1, tmp};
   const int it = pcg(&o, di, b, phi, rtol, maxit);
   project_mean_zero(P->n, dom, phi);
-  free(b); free(di); free(de); free(tmp); free(dom); free(Dk);
+  free(b); free(di); free(de); free(tmp); free(dom); free(Deo);
   return it;
 }
 
@@ -638,7 +636,7 @@ int orc_run(const orc_problem* P, orc_state* S, int32_t nsteps, orc_info* info) 
       if (P->jacobi_sweeps > inf.cg_max) inf.cg_max = P->jacobi_sweeps;
     } else if (P->model == 0) {
       memcpy(vn, vs, (size_t)N * sizeof(double));
-      orc_op o = {P, P->mask, P->Di, NULL, P->dt, 0, tmp};
+      const orc_op o = {P, P->mask, P->Di, NULL, NULL, P->dt, 0, tmp};
       const int it = pcg(&o, dinv, vs, vn, P->cg_rtol, P->cg_maxit);
       if (it < 0) { rc = 1; inf.cg_fail++; inf.cg_iters += P->cg_maxit; }
       else { inf.cg_iters += it; if (it > inf.cg_max) inf.cg_max = it; }

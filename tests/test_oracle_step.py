@@ -193,6 +193,28 @@ def test_activation_mirror_symmetry_and_planar_speed(orc):
     assert 0.2 < cv.mean() < 0.6
 
 
+@pytest.mark.parametrize("dt", [0.03, 0.01, 0.007, 0.05])
+@pytest.mark.parametrize("diff", ["explicit", "be_pcg"])
+def test_activation_time_closed_form(orc, dt, diff):
+    """One tissue voxel, ionic currents off, a constant stimulus amp: then
+    v_n = n dt amp and the potential reaches theta at exactly t = theta/amp,
+    whatever dt.  The interpolated crossing time must give that to rounding;
+    basing the interpolation on t_{n+1} instead of t_n, or interpolating
+    from the wrong end, would be off by up to one dt."""
+    amp, theta = 0.7, 0.5
+    st = [E.Stim(lo=(0, 0, 0), hi=(1, 1, 1), amp=amp, t_on=0.0, t_off=1e9)]
+    inst = box((1, 1, 1), dt=dt, stims=st, diff=diff, ionic=NO_IONIC)
+    inst.theta = theta
+    o = orc.Oracle(inst)
+    nsteps = int(math.ceil(theta / amp / dt)) + 3
+    rc, _ = o.run(nsteps)
+    assert rc == 0
+    T = float(o.tact[0])
+    assert abs(T - theta / amp) <= 1e-12, (T, theta / amp)
+    # the potential itself is the running sum n dt amp
+    assert abs(o.v[0] - nsteps * dt * amp) <= 1e-12
+
+
 def test_adjoint_matches_central_differences(orc):
     """Gradient of sum (T - T*)^2 with respect to the per-voxel conductivity
     scale, against central differences in FP64 along smooth directions."""
