@@ -140,14 +140,17 @@ typedef struct {
                                 Boundary Conditions of eqn:bidomain1).  It
                                 must not overlap mask (EP_ERR_ARG).  The
                                 extracellular potential is then solved on
-                                heart + bath: the voxel tensor D_i + D_e on
-                                the heart, sig_bath I on the bath, faces that
+                                heart + bath with the operator
+                                -(A_i + A_e): A_i the intracellular operator
+                                on the heart only (no intracellular current
+                                crosses the heart's boundary), A_e over heart
+                                + bath with D_e on heart voxels and
+                                sig_bath I on bath voxels, faces that
                                 straddle the two taking the mean of their
-                                tensors; phi and the normal current are
-                                continuous across the heart's boundary, no
-                                current leaves heart + bath, and the
-                                intracellular current stays in the heart
-                                (v, w and T_act live on the heart only).
+                                tensors (phi and the extracellular normal
+                                current are continuous across the heart's
+                                boundary; no current leaves heart + bath).
+                                v, w and T_act live on the heart only.
                                 Heart + bath must be one face-connected
                                 component; the gauge is sum phi = 0 over it */
   double sig_bath;           /* bath conductivity (mm^2/ms), > 0 with a bath */
@@ -205,10 +208,14 @@ EP_API ep_status ep_set_conductivity_fibres(ep_grid g, const double* fibre,
 EP_API ep_status ep_step(ep_grid g, int32_t nsteps, ep_step_info* info);
 
 /* Solve the bidomain elliptic equation -(A_i + A_e) phi = A_i v for the
- * current v (second line of eqn:bidomain1, heart only, no-flux, gauge
- * sum_tissue phi = 0): FP32 Jacobi-PCG inner solves inside FP64 iterative
- * refinement until ||b - K phi|| <= rel_tol ||b|| (FP64), warm-started from
- * the stored phi.  EP_BIDO grids only (EP_ERR_UNSUPPORTED otherwise). */
+ * current v (second line of eqn:bidomain1, no-flux on the domain's
+ * boundary): on the heart, gauge sum_tissue phi = 0; with a bath, on heart
+ * + bath as described at ep_grid_desc.bath, gauge sum phi = 0 over both.
+ * FP32 PCG inner solves (Jacobi plus an aggregate coarse correction) inside
+ * FP64 iterative refinement until ||b - K phi|| <= rel_tol ||b|| (FP64),
+ * warm-started from the stored phi.  EP_BIDO grids only
+ * (EP_ERR_UNSUPPORTED otherwise); EP_ERR_NOCONV when max_outer refinement
+ * iterations do not reach rel_tol (phi holds the last iterate). */
 EP_API ep_status ep_solve_elliptic(ep_grid g, double rel_tol, int32_t max_outer,
                                    ep_solve_info* info);
 

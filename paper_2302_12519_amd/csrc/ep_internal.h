@@ -96,6 +96,10 @@ void launch_tensor_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask
                          double h, double* tens /*6 arrays, scratch*/, double* c64[6],
                          float* c32[6], const uint8_t* body = nullptr, double sig_body = 0.0);
 
+// acc += add over every active brick, and out32 = (float) acc
+void launch_coef_add(const LaunchCfg& L, double* const acc[6], double* const add[6],
+                     float* const out32[6]);
+
 // corner tensors of the corner-gradient operator A27 (one corner per voxel,
 // the six entries in the slots CX..CYZ read as xx, yy, zz, xy, xz, yz)
 void launch_corner_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask,

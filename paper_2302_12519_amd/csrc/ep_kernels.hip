@@ -156,7 +156,8 @@ __global__ __launch_bounds__(256) void k_box_gather(int n0, int n1, int n2, int 
 // ---------------------------------------------------------------------------
 // Voxel tensors s (sT I + (sL - sT) f f^T) on the tissue (eqn:sigma1).  With
 // body (the elliptic domain with a bath), voxels of the body outside the
-// tissue get the isotropic bath tensor sig_body I.
+// tissue get the isotropic bath tensor sig_body I: the extracellular / bath
+// tensor field of the elliptic operator's second part.
 __global__ __launch_bounds__(kBV) void k_tensor(int nb, const uint8_t* __restrict__ mask,
                                                 const double* __restrict__ fib,
                                                 const double* __restrict__ scale, double sig_l,
@@ -240,6 +241,24 @@ __global__ __launch_bounds__(kBV) void k_coefs(int nb, const int* __restrict__ n
   for (int k = 0; k < 6; ++k) {
     if (out64.c[k]) out64.c[k][g] = c[k];
     if (out32.c[k]) out32.c[k][g] = static_cast<float>(c[k]);
+  }
+}
+
+// acc += add, weight by weight, with an FP32 copy of the sum.  The bidomain
+// elliptic operator is the sum of the intracellular operator on the heart
+// and the extracellular (and bath) operator over the elliptic domain, each
+// assembled over its own domain (eqn:bidomain1 with its boundary
+// conditions).
+__global__ __launch_bounds__(kBV) void k_coef_add(int nb, CoefOut<double> acc,
+                                                  CoefSet<double> add, CoefOut<float> out32) {
+  const int brick = block_brick();
+  if (brick >= nb) return;
+  const int g = brick * kBV + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double s = acc.c[k][g] + add.c[k][g];
+    acc.c[k][g] = s;
+    out32.c[k][g] = static_cast<float>(s);
   }
 }
 
@@ -1672,6 +1691,19 @@ void launch_tensor_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask
   }
   k_coefs<<<L.grid, kBV, 0, L.stream>>>(L.nb, nbr, body ? body : mask, tens, stride,
                                         1.0 / (h * h), o64, o32);
+}
+
+void launch_coef_add(const LaunchCfg& L, double* const acc[6], double* const add[6],
+                     float* const out32[6]) {
+  CoefOut<double> a;
+  CoefSet<double> b;
+  CoefOut<float> o;
+  for (int k = 0; k < 6; ++k) {
+    a.c[k] = acc[k];
+    b.c[k] = add[k];
+    o.c[k] = out32[k];
+  }
+  k_coef_add<<<L.grid, kBV, 0, L.stream>>>(L.nb, a, b, o);
 }
 
 void launch_corner_coefs(const LaunchCfg& L, const int* nbr, const uint8_t* mask,

@@ -1586,12 +1586,15 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
         for (int k = 0; k < 6; ++k)
           (void)hipMemcpyAsync(g->d_ci64[k], g->d_c[k], b64, hipMemcpyDeviceToDevice, g->stream);
       }
-      // A_i + A_e: both tensors share the fibre field and scale, and the
-      // operator is linear in the tensor, so the sum is the operator of
-      // D_i + D_e = s((sT_i + sT_e) I + ((sL_i - sT_i) + (sL_e - sT_e)) f f^T).
-      // with a bath: D_i + D_e on the heart, sig_bath I on the bath
-      launch_tensor_coefs(g->L, g->d_nbr, g->d_mask, dfib, dsc, sl + sel, st + set_, g->h, tens,
-                          g->d_ck64, g->d_ck32, g->bath ? g->d_body : nullptr, g->sig_bath);
+      // K = -(A_i + A_e), each part over its own domain (eqn:bidomain1 and
+      // its boundary conditions): A_i with the intracellular tensor on the
+      // heart only (no intracellular current crosses the heart's boundary),
+      // A_e over the elliptic domain with D_e on the heart and, with a bath,
+      // sig_bath I on the bath (faces straddling the two take the mean).
+      // The weights of a sum of operators are the sums of their weights.
+      launch_tensor_coefs(g->L, g->d_nbr, g->d_mask, dfib, dsc, sel, set_, g->h, tens,
+                          g->d_ck64, nullptr, g->bath ? g->d_body : nullptr, g->sig_bath);
+      launch_coef_add(g->L, g->d_ck64, g->d_ci64, g->d_ck32);
       launch_dinv<float>(g->L, g->d_nbr, cset32(g->d_ck32), 0.0f, -1.0f, g->d_dinvk);
       rc = coarse_setup(g, tmp);
       if (rc != EP_OK) break;

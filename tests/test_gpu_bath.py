@@ -33,14 +33,17 @@ def rel(a, b):
 
 
 def bath_operator(orc, inst, o):
-    """-A_K on heart + bath, with the tensor field built here in numpy."""
+    """-(A_i + A_e) on heart + bath: A_i with D_i on the heart only, A_e with
+    D_e on the heart and sig_bath I on the bath, over both (the extracellular
+    field built here in numpy)."""
     N = inst.nb
     m, bt = inst.mask.ravel() > 0, inst.bath.ravel() > 0
-    Dk = np.zeros((6, N))
-    Dk[:, m] = (o.Di + o.De)[:, m]
-    Dk[:3, bt] = inst.sigma_bath
+    Deo = np.zeros((6, N))
+    Deo[:, m] = o.De[:, m]
+    Deo[:3, bt] = inst.sigma_bath
     dom = (m | bt).reshape(inst.n).astype(np.uint8)
-    return (lambda phi: -orc.apply(inst.n, inst.h, dom, Dk, phi)), dom
+    return (lambda phi: -(orc.apply(inst.n, inst.h, inst.mask, o.Di, phi)
+                          + orc.apply(inst.n, inst.h, dom, Deo, phi))), dom
 
 
 @pytest.mark.parametrize("n", [32, 128, 256])
