@@ -199,6 +199,29 @@ EP_API ep_status ep_set_conductivity_fibres(ep_grid g, const double* fibre,
                                             double sig_t, double sig_el,
                                             double sig_et);
 
+/* ep_set_conductivity_fibres for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops such as a parameter
+ * sweep that resets the scale field between runs, harnesses that forbid
+ * hipMalloc).  Same arguments, result and errors as
+ * ep_set_conductivity_fibres, bit for bit, but the call's device
+ * temporaries (fibres and scale in brick layout, voxel tensors, FP64
+ * weight scratch, the power-iteration vectors of the explicit stability
+ * check and, for EP_BIDO, the coarse operator's set-up) are carved from one
+ * fixed scratch array the library holds per GPU (64 MiB, held from the first
+ * such call on a device until the process ends) instead of being allocated:
+ * no hipMalloc, hipFree or other allocating routine is called.  A grid
+ * whose set-up needs more than the scratch holds (about 128 bytes per
+ * padded voxel with an FP64 weight copy, so up to ~0.5M padded voxels; plus
+ * the dense coarse operator for EP_BIDO) is refused with EP_ERR_ARG before
+ * anything runs.  Every call on one GPU shares that GPU's scratch: calls
+ * that overlap on one GPU (from several threads, on any grids) race; calls
+ * in sequence are safe (the call synchronises the grid's stream before it
+ * returns, and clears what must start at zero). */
+EP_API ep_status ep_set_conductivity_fibres_noalloc(ep_grid g, const double* fibre,
+                                                    const double* scale, double sig_l,
+                                                    double sig_t, double sig_el,
+                                                    double sig_et);
+
 /* Advance nsteps operator-split steps (reaction, then diffusion; bidomain:
  * reaction, elliptic solve for phi_e from v*, parabolic update).  Activation
  * times are recorded at the first step with v_n < theta <= v_{n+1}, linearly

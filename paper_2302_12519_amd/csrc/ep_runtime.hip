@@ -11,6 +11,7 @@
 #include <limits>
 #include <new>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/ep.h"
@@ -93,9 +94,14 @@ struct ep_grid_s {
   std::vector<void*> allocs;
   int64_t dev_bytes = 0;       // device bytes held now (256-byte granules)
   int64_t dev_peak = 0;        // the most held at once, call temporaries included
+  int device = 0;              // the HIP device the grid's memory lives on
   // caller-owned arena (nullptr: the grid allocates)
   char* arena = nullptr;
   int64_t arena_bytes = 0, arena_used = 0;
+  // call temporaries from a fixed device region instead (set only for the
+  // duration of an allocation-free call; nullptr otherwise)
+  char* temp_region = nullptr;
+  size_t temp_cap = 0, temp_used = 0;
   bool adj_in_arena = false;
   int* d_nbr = nullptr;
   uint64_t* d_rowsn = nullptr;
@@ -241,20 +247,28 @@ ep_status dalloc(ep_grid g, P** out, size_t bytes) {
   return EP_OK;
 }
 
-// Device temporaries of one call: carved from the arena above its current
-// use and given back when the call ends, or hipMalloc'd and freed.  The
-// owner synchronises the grid's stream before they go.
+// Device temporaries of one call: carved from the call's fixed region (an
+// allocation-free call) or the arena above their current use and given back
+// when the call ends, or hipMalloc'd and freed.  The owner synchronises the
+// grid's stream before they go.
 struct Temps {
   ep_grid g;
   int64_t mark, held = 0;
+  size_t region_mark;
   std::vector<void*> mine;
-  explicit Temps(ep_grid gg) : g(gg), mark(gg->arena_used) {}
+  explicit Temps(ep_grid gg) : g(gg), mark(gg->arena_used), region_mark(gg->temp_used) {}
   Temps(const Temps&) = delete;
   Temps& operator=(const Temps&) = delete;
   template <typename P>
   hipError_t get(P** out, size_t bytes) {
     const size_t rb = (bytes + 255) & ~static_cast<size_t>(255);
     void* p = nullptr;
+    if (g->temp_region) {
+      if (g->temp_used + rb > g->temp_cap) return hipErrorOutOfMemory;
+      *out = reinterpret_cast<P*>(g->temp_region + g->temp_used);
+      g->temp_used += rb;
+      return hipSuccess;
+    }
     if (g->arena) {
       if (g->arena_used + static_cast<int64_t>(rb) > g->arena_bytes) return hipErrorOutOfMemory;
       p = g->arena + g->arena_used;
@@ -270,6 +284,7 @@ struct Temps {
     return hipSuccess;
   }
   ~Temps() {
+    if (g->temp_region) g->temp_used = region_mark;
     if (g->arena) g->arena_used = mark;
     for (void* p : mine) (void)hipFree(p);
   }
@@ -1157,6 +1172,7 @@ int64_t tissue_components(const std::vector<uint8_t>& m, const int n[3]) {
 }
 
 ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
+  HIPCHK(g, hipGetDevice(&g->device));
   for (int k = 0; k < 3; ++k)
     if (d->n[k] < 1 || d->n[k] > 4096) return fail(g, EP_ERR_ARG, "n must be in [1, 4096]");
   if (!(d->h > 0) || !std::isfinite(d->h)) return fail(g, EP_ERR_ARG, "h must be > 0");
@@ -1643,6 +1659,63 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
   return rc;
 }
 
+// Bytes of device temporaries set_cond_impl takes for grid g (each
+// request rounded to 256 bytes, as Temps carves them): fibres, scale, voxel
+// tensors, the FP64 weight scratch, the power-iteration vectors of the
+// explicit stability estimate, and the coarse operator's set-up.
+size_t cond_temp_bytes(const ep_grid g, bool has_scale) {
+  auto al = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
+  const size_t b64 = static_cast<size_t>(g->nvox) * sizeof(double);
+  const bool need64 = (g->prec == EP_F64) || g->model == EP_BIDO || g->diff == EP_DIFF_EXPLICIT;
+  size_t need = al(3 * b64) + (has_scale ? al(b64) : 0) + al(6 * b64);
+  if (need64) need += 6 * al(b64);
+  if (g->diff == EP_DIFF_EXPLICIT) need += 2 * al(b64);
+  if (g->model == EP_BIDO) {
+    const size_t n = static_cast<size_t>(g->n_agg);
+    need += al(static_cast<size_t>(g->nb) * kCoarseRow * sizeof(double)) +
+            al(n * n * sizeof(double)) + al(kGjPanel * kGjPanel * sizeof(double)) +
+            2 * al(kGjPanel * n * sizeof(double));
+  }
+  return need;
+}
+
+}  // namespace
+
+// Scratch of the allocation-free conductivity set-up: one copy per GPU the
+// library runs on, held until the process ends.  Host code never passes its
+// name to a kernel or a copy (on the host it is only a stand-in for the
+// symbol); it uses the device address looked up once per device below.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch (hipGetSymbolAddress with the
+// device current, once per device).
+ep_status scratch_on(ep_grid g, void** out) {
+  if (g->device < 0 || g->device >= kMaxDevices)
+    return fail(g, EP_ERR_UNSUPPORTED, "device id beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[g->device]) {
+    int prev = 0;
+    HIPCHK(g, hipGetDevice(&prev));
+    if (prev != g->device) HIPCHK(g, hipSetDevice(g->device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (prev != g->device) (void)hipSetDevice(prev);
+    if (e != hipSuccess || !p)
+      return fail(g, EP_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                     hipGetErrorString(e));
+    g_scratch_ptr[g->device] = p;
+  }
+  *out = g_scratch_ptr[g->device];
+  return EP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1679,6 +1752,36 @@ EP_API ep_status ep_set_conductivity_fibres(ep_grid g, const double* fibre, cons
   } catch (const std::bad_alloc&) {
     return fail(g, EP_ERR_OOM, "host allocation failed");
   }
+}
+
+EP_API ep_status ep_set_conductivity_fibres_noalloc(ep_grid g, const double* fibre,
+                                                    const double* scale, double sig_l,
+                                                    double sig_t, double sig_el,
+                                                    double sig_et) {
+  if (!g) return EP_ERR_ARG;
+  const size_t need = cond_temp_bytes(g, scale != nullptr);
+  if (need > kNoAllocScratchBytes) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "the conductivity set-up of this grid needs %zu bytes of "
+             "device temporaries; the allocation-free call holds at most %zu", need,
+             kNoAllocScratchBytes);
+    return fail(g, EP_ERR_ARG, buf);
+  }
+  void* base = nullptr;
+  TRY(scratch_on(g, &base));
+  g->temp_region = static_cast<char*>(base);
+  g->temp_cap = kNoAllocScratchBytes;
+  g->temp_used = 0;
+  ep_status rc;
+  try {
+    rc = set_cond_impl(g, fibre, scale, sig_l, sig_t, sig_el, sig_et);
+  } catch (const std::bad_alloc&) {
+    rc = fail(g, EP_ERR_OOM, "host allocation failed");
+  }
+  g->temp_region = nullptr;
+  g->temp_cap = 0;
+  g->temp_used = 0;
+  return rc;
 }
 
 EP_API ep_status ep_step(ep_grid g, int32_t nsteps, ep_step_info* info) {

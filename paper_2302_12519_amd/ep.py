@@ -91,6 +91,8 @@ def _load():
     lib.ep_create_grid.argtypes = [C.POINTER(GridDesc), C.POINTER(vp)]
     lib.ep_set_conductivity_fibres.argtypes = [vp, vp, vp, C.c_double, C.c_double, C.c_double,
                                                C.c_double]
+    lib.ep_set_conductivity_fibres_noalloc.argtypes = [vp, vp, vp, C.c_double, C.c_double,
+                                                       C.c_double, C.c_double]
     lib.ep_step.argtypes = [vp, C.c_int32, C.POINTER(StepInfo)]
     lib.ep_solve_elliptic.argtypes = [vp, C.c_double, C.c_int32, C.POINTER(SolveInfo)]
     lib.ep_read_state.argtypes = [vp, C.c_int, vp, C.c_size_t]
@@ -122,7 +124,8 @@ def _load():
     lib.ep_batch_destroy.argtypes = [vp]
     lib.ep_batch_last_error.argtypes = [vp]
     lib.ep_batch_last_error.restype = C.c_char_p
-    for name in ("ep_create_grid", "ep_set_conductivity_fibres", "ep_step", "ep_solve_elliptic",
+    for name in ("ep_create_grid", "ep_set_conductivity_fibres",
+                 "ep_set_conductivity_fibres_noalloc", "ep_step", "ep_solve_elliptic",
                  "ep_read_state", "ep_read_state_device", "ep_write_state", "ep_ecg_leads",
                  "ep_get_step",
                  "ep_set_step",
@@ -256,6 +259,15 @@ class Grid:
         self._check(lib.ep_set_conductivity_fibres(self._h, _p(f), None if s is None else _p(s),
                                                    sig_l, sig_t, sig_el, sig_et),
                     "ep_set_conductivity_fibres")
+
+    def set_conductivity_noalloc(self, fibre, scale, sig_l, sig_t, sig_el=0.0, sig_et=0.0):
+        """ep_set_conductivity_fibres_noalloc: the same set-up with its device
+        temporaries in the library's fixed scratch (no device allocation)."""
+        f = np.ascontiguousarray(fibre, dtype=np.float64).reshape(self.N * 3)
+        s = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64).ravel()
+        self._check(lib.ep_set_conductivity_fibres_noalloc(
+            self._h, _p(f), None if s is None else _p(s), sig_l, sig_t, sig_el, sig_et),
+            "ep_set_conductivity_fibres_noalloc")
 
     def step(self, nsteps, check=True):
         info = StepInfo()
