@@ -154,6 +154,18 @@ typedef struct {
                                 Heart + bath must be one face-connected
                                 component; the gauge is sum phi = 0 over it */
   double sig_bath;           /* bath conductivity (mm^2/ms), > 0 with a bath */
+  int32_t ell_precond;       /* bidomain inner-solve preconditioner: 0 (default)
+                                Jacobi plus the coarse correction over
+                                aggregates of 8x8x8 bricks, whose dense
+                                inverse is kept in FP16; 1 Jacobi only (no
+                                coarse inverse is built).  If an inner
+                                solve breaks down ((r, M r) or the step's
+                                curvature not positive: the rounded
+                                preconditioner is not positive definite on
+                                this grid), the grid drops the coarse
+                                correction for good, repeats that pass with
+                                Jacobi alone and reports precond 1 in
+                                ep_solve_info.  Other values: EP_ERR_ARG */
 } ep_grid_desc;
 
 typedef struct {
@@ -172,6 +184,8 @@ typedef struct {
   int32_t outer;             /* refinement iterations */
   int64_t inner_iters;       /* FP32 PCG iterations in total */
   double relres;             /* final ||b - K phi|| / ||b|| in FP64 */
+  int32_t precond;           /* inner preconditioner in use after the call
+                                (0: Jacobi + coarse correction, 1: Jacobi) */
 } ep_solve_info;
 
 /* Create a grid.  Validates the description, builds the brick map of the

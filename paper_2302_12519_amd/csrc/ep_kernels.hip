@@ -867,6 +867,7 @@ __global__ __launch_bounds__(kBV) void k_cg2_update(
     if (!isfinite(rho)) { st.done = 1; st.fail = 1; }
     else if (rho <= in.tol2 * in.bb) st.done = 1;
     else if (in.it >= in.maxit) { st.done = 1; st.fail = 1; }
+    else if (!(gam > 0.0)) { st.done = 1; st.fail = 1; }   // M not positive definite
     else {
       const double beta = (in.it == 0) ? 0.0 : gam / in.rz;
       const double den = (in.it == 0) ? del : del - beta * gam / in.alpha;

@@ -134,6 +134,7 @@ struct ep_grid_s {
   float* d_w32 = nullptr;                 // w = K z,
   float* d_p32 = nullptr;                 // p
   // two-level preconditioner of the inner solve (aggregates of bricks)
+  bool coarse_on = false;        // the coarse correction is applied
   int n_agg = 0, agg_edge = 1;   // aggregates; bricks per aggregate edge
   int agg_ld = 0;                // n_agg rounded up to a multiple of 4 (row pitch)
   int* d_agg = nullptr;          // nb + 1: brick -> aggregate (ghost -> n_agg)
@@ -721,9 +722,10 @@ ep_status cg2_solve(ep_grid g, int maxit, int* chunk_hint, int* iters, bool* fai
                       j == 0 ? g->d_cgp[0] : g->d_cgp[1], g->dmirror, ++g->seq);
     timer_end(g, tu);
     TimerPair* tc = timer_begin(g, KT_COARSE);
-    launch_coarse_apply(g->stream, g->n_agg, g->agg_ld, g->agg_edge == 1, g->d_agg_ptr,
-                        g->d_agg_brk, g->d_rb, g->d_rc, g->d_kinv, g->kinv_unscale, g->d_cc,
-                        cout);
+    if (g->coarse_on)
+      launch_coarse_apply(g->stream, g->n_agg, g->agg_ld, g->agg_edge == 1, g->d_agg_ptr,
+                          g->d_agg_brk, g->d_rb, g->d_rc, g->d_kinv, g->kinv_unscale, g->d_cc,
+                          cout);
     timer_end(g, tc);
     TimerPair* ta = timer_begin(g, KT_STENCIL);
     launch_cg2_apply(g->Le, g->d_nbr, c, 0.0f, -1.0f, g->d_dinvk, r, g->d_cc, g->d_agg, z, w,
@@ -788,6 +790,17 @@ ep_status elliptic(ep_grid g, const T* vsrc, double rtol, int max_outer, ep_solv
     bool failed = false;
     TRY(cg2_solve(g, g->ell_inner_maxit, &g->last_inner, &iters, &failed));
     inner_total += iters;
+    if (failed && iters < g->ell_inner_maxit && g->coarse_on) {
+      // Breakdown before the iteration limit: (r, M r) or the step's
+      // curvature was not positive (or not finite), so the preconditioner
+      // with the rounded coarse inverse is not positive definite on this
+      // grid.  Drop the coarse correction for good and repeat the pass with
+      // Jacobi alone; phi has not been touched.
+      g->coarse_on = false;
+      HIPCHK(g, hipMemsetAsync(g->d_cc, 0, static_cast<size_t>(g->n_agg + 1) * sizeof(float),
+                               g->stream));
+      continue;
+    }
     launch_phi_correct(g->L, g->d_phi, g->d_x32, g->d_body, g->d_partials);
     launch_reduce_sum(g->stream, g->d_partials, G, 1, g->d_sums + 4);
     corrected = true;
@@ -798,6 +811,7 @@ ep_status elliptic(ep_grid g, const T* vsrc, double rtol, int max_outer, ep_solv
     out->outer = outer;
     out->inner_iters = inner_total;
     out->relres = relres;
+    out->precond = g->coarse_on ? 0 : 1;
   }
   return ok ? EP_OK : EP_ERR_NOCONV;
 }
@@ -1227,6 +1241,9 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   g->ell_rtol = d->ell_rtol;
   g->ell_max_outer = d->ell_max_outer;
   g->ell_inner_maxit = d->ell_inner_maxit;
+  if (d->model == EP_BIDO && d->ell_precond != 0 && d->ell_precond != 1)
+    return fail(g, EP_ERR_ARG, "ell_precond must be 0 (Jacobi + coarse) or 1 (Jacobi)");
+  g->coarse_on = d->model == EP_BIDO && d->ell_precond == 0;
   g->stims.assign(d->stim, d->stim + d->n_stim);
 
   if (d->stream) {
@@ -1612,8 +1629,10 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
                           g->d_ck64, nullptr, g->bath ? g->d_body : nullptr, g->sig_bath);
       launch_coef_add(g->L, g->d_ck64, g->d_ci64, g->d_ck32);
       launch_dinv<float>(g->L, g->d_nbr, cset32(g->d_ck32), 0.0f, -1.0f, g->d_dinvk);
-      rc = coarse_setup(g, tmp);
-      if (rc != EP_OK) break;
+      if (g->coarse_on) {
+        rc = coarse_setup(g, tmp);
+        if (rc != EP_OK) break;
+      }
     }
     if (g->diff == EP_DIFF_BE_PCG || g->diff == EP_DIFF_BE_JACOBI) {
       if (g->prec == EP_F64)
@@ -1670,7 +1689,7 @@ size_t cond_temp_bytes(const ep_grid g, bool has_scale) {
   size_t need = al(3 * b64) + (has_scale ? al(b64) : 0) + al(6 * b64);
   if (need64) need += 6 * al(b64);
   if (g->diff == EP_DIFF_EXPLICIT) need += 2 * al(b64);
-  if (g->model == EP_BIDO) {
+  if (g->model == EP_BIDO && g->coarse_on) {
     const size_t n = static_cast<size_t>(g->n_agg);
     need += al(static_cast<size_t>(g->nb) * kCoarseRow * sizeof(double)) +
             al(n * n * sizeof(double)) + al(kGjPanel * kGjPanel * sizeof(double)) +

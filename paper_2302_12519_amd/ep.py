@@ -58,7 +58,7 @@ class GridDesc(C.Structure):
                 ("pcg_maxit", C.c_int32), ("jacobi_sweeps", C.c_int32), ("ell_rtol", C.c_double),
                 ("ell_max_outer", C.c_int32), ("ell_inner_maxit", C.c_int32),
                 ("stream", C.c_void_p), ("arena", C.c_void_p), ("arena_bytes", C.c_int64),
-                ("bath", C.c_void_p), ("sig_bath", C.c_double)]
+                ("bath", C.c_void_p), ("sig_bath", C.c_double), ("ell_precond", C.c_int32)]
 
 
 class StepInfo(C.Structure):
@@ -68,7 +68,8 @@ class StepInfo(C.Structure):
 
 
 class SolveInfo(C.Structure):
-    _fields_ = [("outer", C.c_int32), ("inner_iters", C.c_int64), ("relres", C.c_double)]
+    _fields_ = [("outer", C.c_int32), ("inner_iters", C.c_int64), ("relres", C.c_double),
+                ("precond", C.c_int32)]
 
 
 class BatchDesc(C.Structure):
@@ -147,7 +148,7 @@ def _p(a):
 def make_desc(n, h, dt, mask=None, model="mono", prec="f32", diff="explicit", ionic=None,
               stims=(), theta=0.5, pcg_rtol=1e-6, pcg_maxit=50, ell_rtol=1e-8,
               ell_max_outer=8, ell_inner_maxit=4000, stream=None, arena=None,
-              jacobi_sweeps=10, bath=None, sig_bath=0.0):
+              jacobi_sweeps=10, bath=None, sig_bath=0.0, ell_precond=0):
     """Fill an ep_grid_desc; returns it and the arrays it points into (keep
     them alive while the descriptor is used).  arena: optional caller-owned
     device memory, a torch CUDA tensor whose bytes the grid carves its
@@ -206,6 +207,7 @@ def make_desc(n, h, dt, mask=None, model="mono", prec="f32", diff="explicit", io
         keep.append(b)
         d.bath = _p(b)
         d.sig_bath = float(sig_bath)
+    d.ell_precond = int(ell_precond)
     return d, keep
 
 
@@ -215,11 +217,11 @@ class Grid:
     def __init__(self, n, h, dt, mask=None, model="mono", prec="f32", diff="explicit",
                  ionic=None, stims=(), theta=0.5, pcg_rtol=1e-6, pcg_maxit=50,
                  ell_rtol=1e-8, ell_max_outer=8, ell_inner_maxit=4000, stream=None,
-                 arena=None, jacobi_sweeps=10, bath=None, sig_bath=0.0):
+                 arena=None, jacobi_sweeps=10, bath=None, sig_bath=0.0, ell_precond=0):
         self._desc, keep = make_desc(n, h, dt, mask, model, prec, diff, ionic, stims, theta,
                                      pcg_rtol, pcg_maxit, ell_rtol, ell_max_outer,
                                      ell_inner_maxit, stream, arena, jacobi_sweeps, bath,
-                                     sig_bath)
+                                     sig_bath, ell_precond)
         self._keep = keep
         self.n = tuple(int(k) for k in n)
         self.N = int(np.prod(self.n))
