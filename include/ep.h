@@ -166,6 +166,14 @@ typedef struct {
                                 correction for good, repeats that pass with
                                 Jacobi alone and reports precond 1 in
                                 ep_solve_info.  Other values: EP_ERR_ARG */
+  int32_t persistent_blocks; /* cap on the workgroups of the persistent CG
+                                launches (implicit-Euler PCG, elliptic
+                                inner solve), a positive multiple of 8 (one
+                                share per XCD), e.g. to leave compute units
+                                to other work on the GPU; each block then
+                                walks more bricks.  0: as many as stay
+                                resident (512 or 768 on MI355X).  Other
+                                values: EP_ERR_ARG */
 } ep_grid_desc;
 
 typedef struct {
@@ -355,6 +363,19 @@ EP_API ep_status ep_grid_stats(ep_grid g, int64_t* n_tissue, int64_t* n_bricks,
 EP_API ep_status ep_kernel_timing(ep_grid g, int32_t enable);
 EP_API ep_status ep_kernel_time(ep_grid g, int32_t kernel_id, double* total_ms,
                                 int64_t* launches);
+
+/* Streaming-bandwidth probe for measurement: the practical HBM ceiling on
+ * this GPU, taken with plain HIP kernels of the kind the stencil kernels
+ * are (16-byte loads and stores per lane, a grid-stride loop, 8 blocks of
+ * 256 threads per CU).  Allocates two buffers of `bytes` on the current
+ * device (give well above the 256 MB last-level cache, e.g. 1 GiB), then
+ * times a copy (bytes read + bytes written) and a read-only sum over one
+ * buffer, each the fastest of `reps` runs after a warm-up, with HIP events
+ * on a stream of its own; frees everything.  Outputs in GB/s (1e9 B/s).
+ * Errors: EP_ERR_ARG (bytes < 1 MiB, reps < 1, NULL), EP_ERR_OOM,
+ * EP_ERR_HIP. */
+EP_API ep_status ep_stream_bandwidth(int64_t bytes, int32_t reps, double* copy_gbs,
+                                     double* read_gbs);
 
 EP_API ep_status ep_destroy_grid(ep_grid g);
 EP_API const char* ep_status_string(ep_status s);

@@ -76,6 +76,22 @@ def threads() -> int:
     return int(lib().orc_threads())
 
 
+def set_threads(n: int) -> None:
+    """Run the oracle's OpenMP loops on n threads from now on."""
+    lib().orc_set_threads(C.c_int(int(n)))
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo), or '' if unknown."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
+
+
 def _p(a):
     return a.ctypes.data_as(C.c_void_p)
 

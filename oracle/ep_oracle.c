@@ -839,5 +839,7 @@ int orc_adjoint(const orc_problem* P, const double* D0, const double* v0,
 }
 
 /* Number of threads the oracle's OpenMP loops run with (the CPU baseline
- * reports it as the cores it used). */
+ * reports it as the cores it used), and a way to change it (the baseline's
+ * one-thread figure). */
 int orc_threads(void) { return omp_get_max_threads(); }
+void orc_set_threads(int n) { if (n >= 1) omp_set_num_threads(n); }

@@ -1306,6 +1306,12 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   // 512-thread blocks fit per CU
   g->Le = g->L;
   g->Le.pgrid = std::min(g->grid, 3 * 256);
+  if (d->persistent_blocks != 0) {
+    if (d->persistent_blocks < 0 || d->persistent_blocks % kXcd != 0)
+      return fail(g, EP_ERR_ARG, "persistent_blocks must be 0 or a positive multiple of 8");
+    g->L.pgrid = std::min(g->L.pgrid, static_cast<int>(d->persistent_blocks));
+    g->Le.pgrid = std::min(g->Le.pgrid, static_cast<int>(d->persistent_blocks));
+  }
   if (g->model == EP_BIDO && tissue_components(boxmask, g->n) != 1)
     return fail(g, EP_ERR_ARG, g->bath ? "heart and bath must be one face-connected component"
                                        : "bidomain tissue must be one face-connected component");

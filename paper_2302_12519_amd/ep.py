@@ -58,7 +58,8 @@ class GridDesc(C.Structure):
                 ("pcg_maxit", C.c_int32), ("jacobi_sweeps", C.c_int32), ("ell_rtol", C.c_double),
                 ("ell_max_outer", C.c_int32), ("ell_inner_maxit", C.c_int32),
                 ("stream", C.c_void_p), ("arena", C.c_void_p), ("arena_bytes", C.c_int64),
-                ("bath", C.c_void_p), ("sig_bath", C.c_double), ("ell_precond", C.c_int32)]
+                ("bath", C.c_void_p), ("sig_bath", C.c_double), ("ell_precond", C.c_int32),
+                ("persistent_blocks", C.c_int32)]
 
 
 class StepInfo(C.Structure):
@@ -108,6 +109,8 @@ def _load():
     lib.ep_kernel_time.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     lib.ep_adjoint_scale.argtypes = [vp, C.c_int32, C.c_int32, vp, C.POINTER(C.c_double), vp,
                                      C.POINTER(C.c_int64)]
+    lib.ep_stream_bandwidth.argtypes = [C.c_int64, C.c_int32, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]
     lib.ep_destroy_grid.argtypes = [vp]
     lib.ep_status_string.argtypes = [C.c_int]
     lib.ep_status_string.restype = C.c_char_p
@@ -131,7 +134,7 @@ def _load():
                  "ep_get_step",
                  "ep_set_step",
                  "ep_grid_stats", "ep_kernel_timing", "ep_kernel_time", "ep_destroy_grid",
-                 "ep_adjoint_scale",
+                 "ep_adjoint_scale", "ep_stream_bandwidth",
                  "ep_batch_create", "ep_batch_submit", "ep_batch_advance", "ep_batch_finished",
                  "ep_batch_read", "ep_batch_release", "ep_batch_get_stats", "ep_batch_destroy"):
         getattr(lib, name).restype = C.c_int
@@ -148,7 +151,8 @@ def _p(a):
 def make_desc(n, h, dt, mask=None, model="mono", prec="f32", diff="explicit", ionic=None,
               stims=(), theta=0.5, pcg_rtol=1e-6, pcg_maxit=50, ell_rtol=1e-8,
               ell_max_outer=8, ell_inner_maxit=4000, stream=None, arena=None,
-              jacobi_sweeps=10, bath=None, sig_bath=0.0, ell_precond=0):
+              jacobi_sweeps=10, bath=None, sig_bath=0.0, ell_precond=0,
+              persistent_blocks=0):
     """Fill an ep_grid_desc; returns it and the arrays it points into (keep
     them alive while the descriptor is used).  arena: optional caller-owned
     device memory, a torch CUDA tensor whose bytes the grid carves its
@@ -208,7 +212,18 @@ def make_desc(n, h, dt, mask=None, model="mono", prec="f32", diff="explicit", io
         d.bath = _p(b)
         d.sig_bath = float(sig_bath)
     d.ell_precond = int(ell_precond)
+    d.persistent_blocks = int(persistent_blocks)
     return d, keep
+
+
+def stream_bandwidth(nbytes=1 << 30, reps=5):
+    """ep_stream_bandwidth: (copy GB/s, read-only GB/s) of plain HIP kernels
+    over `nbytes` buffers on the current device."""
+    cp, rd = C.c_double(), C.c_double()
+    st = lib.ep_stream_bandwidth(int(nbytes), int(reps), C.byref(cp), C.byref(rd))
+    if st != EP_OK:
+        raise EPError(st, "ep_stream_bandwidth: " + lib.ep_status_string(st).decode())
+    return cp.value, rd.value
 
 
 class Grid:
@@ -217,11 +232,12 @@ class Grid:
     def __init__(self, n, h, dt, mask=None, model="mono", prec="f32", diff="explicit",
                  ionic=None, stims=(), theta=0.5, pcg_rtol=1e-6, pcg_maxit=50,
                  ell_rtol=1e-8, ell_max_outer=8, ell_inner_maxit=4000, stream=None,
-                 arena=None, jacobi_sweeps=10, bath=None, sig_bath=0.0, ell_precond=0):
+                 arena=None, jacobi_sweeps=10, bath=None, sig_bath=0.0, ell_precond=0,
+                 persistent_blocks=0):
         self._desc, keep = make_desc(n, h, dt, mask, model, prec, diff, ionic, stims, theta,
                                      pcg_rtol, pcg_maxit, ell_rtol, ell_max_outer,
                                      ell_inner_maxit, stream, arena, jacobi_sweeps, bath,
-                                     sig_bath, ell_precond)
+                                     sig_bath, ell_precond, persistent_blocks)
         self._keep = keep
         self.n = tuple(int(k) for k in n)
         self.N = int(np.prod(self.n))

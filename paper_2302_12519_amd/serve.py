@@ -22,7 +22,7 @@ def percentile(xs, q):
 
 
 def serve(batch, requests, fields=("tact",), clock=time.perf_counter, sleep=time.sleep,
-          submit_per_advance=1):
+          submit_per_advance=1, fields_of=None):
     """Run a request stream to completion.
 
     requests: iterable of objects with ``arrival`` (s from stream start),
@@ -31,6 +31,8 @@ def serve(batch, requests, fields=("tact",), clock=time.perf_counter, sleep=time
     advances, so the host work of submission overlaps the launch in flight
     (an advance returns as soon as its launch is queued and reports the
     requests that the previous launch finished).
+    fields_of (optional): rid -> the fields to read for that request
+    instead of ``fields``.
     Returns a dict with per-request latency, results (the requested fields)
     and aggregate figures (makespan, p50/p99 latency, voxel-steps/s)."""
     pending = sorted(requests, key=lambda r: r.arrival)
@@ -59,7 +61,8 @@ def serve(batch, requests, fields=("tact",), clock=time.perf_counter, sleep=time
         for bid in batch.finished():
             t_done = clock() - t0
             rid = rid_of[bid]
-            results[rid] = {f: batch.read(bid, f) for f in fields}
+            want = fields if fields_of is None else fields_of(rid)
+            results[rid] = {f: batch.read(bid, f) for f in want}
             batch.release(bid)
             latency[rid] = t_done - arrival[rid]
             outstanding -= 1

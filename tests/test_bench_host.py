@@ -70,10 +70,23 @@ def test_committed_summary_names_its_kernel_and_source():
     assert float(keys["traffic_bytes_per_launch"]) > 0
 
 
-def test_cpu_baseline_reports_the_oracle_threads():
+def test_cpu_baseline_protocol():
+    """The baseline starts from the given state (the GPU's at its first timed
+    step), solves to the same rtol, reports the median of 3 runs, a
+    one-thread figure, the thread count and the CPU model, and leaves the
+    oracle's thread count as it was."""
     import ep_inputs as E
     import oracle
-    out = bench.cpu_baseline(E.aniso_be(16, steps=2), 0.0)
+    inst = E.aniso_be(16, steps=2)
+    inst.pcg_rtol = 1e-7
+    v, w = E.random_state(inst, 3)
+    threads = oracle.threads()
+    out = bench.cpu_baseline(inst, (v, w, 25), 2.5, 0.0)
+    assert oracle.threads() == threads
     assert out["kind"] == "oracle" and out["unit"] == "voxel-steps/s"
-    assert out["cores"] == oracle.threads() >= 1
-    assert out["value"] > 0 and "first 1 step(s)" in out["sample"]
+    assert out["cores"] == threads >= 1
+    assert out["value"] > 0 and out["value_1_thread"] > 0
+    assert len(out["runs_s"]) == 3 and out["steps_per_run"] == 1
+    assert "step 25" in out["sample"] and "rtol 1e-07" in out["sample"]
+    assert out["oracle_cg_iters_per_step"] > 0 and out["gpu_cg_iters_per_step"] == 2.5
+    assert isinstance(out["cpu_model"], str)

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import ep_inputs as E
+from parity_util import one_sided_activations
 
 pytestmark = pytest.mark.gpu
 
@@ -46,18 +47,18 @@ def test_plain_box_fp64_every_step(P, orc):
     say("case plain_box_32 fp64 per-step")
     g = P.Grid.from_instance(inst)
     o = orc.Oracle(inst)
-    worst = 0.0
+    worst = worst_w = 0.0
+    v, w = g.read("v"), g.read("w")
     for n in range(1000):
-        if n % 50 == 0 or n < 3:
-            # compare one step from the identical (GPU) state
-            v, w = g.read("v"), g.read("w")
-            o.set_state(v=v, w=w, step=n)
-            o.run(1)
-            g.step(1)
-            worst = max(worst, rel(g.read("v"), o.field("v")))
-        else:
-            g.step(1)
+        # one step from the identical (GPU) state, at every step of the run
+        o.set_state(v=v, w=w, step=n)
+        o.run(1)
+        g.step(1)
+        v, w = g.read("v"), g.read("w")
+        worst = max(worst, rel(v, o.field("v")))
+        worst_w = max(worst_w, rel(w, o.field("w")))
     assert worst <= 1e-12, worst
+    assert worst_w <= 1e-12, worst_w
     # whole-trajectory difference from identical initial states
     g2 = P.Grid.from_instance(inst)
     o2 = orc.Oracle(inst)
@@ -163,6 +164,42 @@ def test_be_pcg_fp32_run(P, orc, rtol):
     assert err <= (1e-4 if rtol <= 1e-7 else 5e-4)
 
 
+_ORACLE_RUNS = {}
+
+
+@pytest.mark.parametrize("blocks", [8, 0])
+def test_be_pcg_fp32_1000_steps(P, orc, blocks):
+    """The FP32 bar on the implicit path: 1000 steps of dt 0.05 (50 ms:
+    stimulus, wavefronts sweeping the shell, repolarisation under way) on a
+    48^3 shell (168 bricks), PCG to 1e-7, against the FP64 oracle: max-abs
+    normalised potential <= 1e-4 and activation times within one dt, at
+    every voxel.  blocks 8 caps the persistent launches at 8 workgroups, so
+    each walks 21 bricks (the multi-brick path of the full-size grid);
+    0 keeps the default (one brick per workgroup at this size)."""
+    inst = E.aniso_be(48, steps=1000)
+    inst.pcg_rtol = 1e-7
+    say(f"case aniso_be_48 fp32 1000 steps persistent_blocks {blocks}")
+    g = P.Grid.from_instance(inst, persistent_blocks=blocks)
+    info = g.step(1000)
+    if "be48" not in _ORACLE_RUNS:
+        o = orc.Oracle(inst, cg_rtol=1e-10)
+        o.run(1000)
+        _ORACLE_RUNS["be48"] = (o.field("v").copy(), o.field("tact").copy())
+    vo, To = _ORACLE_RUNS["be48"]
+    v = g.read("v")
+    err = np.abs(v - vo).max() / np.abs(vo).max()
+    T = g.read("tact")
+    fin = np.isfinite(To) & np.isfinite(T)
+    odd, odd_ok = one_sided_activations(T, To, v, vo, inst.theta, 1000 * inst.dt, inst.dt)
+    dT = np.abs(T[fin] - To[fin]).max()
+    say(f"aniso_be_48 fp32 1000 steps: iters {info['cg_iters']}, err {err:.2e}, dT {dT:.2e} ms, "
+        f"activated {int(fin.sum())} of {inst.nt}, one-sided {odd}")
+    assert fin.sum() > 0.9 * inst.nt
+    assert err <= 1e-4
+    assert dT <= inst.dt
+    assert odd_ok and odd <= 10
+
+
 # ---------------------------------------------------------------------------
 # bidomain
 # ---------------------------------------------------------------------------
@@ -207,6 +244,30 @@ def test_bidomain_steps(P, orc):
         f"phi err {perr:.2e}")
     assert err <= 1e-4
     assert perr <= 1e-3
+
+
+def test_bidomain_64_from_mid_run_state(P, orc):
+    """C3's shell at 64^3 (78,616 voxels): 40 GPU steps from rest (stimulus
+    and young wavefronts), then the GPU state is handed to the oracle and
+    both advance 8 more steps: v and phi (heart) against the oracle's FP64
+    step (its elliptic CG to 1e-10)."""
+    inst = E.bidomain(64, steps=48)
+    say("case bidomain_64 fp32 40 + 8 steps")
+    g = P.Grid.from_instance(inst)
+    g.step(40)
+    o = orc.Oracle(inst, cg_rtol=1e-10)
+    o.set_state(v=g.read("v"), w=g.read("w"), phi=g.read("phi"), step=40)
+    info = g.step(8)
+    o.run(8)
+    v, vo = g.read("v"), o.field("v")
+    phi, po = g.read("phi"), o.field("phi")
+    g.close()
+    err = np.abs(v - vo).max() / np.abs(vo).max()
+    perr = rel(phi, po)
+    say(f"bidomain_64: inner {info['cg_iters']} outer {info['ell_outer']} v err {err:.2e} "
+        f"phi err {perr:.2e}")
+    assert err <= 1e-4
+    assert perr <= 1e-4
 
 
 # ---------------------------------------------------------------------------
