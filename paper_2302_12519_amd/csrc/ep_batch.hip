@@ -5,7 +5,8 @@
 // allocation holding its neighbour table, FP32 operator weights, ping-pong
 // v / w, activation times and stimulus amplitudes.  A work list of
 // (slot, brick) pairs lists every brick of every running request; one
-// persistent launch of k_batch_step advances all of them by one step, each
+// persistent launch of k_batch_step (a fixed grid of resident blocks that
+// strides over the list) advances all of them by one step, each
 // brick with exactly the per-grid explicit kernel's arithmetic (so a request
 // gives the same bits alone, in any mix, or through ep_step).  The state of
 // step s lives in buffer s & 1, and a launch for substep k skips slots whose
@@ -40,6 +41,7 @@ using namespace dev;
 
 struct SlotDev {
   const int* nbr;
+  const uint64_t* rowsn;  // (nb + 1) * 27 row masks of each brick's neighbourhood
   const float* c[6];
   float* v[2];
   float* w[2];
@@ -49,7 +51,7 @@ struct SlotDev {
   float dt, theta;
   double dtd, t_on, t_off;
   long long step, n_steps;
-  int active, pad;
+  int active, nb;         // nb: active bricks (the ghost brick's id)
 };
 
 struct WorkItem {
@@ -57,67 +59,114 @@ struct WorkItem {
 };
 
 // One explicit step of every running request's bricks (substep k of the
-// current graph launch): one block per work item.  The grid size of the
-// captured launches is set to the work-list length whenever the list is
-// rebuilt, so the hardware keeps many bricks' dependent metadata loads
-// (work item, slot, neighbour row) in flight at once.
-__global__ __launch_bounds__(kBV) void k_batch_step(const SlotDev* __restrict__ slots,
+// current graph launch).  Persistent: the work list is dealt to the 8 XCDs
+// in contiguous ranges (a request's bricks are consecutive in the list, so
+// halo neighbours tend to share an XCD's L2), and each block strides
+// through its XCD's range.  The work record and neighbour row of a block's
+// next brick are loaded one brick ahead, so the dependent metadata chain
+// (work item -> slot -> neighbour row) overlaps the current brick.  Each
+// brick takes exactly the per-grid explicit kernel's arithmetic.
+__global__ __launch_bounds__(kBV) __attribute__((amdgpu_waves_per_eu(6))) void k_batch_step(const SlotDev* __restrict__ slots,
                                                     const WorkItem* __restrict__ work,
                                                     const int* __restrict__ count, int k,
                                                     int* flags) {
   __shared__ float s[kTile];
-  __shared__ int nbs[kNbr];
+  __shared__ int nbs[2][kNbr];
+  __shared__ uint64_t rows[2][kNbr];
   const int n = *count;
-  {
-    const int i = blockIdx.x;
-    if (i >= n) return;
-    const WorkItem it = work[i];
+  const int xcd = blockIdx.x % kXcd, gper = gridDim.x / kXcd;
+  const int per = (n + kXcd - 1) / kXcd;
+  const int hi = min(n, (xcd + 1) * per);
+  int i = xcd * per + static_cast<int>(blockIdx.x) / kXcd;
+  WorkItem it{0, 0};
+  int nbv = 0;
+  uint64_t rmv = 0;
+  if (i < hi) {
+    it = work[i];
+    if (threadIdx.x < kNbr) {
+      nbv = slots[it.slot].nbr[it.brick * kNbr + threadIdx.x];
+      rmv = slots[it.slot].rowsn[it.brick * kNbr + threadIdx.x];
+    }
+  }
+  int buf = 0;
+  for (; i < hi; i += gper) {
+    if (threadIdx.x < kNbr) {
+      nbs[buf][threadIdx.x] = nbv;
+      rows[buf][threadIdx.x] = rmv;
+    }
+    // publishes this brick's neighbour row and row masks; every thread has
+    // also finished reading the previous brick's tile
+    __syncthreads();
     const SlotDev* sd = slots + it.slot;
-    const long long st = sd->step + k;
-    if (st >= sd->n_steps) return;
     const int brick = it.brick;
-    if (threadIdx.x < kNbr) nbs[threadIdx.x] = sd->nbr[brick * kNbr + threadIdx.x];
-    __syncthreads();
-    const int par = static_cast<int>(st & 1);
-    const float* __restrict__ v = sd->v[par];
-    const float* __restrict__ w = sd->w[par];
-    float* __restrict__ vout = sd->v[par ^ 1];
-    float* __restrict__ wout = sd->w[par ^ 1];
-    const double tn = static_cast<double>(st) * sd->dtd;
-    const float* __restrict__ jstim =
-        (sd->jamp && sd->t_on <= tn && tn < sd->t_off) ? sd->jamp : nullptr;
-    const IonicT<float> ion = sd->ion;
-    const float dt = sd->dt, theta = sd->theta;
-    CoefSet<float> c;
-    for (int q = 0; q < 6; ++q) c.c[q] = sd->c[q];
-    const Cell q = cell_setup(nbs, brick);
-    const float v0 = v[q.g], w0 = w[q.g];
-    const float j0 = jstim ? jstim[q.g] : 0.0f;
-    float hv = 0.0f, hw = 0.0f, hj = 0.0f;
-    if (q.has_halo) {
-      hv = v[q.hg];
-      hw = w[q.hg];
-      hj = jstim ? jstim[q.hg] : 0.0f;
+    // the next brick's work record, neighbour row and row masks
+    const int i2 = i + gper;
+    WorkItem it2{0, 0};
+    int nbv2 = 0;
+    uint64_t rmv2 = 0;
+    if (i2 < hi) {
+      it2 = work[i2];
+      if (threadIdx.x < kNbr) {
+        nbv2 = slots[it2.slot].nbr[it2.brick * kNbr + threadIdx.x];
+        rmv2 = slots[it2.slot].rowsn[it2.brick * kNbr + threadIdx.x];
+      }
     }
-    float k18[18];
-    gather18(c, nbs, brick, q.lx, q.ly, q.lz, k18);
-    float vs, ws;
-    ms_step(v0, w0, j0, ion, dt, vs, ws);
-    s[q.C] = vs;
-    if (q.has_halo) {
-      float a, b;
-      ms_step(hv, hw, hj, ion, dt, a, b);
-      s[q.hC] = a;
+    const long long st = sd->step + k;
+    if (st < sd->n_steps) {
+      const int* nb = nbs[buf];
+      const uint64_t* rowm = rows[buf];
+      const int ghost = sd->nb;
+      const int par = static_cast<int>(st & 1);
+      const float* __restrict__ v = sd->v[par];
+      const float* __restrict__ w = sd->w[par];
+      float* __restrict__ vout = sd->v[par ^ 1];
+      float* __restrict__ wout = sd->w[par ^ 1];
+      const double tn = static_cast<double>(st) * sd->dtd;
+      const float* __restrict__ jstim =
+          (sd->jamp && sd->t_on <= tn && tn < sd->t_off) ? sd->jamp : nullptr;
+      const IonicT<float> ion = sd->ion;
+      const float dt = sd->dt, theta = sd->theta;
+      CoefSet<float> c;
+      for (int q = 0; q < 6; ++q) c.c[q] = sd->c[q];
+      // rows without tissue read the all-zero ghost brick and are not
+      // stored: their values take no part in any tissue voxel's update (a
+      // zero potential and stimulus give the same reaction value as the
+      // stored rest state, and every weight coupling them is zero)
+      const Cell q = cell_setup(nb, brick, rowm, ghost);
+      const float v0 = v[q.gl], w0 = w[q.gl];
+      const float j0 = jstim ? jstim[q.gl] : 0.0f;
+      float hv = 0.0f, hw = 0.0f, hj = 0.0f;
+      if (q.has_halo) {
+        hv = v[q.hgl];
+        hw = w[q.hgl];
+        hj = jstim ? jstim[q.hgl] : 0.0f;
+      }
+      float k18[18];
+      gather18(c, nb, brick, q.lx, q.ly, q.lz, k18, rowm, ghost);
+      float vs, ws;
+      ms_step(v0, w0, j0, ion, dt, vs, ws);
+      s[q.C] = vs;
+      if (q.has_halo) {
+        float a, b;
+        ms_step(hv, hw, hj, ion, dt, a, b);
+        s[q.hC] = a;
+      }
+      __syncthreads();
+      const float vn = vs + dt * apply19(s, q.C, k18);
+      if (q.live) {
+        vout[q.g] = vn;
+        wout[q.g] = ws;
+        if (v0 < theta && theta <= vn) {
+          if (isinf(sd->tact[q.g]))
+            sd->tact[q.g] = static_cast<float>(tn) + dt * (theta - v0) / (vn - v0);
+        }
+        if (!isfinite(vn)) flags[0] = 1;
+      }
     }
-    __syncthreads();
-    const float vn = vs + dt * apply19(s, q.C, k18);
-    vout[q.g] = vn;
-    wout[q.g] = ws;
-    if (v0 < theta && theta <= vn) {
-      if (isinf(sd->tact[q.g]))
-        sd->tact[q.g] = static_cast<float>(tn) + dt * (theta - v0) / (vn - v0);
-    }
-    if (!isfinite(vn)) flags[0] = 1;
+    it = it2;
+    nbv = nbv2;
+    rmv = rmv2;
+    buf ^= 1;
   }
 }
 
@@ -179,6 +228,7 @@ class Arena {
 size_t region_bytes(const BrickMap& m) {
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   return al(static_cast<size_t>(m.nb + 1) * kNbr * sizeof(int)) +
+         al(static_cast<size_t>(m.nb + 1) * kNbr * sizeof(uint64_t)) +
          12 * al(static_cast<size_t>(m.nvox) * sizeof(float));
 }
 
@@ -192,8 +242,12 @@ struct ep_batch_request {
   int n[3] = {0, 0, 0};
   double h = 0, dt = 0, theta = 0.5;
   ep_ionic ionic{};
-  std::vector<double> fib_b;     // 3 per voxel, brick layout, zero off tissue
-  std::vector<double> scale_b;   // brick layout (empty: scale 1)
+  // 3 fibre components per voxel and the scale (null: scale 1) in brick
+  // layout, written on tissue only: the coefficient kernels never use the
+  // values of other voxels, so the buffers are not cleared (clearing tens
+  // of MB per request dominated the host cost of a submission)
+  std::unique_ptr<double[]> fib_b;
+  std::unique_ptr<double[]> scale_b;
   std::vector<int64_t> stim_idx; // stimulated voxels (brick layout) and their
   std::vector<double> stim_amp;  // summed amplitudes, same rule as the per-grid path
   double sig_l = 0, sig_t = 0;
@@ -321,6 +375,8 @@ ep_status admit(ep_batch b, ep_batch_request* r, int slot) {
   char* base = b->arena_base + r->off;
   int* d_nbr = reinterpret_cast<int*>(base);
   char* p = base + al(static_cast<size_t>(m.nb + 1) * kNbr * sizeof(int));
+  uint64_t* d_rowsn = reinterpret_cast<uint64_t*>(p);
+  p += al(static_cast<size_t>(m.nb + 1) * kNbr * sizeof(uint64_t));
   float* arr[12];
   for (int k = 0; k < 12; ++k) {
     arr[k] = reinterpret_cast<float*>(p);
@@ -330,19 +386,23 @@ ep_status admit(ep_batch b, ep_batch_request* r, int slot) {
   if (ep_status s = grow_scratch(b, m.nvox); s != EP_OK) return s;
   if (ep_status s = grow_stim(b, r->stim_idx.size()); s != EP_OK) return s;
   BHIP(b, hipMemsetAsync(base, 0, r->bytes, b->stream));
-  // rest state on the real bricks (the ghost brick stays zero): w = 1,
-  // T_act = +inf
+  // rest state on the real bricks (the ghost brick stays zero): w = 1 in
+  // both buffers (rows without tissue are never stored), T_act = +inf
   BHIP(b, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(arr[8]), 0x3f800000u, nreal,
+                            b->stream));
+  BHIP(b, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(arr[9]), 0x3f800000u, nreal,
                             b->stream));
   BHIP(b, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(arr[10]), 0x7f800000u, nreal,
                             b->stream));
   BHIP(b, hipMemcpyAsync(d_nbr, m.nbr.data(), m.nbr.size() * sizeof(int), hipMemcpyHostToDevice,
                          b->stream));
-  BHIP(b, hipMemcpyAsync(b->d_mask, m.mask.data(), nv, hipMemcpyHostToDevice, b->stream));
-  BHIP(b, hipMemcpyAsync(b->d_fib, r->fib_b.data(), 3 * nv * sizeof(double),
+  BHIP(b, hipMemcpyAsync(d_rowsn, m.rowsn.data(), m.rowsn.size() * sizeof(uint64_t),
                          hipMemcpyHostToDevice, b->stream));
-  if (!r->scale_b.empty())
-    BHIP(b, hipMemcpyAsync(b->d_scale, r->scale_b.data(), nv * sizeof(double),
+  BHIP(b, hipMemcpyAsync(b->d_mask, m.mask.data(), nv, hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(b->d_fib, r->fib_b.get(), 3 * nv * sizeof(double),
+                         hipMemcpyHostToDevice, b->stream));
+  if (r->scale_b)
+    BHIP(b, hipMemcpyAsync(b->d_scale, r->scale_b.get(), nv * sizeof(double),
                            hipMemcpyHostToDevice, b->stream));
   BHIP(b, hipMemsetAsync(b->d_tens, 0, 6 * nv * sizeof(double), b->stream));
   if (!r->stim_idx.empty()) {
@@ -361,12 +421,14 @@ ep_status admit(ep_batch b, ep_batch_request* r, int slot) {
   L.rowsn = nullptr;
   float* c32[6];
   for (int k = 0; k < 6; ++k) c32[k] = arr[k];
-  launch_tensor_coefs(L, d_nbr, b->d_mask, b->d_fib, r->scale_b.empty() ? nullptr : b->d_scale,
+  launch_tensor_coefs(L, d_nbr, b->d_mask, b->d_fib, r->scale_b ? b->d_scale : nullptr,
                       r->sig_l, r->sig_t, r->h, b->d_tens, nullptr, c32);
   BHIP(b, hipGetLastError());
   SlotDev& sd = b->h_up[slot];
   sd = SlotDev{};
   sd.nbr = d_nbr;
+  sd.rowsn = d_rowsn;
+  sd.nb = m.nb;
   for (int k = 0; k < 6; ++k) sd.c[k] = arr[k];
   sd.v[0] = arr[6];
   sd.v[1] = arr[7];
@@ -401,6 +463,16 @@ ep_status admit(ep_batch b, ep_batch_request* r, int slot) {
 }
 
 ep_status set_step_grid(ep_batch b);
+
+// Grid of the captured step launches: persistent, as many blocks as stay
+// resident (3 per CU at the step kernel's register use), or fewer for a
+// short work list; a multiple of 8 (one share per XCD).
+unsigned step_blocks(int work_count) {
+  const int cap = 3 * 256;
+  const int want = std::min(cap, std::max(1, work_count));
+  return static_cast<unsigned>(((want + kXcd - 1) / kXcd) * kXcd);
+}
+
 
 // Work list of every running request's bricks.  Staged through pinned host
 // memory and enqueued without waiting: the previous graph launch, which
@@ -455,14 +527,13 @@ ep_status rebuild_work(ep_batch b) {
   b->work_count = n;
   b->work_dirty = false;
   // no launch is in flight here (the advance waited for it): resize the grid
-  if (b->exec && b->graph_blocks != std::max(1, n))
+  if (b->exec && b->graph_blocks != static_cast<int>(step_blocks(n)))
     if (ep_status s = set_step_grid(b); s != EP_OK) return s;
   return EP_OK;
 }
 
-// Grid of the captured step launches: one block per work item.
 ep_status set_step_grid(ep_batch b) {
-  const unsigned blocks = static_cast<unsigned>(std::max(1, b->work_count));
+  const unsigned blocks = step_blocks(b->work_count);
   for (hipGraphNode_t node : b->step_nodes) {
     hipKernelNodeParams kp{};
     BHIP(b, hipGraphKernelNodeGetParams(node, &kp));
@@ -476,7 +547,7 @@ ep_status set_step_grid(ep_batch b) {
 ep_status capture(ep_batch b) {
   if (b->exec) return EP_OK;
   BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-  const unsigned blocks = static_cast<unsigned>(std::max(1, b->work_count));
+  const unsigned blocks = step_blocks(b->work_count);
   for (int k = 0; k < b->K; ++k)
     k_batch_step<<<blocks, kBV, 0, b->stream>>>(b->d_slots, b->d_work, b->d_count, k, b->d_flags);
   k_batch_advance<<<(b->max_slots + 255) / 256, 256, 0, b->stream>>>(b->d_slots, b->max_slots,
@@ -633,17 +704,25 @@ EP_API ep_status ep_batch_submit(ep_batch b, const ep_grid_desc* d, const double
     const BrickMap& m = r->map;
     const size_t nv = static_cast<size_t>(m.nvox);
     // fibres (and scale) to brick layout, validated on tissue
-    r->fib_b.assign(3 * nv, 0.0);
-    if (scale) r->scale_b.assign(nv, 0.0);
+    r->fib_b.reset(new double[3 * nv]);
+    if (scale) r->scale_b.reset(new double[nv]);
     std::atomic<int> bad{0};   // 1: non-unit fibre, 2: bad scale
-    std::vector<double> smax_x(r->n[0], 0.0);
-    parallel_for(r->n[0], [&](int64_t xx) {
-      const int x = static_cast<int>(xx);
+    std::vector<double> smax_b(m.nb, 0.0);
+    // one brick per task: its tissue rows are short contiguous runs of the
+    // box-layout input and one contiguous block of the output
+    parallel_for(m.nb, [&](int64_t id) {
+      const int bx = m.brick_pos[3 * id], by = m.brick_pos[3 * id + 1],
+                bz = m.brick_pos[3 * id + 2];
+      const uint64_t rows = m.rows[id];
       double sm = 0.0;
-      for (int y = 0; y < r->n[1]; ++y)
-        for (int z = 0; z < r->n[2]; ++z) {
-          const int64_t gi = m.brick_index(x, y, z);
-          if (gi < 0 || !m.mask[gi]) continue;
+      for (int row = 0; row < 64; ++row) {
+        if (!((rows >> row) & 1)) continue;
+        const int x = 8 * bx + (row >> 3), y = 8 * by + (row & 7);
+        for (int lz = 0; lz < 8; ++lz) {
+          const int z = 8 * bz + lz;
+          if (z >= r->n[2]) break;
+          const int64_t gi = id * kBV + row * 8 + lz;
+          if (!m.mask[gi]) continue;
           const int64_t bi = m.box_index(x, y, z);
           const double f0 = fibre[3 * bi], f1 = fibre[3 * bi + 1], f2 = fibre[3 * bi + 2];
           if (!(std::fabs(std::sqrt(f0 * f0 + f1 * f1 + f2 * f2) - 1.0) <= 1e-6)) bad.store(1);
@@ -656,12 +735,13 @@ EP_API ep_status ep_batch_submit(ep_batch b, const ep_grid_desc* d, const double
             sm = std::max(sm, scale[bi]);
           }
         }
-      smax_x[x] = sm;
+      }
+      smax_b[id] = sm;
     });
     if (bad.load() == 1) return bfail(b, EP_ERR_ARG, "fibre is not a unit vector on a tissue voxel");
     if (bad.load() == 2) return bfail(b, EP_ERR_ARG, "scale must be finite and > 0 on tissue");
     double smax = 1.0;
-    if (scale) smax = *std::max_element(smax_x.begin(), smax_x.end());
+    if (scale) smax = *std::max_element(smax_b.begin(), smax_b.end());
     // stimulated voxels with their summed amplitudes (stimuli in order, as
     // the per-grid path sums them)
     std::vector<std::pair<int64_t, double>> sv;
