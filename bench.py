@@ -30,11 +30,11 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 # (FP32 state; each array read or written once):
 #   implicit-step init (k_be_init): reads v, w, the previous step's v, b and
 #             Q, two older increments d (28 B) and the 6 operator weights
-#             (24 B); writes x0, b, d, Q, w, r0 (24 B)                  -> 76 B
-#   PCG launch 0 (k_pcg_step, first): reads r, M^-1 (8 B) and the weights
-#             (24 B), writes p, q (8 B)                                 -> 40 B
-#   PCG iteration (k_pcg_step): reads x, r, q, p, M^-1 (20 B) and the
-#             weights (24 B), writes x, r, p, q (16 B)                  -> 60 B
+#             (24 B); writes x0, b, d, Q, w, z0 = M^-1 r0 (24 B)          -> 76 B
+#   PCG launch 0 (k_pcg_step, first): reads z (4 B) and the weights
+#             (24 B), writes p, t = M^-1 q (8 B)                        -> 36 B
+#   PCG iteration (k_pcg_step): reads x, z, t, p (16 B) and the weights
+#             (24 B), writes x, z, p, t (16 B)                          -> 56 B
 #   PCG last x update (k_pcg_step, solve done): reads x, p, writes x    -> 12 B
 #   elliptic inner iteration, two-level preconditioner:
 #     update (k_cg2_update): reads z, w, p, s, x, r (24 B), writes p, s,
@@ -47,7 +47,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 #   adjoint step: reads lambda_v, lambda_w, v, w, v_next, crossing step (24 B),
 #             weights and unscaled tensors (48 B), mask (1 B), gradient (8 B,
 #             FP64); writes lambda_v, lambda_w (8 B) and gradient (8 B)  -> 97 B
-ALGO_BYTES = {"be_init": 76, "pcg_first": 40, "pcg_iter": 60, "pcg_final": 12,
+ALGO_BYTES = {"be_init": 76, "pcg_first": 36, "pcg_iter": 56, "pcg_final": 12,
               "cg2_update": 40, "cg2_apply": 40, "stencil_explicit": 40, "adjoint_step": 97}
 STEP_KERNELS = {"be_init": ("k_be_init<float>", "be_init"),
                 "cg_setup": ("k_pcg_step<float> (launch 0: p0 = z0, q0 = K p0)", "pcg_first"),

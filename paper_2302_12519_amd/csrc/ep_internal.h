@@ -158,26 +158,27 @@ void launch_ionic(const LaunchCfg& L, const T* v, const T* w, const T* jstim, T*
 // scalars read from `cin`, publishes them in `cout` and leaves its own
 // partials in `parts`.
 //
-// k_be_init: reaction + r0 = dt A v*, x0 = v*; optionally the activation
-// check of the previous step (x still holds v_prev).  Partials (b.b, r.r).
+// k_be_init: reaction, extrapolated x0, r0 = b - (I - dt A) x0, stored as
+// z0 = M^-1 r0; optionally the activation check of the previous step (x
+// still holds v_prev).  Partials (b.b, r.r).
 template <typename T>
 void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v,
                     const T* w, const T* jstim, const T* bprev, const T* qin, T kd,
                     const T* d2, const T* d3, T q2, T q3, T q4, T* bout, T* dout, T* qout,
-                    T* x, T* wout, T* r, IonicT<T> ion, T dt, T* tact, T theta,
+                    T* x, T* wout, T* z, IonicT<T> ion, T dt, T* tact, T theta,
                     double tprev, int check_prev, int* flags, CGScalars* cout, double* parts,
                     double tol2, int maxit);
 
 
 // One-launch-per-iteration PCG (textbook recurrences with the next
 // residual norms expanded in the previous launch's dots; 7 partials per
-// block).  first: launch 0 of a solve (tests the init's (b.b, r.r)).
+// block), keeping z = M^-1 r and t = M^-1 q.  first: launch 0 of a solve
+// (tests the init's (b.b, r.r)).
 template <typename T>
-void launch_pcg_step(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, const T* dinv,
-                     T* x, const T* r_in, T* r_out, const T* p_in, T* p_out, const T* q_in,
-                     T* q_out, int first, const CGScalars* cin, CGScalars* cout,
-                     const double* prev, double* parts, unsigned long long* mirror,
-                     unsigned seq);
+void launch_pcg_step(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, T* x,
+                     const T* z_in, T* z_out, const T* p_in, T* p_out, const T* t_in, T* t_out,
+                     int first, const CGScalars* cin, CGScalars* cout, const double* prev,
+                     double* parts, unsigned long long* mirror, unsigned seq);
 constexpr int kMaxPartials = 7;   // partial sums per block of any CG launch
 
 // field (brick layout, T) -> caller's device buffer in box layout (O);

@@ -520,7 +520,8 @@ __global__ __launch_bounds__(kBV) void k_ionic(int nb, const T* __restrict__ v,
 // step stores b (bout), d_{n-1} (dout) and
 //   Q_{n+1} = q2 d_{n-1} + q3 d_{n-2} + q4 d_{n-3}   (qout; d2, d3 older ones)
 // for the next one.  No buffer read here is written in the same launch, so
-// halo reads never race with other blocks' writes.  r0 = b - (I - dt A) x0.
+// halo reads never race with other blocks' writes.  r0 = b - (I - dt A) x0;
+// the solve keeps z0 = M^-1 r0 (M the diagonal of I - dt A).
 // When check_prev is set it also records activation for the previous step
 // (vprev -> v) before x0 overwrites vprev's buffer.
 // Partials: (b.b, r.r).
@@ -535,7 +536,7 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
                                                  const T* __restrict__ d3in, T q2, T q3, T q4,
                                                  T* __restrict__ bout, T* __restrict__ dout,
                                                  T* __restrict__ qout, T* x,
-                                                 T* __restrict__ wout, T* __restrict__ r,
+                                                 T* __restrict__ wout, T* __restrict__ z,
                                                  IonicT<T> ion, T dt, T* __restrict__ tact,
                                                  T theta, double tprev, int check_prev,
                                                  int* flags, CGScalars* cout, double* parts,
@@ -593,6 +594,8 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
     ahead.stage(nbt[(m + 1) & 1], rowt[(m + 1) & 1]);
     __syncthreads();
     const T rr = (vs - x0) + dt * apply19(s, q.C, k18);
+    // z0 = M^-1 r0, M the diagonal of I - dt A from this voxel's weights
+    const T z0 = rr / (T(1) - dt * diag19(k18));
     if (check_prev && vp < theta && theta <= v0) {
       if (isinf(tact[q.g])) tact[q.g] = static_cast<T>(tprev) + dt * (theta - vp) / (v0 - vp);
     }
@@ -605,7 +608,7 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
         st_stream<NT>(qout + q.g, q2 * d1 + q3 * d2 + q4 * d3);
       }
       st_stream<NT>(wout + q.g, ws);
-      st_stream<NT>(r + q.g, rr);
+      st_stream<NT>(z + q.g, z0);
     }
     const double rd = static_cast<double>(rr);
     acc[0] += static_cast<double>(vs) * static_cast<double>(vs);
@@ -1020,29 +1023,35 @@ template <typename T> struct Quad {
 // textbook recurrences, with the next residual's two norms, (r, z) and
 // (r, r), expanded in dot products of the previous launch's own vectors, so
 // that the x / r update, the new direction and the operator apply of one
-// iteration share a launch.  K = c0 I + c1 A, z = M^-1 r.
+// iteration share a launch.  K = c0 I + c1 A, M its diagonal (from each
+// voxel's own weights), z = M^-1 r.  The solve keeps z and t = M^-1 q
+// instead of r and q: z' = z - alpha t and q' = K p' = K z' + beta q follow
+// from the recurrences, so the operator is applied to z' and the only
+// vectors read at the halo are z and t (r = M z and q = M t are formed
+// pointwise where needed, and no diagonal array is read).
 //   launch 0: tests the init's residual ((b.b, r.r) partials), then
-//     p_0 = z_0, q_0 = K p_0 (r_0 stays where the init left it);
+//     p_0 = z_0, q_0 = K z_0, t_0 = M^-1 q_0 (z_0 stays where the init left it);
 //   launch k >= 1: from launch k-1's dots, alpha = gamma / delta,
 //     gamma' = gamma - 2 alpha (q, z) + alpha^2 (q, M^-1 q),
 //     rho'   = rho   - 2 alpha (q, r) + alpha^2 (q, q).
 //     If rho' <= tol^2 (b, b) the solve is done and only x += alpha p is
 //     left: a pointwise pass (also taken when maxit is reached, flagged as
-//     failed).  Otherwise r' = r - alpha q, x += alpha p, z' = M^-1 r',
-//     beta = gamma' / gamma, p' = z' + beta p, q' = K p'.
+//     failed).  Otherwise x += alpha p, z' = z - alpha t, beta = gamma' /
+//     gamma, p' = z' + beta p, q' = K z' + beta M t, t' = M^-1 q'.
 // The dots are accumulated in FP64 from the FP32 vectors, so the expansion
 // loses nothing that matters next to the FP32 rounding of r' itself.
 // Partials: (delta, gamma, (q, z), (q, M^-1 q), rho, (q, r), (q, q)) of the
-// launch's own p, q, r.  r, p and q are read at the halo, so a launch writes
-// the other buffer of each pair; x is updated in place.
+// launch's own p, q, r, z, t.  z and t are read at the halo and p by the
+// next launch, so a launch writes the other buffer of each pair; x is
+// updated in place.
 template <typename T, bool NT>
 __global__ __launch_bounds__(kBV) void k_pcg_step(
-    int nb, const int* __restrict__ nbr, CoefSet<T> c, T c0, T c1, const T* __restrict__ dinv,
-    T* __restrict__ x, const T* __restrict__ r_in, T* __restrict__ r_out,
-    const T* __restrict__ p_in, T* __restrict__ p_out, const T* __restrict__ q_in,
-    T* __restrict__ q_out, int first, const CGScalars* __restrict__ cin, CGScalars* cout,
-    const double* __restrict__ prev, double* parts, const uint64_t* __restrict__ rowsn,
-    unsigned long long* mirror, unsigned seq) {
+    int nb, const int* __restrict__ nbr, CoefSet<T> c, T c0, T c1, T* __restrict__ x,
+    const T* __restrict__ z_in, T* __restrict__ z_out, const T* __restrict__ p_in,
+    T* __restrict__ p_out, const T* __restrict__ t_in, T* __restrict__ t_out, int first,
+    const CGScalars* __restrict__ cin, CGScalars* cout, const double* __restrict__ prev,
+    double* parts, const uint64_t* __restrict__ rowsn, unsigned long long* mirror,
+    unsigned seq) {
   const CGScalars in = *cin;
   if (in.done) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1135,40 +1144,42 @@ __global__ __launch_bounds__(kBV) void k_pcg_step(
     ahead.fetch(nbr, rowsn, nxt);
     __syncthreads();
     const Cell e = cell_setup(nbs, brick, rowm, nb);
-    const T rg = r_in[e.gl], dg = dinv[e.gl];
-    const T qg = first ? T(0) : q_in[e.gl];
+    const T zg = z_in[e.gl];
+    const T tg = first ? T(0) : t_in[e.gl];
     const T pg = first ? T(0) : p_in[e.gl];
     const T xg = first ? T(0) : ld_stream<NT>(x + e.gl);
-    T hr = T(0), hd = T(0), hq = T(0), hp = T(0);
+    T hz = T(0), ht = T(0);
     if (e.has_halo) {
-      hr = r_in[e.hgl];
-      hd = dinv[e.hgl];
-      hq = first ? T(0) : q_in[e.hgl];
-      hp = first ? T(0) : p_in[e.hgl];
+      hz = z_in[e.hgl];
+      ht = first ? T(0) : t_in[e.hgl];
     }
     T k18[18];
     gather18(c, nbs, brick, e.lx, e.ly, e.lz, k18, rowm, nb);
-    const T rn = rg - alpha * qg;
-    const T zn = dg * rn;
-    const T pn = zn + beta * pg;
-    s[e.C] = pn;
-    if (e.has_halo) s[e.hC] = hd * (hr - alpha * hq) + beta * hp;
+    // z_k = z_{k-1} - alpha t_{k-1} on the brick and its halo
+    const T zn = zg - alpha * tg;
+    s[e.C] = zn;
+    if (e.has_halo) s[e.hC] = hz - alpha * ht;
     ahead.stage(nbt[(m + 1) & 1], rowt[(m + 1) & 1]);
     __syncthreads();
-    const T qv = c0 * pn + c1 * apply19(s, e.C, k18);
+    // q_k = K p_k = K z_k + beta q_{k-1}, with q_{k-1} = M t_{k-1}
+    const T md = c0 + c1 * diag19(k18);
+    const T qn = (c0 * zn + c1 * apply19(s, e.C, k18)) + beta * (md * tg);
+    const T pn = zn + beta * pg;
+    const T tn = qn / md;
+    const T rn = md * zn;
     if (e.live) {
       if (!first) {
         st_stream<NT>(x + e.g, xg + alpha * pg);
-        st_stream<NT>(r_out + e.g, rn);
+        st_stream<NT>(z_out + e.g, zn);
       }
       st_stream<NT>(p_out + e.g, pn);
-      st_stream<NT>(q_out + e.g, qv);
+      st_stream<NT>(t_out + e.g, tn);
     }
-    const double dr = rn, dz = zn, dp = pn, dq = qv;
+    const double dr = rn, dz = zn, dp = pn, dq = qn;
     acc[0] += dp * dq;
     acc[1] += dr * dz;
     acc[2] += dq * dz;
-    acc[3] += dq * static_cast<double>(dg * qv);
+    acc[3] += dq * static_cast<double>(tn);
     acc[4] += dr * dr;
     acc[5] += dq * dr;
     acc[6] += dq * dq;
@@ -1812,24 +1823,23 @@ template <typename T>
 void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v, const T* w,
                     const T* jstim, const T* bprev, const T* qin, T kd, const T* d2,
                     const T* d3, T q2, T q3, T q4, T* bout, T* dout, T* qout, T* x, T* wout,
-                    T* r, IonicT<T> ion, T dt, T* tact, T theta, double tprev, int check_prev,
+                    T* z, IonicT<T> ion, T dt, T* tact, T theta, double tprev, int check_prev,
                     int* flags, CGScalars* cout, double* parts, double tol2, int maxit) {
   auto k = L.stream_nt ? k_be_init<T, true> : k_be_init<T, false>;
   k<<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, bprev, qin, kd, d2, d3, q2, q3, q4,
-                                   bout, dout, qout, x, wout, r, ion, dt, tact, theta, tprev,
+                                   bout, dout, qout, x, wout, z, ion, dt, tact, theta, tprev,
                                    check_prev, flags, cout, parts, tol2, maxit, L.rowsn);
 }
 
 
 template <typename T>
-void launch_pcg_step(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, const T* dinv,
-                     T* x, const T* r_in, T* r_out, const T* p_in, T* p_out, const T* q_in,
-                     T* q_out, int first, const CGScalars* cin, CGScalars* cout,
-                     const double* prev, double* parts, unsigned long long* mirror,
-                     unsigned seq) {
+void launch_pcg_step(const LaunchCfg& L, const int* nbr, CoefSet<T> c, T c0, T c1, T* x,
+                     const T* z_in, T* z_out, const T* p_in, T* p_out, const T* t_in, T* t_out,
+                     int first, const CGScalars* cin, CGScalars* cout, const double* prev,
+                     double* parts, unsigned long long* mirror, unsigned seq) {
   auto k = L.stream_nt ? k_pcg_step<T, true> : k_pcg_step<T, false>;
-  k<<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, c0, c1, dinv, x, r_in, r_out, p_in, p_out, q_in,
-                                   q_out, first, cin, cout, prev, parts, L.rowsn, mirror, seq);
+  k<<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, c0, c1, x, z_in, z_out, p_in, p_out, t_in,
+                                   t_out, first, cin, cout, prev, parts, L.rowsn, mirror, seq);
 }
 
 template <typename T, typename O>
@@ -1966,8 +1976,8 @@ void launch_loss(const LaunchCfg& L, const uint8_t* mask, const int* cross, cons
                                   const T*, const T*, const T*, const T*, T, const T*,         \
                                   const T*, T, T, T, T*, T*, T*, T*, T*, T*, IonicT<T>, T, T*, \
                                   T, double, int, int*, CGScalars*, double*, double, int);     \
-  template void launch_pcg_step<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T, const T*,  \
-                                   T*, const T*, T*, const T*, T*, const T*, T*, int,          \
+  template void launch_pcg_step<T>(const LaunchCfg&, const int*, CoefSet<T>, T, T, T*,        \
+                                   const T*, T*, const T*, T*, const T*, T*, int,              \
                                    const CGScalars*, CGScalars*, const double*, double*,       \
                                    unsigned long long*, unsigned);                             \
   template void launch_jacobi<T>(const LaunchCfg&, const int*, CoefSet<T>, T, const T*,       \

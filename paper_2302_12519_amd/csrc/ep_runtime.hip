@@ -117,7 +117,7 @@ struct ep_grid_s {
   double* d_ck64[6] = {};     // bidomain: A_i + A_e in FP64
   float* d_ck32[6] = {};      // bidomain: A_i + A_e in FP32
   void* d_cr[2] = {nullptr, nullptr};  // implicit-step PCG vectors (state precision):
-  void* d_cs[2] = {nullptr, nullptr};  // r, p, q, each a ping-pong pair
+  void* d_cs[2] = {nullptr, nullptr};  // z = M^-1 r, p, t = M^-1 q, ping-pong pairs
   void* d_cw[2] = {nullptr, nullptr};
   void* d_dinv = nullptr;
   void* d_bprev[2] = {nullptr, nullptr};  // implicit solve: b of the last two steps
@@ -494,26 +494,25 @@ ep_status wait_status(ep_grid g, unsigned seq, const CGScalars* dev, unsigned lo
 }
 
 // One-launch-per-iteration PCG solve after its init launch (scalars in
-// d_cg[0], the init's (b.b, r.r) partials in d_cgp[0], r0 in rb[0], x0 in x).
-// Launch k reads scalars / partials [k & 1] and writes [(k + 1) & 1]; it
-// reads r_{k-1} from rb[(k - 1) & 1] (r_0 from rb[0]) and writes r_k to
-// rb[k & 1], and p_k, q_k to pb[k & 1], qb[k & 1].  Each launch publishes its
-// convergence test as it starts, so after launches 0 and 1 the host queues
-// one launch at a time while the last one runs its stencil; the launch that
-// finds the solve done does only the last x update.
+// d_cg[0], the init's (b.b, r.r) partials in d_cgp[0], z0 = M^-1 r0 in
+// zb[0], x0 in x).  Launch k reads scalars / partials [k & 1] and writes
+// [(k + 1) & 1]; it reads z_{k-1} from zb[(k - 1) & 1] (z_0 from zb[0]) and
+// writes z_k to zb[k & 1], and p_k, t_k to pb[k & 1], tb[k & 1].  Each
+// launch publishes its convergence test as it starts, so after launches 0
+// and 1 the host queues one launch at a time while the last one runs its
+// stencil; the launch that finds the solve done does only the last x update.
 template <typename T>
-ep_status pcg_step_solve(ep_grid g, CoefSet<T> c, T c0, T c1, const T* dinv, T* x,
-                         T* const rb[2], T* const pb[2], T* const qb[2], int maxit, int* iters,
-                         bool* failed) {
+ep_status pcg_step_solve(ep_grid g, CoefSet<T> c, T c0, T c1, T* x, T* const zb[2],
+                         T* const pb[2], T* const tb[2], int maxit, int* iters, bool* failed) {
   CGScalars* cg = g->d_cg;
   double* const* P = g->d_cgp;
   int n = 0;
   auto launch = [&](int k) {
     TimerPair* t0 = timer_begin(g, k == 0 ? KT_CGSETUP : KT_STENCIL);
-    launch_pcg_step<T>(g->L, g->d_nbr, c, c0, c1, dinv, x, rb[k == 0 ? 0 : (k - 1) & 1],
-                       rb[k & 1], pb[(k + 1) & 1], pb[k & 1], qb[(k + 1) & 1], qb[k & 1],
-                       k == 0 ? 1 : 0, cg + (k & 1), cg + ((k + 1) & 1), P[k & 1],
-                       P[(k + 1) & 1], g->dmirror, ++g->seq);
+    launch_pcg_step<T>(g->L, g->d_nbr, c, c0, c1, x, zb[k == 0 ? 0 : (k - 1) & 1], zb[k & 1],
+                       pb[(k + 1) & 1], pb[k & 1], tb[(k + 1) & 1], tb[k & 1], k == 0 ? 1 : 0,
+                       cg + (k & 1), cg + ((k + 1) & 1), P[k & 1], P[(k + 1) & 1], g->dmirror,
+                       ++g->seq);
     timer_end(g, t0);
     ++n;
   };
@@ -572,10 +571,9 @@ template <typename T>
 ep_status step_be(ep_grid g, const T* jstim, ep_step_info* acc) {
   const int c = g->cur, n = 1 - c;
   T* x = static_cast<T*>(g->d_v[n]);
-  T* r[2] = {static_cast<T*>(g->d_cr[0]), static_cast<T*>(g->d_cr[1])};
+  T* zv[2] = {static_cast<T*>(g->d_cr[0]), static_cast<T*>(g->d_cr[1])};
   T* pv[2] = {static_cast<T*>(g->d_cs[0]), static_cast<T*>(g->d_cs[1])};
-  T* qv[2] = {static_cast<T*>(g->d_cw[0]), static_cast<T*>(g->d_cw[1])};
-  const T* dinv = static_cast<const T*>(g->d_dinv);
+  T* tv[2] = {static_cast<T*>(g->d_cw[0]), static_cast<T*>(g->d_cw[1])};
   // x (= d_v[n]) still holds the previous step's v: check its activation here
   // initial guess: polynomial through the last K = min(pred_len, 4) diffusion
   // increments; Q_n came from the previous step, Q_{n+1} is written now
@@ -602,14 +600,14 @@ ep_status step_be(ep_grid g, const T* jstim, ep_step_info* acc) {
                     d3, q2, q3, q4, static_cast<T*>(g->d_bprev[g->bsel]),
                     static_cast<T*>(g->d_dprev[g->dsel]), static_cast<T*>(g->d_q[g->bsel]),
                     x, static_cast<T*>(g->d_w[n]),
-                    r[0], ionic_t<T>(g), static_cast<T>(g->dt), static_cast<T*>(g->d_tact),
+                    zv[0], ionic_t<T>(g), static_cast<T>(g->dt), static_cast<T*>(g->d_tact),
                     static_cast<T>(g->theta), static_cast<double>(g->step - 1) * g->dt,
                     g->have_prev ? 1 : 0, g->d_flags, g->d_cg, g->d_cgp[0],
                     g->pcg_rtol * g->pcg_rtol, g->pcg_maxit);
   timer_end(g, ti);
   int iters = 0;
   bool failed = false;
-  TRY(pcg_step_solve<T>(g, coefs<T>(g), T(1), static_cast<T>(-g->dt), dinv, x, r, pv, qv,
+  TRY(pcg_step_solve<T>(g, coefs<T>(g), T(1), static_cast<T>(-g->dt), x, zv, pv, tv,
                         g->pcg_maxit, &iters, &failed));
   acc->cg_iters += iters;
   acc->cg_max = std::max(acc->cg_max, iters);
@@ -1352,7 +1350,6 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
       TRY(dalloc(g, &g->d_cs[k], vb));
       TRY(dalloc(g, &g->d_cw[k], vb));
     }
-    TRY(dalloc(g, &g->d_dinv, vb));
     for (int k = 0; k < 2; ++k) TRY(dalloc(g, &g->d_bprev[k], vb));
     for (int k = 0; k < kDRing; ++k) TRY(dalloc(g, &g->d_dprev[k], vb));
     for (int k = 0; k < 2; ++k) TRY(dalloc(g, &g->d_q[k], vb));
@@ -1640,7 +1637,7 @@ ep_status set_cond_impl(ep_grid g, const double* fibre, const double* scale, dou
         if (rc != EP_OK) break;
       }
     }
-    if (g->diff == EP_DIFF_BE_PCG || g->diff == EP_DIFF_BE_JACOBI) {
+    if (g->diff == EP_DIFF_BE_JACOBI) {
       if (g->prec == EP_F64)
         launch_dinv<double>(g->L, g->d_nbr, coefs<double>(g), 1.0, -g->dt,
                             static_cast<double*>(g->d_dinv));
