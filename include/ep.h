@@ -197,7 +197,8 @@ typedef struct {
 } ep_solve_info;
 
 /* Create a grid.  Validates the description, builds the brick map of the
- * tissue mask (voxel geometry as in the Geometry section: tissue voxels are
+ * tissue mask (at most 2^29 voxels in the 8x8x8 bricks holding tissue, else
+ * EP_ERR_UNSUPPORTED) (voxel geometry as in the Geometry section: tissue voxels are
  * the volume pass of the SDF encoding), allocates device state (v = 0,
  * w = 1 on tissue, phi = 0, T_act = +inf) and copies stimuli.  On failure
  * *out is NULL.  Errors: EP_ERR_ARG (bad sizes/values, NULL desc or out,

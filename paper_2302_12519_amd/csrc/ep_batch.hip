@@ -133,13 +133,13 @@ __global__ __launch_bounds__(kBV) __attribute__((amdgpu_waves_per_eu(6))) void k
       // zero potential and stimulus give the same reaction value as the
       // stored rest state, and every weight coupling them is zero)
       const Cell q = cell_setup(nb, brick, rowm, ghost);
-      const float v0 = v[q.gl], w0 = w[q.gl];
-      const float j0 = jstim ? jstim[q.gl] : 0.0f;
+      const float v0 = at(v, q.gl), w0 = at(w, q.gl);
+      const float j0 = jstim ? at(jstim, q.gl) : 0.0f;
       float hv = 0.0f, hw = 0.0f, hj = 0.0f;
       if (q.has_halo) {
-        hv = v[q.hgl];
-        hw = w[q.hgl];
-        hj = jstim ? jstim[q.hgl] : 0.0f;
+        hv = at(v, q.hgl);
+        hw = at(w, q.hgl);
+        hj = jstim ? at(jstim, q.hgl) : 0.0f;
       }
       float k18[18];
       gather18(c, nb, brick, q.lx, q.ly, q.lz, k18, rowm, ghost);
@@ -154,11 +154,11 @@ __global__ __launch_bounds__(kBV) __attribute__((amdgpu_waves_per_eu(6))) void k
       __syncthreads();
       const float vn = vs + dt * apply19(s, q.C, k18);
       if (q.live) {
-        vout[q.g] = vn;
-        wout[q.g] = ws;
+        at(vout, q.g) = vn;
+        at(wout, q.g) = ws;
         if (v0 < theta && theta <= vn) {
-          if (isinf(sd->tact[q.g]))
-            sd->tact[q.g] = static_cast<float>(tn) + dt * (theta - v0) / (vn - v0);
+          if (isinf(at(sd->tact, q.g)))
+            at(sd->tact, q.g) = static_cast<float>(tn) + dt * (theta - v0) / (vn - v0);
         }
         if (!isfinite(vn)) flags[0] = 1;
       }
@@ -703,6 +703,8 @@ EP_API ep_status ep_batch_submit(ep_batch b, const ep_grid_desc* d, const double
     if (!build_brick_map(r->n, d->mask, r->map, merr)) return bfail(b, EP_ERR_ARG, merr);
     const BrickMap& m = r->map;
     const size_t nv = static_cast<size_t>(m.nvox);
+    if (m.nvox > (int64_t(1) << 29))
+      return bfail(b, EP_ERR_UNSUPPORTED, "request too large: more than 2^29 voxels in active bricks");
     // fibres (and scale) to brick layout, validated on tissue
     r->fib_b.reset(new double[3 * nv]);
     if (scale) r->scale_b.reset(new double[nv]);

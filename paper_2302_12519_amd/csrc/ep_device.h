@@ -5,6 +5,7 @@
 #pragma once
 
 #include <cmath>
+#include <cstdint>
 
 #include "ep_internal.h"
 
@@ -13,6 +14,24 @@ namespace dev {
 
 
 __device__ __forceinline__ int tidx(int x, int y, int z) { return (x * kH + y) * kH + z; }
+
+// Element i of a per-voxel array, addressed as base + a 32-bit unsigned
+// byte offset: the compiler then keeps the base in scalar registers and
+// needs one vector register per distinct index (global_load with saddr)
+// instead of a 64-bit address per load.  Every per-voxel array is below
+// 4 GiB (the grid creation refuses larger grids), so the offset never wraps.
+template <typename T>
+__device__ __forceinline__ const T& at(const T* base, int i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
+                                     static_cast<uint64_t>(static_cast<uint32_t>(i) *
+                                                           static_cast<uint32_t>(sizeof(T))));
+}
+template <typename T>
+__device__ __forceinline__ T& at(T* base, int i) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) +
+                               static_cast<uint64_t>(static_cast<uint32_t>(i) *
+                                                     static_cast<uint32_t>(sizeof(T))));
+}
 
 // Workgroups are dealt round-robin to the 8 XCDs; hand each XCD a contiguous
 // run of bricks so that halo neighbours tend to sit in the same L2.
@@ -110,24 +129,24 @@ __device__ __forceinline__ void gather18(const CoefSet<T>& c, const int* nbs, in
     gxz = (l0 && vox_live(rowm, lx - 1, ly, lz - 1)) ? gxz : gh;
     gyz = (l0 && vox_live(rowm, lx, ly - 1, lz - 1)) ? gyz : gh;
   }
-  k[0] = c.c[CX][g];
-  k[1] = c.c[CX][gx];
-  k[2] = c.c[CY][g];
-  k[3] = c.c[CY][gy];
-  k[4] = c.c[CZ][g];
-  k[5] = c.c[CZ][gz];
-  k[6] = c.c[CXY][g];
-  k[7] = c.c[CXY][gxy];
-  k[8] = c.c[CXY][gy];
-  k[9] = c.c[CXY][gx];
-  k[10] = c.c[CXZ][g];
-  k[11] = c.c[CXZ][gxz];
-  k[12] = c.c[CXZ][gz];
-  k[13] = c.c[CXZ][gx];
-  k[14] = c.c[CYZ][g];
-  k[15] = c.c[CYZ][gyz];
-  k[16] = c.c[CYZ][gz];
-  k[17] = c.c[CYZ][gy];
+  k[0] = at(c.c[CX], g);
+  k[1] = at(c.c[CX], gx);
+  k[2] = at(c.c[CY], g);
+  k[3] = at(c.c[CY], gy);
+  k[4] = at(c.c[CZ], g);
+  k[5] = at(c.c[CZ], gz);
+  k[6] = at(c.c[CXY], g);
+  k[7] = at(c.c[CXY], gxy);
+  k[8] = at(c.c[CXY], gy);
+  k[9] = at(c.c[CXY], gx);
+  k[10] = at(c.c[CXZ], g);
+  k[11] = at(c.c[CXZ], gxz);
+  k[12] = at(c.c[CXZ], gz);
+  k[13] = at(c.c[CXZ], gx);
+  k[14] = at(c.c[CYZ], g);
+  k[15] = at(c.c[CYZ], gyz);
+  k[16] = at(c.c[CYZ], gz);
+  k[17] = at(c.c[CYZ], gy);
 }
 
 // (A u)_p from the LDS tile s at tile cell C.  Faces: a (u_q - u_p).  Each

@@ -321,13 +321,13 @@ __global__ __launch_bounds__(kBV) void k_explicit(int nb, const int* __restrict_
   if (threadIdx.x < kNbr) nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
   __syncthreads();
   const Cell q = cell_setup(nbs, brick);
-  const T v0 = v[q.g], w0 = w[q.g];
-  const T j0 = jstim ? jstim[q.g] : T(0);
+  const T v0 = at(v, q.g), w0 = at(w, q.g);
+  const T j0 = jstim ? at(jstim, q.g) : T(0);
   T hv = T(0), hw = T(0), hj = T(0);
   if (q.has_halo) {
-    hv = v[q.hg];
-    hw = w[q.hg];
-    hj = jstim ? jstim[q.hg] : T(0);
+    hv = at(v, q.hg);
+    hw = at(w, q.hg);
+    hj = jstim ? at(jstim, q.hg) : T(0);
   }
   T k18[18];
   gather18(c, nbs, brick, q.lx, q.ly, q.lz, k18);
@@ -341,12 +341,12 @@ __global__ __launch_bounds__(kBV) void k_explicit(int nb, const int* __restrict_
   }
   __syncthreads();
   const T vn = vs + dt * apply19(s, q.C, k18);
-  vout[q.g] = vn;
-  wout[q.g] = ws;
+  at(vout, q.g) = vn;
+  at(wout, q.g) = ws;
   if (v0 < theta && theta <= vn) {
-    if (isinf(tact[q.g])) {
-      tact[q.g] = static_cast<T>(tn) + dt * (theta - v0) / (vn - v0);
-      if (cross) cross[q.g] = step;
+    if (isinf(at(tact, q.g))) {
+      at(tact, q.g) = static_cast<T>(tn) + dt * (theta - v0) / (vn - v0);
+      if (cross) at(cross, q.g) = step;
     }
   }
   if (!isfinite(vn)) flags[0] = 1;
@@ -406,13 +406,13 @@ __global__ __launch_bounds__(kBV) void k_explicit27(int nb, const int* __restric
   if (threadIdx.x < kNbr) nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
   __syncthreads();
   const Cell q = cell_setup(nbs, brick);
-  const T v0 = v[q.g], w0 = w[q.g];
-  const T j0 = jstim ? jstim[q.g] : T(0);
+  const T v0 = at(v, q.g), w0 = at(w, q.g);
+  const T j0 = jstim ? at(jstim, q.g) : T(0);
   T hv = T(0), hw = T(0), hj = T(0);
   if (q.has_halo) {
-    hv = v[q.hg];
-    hw = w[q.hg];
-    hj = jstim ? jstim[q.hg] : T(0);
+    hv = at(v, q.hg);
+    hw = at(w, q.hg);
+    hj = jstim ? at(jstim, q.hg) : T(0);
   }
   // the 8 corner cells of the tile, which the 19-point halo leaves out
   const bool tcorner = threadIdx.x >= kHalo && threadIdx.x < kHalo + 8;
@@ -471,10 +471,10 @@ __global__ __launch_bounds__(kBV) void k_explicit27(int nb, const int* __restric
         a += fx + fy + fz;
       }
   const T vn = vs + dt * a;
-  vout[q.g] = vn;
-  wout[q.g] = ws;
-  if (v0 < theta && theta <= vn && isinf(tact[q.g]))
-    tact[q.g] = static_cast<T>(tn) + dt * (theta - v0) / (vn - v0);
+  at(vout, q.g) = vn;
+  at(wout, q.g) = ws;
+  if (v0 < theta && theta <= vn && isinf(at(tact, q.g)))
+    at(tact, q.g) = static_cast<T>(tn) + dt * (theta - v0) / (vn - v0);
   if (!isfinite(vn)) flags[0] = 1;
 }
 
@@ -564,20 +564,20 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
     ahead.fetch(nbr, rowsn, nxt);
     __syncthreads();
     const Cell q = cell_setup(nbs, brick, rowm, nb);
-    const T v0 = v[q.gl], w0 = w[q.gl];
-    const T j0 = jstim ? jstim[q.gl] : T(0);
-    const T vp = check_prev ? ld_stream<NT>(x + q.gl) : T(0);
-    const T b1 = bprev ? bprev[q.gl] : T(0);
-    const T q0 = qin ? qin[q.gl] : T(0);
-    const T d2 = d2in ? ld_stream<NT>(d2in + q.gl) : T(0);
-    const T d3 = d3in ? ld_stream<NT>(d3in + q.gl) : T(0);
+    const T v0 = at(v, q.gl), w0 = at(w, q.gl);
+    const T j0 = jstim ? at(jstim, q.gl) : T(0);
+    const T vp = check_prev ? ld_stream<NT>(&at(x, q.gl)) : T(0);
+    const T b1 = bprev ? at(bprev, q.gl) : T(0);
+    const T q0 = qin ? at(qin, q.gl) : T(0);
+    const T d2 = d2in ? ld_stream<NT>(&at(d2in, q.gl)) : T(0);
+    const T d3 = d3in ? ld_stream<NT>(&at(d3in, q.gl)) : T(0);
     T hv = T(0), hw = T(0), hj = T(0), hb1 = T(0), hq = T(0);
     if (q.has_halo) {
-      hv = v[q.hgl];
-      hw = w[q.hgl];
-      hj = jstim ? jstim[q.hgl] : T(0);
-      hb1 = bprev ? bprev[q.hgl] : T(0);
-      hq = qin ? qin[q.hgl] : T(0);
+      hv = at(v, q.hgl);
+      hw = at(w, q.hgl);
+      hj = jstim ? at(jstim, q.hgl) : T(0);
+      hb1 = bprev ? at(bprev, q.hgl) : T(0);
+      hq = qin ? at(qin, q.hgl) : T(0);
     }
     T k18[18];
     gather18(c, nbs, brick, q.lx, q.ly, q.lz, k18, rowm, nb);
@@ -597,18 +597,18 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
     // z0 = M^-1 r0, M the diagonal of I - dt A from this voxel's weights
     const T z0 = rr / (T(1) - dt * diag19(k18));
     if (check_prev && vp < theta && theta <= v0) {
-      if (isinf(tact[q.g])) tact[q.g] = static_cast<T>(tprev) + dt * (theta - vp) / (v0 - vp);
+      if (isinf(at(tact, q.g))) at(tact, q.g) = static_cast<T>(tprev) + dt * (theta - vp) / (v0 - vp);
     }
     if (!isfinite(v0)) flags[0] = 1;
     if (q.live) {
-      st_stream<NT>(x + q.g, x0);
-      st_stream<NT>(bout + q.g, vs);
+      st_stream<NT>(&at(x, q.g), x0);
+      st_stream<NT>(&at(bout, q.g), vs);
       if (bprev) {
-        st_stream<NT>(dout + q.g, d1);
-        st_stream<NT>(qout + q.g, q2 * d1 + q3 * d2 + q4 * d3);
+        st_stream<NT>(&at(dout, q.g), d1);
+        st_stream<NT>(&at(qout, q.g), q2 * d1 + q3 * d2 + q4 * d3);
       }
-      st_stream<NT>(wout + q.g, ws);
-      st_stream<NT>(z + q.g, z0);
+      st_stream<NT>(&at(wout, q.g), ws);
+      st_stream<NT>(&at(z, q.g), z0);
     }
     const double rd = static_cast<double>(rr);
     acc[0] += static_cast<double>(vs) * static_cast<double>(vs);
@@ -988,12 +988,12 @@ __global__ __launch_bounds__(kBV) void k_cg2_apply(
     ahead.fetch(nbr, rowsn, nxt);
     __syncthreads();
     const Cell e = cell_setup(nbs, brick);
-    const float rg = r[e.g], dg = dinv[e.g];
+    const float rg = at(r, e.g), dg = at(dinv, e.g);
     const float cown = cc[agg[brick]];
     float hr = 0.0f, hd = 0.0f, hc = 0.0f;
     if (e.has_halo) {
-      hr = r[e.hg];
-      hd = dinv[e.hg];
+      hr = at(r, e.hg);
+      hd = at(dinv, e.hg);
       hc = cc[agg[e.hg / kBV]];
     }
     float k18[18];
@@ -1004,8 +1004,8 @@ __global__ __launch_bounds__(kBV) void k_cg2_apply(
     ahead.stage(nbt[(m + 1) & 1], rowt[(m + 1) & 1]);
     __syncthreads();
     const float wv = c0 * zn + c1 * apply19(s, e.C, k18);
-    z[e.g] = zn;
-    w[e.g] = wv;
+    at(z, e.g) = zn;
+    at(w, e.g) = wv;
     acc[0] += static_cast<double>(rg) * static_cast<double>(zn);
     acc[1] += static_cast<double>(zn) * static_cast<double>(wv);
     acc[2] += static_cast<double>(rg) * static_cast<double>(rg);
@@ -1144,14 +1144,14 @@ __global__ __launch_bounds__(kBV) void k_pcg_step(
     ahead.fetch(nbr, rowsn, nxt);
     __syncthreads();
     const Cell e = cell_setup(nbs, brick, rowm, nb);
-    const T zg = z_in[e.gl];
-    const T tg = first ? T(0) : t_in[e.gl];
-    const T pg = first ? T(0) : p_in[e.gl];
-    const T xg = first ? T(0) : ld_stream<NT>(x + e.gl);
+    const T zg = at(z_in, e.gl);
+    const T tg = first ? T(0) : at(t_in, e.gl);
+    const T pg = first ? T(0) : at(p_in, e.gl);
+    const T xg = first ? T(0) : ld_stream<NT>(&at(x, e.gl));
     T hz = T(0), ht = T(0);
     if (e.has_halo) {
-      hz = z_in[e.hgl];
-      ht = first ? T(0) : t_in[e.hgl];
+      hz = at(z_in, e.hgl);
+      ht = first ? T(0) : at(t_in, e.hgl);
     }
     T k18[18];
     gather18(c, nbs, brick, e.lx, e.ly, e.lz, k18, rowm, nb);
@@ -1169,11 +1169,11 @@ __global__ __launch_bounds__(kBV) void k_pcg_step(
     const T rn = md * zn;
     if (e.live) {
       if (!first) {
-        st_stream<NT>(x + e.g, xg + alpha * pg);
-        st_stream<NT>(z_out + e.g, zn);
+        st_stream<NT>(&at(x, e.g), xg + alpha * pg);
+        st_stream<NT>(&at(z_out, e.g), zn);
       }
-      st_stream<NT>(p_out + e.g, pn);
-      st_stream<NT>(t_out + e.g, tn);
+      st_stream<NT>(&at(p_out, e.g), pn);
+      st_stream<NT>(&at(t_out, e.g), tn);
     }
     const double dr = rn, dz = zn, dp = pn, dq = qn;
     acc[0] += dp * dq;
@@ -1245,14 +1245,14 @@ __global__ __launch_bounds__(kBV) void k_jacobi(int nb, const int* __restrict__ 
   }
   __syncthreads();
   const Cell e = cell_setup(nbs, brick, rowm, nb);
-  const T xg = x_in[e.gl], bg = b[e.gl], dg = dinv[e.gl];
+  const T xg = at(x_in, e.gl), bg = at(b, e.gl), dg = at(dinv, e.gl);
   s[e.C] = xg;
-  if (e.has_halo) s[e.hC] = x_in[e.hgl];
+  if (e.has_halo) s[e.hC] = at(x_in, e.hgl);
   T k18[18];
   gather18(c, nbs, brick, e.lx, e.ly, e.lz, k18, rowm, nb);
   __syncthreads();
   const T r = (bg - xg) + dt * apply19(s, e.C, k18);
-  if (e.live) x_out[e.g] = xg + dg * r;
+  if (e.live) at(x_out, e.g) = xg + dg * r;
 }
 
 // Jacobi: dinv = 1 / (c0 + c1 A_pp) where positive, else 0.
@@ -1325,11 +1325,11 @@ __global__ __launch_bounds__(kBV) void k_resid64(int nb, const int* __restrict__
   if (threadIdx.x < kNbr) nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
   __syncthreads();
   const Cell q = cell_setup(nbs, brick);
-  sa[q.C] = static_cast<double>(vs[q.g]);
-  sb[q.C] = phi[q.g];
+  sa[q.C] = static_cast<double>(at(vs, q.g));
+  sb[q.C] = at(phi, q.g);
   if (q.has_halo) {
-    sa[q.hC] = static_cast<double>(vs[q.hg]);
-    sb[q.hC] = phi[q.hg];
+    sa[q.hC] = static_cast<double>(at(vs, q.hg));
+    sb[q.hC] = at(phi, q.hg);
   }
   __syncthreads();
   double k18[18];
@@ -1337,7 +1337,7 @@ __global__ __launch_bounds__(kBV) void k_resid64(int nb, const int* __restrict__
   const double b = apply19(sa, q.C, k18);
   gather18(ck, nbs, brick, q.lx, q.ly, q.lz, k18);
   const double r = b + apply19(sb, q.C, k18);
-  r64[q.g] = r;
+  at(r64, q.g) = r;
   double acc[3] = {r * r, r, b * b};
   block_partials<3>(acc, partials);
 }
@@ -1424,14 +1424,14 @@ __global__ __launch_bounds__(kBV) void k_parabolic(int nb, const int* __restrict
   if (threadIdx.x < kNbr) nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
   __syncthreads();
   const Cell q = cell_setup(nbs, brick);
-  const T vsg = vs[q.g];
-  const double pg = phi[q.g];
-  const T v0 = vold[q.g];
+  const T vsg = at(vs, q.g);
+  const double pg = at(phi, q.g);
+  const T v0 = at(vold, q.g);
   T hv = T(0);
   double hp = 0.0;
   if (q.has_halo) {
-    hv = vs[q.hg];
-    hp = phi[q.hg];
+    hv = at(vs, q.hg);
+    hp = at(phi, q.hg);
   }
   T k18[18];
   gather18(ci, nbs, brick, q.lx, q.ly, q.lz, k18);
@@ -1439,9 +1439,9 @@ __global__ __launch_bounds__(kBV) void k_parabolic(int nb, const int* __restrict
   if (q.has_halo) s[q.hC] = hv + static_cast<T>(hp);
   __syncthreads();
   const T vn = vsg + dt * apply19(s, q.C, k18);
-  vout[q.g] = vn;
+  at(vout, q.g) = vn;
   if (v0 < theta && theta <= vn) {
-    if (isinf(tact[q.g])) tact[q.g] = static_cast<T>(tn) + dt * (theta - v0) / (vn - v0);
+    if (isinf(at(tact, q.g))) at(tact, q.g) = static_cast<T>(tn) + dt * (theta - v0) / (vn - v0);
   }
   if (!isfinite(vn)) flags[0] = 1;
 }
@@ -1458,14 +1458,14 @@ __global__ __launch_bounds__(kBV) void k_apply(int nb, const int* __restrict__ n
   if (threadIdx.x < kNbr) nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
   __syncthreads();
   const Cell q = cell_setup(nbs, brick);
-  const T xg = x[q.g];
+  const T xg = at(x, q.g);
   s[q.C] = xg;
-  if (q.has_halo) s[q.hC] = x[q.hg];
+  if (q.has_halo) s[q.hC] = at(x, q.hg);
   T k18[18];
   gather18(c, nbs, brick, q.lx, q.ly, q.lz, k18);
   __syncthreads();
   const T yv = apply19(s, q.C, k18);
-  y[q.g] = yv;
+  at(y, q.g) = yv;
   double acc[2] = {static_cast<double>(yv) * static_cast<double>(yv),
                    static_cast<double>(xg) * static_cast<double>(yv)};
   if (partials) block_partials<2>(acc, partials);
@@ -1603,17 +1603,17 @@ __global__ __launch_bounds__(kBV) void k_adj_step(
   if (threadIdx.x < kNbr) nbs[threadIdx.x] = nbr[brick * kNbr + threadIdx.x];
   __syncthreads();
   const Cell q = cell_setup(nbs, brick);
-  const T mu = lv_in[q.g], v0 = v[q.g], w0 = w[q.g];
-  const T j0 = jstim ? jstim[q.g] : T(0);
-  const uint8_t m0 = mask[q.g];
+  const T mu = at(lv_in, q.g), v0 = at(v, q.g), w0 = at(w, q.g);
+  const T j0 = jstim ? at(jstim, q.g) : T(0);
+  const uint8_t m0 = at(mask, q.g);
   T hm = T(0), hv = T(0), hw = T(0), hj = T(0);
   uint8_t hk = 0;
   if (q.has_halo) {
-    hm = lv_in[q.hg];
-    hv = v[q.hg];
-    hw = w[q.hg];
-    hj = jstim ? jstim[q.hg] : T(0);
-    hk = mask[q.hg];
+    hm = at(lv_in, q.hg);
+    hv = at(v, q.hg);
+    hw = at(w, q.hg);
+    hj = jstim ? at(jstim, q.hg) : T(0);
+    hk = at(mask, q.hg);
   }
   T k18[18];
   gather18(c, nbs, brick, q.lx, q.ly, q.lz, k18);
@@ -1634,25 +1634,25 @@ __global__ __launch_bounds__(kBV) void k_adj_step(
   }
   __syncthreads();
   if (!m0) {
-    lv_out[q.g] = T(0);
-    lw_out[q.g] = T(0);
+    at(lv_out, q.g) = T(0);
+    at(lw_out, q.g) = T(0);
     return;
   }
   const T nu = mu + dt * apply19(sm, q.C, k18);
-  grad[q.g] -= static_cast<double>(dt * dB_ds(sm, su, mk, q.C, dq, inv_h2));
+  at(grad, q.g) -= static_cast<double>(dt * dB_ds(sm, su, mk, q.C, dq, inv_h2));
   const T dvs_dv = T(1) + dt * (ion.exc * (T(2) * v0 - T(3) * v0 * v0) * w0 * ion.inv_tau_in -
                                 ion.inv_tau_out);
   const T dvs_dw = dt * ion.exc * v0 * v0 * (T(1) - v0) * ion.inv_tau_in;
   const T dws_dw = (v0 < ion.v_gate) ? T(1) - dt * ion.inv_tau_open : T(1) - dt * ion.inv_tau_close;
   T lvn = nu * dvs_dv;
-  const int cs = cross[q.g];
-  if ((cs == n || (vprev && cs == n - 1)) && isfinite(tstar[q.g])) {
-    const T dl = T(2) * (tact[q.g] - tstar[q.g]);
-    if (cs == n) lvn += cross_seed(v0, vnext[q.g], theta, dt, dl, true);
-    else lvn += cross_seed(vprev[q.g], v0, theta, dt, dl, false);
+  const int cs = at(cross, q.g);
+  if ((cs == n || (vprev && cs == n - 1)) && isfinite(at(tstar, q.g))) {
+    const T dl = T(2) * (at(tact, q.g) - at(tstar, q.g));
+    if (cs == n) lvn += cross_seed(v0, at(vnext, q.g), theta, dt, dl, true);
+    else lvn += cross_seed(at(vprev, q.g), v0, theta, dt, dl, false);
   }
-  lv_out[q.g] = lvn;
-  lw_out[q.g] = nu * dvs_dw + lw_in[q.g] * dws_dw;
+  at(lv_out, q.g) = lvn;
+  at(lw_out, q.g) = nu * dvs_dw + at(lw_in, q.g) * dws_dw;
 }
 
 // loss partials over voxels activated in the run and in the target:

@@ -1278,6 +1278,10 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   g->nb = nb;
   g->n_body = bm.n_tissue;
   g->nvox = bm.nvox;
+  // kernels address per-voxel arrays with 32-bit byte offsets, and some
+  // arrays are FP64 (bidomain, FP64 state, the set-up's weight copy)
+  if (g->nvox > (int64_t(1) << 29))
+    return fail(g, EP_ERR_UNSUPPORTED, "grid too large: more than 2^29 voxels in active bricks");
   if (g->bath) {
     // the heart alone, in brick layout
     g->hmask.assign(g->hbody.size(), 0);
