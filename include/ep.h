@@ -280,7 +280,8 @@ EP_API ep_status ep_solve_elliptic(ep_grid g, double rel_tol, int32_t max_outer,
  *    step), as ep_step would leave it.
  *  - tstar: host, box layout, n0*n1*n2 entries in ms; non-finite = no target.
  *  - grad: host output, box layout, dL/ds per voxel (0 off tissue), in the
- *    state precision of the grid, accumulated in FP64.
+ *    state precision of the grid, accumulated in FP64; NULL computes the
+ *    loss only (the forward run, no checkpoints and no backward pass).
  *  - loss, n_used: L and the number of voxels in the sum.
  *  - ckpt_every K >= 1: the forward run keeps (v, w) every K steps; the
  *    backward pass recomputes one K-step segment at a time.  Device memory:
@@ -289,7 +290,8 @@ EP_API ep_status ep_solve_elliptic(ep_grid g, double rel_tol, int32_t max_outer,
  *  - The gate-switch derivative at v = v_gate (a Dirac) is dropped: the
  *    gradient is that of the piecewise-smooth map with the branch held.
  * Errors: EP_ERR_UNSUPPORTED (not explicit monodomain), EP_ERR_STATE (no
- * conductivity), EP_ERR_ARG (NULL, nsteps < 1, ckpt_every < 0), EP_ERR_OOM
+ * conductivity), EP_ERR_ARG (NULL tstar / loss / n_used, nsteps < 1,
+ * ckpt_every < 0), EP_ERR_OOM
  * (work block does not fit), EP_ERR_NONFINITE, EP_ERR_HIP. */
 EP_API ep_status ep_adjoint_scale(ep_grid g, int32_t nsteps, int32_t ckpt_every,
                                   const double* tstar, double* loss, double* grad,

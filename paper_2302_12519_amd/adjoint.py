@@ -1,11 +1,13 @@
 """Activation-time loss as a differentiable function of the per-voxel
 conductivity scale (``torch.autograd.Function``).
 
-The forward call runs the explicit monodomain simulation and the discrete
-adjoint together in the HIP library (``ep_adjoint_scale``: checkpointed
-forward, per-segment recompute, one fused adjoint kernel per step); autograd's
-backward only multiplies the stored gradient by the incoming cotangent.
-torch carries the tensors; no arithmetic of the method runs here.
+When the scale needs a gradient, the forward call runs the explicit
+monodomain simulation and the discrete adjoint together in the HIP library
+(``ep_adjoint_scale``: checkpointed forward, per-segment recompute, one fused
+adjoint kernel per step) and autograd's backward only multiplies the stored
+gradient by the incoming cotangent; otherwise it runs the forward simulation
+and the loss alone.  torch carries the tensors; no arithmetic of the method
+runs here.
 """
 from __future__ import annotations
 
@@ -27,14 +29,16 @@ class ActivationTimeLoss(torch.autograd.Function):
         grid.write("v", v0)
         grid.write("w", w0)
         grid.step_index = int(step0)
-        loss, grad, used = grid.adjoint_scale(tstar, nsteps, ckpt_every)
-        ctx.grad = torch.from_numpy(np.ascontiguousarray(grad)).to(scale.device, scale.dtype)
+        want = bool(ctx.needs_input_grad[0])
+        loss, grad, used = grid.adjoint_scale(tstar, nsteps, ckpt_every, grad=want)
+        ctx.grad = (torch.from_numpy(np.ascontiguousarray(grad)).to(scale.device, scale.dtype)
+                    if want else None)
         ctx.n_used = used
         return torch.tensor(loss, dtype=scale.dtype, device=scale.device)
 
     @staticmethod
     def backward(ctx, gout):
-        return (gout * ctx.grad,) + (None,) * 10
+        return (gout * ctx.grad if ctx.grad is not None else None,) + (None,) * 10
 
 
 def activation_time_loss(grid: Grid, scale, fibre, sig_l, sig_t, tstar, nsteps, v0=None,

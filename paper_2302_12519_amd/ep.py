@@ -305,18 +305,20 @@ class Grid:
         out["status"] = st
         return out
 
-    def adjoint_scale(self, tstar, nsteps, ckpt_every=0):
+    def adjoint_scale(self, tstar, nsteps, ckpt_every=0, grad=True):
         """Run ``nsteps`` explicit steps with a fresh T_act and return
-        (loss, dL/dscale in box layout, voxels in the loss)."""
+        (loss, dL/dscale in box layout, voxels in the loss); with
+        ``grad=False`` only the forward run and the loss (gradient None)."""
         t = np.ascontiguousarray(tstar, dtype=np.float64).ravel()
         if t.size != self.N:
             raise ValueError("tstar size does not match n")
-        grad = np.empty(self.N, dtype=np.float64)
+        g = np.empty(self.N, dtype=np.float64) if grad else None
         loss, used = C.c_double(), C.c_int64()
         self._check(lib.ep_adjoint_scale(self._h, int(nsteps), int(ckpt_every), _p(t),
-                                         C.byref(loss), _p(grad), C.byref(used)),
+                                         C.byref(loss), None if g is None else _p(g),
+                                         C.byref(used)),
                     "ep_adjoint_scale")
-        return loss.value, grad.reshape(self.n), used.value
+        return loss.value, (None if g is None else g.reshape(self.n)), used.value
 
     def read(self, field):
         out = np.empty(self.N, dtype=np.float64)

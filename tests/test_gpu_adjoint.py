@@ -129,6 +129,29 @@ def test_autograd_function(P, small):
     g.close()
 
 
+def test_forward_only_call(P, small):
+    """Without a gradient to compute (the scale does not require one, or
+    grad=False), the call runs the forward simulation and the loss only: the
+    same loss, voxel count and final state as the full call."""
+    import torch
+    from paper_2302_12519_amd.adjoint import activation_time_loss
+    inst, tstar, _, _ = small
+    say("case adjoint forward only")
+    L, gr, used = gpu_adjoint(P, inst, tstar, "f32")
+    g = P.Grid.from_instance(dict_inst(inst, "f32"))
+    L2, g2, used2 = g.adjoint_scale(tstar, STEPS, 0, grad=False)
+    v_a = g.read("v")
+    g.close()
+    assert g2 is None and L2 == L and used2 == used
+    g = P.Grid.from_instance(dict_inst(inst, "f32"))
+    g.step(STEPS)
+    assert np.array_equal(g.read("v"), v_a)
+    s = torch.tensor(inst.scale, dtype=torch.float64, device="cuda")   # no grad
+    loss = activation_time_loss(g, s, inst.fibre, inst.sigma_l, inst.sigma_t, tstar, STEPS)
+    g.close()
+    assert loss.item() == L and not loss.requires_grad
+
+
 def test_adjoint_errors(P, small):
     inst, tstar, _, _ = small
     ep = P.ep
