@@ -925,11 +925,15 @@ ep_status adjoint_impl(ep_grid g, int32_t nsteps, int32_t K, const double* tstar
                        double* loss, double* grad_box, int64_t* n_used) {
   const int64_t nv = g->nvox;
   const size_t vb = static_cast<size_t>(nv) * sizeof(T);
-  const int S = (nsteps + K - 1) / K;
+  // without grad_box only the forward run and the loss: no checkpoints
+  const bool want_grad = grad_box != nullptr;
+  const int S = want_grad ? (nsteps + K - 1) / K : 0;
   // work block: grad (FP64), cross, T*, lv/lw ping-pong, checkpoints, segment
-  const size_t n_arr = 1 + 4 + 3 * static_cast<size_t>(S) + 2 * (static_cast<size_t>(K) + 1);
+  const size_t n_arr =
+      want_grad ? 1 + 4 + 3 * static_cast<size_t>(S) + 2 * (static_cast<size_t>(K) + 1) : 1;
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  const size_t need = al(nv * sizeof(double)) + al(nv * sizeof(int)) + n_arr * al(vb);
+  const size_t need =
+      (want_grad ? al(nv * sizeof(double)) : 0) + al(nv * sizeof(int)) + n_arr * al(vb);
   if (need > g->adj_cap) {
     if (g->d_adj && !g->adj_in_arena) {
       HIPCHK(g, hipStreamSynchronize(g->stream));
@@ -964,20 +968,28 @@ ep_status adjoint_impl(ep_grid g, int32_t nsteps, int32_t K, const double* tstar
     off += al(b);
     return p;
   };
-  double* d_grad = static_cast<double*>(take(nv * sizeof(double)));
+  double* d_grad = want_grad ? static_cast<double*>(take(nv * sizeof(double))) : nullptr;
   int* d_cross = static_cast<int*>(take(nv * sizeof(int)));
   T* d_tstar = static_cast<T*>(take(vb));
-  T* lv[2] = {static_cast<T*>(take(vb)), static_cast<T*>(take(vb))};
-  T* lw[2] = {static_cast<T*>(take(vb)), static_cast<T*>(take(vb))};
-  std::vector<T*> ck_v(S), ck_w(S), ck_vp(S), seg_v(K + 1), seg_w(K + 1);
-  for (int c = 0; c < S; ++c) {
-    ck_v[c] = static_cast<T*>(take(vb));
-    ck_w[c] = static_cast<T*>(take(vb));
-    ck_vp[c] = static_cast<T*>(take(vb));
-  }
-  for (int i = 0; i <= K; ++i) {
-    seg_v[i] = static_cast<T*>(take(vb));
-    seg_w[i] = static_cast<T*>(take(vb));
+  T* lv[2] = {nullptr, nullptr};
+  T* lw[2] = {nullptr, nullptr};
+  std::vector<T*> ck_v(S), ck_w(S), ck_vp(S), seg_v, seg_w;
+  if (want_grad) {
+    for (int i = 0; i < 2; ++i) {
+      lv[i] = static_cast<T*>(take(vb));
+      lw[i] = static_cast<T*>(take(vb));
+    }
+    for (int c = 0; c < S; ++c) {
+      ck_v[c] = static_cast<T*>(take(vb));
+      ck_w[c] = static_cast<T*>(take(vb));
+      ck_vp[c] = static_cast<T*>(take(vb));
+    }
+    seg_v.resize(K + 1);
+    seg_w.resize(K + 1);
+    for (int i = 0; i <= K; ++i) {
+      seg_v[i] = static_cast<T*>(take(vb));
+      seg_w[i] = static_cast<T*>(take(vb));
+    }
   }
 
   // targets to brick layout (non-finite = no target; non-tissue = no target)
@@ -996,7 +1008,7 @@ ep_status adjoint_impl(ep_grid g, int32_t nsteps, int32_t K, const double* tstar
     HIPCHK(g, hipMemcpyAsync(d_tstar, ht.data(), vb, hipMemcpyHostToDevice, g->stream));
     HIPCHK(g, hipStreamSynchronize(g->stream));
   }
-  HIPCHK(g, hipMemsetAsync(d_grad, 0, nv * sizeof(double), g->stream));
+  if (want_grad) HIPCHK(g, hipMemsetAsync(d_grad, 0, nv * sizeof(double), g->stream));
   HIPCHK(g, hipMemsetAsync(d_cross, 0xff, nv * sizeof(int), g->stream));  // -1
   {
     std::vector<T> inf(nv, std::numeric_limits<T>::infinity());
@@ -1016,7 +1028,7 @@ ep_status adjoint_impl(ep_grid g, int32_t nsteps, int32_t K, const double* tstar
   // forward
   for (int32_t s = 0; s < nsteps; ++s) {
     const int cu = g->cur, nx = 1 - cu;
-    if (s % K == 0) {
+    if (want_grad && s % K == 0) {
       const int ci = s / K;
       HIPCHK(g, hipMemcpyAsync(ck_v[ci], g->d_v[cu], vb, hipMemcpyDeviceToDevice, g->stream));
       HIPCHK(g, hipMemcpyAsync(ck_w[ci], g->d_w[cu], vb, hipMemcpyDeviceToDevice, g->stream));
@@ -1051,6 +1063,10 @@ ep_status adjoint_impl(ep_grid g, int32_t nsteps, int32_t K, const double* tstar
   }
   *loss = g->hs->sums[0];
   *n_used = static_cast<int64_t>(g->hs->sums[1] + 0.5);
+  if (!want_grad) {
+    timer_collect(g);
+    return EP_OK;
+  }
 
   // backward: lambda_N from the crossings of the last step
   int a = 0;
@@ -1827,7 +1843,7 @@ EP_API ep_status ep_adjoint_scale(ep_grid g, int32_t nsteps, int32_t ckpt_every,
                                   const double* tstar, double* loss, double* grad,
                                   int64_t* n_used) {
   if (!g) return EP_ERR_ARG;
-  if (!tstar || !loss || !grad || !n_used) return fail(g, EP_ERR_ARG, "NULL argument");
+  if (!tstar || !loss || !n_used) return fail(g, EP_ERR_ARG, "NULL argument");
   if (nsteps < 1) return fail(g, EP_ERR_ARG, "nsteps must be >= 1");
   if (ckpt_every < 0) return fail(g, EP_ERR_ARG, "ckpt_every must be >= 0");
   if (g->model != EP_MONO || g->diff != EP_DIFF_EXPLICIT)
