@@ -276,27 +276,50 @@ def bench_serving(count, K=16, n_err=3):
 
 
 def bench_plain_fp64(steps=1000):
-    """Plain monodomain 32^3 FP64 box (dt 0.01, 1000 steps): microseconds per
-    step of the fused explicit kernel; this size is launch-bound."""
+    """Plain monodomain 32^3 FP64 box (dt 0.01, 1000 steps from rest, the
+    stimulus on for the first 1 ms): microseconds per step with several
+    steps per cooperative launch (the library's default at this size) and
+    with one launch per step, each the median of 3 timed runs after a
+    warm-up run; the multi-step result's error against the oracle."""
     import ep_inputs as E
     import torch
     from paper_2302_12519_amd import Grid
     inst = E.plain_box(32, steps=steps, prec="f64")
-    g = Grid.from_instance(inst)
-    g.step(10)
-    torch.cuda.synchronize()
-    t = time.perf_counter()
-    g.step(steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t
-    g.close()
-    # accuracy: the same 1000 steps from rest against the oracle
-    g = Grid.from_instance(inst)
-    g.step(steps)
-    err = oracle_run_error(inst, {"v": g.read("v"), "tact": g.read("tact")}, steps)
-    g.close()
-    return {"us_per_step": 1e6 * dt / steps, "voxel_steps_per_s": inst.nt * steps / dt,
-            "err_vs_oracle": err}
+    out = {}
+    for name, spl in (("multistep", 0), ("one_launch_per_step", 1)):
+        g = Grid.from_instance(inst, steps_per_launch=spl)
+        times = []
+        for rep in range(4):
+            g.write("v", np.zeros(inst.n))
+            g.write("w", np.ones(inst.n))
+            g.write("tact", np.full(inst.n, np.inf))
+            g.step_index = 0
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            g.step(steps)
+            torch.cuda.synchronize()
+            if rep:
+                times.append(time.perf_counter() - t)
+        dt = float(np.median(times))
+        res = {"us_per_step": 1e6 * dt / steps, "voxel_steps_per_s": inst.nt * steps / dt}
+        if spl == 0:
+            g.kernel_timing(kernels=["multistep"])
+            g.write("v", np.zeros(inst.n))
+            g.write("w", np.ones(inst.n))
+            g.write("tact", np.full(inst.n, np.inf))
+            g.step_index = 0
+            g.step(steps)
+            ms, launches = g.kernel_time("multistep")
+            res["launches"] = launches
+            res["kernel_us_per_step"] = 1e3 * ms / steps
+            res["err_vs_oracle"] = oracle_run_error(
+                inst, {"v": g.read("v"), "tact": g.read("tact")}, steps)
+        g.close()
+        out[name] = res
+    out["us_per_step"] = out["multistep"]["us_per_step"]
+    out["voxel_steps_per_s"] = out["multistep"]["voxel_steps_per_s"]
+    out["err_vs_oracle"] = out["multistep"]["err_vs_oracle"]
+    return out
 
 
 def bench_jacobi(n, steps=200, sweeps=(4, 10)):

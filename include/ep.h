@@ -174,6 +174,18 @@ typedef struct {
                                 walks more bricks.  0: as many as stay
                                 resident (512 or 768 on MI355X).  Other
                                 values: EP_ERR_ARG */
+  int32_t steps_per_launch;  /* EP_MONO + EP_DIFF_EXPLICIT: a grid whose bricks
+                                all fit on the device at once (a few hundred
+                                8x8x8 bricks; ep_grid_stats' n_bricks) runs a
+                                stretch of steps under one stimulus state in
+                                one cooperative launch (v* exchanged through
+                                global memory, one grid-wide barrier per
+                                step), with bitwise the results of one
+                                launch per step.  0 (default): at most 4096 steps per
+                                launch; 1: one launch per step; k > 1: at
+                                most k steps per launch.  Ignored by other
+                                grids and by ep_batch_submit.  Negative:
+                                EP_ERR_ARG */
 } ep_grid_desc;
 
 typedef struct {
@@ -362,7 +374,9 @@ EP_API ep_status ep_grid_stats(ep_grid g, int64_t* n_tissue, int64_t* n_bricks,
  * step; 7: the implicit-Euler solve's last launch, which only applies the
  * last x update, or the update launch of an elliptic inner iteration (x, r,
  * p, s and the brick sums of r); 8: the coarse correction of an elliptic
- * inner iteration (aggregate sums and the GEMV with the coarse inverse). */
+ * inner iteration (aggregate sums and the GEMV with the coarse inverse);
+ * 9: a multi-step explicit launch (several steps, see steps_per_launch;
+ * explicit steps that run one per launch count under 0). */
 EP_API ep_status ep_kernel_timing(ep_grid g, int32_t enable);
 EP_API ep_status ep_kernel_time(ep_grid g, int32_t kernel_id, double* total_ms,
                                 int64_t* launches);

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libep_hip.so")
-SOURCES = ["ep_kernels.hip", "ep_runtime.hip", "ep_batch.hip", "ep_stream.hip"]
+SOURCES = ["ep_kernels.hip", "ep_multistep.hip", "ep_runtime.hip", "ep_batch.hip",
+           "ep_stream.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -149,6 +149,23 @@ void launch_explicit(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* 
                      const T* w, const T* jstim, T* vout, T* wout, T* tact,
                      IonicT<T> ion, T dt, T theta, double tn, int* flags, int* cross, int step);
 
+// ---- several explicit steps per launch (ep_multistep.hip) -----------------
+// Workgroups of the multi-step kernel that fit on the device at once (0: no
+// cooperative launch); a grid with at most this many bricks can use it.
+template <typename T>
+int explicit_ms_capacity();
+// nsteps explicit steps from step0 in one cooperative launch of nb
+// workgroups (one brick each, one grid-wide barrier per step).  vin/win may
+// alias vout/wout; xa, xb: (nb + 1) * 512 exchange arrays with a zero ghost
+// brick; count: the barrier's arrival counter (cleared here, eagerly);
+// flags[0]: non-finite potential, flags[2]: a barrier wait timed out.
+template <typename T>
+hipError_t launch_explicit_ms(hipStream_t st, int nb, const int* nbr, CoefSet<T> c,
+                              const T* vin, const T* win, const T* jstim, T* vout, T* wout,
+                              T* tact, T* xa, T* xb, IonicT<T> ion, T dt, T theta, double dt64,
+                              long long step0, int nsteps, double* qacc, const double* qstep,
+                              double qscale, unsigned* count, int* flags);
+
 template <typename T>
 void launch_ionic(const LaunchCfg& L, const T* v, const T* w, const T* jstim, T* vs,
                   T* wout, IonicT<T> ion, T dt);

@@ -51,7 +51,10 @@ constexpr int kPredOrder = 4;
 constexpr int kDRing = 3;
 
 enum { KT_STENCIL = 0, KT_CGSETUP = 1, KT_PARABOLIC = 2, KT_RESID = 3, KT_CGTAIL = 4,
-       KT_ADJ = 5, KT_INIT = 6, KT_UPDATE = 7, KT_COARSE = 8, kTimers = 9 };
+       KT_ADJ = 5, KT_INIT = 6, KT_UPDATE = 7, KT_COARSE = 8, KT_MULTI = 9, kTimers = 10 };
+// explicit monodomain grids that fit one co-resident launch run at most this
+// many steps per launch (a stimulus switching on or off ends a launch too)
+constexpr int kMsMaxSteps = 4096;
 // the two-level preconditioner keeps at most this many aggregates (the dense
 // inverse is kMaxAgg^2 FP32); aggregates are cubes of 1, 2, 4, ... bricks
 constexpr int kMaxAgg = 8192;
@@ -152,7 +155,12 @@ struct ep_grid_s {
   double* d_partials = nullptr;   // per-block partial sums of one-brick-per-block launches
   double* d_cgp[2] = {nullptr, nullptr};  // persistent CG launches: ping-pong partials
   CGScalars* d_cg = nullptr;      // two solver-scalar records, ping-pong
-  int* d_flags = nullptr;
+  int* d_flags = nullptr;       // [0] non-finite v, [2] a multi-step barrier timed out
+  // explicit monodomain, small grids: several steps per cooperative launch
+  bool ms_on = false;
+  int steps_per_launch = 0;    // caller's cap (0: kMsMaxSteps, 1: one step per launch)
+  void* d_xms[2] = {nullptr, nullptr};  // v* exchange arrays (state precision)
+  unsigned* d_bar = nullptr;   // grid-barrier arrival counter
   double* d_sums = nullptr;    // 8 doubles
   double* d_qacc = nullptr;
   double* d_qstep = nullptr;
@@ -427,9 +435,11 @@ ep_status build_stimuli(ep_grid g) {
 }
 
 // Refresh the stimulus current field for step `step`; returns the field
-// pointer, or nullptr when no stimulus is active.
+// pointer, or nullptr when no stimulus is active.  With accum, the step's
+// injected charge is added to the call's total by a launch here (the
+// multi-step kernel adds it itself).
 template <typename T>
-ep_status update_stimulus(ep_grid g, int64_t step, const T** jstim) {
+ep_status update_stimulus(ep_grid g, int64_t step, const T** jstim, bool accum = true) {
   *jstim = nullptr;
   if (g->stim_u.empty()) return EP_OK;
   const double tn = static_cast<double>(step) * g->dt;
@@ -456,10 +466,31 @@ ep_status update_stimulus(ep_grid g, int64_t step, const T** jstim) {
     g->stim_built = true;
   }
   if (any) {
-    launch_q_accum(g->stream, g->d_qacc, g->d_qstep, g->dt * g->h * g->h * g->h);
+    if (accum) launch_q_accum(g->stream, g->d_qacc, g->d_qstep, g->dt * g->h * g->h * g->h);
     *jstim = static_cast<const T*>(g->d_jstim);
   }
   return EP_OK;
+}
+
+// Steps from `step` (at most `avail`) over which the set of active stimuli
+// stays what it is at `step`.
+int stim_run(const ep_grid g, int64_t step, int avail) {
+  if (g->stim_u.empty()) return avail;
+  auto on = [&](int64_t st, const ep_stim& s) {
+    const double tn = static_cast<double>(st) * g->dt;
+    return s.t_on <= tn && tn < s.t_off;
+  };
+  int m = 1;
+  for (; m < avail; ++m) {
+    bool same = true;
+    for (const ep_stim& s : g->stims)
+      if (on(step + m, s) != on(step, s)) {
+        same = false;
+        break;
+      }
+    if (!same) break;
+  }
+  return m;
 }
 
 // Wait until the CG status word shows launch `seq` and return it.  Spins on
@@ -551,6 +582,35 @@ ep_status step_explicit(ep_grid g, const T* jstim) {
                      static_cast<T>(g->dt), static_cast<T>(g->theta),
                      static_cast<double>(g->step) * g->dt, g->d_flags, nullptr, 0);
   timer_end(g, t0);
+  return EP_OK;
+}
+
+// Several explicit steps in one cooperative launch (grids whose bricks all
+// fit on the device at once): as many as stay under one stimulus state, at
+// most `avail`; *taken reports how many.
+template <typename T>
+ep_status step_explicit_ms(ep_grid g, int32_t avail, int32_t* taken) {
+  const int cap = g->steps_per_launch > 1 ? g->steps_per_launch : kMsMaxSteps;
+  const int m = std::min(stim_run(g, g->step, avail), cap);
+  const T* jstim = nullptr;
+  TRY(update_stimulus<T>(g, g->step, &jstim, /*accum=*/m < 2));
+  if (m < 2) {
+    TRY(step_explicit<T>(g, jstim));
+    *taken = 1;
+    return EP_OK;
+  }
+  const int c = g->cur, n = (g->cur + m) & 1;
+  TimerPair* tp = timer_begin(g, KT_MULTI);
+  const hipError_t e = launch_explicit_ms<T>(
+      g->stream, g->nb, g->d_nbr, coefs<T>(g), static_cast<const T*>(g->d_v[c]),
+      static_cast<const T*>(g->d_w[c]), jstim, static_cast<T*>(g->d_v[n]),
+      static_cast<T*>(g->d_w[n]), static_cast<T*>(g->d_tact), static_cast<T*>(g->d_xms[0]),
+      static_cast<T*>(g->d_xms[1]), ionic_t<T>(g), static_cast<T>(g->dt),
+      static_cast<T>(g->theta), g->dt, static_cast<long long>(g->step), m, g->d_qacc,
+      jstim ? g->d_qstep : nullptr, g->dt * g->h * g->h * g->h, g->d_bar, g->d_flags);
+  timer_end(g, tp);
+  HIPCHK(g, e);
+  *taken = m;
   return EP_OK;
 }
 
@@ -854,6 +914,15 @@ ep_status run_steps(ep_grid g, int32_t nsteps, ep_step_info* info) {
   HIPCHK(g, hipMemsetAsync(g->d_qacc, 0, sizeof(double), g->stream));
   g->hs->flags[1] = 0;
   for (int32_t s = 0; s < nsteps; ++s) {
+    if (g->ms_on) {
+      int32_t m = 1;
+      TRY(step_explicit_ms<T>(g, nsteps - s, &m));
+      g->cur = (g->cur + m) & 1;
+      g->step += m;
+      g->have_prev = true;
+      s += m - 1;
+      continue;
+    }
     const T* jstim = nullptr;
     TRY(update_stimulus<T>(g, g->step, &jstim));
     if (g->model == EP_BIDO) {
@@ -891,7 +960,7 @@ ep_status run_steps(ep_grid g, int32_t nsteps, ep_step_info* info) {
                            g->stream));
   HIPCHK(g, hipMemcpyAsync(&g->hs->qacc, g->d_qacc, sizeof(double), hipMemcpyDeviceToHost,
                            g->stream));
-  HIPCHK(g, hipMemcpyAsync(g->hs->flags, g->d_flags, sizeof(int), hipMemcpyDeviceToHost,
+  HIPCHK(g, hipMemcpyAsync(g->hs->flags, g->d_flags, 4 * sizeof(int), hipMemcpyDeviceToHost,
                            g->stream));
   const bool be = g->model == EP_MONO && g->diff == EP_DIFF_BE_PCG && nsteps > 0 && g->last_cg;
   if (be)
@@ -907,6 +976,15 @@ ep_status run_steps(ep_grid g, int32_t nsteps, ep_step_info* info) {
   acc.q_stim = g->hs->qacc;
   acc.mass = h3 * g->hs->sums[3];
   if (info) *info = acc;
+  if (g->hs->flags[2]) {
+    // cannot happen with a cooperative launch; should it, the grid goes back
+    // to one launch per step and the state of this call is not to be used
+    g->ms_on = false;
+    g->hs->flags[2] = 0;
+    HIPCHK(g, hipMemsetAsync(g->d_flags + 2, 0, sizeof(int), g->stream));
+    HIPCHK(g, hipStreamSynchronize(g->stream));
+    return fail(g, EP_ERR_HIP, "a grid-wide barrier of the multi-step kernel timed out");
+  }
   if (g->hs->flags[0]) g->nonfinite = true;
   if (g->nonfinite) return fail(g, EP_ERR_NONFINITE, "non-finite potential");
   if (noconv) return fail(g, EP_ERR_NOCONV, "a linear solve hit its iteration limit");
@@ -1324,6 +1402,7 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   // 512-thread blocks fit per CU
   g->Le = g->L;
   g->Le.pgrid = std::min(g->grid, 3 * 256);
+  if (d->steps_per_launch < 0) return fail(g, EP_ERR_ARG, "steps_per_launch must be >= 0");
   if (d->persistent_blocks != 0) {
     if (d->persistent_blocks < 0 || d->persistent_blocks % kXcd != 0)
       return fail(g, EP_ERR_ARG, "persistent_blocks must be 0 or a positive multiple of 8");
@@ -1381,6 +1460,16 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   }
   if (g->model == EP_MONO && g->diff == EP_DIFF_EXPLICIT)
     for (int k = 0; k < 6; ++k) TRY(dalloc(g, &g->d_d0[k], vb));
+  g->steps_per_launch = d->steps_per_launch;
+  if (g->model == EP_MONO && g->diff == EP_DIFF_EXPLICIT && d->steps_per_launch != 1) {
+    const int cap = g->prec == EP_F64 ? explicit_ms_capacity<double>()
+                                      : explicit_ms_capacity<float>();
+    if (nb <= cap) {
+      for (int k = 0; k < 2; ++k) TRY(dalloc(g, &g->d_xms[k], vb));
+      TRY(dalloc(g, &g->d_bar, sizeof(unsigned)));
+      g->ms_on = true;
+    }
+  }
   if (g->model == EP_BIDO) {
     const size_t b64 = static_cast<size_t>(g->nvox) * sizeof(double);
     const size_t b32 = static_cast<size_t>(g->nvox) * sizeof(float);

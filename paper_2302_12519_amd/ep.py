@@ -30,7 +30,7 @@ EP_MONO, EP_BIDO = 0, 1
 EP_DIFF_EXPLICIT, EP_DIFF_BE_PCG, EP_DIFF_BE_JACOBI, EP_DIFF_EXPLICIT27 = 0, 1, 2, 3
 FIELDS = {"v": 0, "w": 1, "phi": 2, "tact": 3}
 KERNELS = {"stencil": 0, "cg_setup": 1, "parabolic": 2, "resid": 3, "cg_tail": 4, "adjoint": 5,
-           "be_init": 6, "cg_update": 7, "coarse": 8}
+           "be_init": 6, "cg_update": 7, "coarse": 8, "multistep": 9}
 
 
 class EPError(RuntimeError):
@@ -59,7 +59,7 @@ class GridDesc(C.Structure):
                 ("ell_max_outer", C.c_int32), ("ell_inner_maxit", C.c_int32),
                 ("stream", C.c_void_p), ("arena", C.c_void_p), ("arena_bytes", C.c_int64),
                 ("bath", C.c_void_p), ("sig_bath", C.c_double), ("ell_precond", C.c_int32),
-                ("persistent_blocks", C.c_int32)]
+                ("persistent_blocks", C.c_int32), ("steps_per_launch", C.c_int32)]
 
 
 class StepInfo(C.Structure):
@@ -152,7 +152,7 @@ def make_desc(n, h, dt, mask=None, model="mono", prec="f32", diff="explicit", io
               stims=(), theta=0.5, pcg_rtol=1e-6, pcg_maxit=50, ell_rtol=1e-8,
               ell_max_outer=8, ell_inner_maxit=4000, stream=None, arena=None,
               jacobi_sweeps=10, bath=None, sig_bath=0.0, ell_precond=0,
-              persistent_blocks=0):
+              persistent_blocks=0, steps_per_launch=0):
     """Fill an ep_grid_desc; returns it and the arrays it points into (keep
     them alive while the descriptor is used).  arena: optional caller-owned
     device memory, a torch CUDA tensor whose bytes the grid carves its
@@ -213,6 +213,7 @@ def make_desc(n, h, dt, mask=None, model="mono", prec="f32", diff="explicit", io
         d.sig_bath = float(sig_bath)
     d.ell_precond = int(ell_precond)
     d.persistent_blocks = int(persistent_blocks)
+    d.steps_per_launch = int(steps_per_launch)
     return d, keep
 
 
@@ -233,11 +234,12 @@ class Grid:
                  ionic=None, stims=(), theta=0.5, pcg_rtol=1e-6, pcg_maxit=50,
                  ell_rtol=1e-8, ell_max_outer=8, ell_inner_maxit=4000, stream=None,
                  arena=None, jacobi_sweeps=10, bath=None, sig_bath=0.0, ell_precond=0,
-                 persistent_blocks=0):
+                 persistent_blocks=0, steps_per_launch=0):
         self._desc, keep = make_desc(n, h, dt, mask, model, prec, diff, ionic, stims, theta,
                                      pcg_rtol, pcg_maxit, ell_rtol, ell_max_outer,
                                      ell_inner_maxit, stream, arena, jacobi_sweeps, bath,
-                                     sig_bath, ell_precond, persistent_blocks)
+                                     sig_bath, ell_precond, persistent_blocks,
+                                     steps_per_launch)
         self._keep = keep
         self.n = tuple(int(k) for k in n)
         self.N = int(np.prod(self.n))
