@@ -174,18 +174,19 @@ typedef struct {
                                 walks more bricks.  0: as many as stay
                                 resident (512 or 768 on MI355X).  Other
                                 values: EP_ERR_ARG */
-  int32_t steps_per_launch;  /* EP_MONO + EP_DIFF_EXPLICIT: a grid whose bricks
-                                all fit on the device at once (a few hundred
-                                8x8x8 bricks; ep_grid_stats' n_bricks) runs a
-                                stretch of steps under one stimulus state in
-                                one cooperative launch (v* exchanged through
-                                global memory, one grid-wide barrier per
-                                step), with bitwise the results of one
-                                launch per step.  0 (default): at most 4096 steps per
-                                launch; 1: one launch per step; k > 1: at
-                                most k steps per launch.  Ignored by other
-                                grids and by ep_batch_submit.  Negative:
-                                EP_ERR_ARG */
+  int32_t steps_per_launch;  /* EP_MONO + EP_DIFF_EXPLICIT on a grid of at
+                                most 128 8x8x8 bricks (ep_grid_stats'
+                                n_bricks; beyond that one launch per step is
+                                faster) whose bricks all fit on the device at
+                                once: a stretch of steps under one stimulus
+                                state runs in one cooperative launch (v*
+                                exchanged through global memory, one
+                                grid-wide barrier per step), with bitwise the
+                                results of one launch per step.  0
+                                (default): at most 4096 steps per launch; 1:
+                                one launch per step; k > 1: at most k steps
+                                per launch.  Ignored by other grids and by
+                                ep_batch_submit.  Negative: EP_ERR_ARG */
 } ep_grid_desc;
 
 typedef struct {
@@ -378,6 +379,12 @@ EP_API ep_status ep_grid_stats(ep_grid g, int64_t* n_tissue, int64_t* n_bricks,
  * 9: a multi-step explicit launch (several steps, see steps_per_launch;
  * explicit steps that run one per launch count under 0). */
 EP_API ep_status ep_kernel_timing(ep_grid g, int32_t enable);
+/* Time only the launches of the steps whose index (ep_get_step) is a
+ * multiple of `steps` (1, the default: every step), so that a long run can
+ * be timed on a sample of its steps without an event pair around every
+ * launch (each pair delays the launch that follows by several us).  Kept
+ * across ep_kernel_timing calls.  Errors: EP_ERR_ARG (steps < 1). */
+EP_API ep_status ep_kernel_timing_period(ep_grid g, int32_t steps);
 EP_API ep_status ep_kernel_time(ep_grid g, int32_t kernel_id, double* total_ms,
                                 int64_t* launches);
 

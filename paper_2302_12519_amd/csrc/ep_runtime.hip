@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -55,6 +56,12 @@ enum { KT_STENCIL = 0, KT_CGSETUP = 1, KT_PARABOLIC = 2, KT_RESID = 3, KT_CGTAIL
 // explicit monodomain grids that fit one co-resident launch run at most this
 // many steps per launch (a stimulus switching on or off ends a launch too)
 constexpr int kMsMaxSteps = 4096;
+// ... and only grids of at most this many bricks: the grid-wide barrier's
+// cost grows with the workgroups that meet at it, and beyond about 128 of
+// them one launch per step is faster (measured on MI355X: 64 bricks 3.3
+// against 4.6 us per step in FP64; 152 bricks 4.5 against 4.8; 312 bricks
+// 10.2 against 6.2)
+constexpr int kMsMaxBricks = 128;
 // the two-level preconditioner keeps at most this many aggregates (the dense
 // inverse is kMaxAgg^2 FP32); aggregates are cubes of 1, 2, 4, ... bricks
 constexpr int kMaxAgg = 8192;
@@ -195,8 +202,10 @@ struct ep_grid_s {
   int last_inner = 50;
   std::string err;
 
-  // timing: bit k set = launches of kernel id k are bracketed by events
+  // timing: bit k set = launches of kernel id k are bracketed by events,
+  // in the steps whose index is a multiple of timing_period
   uint32_t timing = 0;
+  int timing_period = 1;
   size_t tused[kTimers] = {};
   std::vector<TimerPair> tk[kTimers];
   double tms[kTimers] = {};
@@ -348,11 +357,22 @@ IonicT<T> ionic_t(const ep_grid g) {
 }
 
 // ---- timing ---------------------------------------------------------------
+// launches of the current step are timed (every step, or a sample of them)
+bool timing_step(const ep_grid g) {
+  return g->timing_period <= 1 || g->step % g->timing_period == 0;
+}
+
 TimerPair* timer_begin(ep_grid g, int id) {
-  if (!((g->timing >> id) & 1u)) return nullptr;
+  if (!((g->timing >> id) & 1u) || !timing_step(g)) return nullptr;
   if (g->tused[id] == g->tk[id].size()) {
     TimerPair tp;
-    if (hipEventCreate(&tp.a) != hipSuccess || hipEventCreate(&tp.b) != hipSuccess) return nullptr;
+    // timing-only events: no system-scope fence (cache write-back and
+    // invalidation) when they complete, which would otherwise stall the
+    // launch that follows; the totals are read after a stream synchronize
+    constexpr unsigned kTimingEvent = hipEventDisableSystemFence;
+    if (hipEventCreateWithFlags(&tp.a, kTimingEvent) != hipSuccess ||
+        hipEventCreateWithFlags(&tp.b, kTimingEvent) != hipSuccess)
+      return nullptr;
     g->tk[id].push_back(tp);
   }
   TimerPair* tp = &g->tk[id][g->tused[id]++];
@@ -366,7 +386,7 @@ void timer_end(ep_grid g, TimerPair* tp) {
 
 // move the last `count` pairs recorded under `from` to `to`
 void timer_retag(ep_grid g, int from, int to, int count) {
-  if (!g->timing) return;
+  if (!g->timing || !timing_step(g)) return;
   for (int i = 0; i < count && g->tused[from] > 0; ++i) {
     TimerPair tp = g->tk[from][--g->tused[from]];
     g->tk[from].erase(g->tk[from].begin() + static_cast<long>(g->tused[from]));
@@ -493,23 +513,34 @@ int stim_run(const ep_grid g, int64_t step, int avail) {
   return m;
 }
 
-// Wait until the CG status word shows launch `seq` and return it.  Spins on
-// the coherent host word; every 1024 spins it checks the stream, and should
-// the stream drain without the word (it never should), the device copy of
-// the scalars (`dev`) is read instead.
+// Wait until the CG status word shows launch `seq` (or a later one) and
+// return it.  Spins on the coherent host word and makes no HIP call on the
+// way: with a stream query every 1024 spins, the profiler showed a 6 us
+// gap before every launch queued while the host waited.  Only after 5 ms
+// without the word (far longer than any CG launch) does it check the
+// stream, and should the stream have drained without the word (it never
+// should), the device copy of the scalars (`dev`) is read instead.
 ep_status wait_status(ep_grid g, unsigned seq, const CGScalars* dev, unsigned long long* out) {
+  // launch numbers increase by one per CG launch (modulo 2^32); a later
+  // launch's word serves too (`done` and the iteration count carry over)
+  auto reached = [seq](unsigned long long v) {
+    return static_cast<int>(static_cast<unsigned>(v >> 32) - seq) >= 0;
+  };
+  using clock = std::chrono::steady_clock;
+  auto next_check = clock::now() + std::chrono::milliseconds(5);
   for (uint64_t spin = 1;; ++spin) {
     const unsigned long long v = *g->hmirror;
-    if (static_cast<unsigned>(v >> 32) == seq) {
+    if (reached(v)) {
       *out = v;
       return EP_OK;
     }
-    if ((spin & 1023) == 0) {
+    if ((spin & 1023) == 0 && clock::now() >= next_check) {
+      next_check = clock::now() + std::chrono::milliseconds(5);
       const hipError_t e = hipStreamQuery(g->stream);
       if (e == hipErrorNotReady) continue;
       if (e != hipSuccess) return fail(g, EP_ERR_HIP, std::string("CG wait: ") + hipGetErrorString(e));
       const unsigned long long w = *g->hmirror;
-      if (static_cast<unsigned>(w >> 32) == seq) {
+      if (reached(w)) {
         *out = w;
         return EP_OK;
       }
@@ -529,9 +560,11 @@ ep_status wait_status(ep_grid g, unsigned seq, const CGScalars* dev, unsigned lo
 // zb[0], x0 in x).  Launch k reads scalars / partials [k & 1] and writes
 // [(k + 1) & 1]; it reads z_{k-1} from zb[(k - 1) & 1] (z_0 from zb[0]) and
 // writes z_k to zb[k & 1], and p_k, t_k to pb[k & 1], tb[k & 1].  Each
-// launch publishes its convergence test as it starts, so after launches 0
-// and 1 the host queues one launch at a time while the last one runs its
-// stencil; the launch that finds the solve done does only the last x update.
+// launch publishes its convergence test as it starts, so the host queues
+// the next launch while the current one runs its stencil (launches 0 and 1
+// go together); the launch that finds the solve done does only the last x
+// update.  (Keeping two launches queued instead measured the same: the
+// extra launch after the last update cost what it saved.)
 template <typename T>
 ep_status pcg_step_solve(ep_grid g, CoefSet<T> c, T c0, T c1, T* x, T* const zb[2],
                          T* const pb[2], T* const tb[2], int maxit, int* iters, bool* failed) {
@@ -547,13 +580,16 @@ ep_status pcg_step_solve(ep_grid g, CoefSet<T> c, T c0, T c1, T* x, T* const zb[
     timer_end(g, t0);
     ++n;
   };
+  const int last = maxit + 1;      // launches 0 .. maxit + 1 at most
   int k = 0;
   launch(k++);
+  launch(k++);
+  const unsigned seq1 = g->seq;    // launch number of launch 1
   unsigned long long st = 0;
-  for (;;) {
-    launch(k++);
-    TRY(wait_status(g, g->seq, cg + (k & 1), &st));
-    if ((st & 1) || k >= maxit + 2) break;
+  for (int w = 1;; ++w) {
+    if (w > 1 && k <= last) launch(k++);   // launch w, queued behind w - 1
+    TRY(wait_status(g, seq1 + static_cast<unsigned>(w - 1), cg + ((w + 1) & 1), &st));
+    if ((st & 1) || w >= last) break;
   }
   const int it = static_cast<int>((st >> 2) & 0x3fffffff);
   *iters = it;
@@ -1464,7 +1500,7 @@ ep_status create_impl(const ep_grid_desc* d, ep_grid g) {
   if (g->model == EP_MONO && g->diff == EP_DIFF_EXPLICIT && d->steps_per_launch != 1) {
     const int cap = g->prec == EP_F64 ? explicit_ms_capacity<double>()
                                       : explicit_ms_capacity<float>();
-    if (nb <= cap) {
+    if (nb <= std::min(cap, kMsMaxBricks)) {
       for (int k = 0; k < 2; ++k) TRY(dalloc(g, &g->d_xms[k], vb));
       TRY(dalloc(g, &g->d_bar, sizeof(unsigned)));
       g->ms_on = true;
@@ -2098,6 +2134,12 @@ EP_API ep_status ep_kernel_timing(ep_grid g, int32_t enable) {
     g->tcount[k] = 0;
     g->tused[k] = 0;
   }
+  return EP_OK;
+}
+
+EP_API ep_status ep_kernel_timing_period(ep_grid g, int32_t steps) {
+  if (!g || steps < 1) return EP_ERR_ARG;
+  g->timing_period = steps;
   return EP_OK;
 }
 

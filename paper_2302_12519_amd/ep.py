@@ -107,6 +107,7 @@ def _load():
                                   C.POINTER(C.c_int64)]
     lib.ep_kernel_timing.argtypes = [vp, C.c_int32]
     lib.ep_kernel_time.argtypes = [vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    lib.ep_kernel_timing_period.argtypes = [vp, C.c_int32]
     lib.ep_adjoint_scale.argtypes = [vp, C.c_int32, C.c_int32, vp, C.POINTER(C.c_double), vp,
                                      C.POINTER(C.c_int64)]
     lib.ep_stream_bandwidth.argtypes = [C.c_int64, C.c_int32, C.POINTER(C.c_double),
@@ -133,7 +134,8 @@ def _load():
                  "ep_read_state", "ep_read_state_device", "ep_write_state", "ep_ecg_leads",
                  "ep_get_step",
                  "ep_set_step",
-                 "ep_grid_stats", "ep_kernel_timing", "ep_kernel_time", "ep_destroy_grid",
+                 "ep_grid_stats", "ep_kernel_timing", "ep_kernel_timing_period",
+                 "ep_kernel_time", "ep_destroy_grid",
                  "ep_adjoint_scale", "ep_stream_bandwidth",
                  "ep_batch_create", "ep_batch_submit", "ep_batch_advance", "ep_batch_finished",
                  "ep_batch_read", "ep_batch_release", "ep_batch_get_stats", "ep_batch_destroy"):
@@ -372,9 +374,11 @@ class Grid:
         self._check(lib.ep_ecg_leads(self._h, _p(e), _p(out)), "ep_ecg_leads")
         return out
 
-    def kernel_timing(self, enable=True, kernels=None):
+    def kernel_timing(self, enable=True, kernels=None, every=1):
         """Time launches with HIP events: all kernels, or only those named in
-        `kernels` (keys of KERNELS); resets the totals."""
+        `kernels` (keys of KERNELS), in every step or (every > 1) only in
+        the steps whose index is a multiple of `every`; resets the totals."""
+        self._check(lib.ep_kernel_timing_period(self._h, int(every)), "ep_kernel_timing_period")
         if not enable:
             mask = 0
         elif kernels is None:

@@ -97,3 +97,31 @@ def test_bidomain_bath_grid_in_caller_arena(P):
     with pytest.raises(P.EPError) as e:
         P.Grid.from_instance(inst, arena=small)
     assert e.value.status == P.ep.EP_ERR_OOM
+
+
+def test_kernel_timing_on_a_sample_of_steps(P):
+    """ep_kernel_timing_period: with a period of 4 only the launches of steps
+    whose index is a multiple of 4 are timed, each implicit step's launches
+    keep their roles (one init, one set-up and one last-update launch per
+    timed step), and the results do not change."""
+    inst = be_shell(17, prec="f32")
+    say("case kernel timing period")
+    runs = {}
+    for every in (1, 4):
+        g = P.Grid.from_instance(inst)
+        g.step(3)                                    # steps 0..2
+        g.kernel_timing(True, every=every)
+        g.step(12)                                   # steps 3..14: 4, 8, 12 sampled
+        counts = {k: g.kernel_time(k)[1] for k in ("be_init", "cg_setup", "cg_update",
+                                                   "stencil")}
+        runs[every] = (counts, g.read("v"))
+        g.close()
+    full, sampled = runs[1][0], runs[4][0]
+    assert full["be_init"] == full["cg_setup"] == full["cg_update"] == 12
+    assert sampled["be_init"] == sampled["cg_setup"] == sampled["cg_update"] == 3
+    assert 0 <= sampled["stencil"] < full["stencil"]
+    assert np.array_equal(runs[1][1], runs[4][1])
+    g = P.Grid.from_instance(inst)
+    with pytest.raises(P.EPError):
+        g.kernel_timing(True, every=0)
+    g.close()

@@ -22,8 +22,9 @@ def _kernels():
 
 
 def test_there_are_summaries():
-    assert any(f.startswith("k_be_init") for f in FILES)
-    assert any(f.startswith("traffic_k_be_init") for f in FILES)
+    assert "k_pcg_step_aniso_be_256.txt" in FILES
+    assert "traffic_k_pcg_step_aniso_be_256.txt" in FILES
+    assert "traffic_k_be_init_aniso_be_256.txt" in FILES
 
 
 @pytest.mark.parametrize("name", FILES)
@@ -38,7 +39,7 @@ def test_summary_is_short_text_with_its_command(name):
 
 @pytest.mark.parametrize("name", FILES)
 def test_summary_names_a_defined_kernel(name):
-    m = re.search(r"(k_[a-z0-9]+(?:_[a-z0-9]+)*?)_(?:aniso|bidomain|adjoint|serving|plain)",
+    m = re.search(r"(k_[a-z0-9]+(?:_[a-z0-9]+)*?)_(?:aniso|bidomain|adjoint|serving|plain|cuboid)",
                   name)
     assert m, name
     assert m.group(1) in _kernels(), (name, m.group(1))
