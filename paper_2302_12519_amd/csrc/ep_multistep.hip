@@ -124,8 +124,14 @@ __global__ __launch_bounds__(kBV) void k_explicit_ms(
   at(wout, q.g) = w;
   if (crossed) at(tact, q.g) = ta;
   if (bad) flags[0] = 1;
-  if (qstep && blockIdx.x == 0 && threadIdx.x == 0)
-    for (int k = 0; k < nsteps; ++k) qacc[0] += qscale * qstep[0];
+  if (qstep && blockIdx.x == 0 && threadIdx.x == 0) {
+    // the per-step launches' additions, in registers: each is one fused
+    // multiply-add, as k_q_accum compiles to
+    const double q0 = qstep[0];
+    double a = qacc[0];
+    for (int k = 0; k < nsteps; ++k) a = fma(qscale, q0, a);
+    qacc[0] = a;
+  }
 }
 
 template <typename T>
