@@ -182,3 +182,15 @@ def test_single_tissue_voxel_and_zero_steps(P, orc):
     o.run(100)
     assert np.abs(g.read("v") - o.field("v")).max() <= 1e-12 * max(np.abs(o.field("v")).max(), 1)
     g.close()
+
+
+def test_grid_beyond_the_voxel_limit_refused(P):
+    """The kernels address per-voxel arrays with 32-bit byte offsets, so a
+    grid is limited to 2^29 stored voxels: an all-tissue 816^3 box (102^3
+    bricks, 543M stored voxels) is refused with EP_ERR_UNSUPPORTED before
+    any device memory is taken (an 800^3 box, 512M voxels, would fit)."""
+    say("case 816^3 box beyond the voxel limit")
+    ion = E.plain_box(8, steps=1, prec="f32").ionic
+    with pytest.raises(P.EPError) as e:
+        P.Grid((816, 816, 816), 0.25, 0.01, ionic=ion)
+    assert e.value.status == P.ep.EP_ERR_UNSUPPORTED

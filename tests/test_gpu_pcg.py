@@ -6,7 +6,9 @@ launch that finds the solve done applying the last x update):
   initial guess goes through every order it uses;
 - a solve that is done before its first iteration (zero right-hand side);
 - the iteration limit, reported as EP_ERR_NOCONV;
-- bitwise reproducibility of FP32 runs (fixed-order reductions).
+- bitwise reproducibility of FP32 runs (fixed-order reductions), also when
+  the steps are split over several calls;
+- the activation check of steps whose guess already solves the system.
 """
 import numpy as np
 import pytest
@@ -115,3 +117,53 @@ def test_be_pcg_fp32_bitwise_reproducible(P):
     assert np.array_equal(v1, v2) and np.array_equal(w1, w2)
     assert np.array_equal(t1, t2, equal_nan=True)
 
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_be_pcg_activation_when_the_guess_solves(P, orc, prec):
+    """A uniform state has no diffusion, so every step's initial guess solves
+    the system and no launch makes a last x update.  From v = 0.45, w = 1
+    the reaction carries every voxel across theta = 0.5 during step 4; T_act
+    must match the oracle's on every voxel."""
+    inst = be_shell(17, n_stim=0, prec=prec)
+    say(f"case shell_17 {prec} BE-PCG uniform state crossing threshold")
+    m = inst.mask.astype(np.float64)
+    g = P.Grid.from_instance(inst)
+    o = orc.Oracle(inst)
+    g.write("v", 0.45 * m)
+    g.write("w", m)
+    o.set_state(v=0.45 * m, w=m)
+    info = g.step(8)
+    o.run(8)
+    T, To = g.read("tact"), o.field("tact")
+    v = g.read("v")
+    g.close()
+    tis = inst.mask > 0
+    tol = 1e-12 if prec == "f64" else 1e-6
+    assert info["cg_iters"] == 0
+    assert np.isfinite(To[tis]).all() and np.isfinite(T[tis]).all()
+    assert np.abs(T[tis] - To[tis]).max() <= tol
+    assert np.abs(v - o.field("v")).max() <= tol
+
+
+def test_be_pcg_split_calls_bitwise(P):
+    """The solver state carried between steps (the extrapolation history, the
+    activation check of each step) does not depend on how the steps are
+    grouped into calls: 60 FP32 steps in one call and in six calls of ten
+    give bitwise the same v, w and T_act."""
+    inst = E.aniso_be(40, steps=60)
+    inst.pcg_rtol = 1e-7
+    say("case aniso_be_40 fp32 one call against six")
+    out = []
+    for calls in (1, 6):
+        g = P.Grid.from_instance(inst)
+        it = 0
+        for _ in range(calls):
+            it += g.step(60 // calls)["cg_iters"]
+        out.append((g.read("v"), g.read("w"), g.read("tact"), it))
+        g.close()
+    (v1, w1, t1, i1), (v2, w2, t2, i2) = out
+    assert i1 == i2
+    assert np.isfinite(t1).sum() > 0
+    assert np.array_equal(v1, v2) and np.array_equal(w1, w2)
+    assert np.array_equal(t1, t2, equal_nan=True)
