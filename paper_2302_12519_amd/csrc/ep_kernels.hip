@@ -1019,6 +1019,259 @@ template <typename T> struct Quad {
   typedef T V __attribute__((ext_vector_type(4)));
 };
 
+// ---------------------------------------------------------------------------
+// Pipelined brick loop of the FP32 CG iteration.  A block's next brick is
+// staged into LDS by direct global-to-LDS loads while the current brick is
+// computed, so its load latency overlaps that work instead of following it:
+//   own cells of z, t, p, x and of the six weight arrays (lane order = the
+//   brick's voxel order), the 480 halo cells of z and t (halo_cell order),
+//   and the 600 weights of cells on the brick's -x, -y, -z sides that the
+//   19-point operator of its own voxels uses (the weight halo, below).
+// Every staged value is the one gather18 / cell_setup would load (rows
+// without tissue read the ghost brick's zeros), and the arithmetic is the
+// general iteration's, so the results are bitwise those of the one-brick-
+// at-a-time loop.  A brick's outputs are stored one stage later, after the
+// next staging loads are issued, so that the wait for a stage does not also
+// wait for the stores just issued.
+// A stage is one flat LDS array, so that every access to it has the same
+// underlying object and the compiler can tell the stage being read from the
+// one being filled.
+// Weight halo: CX on the x = -1 plane (y*8+z), CY on y = -1 (x*8+z), CZ on
+// z = -1 (x*8+y); then 136 entries for each edge weight:
+//   CXY: x = -1 plane (y*8+z), y = -1 plane (x*8+z), the (-1,-1,z) edge;
+//   CXZ: x = -1 (y*8+z), z = -1 (x*8+y), the (-1,y,-1) edge;
+//   CYZ: y = -1 (x*8+z), z = -1 (x*8+y), the (x,-1,-1) edge.
+constexpr int kStZ = 0, kStT = 512, kStP = 1024, kStX = 1536, kStW = 2048;   // own cells
+constexpr int kStHZ = 5120, kStHT = 5632;                                    // halo cells
+constexpr int kStWH = 6144;                                                  // weight halo
+constexpr int kWhCX = 0, kWhCY = 64, kWhCZ = 128, kWhCXY = 192, kWhCXZ = 328, kWhCYZ = 464;
+constexpr int kStage = kStWH + 600;
+
+// entry m of weight array a's halo: coordinates relative to the brick
+__device__ __forceinline__ void wh_coords(int a, int m, int& tx, int& ty, int& tz) {
+  const int i = (m >> 3) & 7, j = m & 7, e = m - 128;
+  switch (a) {
+    case CX: tx = -1; ty = i; tz = j; break;
+    case CY: tx = i; ty = -1; tz = j; break;
+    case CZ: tx = i; ty = j; tz = -1; break;
+    case CXY:
+      if (m < 64) { tx = -1; ty = i; tz = j; }
+      else if (m < 128) { tx = i; ty = -1; tz = j; }
+      else { tx = -1; ty = -1; tz = e; }
+      break;
+    case CXZ:
+      if (m < 64) { tx = -1; ty = i; tz = j; }
+      else if (m < 128) { tx = i; ty = j; tz = -1; }
+      else { tx = -1; ty = e; tz = -1; }
+      break;
+    default:   // CYZ
+      if (m < 64) { tx = i; ty = -1; tz = j; }
+      else if (m < 128) { tx = i; ty = j; tz = -1; }
+      else { tx = e; ty = -1; tz = -1; }
+  }
+}
+
+// gather18's weights from a staged brick F (flat stage)
+__device__ __forceinline__ void gather18_lds(const float* F, int t, int lx, int ly, int lz,
+                                             float k[18]) {
+  constexpr int W = kStW, H = kStWH;
+  k[0] = F[W + CX * kBV + t];
+  k[1] = F[lx ? W + CX * kBV + t - 64 : H + kWhCX + ly * 8 + lz];
+  k[2] = F[W + CY * kBV + t];
+  k[3] = F[ly ? W + CY * kBV + t - 8 : H + kWhCY + lx * 8 + lz];
+  k[4] = F[W + CZ * kBV + t];
+  k[5] = F[lz ? W + CZ * kBV + t - 1 : H + kWhCZ + lx * 8 + ly];
+  k[6] = F[W + CXY * kBV + t];
+  k[7] = F[(lx && ly) ? W + CXY * kBV + t - 72
+           : (!lx && !ly) ? H + kWhCXY + 128 + lz
+           : !lx ? H + kWhCXY + (ly - 1) * 8 + lz : H + kWhCXY + 64 + (lx - 1) * 8 + lz];
+  k[8] = F[ly ? W + CXY * kBV + t - 8 : H + kWhCXY + 64 + lx * 8 + lz];
+  k[9] = F[lx ? W + CXY * kBV + t - 64 : H + kWhCXY + ly * 8 + lz];
+  k[10] = F[W + CXZ * kBV + t];
+  k[11] = F[(lx && lz) ? W + CXZ * kBV + t - 65
+            : (!lx && !lz) ? H + kWhCXZ + 128 + ly
+            : !lx ? H + kWhCXZ + ly * 8 + (lz - 1) : H + kWhCXZ + 64 + (lx - 1) * 8 + ly];
+  k[12] = F[lz ? W + CXZ * kBV + t - 1 : H + kWhCXZ + 64 + lx * 8 + ly];
+  k[13] = F[lx ? W + CXZ * kBV + t - 64 : H + kWhCXZ + ly * 8 + lz];
+  k[14] = F[W + CYZ * kBV + t];
+  k[15] = F[(ly && lz) ? W + CYZ * kBV + t - 9
+            : (!ly && !lz) ? H + kWhCYZ + 128 + lx
+            : !ly ? H + kWhCYZ + lx * 8 + (lz - 1) : H + kWhCYZ + 64 + lx * 8 + (ly - 1)];
+  k[16] = F[lz ? W + CYZ * kBV + t - 1 : H + kWhCYZ + 64 + lx * 8 + ly];
+  k[17] = F[ly ? W + CYZ * kBV + t - 8 : H + kWhCYZ + lx * 8 + lz];
+}
+
+// one direct global-to-LDS dword load per active lane: lane i of the wave
+// writes dst[i] (dst the same in every lane of the wave)
+template <bool NT>
+__device__ __forceinline__ void lds_load(const float* base, int i, float* dst) {
+  const float* src = reinterpret_cast<const float*>(
+      reinterpret_cast<const char*>(base) +
+      static_cast<uint64_t>(static_cast<uint32_t>(i) * 4u));
+  __builtin_amdgcn_global_load_lds(src, dst, 4, 0, NT ? 2 : 0);
+}
+
+// weight-halo entries [m0, m0 + n) of array a, one per lane from lane l0 on
+__device__ __forceinline__ void wh_load(float* F, const float* base, int a, int m0, int off,
+                                        int lane, int l0, int n, int nb, const int* nbs,
+                                        const uint64_t* rowm) {
+  if (lane < l0 || lane >= l0 + n) return;
+  const int m = m0 + lane - l0;
+  int tx, ty, tz;
+  wh_coords(a, m, tx, ty, tz);
+  const int ox = tx < 0 ? 0 : 1, oy = ty < 0 ? 0 : 1, oz = tz < 0 ? 0 : 1;
+  const int g = vox_live(rowm, tx, ty, tz)
+                    ? nbs[ox * 9 + oy * 3 + oz] * kBV + (((tx & 7) * 8 + (ty & 7)) * 8 + (tz & 7))
+                    : nb * kBV + lane;
+  lds_load<false>(base, g, F + off + m0 - l0);
+}
+
+// issue the staging loads of `brick` (table nbs / rowm in LDS) into F
+template <bool NT>
+__device__ __forceinline__ void pcg_stage(float* F, int brick, int nb, const int* nbs,
+                                          const uint64_t* rowm, const CoefSet<float>& c,
+                                          const float* x, const float* z_in, const float* p_in,
+                                          const float* t_in) {
+  const int t = threadIdx.x, w0 = t & ~63, lane = t & 63, wave = t >> 6;
+  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
+  const int gl = vox_live(rowm, lx, ly, lz) ? brick * kBV + t : nb * kBV + t;
+  lds_load<false>(z_in, gl, F + kStZ + w0);
+  lds_load<false>(t_in, gl, F + kStT + w0);
+  lds_load<false>(p_in, gl, F + kStP + w0);
+  lds_load<NT>(x, gl, F + kStX + w0);
+#pragma unroll
+  for (int a = 0; a < 6; ++a) lds_load<false>(c.c[a], gl, F + kStW + a * kBV + w0);
+  if (t < kHalo) {
+    int hx, hy, hz;
+    halo_cell(t, hx, hy, hz);
+    const int hgl = vox_live(rowm, hx - 1, hy - 1, hz - 1) ? tile_global(nbs, hx, hy, hz)
+                                                            : nb * kBV + t;
+    lds_load<false>(z_in, hgl, F + kStHZ + w0);
+    lds_load<false>(t_in, hgl, F + kStHT + w0);
+  }
+  // the weight halo, one array per wave (wave-uniform bases)
+  const int H = kStWH;
+  switch (wave) {
+    case 0:
+      wh_load(F, c.c[CX], CX, 0, H + kWhCX, lane, 0, 64, nb, nbs, rowm);
+      wh_load(F, c.c[CYZ], CYZ, 64, H + kWhCYZ, lane, 0, 64, nb, nbs, rowm);
+      break;
+    case 1:
+      wh_load(F, c.c[CY], CY, 0, H + kWhCY, lane, 0, 64, nb, nbs, rowm);
+      wh_load(F, c.c[CXY], CXY, 128, H + kWhCXY, lane, 0, 8, nb, nbs, rowm);
+      wh_load(F, c.c[CXZ], CXZ, 128, H + kWhCXZ, lane, 8, 8, nb, nbs, rowm);
+      wh_load(F, c.c[CYZ], CYZ, 128, H + kWhCYZ, lane, 16, 8, nb, nbs, rowm);
+      break;
+    case 2: wh_load(F, c.c[CZ], CZ, 0, H + kWhCZ, lane, 0, 64, nb, nbs, rowm); break;
+    case 3: wh_load(F, c.c[CXY], CXY, 0, H + kWhCXY, lane, 0, 64, nb, nbs, rowm); break;
+    case 4: wh_load(F, c.c[CXY], CXY, 64, H + kWhCXY, lane, 0, 64, nb, nbs, rowm); break;
+    case 5: wh_load(F, c.c[CXZ], CXZ, 0, H + kWhCXZ, lane, 0, 64, nb, nbs, rowm); break;
+    case 6: wh_load(F, c.c[CXZ], CXZ, 64, H + kWhCXZ, lane, 0, 64, nb, nbs, rowm); break;
+    default: wh_load(F, c.c[CYZ], CYZ, 0, H + kWhCYZ, lane, 0, 64, nb, nbs, rowm);
+  }
+}
+
+// The general CG iteration's brick loop, pipelined (see pcg_stage): alpha,
+// beta from this launch's scalars; partials as the one-brick-at-a-time loop.
+template <bool NT>
+__device__ __forceinline__ void pcg_iter_pipelined(
+    int nb, const int* __restrict__ nbr, const uint64_t* __restrict__ rowsn,
+    const CoefSet<float>& c, float c0, float c1, float alpha, float beta,
+    float* __restrict__ x, const float* __restrict__ z_in, float* __restrict__ z_out,
+    const float* __restrict__ p_in, float* __restrict__ p_out, const float* __restrict__ t_in,
+    float* __restrict__ t_out, double* parts) {
+  __shared__ float S0[kStage], S1[kStage];
+  __shared__ float s[kTile];
+  __shared__ int nbt[2][kNbr];
+  __shared__ uint64_t rowt[2][kNbr];
+  const int t = threadIdx.x;
+  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
+  const int C = tidx(lx + 1, ly + 1, lz + 1);
+  int hC = 0;
+  if (t < kHalo) {
+    int hx, hy, hz;
+    halo_cell(t, hx, hy, hz);
+    hC = tidx(hx, hy, hz);
+  }
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  NbrAhead ahead;
+  // outputs of the previous brick, stored one stage later
+  int pend_brick = -1;   // the same in every thread
+  bool pend = false;
+  float ox = 0.f, oz = 0.f, op = 0.f, ot = 0.f;
+  int cur = pbrick(0, nb);
+  ahead.fetch(nbr, rowsn, cur);
+  ahead.stage(nbt[0], rowt[0]);
+  __syncthreads();
+  if (cur >= 0) pcg_stage<NT>(S0, cur, nb, nbt[0], rowt[0], c, x, z_in, p_in, t_in);
+  ahead.fetch(nbr, rowsn, pbrick(1, nb));
+  // one brick: S holds its stage, N receives the next brick's
+  auto brick_step = [&](const float* S, float* N, int m) -> bool {
+    if (cur < 0) return false;
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's staging loads have landed
+    __syncthreads();                 // every wave's; the previous brick is done with LDS
+    const bool live = vox_live(rowt[m & 1], lx, ly, lz);
+    const float tg = S[kStT + t];
+    const float zn = S[kStZ + t] - alpha * tg;
+    s[C] = zn;
+    if (t < kHalo) s[hC] = S[kStHZ + t] - alpha * S[kStHT + t];
+    ahead.stage(nbt[(m + 1) & 1], rowt[(m + 1) & 1]);
+    __syncthreads();
+    const int nxt = pbrick(m + 1, nb);
+    if (nxt >= 0)
+      pcg_stage<NT>(N, nxt, nb, nbt[(m + 1) & 1], rowt[(m + 1) & 1], c, x, z_in, p_in, t_in);
+    ahead.fetch(nbr, rowsn, pbrick(m + 2, nb));
+    if (pend) {
+      const int g = pend_brick * kBV + t;
+      st_stream<NT>(&at(x, g), ox);
+      st_stream<NT>(&at(z_out, g), oz);
+      st_stream<NT>(&at(p_out, g), op);
+      st_stream<NT>(&at(t_out, g), ot);
+    }
+    float k18[18];
+    gather18_lds(S, t, lx, ly, lz, k18);
+    if (!live) {
+#pragma unroll
+      for (int i = 0; i < 18; ++i) k18[i] = 0.f;
+    }
+    const float pg = S[kStP + t], xg = S[kStX + t];
+    // q_k = K p_k = K z_k + beta q_{k-1}, with q_{k-1} = M t_{k-1}
+    const float md = c0 + c1 * diag19(k18);
+    const float qn = (c0 * zn + c1 * apply19(s, C, k18)) + beta * (md * tg);
+    const float pn = zn + beta * pg;
+    const float tn = qn / md;
+    const float rn = md * zn;
+    pend = live;
+    pend_brick = cur;
+    ox = xg + alpha * pg;
+    oz = zn;
+    op = pn;
+    ot = tn;
+    const double dr = rn, dz = zn, dp = pn, dq = qn;
+    acc[0] += dp * dq;
+    acc[1] += dr * dz;
+    acc[2] += dq * dz;
+    acc[3] += dq * static_cast<double>(tn);
+    acc[4] += dr * dr;
+    acc[5] += dq * dr;
+    acc[6] += dq * dq;
+    cur = nxt;
+    return true;
+  };
+  for (int m = 0;; m += 2) {
+    if (!brick_step(S0, S1, m)) break;
+    if (!brick_step(S1, S0, m + 1)) break;
+  }
+  if (pend) {
+    const int g = pend_brick * kBV + t;
+    st_stream<NT>(&at(x, g), ox);
+    st_stream<NT>(&at(z_out, g), oz);
+    st_stream<NT>(&at(p_out, g), op);
+    st_stream<NT>(&at(t_out, g), ot);
+  }
+  block_partials<7>(acc, parts);
+}
+
 // Jacobi-PCG with one launch per iteration and no set-up apply: the
 // textbook recurrences, with the next residual's two norms, (r, z) and
 // (r, r), expanded in dot products of the previous launch's own vectors, so
@@ -1045,7 +1298,7 @@ template <typename T> struct Quad {
 // next launch, so a launch writes the other buffer of each pair; x is
 // updated in place.
 template <typename T, bool NT>
-__global__ __launch_bounds__(kBV) void k_pcg_step(
+__global__ __launch_bounds__(kBV) __attribute__((amdgpu_waves_per_eu(4))) void k_pcg_step(
     int nb, const int* __restrict__ nbr, CoefSet<T> c, T c0, T c1, T* __restrict__ x,
     const T* __restrict__ z_in, T* __restrict__ z_out, const T* __restrict__ p_in,
     T* __restrict__ p_out, const T* __restrict__ t_in, T* __restrict__ t_out, int first,
@@ -1128,6 +1381,13 @@ __global__ __launch_bounds__(kBV) void k_pcg_step(
     return;
   }
   if (st.done) return;
+  if constexpr (sizeof(T) == 4) {
+    if (!first) {
+      pcg_iter_pipelined<NT>(nb, nbr, rowsn, c, c0, c1, alpha, beta, x, z_in, z_out, p_in,
+                             p_out, t_in, t_out, parts);
+      return;
+    }
+  }
   __shared__ T s[kTile];
   __shared__ int nbt[2][kNbr];
   __shared__ uint64_t rowt[2][kNbr];
