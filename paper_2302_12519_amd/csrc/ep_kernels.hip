@@ -511,6 +511,431 @@ __global__ __launch_bounds__(kBV) void k_ionic(int nb, const T* __restrict__ v,
 //   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
 // so its three dot products share one reduction.
 
+// ---------------------------------------------------------------------------
+// Pipelined brick loop of the FP32 CG iteration.  A block's next brick is
+// staged into LDS by direct global-to-LDS loads while the current brick is
+// computed, so its load latency overlaps that work instead of following it:
+//   own cells of z, t, p, x and of the six weight arrays (lane order = the
+//   brick's voxel order), the 480 halo cells of z and t (halo_cell order),
+//   and the 600 weights of cells on the brick's -x, -y, -z sides that the
+//   19-point operator of its own voxels uses (the weight halo, below).
+// Every staged value is the one gather18 / cell_setup would load (rows
+// without tissue read the ghost brick's zeros), and the arithmetic is the
+// general iteration's, so the results are bitwise those of the one-brick-
+// at-a-time loop.  A brick's outputs are stored one stage later, after the
+// next staging loads are issued, so that the wait for a stage does not also
+// wait for the stores just issued.
+// A stage is one flat LDS array, so that every access to it has the same
+// underlying object and the compiler can tell the stage being read from the
+// one being filled.
+// Weight halo: CX on the x = -1 plane (y*8+z), CY on y = -1 (x*8+z), CZ on
+// z = -1 (x*8+y); then 136 entries for each edge weight:
+//   CXY: x = -1 plane (y*8+z), y = -1 plane (x*8+z), the (-1,-1,z) edge;
+//   CXZ: x = -1 (y*8+z), z = -1 (x*8+y), the (-1,y,-1) edge;
+//   CYZ: y = -1 (x*8+z), z = -1 (x*8+y), the (x,-1,-1) edge.
+constexpr int kStZ = 0, kStT = 512, kStP = 1024, kStX = 1536, kStW = 2048;   // own cells
+constexpr int kStHZ = 5120, kStHT = 5632;                                    // halo cells
+constexpr int kStWH = 6144;                                                  // weight halo
+constexpr int kWhCX = 0, kWhCY = 64, kWhCZ = 128, kWhCXY = 192, kWhCXZ = 328, kWhCYZ = 464;
+constexpr int kStage = kStWH + 600;
+
+// entry m of weight array a's halo: coordinates relative to the brick
+__device__ __forceinline__ void wh_coords(int a, int m, int& tx, int& ty, int& tz) {
+  const int i = (m >> 3) & 7, j = m & 7, e = m - 128;
+  switch (a) {
+    case CX: tx = -1; ty = i; tz = j; break;
+    case CY: tx = i; ty = -1; tz = j; break;
+    case CZ: tx = i; ty = j; tz = -1; break;
+    case CXY:
+      if (m < 64) { tx = -1; ty = i; tz = j; }
+      else if (m < 128) { tx = i; ty = -1; tz = j; }
+      else { tx = -1; ty = -1; tz = e; }
+      break;
+    case CXZ:
+      if (m < 64) { tx = -1; ty = i; tz = j; }
+      else if (m < 128) { tx = i; ty = j; tz = -1; }
+      else { tx = -1; ty = e; tz = -1; }
+      break;
+    default:   // CYZ
+      if (m < 64) { tx = i; ty = -1; tz = j; }
+      else if (m < 128) { tx = i; ty = j; tz = -1; }
+      else { tx = e; ty = -1; tz = -1; }
+  }
+}
+
+// gather18's weights from a staged brick F (flat stage): the own cells of
+// the six weight arrays at W (array a at W + a * 512), the weight halo at H
+template <int W, int H>
+__device__ __forceinline__ void gather18_lds(const float* F, int t, int lx, int ly, int lz,
+                                             float k[18]) {
+  k[0] = F[W + CX * kBV + t];
+  k[1] = F[lx ? W + CX * kBV + t - 64 : H + kWhCX + ly * 8 + lz];
+  k[2] = F[W + CY * kBV + t];
+  k[3] = F[ly ? W + CY * kBV + t - 8 : H + kWhCY + lx * 8 + lz];
+  k[4] = F[W + CZ * kBV + t];
+  k[5] = F[lz ? W + CZ * kBV + t - 1 : H + kWhCZ + lx * 8 + ly];
+  k[6] = F[W + CXY * kBV + t];
+  k[7] = F[(lx && ly) ? W + CXY * kBV + t - 72
+           : (!lx && !ly) ? H + kWhCXY + 128 + lz
+           : !lx ? H + kWhCXY + (ly - 1) * 8 + lz : H + kWhCXY + 64 + (lx - 1) * 8 + lz];
+  k[8] = F[ly ? W + CXY * kBV + t - 8 : H + kWhCXY + 64 + lx * 8 + lz];
+  k[9] = F[lx ? W + CXY * kBV + t - 64 : H + kWhCXY + ly * 8 + lz];
+  k[10] = F[W + CXZ * kBV + t];
+  k[11] = F[(lx && lz) ? W + CXZ * kBV + t - 65
+            : (!lx && !lz) ? H + kWhCXZ + 128 + ly
+            : !lx ? H + kWhCXZ + ly * 8 + (lz - 1) : H + kWhCXZ + 64 + (lx - 1) * 8 + ly];
+  k[12] = F[lz ? W + CXZ * kBV + t - 1 : H + kWhCXZ + 64 + lx * 8 + ly];
+  k[13] = F[lx ? W + CXZ * kBV + t - 64 : H + kWhCXZ + ly * 8 + lz];
+  k[14] = F[W + CYZ * kBV + t];
+  k[15] = F[(ly && lz) ? W + CYZ * kBV + t - 9
+            : (!ly && !lz) ? H + kWhCYZ + 128 + lx
+            : !ly ? H + kWhCYZ + lx * 8 + (lz - 1) : H + kWhCYZ + 64 + lx * 8 + (ly - 1)];
+  k[16] = F[lz ? W + CYZ * kBV + t - 1 : H + kWhCYZ + 64 + lx * 8 + ly];
+  k[17] = F[ly ? W + CYZ * kBV + t - 8 : H + kWhCYZ + lx * 8 + lz];
+}
+
+// one direct global-to-LDS dword load per active lane: lane i of the wave
+// writes dst[i] (dst the same in every lane of the wave)
+template <bool NT>
+__device__ __forceinline__ void lds_load(const float* base, int i, float* dst) {
+  const float* src = reinterpret_cast<const float*>(
+      reinterpret_cast<const char*>(base) +
+      static_cast<uint64_t>(static_cast<uint32_t>(i) * 4u));
+  __builtin_amdgcn_global_load_lds(src, dst, 4, 0, NT ? 2 : 0);
+}
+
+// weight-halo entries [m0, m0 + n) of array a, one per lane from lane l0 on
+__device__ __forceinline__ void wh_load(float* F, const float* base, int a, int m0, int off,
+                                        int lane, int l0, int n, int nb, const int* nbs,
+                                        const uint64_t* rowm) {
+  if (lane < l0 || lane >= l0 + n) return;
+  const int m = m0 + lane - l0;
+  int tx, ty, tz;
+  wh_coords(a, m, tx, ty, tz);
+  const int ox = tx < 0 ? 0 : 1, oy = ty < 0 ? 0 : 1, oz = tz < 0 ? 0 : 1;
+  const int g = vox_live(rowm, tx, ty, tz)
+                    ? nbs[ox * 9 + oy * 3 + oz] * kBV + (((tx & 7) * 8 + (ty & 7)) * 8 + (tz & 7))
+                    : nb * kBV + lane;
+  lds_load<false>(base, g, F + off + m0 - l0);
+}
+
+// global index a halo thread t (< 480) loads: its halo cell, or the ghost
+// brick when the cell's row holds no tissue
+__device__ __forceinline__ int halo_index(int t, int nb, const int* nbs, const uint64_t* rowm) {
+  int hx, hy, hz;
+  halo_cell(t, hx, hy, hz);
+  return vox_live(rowm, hx - 1, hy - 1, hz - 1) ? tile_global(nbs, hx, hy, hz) : nb * kBV + t;
+}
+
+// stage the six weight arrays of a brick: own cells (index gl) at W, the
+// weight halo at H, one array per wave (wave-uniform bases)
+template <int W, int H>
+__device__ __forceinline__ void stage_weights(float* F, int gl, int nb, const int* nbs,
+                                              const uint64_t* rowm, const CoefSet<float>& c) {
+  const int t = threadIdx.x, w0 = t & ~63, lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) lds_load<false>(c.c[a], gl, F + W + a * kBV + w0);
+  switch (wave) {
+    case 0:
+      wh_load(F, c.c[CX], CX, 0, H + kWhCX, lane, 0, 64, nb, nbs, rowm);
+      wh_load(F, c.c[CYZ], CYZ, 64, H + kWhCYZ, lane, 0, 64, nb, nbs, rowm);
+      break;
+    case 1:
+      wh_load(F, c.c[CY], CY, 0, H + kWhCY, lane, 0, 64, nb, nbs, rowm);
+      wh_load(F, c.c[CXY], CXY, 128, H + kWhCXY, lane, 0, 8, nb, nbs, rowm);
+      wh_load(F, c.c[CXZ], CXZ, 128, H + kWhCXZ, lane, 8, 8, nb, nbs, rowm);
+      wh_load(F, c.c[CYZ], CYZ, 128, H + kWhCYZ, lane, 16, 8, nb, nbs, rowm);
+      break;
+    case 2: wh_load(F, c.c[CZ], CZ, 0, H + kWhCZ, lane, 0, 64, nb, nbs, rowm); break;
+    case 3: wh_load(F, c.c[CXY], CXY, 0, H + kWhCXY, lane, 0, 64, nb, nbs, rowm); break;
+    case 4: wh_load(F, c.c[CXY], CXY, 64, H + kWhCXY, lane, 0, 64, nb, nbs, rowm); break;
+    case 5: wh_load(F, c.c[CXZ], CXZ, 0, H + kWhCXZ, lane, 0, 64, nb, nbs, rowm); break;
+    case 6: wh_load(F, c.c[CXZ], CXZ, 64, H + kWhCXZ, lane, 0, 64, nb, nbs, rowm); break;
+    default: wh_load(F, c.c[CYZ], CYZ, 0, H + kWhCYZ, lane, 0, 64, nb, nbs, rowm);
+  }
+}
+
+// issue the staging loads of `brick` (table nbs / rowm in LDS) into F; the
+// first launch of a solve reads z alone (t, p, x are not yet formed)
+template <bool NT, bool FIRST>
+__device__ __forceinline__ void pcg_stage(float* F, int brick, int nb, const int* nbs,
+                                          const uint64_t* rowm, const CoefSet<float>& c,
+                                          const float* x, const float* z_in, const float* p_in,
+                                          const float* t_in) {
+  const int t = threadIdx.x, w0 = t & ~63;
+  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
+  const int gl = vox_live(rowm, lx, ly, lz) ? brick * kBV + t : nb * kBV + t;
+  lds_load<false>(z_in, gl, F + kStZ + w0);
+  if constexpr (!FIRST) {
+    lds_load<false>(t_in, gl, F + kStT + w0);
+    lds_load<false>(p_in, gl, F + kStP + w0);
+    lds_load<NT>(x, gl, F + kStX + w0);
+  }
+  if (t < kHalo) {
+    const int hgl = halo_index(t, nb, nbs, rowm);
+    lds_load<false>(z_in, hgl, F + kStHZ + w0);
+    if constexpr (!FIRST) lds_load<false>(t_in, hgl, F + kStHT + w0);
+  }
+  stage_weights<kStW, kStWH>(F, gl, nb, nbs, rowm, c);
+}
+
+// The CG launches' brick loop, pipelined (see pcg_stage): alpha, beta from
+// this launch's scalars; partials as the one-brick-at-a-time loop.  FIRST:
+// launch 0 (t, p, x taken as zero, only p and t stored).
+// S0, S1: the two stages (kStage floats each); s: the tile; nbt, rowt: the
+// double-buffered neighbour table and row masks (2 x kNbr each).
+template <bool NT, bool FIRST>
+__device__ __forceinline__ void pcg_iter_pipelined(
+    float* S0, float* S1, float* s, int (*nbt)[kNbr], uint64_t (*rowt)[kNbr], int nb,
+    const int* __restrict__ nbr, const uint64_t* __restrict__ rowsn,
+    const CoefSet<float>& c, float c0, float c1, float alpha, float beta,
+    float* __restrict__ x, const float* __restrict__ z_in, float* __restrict__ z_out,
+    const float* __restrict__ p_in, float* __restrict__ p_out, const float* __restrict__ t_in,
+    float* __restrict__ t_out, double* parts) {
+  const int t = threadIdx.x;
+  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
+  const int C = tidx(lx + 1, ly + 1, lz + 1);
+  int hC = 0;
+  if (t < kHalo) {
+    int hx, hy, hz;
+    halo_cell(t, hx, hy, hz);
+    hC = tidx(hx, hy, hz);
+  }
+  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  NbrAhead ahead;
+  // outputs of the previous brick, stored one stage later
+  int pend_brick = -1;   // the same in every thread
+  bool pend = false;
+  float ox = 0.f, oz = 0.f, op = 0.f, ot = 0.f;
+  int cur = pbrick(0, nb);
+  ahead.fetch(nbr, rowsn, cur);
+  ahead.stage(nbt[0], rowt[0]);
+  __syncthreads();
+  if (cur >= 0) pcg_stage<NT, FIRST>(S0, cur, nb, nbt[0], rowt[0], c, x, z_in, p_in, t_in);
+  ahead.fetch(nbr, rowsn, pbrick(1, nb));
+  // one brick: S holds its stage, N receives the next brick's
+  auto brick_step = [&](const float* S, float* N, int m) -> bool {
+    if (cur < 0) return false;
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's staging loads have landed
+    __syncthreads();                 // every wave's; the previous brick is done with LDS
+    const bool live = vox_live(rowt[m & 1], lx, ly, lz);
+    const float tg = FIRST ? 0.f : S[kStT + t];
+    const float zn = S[kStZ + t] - alpha * tg;
+    s[C] = zn;
+    if (t < kHalo) s[hC] = S[kStHZ + t] - alpha * (FIRST ? 0.f : S[kStHT + t]);
+    ahead.stage(nbt[(m + 1) & 1], rowt[(m + 1) & 1]);
+    __syncthreads();
+    const int nxt = pbrick(m + 1, nb);
+    if (nxt >= 0)
+      pcg_stage<NT, FIRST>(N, nxt, nb, nbt[(m + 1) & 1], rowt[(m + 1) & 1], c, x, z_in, p_in,
+                           t_in);
+    ahead.fetch(nbr, rowsn, pbrick(m + 2, nb));
+    if (pend) {
+      const int g = pend_brick * kBV + t;
+      if constexpr (!FIRST) {
+        st_stream<NT>(&at(x, g), ox);
+        st_stream<NT>(&at(z_out, g), oz);
+      }
+      st_stream<NT>(&at(p_out, g), op);
+      st_stream<NT>(&at(t_out, g), ot);
+    }
+    float k18[18];
+    gather18_lds<kStW, kStWH>(S, t, lx, ly, lz, k18);
+    if (!live) {
+#pragma unroll
+      for (int i = 0; i < 18; ++i) k18[i] = 0.f;
+    }
+    const float pg = FIRST ? 0.f : S[kStP + t], xg = FIRST ? 0.f : S[kStX + t];
+    // q_k = K p_k = K z_k + beta q_{k-1}, with q_{k-1} = M t_{k-1}
+    const float md = c0 + c1 * diag19(k18);
+    const float qn = (c0 * zn + c1 * apply19(s, C, k18)) + beta * (md * tg);
+    const float pn = zn + beta * pg;
+    const float tn = qn / md;
+    const float rn = md * zn;
+    pend = live;
+    pend_brick = cur;
+    ox = xg + alpha * pg;
+    oz = zn;
+    op = pn;
+    ot = tn;
+    const double dr = rn, dz = zn, dp = pn, dq = qn;
+    acc[0] += dp * dq;
+    acc[1] += dr * dz;
+    acc[2] += dq * dz;
+    acc[3] += dq * static_cast<double>(tn);
+    acc[4] += dr * dr;
+    acc[5] += dq * dr;
+    acc[6] += dq * dq;
+    cur = nxt;
+    return true;
+  };
+  for (int m = 0;; m += 2) {
+    if (!brick_step(S0, S1, m)) break;
+    if (!brick_step(S1, S0, m + 1)) break;
+  }
+  if (pend) {
+    const int g = pend_brick * kBV + t;
+    if constexpr (!FIRST) {
+      st_stream<NT>(&at(x, g), ox);
+      st_stream<NT>(&at(z_out, g), oz);
+    }
+    st_stream<NT>(&at(p_out, g), op);
+    st_stream<NT>(&at(t_out, g), ot);
+  }
+  block_partials<7>(acc, parts);
+}
+
+// Stage of the pipelined init kernel (flat, floats): own cells of v, w, the
+// previous v, b_{n-1}, Q_n, d_{n-2}, d_{n-3} and the six weights, halo cells
+// (480 each) of v, w, b_{n-1}, Q_n, then the weight halo.  The stimulus
+// current, present only while a stimulus is on, is read directly.
+constexpr int kIV = 0, kIW = 512, kIVP = 1024, kIB1 = 1536, kIQ0 = 2048, kID2 = 2560,
+              kID3 = 3072, kIWt = 3584;
+constexpr int kIHV = 6656, kIHW = kIHV + kHalo, kIHB = kIHW + kHalo, kIHQ = kIHB + kHalo;
+constexpr int kIWH = kIHQ + kHalo;
+constexpr int kIStage = kIWH + 600;
+
+struct BeInitArgs {
+  const float *v, *w, *jstim, *bprev, *qin, *d2in, *d3in;
+  float *bout, *dout, *qout, *x, *wout, *z;
+  float kd, q2, q3, q4;
+  bool check_prev;
+};
+
+template <bool NT>
+__device__ __forceinline__ void be_init_stage(float* F, int brick, int nb, const int* nbs,
+                                              const uint64_t* rowm, const CoefSet<float>& c,
+                                              const BeInitArgs& A) {
+  const int t = threadIdx.x, w0 = t & ~63;
+  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
+  const int gl = vox_live(rowm, lx, ly, lz) ? brick * kBV + t : nb * kBV + t;
+  lds_load<false>(A.v, gl, F + kIV + w0);
+  lds_load<false>(A.w, gl, F + kIW + w0);
+  if (A.check_prev) lds_load<NT>(A.x, gl, F + kIVP + w0);
+  if (A.bprev) lds_load<false>(A.bprev, gl, F + kIB1 + w0);
+  if (A.qin) lds_load<false>(A.qin, gl, F + kIQ0 + w0);
+  if (A.d2in) lds_load<NT>(A.d2in, gl, F + kID2 + w0);
+  if (A.d3in) lds_load<NT>(A.d3in, gl, F + kID3 + w0);
+  if (t < kHalo) {
+    const int hgl = halo_index(t, nb, nbs, rowm);
+    lds_load<false>(A.v, hgl, F + kIHV + w0);
+    lds_load<false>(A.w, hgl, F + kIHW + w0);
+    if (A.bprev) lds_load<false>(A.bprev, hgl, F + kIHB + w0);
+    if (A.qin) lds_load<false>(A.qin, hgl, F + kIHQ + w0);
+  }
+  stage_weights<kIWt, kIWH>(F, gl, nb, nbs, rowm, c);
+}
+
+// k_be_init's brick loop, pipelined like the CG launches (see pcg_stage);
+// the arithmetic is the one-brick-at-a-time loop's, so the results are
+// bitwise the same.
+template <bool NT>
+__device__ __forceinline__ void be_init_pipelined(
+    float* S0, float* S1, float* s, int (*nbt)[kNbr], uint64_t (*rowt)[kNbr], int nb,
+    const int* __restrict__ nbr, const uint64_t* __restrict__ rowsn, const CoefSet<float>& c,
+    const BeInitArgs& A, const IonicT<float>& ion, float dt, float* __restrict__ tact,
+    float theta, double tprev, int* flags, double* parts) {
+  const int t = threadIdx.x;
+  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
+  const int C = tidx(lx + 1, ly + 1, lz + 1);
+  int hC = 0;
+  if (t < kHalo) {
+    int hx, hy, hz;
+    halo_cell(t, hx, hy, hz);
+    hC = tidx(hx, hy, hz);
+  }
+  double acc[2] = {0.0, 0.0};
+  NbrAhead ahead;
+  int pend_brick = -1;   // the same in every thread
+  bool pend = false;
+  float o_x = 0.f, o_b = 0.f, o_d = 0.f, o_q = 0.f, o_w = 0.f, o_z = 0.f;
+  int cur = pbrick(0, nb);
+  ahead.fetch(nbr, rowsn, cur);
+  ahead.stage(nbt[0], rowt[0]);
+  __syncthreads();
+  if (cur >= 0) be_init_stage<NT>(S0, cur, nb, nbt[0], rowt[0], c, A);
+  ahead.fetch(nbr, rowsn, pbrick(1, nb));
+  auto flush = [&]() {
+    if (!pend) return;
+    const int g = pend_brick * kBV + t;
+    st_stream<NT>(&at(A.x, g), o_x);
+    st_stream<NT>(&at(A.bout, g), o_b);
+    if (A.bprev) {
+      st_stream<NT>(&at(A.dout, g), o_d);
+      st_stream<NT>(&at(A.qout, g), o_q);
+    }
+    st_stream<NT>(&at(A.wout, g), o_w);
+    st_stream<NT>(&at(A.z, g), o_z);
+  };
+  auto brick_step = [&](const float* S, float* N, int m) -> bool {
+    if (cur < 0) return false;
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's staging loads have landed
+    __syncthreads();                 // every wave's; the previous brick is done with LDS
+    const uint64_t* rowm = rowt[m & 1];
+    const int* nbs = nbt[m & 1];
+    const bool live = vox_live(rowm, lx, ly, lz);
+    const int gl = live ? cur * kBV + t : nb * kBV + t;
+    const float v0 = S[kIV + t], w0 = S[kIW + t];
+    const float j0 = A.jstim ? at(A.jstim, gl) : 0.f;
+    const float b1 = A.bprev ? S[kIB1 + t] : 0.f;
+    const float q0 = A.qin ? S[kIQ0 + t] : 0.f;
+    float vs, ws;
+    ms_step(v0, w0, j0, ion, dt, vs, ws);
+    const float d1 = v0 - b1;
+    const float x0 = A.bprev ? vs + (A.kd * d1 + q0) : vs;
+    s[C] = x0;
+    if (t < kHalo) {
+      const float hv = S[kIHV + t], hw = S[kIHW + t];
+      const float hj = A.jstim ? at(A.jstim, halo_index(t, nb, nbs, rowm)) : 0.f;
+      const float hb1 = A.bprev ? S[kIHB + t] : 0.f;
+      const float hq = A.qin ? S[kIHQ + t] : 0.f;
+      float a, b;
+      ms_step(hv, hw, hj, ion, dt, a, b);
+      s[hC] = A.bprev ? a + (A.kd * (hv - hb1) + hq) : a;
+    }
+    ahead.stage(nbt[(m + 1) & 1], rowt[(m + 1) & 1]);
+    __syncthreads();
+    const int nxt = pbrick(m + 1, nb);
+    if (nxt >= 0) be_init_stage<NT>(N, nxt, nb, nbt[(m + 1) & 1], rowt[(m + 1) & 1], c, A);
+    ahead.fetch(nbr, rowsn, pbrick(m + 2, nb));
+    flush();
+    float k18[18];
+    gather18_lds<kIWt, kIWH>(S, t, lx, ly, lz, k18);
+    if (!live) {
+#pragma unroll
+      for (int i = 0; i < 18; ++i) k18[i] = 0.f;
+    }
+    const float rr = (vs - x0) + dt * apply19(s, C, k18);
+    // z0 = M^-1 r0, M the diagonal of I - dt A from this voxel's weights
+    const float z0 = rr / (1.f - dt * diag19(k18));
+    const float vp = A.check_prev ? S[kIVP + t] : 0.f;
+    if (A.check_prev && vp < theta && theta <= v0) {
+      const int g = cur * kBV + t;
+      if (isinf(at(tact, g))) at(tact, g) = static_cast<float>(tprev) + dt * (theta - vp) / (v0 - vp);
+    }
+    if (!isfinite(v0)) flags[0] = 1;
+    pend = live;
+    pend_brick = cur;
+    o_x = x0;
+    o_b = vs;
+    o_d = d1;
+    o_q = A.q2 * d1 + A.q3 * (A.d2in ? S[kID2 + t] : 0.f) + A.q4 * (A.d3in ? S[kID3 + t] : 0.f);
+    o_w = ws;
+    o_z = z0;
+    const double rd = static_cast<double>(rr);
+    acc[0] += static_cast<double>(vs) * static_cast<double>(vs);
+    acc[1] += rd * rd;
+    cur = nxt;
+    return true;
+  };
+  for (int m = 0;; m += 2) {
+    if (!brick_step(S0, S1, m)) break;
+    if (!brick_step(S1, S0, m + 1)) break;
+  }
+  flush();
+  block_partials<2>(acc, parts);
+}
+
 // Reaction fused with the initial guess and residual of the implicit solve
 // (I - dt A) x = b, b = v*.  The guess extrapolates the diffusion increment
 // d_k = v_{k+1} - b_k of the past steps by the polynomial through the last
@@ -542,15 +967,15 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
                                                  int* flags, CGScalars* cout, double* parts,
                                                  double tol2, int maxit,
                                                  const uint64_t* __restrict__ rowsn) {
-  __shared__ T s[kTile];
-  __shared__ int nbt[2][kNbr];
-  __shared__ uint64_t rowt[2][kNbr];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     CGScalars st = {};
     st.tol2 = tol2;
     st.maxit = maxit;
     *cout = st;
   }
+  __shared__ T s[kTile];
+  __shared__ int nbt[2][kNbr];
+  __shared__ uint64_t rowt[2][kNbr];
   double acc[2] = {0.0, 0.0};
   NbrAhead ahead;
   int nxt = pbrick(0, nb);
@@ -615,6 +1040,27 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
     acc[1] += rd * rd;
   }
   block_partials<2>(acc, parts);
+}
+
+// k_be_init of FP32 grids with the pipelined brick loop (the same arguments
+// and results; four waves per SIMD keep two blocks resident per CU).
+template <bool NT>
+__global__ __launch_bounds__(kBV) __attribute__((amdgpu_waves_per_eu(4))) void k_be_init_pipe(
+    int nb, const int* __restrict__ nbr, CoefSet<float> c, const BeInitArgs A,
+    IonicT<float> ion, float dt, float* __restrict__ tact, float theta, double tprev,
+    int* flags, CGScalars* cout, double* parts, double tol2, int maxit,
+    const uint64_t* __restrict__ rowsn) {
+  __shared__ float S0[kIStage], S1[kIStage], s[kTile];
+  __shared__ int nbt[2][kNbr];
+  __shared__ uint64_t rowt[2][kNbr];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    CGScalars st = {};
+    st.tol2 = tol2;
+    st.maxit = maxit;
+    *cout = st;
+  }
+  be_init_pipelined<NT>(S0, S1, s, nbt, rowt, nb, nbr, rowsn, c, A, ion, dt, tact, theta, tprev,
+                        flags, parts);
 }
 
 // Status word of a CG launch for the host, written with one 8-byte store to
@@ -1019,259 +1465,6 @@ template <typename T> struct Quad {
   typedef T V __attribute__((ext_vector_type(4)));
 };
 
-// ---------------------------------------------------------------------------
-// Pipelined brick loop of the FP32 CG iteration.  A block's next brick is
-// staged into LDS by direct global-to-LDS loads while the current brick is
-// computed, so its load latency overlaps that work instead of following it:
-//   own cells of z, t, p, x and of the six weight arrays (lane order = the
-//   brick's voxel order), the 480 halo cells of z and t (halo_cell order),
-//   and the 600 weights of cells on the brick's -x, -y, -z sides that the
-//   19-point operator of its own voxels uses (the weight halo, below).
-// Every staged value is the one gather18 / cell_setup would load (rows
-// without tissue read the ghost brick's zeros), and the arithmetic is the
-// general iteration's, so the results are bitwise those of the one-brick-
-// at-a-time loop.  A brick's outputs are stored one stage later, after the
-// next staging loads are issued, so that the wait for a stage does not also
-// wait for the stores just issued.
-// A stage is one flat LDS array, so that every access to it has the same
-// underlying object and the compiler can tell the stage being read from the
-// one being filled.
-// Weight halo: CX on the x = -1 plane (y*8+z), CY on y = -1 (x*8+z), CZ on
-// z = -1 (x*8+y); then 136 entries for each edge weight:
-//   CXY: x = -1 plane (y*8+z), y = -1 plane (x*8+z), the (-1,-1,z) edge;
-//   CXZ: x = -1 (y*8+z), z = -1 (x*8+y), the (-1,y,-1) edge;
-//   CYZ: y = -1 (x*8+z), z = -1 (x*8+y), the (x,-1,-1) edge.
-constexpr int kStZ = 0, kStT = 512, kStP = 1024, kStX = 1536, kStW = 2048;   // own cells
-constexpr int kStHZ = 5120, kStHT = 5632;                                    // halo cells
-constexpr int kStWH = 6144;                                                  // weight halo
-constexpr int kWhCX = 0, kWhCY = 64, kWhCZ = 128, kWhCXY = 192, kWhCXZ = 328, kWhCYZ = 464;
-constexpr int kStage = kStWH + 600;
-
-// entry m of weight array a's halo: coordinates relative to the brick
-__device__ __forceinline__ void wh_coords(int a, int m, int& tx, int& ty, int& tz) {
-  const int i = (m >> 3) & 7, j = m & 7, e = m - 128;
-  switch (a) {
-    case CX: tx = -1; ty = i; tz = j; break;
-    case CY: tx = i; ty = -1; tz = j; break;
-    case CZ: tx = i; ty = j; tz = -1; break;
-    case CXY:
-      if (m < 64) { tx = -1; ty = i; tz = j; }
-      else if (m < 128) { tx = i; ty = -1; tz = j; }
-      else { tx = -1; ty = -1; tz = e; }
-      break;
-    case CXZ:
-      if (m < 64) { tx = -1; ty = i; tz = j; }
-      else if (m < 128) { tx = i; ty = j; tz = -1; }
-      else { tx = -1; ty = e; tz = -1; }
-      break;
-    default:   // CYZ
-      if (m < 64) { tx = i; ty = -1; tz = j; }
-      else if (m < 128) { tx = i; ty = j; tz = -1; }
-      else { tx = e; ty = -1; tz = -1; }
-  }
-}
-
-// gather18's weights from a staged brick F (flat stage)
-__device__ __forceinline__ void gather18_lds(const float* F, int t, int lx, int ly, int lz,
-                                             float k[18]) {
-  constexpr int W = kStW, H = kStWH;
-  k[0] = F[W + CX * kBV + t];
-  k[1] = F[lx ? W + CX * kBV + t - 64 : H + kWhCX + ly * 8 + lz];
-  k[2] = F[W + CY * kBV + t];
-  k[3] = F[ly ? W + CY * kBV + t - 8 : H + kWhCY + lx * 8 + lz];
-  k[4] = F[W + CZ * kBV + t];
-  k[5] = F[lz ? W + CZ * kBV + t - 1 : H + kWhCZ + lx * 8 + ly];
-  k[6] = F[W + CXY * kBV + t];
-  k[7] = F[(lx && ly) ? W + CXY * kBV + t - 72
-           : (!lx && !ly) ? H + kWhCXY + 128 + lz
-           : !lx ? H + kWhCXY + (ly - 1) * 8 + lz : H + kWhCXY + 64 + (lx - 1) * 8 + lz];
-  k[8] = F[ly ? W + CXY * kBV + t - 8 : H + kWhCXY + 64 + lx * 8 + lz];
-  k[9] = F[lx ? W + CXY * kBV + t - 64 : H + kWhCXY + ly * 8 + lz];
-  k[10] = F[W + CXZ * kBV + t];
-  k[11] = F[(lx && lz) ? W + CXZ * kBV + t - 65
-            : (!lx && !lz) ? H + kWhCXZ + 128 + ly
-            : !lx ? H + kWhCXZ + ly * 8 + (lz - 1) : H + kWhCXZ + 64 + (lx - 1) * 8 + ly];
-  k[12] = F[lz ? W + CXZ * kBV + t - 1 : H + kWhCXZ + 64 + lx * 8 + ly];
-  k[13] = F[lx ? W + CXZ * kBV + t - 64 : H + kWhCXZ + ly * 8 + lz];
-  k[14] = F[W + CYZ * kBV + t];
-  k[15] = F[(ly && lz) ? W + CYZ * kBV + t - 9
-            : (!ly && !lz) ? H + kWhCYZ + 128 + lx
-            : !ly ? H + kWhCYZ + lx * 8 + (lz - 1) : H + kWhCYZ + 64 + lx * 8 + (ly - 1)];
-  k[16] = F[lz ? W + CYZ * kBV + t - 1 : H + kWhCYZ + 64 + lx * 8 + ly];
-  k[17] = F[ly ? W + CYZ * kBV + t - 8 : H + kWhCYZ + lx * 8 + lz];
-}
-
-// one direct global-to-LDS dword load per active lane: lane i of the wave
-// writes dst[i] (dst the same in every lane of the wave)
-template <bool NT>
-__device__ __forceinline__ void lds_load(const float* base, int i, float* dst) {
-  const float* src = reinterpret_cast<const float*>(
-      reinterpret_cast<const char*>(base) +
-      static_cast<uint64_t>(static_cast<uint32_t>(i) * 4u));
-  __builtin_amdgcn_global_load_lds(src, dst, 4, 0, NT ? 2 : 0);
-}
-
-// weight-halo entries [m0, m0 + n) of array a, one per lane from lane l0 on
-__device__ __forceinline__ void wh_load(float* F, const float* base, int a, int m0, int off,
-                                        int lane, int l0, int n, int nb, const int* nbs,
-                                        const uint64_t* rowm) {
-  if (lane < l0 || lane >= l0 + n) return;
-  const int m = m0 + lane - l0;
-  int tx, ty, tz;
-  wh_coords(a, m, tx, ty, tz);
-  const int ox = tx < 0 ? 0 : 1, oy = ty < 0 ? 0 : 1, oz = tz < 0 ? 0 : 1;
-  const int g = vox_live(rowm, tx, ty, tz)
-                    ? nbs[ox * 9 + oy * 3 + oz] * kBV + (((tx & 7) * 8 + (ty & 7)) * 8 + (tz & 7))
-                    : nb * kBV + lane;
-  lds_load<false>(base, g, F + off + m0 - l0);
-}
-
-// issue the staging loads of `brick` (table nbs / rowm in LDS) into F
-template <bool NT>
-__device__ __forceinline__ void pcg_stage(float* F, int brick, int nb, const int* nbs,
-                                          const uint64_t* rowm, const CoefSet<float>& c,
-                                          const float* x, const float* z_in, const float* p_in,
-                                          const float* t_in) {
-  const int t = threadIdx.x, w0 = t & ~63, lane = t & 63, wave = t >> 6;
-  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
-  const int gl = vox_live(rowm, lx, ly, lz) ? brick * kBV + t : nb * kBV + t;
-  lds_load<false>(z_in, gl, F + kStZ + w0);
-  lds_load<false>(t_in, gl, F + kStT + w0);
-  lds_load<false>(p_in, gl, F + kStP + w0);
-  lds_load<NT>(x, gl, F + kStX + w0);
-#pragma unroll
-  for (int a = 0; a < 6; ++a) lds_load<false>(c.c[a], gl, F + kStW + a * kBV + w0);
-  if (t < kHalo) {
-    int hx, hy, hz;
-    halo_cell(t, hx, hy, hz);
-    const int hgl = vox_live(rowm, hx - 1, hy - 1, hz - 1) ? tile_global(nbs, hx, hy, hz)
-                                                            : nb * kBV + t;
-    lds_load<false>(z_in, hgl, F + kStHZ + w0);
-    lds_load<false>(t_in, hgl, F + kStHT + w0);
-  }
-  // the weight halo, one array per wave (wave-uniform bases)
-  const int H = kStWH;
-  switch (wave) {
-    case 0:
-      wh_load(F, c.c[CX], CX, 0, H + kWhCX, lane, 0, 64, nb, nbs, rowm);
-      wh_load(F, c.c[CYZ], CYZ, 64, H + kWhCYZ, lane, 0, 64, nb, nbs, rowm);
-      break;
-    case 1:
-      wh_load(F, c.c[CY], CY, 0, H + kWhCY, lane, 0, 64, nb, nbs, rowm);
-      wh_load(F, c.c[CXY], CXY, 128, H + kWhCXY, lane, 0, 8, nb, nbs, rowm);
-      wh_load(F, c.c[CXZ], CXZ, 128, H + kWhCXZ, lane, 8, 8, nb, nbs, rowm);
-      wh_load(F, c.c[CYZ], CYZ, 128, H + kWhCYZ, lane, 16, 8, nb, nbs, rowm);
-      break;
-    case 2: wh_load(F, c.c[CZ], CZ, 0, H + kWhCZ, lane, 0, 64, nb, nbs, rowm); break;
-    case 3: wh_load(F, c.c[CXY], CXY, 0, H + kWhCXY, lane, 0, 64, nb, nbs, rowm); break;
-    case 4: wh_load(F, c.c[CXY], CXY, 64, H + kWhCXY, lane, 0, 64, nb, nbs, rowm); break;
-    case 5: wh_load(F, c.c[CXZ], CXZ, 0, H + kWhCXZ, lane, 0, 64, nb, nbs, rowm); break;
-    case 6: wh_load(F, c.c[CXZ], CXZ, 64, H + kWhCXZ, lane, 0, 64, nb, nbs, rowm); break;
-    default: wh_load(F, c.c[CYZ], CYZ, 0, H + kWhCYZ, lane, 0, 64, nb, nbs, rowm);
-  }
-}
-
-// The general CG iteration's brick loop, pipelined (see pcg_stage): alpha,
-// beta from this launch's scalars; partials as the one-brick-at-a-time loop.
-template <bool NT>
-__device__ __forceinline__ void pcg_iter_pipelined(
-    int nb, const int* __restrict__ nbr, const uint64_t* __restrict__ rowsn,
-    const CoefSet<float>& c, float c0, float c1, float alpha, float beta,
-    float* __restrict__ x, const float* __restrict__ z_in, float* __restrict__ z_out,
-    const float* __restrict__ p_in, float* __restrict__ p_out, const float* __restrict__ t_in,
-    float* __restrict__ t_out, double* parts) {
-  __shared__ float S0[kStage], S1[kStage];
-  __shared__ float s[kTile];
-  __shared__ int nbt[2][kNbr];
-  __shared__ uint64_t rowt[2][kNbr];
-  const int t = threadIdx.x;
-  const int lx = t >> 6, ly = (t >> 3) & 7, lz = t & 7;
-  const int C = tidx(lx + 1, ly + 1, lz + 1);
-  int hC = 0;
-  if (t < kHalo) {
-    int hx, hy, hz;
-    halo_cell(t, hx, hy, hz);
-    hC = tidx(hx, hy, hz);
-  }
-  double acc[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  NbrAhead ahead;
-  // outputs of the previous brick, stored one stage later
-  int pend_brick = -1;   // the same in every thread
-  bool pend = false;
-  float ox = 0.f, oz = 0.f, op = 0.f, ot = 0.f;
-  int cur = pbrick(0, nb);
-  ahead.fetch(nbr, rowsn, cur);
-  ahead.stage(nbt[0], rowt[0]);
-  __syncthreads();
-  if (cur >= 0) pcg_stage<NT>(S0, cur, nb, nbt[0], rowt[0], c, x, z_in, p_in, t_in);
-  ahead.fetch(nbr, rowsn, pbrick(1, nb));
-  // one brick: S holds its stage, N receives the next brick's
-  auto brick_step = [&](const float* S, float* N, int m) -> bool {
-    if (cur < 0) return false;
-    __builtin_amdgcn_s_waitcnt(0);   // this wave's staging loads have landed
-    __syncthreads();                 // every wave's; the previous brick is done with LDS
-    const bool live = vox_live(rowt[m & 1], lx, ly, lz);
-    const float tg = S[kStT + t];
-    const float zn = S[kStZ + t] - alpha * tg;
-    s[C] = zn;
-    if (t < kHalo) s[hC] = S[kStHZ + t] - alpha * S[kStHT + t];
-    ahead.stage(nbt[(m + 1) & 1], rowt[(m + 1) & 1]);
-    __syncthreads();
-    const int nxt = pbrick(m + 1, nb);
-    if (nxt >= 0)
-      pcg_stage<NT>(N, nxt, nb, nbt[(m + 1) & 1], rowt[(m + 1) & 1], c, x, z_in, p_in, t_in);
-    ahead.fetch(nbr, rowsn, pbrick(m + 2, nb));
-    if (pend) {
-      const int g = pend_brick * kBV + t;
-      st_stream<NT>(&at(x, g), ox);
-      st_stream<NT>(&at(z_out, g), oz);
-      st_stream<NT>(&at(p_out, g), op);
-      st_stream<NT>(&at(t_out, g), ot);
-    }
-    float k18[18];
-    gather18_lds(S, t, lx, ly, lz, k18);
-    if (!live) {
-#pragma unroll
-      for (int i = 0; i < 18; ++i) k18[i] = 0.f;
-    }
-    const float pg = S[kStP + t], xg = S[kStX + t];
-    // q_k = K p_k = K z_k + beta q_{k-1}, with q_{k-1} = M t_{k-1}
-    const float md = c0 + c1 * diag19(k18);
-    const float qn = (c0 * zn + c1 * apply19(s, C, k18)) + beta * (md * tg);
-    const float pn = zn + beta * pg;
-    const float tn = qn / md;
-    const float rn = md * zn;
-    pend = live;
-    pend_brick = cur;
-    ox = xg + alpha * pg;
-    oz = zn;
-    op = pn;
-    ot = tn;
-    const double dr = rn, dz = zn, dp = pn, dq = qn;
-    acc[0] += dp * dq;
-    acc[1] += dr * dz;
-    acc[2] += dq * dz;
-    acc[3] += dq * static_cast<double>(tn);
-    acc[4] += dr * dr;
-    acc[5] += dq * dr;
-    acc[6] += dq * dq;
-    cur = nxt;
-    return true;
-  };
-  for (int m = 0;; m += 2) {
-    if (!brick_step(S0, S1, m)) break;
-    if (!brick_step(S1, S0, m + 1)) break;
-  }
-  if (pend) {
-    const int g = pend_brick * kBV + t;
-    st_stream<NT>(&at(x, g), ox);
-    st_stream<NT>(&at(z_out, g), oz);
-    st_stream<NT>(&at(p_out, g), op);
-    st_stream<NT>(&at(t_out, g), ot);
-  }
-  block_partials<7>(acc, parts);
-}
-
 // Jacobi-PCG with one launch per iteration and no set-up apply: the
 // textbook recurrences, with the next residual's two norms, (r, z) and
 // (r, r), expanded in dot products of the previous launch's own vectors, so
@@ -1382,12 +1575,17 @@ __global__ __launch_bounds__(kBV) __attribute__((amdgpu_waves_per_eu(4))) void k
   }
   if (st.done) return;
   if constexpr (sizeof(T) == 4) {
-    if (!first) {
-      pcg_iter_pipelined<NT>(nb, nbr, rowsn, c, c0, c1, alpha, beta, x, z_in, z_out, p_in,
-                             p_out, t_in, t_out, parts);
-      return;
-    }
-  }
+    __shared__ float S0[kStage], S1[kStage], s[kTile];
+    __shared__ int nbt[2][kNbr];
+    __shared__ uint64_t rowt[2][kNbr];
+    if (first)
+      pcg_iter_pipelined<NT, true>(S0, S1, s, nbt, rowt, nb, nbr, rowsn, c, c0, c1, alpha, beta,
+                                   x, z_in, z_out, p_in, p_out, t_in, t_out, parts);
+    else
+      pcg_iter_pipelined<NT, false>(S0, S1, s, nbt, rowt, nb, nbr, rowsn, c, c0, c1, alpha,
+                                    beta, x, z_in, z_out, p_in, p_out, t_in, t_out, parts);
+    return;
+  } else {
   __shared__ T s[kTile];
   __shared__ int nbt[2][kNbr];
   __shared__ uint64_t rowt[2][kNbr];
@@ -1445,6 +1643,7 @@ __global__ __launch_bounds__(kBV) __attribute__((amdgpu_waves_per_eu(4))) void k
     acc[6] += dq * dq;
   }
   block_partials<7>(acc, parts);
+  }
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_reduce(const double* __restrict__ partials,
@@ -2085,10 +2284,18 @@ void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v
                     const T* d3, T q2, T q3, T q4, T* bout, T* dout, T* qout, T* x, T* wout,
                     T* z, IonicT<T> ion, T dt, T* tact, T theta, double tprev, int check_prev,
                     int* flags, CGScalars* cout, double* parts, double tol2, int maxit) {
-  auto k = L.stream_nt ? k_be_init<T, true> : k_be_init<T, false>;
-  k<<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, bprev, qin, kd, d2, d3, q2, q3, q4,
-                                   bout, dout, qout, x, wout, z, ion, dt, tact, theta, tprev,
-                                   check_prev, flags, cout, parts, tol2, maxit, L.rowsn);
+  if constexpr (sizeof(T) == 4) {
+    const BeInitArgs A = {v, w, jstim, bprev, qin, d2, d3, bout, dout, qout, x, wout, z,
+                          kd, q2, q3, q4, check_prev != 0};
+    auto k = L.stream_nt ? k_be_init_pipe<true> : k_be_init_pipe<false>;
+    k<<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, A, ion, dt, tact, theta, tprev, flags, cout,
+                                     parts, tol2, maxit, L.rowsn);
+  } else {
+    auto k = L.stream_nt ? k_be_init<T, true> : k_be_init<T, false>;
+    k<<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, v, w, jstim, bprev, qin, kd, d2, d3, q2, q3,
+                                     q4, bout, dout, qout, x, wout, z, ion, dt, tact, theta,
+                                     tprev, check_prev, flags, cout, parts, tol2, maxit, L.rowsn);
+  }
 }
 
 
