@@ -512,17 +512,19 @@ __global__ __launch_bounds__(kBV) void k_ionic(int nb, const T* __restrict__ v,
 // so its three dot products share one reduction.
 
 // ---------------------------------------------------------------------------
-// Pipelined brick loop of the FP32 CG iteration.  A block's next brick is
-// staged into LDS by direct global-to-LDS loads while the current brick is
-// computed, so its load latency overlaps that work instead of following it:
+// Pipelined brick loop of the FP32 implicit-step kernels (the CG launches
+// and the init kernel below).  A block's next brick is staged into LDS by
+// direct global-to-LDS loads while the current brick is computed, so its
+// load latency overlaps that work instead of following it.  For the CG
+// launches a stage holds:
 //   own cells of z, t, p, x and of the six weight arrays (lane order = the
 //   brick's voxel order), the 480 halo cells of z and t (halo_cell order),
 //   and the 600 weights of cells on the brick's -x, -y, -z sides that the
 //   19-point operator of its own voxels uses (the weight halo, below).
 // Every staged value is the one gather18 / cell_setup would load (rows
 // without tissue read the ghost brick's zeros), and the arithmetic is the
-// general iteration's, so the results are bitwise those of the one-brick-
-// at-a-time loop.  A brick's outputs are stored one stage later, after the
+// one-brick-at-a-time loop's, so the results are bitwise those of that
+// loop.  A brick's outputs are stored one stage later, after the
 // next staging loads are issued, so that the wait for a stage does not also
 // wait for the stores just issued.
 // A stage is one flat LDS array, so that every access to it has the same
@@ -949,7 +951,7 @@ __device__ __forceinline__ void be_init_pipelined(
 // the solve keeps z0 = M^-1 r0 (M the diagonal of I - dt A).
 // When check_prev is set it also records activation for the previous step
 // (vprev -> v) before x0 overwrites vprev's buffer.
-// Partials: (b.b, r.r).
+// Partials: (b.b, r.r).  FP32 grids run the pipelined overload below.
 template <typename T, bool NT>
 __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__ nbr,
                                                  CoefSet<T> c, const T* __restrict__ v,
@@ -1042,10 +1044,12 @@ __global__ __launch_bounds__(kBV) void k_be_init(int nb, const int* __restrict__
   block_partials<2>(acc, parts);
 }
 
-// k_be_init of FP32 grids with the pipelined brick loop (the same arguments
-// and results; four waves per SIMD keep two blocks resident per CU).
+
+// k_be_init of FP32 grids, with the pipelined brick loop: the same work and
+// results as the template above (the arguments gathered in BeInitArgs); the
+// four waves per SIMD asked for keep two blocks resident per CU.
 template <bool NT>
-__global__ __launch_bounds__(kBV) __attribute__((amdgpu_waves_per_eu(4))) void k_be_init_pipe(
+__global__ __launch_bounds__(kBV) __attribute__((amdgpu_waves_per_eu(4))) void k_be_init(
     int nb, const int* __restrict__ nbr, CoefSet<float> c, const BeInitArgs A,
     IonicT<float> ion, float dt, float* __restrict__ tact, float theta, double tprev,
     int* flags, CGScalars* cout, double* parts, double tol2, int maxit,
@@ -2287,7 +2291,7 @@ void launch_be_init(const LaunchCfg& L, const int* nbr, CoefSet<T> c, const T* v
   if constexpr (sizeof(T) == 4) {
     const BeInitArgs A = {v, w, jstim, bprev, qin, d2, d3, bout, dout, qout, x, wout, z,
                           kd, q2, q3, q4, check_prev != 0};
-    auto k = L.stream_nt ? k_be_init_pipe<true> : k_be_init_pipe<false>;
+    auto k = L.stream_nt ? k_be_init<true> : k_be_init<false>;
     k<<<L.pgrid, kBV, 0, L.stream>>>(L.nb, nbr, c, A, ion, dt, tact, theta, tprev, flags, cout,
                                      parts, tol2, maxit, L.rowsn);
   } else {
