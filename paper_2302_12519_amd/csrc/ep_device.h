@@ -249,5 +249,132 @@ __device__ __forceinline__ Cell cell_setup(const int* nbs, int brick,
   return c;
 }
 
+// ---------------------------------------------------------------------------
+// Staging a brick into LDS with direct global-to-LDS loads (the pipelined
+// brick loops): the weight halo (the weights of cells on a brick's -x, -y,
+// -z sides that its own voxels' 19-point rows use) and helpers.
+// Weight halo: CX on the x = -1 plane (y*8+z), CY on y = -1 (x*8+z), CZ on
+// z = -1 (x*8+y); then 136 entries for each edge weight:
+//   CXY: x = -1 plane (y*8+z), y = -1 plane (x*8+z), the (-1,-1,z) edge;
+//   CXZ: x = -1 (y*8+z), z = -1 (x*8+y), the (-1,y,-1) edge;
+//   CYZ: y = -1 (x*8+z), z = -1 (x*8+y), the (x,-1,-1) edge.
+constexpr int kWHalo = 600;
+constexpr int kWhCX = 0, kWhCY = 64, kWhCZ = 128, kWhCXY = 192, kWhCXZ = 328, kWhCYZ = 464;
+// entry m of weight array a's halo: coordinates relative to the brick
+__device__ __forceinline__ void wh_coords(int a, int m, int& tx, int& ty, int& tz) {
+  const int i = (m >> 3) & 7, j = m & 7, e = m - 128;
+  switch (a) {
+    case CX: tx = -1; ty = i; tz = j; break;
+    case CY: tx = i; ty = -1; tz = j; break;
+    case CZ: tx = i; ty = j; tz = -1; break;
+    case CXY:
+      if (m < 64) { tx = -1; ty = i; tz = j; }
+      else if (m < 128) { tx = i; ty = -1; tz = j; }
+      else { tx = -1; ty = -1; tz = e; }
+      break;
+    case CXZ:
+      if (m < 64) { tx = -1; ty = i; tz = j; }
+      else if (m < 128) { tx = i; ty = j; tz = -1; }
+      else { tx = -1; ty = e; tz = -1; }
+      break;
+    default:   // CYZ
+      if (m < 64) { tx = i; ty = -1; tz = j; }
+      else if (m < 128) { tx = i; ty = j; tz = -1; }
+      else { tx = e; ty = -1; tz = -1; }
+  }
+}
+
+// gather18's weights from a staged brick F (flat stage): the own cells of
+// the six weight arrays at W (array a at W + a * 512), the weight halo at H
+template <int W, int H>
+__device__ __forceinline__ void gather18_lds(const float* F, int t, int lx, int ly, int lz,
+                                             float k[18]) {
+  k[0] = F[W + CX * kBV + t];
+  k[1] = F[lx ? W + CX * kBV + t - 64 : H + kWhCX + ly * 8 + lz];
+  k[2] = F[W + CY * kBV + t];
+  k[3] = F[ly ? W + CY * kBV + t - 8 : H + kWhCY + lx * 8 + lz];
+  k[4] = F[W + CZ * kBV + t];
+  k[5] = F[lz ? W + CZ * kBV + t - 1 : H + kWhCZ + lx * 8 + ly];
+  k[6] = F[W + CXY * kBV + t];
+  k[7] = F[(lx && ly) ? W + CXY * kBV + t - 72
+           : (!lx && !ly) ? H + kWhCXY + 128 + lz
+           : !lx ? H + kWhCXY + (ly - 1) * 8 + lz : H + kWhCXY + 64 + (lx - 1) * 8 + lz];
+  k[8] = F[ly ? W + CXY * kBV + t - 8 : H + kWhCXY + 64 + lx * 8 + lz];
+  k[9] = F[lx ? W + CXY * kBV + t - 64 : H + kWhCXY + ly * 8 + lz];
+  k[10] = F[W + CXZ * kBV + t];
+  k[11] = F[(lx && lz) ? W + CXZ * kBV + t - 65
+            : (!lx && !lz) ? H + kWhCXZ + 128 + ly
+            : !lx ? H + kWhCXZ + ly * 8 + (lz - 1) : H + kWhCXZ + 64 + (lx - 1) * 8 + ly];
+  k[12] = F[lz ? W + CXZ * kBV + t - 1 : H + kWhCXZ + 64 + lx * 8 + ly];
+  k[13] = F[lx ? W + CXZ * kBV + t - 64 : H + kWhCXZ + ly * 8 + lz];
+  k[14] = F[W + CYZ * kBV + t];
+  k[15] = F[(ly && lz) ? W + CYZ * kBV + t - 9
+            : (!ly && !lz) ? H + kWhCYZ + 128 + lx
+            : !ly ? H + kWhCYZ + lx * 8 + (lz - 1) : H + kWhCYZ + 64 + lx * 8 + (ly - 1)];
+  k[16] = F[lz ? W + CYZ * kBV + t - 1 : H + kWhCYZ + 64 + lx * 8 + ly];
+  k[17] = F[ly ? W + CYZ * kBV + t - 8 : H + kWhCYZ + lx * 8 + lz];
+}
+
+// one direct global-to-LDS dword load per active lane: lane i of the wave
+// writes dst[i] (dst the same in every lane of the wave)
+template <bool NT>
+__device__ __forceinline__ void lds_load(const float* base, int i, float* dst) {
+  const float* src = reinterpret_cast<const float*>(
+      reinterpret_cast<const char*>(base) +
+      static_cast<uint64_t>(static_cast<uint32_t>(i) * 4u));
+  __builtin_amdgcn_global_load_lds(src, dst, 4, 0, NT ? 2 : 0);
+}
+
+// weight-halo entries [m0, m0 + n) of array a, one per lane from lane l0 on
+__device__ __forceinline__ void wh_load(float* F, const float* base, int a, int m0, int off,
+                                        int lane, int l0, int n, int nb, const int* nbs,
+                                        const uint64_t* rowm) {
+  if (lane < l0 || lane >= l0 + n) return;
+  const int m = m0 + lane - l0;
+  int tx, ty, tz;
+  wh_coords(a, m, tx, ty, tz);
+  const int ox = tx < 0 ? 0 : 1, oy = ty < 0 ? 0 : 1, oz = tz < 0 ? 0 : 1;
+  const int g = vox_live(rowm, tx, ty, tz)
+                    ? nbs[ox * 9 + oy * 3 + oz] * kBV + (((tx & 7) * 8 + (ty & 7)) * 8 + (tz & 7))
+                    : nb * kBV + lane;
+  lds_load<false>(base, g, F + off + m0 - l0);
+}
+
+// global index a halo thread t (< 480) loads: its halo cell, or the ghost
+// brick when the cell's row holds no tissue
+__device__ __forceinline__ int halo_index(int t, int nb, const int* nbs, const uint64_t* rowm) {
+  int hx, hy, hz;
+  halo_cell(t, hx, hy, hz);
+  return vox_live(rowm, hx - 1, hy - 1, hz - 1) ? tile_global(nbs, hx, hy, hz) : nb * kBV + t;
+}
+
+// stage the six weight arrays of a brick: own cells (index gl) at W, the
+// weight halo at H, one array per wave (wave-uniform bases)
+template <int W, int H>
+__device__ __forceinline__ void stage_weights(float* F, int gl, int nb, const int* nbs,
+                                              const uint64_t* rowm, const CoefSet<float>& c) {
+  const int t = threadIdx.x, w0 = t & ~63, lane = t & 63, wave = t >> 6;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) lds_load<false>(c.c[a], gl, F + W + a * kBV + w0);
+  switch (wave) {
+    case 0:
+      wh_load(F, c.c[CX], CX, 0, H + kWhCX, lane, 0, 64, nb, nbs, rowm);
+      wh_load(F, c.c[CYZ], CYZ, 64, H + kWhCYZ, lane, 0, 64, nb, nbs, rowm);
+      break;
+    case 1:
+      wh_load(F, c.c[CY], CY, 0, H + kWhCY, lane, 0, 64, nb, nbs, rowm);
+      wh_load(F, c.c[CXY], CXY, 128, H + kWhCXY, lane, 0, 8, nb, nbs, rowm);
+      wh_load(F, c.c[CXZ], CXZ, 128, H + kWhCXZ, lane, 8, 8, nb, nbs, rowm);
+      wh_load(F, c.c[CYZ], CYZ, 128, H + kWhCYZ, lane, 16, 8, nb, nbs, rowm);
+      break;
+    case 2: wh_load(F, c.c[CZ], CZ, 0, H + kWhCZ, lane, 0, 64, nb, nbs, rowm); break;
+    case 3: wh_load(F, c.c[CXY], CXY, 0, H + kWhCXY, lane, 0, 64, nb, nbs, rowm); break;
+    case 4: wh_load(F, c.c[CXY], CXY, 64, H + kWhCXY, lane, 0, 64, nb, nbs, rowm); break;
+    case 5: wh_load(F, c.c[CXZ], CXZ, 0, H + kWhCXZ, lane, 0, 64, nb, nbs, rowm); break;
+    case 6: wh_load(F, c.c[CXZ], CXZ, 64, H + kWhCXZ, lane, 0, 64, nb, nbs, rowm); break;
+    default: wh_load(F, c.c[CYZ], CYZ, 0, H + kWhCYZ, lane, 0, 64, nb, nbs, rowm);
+  }
+}
+
 }  // namespace dev
 }  // namespace ep
