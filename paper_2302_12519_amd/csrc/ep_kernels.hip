@@ -16,7 +16,10 @@
 // blocks, redundantly) sums the previous launch's slots in a fixed order
 // before using the totals.  The CG kernels are persistent (a fixed grid that
 // strides over the bricks), so that sum costs a few hundred loads per block,
-// and one CG iteration is one launch.
+// and one CG iteration is one launch.  The FP32 implicit-step kernels also
+// stage each block's next brick into LDS (direct global-to-LDS loads) while
+// computing the current one, so the load wait of a brick overlaps the work
+// of the one before it.
 //
 // What each kernel computes, with the passage it follows (thesis):
 //   k_tensor, k_coefs, k_unit_tensor: voxel conductivity tensors (eqn:sigma1)
