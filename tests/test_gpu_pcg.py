@@ -8,7 +8,8 @@ launch that finds the solve done applying the last x update):
 - the iteration limit, reported as EP_ERR_NOCONV;
 - bitwise reproducibility of FP32 runs (fixed-order reductions), also when
   the steps are split over several calls;
-- the activation check of steps whose guess already solves the system.
+- the activation check of steps whose guess already solves the system;
+- FP32 iteration counts step by step against FP64 on the same problem.
 """
 import numpy as np
 import pytest
@@ -167,3 +168,26 @@ def test_be_pcg_split_calls_bitwise(P):
     assert np.isfinite(t1).sum() > 0
     assert np.array_equal(v1, v2) and np.array_equal(w1, w2)
     assert np.array_equal(t1, t2, equal_nan=True)
+
+
+def test_be_pcg_fp32_iterations_match_fp64(P):
+    """The FP32 solver is CG in its own right, not just a method that ends
+    within tolerance: step by step on the same problem it needs the FP64
+    solver's iteration count while the counts are large (the first 30
+    steps: 3 to 8 iterations, where a wrong search direction or step length
+    shows at once), and at most one more later, where FP32 rounding near
+    the 1e-7 tolerance can cost one."""
+    say("case aniso_be_40 fp32 against fp64 iteration counts, 60 steps")
+    counts = {}
+    for prec in ("f64", "f32"):
+        inst = E.aniso_be(40, steps=60)
+        inst.pcg_rtol = 1e-7
+        g = P.Grid.from_instance(inst, prec=prec)
+        counts[prec] = np.array([g.step(1)["cg_iters"] for _ in range(60)])
+        g.close()
+    a, b = counts["f64"], counts["f32"]
+    say(f"iterations: fp64 {a.sum()}, fp32 {b.sum()}; first 30 steps equal: "
+        f"{int((a[:30] == b[:30]).sum())}")
+    assert a[:30].min() >= 3
+    assert np.array_equal(a[:30], b[:30])
+    assert np.all(b - a <= 1) and np.all(b - a >= -1)
