@@ -416,10 +416,10 @@ EP_API const char* ep_last_error(ep_grid g);
  *    all stimuli of a request sharing one time window); host data is copied.
  *  - ep_batch_advance admits queued requests in FIFO order while their
  *    device memory fits the HBM budget and a slot is free (their grids,
- *    coefficients and state are built on the device), then launches one
- *    captured graph of K steps in which every admitted request advances by up
- *    to K steps (a request never steps past its own count), and detects the
- *    requests that have finished.  Requests admitted later join running
+ *    coefficients and state are built on the device while the previous
+ *    launch runs), then launches one captured graph of K steps in which every
+ *    admitted request advances by up to K steps (a request never steps past
+ *    its own count), and detects the requests that have finished.  Requests admitted later join running
  *    ones at the next graph boundary; their work shares each launch.
  *  - finished requests stay resident until ep_batch_release; read their
  *    fields with ep_batch_read (same layout and conventions as

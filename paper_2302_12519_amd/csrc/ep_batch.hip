@@ -12,7 +12,9 @@
 // step s lives in buffer s & 1, and a launch for substep k skips slots whose
 // step + k has reached their own step count.  K substeps plus a counter
 // update are captured once in a hipGraph; admission and retirement only
-// rewrite the slot table and the work list between graph launches.
+// rewrite the slot table and the work list between graph launches.  A new
+// request's region is built on a stream of its own while the graph launch
+// in flight runs; the next launch waits for it.
 //
 // Host side: FIFO admission by HBM budget (first-fit arena with coalescing)
 // and free slots, request bookkeeping and result read-back.
@@ -273,6 +275,13 @@ struct ep_batch_s {
   SlotDev* h_slots = nullptr;   // pinned read-back of the slot table
   SlotDev* h_up = nullptr;      // pinned staging of slot uploads (one per slot, and a zero entry)
   hipStream_t rstream = nullptr;  // result reads (finished requests only)
+  hipStream_t astream = nullptr;  // admissions (uploads and coefficient kernels)
+  hipEvent_t ev_adm = nullptr;    // end of the admissions of an advance
+  char* h_stage = nullptr;        // pinned upload staging: two halves of kStageHalf bytes
+  hipEvent_t ev_stage[2] = {nullptr, nullptr};  // end of each half's copy
+  bool stage_busy[2] = {false, false};
+  int stage_next = 0;
+  std::vector<int> unpublished;   // admitted slots not yet in the device slot table
   hipEvent_t ev_done = nullptr;   // end of the graph launch in flight
   bool inflight = false;
   std::vector<long long> launch_before;  // per slot: step at the launch in flight, -1 = not in it
@@ -321,9 +330,38 @@ ep_status bfail(ep_batch b, ep_status s, const std::string& msg) {
       return bfail((b), EP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// Upload of host data to the device on the admission stream, through the
+// pinned staging halves: the host fills one half with all pool threads
+// while the copy engine drains the other (a pageable copy would be staged
+// by one host thread).  Returns once the last piece is enqueued; the source
+// may be reused at once.
+constexpr size_t kStageHalf = size_t(8) << 20;
+
+ep_status upload(ep_batch b, void* dst, const void* src, size_t bytes) {
+  const char* s = static_cast<const char*>(src);
+  char* d = static_cast<char*>(dst);
+  for (size_t off = 0; off < bytes; off += kStageHalf) {
+    const size_t len = std::min(kStageHalf, bytes - off);
+    const int h = b->stage_next;
+    b->stage_next ^= 1;
+    if (b->stage_busy[h]) BHIP(b, hipEventSynchronize(b->ev_stage[h]));
+    char* st = b->h_stage + h * kStageHalf;
+    constexpr size_t kPiece = size_t(256) << 10;
+    const int64_t np = static_cast<int64_t>((len + kPiece - 1) / kPiece);
+    parallel_for(np, [&](int64_t i) {
+      const size_t o = static_cast<size_t>(i) * kPiece;
+      std::memcpy(st + o, s + off + o, std::min(kPiece, len - o));
+    });
+    BHIP(b, hipMemcpyAsync(d + off, st, len, hipMemcpyHostToDevice, b->astream));
+    BHIP(b, hipEventRecord(b->ev_stage[h], b->astream));
+    b->stage_busy[h] = true;
+  }
+  return EP_OK;
+}
+
 ep_status grow_scratch(ep_batch b, int64_t nvox) {
   if (nvox <= b->scratch_vox) return EP_OK;
-  BHIP(b, hipStreamSynchronize(b->stream));
+  BHIP(b, hipStreamSynchronize(b->astream));
   (void)hipFree(b->d_fib);
   (void)hipFree(b->d_scale);
   (void)hipFree(b->d_tens);
@@ -349,7 +387,7 @@ ep_status grow_scratch(ep_batch b, int64_t nvox) {
 
 ep_status grow_stim(ep_batch b, size_t n) {
   if (n <= b->stim_cap) return EP_OK;
-  BHIP(b, hipStreamSynchronize(b->stream));
+  BHIP(b, hipStreamSynchronize(b->astream));
   (void)hipFree(b->d_stim_idx);
   (void)hipFree(b->d_stim_amp);
   b->d_stim_idx = nullptr;
@@ -365,8 +403,10 @@ ep_status grow_stim(ep_batch b, size_t n) {
 }
 
 // Build a request's device region: weights, initial state, stimulus field.
-// Everything is enqueued on the batch stream without waiting: the host
-// sources are owned by the request (alive until its release) or pinned.
+// Everything is enqueued on the admission stream, so that it runs beside
+// the graph launch in flight: the region was free (no launch in flight
+// reads it), host data goes through the pinned staging halves, and the
+// coefficient scratch is used by admissions only.
 ep_status admit(ep_batch b, ep_batch_request* r, int slot) {
   const BrickMap& m = r->map;
   const size_t nv = static_cast<size_t>(m.nvox);
@@ -385,39 +425,44 @@ ep_status admit(ep_batch b, ep_batch_request* r, int slot) {
   // arr: 0-5 weights, 6-7 v, 8-9 w, 10 tact, 11 jamp
   if (ep_status s = grow_scratch(b, m.nvox); s != EP_OK) return s;
   if (ep_status s = grow_stim(b, r->stim_idx.size()); s != EP_OK) return s;
-  BHIP(b, hipMemsetAsync(base, 0, r->bytes, b->stream));
+  BHIP(b, hipMemsetAsync(base, 0, r->bytes, b->astream));
   // rest state on the real bricks (the ghost brick stays zero): w = 1 in
   // both buffers (rows without tissue are never stored), T_act = +inf
   BHIP(b, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(arr[8]), 0x3f800000u, nreal,
-                            b->stream));
+                            b->astream));
   BHIP(b, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(arr[9]), 0x3f800000u, nreal,
-                            b->stream));
+                            b->astream));
   BHIP(b, hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(arr[10]), 0x7f800000u, nreal,
-                            b->stream));
-  BHIP(b, hipMemcpyAsync(d_nbr, m.nbr.data(), m.nbr.size() * sizeof(int), hipMemcpyHostToDevice,
-                         b->stream));
-  BHIP(b, hipMemcpyAsync(d_rowsn, m.rowsn.data(), m.rowsn.size() * sizeof(uint64_t),
-                         hipMemcpyHostToDevice, b->stream));
-  BHIP(b, hipMemcpyAsync(b->d_mask, m.mask.data(), nv, hipMemcpyHostToDevice, b->stream));
-  BHIP(b, hipMemcpyAsync(b->d_fib, r->fib_b.get(), 3 * nv * sizeof(double),
-                         hipMemcpyHostToDevice, b->stream));
+                            b->astream));
+  if (ep_status s = upload(b, d_nbr, m.nbr.data(), m.nbr.size() * sizeof(int)); s != EP_OK)
+    return s;
+  if (ep_status s = upload(b, d_rowsn, m.rowsn.data(), m.rowsn.size() * sizeof(uint64_t));
+      s != EP_OK)
+    return s;
+  if (ep_status s = upload(b, b->d_mask, m.mask.data(), nv); s != EP_OK) return s;
+  if (ep_status s = upload(b, b->d_fib, r->fib_b.get(), 3 * nv * sizeof(double)); s != EP_OK)
+    return s;
   if (r->scale_b)
-    BHIP(b, hipMemcpyAsync(b->d_scale, r->scale_b.get(), nv * sizeof(double),
-                           hipMemcpyHostToDevice, b->stream));
-  BHIP(b, hipMemsetAsync(b->d_tens, 0, 6 * nv * sizeof(double), b->stream));
+    if (ep_status s = upload(b, b->d_scale, r->scale_b.get(), nv * sizeof(double)); s != EP_OK)
+      return s;
+  BHIP(b, hipMemsetAsync(b->d_tens, 0, 6 * nv * sizeof(double), b->astream));
   if (!r->stim_idx.empty()) {
-    BHIP(b, hipMemcpyAsync(b->d_stim_idx, r->stim_idx.data(), r->stim_idx.size() * sizeof(int64_t),
-                           hipMemcpyHostToDevice, b->stream));
-    BHIP(b, hipMemcpyAsync(b->d_stim_amp, r->stim_amp.data(), r->stim_amp.size() * sizeof(double),
-                           hipMemcpyHostToDevice, b->stream));
-    launch_stim_scatter<float>(b->stream, b->d_stim_idx, b->d_stim_amp,
+    if (ep_status s = upload(b, b->d_stim_idx, r->stim_idx.data(),
+                             r->stim_idx.size() * sizeof(int64_t));
+        s != EP_OK)
+      return s;
+    if (ep_status s = upload(b, b->d_stim_amp, r->stim_amp.data(),
+                             r->stim_amp.size() * sizeof(double));
+        s != EP_OK)
+      return s;
+    launch_stim_scatter<float>(b->astream, b->d_stim_idx, b->d_stim_amp,
                                static_cast<int>(r->stim_idx.size()), arr[11], b->d_qstep);
   }
   LaunchCfg L;
   L.nb = m.nb;
   L.grid = grid_for(m.nb);
   L.pgrid = L.grid;
-  L.stream = b->stream;
+  L.stream = b->astream;
   L.rowsn = nullptr;
   float* c32[6];
   for (int k = 0; k < 6; ++k) c32[k] = arr[k];
@@ -450,15 +495,23 @@ ep_status admit(ep_batch b, ep_batch_request* r, int slot) {
   sd.step = 0;
   sd.n_steps = r->n_steps;
   sd.active = 1;
-  // from pinned staging that nothing rewrites before the copy has run
-  BHIP(b, hipMemcpyAsync(b->d_slots + slot, &sd, sizeof(SlotDev), hipMemcpyHostToDevice,
-                         b->stream));
-  b->h_slots[slot] = sd;
+  // the slot-table entry goes in after the launch in flight (publish_slot)
   r->slot = slot;
   b->slot_owner[slot] = r->id;
   b->st.admitted += 1;
   b->st.resident += 1;
   b->work_dirty = true;
+  return EP_OK;
+}
+
+// Enter an admitted request into the slot table, from pinned staging that
+// nothing rewrites before the copy has run.  Called after the wait for the
+// launch in flight, whose last kernel advances every active slot and whose
+// read-back overwrites the host copy of the table.
+ep_status publish_slot(ep_batch b, int slot) {
+  BHIP(b, hipMemcpyAsync(b->d_slots + slot, b->h_up + slot, sizeof(SlotDev),
+                         hipMemcpyHostToDevice, b->stream));
+  b->h_slots[slot] = b->h_up[slot];
   return EP_OK;
 }
 
@@ -623,8 +676,18 @@ EP_API ep_status ep_batch_create(const ep_batch_desc* d, ep_batch* out) {
     }
     b->h_up = static_cast<SlotDev*>(hu);
     std::memset(b->h_up, 0, (b->max_slots + 1) * sizeof(SlotDev));
+    void* hs = nullptr;
+    if (hipHostMalloc(&hs, 2 * kStageHalf, hipHostMallocDefault) != hipSuccess) {
+      s = EP_ERR_OOM;
+      break;
+    }
+    b->h_stage = static_cast<char*>(hs);
     if (hipStreamCreateWithFlags(&b->rstream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming) != hipSuccess) {
+        hipStreamCreateWithFlags(&b->astream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_adm, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_stage[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_stage[1], hipEventDisableTiming) != hipSuccess) {
       s = EP_ERR_HIP;
       break;
     }
@@ -796,6 +859,29 @@ EP_API ep_status ep_batch_submit(ep_batch b, const ep_grid_desc* d, const double
 EP_API ep_status ep_batch_advance(ep_batch b, int32_t* n_finished) {
   if (!b) return EP_ERR_ARG;
   try {
+    // admission, FIFO while memory and a slot are free, before the wait:
+    // the uploads and coefficient kernels run beside the launch in flight
+    // (slots and regions freed by releases are not in its work list)
+    while (!b->queue.empty()) {
+      ep_batch_request* r = b->queue.front();
+      int slot = -1;
+      for (int s = 0; s < b->max_slots; ++s)
+        if (b->slot_owner[s] < 0) { slot = s; break; }
+      if (slot < 0) break;
+      const size_t off = b->arena.alloc(r->bytes);
+      if (off == std::numeric_limits<size_t>::max()) break;
+      r->off = off;
+      b->queue.pop_front();
+      if (ep_status s = admit(b, r, slot); s != EP_OK) return s;
+      b->unpublished.push_back(slot);
+      b->arena_peak = std::max(b->arena_peak, b->arena.used());
+    }
+    b->st.queued = static_cast<int32_t>(b->queue.size());
+    if (!b->unpublished.empty()) {
+      // the next launch runs after the admissions
+      BHIP(b, hipEventRecord(b->ev_adm, b->astream));
+      BHIP(b, hipStreamWaitEvent(b->stream, b->ev_adm, 0));
+    }
     // results of the graph launch in flight: wait for it, read the slot table
     int nfin = 0;
     if (b->inflight) {
@@ -817,26 +903,18 @@ EP_API ep_status ep_batch_advance(ep_batch b, int32_t* n_finished) {
         }
       }
     }
-    // admission: FIFO while memory and a slot are free
-    while (!b->queue.empty()) {
-      ep_batch_request* r = b->queue.front();
-      int slot = -1;
-      for (int s = 0; s < b->max_slots; ++s)
-        if (b->slot_owner[s] < 0) { slot = s; break; }
-      if (slot < 0) break;
-      const size_t off = b->arena.alloc(r->bytes);
-      if (off == std::numeric_limits<size_t>::max()) break;
-      r->off = off;
-      b->queue.pop_front();
-      if (ep_status s = admit(b, r, slot); s != EP_OK) return s;
-      b->arena_peak = std::max(b->arena_peak, b->arena.used());
-    }
-    b->st.queued = static_cast<int32_t>(b->queue.size());
+    const bool admitted = !b->unpublished.empty();
+    for (int slot : b->unpublished)
+      if (ep_status s = publish_slot(b, slot); s != EP_OK) return s;
+    b->unpublished.clear();
     if (b->work_dirty)
       if (ep_status s = rebuild_work(b); s != EP_OK) return s;
     if (ep_status s = capture(b); s != EP_OK) return s;
-    // one graph launch of K steps for every running request; the host
-    // returns at once and collects the results at the next call
+    // one graph launch of K steps for every running request, two after an
+    // admission (the host goes on building requests meanwhile, and a short
+    // launch would leave the device idle); the host returns at once and
+    // collects the results at the next call.  A slot that reaches its step
+    // count in the first launch is skipped by the second.
     bool any = false;
     for (int s = 0; s < b->max_slots; ++s) {
       const int64_t id = b->slot_owner[s];
@@ -846,8 +924,10 @@ EP_API ep_status ep_batch_advance(ep_batch b, int32_t* n_finished) {
       }
     }
     if (any) {
-      BHIP(b, hipGraphLaunch(b->exec, b->stream));
-      b->st.graph_launches += 1;
+      for (int l = 0; l < (admitted ? 2 : 1); ++l) {
+        BHIP(b, hipGraphLaunch(b->exec, b->stream));
+        b->st.graph_launches += 1;
+      }
       BHIP(b, hipMemcpyAsync(b->h_slots, b->d_slots, b->max_slots * sizeof(SlotDev),
                              hipMemcpyDeviceToHost, b->stream));
       BHIP(b, hipEventRecord(b->ev_done, b->stream));
@@ -887,10 +967,13 @@ EP_API ep_status ep_batch_read(ep_batch b, int64_t id, ep_field f, double* host_
     int64_t step = r->n_steps;
     hipStream_t rs = b->rstream;
     if (!r->finished) {
+      BHIP(b, hipStreamSynchronize(b->astream));
       BHIP(b, hipStreamSynchronize(b->stream));
       SlotDev cur{};
-      BHIP(b, hipMemcpy(&cur, b->d_slots + r->slot, sizeof(SlotDev), hipMemcpyDeviceToHost));
-      step = cur.step;
+      if (std::find(b->unpublished.begin(), b->unpublished.end(), r->slot) ==
+          b->unpublished.end())
+        BHIP(b, hipMemcpy(&cur, b->d_slots + r->slot, sizeof(SlotDev), hipMemcpyDeviceToHost));
+      step = cur.step;   // 0 for a request that no launch has stepped yet
       rs = b->stream;
     }
     const SlotDev& sd = b->h_up[r->slot];   // the request's buffer pointers
@@ -922,9 +1005,13 @@ EP_API ep_status ep_batch_release(ep_batch b, int64_t id) {
   ep_batch_request* r = it->second;
   if (r->slot >= 0) {
     if (!r->finished) {
-      // still in the work list of the launch in flight: let it end first
+      // still in the work list of the launch in flight, or being admitted:
+      // let both end first
+      BHIP(b, hipStreamSynchronize(b->astream));
       BHIP(b, hipStreamSynchronize(b->stream));
       b->launch_before[r->slot] = -1;
+      b->unpublished.erase(std::remove(b->unpublished.begin(), b->unpublished.end(), r->slot),
+                           b->unpublished.end());
     }
     // clear the slot after the launch in flight (the zero entry of the
     // pinned staging area is never written)
@@ -957,6 +1044,7 @@ EP_API ep_status ep_batch_get_stats(ep_batch b, ep_batch_stats* s) {
 EP_API ep_status ep_batch_destroy(ep_batch b) {
   if (!b) return EP_ERR_ARG;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->astream) (void)hipStreamSynchronize(b->astream);
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (auto& kv : b->all) delete kv.second;
@@ -975,7 +1063,12 @@ EP_API ep_status ep_batch_destroy(ep_batch b) {
   if (b->h_slots) (void)hipHostFree(b->h_slots);
   if (b->h_up) (void)hipHostFree(b->h_up);
   if (b->ev_done) (void)hipEventDestroy(b->ev_done);
+  if (b->ev_adm) (void)hipEventDestroy(b->ev_adm);
+  for (hipEvent_t e : b->ev_stage)
+    if (e) (void)hipEventDestroy(e);
+  if (b->h_stage) (void)hipHostFree(b->h_stage);
   if (b->rstream) (void)hipStreamDestroy(b->rstream);
+  if (b->astream) (void)hipStreamDestroy(b->astream);
   if (b->h_work) (void)hipHostFree(b->h_work);
   if (b->h_count) (void)hipHostFree(b->h_count);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
