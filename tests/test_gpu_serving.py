@@ -103,6 +103,52 @@ def test_mix_of_full_size_requests_matches_oracle(P, orc):
         assert odd_ok and odd <= 10
 
 
+def test_read_and_cancel_while_running(P, stream6):
+    """A running request read between advances holds the state of a whole
+    step: bitwise one of the per-grid path's states, at a multiple of K.
+    Cancelling a running request frees its slot for a later one, and neither
+    the request that keeps running nor the newcomer changes its bits."""
+    ep = P.ep
+    a, c, d = stream6[0], stream6[1], stream6[2]
+    K = 4
+    say(f"case serving read/cancel while running: requests {a.rid}, {c.rid}, {d.rid}, K {K}")
+    b = ep.Batch(64 << 20, max_slots=2, steps_per_launch=K)
+    ia = b.submit_instance(a.inst, n_steps=40)
+    ic = b.submit_instance(c.inst, n_steps=40)
+    b.advance()
+    b.advance()
+    va = b.read(ia, "v")
+    g = P.Grid.from_instance(a.inst)
+    match = None
+    for s in range(1, 41):
+        g.step(1)
+        if np.array_equal(g.read("v"), va, equal_nan=True):
+            match = s
+            break
+    g.close()
+    say(f"  running read matches per-grid step {match}")
+    assert match is not None and match % K == 0
+    b.release(ic)
+    idd = b.submit_instance(d.inst, n_steps=30)
+    done = set()
+    for _ in range(100):
+        if len(done) == 2:
+            break
+        b.advance()
+        done.update(b.finished())
+    assert done == {ia, idd}
+    res = {rid: {f: b.read(rid, f) for f in ("v", "tact")} for rid in (ia, idd)}
+    st = b.stats()
+    b.close()
+    assert st["admitted"] == 3 and st["released"] == 1
+    for rid, inst, steps in ((ia, a.inst, 40), (idd, d.inst, 30)):
+        g = P.Grid.from_instance(inst)
+        g.step(steps)
+        for f in ("v", "tact"):
+            assert np.array_equal(res[rid][f], g.read(f), equal_nan=True), (rid, f)
+        g.close()
+
+
 def test_batch_errors(P, stream6):
     ep = P.ep
     b = ep.Batch(4 << 20, max_slots=2, steps_per_launch=4)
