@@ -22,17 +22,21 @@ def percentile(xs, q):
 
 
 def serve(batch, requests, fields=("tact",), clock=time.perf_counter, sleep=time.sleep,
-          submit_per_advance=4, fields_of=None):
+          submit_per_advance=1, fields_of=None):
     """Run a request stream to completion.
 
     requests: iterable of objects with ``arrival`` (s from stream start),
     ``rid`` (caller id) and ``submit(batch) -> batch id``.
     At most ``submit_per_advance`` arrived requests are submitted between two
-    advances, so the host work of submission overlaps the launch in flight
-    (an advance returns as soon as its launch is queued and reports the
-    requests that the previous launch finished).  On the 64-request serving
-    workload 4 gave the lowest Poisson latency (p99 0.044 s against 0.054 s
-    with 1) and the same burst makespan (0.35-0.37 s for 1 to 64).
+    advances, so the host work of submission overlaps the launches in flight
+    (an advance builds its admissions beside the launch in flight, returns
+    as soon as its own launches are queued and reports the requests that
+    the previous launch finished).  On the 64-request serving workload one
+    per advance gave the shortest burst (makespan 0.305-0.311 s, p50
+    0.216 s, against 0.316-0.320 s and 0.271 s with 4 and 0.357-0.374 s
+    with all 64 at once) and the same or lower Poisson latency (175 req/s:
+    p50 0.020-0.021 s, p99 0.043-0.044 s, against 0.022 s and
+    0.044-0.046 s with 4).
     fields_of (optional): rid -> the fields to read for that request
     instead of ``fields``.
     Returns a dict with per-request latency, results (the requested fields)
