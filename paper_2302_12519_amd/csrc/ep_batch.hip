@@ -60,6 +60,31 @@ struct WorkItem {
   int slot, brick;
 };
 
+// A slot's buffers are device memory, but pointers read from memory are
+// generic to the compiler: its accesses through them would be flat ones,
+// which take a 64-bit address per lane and count against the LDS counter
+// too (so every LDS wait would also wait for memory).  These load and store
+// element i through the global address space, as a scalar base plus a
+// 32-bit byte offset, like at().
+template <typename T>
+__device__ __forceinline__ T gld(const T* p, int i) {
+  using GC = __attribute__((address_space(1))) const char*;
+  using GT = __attribute__((address_space(1))) const T*;
+  return *(GT)((GC)p + static_cast<uint64_t>(static_cast<uint32_t>(i) *
+                                             static_cast<uint32_t>(sizeof(T))));
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, int i, T v) {
+  using GC = __attribute__((address_space(1))) char*;
+  using GT = __attribute__((address_space(1))) T*;
+  *(GT)((GC)p + static_cast<uint64_t>(static_cast<uint32_t>(i) *
+                                      static_cast<uint32_t>(sizeof(T)))) = v;
+}
+struct GLoad {
+  template <typename T>
+  __device__ __forceinline__ T operator()(const T* p, int i) const { return gld(p, i); }
+};
+
 // One explicit step of every running request's bricks (substep k of the
 // current graph launch).  Persistent: the work list is dealt to the 8 XCDs
 // in contiguous ranges (a request's bricks are consecutive in the list, so
@@ -86,8 +111,8 @@ __global__ __launch_bounds__(kBV) __attribute__((amdgpu_waves_per_eu(6))) void k
   if (i < hi) {
     it = work[i];
     if (threadIdx.x < kNbr) {
-      nbv = slots[it.slot].nbr[it.brick * kNbr + threadIdx.x];
-      rmv = slots[it.slot].rowsn[it.brick * kNbr + threadIdx.x];
+      nbv = gld(slots[it.slot].nbr, it.brick * kNbr + threadIdx.x);
+      rmv = gld(slots[it.slot].rowsn, it.brick * kNbr + threadIdx.x);
     }
   }
   int buf = 0;
@@ -109,8 +134,8 @@ __global__ __launch_bounds__(kBV) __attribute__((amdgpu_waves_per_eu(6))) void k
     if (i2 < hi) {
       it2 = work[i2];
       if (threadIdx.x < kNbr) {
-        nbv2 = slots[it2.slot].nbr[it2.brick * kNbr + threadIdx.x];
-        rmv2 = slots[it2.slot].rowsn[it2.brick * kNbr + threadIdx.x];
+        nbv2 = gld(slots[it2.slot].nbr, it2.brick * kNbr + threadIdx.x);
+        rmv2 = gld(slots[it2.slot].rowsn, it2.brick * kNbr + threadIdx.x);
       }
     }
     const long long st = sd->step + k;
@@ -123,6 +148,7 @@ __global__ __launch_bounds__(kBV) __attribute__((amdgpu_waves_per_eu(6))) void k
       const float* __restrict__ w = sd->w[par];
       float* __restrict__ vout = sd->v[par ^ 1];
       float* __restrict__ wout = sd->w[par ^ 1];
+      float* __restrict__ tact = sd->tact;
       const double tn = static_cast<double>(st) * sd->dtd;
       const float* __restrict__ jstim =
           (sd->jamp && sd->t_on <= tn && tn < sd->t_off) ? sd->jamp : nullptr;
@@ -135,16 +161,16 @@ __global__ __launch_bounds__(kBV) __attribute__((amdgpu_waves_per_eu(6))) void k
       // zero potential and stimulus give the same reaction value as the
       // stored rest state, and every weight coupling them is zero)
       const Cell q = cell_setup(nb, brick, rowm, ghost);
-      const float v0 = at(v, q.gl), w0 = at(w, q.gl);
-      const float j0 = jstim ? at(jstim, q.gl) : 0.0f;
+      const float v0 = gld(v, q.gl), w0 = gld(w, q.gl);
+      const float j0 = jstim ? gld(jstim, q.gl) : 0.0f;
       float hv = 0.0f, hw = 0.0f, hj = 0.0f;
       if (q.has_halo) {
-        hv = at(v, q.hgl);
-        hw = at(w, q.hgl);
-        hj = jstim ? at(jstim, q.hgl) : 0.0f;
+        hv = gld(v, q.hgl);
+        hw = gld(w, q.hgl);
+        hj = jstim ? gld(jstim, q.hgl) : 0.0f;
       }
       float k18[18];
-      gather18(c, nb, brick, q.lx, q.ly, q.lz, k18, rowm, ghost);
+      gather18(c, nb, brick, q.lx, q.ly, q.lz, k18, rowm, ghost, GLoad{});
       float vs, ws;
       ms_step(v0, w0, j0, ion, dt, vs, ws);
       s[q.C] = vs;
@@ -156,11 +182,11 @@ __global__ __launch_bounds__(kBV) __attribute__((amdgpu_waves_per_eu(6))) void k
       __syncthreads();
       const float vn = vs + dt * apply19(s, q.C, k18);
       if (q.live) {
-        at(vout, q.g) = vn;
-        at(wout, q.g) = ws;
+        gst(vout, q.g, vn);
+        gst(wout, q.g, ws);
         if (v0 < theta && theta <= vn) {
-          if (isinf(at(sd->tact, q.g)))
-            at(sd->tact, q.g) = static_cast<float>(tn) + dt * (theta - v0) / (vn - v0);
+          if (isinf(gld(tact, q.g)))
+            gst(tact, q.g, static_cast<float>(tn) + dt * (theta - v0) / (vn - v0));
         }
         if (!isfinite(vn)) flags[0] = 1;
       }

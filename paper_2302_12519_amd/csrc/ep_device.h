@@ -103,14 +103,19 @@ __device__ __forceinline__ bool vox_live(const uint64_t* rowm, int tx, int ty, i
 //  6 bxy(p)  7 bxy(p-x-y)  8 bxy(p-y)  9 bxy(p-x)
 // 10 bxz(p) 11 bxz(p-x-z) 12 bxz(p-z) 13 bxz(p-x)
 // 14 byz(p) 15 byz(p-y-z) 16 byz(p-z) 17 byz(p-y)
-// With rowm, weights stored in empty rows are read as zero without a load
-// (and a voxel in an empty row gets all zeros).
 // With rowm, a weight stored in an empty row is loaded from the ghost brick
-// (nb is the ghost brick id), so it reads zero.
-template <typename T>
+// (nb is the ghost brick id), so it reads zero.  ld(p, i) loads element i of
+// array p (at() unless a caller needs another access form).
+struct AtLoad {
+  template <typename T>
+  __device__ __forceinline__ T operator()(const T* p, int i) const { return at(p, i); }
+};
+
+template <typename T, typename Ld = AtLoad>
 __device__ __forceinline__ void gather18(const CoefSet<T>& c, const int* nbs, int brick, int lx,
                                          int ly, int lz, T k[18],
-                                         const uint64_t* rowm = nullptr, int nb = 0) {
+                                         const uint64_t* rowm = nullptr, int nb = 0,
+                                         Ld ld = Ld{}) {
   int g = brick * kBV + (lx * 8 + ly) * 8 + lz;
   int gx = nb_global(nbs, brick, lx, ly, lz, -1, 0, 0);
   int gy = nb_global(nbs, brick, lx, ly, lz, 0, -1, 0);
@@ -129,24 +134,24 @@ __device__ __forceinline__ void gather18(const CoefSet<T>& c, const int* nbs, in
     gxz = (l0 && vox_live(rowm, lx - 1, ly, lz - 1)) ? gxz : gh;
     gyz = (l0 && vox_live(rowm, lx, ly - 1, lz - 1)) ? gyz : gh;
   }
-  k[0] = at(c.c[CX], g);
-  k[1] = at(c.c[CX], gx);
-  k[2] = at(c.c[CY], g);
-  k[3] = at(c.c[CY], gy);
-  k[4] = at(c.c[CZ], g);
-  k[5] = at(c.c[CZ], gz);
-  k[6] = at(c.c[CXY], g);
-  k[7] = at(c.c[CXY], gxy);
-  k[8] = at(c.c[CXY], gy);
-  k[9] = at(c.c[CXY], gx);
-  k[10] = at(c.c[CXZ], g);
-  k[11] = at(c.c[CXZ], gxz);
-  k[12] = at(c.c[CXZ], gz);
-  k[13] = at(c.c[CXZ], gx);
-  k[14] = at(c.c[CYZ], g);
-  k[15] = at(c.c[CYZ], gyz);
-  k[16] = at(c.c[CYZ], gz);
-  k[17] = at(c.c[CYZ], gy);
+  k[0] = ld(c.c[CX], g);
+  k[1] = ld(c.c[CX], gx);
+  k[2] = ld(c.c[CY], g);
+  k[3] = ld(c.c[CY], gy);
+  k[4] = ld(c.c[CZ], g);
+  k[5] = ld(c.c[CZ], gz);
+  k[6] = ld(c.c[CXY], g);
+  k[7] = ld(c.c[CXY], gxy);
+  k[8] = ld(c.c[CXY], gy);
+  k[9] = ld(c.c[CXY], gx);
+  k[10] = ld(c.c[CXZ], g);
+  k[11] = ld(c.c[CXZ], gxz);
+  k[12] = ld(c.c[CXZ], gz);
+  k[13] = ld(c.c[CXZ], gx);
+  k[14] = ld(c.c[CYZ], g);
+  k[15] = ld(c.c[CYZ], gyz);
+  k[16] = ld(c.c[CYZ], gz);
+  k[17] = ld(c.c[CYZ], gy);
 }
 
 // (A u)_p from the LDS tile s at tile cell C.  Faces: a (u_q - u_p).  Each
