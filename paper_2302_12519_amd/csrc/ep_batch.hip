@@ -936,11 +936,11 @@ EP_API ep_status ep_batch_advance(ep_batch b, int32_t* n_finished) {
     if (b->work_dirty)
       if (ep_status s = rebuild_work(b); s != EP_OK) return s;
     if (ep_status s = capture(b); s != EP_OK) return s;
-    // one graph launch of K steps for every running request, two after an
-    // admission (the host goes on building requests meanwhile, and a short
-    // launch would leave the device idle); the host returns at once and
+    // one graph launch of K steps for every running request, three after
+    // an admission (the host goes on building requests meanwhile, and short
+    // launches would leave the device idle); the host returns at once and
     // collects the results at the next call.  A slot that reaches its step
-    // count in the first launch is skipped by the second.
+    // count in one launch is skipped by the later ones.
     bool any = false;
     for (int s = 0; s < b->max_slots; ++s) {
       const int64_t id = b->slot_owner[s];
@@ -950,7 +950,7 @@ EP_API ep_status ep_batch_advance(ep_batch b, int32_t* n_finished) {
       }
     }
     if (any) {
-      for (int l = 0; l < (admitted ? 2 : 1); ++l) {
+      for (int l = 0; l < (admitted ? 3 : 1); ++l) {
         BHIP(b, hipGraphLaunch(b->exec, b->stream));
         b->st.graph_launches += 1;
       }
