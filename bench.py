@@ -78,7 +78,7 @@ def parse():
     ap.add_argument("--serving", type=int, default=64,
                     help="requests of the serving measurement (0 skips it)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-box FP64 line")
-    ap.add_argument("--serving-k", type=int, default=16,
+    ap.add_argument("--serving-k", type=int, default=32,
                     help="steps per captured graph launch of the serving line")
     ap.add_argument("--jacobi", type=int, default=256,
                     help="grid edge of the fixed-sweep Jacobi line (0 = skip)")
@@ -199,7 +199,7 @@ def oracle_run_error(inst, results, steps):
     return out
 
 
-def bench_serving(count, K=16, n_err=3):
+def bench_serving(count, K=32, n_err=3):
     """Serving workload: `count` requests (grids 48^3..160^3 shells, sigma x
     U[0.5,1.5], excitability U[0.8,1.2], 200..1000 FP32 explicit steps).  A
     burst run measures capacity; a Poisson stream at 0.9 x capacity gives
