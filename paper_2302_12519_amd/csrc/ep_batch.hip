@@ -898,7 +898,15 @@ EP_API ep_status ep_batch_advance(ep_batch b, int32_t* n_finished) {
       if (off == std::numeric_limits<size_t>::max()) break;
       r->off = off;
       b->queue.pop_front();
-      if (ep_status s = admit(b, r, slot); s != EP_OK) return s;
+      if (ep_status s = admit(b, r, slot); s != EP_OK) {
+        // back to the head of the queue with its region freed, for a later
+        // advance to try again (what the failed admission enqueued into the
+        // region runs before any later admission's, on the same stream)
+        b->arena.release(off, r->bytes);
+        b->queue.push_front(r);
+        b->st.queued = static_cast<int32_t>(b->queue.size());
+        return s;
+      }
       b->unpublished.push_back(slot);
       b->arena_peak = std::max(b->arena_peak, b->arena.used());
     }
